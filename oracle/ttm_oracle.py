@@ -1,0 +1,561 @@
+"""FP64 CPU oracle for tensorial template matching (TTM) and classical template
+matching (TM).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the library's product path imports,
+calls or links this module: it is used by ``tests/``, by the smoke check and by
+the benchmark's CPU-baseline leg.  It is a plain, slow, obviously correct
+implementation written from the paper (Almira, Phelippeau, Martinez-Sanchez,
+"Fast Normalized Cross-Correlation for Template Matching with Rotations",
+arXiv 2311.07561).  Every correlation is a *direct spatial sum* (no FFT), every
+reduction is in float64, and each function cites the passage it follows.
+
+Readings of points where the paper is silent (listed in the design doc as well):
+
+* grid: C-order ``[n0][n1][n2]``; correlation is circular,
+  ``(f * g)(x) = sum_u f((x + u - c) mod N) g(u)`` with ``c = L // 2`` the
+  template centre (Section 2, eq. "correlation", with the template measured from
+  its centre); results are compared in the *valid region* where the window
+  ``[x - c, x - c + L)`` lies inside the image on every axis;
+* unit quaternion ``Q = (a, b, c, d)`` scalar first, active Hamilton rotation;
+* ``t_R(u) = t(c + R^-1 (u - c))`` (Section 2, ``t_R = O_{R^-1}(t)``), sampled
+  trilinearly with zero outside the L-box;
+* mask ``m`` and filter ``h = delta``: ``S(f) = m f`` (Section 2, the practical
+  SSP operator with an identity filter);
+* rotate the raw template, then normalise it under the mask, per rotation, so
+  that every rotated template satisfies ``<s,1>_S = 0`` and ``||s||_S = 1``
+  exactly on the grid;
+* ``w(x) = 0`` where the local masked variance ``v`` is at most
+  ``eps_v * m_sum * var(f)``;
+* symmetric tensors of ``S^n(R^4)`` are stored packed, one entry per multi-index
+  ``alpha`` with ``|alpha| = n`` (order: ``alpha_1`` from ``n`` down to 0, then
+  ``alpha_2``, then ``alpha_3``; ``alpha_4`` is the remainder), with
+  multiplicity ``mu_alpha = n! / prod(alpha_i!)``;
+* the SO(3) integral is a caller-supplied quadrature ``{(Q_j, omega_j)}`` over
+  unit quaternions, ``sum omega_j = 1`` (normalised Haar measure).
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+EPS_V_DEFAULT = 1e-5
+
+
+# ----------------------------------------------------------------------------
+# quaternions (Section 2, quaternion facts; Section 4, the S^3 parametrisation)
+# ----------------------------------------------------------------------------
+
+def quat_to_matrix(q) -> np.ndarray:
+    """Rotation matrix of the unit quaternion ``q = a + b i + c j + d k``: the
+    map ``v -> q v q*`` on pure quaternions ``v = (0, v0, v1, v2)``."""
+    q = np.asarray(q, dtype=np.float64)
+    a, b, c, d = q / np.linalg.norm(q)
+    # written out from q v q* with the Hamilton product
+    return np.array([
+        [a * a + b * b - c * c - d * d, 2.0 * (b * c - a * d), 2.0 * (b * d + a * c)],
+        [2.0 * (b * c + a * d), a * a - b * b + c * c - d * d, 2.0 * (c * d - a * b)],
+        [2.0 * (b * d - a * c), 2.0 * (c * d + a * b), a * a - b * b - c * c + d * d],
+    ])
+
+
+def quat_mul(p, q) -> np.ndarray:
+    """Hamilton product ``p q``."""
+    a1, b1, c1, d1 = p
+    a2, b2, c2, d2 = q
+    return np.array([
+        a1 * a2 - b1 * b2 - c1 * c2 - d1 * d2,
+        a1 * b2 + b1 * a2 + c1 * d2 - d1 * c2,
+        a1 * c2 - b1 * d2 + c1 * a2 + d1 * b2,
+        a1 * d2 + b1 * c2 - c1 * b2 + d1 * a2,
+    ])
+
+
+def quat_canonical(q) -> np.ndarray:
+    """Unit quaternion with scalar part > 0 (first nonzero component > 0 when
+    the scalar part is 0): ``q`` and ``-q`` are the same rotation."""
+    q = np.asarray(q, dtype=np.float64)
+    q = q / np.linalg.norm(q)
+    for v in q:
+        if v != 0.0:
+            return q if v > 0 else -q
+    return q
+
+
+def rotation_angle_deg(q1, q2) -> float:
+    """Angle of the rotation taking ``q1`` to ``q2``: ``2 acos |<q1, q2>|``
+    (the inner product of unit quaternions is ``Re(q2^-1 q1)``, Section 2)."""
+    q1 = np.asarray(q1, dtype=np.float64)
+    q2 = np.asarray(q2, dtype=np.float64)
+    d = abs(float(np.dot(q1 / np.linalg.norm(q1), q2 / np.linalg.norm(q2))))
+    return math.degrees(2.0 * math.acos(min(1.0, d)))
+
+
+# ----------------------------------------------------------------------------
+# packed symmetric tensors (Section 3.1)
+# ----------------------------------------------------------------------------
+
+def multi_indices(n: int) -> np.ndarray:
+    """Multi-indices ``alpha`` of ``S^n(R^4)`` in storage order."""
+    out = []
+    for a1 in range(n, -1, -1):
+        for a2 in range(n - a1, -1, -1):
+            for a3 in range(n - a1 - a2, -1, -1):
+                out.append((a1, a2, a3, n - a1 - a2 - a3))
+    return np.array(out, dtype=np.int64)
+
+
+def num_components(n: int) -> int:
+    """``dim S^n(R^4) = C(n + 3, 3)`` (Section 3.1)."""
+    return math.comb(n + 3, 3)
+
+
+def multiplicities(n: int) -> np.ndarray:
+    """How many of the ``4^n`` entries of a symmetric tensor equal the packed
+    entry ``alpha``: ``n! / (alpha_1! alpha_2! alpha_3! alpha_4!)``."""
+    f = math.factorial
+    return np.array([f(n) // (f(a[0]) * f(a[1]) * f(a[2]) * f(a[3]))
+                     for a in multi_indices(n)], dtype=np.float64)
+
+
+def monomials(q: np.ndarray, n: int) -> np.ndarray:
+    """``Q^alpha = a^alpha1 b^alpha2 c^alpha3 d^alpha4`` for each packed alpha;
+    ``q`` has shape (..., 4); result (..., K).  These are the packed entries of
+    the tensor power ``Q^{(.)n}`` (Section 3.1)."""
+    q = np.asarray(q, dtype=np.float64)
+    al = multi_indices(n)
+    out = np.ones(q.shape[:-1] + (len(al),))
+    for i in range(4):
+        out *= q[..., i, None] ** al[:, i]
+    return out
+
+
+def unpack_symmetric(A: np.ndarray, n: int) -> np.ndarray:
+    """Full ``4^n`` array of a packed symmetric tensor (brute-force helper)."""
+    al = multi_indices(n)
+    lookup = {tuple(a): k for k, a in enumerate(al)}
+    full = np.zeros((4,) * n)
+    for idx in itertools.product(range(4), repeat=n):
+        cnt = [0, 0, 0, 0]
+        for i in idx:
+            cnt[i] += 1
+        full[idx] = A[lookup[tuple(cnt)]]
+    return full
+
+
+def tensor_apply(A: np.ndarray, n: int, q: np.ndarray) -> float:
+    """``A x^n = <A, x^{(.)n}> = sum_alpha mu_alpha A_alpha x^alpha``
+    (Section 3.1)."""
+    return float(np.dot(multiplicities(n) * A, monomials(q, n)))
+
+
+def tensor_apply_nm1(A: np.ndarray, n: int, q: np.ndarray) -> np.ndarray:
+    """``A x^{n-1}``: the vector with ``(A x^{n-1})_i = (1/n) d(A x^n)/dx_i``
+    (Section 3.1, the gradient identity)."""
+    q = np.asarray(q, dtype=np.float64)
+    al = multi_indices(n)
+    mu = multiplicities(n)
+    out = np.zeros(4)
+    for k, a in enumerate(al):
+        for i in range(4):
+            if a[i] == 0:
+                continue
+            e = a.copy()
+            e[i] -= 1
+            out[i] += mu[k] * A[k] * a[i] / n * np.prod(q ** e)
+    return out
+
+
+def tensor_apply_nm2(A: np.ndarray, n: int, q: np.ndarray) -> np.ndarray:
+    """``A x^{n-2}``: the 4x4 matrix with Hessian ``n (n-1) A x^{n-2}``."""
+    q = np.asarray(q, dtype=np.float64)
+    al = multi_indices(n)
+    mu = multiplicities(n)
+    out = np.zeros((4, 4))
+    for k, a in enumerate(al):
+        for i in range(4):
+            for j in range(4):
+                e = a.copy()
+                e[i] -= 1
+                e[j] -= 1
+                coef = a[i] * (a[j] - (1 if i == j else 0))
+                if coef == 0 or np.any(e < 0):
+                    continue
+                out[i, j] += mu[k] * A[k] * coef / (n * (n - 1)) * np.prod(q ** e)
+    return out
+
+
+def frobenius_norm(A: np.ndarray, n: int) -> float:
+    """Frobenius norm over all ``4^n`` entries of a packed symmetric tensor."""
+    return float(math.sqrt(np.dot(multiplicities(n), np.asarray(A) ** 2)))
+
+
+# ----------------------------------------------------------------------------
+# template geometry: mask, rotation, normalisation (Section 2, Algorithm 1)
+# ----------------------------------------------------------------------------
+
+def template_centre(L) -> np.ndarray:
+    return np.array([int(l) // 2 for l in L], dtype=np.int64)
+
+
+def rotate_trilinear(t: np.ndarray, q) -> np.ndarray:
+    """``t_R(u) = t(c + R^-1 (u - c))`` sampled trilinearly, zero outside the
+    box (Section 2: ``t_R = O_{R^-1}(t)``)."""
+    t = np.asarray(t, dtype=np.float64)
+    L = np.array(t.shape)
+    c = template_centre(L).astype(np.float64)
+    r_inv = quat_to_matrix(q).T
+    grids = np.meshgrid(*[np.arange(l, dtype=np.float64) for l in L], indexing="ij")
+    u = np.stack(grids, axis=-1) - c
+    p = u @ r_inv.T + c                      # p = c + R^-1 (u - c)
+    p0 = np.floor(p)
+    fr = p - p0
+    p0 = p0.astype(np.int64)
+    out = np.zeros(t.shape)
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                idx = p0 + np.array([dz, dy, dx])
+                wgt = ((fr[..., 0] if dz else 1 - fr[..., 0]) *
+                       (fr[..., 1] if dy else 1 - fr[..., 1]) *
+                       (fr[..., 2] if dx else 1 - fr[..., 2]))
+                inside = np.all((idx >= 0) & (idx < L), axis=-1)
+                vals = np.zeros(t.shape)
+                ii = idx[inside]
+                vals[inside] = t[ii[:, 0], ii[:, 1], ii[:, 2]]
+                out += wgt * vals
+    return out
+
+
+def masked_normalize(g: np.ndarray, m: np.ndarray) -> np.ndarray:
+    """``m * (g - <g,m>/m_sum) / sqrt(<g^2,m> - <g,m>^2/m_sum)``: the template
+    made S-orthogonal to the constant image and of unit S-norm, then passed
+    through ``S`` (Algorithm 1, template pre-processing; Section 2, closed form
+    of ``m (h * P_S(t) / ||P_S(t)||_S)``)."""
+    g = np.asarray(g, dtype=np.float64)
+    m = np.asarray(m, dtype=np.float64)
+    msum = m.sum()
+    if not msum > 0:
+        raise ValueError("mask has no mass")
+    s1 = float((g * m).sum())
+    s2 = float((g * g * m).sum())
+    var = s2 - s1 * s1 / msum
+    if not var > 0:
+        raise ValueError("template has zero variance under the mask")
+    return m * (g - s1 / msum) / math.sqrt(var)
+
+
+def rotated_template(t, m, q) -> np.ndarray:
+    """``s_R``: raw template rotated by ``R(q)``, then normalised under ``m``."""
+    return masked_normalize(rotate_trilinear(t, q), m)
+
+
+# ----------------------------------------------------------------------------
+# direct spatial correlation and local normalisation (Section 2)
+# ----------------------------------------------------------------------------
+
+def valid_region(N, L) -> tuple:
+    """Inclusive-exclusive bounds ``[lo, hi)`` per axis of the positions whose
+    template window lies inside the image."""
+    c = template_centre(L)
+    lo = c
+    hi = np.array(N) - np.array(L) + c + 1
+    return lo, hi
+
+
+def valid_mask(N, L) -> np.ndarray:
+    lo, hi = valid_region(N, L)
+    out = np.zeros(tuple(N), dtype=bool)
+    out[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] = True
+    return out
+
+
+def windows(f: np.ndarray, xs: np.ndarray, L) -> np.ndarray:
+    """``W[p, u] = f((x_p + u - c) mod N)`` for the positions ``xs`` (P, 3):
+    the translated image ``tau_x f`` restricted to the template box."""
+    f = np.asarray(f, dtype=np.float64)
+    N = np.array(f.shape)
+    c = template_centre(L)
+    xs = np.asarray(xs, dtype=np.int64).reshape(-1, 3)
+    i0 = (xs[:, 0, None] + np.arange(L[0]) - c[0]) % N[0]
+    i1 = (xs[:, 1, None] + np.arange(L[1]) - c[1]) % N[1]
+    i2 = (xs[:, 2, None] + np.arange(L[2]) - c[2]) % N[2]
+    return f[i0[:, :, None, None], i1[:, None, :, None], i2[:, None, None, :]]
+
+
+def correlate_at(f: np.ndarray, g: np.ndarray, xs: np.ndarray,
+                 chunk: int = 512) -> np.ndarray:
+    """Cross-correlation ``(f * g)(x) = sum_u f(x + u - c) g(u)`` (Section 2,
+    eq. "correlation") at positions ``xs``; ``g`` is one template (L^3) or a
+    stack (K, L^3).  Returns (P,) or (P, K)."""
+    g = np.asarray(g, dtype=np.float64)
+    single = g.ndim == 3
+    gs = g[None] if single else g
+    L = gs.shape[1:]
+    xs = np.asarray(xs, dtype=np.int64).reshape(-1, 3)
+    out = np.empty((len(xs), gs.shape[0]))
+    gm = gs.reshape(gs.shape[0], -1).T
+    for s in range(0, len(xs), chunk):
+        w = windows(f, xs[s:s + chunk], L).reshape(-1, gm.shape[0])
+        out[s:s + chunk] = w @ gm
+    return out[:, 0] if single else out
+
+
+def local_norm_at(f: np.ndarray, m: np.ndarray, xs: np.ndarray,
+                  eps_v: float = EPS_V_DEFAULT, chunk: int = 512) -> np.ndarray:
+    """``w(x) = 1 / ||P_S tau_x f||_S`` (Section 2) by the two-pass definition:
+    masked mean ``mu_x``, then ``v_x = sum_u m(u) (f(x+u-c) - mu_x)^2``; ``w = 0``
+    where ``v_x <= eps_v * m_sum * var(f)``."""
+    f = np.asarray(f, dtype=np.float64)
+    m = np.asarray(m, dtype=np.float64)
+    msum = m.sum()
+    floor = eps_v * msum * float(f.var())
+    xs = np.asarray(xs, dtype=np.int64).reshape(-1, 3)
+    out = np.empty(len(xs))
+    mv = m.reshape(-1)
+    for s in range(0, len(xs), chunk):
+        w = windows(f, xs[s:s + chunk], m.shape).reshape(-1, mv.size)
+        mu = (w @ mv) / msum
+        v = ((w - mu[:, None]) ** 2) @ mv
+        out[s:s + chunk] = np.where(v > floor, 1.0 / np.sqrt(np.maximum(v, 1e-300)), 0.0)
+    return out
+
+
+def all_positions(N) -> np.ndarray:
+    g = np.meshgrid(*[np.arange(n) for n in N], indexing="ij")
+    return np.stack([x.reshape(-1) for x in g], axis=1)
+
+
+# ----------------------------------------------------------------------------
+# classical template matching (Algorithm 1 with a loop over rotations)
+# ----------------------------------------------------------------------------
+
+def classical_ncc_at(f, t, m, quats, xs, eps_v: float = EPS_V_DEFAULT):
+    """``c(x, R_j) = w(x) (f * s_{R_j})(x)`` for every rotation (Section 2,
+    eq. for c(x,R); Algorithm 1).  Returns the (P, J) matrix."""
+    s = np.stack([rotated_template(t, m, q) for q in quats])
+    corr = correlate_at(f, s, xs)
+    w = local_norm_at(f, m, xs, eps_v)
+    return corr * w[:, None]
+
+
+def classical_best_at(f, t, m, quats, xs, eps_v: float = EPS_V_DEFAULT):
+    """Per position the largest NCC over the rotation list and its index
+    (lowest index on ties)."""
+    c = classical_ncc_at(f, t, m, quats, xs, eps_v)
+    idx = np.argmax(c, axis=1)        # first maximum
+    return c[np.arange(len(c)), idx], idx
+
+
+# ----------------------------------------------------------------------------
+# tensor template, tensor field, score (Section 3.2, 3.4)
+# ----------------------------------------------------------------------------
+
+def tensor_template(t, m, n: int, quats, weights) -> np.ndarray:
+    """Packed tensor template ``T_alpha(u) = sum_j omega_j Q_j^alpha s_{R_j}(u)``:
+    the quadrature form of ``T(z) = int R^{(.)n} S(t)_R(z) dR`` (Section 3.2)."""
+    if n < 2 or n % 2:
+        raise ValueError("tensor order must be even and >= 2")
+    quats = np.asarray(quats, dtype=np.float64)
+    weights = np.asarray(weights, dtype=np.float64)
+    K = num_components(n)
+    T = np.zeros((K,) + tuple(np.shape(t)))
+    mono = monomials(quats / np.linalg.norm(quats, axis=1, keepdims=True), n)
+    for j, q in enumerate(quats):
+        s = rotated_template(t, m, q)
+        T += (weights[j] * mono[j])[:, None, None, None] * s[None]
+    return T
+
+
+def tensor_field_at(f, T, m, xs, eps_v: float = EPS_V_DEFAULT) -> np.ndarray:
+    """``C_alpha(x) = w(x) <tau_x f, T_alpha>`` (Section 3.2): (P, K)."""
+    corr = correlate_at(f, T, xs)
+    w = local_norm_at(f, m, xs, eps_v)
+    return corr * w[:, None]
+
+
+def score_from_field(C: np.ndarray, n: int) -> np.ndarray:
+    """Frobenius norm of each packed ``C_n(x)`` (Section 3.4)."""
+    C = np.asarray(C, dtype=np.float64)
+    return np.sqrt(C ** 2 @ multiplicities(n))
+
+
+def score_map(f, T, m, n: int, eps_v: float = EPS_V_DEFAULT,
+              chunk: int = 512) -> np.ndarray:
+    """Frobenius score ``F(x) = ||C_n(x)||_F`` over the whole image; zero
+    outside the valid region."""
+    f = np.asarray(f, dtype=np.float64)
+    N = f.shape
+    L = T.shape[1:]
+    vm = valid_mask(N, L)
+    xs = np.argwhere(vm)
+    out = np.zeros(N)
+    vals = np.empty(len(xs))
+    for s in range(0, len(xs), chunk * 8):
+        C = tensor_field_at(f, T, m, xs[s:s + chunk * 8], eps_v)
+        vals[s:s + chunk * 8] = score_from_field(C, n)
+    out[vm] = vals
+    return out
+
+
+def w_map(f, m, eps_v: float = EPS_V_DEFAULT) -> np.ndarray:
+    """``w(x)`` over the whole image; zero outside the valid region."""
+    N = np.shape(f)
+    vm = valid_mask(N, np.shape(m))
+    out = np.zeros(N)
+    out[vm] = local_norm_at(f, m, np.argwhere(vm), eps_v)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# candidate positions (Section 3.4: Frobenius norm as the position proxy)
+# ----------------------------------------------------------------------------
+
+def find_peaks(F: np.ndarray, L, threshold: float, min_dist: float,
+               max_peaks: int) -> np.ndarray:
+    """Candidates are valid-region voxels strictly above all 26 neighbours and
+    above ``threshold``; sorted by score (descending, ties by lower linear
+    index); greedy suppression of any candidate within Euclidean distance
+    ``min_dist`` of an accepted one; at most ``max_peaks`` kept.  Returns
+    (P, 3) int64 positions in acceptance order."""
+    F = np.asarray(F)
+    N = F.shape
+    lo, hi = valid_region(N, L)
+    cands = []
+    for x0 in range(lo[0], hi[0]):
+        for x1 in range(lo[1], hi[1]):
+            for x2 in range(lo[2], hi[2]):
+                v = F[x0, x1, x2]
+                if not v > threshold:
+                    continue
+                ok = True
+                for d0 in (-1, 0, 1):
+                    for d1 in (-1, 0, 1):
+                        for d2 in (-1, 0, 1):
+                            if d0 == d1 == d2 == 0:
+                                continue
+                            y0, y1, y2 = x0 + d0, x1 + d1, x2 + d2
+                            if 0 <= y0 < N[0] and 0 <= y1 < N[1] and 0 <= y2 < N[2]:
+                                if not v > F[y0, y1, y2]:
+                                    ok = False
+                    if not ok:
+                        break
+                if ok:
+                    cands.append((v, (x0 * N[1] + x1) * N[2] + x2, (x0, x1, x2)))
+    cands.sort(key=lambda e: (-e[0], e[1]))
+    acc = []
+    for v, lin, p in cands:
+        if len(acc) >= max_peaks:
+            break
+        if all((p[0] - a[0]) ** 2 + (p[1] - a[1]) ** 2 + (p[2] - a[2]) ** 2
+               >= min_dist * min_dist for a in acc):
+            acc.append(p)
+    return np.array(acc, dtype=np.int64).reshape(-1, 3)
+
+
+def find_peaks_fast(F: np.ndarray, L, threshold: float, min_dist: float,
+                    max_peaks: int) -> np.ndarray:
+    """Same result as :func:`find_peaks`, with the local-maximum test done by
+    array comparisons (for larger maps)."""
+    F = np.asarray(F)
+    N = F.shape
+    lo, hi = valid_region(N, L)
+    is_max = np.zeros(N, dtype=bool)
+    sub = (slice(lo[0], hi[0]), slice(lo[1], hi[1]), slice(lo[2], hi[2]))
+    core = F[sub]
+    ok = core > threshold
+    pad = np.pad(F, 1, mode="constant", constant_values=-np.inf)
+    for d0 in (-1, 0, 1):
+        for d1 in (-1, 0, 1):
+            for d2 in (-1, 0, 1):
+                if d0 == d1 == d2 == 0:
+                    continue
+                nb = pad[lo[0] + 1 + d0:hi[0] + 1 + d0,
+                         lo[1] + 1 + d1:hi[1] + 1 + d1,
+                         lo[2] + 1 + d2:hi[2] + 1 + d2]
+                ok &= core > nb
+    is_max[sub] = ok
+    pts = np.argwhere(is_max)
+    vals = F[is_max]
+    lin = (pts[:, 0] * N[1] + pts[:, 1]) * N[2] + pts[:, 2]
+    order = np.lexsort((lin, -vals))
+    acc = []
+    d2min = min_dist * min_dist
+    for k in order:
+        if len(acc) >= max_peaks:
+            break
+        p = pts[k]
+        if all(((p - a) ** 2).sum() >= d2min for a in acc):
+            acc.append(p)
+    return np.array(acc, dtype=np.int64).reshape(-1, 3)
+
+
+# ----------------------------------------------------------------------------
+# rotation at a candidate: dominant Z-eigenpair (Section 3.3, Theorem "main";
+# Section 3.1, eq. "Zeigen"; Section 3.4, SS-HOPM)
+# ----------------------------------------------------------------------------
+
+def sshopm(A: np.ndarray, n: int, q0, tol: float = 1e-14,
+           max_iter: int = 20000, tau: float = 1e-6):
+    """Shifted symmetric higher-order power method for ``max A x^n`` on the
+    unit sphere: ``x <- (A x^{n-1} + alpha x) / ||.||`` with the shift chosen at
+    each step so that ``(1/n) A x^n + (alpha/2)||x||^2`` is locally convex,
+    ``alpha = max(0, tau - (n-1) lambda_min(A x^{n-2}))``.  Stops when
+    ``|delta lambda| <= tol * max(1, |lambda|)``.  Returns (x, lambda, iters,
+    converged)."""
+    x = np.asarray(q0, dtype=np.float64)
+    x = x / np.linalg.norm(x)
+    lam = tensor_apply(A, n, x)
+    for it in range(1, max_iter + 1):
+        hmin = float(np.linalg.eigvalsh(tensor_apply_nm2(A, n, x))[0])
+        alpha = max(0.0, tau - (n - 1) * hmin)
+        y = tensor_apply_nm1(A, n, x) + alpha * x
+        x = y / np.linalg.norm(y)
+        new = tensor_apply(A, n, x)
+        if abs(new - lam) <= tol * max(1.0, abs(new)):
+            return x, new, it, True
+        lam = new
+    return x, lam, max_iter, False
+
+
+def oracle_sphere_points(count: int) -> np.ndarray:
+    """Dense near-uniform set on S^3 (super-Fibonacci spiral, Alexa 2022) used
+    for the brute-force search."""
+    phi = math.sqrt(2.0)
+    psi = 1.533751168755204288118041
+    s = np.arange(count, dtype=np.float64) + 0.5
+    r = np.sqrt(s / count)
+    rr = np.sqrt(1.0 - s / count)
+    a = 2.0 * np.pi * s / phi
+    b = 2.0 * np.pi * s / psi
+    return np.stack([r * np.sin(a), r * np.cos(a), rr * np.sin(b), rr * np.cos(b)], axis=1)
+
+
+def dominant_z_eigenpair(A: np.ndarray, n: int, n_brute: int = 200000,
+                         n_polish: int = 4):
+    """Global maximiser of ``phi(Q) = A Q^n`` on S^3: brute force over a dense
+    point set, then SS-HOPM polish from the best few points.  Returns
+    (q canonical, lambda, second_best_lambda_far) where the last is the best
+    polished value at least 5 degrees away (for ambiguity checks)."""
+    pts = oracle_sphere_points(n_brute)
+    vals = monomials(pts, n) @ (multiplicities(n) * A)
+    order = np.argsort(-vals)
+    polished = []
+    seen = []
+    for k in order:
+        p = pts[k]
+        if any(rotation_angle_deg(p, s) < 10.0 for s in seen):
+            continue
+        seen.append(p)
+        x, lam, _, _ = sshopm(A, n, p)
+        polished.append((lam, quat_canonical(x)))
+        if len(seen) >= n_polish:
+            break
+    polished.sort(key=lambda e: -e[0])
+    best_lam, best_q = polished[0]
+    second = -np.inf
+    for lam, q in polished[1:]:
+        if rotation_angle_deg(q, best_q) > 5.0:
+            second = max(second, lam)
+    return best_q, best_lam, second

@@ -1,0 +1,442 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms,
+brute force over all 4^n tensor entries, a library FFT, exact grid rotations,
+Cauchy-Schwarz, the planted-copy theorem, or values the paper prints.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ttm_oracle as O
+from paper_2311_07561_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rng(s):
+    return np.random.default_rng(s)
+
+
+# --------------------------------------------------------------------------
+# packed symmetric tensors (Section 3.1)
+# --------------------------------------------------------------------------
+
+def test_paper_dimension_counts():
+    facts = json.load(open(os.path.join(GOLDEN, "paper_facts.json")))
+    assert O.num_components(4) == facts["dim_S4_R4"]["value"]
+    assert len(O.multi_indices(4)) == facts["components_order4"]["value"]
+    assert int(O.multiplicities(4).sum()) == facts["dim_T4_R4"]["value"]
+    rot = facts["rotations_for_accuracy"]["value"]
+    assert rot["13"] // O.num_components(4) == facts["speedup_13deg"]["value"]
+    for n, k in [(2, 10), (4, 35), (6, 84), (8, 165)]:
+        al = O.multi_indices(n)
+        assert len(al) == k == O.num_components(n)
+        assert len({tuple(a) for a in al}) == k
+        assert np.all(al.sum(axis=1) == n) and np.all(al >= 0)
+        assert int(O.multiplicities(n).sum()) == 4 ** n
+    assert tuple(O.multi_indices(4)[0]) == (4, 0, 0, 0)
+    assert tuple(O.multi_indices(4)[-1]) == (0, 0, 0, 4)
+
+
+@pytest.mark.parametrize("n", [2, 4, 6])
+def test_power_inner_product_identity(n):
+    # x^{(.)n} . y^{(.)n} = (x . y)^n  (Section 3.1, multinomial theorem)
+    r = _rng(n)
+    for _ in range(5):
+        x, y = r.standard_normal(4), r.standard_normal(4)
+        packed = float(np.sum(O.multiplicities(n) * O.monomials(x, n) * O.monomials(y, n)))
+        assert packed == pytest.approx(float(np.dot(x, y)) ** n, rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("n", [2, 4])
+def test_packed_norm_and_contraction_vs_all_entries(n):
+    r = _rng(10 + n)
+    A = r.standard_normal(O.num_components(n))
+    full = O.unpack_symmetric(A, n)
+    # symmetric under index permutation
+    assert np.allclose(full, np.transpose(full, list(reversed(range(n)))))
+    assert O.frobenius_norm(A, n) == pytest.approx(math.sqrt(float((full ** 2).sum())), rel=1e-13)
+    x = r.standard_normal(4)
+    brute = full
+    for _ in range(n):
+        brute = brute @ x
+    assert O.tensor_apply(A, n, x) == pytest.approx(float(brute), rel=1e-12)
+    v = full
+    for _ in range(n - 1):
+        v = v @ x
+    assert np.allclose(O.tensor_apply_nm1(A, n, x), v, rtol=1e-12, atol=1e-12)
+    M = full
+    for _ in range(n - 2):
+        M = M @ x
+    assert np.allclose(O.tensor_apply_nm2(A, n, x), M, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [2, 4, 6])
+def test_gradient_identity_finite_differences(n):
+    # grad (A x^n) = n A x^{n-1}  (Section 3.1)
+    r = _rng(20 + n)
+    A = r.standard_normal(O.num_components(n))
+    x = r.standard_normal(4)
+    h = 1e-6
+    fd = np.array([(O.tensor_apply(A, n, x + h * e) - O.tensor_apply(A, n, x - h * e)) / (2 * h)
+                   for e in np.eye(4)])
+    assert np.allclose(fd, n * O.tensor_apply_nm1(A, n, x), rtol=1e-6, atol=1e-6)
+    hfd = np.array([(O.tensor_apply_nm1(A, n, x + h * e) - O.tensor_apply_nm1(A, n, x - h * e)) / (2 * h)
+                    for e in np.eye(4)]).T * n
+    assert np.allclose(hfd, n * (n - 1) * O.tensor_apply_nm2(A, n, x), rtol=1e-5, atol=1e-5)
+
+
+def _closed_form_moment(alpha):
+    # E_{S^3}[prod Q_i^{2 b_i}] = prod (2 b_i - 1)!! / prod_{k<|b|} (4 + 2k); 0 if an exponent is odd
+    if any(a % 2 for a in alpha):
+        return 0.0
+    b = [a // 2 for a in alpha]
+    num = 1.0
+    for bi in b:
+        for k in range(1, 2 * bi, 2):
+            num *= k
+    den = 1.0
+    for k in range(sum(b)):
+        den *= 4 + 2 * k
+    return num / den
+
+
+def test_closed_form_moments_sanity():
+    assert _closed_form_moment((2, 0, 0, 0)) == pytest.approx(0.25)
+    assert _closed_form_moment((4, 0, 0, 0)) == pytest.approx(1 / 8)
+    assert _closed_form_moment((2, 2, 0, 0)) == pytest.approx(1 / 24)
+    assert _closed_form_moment((6, 0, 0, 0)) == pytest.approx(5 / 64)
+    # Monte Carlo cross-check of the formula
+    q = synth.random_quaternions(_rng(3), 400000)
+    assert np.mean(q[:, 1] ** 2 * q[:, 2] ** 2) == pytest.approx(1 / 24, rel=0.03)
+    # the binary octahedral group is a 7-design: group averages equal the moments
+    g = synth.binary_octahedral()
+    for n in (2, 4, 6):
+        mono = O.monomials(g, n).mean(axis=0)
+        ref = np.array([_closed_form_moment(tuple(a)) for a in O.multi_indices(n)])
+        assert np.allclose(mono, ref, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# quaternions and rotations (Section 2)
+# --------------------------------------------------------------------------
+
+def test_quaternion_matrix_is_hamilton_conjugation():
+    r = _rng(5)
+    for _ in range(10):
+        q = r.standard_normal(4)
+        q /= np.linalg.norm(q)
+        v = r.standard_normal(3)
+        qc = q * np.array([1, -1, -1, -1])
+        rv = O.quat_mul(O.quat_mul(q, np.concatenate([[0.0], v])), qc)
+        R = O.quat_to_matrix(q)
+        assert abs(rv[0]) < 1e-13
+        assert np.allclose(R @ v, rv[1:], atol=1e-13)
+        assert np.allclose(R @ R.T, np.eye(3), atol=1e-13)
+        assert np.linalg.det(R) == pytest.approx(1.0)
+        p = r.standard_normal(4)
+        p /= np.linalg.norm(p)
+        assert np.allclose(O.quat_to_matrix(O.quat_mul(p, q)), O.quat_to_matrix(p) @ R, atol=1e-13)
+    # unit quaternion inner product is Re(y^-1 x) (Section 2, eq. producto2)
+    x, y = r.standard_normal(4), r.standard_normal(4)
+    x /= np.linalg.norm(x)
+    y /= np.linalg.norm(y)
+    yinv = y * np.array([1, -1, -1, -1])
+    assert O.quat_mul(yinv, x)[0] == pytest.approx(float(np.dot(x, y)))
+
+
+def test_rotation_about_axis0_is_numpy_rot90():
+    L = 9                             # odd: the centre L//2 is the array centre
+    t = _rng(6).standard_normal((L, L, L))
+    q = np.array([math.cos(math.pi / 4), math.sin(math.pi / 4), 0, 0])
+    got = O.rotate_trilinear(t, q)
+    assert np.allclose(got, np.rot90(t, 1, axes=(1, 2)), atol=1e-12)
+
+
+def test_rotation_composition_on_exact_grid_rotations():
+    # t_{R1 R2} = (t_{R2})_{R1}  (Section 2, composition of rotations)
+    L = 10
+    t = _rng(7).standard_normal((L, L, L))
+    g = synth.binary_octahedral()
+    r = _rng(8)
+    for _ in range(6):
+        q1, q2 = g[r.integers(len(g))], g[r.integers(len(g))]
+        lhs = O.rotate_trilinear(t, O.quat_mul(q1, q2))
+        rhs = O.rotate_trilinear(O.rotate_trilinear(t, q2), q1)
+        # a 90-degree rotation about the centre can move part of an even box out of it
+        keep = (np.abs(O.rotate_trilinear(np.ones_like(t), O.quat_mul(q1, q2)) - 1) < 1e-12) & \
+               (np.abs(O.rotate_trilinear(O.rotate_trilinear(np.ones_like(t), q2), q1) - 1) < 1e-12)
+        assert keep.sum() > 0.5 * t.size
+        assert np.allclose(lhs[keep], rhs[keep], atol=1e-12)
+
+
+def test_trilinear_reproduces_linear_functions():
+    # trilinear interpolation is exact for affine functions away from the border
+    L = 12
+    ax = np.arange(L, dtype=np.float64)
+    g = np.meshgrid(ax, ax, ax, indexing="ij")
+    coef = np.array([0.3, -1.1, 0.7])
+    t = 2.0 + coef[0] * g[0] + coef[1] * g[1] + coef[2] * g[2]
+    q = synth.random_quaternions(_rng(9), 1)[0]
+    got = O.rotate_trilinear(t, q)
+    c = L // 2
+    R = O.quat_to_matrix(q)
+    u = np.stack(g, axis=-1) - c
+    p = u @ R + c                                  # c + R^-1 (u - c)
+    inside = np.all((p >= 0) & (p <= L - 1), axis=-1)
+    expect = 2.0 + p @ coef
+    assert inside.sum() > 100
+    assert np.allclose(got[inside], expect[inside], atol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# correlation and local normalisation (Section 2)
+# --------------------------------------------------------------------------
+
+def _fft_correlation(f, g):
+    """Circular correlation by the library FFT: the template is wrapped so
+    that its centre sits at the origin, then F^-1(F(f) conj F(g))."""
+    N = f.shape
+    L = g.shape
+    c = O.template_centre(L)
+    big = np.zeros(N)
+    for u0 in range(L[0]):
+        for u1 in range(L[1]):
+            for u2 in range(L[2]):
+                big[(u0 - c[0]) % N[0], (u1 - c[1]) % N[1], (u2 - c[2]) % N[2]] += g[u0, u1, u2]
+    return np.real(np.fft.ifftn(np.fft.fftn(f) * np.conj(np.fft.fftn(big))))
+
+
+def test_direct_correlation_equals_fft_and_loops():
+    r = _rng(11)
+    f = r.standard_normal((12, 10, 14))
+    g = r.standard_normal((5, 4, 6))
+    xs = O.all_positions(f.shape)
+    direct = O.correlate_at(f, g, xs).reshape(f.shape)
+    assert np.allclose(direct, _fft_correlation(f, g), atol=1e-11)
+    # a few by explicit loops
+    c = O.template_centre(g.shape)
+    for x in [(0, 0, 0), (5, 3, 7), (11, 9, 13)]:
+        s = 0.0
+        for u0 in range(5):
+            for u1 in range(4):
+                for u2 in range(6):
+                    s += f[(x[0] + u0 - c[0]) % 12, (x[1] + u1 - c[1]) % 10, (x[2] + u2 - c[2]) % 14] * g[u0, u1, u2]
+        assert direct[x] == pytest.approx(s, abs=1e-12)
+
+
+def test_local_norm_two_pass_equals_one_pass_fft():
+    # ||P_S tau_x f||_S^2 = <(tau_x f)^2, m> - <tau_x f, m>^2 / <1, m>   (Section 2)
+    r = _rng(12)
+    f = 3.0 + r.standard_normal((14, 12, 10))
+    m = synth.ball_mask(7, 3.5)
+    m1 = _fft_correlation(f, m)
+    m2 = _fft_correlation(f * f, m)
+    v = m2 - m1 ** 2 / m.sum()
+    xs = O.all_positions(f.shape)
+    w = O.local_norm_at(f, m, xs).reshape(f.shape)
+    assert np.allclose(w, 1.0 / np.sqrt(v), rtol=1e-9)
+
+
+def test_local_norm_constant_window_is_zero():
+    f = np.ones((12, 12, 12))
+    f[0, 0, 0] = 5.0
+    m = synth.ball_mask(4, 2.0)
+    w = O.local_norm_at(f, m, np.array([[6, 6, 6]]))
+    assert w[0] == 0.0
+
+
+# --------------------------------------------------------------------------
+# classical NCC (Theorem "similar", Theorem "ThCTM")
+# --------------------------------------------------------------------------
+
+def _random_setup(seed, N=(14, 14, 14), L=8):
+    r = _rng(seed)
+    f = r.standard_normal(N)
+    t = synth.make_blob_template(r, L, 3, L / 2).grid()
+    m = synth.ball_mask(L, L / 2)
+    return f, t, m
+
+
+def test_ncc_bounded_by_cauchy_schwarz():
+    f, t, m = _random_setup(13)
+    # structured image too, to approach the bound
+    f = f + 3 * np.roll(np.pad(t, 3), 2, axis=0)[:14, :14, :14]
+    quats = synth.random_quaternions(_rng(14), 12)
+    xs = O.all_positions(f.shape)
+    c = O.classical_ncc_at(f, t, m, quats, xs)
+    assert np.all(np.abs(c) <= 1.0 + 1e-12)
+    assert np.abs(c).max() > 0.3
+
+
+def test_ncc_is_one_at_noiseless_copy_and_affine_invariant():
+    f, t, m = _random_setup(15)
+    # radius 3 keeps every rotated sample inside the 8-box, where adding a
+    # constant to t commutes with zero-filled resampling
+    m = synth.ball_mask(t.shape[0], 3.0)
+    q = synth.random_quaternions(_rng(16), 1)[0]
+    s = O.rotated_template(t, m, q)
+    L = t.shape[0]
+    c = L // 2
+    x0 = np.array([7, 6, 8])
+    g = f.copy()
+    sl = tuple(slice(x0[i] - c, x0[i] - c + L) for i in range(3))
+    inside = m > 0
+    win = g[sl]
+    win[inside] = 2.5 * s[inside] - 1.25            # alpha s + beta inside the mask
+    g[sl] = win
+    val = O.classical_ncc_at(g, t, m, q[None], x0[None])[0, 0]
+    assert val == pytest.approx(1.0, abs=1e-12)
+    xs = O.all_positions(g.shape)[::7]
+    base = O.classical_ncc_at(g, t, m, q[None], xs)
+    # f -> a f + b, t -> d t + e: unchanged if a d > 0, negated if a d < 0
+    same = O.classical_ncc_at(3.0 * g + 2.0, 0.5 * t - 7.0, m, q[None], xs)
+    flip = O.classical_ncc_at(-3.0 * g + 2.0, 0.5 * t + 1.0, m, q[None], xs)
+    assert np.allclose(same, base, atol=1e-10)
+    assert np.allclose(flip, -base, atol=1e-10)
+
+
+def test_classical_argmax_finds_planted_rotation():
+    f, t, m = _random_setup(17)
+    quats = synth.random_quaternions(_rng(18), 20)
+    k = 13
+    s = O.rotated_template(t, m, quats[k])
+    L = t.shape[0]
+    x0 = np.array([7, 7, 7])
+    sl = tuple(slice(x0[i] - L // 2, x0[i] - L // 2 + L) for i in range(3))
+    win = f[sl]
+    win[m > 0] = s[m > 0]
+    f[sl] = win
+    best, idx = O.classical_best_at(f, t, m, quats, x0[None])
+    assert idx[0] == k and best[0] == pytest.approx(1.0, abs=1e-12)
+
+
+# --------------------------------------------------------------------------
+# tensor template and tensor field (Sections 3.2-3.4)
+# --------------------------------------------------------------------------
+
+def test_rotation_invariant_template_gives_degenerate_tensor():
+    # A template invariant under the cube rotations, integrated with the binary
+    # octahedral group (a 7-design), gives T_alpha = E[Q^alpha] s exactly.
+    L = 10
+    c = L // 2
+    ax = np.arange(L) - c
+    g = np.meshgrid(ax, ax, ax, indexing="ij")
+    rad2 = g[0] ** 2 + g[1] ** 2 + g[2] ** 2
+    t = np.exp(-rad2 / 6.0) + 0.3 * np.cos(rad2 / 3.0)
+    m = synth.ball_mask(L, 4.5)
+    quats = synth.binary_octahedral()
+    w = np.full(len(quats), 1.0 / len(quats))
+    s = O.rotated_template(t, m, np.array([1.0, 0, 0, 0]))
+    for n in (2, 4, 6):
+        T = O.tensor_template(t, m, n, quats, w)
+        M = np.array([_closed_form_moment(tuple(a)) for a in O.multi_indices(n)])
+        assert np.allclose(T, M[:, None, None, None] * s[None], atol=1e-12)
+        # then phi(Q) = C Q^n is the same for every unit Q
+        A = M * 0.37
+        vals = [O.tensor_apply(A, n, q) for q in synth.random_quaternions(_rng(n), 5)]
+        assert np.allclose(vals, vals[0], atol=1e-14)
+
+
+def test_tensor_field_is_integral_of_classical_ncc():
+    # C_n(x) = int R^{(.)n} c(x,R) dR  (Section 3.2), exactly on any quadrature;
+    # and phi(Q) = C_n(x) Q^n = int (Q.R)^n c(x,R) dR (proof of Theorem "main")
+    f, t, m = _random_setup(19)
+    n = 4
+    quats = synth.random_quaternions(_rng(20), 30)
+    wts = _rng(21).uniform(0.5, 1.5, len(quats))
+    wts /= wts.sum()
+    T = O.tensor_template(t, m, n, quats, wts)
+    xs = np.array([[7, 7, 7], [5, 9, 6], [8, 4, 10]])
+    C = O.tensor_field_at(f, T, m, xs)
+    c = O.classical_ncc_at(f, t, m, quats, xs)
+    ref = c @ (wts[:, None] * O.monomials(quats, n))
+    assert np.allclose(C, ref, atol=1e-13)
+    Q = synth.random_quaternions(_rng(22), 3)
+    for p in range(len(xs)):
+        for q in Q:
+            lhs = O.tensor_apply(C[p], n, q)
+            rhs = float(np.sum(wts * (quats @ q) ** n * c[p]))
+            assert lhs == pytest.approx(rhs, abs=1e-13)
+
+
+def test_spectral_norm_bound():
+    # ||T||_sigma >= ||T||_F / 2^{n-1}, ||T||_sigma = max |T Q^n|  (Section 3.4)
+    for n in (2, 4, 6):
+        for seed in range(4):
+            A = _rng(30 + seed).standard_normal(O.num_components(n))
+            pts = O.oracle_sphere_points(20000)
+            vals = O.monomials(pts, n) @ (O.multiplicities(n) * A)
+            assert np.abs(vals).max() >= O.frobenius_norm(A, n) / 2 ** (n - 1)
+
+
+def test_sshopm_reaches_brute_force_maximum():
+    for n in (2, 4, 6):
+        A = _rng(40 + n).standard_normal(O.num_components(n))
+        q, lam, _ = O.dominant_z_eigenpair(A, n, n_brute=50000)
+        pts = O.oracle_sphere_points(50000)
+        vals = O.monomials(pts, n) @ (O.multiplicities(n) * A)
+        assert lam >= vals.max() - 1e-12
+        # a Z-eigenpair: A q^{n-1} = lambda q
+        assert np.allclose(O.tensor_apply_nm1(A, n, q), lam * q, atol=1e-8)
+        if n == 2:
+            # order 2: the dominant Z-eigenvalue is the top matrix eigenvalue
+            assert lam == pytest.approx(np.linalg.eigvalsh(O.unpack_symmetric(A, 2))[-1], abs=1e-10)
+
+
+def test_theorem_main_recovers_planted_rotation():
+    # a noiseless analytic copy at x0 rotated by R*: phi peaks at R* (Theorem "main")
+    # the quadrature must resolve c(x, R) over SO(3): 10^4 rotations (~5 degree
+    # spacing) bring the recovered pose within a fraction of a degree
+    L, n = 12, 4
+    tm = synth.make_blob_template(_rng(50), L, 5, L / 2)
+    t = tm.grid()
+    m = synth.ball_mask(L, L / 2)
+    qs = synth.super_fibonacci(10000)
+    wts = np.full(len(qs), 1.0 / len(qs))
+    T = O.tensor_template(t, m, n, qs, wts)
+    errs = []
+    for k, qtrue in enumerate(synth.random_quaternions(_rng(51), 3)):
+        x0 = np.array([[12, 12, 12]])
+        f = synth.render_copies((24, 24, 24), tm, x0, qtrue[None])
+        C = O.tensor_field_at(f, T, m, x0)[0]
+        q, lam, second = O.dominant_z_eigenpair(C, n, n_brute=60000)
+        errs.append(O.rotation_angle_deg(q, qtrue))
+    assert max(errs) < 1.0, errs
+
+
+# --------------------------------------------------------------------------
+# candidate positions
+# --------------------------------------------------------------------------
+
+def test_find_peaks_hand_made():
+    F = np.zeros((12, 12, 12))
+    F[4, 4, 4] = 5.0
+    F[4, 4, 5] = 4.0          # neighbour of a larger value: not a local max
+    F[8, 8, 8] = 3.0
+    F[4, 8, 4] = 5.0          # tie with (4,4,4): lower linear index first
+    F[5, 5, 7] = 2.0          # within distance 4 of (4,4,4): suppressed
+    F[1, 1, 1] = 9.0          # outside the valid region for L=4
+    got = O.find_peaks(F, (4, 4, 4), 0.5, 4.0, 10)
+    assert [tuple(p) for p in got] == [(4, 4, 4), (4, 8, 4), (8, 8, 8)]
+    got = O.find_peaks(F, (4, 4, 4), 3.5, 4.0, 10)
+    assert [tuple(p) for p in got] == [(4, 4, 4), (4, 8, 4)]
+    got = O.find_peaks(F, (4, 4, 4), 0.5, 4.0, 1)
+    assert [tuple(p) for p in got] == [(4, 4, 4)]
+    # plateaus (equal neighbours) are not strict maxima
+    F2 = np.zeros((10, 10, 10))
+    F2[5, 5, 5] = F2[5, 5, 6] = 1.0
+    assert len(O.find_peaks(F2, (4, 4, 4), 0.1, 2.0, 10)) == 0
+
+
+def test_find_peaks_fast_matches_loops():
+    r = _rng(60)
+    F = r.random((14, 13, 12))
+    for thr, d in [(0.5, 3.0), (0.9, 5.0), (0.0, 1.0)]:
+        a = O.find_peaks(F, (5, 4, 6), thr, d, 7)
+        b = O.find_peaks_fast(F, (5, 4, 6), thr, d, 7)
+        assert np.array_equal(a, b)
