@@ -1,0 +1,229 @@
+/*
+ * ttm.h -- C ABI of libttm, an MI355X (gfx950) implementation of tensorial
+ * template matching (TTM) and of classical rotation-sampled normalised
+ * cross-correlation (TM), after Almira, Phelippeau, Martinez-Sanchez, "Fast
+ * Normalized Cross-Correlation for Template Matching with Rotations"
+ * (arXiv 2311.07561).
+ *
+ * General rules for every entry point
+ * ------------------------------------
+ * - Volumes are C-order float32 arrays [n0][n1][n2] (n2 fastest); the voxel
+ *   (i0,i1,i2) is the point u = (i0,i1,i2).  Templates and masks are [L0][L1][L2]
+ *   with their centre at the integer voxel c = (L0/2, L1/2, L2/2) (floor).
+ * - Pointers are DEVICE pointers unless the argument name ends in "_host".
+ *   The caller owns all memory: the library never allocates, frees or keeps a
+ *   pointer after a call returns.  Scratch memory is a caller-provided
+ *   workspace of at least the size the matching *_workspace_bytes call returns
+ *   (256-byte alignment or better).
+ * - Every call is asynchronous on `stream`: arguments are validated on the
+ *   host before anything is enqueued, and a non-OK status means nothing was
+ *   enqueued (TTM_E_HIP: a launch failed part-way; the stream's work is then
+ *   undefined).  Host arrays are only read during the call.
+ * - Correlation is circular: (f * g)(x) = sum_u f((x + u - c) mod N) g(u)
+ *   (Section 2, eq. "correlation", with the template measured from its
+ *   centre).  Outputs are defined in the VALID region, the positions whose
+ *   window [x - c, x - c + L) lies inside the volume on every axis; every
+ *   per-voxel output is 0 outside it (indices -1).
+ * - The SSP operator is the paper's practical one with an identity filter:
+ *   S(f) = m . f for the given mask m (Section 2, lemma "opSSP" with h = delta).
+ * - Supported FFT lengths: every axis of N must satisfy
+ *   ttm_supported_length() (powers of two from 16 to 512).
+ * - No C++ exception crosses this interface.
+ */
+#ifndef TTM_H
+#define TTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TTM_OK = 0,
+  TTM_E_ARG = -1,        /* a pointer, order, count or option is invalid       */
+  TTM_E_SIZE = -2,       /* a dimension is unsupported or inconsistent         */
+  TTM_E_WORKSPACE = -3,  /* the workspace is NULL or smaller than required     */
+  TTM_E_HIP = -4,        /* a HIP launch or call failed                        */
+  TTM_E_NONFINITE = -5   /* reserved: non-finite input detected                */
+} ttm_status;
+
+typedef struct {
+  int32_t n0, n1, n2;    /* extents, C order, n2 fastest */
+} ttm_dims;
+
+/* Options for correlation, peak picking and pose recovery. */
+typedef struct {
+  float eps_v;           /* w(x) = 0 where the local masked variance v(x) is
+                            <= eps_v * m_sum * var(f); default 1e-5            */
+  float threshold;       /* peak candidates need F(x) > threshold (>= 0)       */
+  float min_dist;        /* greedy suppression radius between peaks (voxels)   */
+  int32_t max_peaks;     /* at most this many peaks (1..4096)                  */
+  int32_t n_seeds;       /* S^3 seed points scanned before SS-HOPM (64..65536) */
+  int32_t hopm_max_iter; /* SS-HOPM iteration cap                              */
+  double hopm_tol;       /* stop when |d lambda| <= tol * max(1, |lambda|)     */
+} ttm_options;
+
+/* Pose flags (bit set in out_flags). */
+#define TTM_POSE_NOT_CONVERGED 1   /* SS-HOPM hit hopm_max_iter               */
+#define TTM_POSE_ZERO_NORM     2   /* w(x) = 0 at the peak: pose undefined    */
+#define TTM_PEAKS_TRUNCATED    4   /* the candidate list overflowed; fewer
+                                      than max_peaks may have been accepted   */
+
+/* Fills *opt with the defaults (eps_v 1e-5, threshold 0, min_dist 8,
+ * max_peaks 64, n_seeds 4096, hopm_max_iter 1000, hopm_tol 1e-12). */
+void ttm_default_options(ttm_options* opt);
+
+/* Number of independent components of a symmetric tensor of order n on R^4:
+ * C(n+3, 3) (Section 3.1).  Returns TTM_E_ARG for odd n or n < 2 (the main
+ * theorem needs an even order, Section 3.3) and for n > 8. */
+int32_t ttm_num_components(int32_t order_n);
+
+/* 1 if an FFT axis of this length is supported, else 0. */
+int32_t ttm_supported_length(int32_t n);
+
+/* Human-readable name of a status code (static storage). */
+const char* ttm_status_string(int32_t status);
+
+/* ---------------------------------------------------------------------------
+ * Tensor template (Section 3.2): T(z) = int_SO(3) R^{(.)n} S(t)_R(z) dR, in
+ * packed form T_alpha(u) = sum_j omega_j Q_j^alpha s_j(u), where s_j is the raw
+ * template rotated by Q_j (t_R(u) = t(c + R^-1 (u - c)), trilinear, zero
+ * outside the box) and then normalised under the mask
+ * (s = m (g - <g,m>/m_sum) / sqrt(<g^2,m> - <g,m>^2/m_sum), Algorithm 1).
+ * Packed order of alpha (|alpha| = n): alpha1 from n down to 0, then alpha2,
+ * then alpha3; alpha4 is the remainder.  Q = (a,b,c,d) = a + bi + cj + dk,
+ * active Hamilton rotation, vector part on axes (0,1,2).
+ *
+ *   tmpl, mask        [L0][L1][L2] float32; mask values >= 0 with m_sum > 0
+ *   order_n           even, 2..8; K = ttm_num_components(order_n)
+ *   quats_host        n_rot x 4 float32 unit quaternions (normalised here)
+ *   weights_host      n_rot float64 quadrature weights, sum = 1 (+-1e-6)
+ *   out_components    K x [L0][L1][L2] float32 (written)
+ *   N, out_bank       optional: the correlation bank for images of extent N
+ *                     (ttm_bank_bytes(N, L, K) bytes, opaque); NULL = skip
+ *
+ * The bank holds the K components and the mask, each transformed along axes
+ * 2 and 1 (an R2C then a C2C FFT of the zero-padded [L0][n1][n2/2+1] block); it
+ * is built once per template and image extent and read by ttm_correlate.
+ * Errors: TTM_E_ARG (NULL, odd order, n_rot < 1, a zero or non-finite
+ * quaternion, weights not summing to 1 within 1e-6), TTM_E_SIZE (L larger than
+ * N, unsupported N), TTM_E_WORKSPACE, TTM_E_HIP.  The mask must have a positive
+ * sum; a rotation under which the template has zero masked variance (or a
+ * zero mask) contributes nothing to the components.
+ * ------------------------------------------------------------------------- */
+size_t ttm_bank_bytes(ttm_dims N, ttm_dims L, int32_t K);
+size_t ttm_build_workspace_bytes(ttm_dims L, int32_t order_n, int32_t n_rot,
+                                 ttm_dims N);
+ttm_status ttm_build_tensor_template(
+    const float* tmpl, const float* mask, ttm_dims L, int32_t order_n,
+    const float* quats_host, const double* weights_host, int32_t n_rot,
+    float* out_components, ttm_dims N, void* out_bank,
+    void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Correlation (Sections 2, 3.2, 3.4): for every valid voxel x
+ *   w(x)      = 1 / ||P_S tau_x f||_S
+ *             = 1 / sqrt(<(tau_x f)^2, m> - <tau_x f, m>^2 / m_sum)
+ *               (0 where v(x) <= eps_v m_sum var(f))
+ *   C_alpha(x)= w(x) <tau_x f, T_alpha>            (the correlated tensor field)
+ *   F(x)      = ||C_n(x)||_F = sqrt(sum_alpha mu_alpha C_alpha(x)^2),
+ *               mu_alpha = n!/prod(alpha_i!)       (Frobenius position proxy)
+ * Path: image mean shift (allowed by the affine invariance of Theorem "ThCTM"),
+ * R2C FFT of f and f^2, K+2 spectral products fanned out from one read of the
+ * image spectrum, batched C2R inverse FFTs, local normalisation and score
+ * fused into the last inverse pass.  All arithmetic in float32 except the
+ * image moments and the variance subtraction (float64).
+ *
+ *   image      [n0][n1][n2] float32
+ *   bank       from ttm_build_tensor_template with the same N, L, order
+ *   mask       [L0][L1][L2] float32, the mask used to build the bank
+ *   opt        options (eps_v is used)
+ *   out_score  [n0][n1][n2] float32 F(x) (written)
+ *   out_w      [n0][n1][n2] float32 w(x), or NULL
+ * Errors: TTM_E_ARG, TTM_E_SIZE, TTM_E_WORKSPACE, TTM_E_HIP.
+ * ------------------------------------------------------------------------- */
+size_t ttm_correlate_workspace_bytes(ttm_dims N, ttm_dims L, int32_t K);
+ttm_status ttm_correlate(
+    const float* image, ttm_dims N, const void* bank, ttm_dims L,
+    int32_t order_n, const float* mask, const ttm_options* opt,
+    float* out_score, float* out_w, void* ws, size_t ws_bytes,
+    hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Position and rotation recovery (Sections 3.3, 3.4).
+ * Peaks: valid voxels with F(x) > threshold and F(x) strictly greater than all
+ * 26 neighbours, ordered by F descending (ties: lower linear index first),
+ * greedily suppressed within min_dist of an accepted peak, at most max_peaks.
+ * At each peak the tensor C_n(x) is recomputed directly in float64 from the
+ * image window and the components (two-pass local variance), and its dominant
+ * Z-eigenpair (max C Q^n on |Q| = 1, eq. "Zeigen") is found by a scan of
+ * n_seeds S^3 points followed by SS-HOPM from the 4 best (adaptive shift); by
+ * Theorem "main" the eigenvector is the rotation of the match.
+ *
+ *   score            [n0][n1][n2] float32 from ttm_correlate
+ *   image            the correlated image; components: K x [L0][L1][L2] float32
+ *   mask             the mask used for the components
+ *   out_pos          max_peaks x 3 int32 (i0,i1,i2)
+ *   out_quat         max_peaks x 4 float32, canonical (a > 0)
+ *   out_lambda       max_peaks float64 dominant Z-eigenvalue C Q^n
+ *   out_peak_score   max_peaks float32 F at the peak
+ *   out_flags        max_peaks int32 TTM_POSE_* bits
+ *   out_C            max_peaks x K float64 C_alpha at the peak, or NULL
+ *   out_count        2 int32: [0] number of peaks written, [1] flags
+ *                    (TTM_PEAKS_TRUNCATED when the bounded candidate list ran
+ *                    out before max_peaks peaks were accepted)
+ * Only the first out_count[0] rows are defined.  The mask must have a
+ * positive sum (otherwise w = 0 and every pose is flagged TTM_POSE_ZERO_NORM).
+ * ------------------------------------------------------------------------- */
+size_t ttm_pose_workspace_bytes(ttm_dims N, ttm_dims L, int32_t order_n,
+                                const ttm_options* opt);
+ttm_status ttm_recover_pose(
+    const float* score, const float* image, const float* components,
+    const float* mask, ttm_dims N, ttm_dims L, int32_t order_n,
+    const ttm_options* opt, int32_t* out_pos, float* out_quat,
+    double* out_lambda, float* out_peak_score, int32_t* out_flags,
+    double* out_C, int32_t* out_count, void* ws, size_t ws_bytes,
+    hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Classical template matching with rotations (Algorithm 1 with a loop over
+ * the rotation list): for every valid voxel
+ *   out_best_ncc(x) = max_j c(x, R_j),  c(x,R) = w(x) (f * s_R)(x)
+ *   out_best_rot(x) = lowest j attaining the maximum
+ * with s_R the rotated-then-normalised template as in the tensor build.
+ * Where w(x) = 0 every c is 0 and the index is 0.
+ *
+ *   image [n0][n1][n2]; tmpl, mask [L0][L1][L2]; quats_host n_rot x 4 float32
+ * Errors: TTM_E_ARG, TTM_E_SIZE, TTM_E_WORKSPACE, TTM_E_HIP.
+ * ------------------------------------------------------------------------- */
+size_t tm_classical_workspace_bytes(ttm_dims N, ttm_dims L, int32_t n_rot);
+ttm_status tm_classical(
+    const float* image, ttm_dims N, const float* tmpl, const float* mask,
+    ttm_dims L, const float* quats_host, int32_t n_rot,
+    const ttm_options* opt, float* out_best_ncc, int32_t* out_best_rot,
+    void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Instrumentation (not part of the method).  When enabled, every call records
+ * a HIP event pair on its stream around each kernel group, by class:
+ *   0 image moments, 1 axis-2 R2C rows, 2 axis-1 forward pencils,
+ *   3 pass 1 (axis-0 fan-out), 4 axis-1 inverse pencils, 5 pass 3 (axis-2 C2R
+ *   + reduction), 6 peaks, 7 pose, 8 tensor build, 9 classical epilogue.
+ * ttm_profile_read waits for the recorded events, writes the summed
+ * milliseconds and launch counts of the first n classes, clears the record
+ * and returns the number of classes (or TTM_E_HIP).  Event pairs are created
+ * on first use and reused; with profiling off nothing is recorded.
+ * ------------------------------------------------------------------------- */
+#define TTM_PROFILE_CLASSES 10
+void ttm_profile_enable(int32_t on);
+int32_t ttm_profile_read(double* ms_out, int64_t* launches_out, int32_t n);
+const char* ttm_profile_class_name(int32_t cls);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTM_H */

@@ -1,0 +1,462 @@
+// The extern "C" entry points of libttm: argument validation on the host,
+// workspace carving, and the launch sequence of each call (all asynchronous on
+// the caller's stream).
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "ttm_internal.h"
+
+namespace ttm {
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures.  Every block is 256-byte aligned.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+  size_t size() const { return (off + 255) & ~size_t(255); }
+};
+
+static bool dims_ok(const ttm_dims& d) { return d.n0 > 0 && d.n1 > 0 && d.n2 > 0; }
+static bool image_dims_ok(const ttm_dims& N) {
+  return supported_len(N.n0) && supported_len(N.n1) && supported_len(N.n2);
+}
+static bool fits(const ttm_dims& L, const ttm_dims& N) {
+  return L.n0 <= N.n0 && L.n1 <= N.n1 && L.n2 <= N.n2;
+}
+
+static Geo make_geo(const ttm_dims& N, const ttm_dims& L) {
+  Geo g;
+  g.n0 = N.n0; g.n1 = N.n1; g.n2 = N.n2; g.h2 = N.n2 / 2 + 1;
+  g.L0 = L.n0; g.L1 = L.n1; g.L2 = L.n2;
+  g.c0 = L.n0 / 2; g.c1 = L.n1 / 2; g.c2 = L.n2 / 2;
+  return g;
+}
+
+#define TTM_TRY(expr)                         \
+  do {                                        \
+    if ((expr) != hipSuccess) return TTM_E_HIP; \
+  } while (0)
+
+// ---- optional event-pair instrumentation --------------------------------------
+enum ProfClass { PC_STATS = 0, PC_ROWS, PC_PEN_FWD, PC_PASS1, PC_PEN_INV, PC_PASS3, PC_PEAKS, PC_POSE,
+                 PC_BUILD, PC_EPI, PC_COUNT };
+static const char* kProfNames[PC_COUNT] = {"image_moments", "r2c_rows", "pencils_fwd", "pass1_fanout",
+                                           "pencils_inv", "pass3_c2r_reduce", "peaks", "pose",
+                                           "tensor_build", "classical_epilogue"};
+struct Prof {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  std::vector<std::pair<int, int>> used;   // (class, pool index)
+};
+static Prof& prof() {
+  static Prof p;
+  return p;
+}
+// RAII: records the start event on construction and the stop event on
+// destruction (both on stream s) when profiling is on.
+struct ProfScope {
+  int idx = -1;
+  hipStream_t s;
+  ProfScope(int cls, hipStream_t st) : s(st) {
+    Prof& p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    if (!p.on) return;
+    if (p.used.size() == p.pool.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+      p.pool.emplace_back(a, b);
+    }
+    idx = (int)p.used.size();
+    p.used.emplace_back(cls, idx);
+    (void)hipEventRecord(p.pool[idx].first, s);
+  }
+  ~ProfScope() {
+    if (idx < 0) return;
+    Prof& p = prof();
+    std::lock_guard<std::mutex> g(p.mu);
+    (void)hipEventRecord(p.pool[idx].second, s);
+  }
+};
+#define TTM_PROF(cls, expr)                  \
+  do {                                       \
+    ProfScope _ps(cls, stream);              \
+    TTM_TRY(expr);                           \
+  } while (0)
+
+// ---- layouts ----------------------------------------------------------------
+struct BuildWs {
+  float* quats; double* weights; double* rstats; double* coef;
+};
+static BuildWs build_layout(Carve& c, int nrot, int K) {
+  BuildWs w;
+  w.quats = c.take<float>((size_t)nrot * 4);
+  w.weights = c.take<double>((size_t)nrot);
+  w.rstats = c.take<double>((size_t)nrot * 2);
+  w.coef = c.take<double>((size_t)nrot * K);
+  return w;
+}
+
+struct CorrWs {
+  float2* Xf; float2* Xg; float2* H; double* stats; double* partials; float* mu;
+};
+static CorrWs corr_layout(Carve& c, const Geo& g, int K) {
+  CorrWs w;
+  w.Xf = c.take<float2>(g.half());
+  w.Xg = c.take<float2>(g.half());
+  w.H = c.take<float2>(g.half() * (size_t)(K + 2));
+  w.stats = c.take<double>(4);
+  w.partials = c.take<double>(2 * 512);
+  w.mu = c.take<float>(kMaxK);
+  return w;
+}
+
+struct PoseWs {
+  unsigned* hist; unsigned* ctrl; unsigned long long* cand; double* stats; double* partials;
+};
+static PoseWs pose_layout(Carve& c) {
+  PoseWs w;
+  w.hist = c.take<unsigned>(kHistBins);
+  w.ctrl = c.take<unsigned>(4);
+  w.cand = c.take<unsigned long long>(kCandCap);
+  w.stats = c.take<double>(4);
+  w.partials = c.take<double>(2 * 512);
+  return w;
+}
+
+constexpr int kClassicalBatch = 32;
+struct ClassWs {
+  float* quats; double* rstats; float2* Xf; float2* Xg; float2* H; float* tbatch; float2* bbank;
+  float* w; double* stats; double* partials;
+};
+static ClassWs class_layout(Carve& c, const Geo& g, int nrot) {
+  ClassWs w;
+  const int B = nrot < kClassicalBatch ? nrot : kClassicalBatch;
+  const int nH = B > 2 ? B : 2;
+  const size_t L3 = (size_t)g.L0 * g.L1 * g.L2;
+  w.quats = c.take<float>((size_t)nrot * 4);
+  w.rstats = c.take<double>((size_t)nrot * 2);
+  w.Xf = c.take<float2>(g.half());
+  w.Xg = c.take<float2>(g.half());
+  w.H = c.take<float2>(g.half() * (size_t)nH);
+  w.tbatch = c.take<float>(L3 * (size_t)(B > 1 ? B : 1));
+  w.bbank = c.take<float2>(g.bank_slab() * (size_t)(B > 1 ? B : 1));
+  w.w = c.take<float>(g.vol());
+  w.stats = c.take<double>(4);
+  w.partials = c.take<double>(2 * 512);
+  return w;
+}
+
+// forward axis-2 and axis-1 transforms of the image and of its square
+static ttm_status image_forward(const Geo& g, const float* image, float2* Xf, float2* Xg,
+                                double* stats, double* partials, const float* mask, hipStream_t stream) {
+  const long L3 = (long)g.L0 * g.L1 * g.L2;
+  const long rows = (long)g.n0 * g.n1;
+  TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), partials, stats, stream));
+  TTM_PROF(PC_STATS, launch_mask_sum(mask, L3, stats + 2, stream));
+  TTM_PROF(PC_ROWS, launch_r2c_rows(g.n2, image, g.n2, g.n2, rows, Xf, Xg, rows, 0, 1, stats, stream));
+  TTM_PROF(PC_PEN_FWD, launch_pencils(g.n1, false, Xf, (long)g.n0 * g.h2, g.h2, (long)g.n1 * g.h2, g.h2, g.n1,
+                                      0, 2, (long)(Xg - Xf), stream));
+  return TTM_OK;
+}
+
+// bank entries for nent real [L0][L1][L2] blocks: rows R2C then axis-1 forward
+static ttm_status bank_forward(const Geo& g, const float* src, int nent, float2* bank, hipStream_t stream) {
+  const long rows = (long)nent * g.L0 * g.L1;
+  TTM_PROF(PC_ROWS, launch_r2c_rows(g.n2, src, g.L2, g.L2, rows, bank, nullptr, g.L1, g.n1, 0, nullptr, stream));
+  TTM_PROF(PC_PEN_FWD, launch_pencils(g.n1, false, bank, (long)nent * g.L0 * g.h2, g.h2, (long)g.n1 * g.h2,
+                                      g.h2, g.L1, 0, 1, 0, stream));
+  return TTM_OK;
+}
+
+#define TTM_CALL(expr)                     \
+  do {                                     \
+    const ttm_status _st = (expr);         \
+    if (_st != TTM_OK) return _st;         \
+  } while (0)
+
+}  // namespace ttm
+
+using namespace ttm;
+
+extern "C" {
+
+void ttm_default_options(ttm_options* o) {
+  if (!o) return;
+  o->eps_v = 1e-5f;
+  o->threshold = 0.0f;
+  o->min_dist = 8.0f;
+  o->max_peaks = 64;
+  o->n_seeds = 4096;
+  o->hopm_max_iter = 1000;
+  o->hopm_tol = 1e-12;
+}
+
+int32_t ttm_num_components(int32_t n) {
+  if (n < 2 || n > kMaxOrder || (n & 1)) return TTM_E_ARG;
+  return num_components(n);
+}
+
+int32_t ttm_supported_length(int32_t n) { return supported_len(n) ? 1 : 0; }
+
+const char* ttm_status_string(int32_t s) {
+  switch (s) {
+    case TTM_OK: return "TTM_OK";
+    case TTM_E_ARG: return "TTM_E_ARG: invalid argument";
+    case TTM_E_SIZE: return "TTM_E_SIZE: unsupported or inconsistent size";
+    case TTM_E_WORKSPACE: return "TTM_E_WORKSPACE: workspace missing or too small";
+    case TTM_E_HIP: return "TTM_E_HIP: HIP launch failed";
+    case TTM_E_NONFINITE: return "TTM_E_NONFINITE: non-finite input";
+    default: return "unknown status";
+  }
+}
+
+size_t ttm_bank_bytes(ttm_dims N, ttm_dims L, int32_t K) {
+  if (!dims_ok(N) || !dims_ok(L) || K < 1) return 0;
+  return (size_t)(K + 1) * L.n0 * N.n1 * (N.n2 / 2 + 1) * sizeof(float2);
+}
+
+size_t ttm_build_workspace_bytes(ttm_dims L, int32_t order_n, int32_t n_rot, ttm_dims N) {
+  (void)L; (void)N;
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || n_rot < 1) return 0;
+  Carve c(nullptr);
+  build_layout(c, n_rot, K);
+  return c.size();
+}
+
+ttm_status ttm_build_tensor_template(const float* tmpl, const float* mask, ttm_dims L, int32_t order_n,
+                                     const float* quats_host, const double* weights_host, int32_t n_rot,
+                                     float* out_components, ttm_dims N, void* out_bank, void* ws,
+                                     size_t ws_bytes, hipStream_t stream) {
+  if (!tmpl || !mask || !quats_host || !weights_host || !out_components) return TTM_E_ARG;
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || n_rot < 1) return TTM_E_ARG;
+  if (!dims_ok(L) || L.n2 > 512) return TTM_E_SIZE;
+  if ((long)L.n0 * L.n1 * L.n2 > (1L << 24)) return TTM_E_SIZE;
+  double wsum = 0.0;
+  for (int j = 0; j < n_rot; ++j) {
+    const float* q = quats_host + 4 * j;
+    const double nq = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3];
+    if (!std::isfinite(nq) || nq <= 0.0) return TTM_E_ARG;
+    if (!std::isfinite(weights_host[j])) return TTM_E_ARG;
+    wsum += weights_host[j];
+  }
+  if (std::fabs(wsum - 1.0) > 1e-6) return TTM_E_ARG;
+  if (out_bank) {
+    if (!image_dims_ok(N)) return TTM_E_SIZE;
+    if (!fits(L, N)) return TTM_E_SIZE;
+  }
+  if (!ws || ws_bytes < ttm_build_workspace_bytes(L, order_n, n_rot, N)) return TTM_E_WORKSPACE;
+  Carve c(ws);
+  BuildWs w = build_layout(c, n_rot, K);
+  TTM_TRY(hipMemcpyAsync(w.quats, quats_host, sizeof(float) * 4 * (size_t)n_rot, hipMemcpyHostToDevice, stream));
+  TTM_TRY(hipMemcpyAsync(w.weights, weights_host, sizeof(double) * (size_t)n_rot, hipMemcpyHostToDevice, stream));
+  TTM_PROF(PC_BUILD, launch_rot_stats(tmpl, mask, L.n0, L.n1, L.n2, w.quats, n_rot, w.rstats, stream));
+  TTM_PROF(PC_BUILD, launch_build_coef(w.quats, w.weights, w.rstats, n_rot, order_n, w.coef, stream));
+  TTM_PROF(PC_BUILD, launch_build_accum(tmpl, mask, L.n0, L.n1, L.n2, w.quats, w.rstats, w.coef, n_rot, K, out_components,
+                             stream));
+  if (out_bank) {
+    const Geo g = make_geo(N, L);
+    float2* bank = static_cast<float2*>(out_bank);
+    TTM_CALL(bank_forward(g, out_components, K, bank, stream));
+    TTM_CALL(bank_forward(g, mask, 1, bank + (long)K * g.bank_slab(), stream));
+  }
+  return TTM_OK;
+}
+
+size_t ttm_correlate_workspace_bytes(ttm_dims N, ttm_dims L, int32_t K) {
+  if (!dims_ok(N) || !dims_ok(L) || K < 1) return 0;
+  Carve c(nullptr);
+  corr_layout(c, make_geo(N, L), K);
+  return c.size();
+}
+
+ttm_status ttm_correlate(const float* image, ttm_dims N, const void* bank, ttm_dims L, int32_t order_n,
+                         const float* mask, const ttm_options* opt, float* out_score, float* out_w, void* ws,
+                         size_t ws_bytes, hipStream_t stream) {
+  if (!image || !bank || !mask || !opt || !out_score) return TTM_E_ARG;
+  const int K = ttm_num_components(order_n);
+  if (K < 0) return TTM_E_ARG;
+  if (!(opt->eps_v >= 0.0f)) return TTM_E_ARG;
+  if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
+  if (!ws || ws_bytes < ttm_correlate_workspace_bytes(N, L, K)) return TTM_E_WORKSPACE;
+  const Geo g = make_geo(N, L);
+  Carve c(ws);
+  CorrWs w = corr_layout(c, g, K);
+  const float2* bk = static_cast<const float2*>(bank);
+  const long half = g.half();
+  TTM_PROF(PC_STATS, launch_multiplicities(order_n, w.mu, stream));
+  TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream));
+  TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, bk, g.bank_slab(), K + 1, w.H, half, stream));
+  TTM_PROF(PC_PASS1, launch_pass1(g, w.Xg, bk + (long)K * g.bank_slab(), g.bank_slab(), 1, w.H + (long)(K + 1) * half, half,
+                       stream));
+  TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.h2, g.h2, (long)g.n1 * g.h2, g.h2, g.n1, g.c1, K + 2,
+                         half, stream));
+  Pass3Args a;
+  std::memset(&a, 0, sizeof(a));
+  a.H = w.H;
+  a.pstride = half;
+  a.npairs = K;
+  a.mode = P3_SCORE;
+  a.mu = w.mu;
+  a.stats = w.stats;
+  a.eps_v = opt->eps_v;
+  a.out_score = out_score;
+  a.out_w = out_w;
+  TTM_PROF(PC_PASS3, launch_pass3(g, a, stream));
+  return TTM_OK;
+}
+
+size_t ttm_pose_workspace_bytes(ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt) {
+  (void)N; (void)L; (void)order_n; (void)opt;
+  Carve c(nullptr);
+  pose_layout(c);
+  return c.size();
+}
+
+ttm_status ttm_recover_pose(const float* score, const float* image, const float* components, const float* mask,
+                            ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt, int32_t* out_pos,
+                            float* out_quat, double* out_lambda, float* out_peak_score, int32_t* out_flags,
+                            double* out_C, int32_t* out_count, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!score || !image || !components || !mask || !opt || !out_pos || !out_quat || !out_lambda ||
+      !out_peak_score || !out_flags || !out_count)
+    return TTM_E_ARG;
+  const int K = ttm_num_components(order_n);
+  if (K < 0) return TTM_E_ARG;
+  if (opt->max_peaks < 1 || opt->max_peaks > 4096) return TTM_E_ARG;
+  if (opt->n_seeds < 64 || opt->n_seeds > 65536) return TTM_E_ARG;
+  if (opt->hopm_max_iter < 1 || !(opt->hopm_tol > 0.0)) return TTM_E_ARG;
+  if (!(opt->threshold >= 0.0f) || !(opt->min_dist >= 0.0f) || !(opt->eps_v >= 0.0f)) return TTM_E_ARG;
+  if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
+  if (!ws || ws_bytes < ttm_pose_workspace_bytes(N, L, order_n, opt)) return TTM_E_WORKSPACE;
+  const Geo g = make_geo(N, L);
+  Carve c(ws);
+  PoseWs w = pose_layout(c);
+  TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), w.partials, w.stats, stream));
+  PeakWs pw{w.hist, w.ctrl, w.cand};
+  TTM_PROF(PC_PEAKS, launch_peaks(g, score, opt->threshold, opt->min_dist, opt->max_peaks, pw, out_pos, out_peak_score,
+                       out_count, stream));
+  TTM_PROF(PC_POSE, launch_pose(g, image, components, mask, order_n, w.stats, opt->eps_v, opt->n_seeds,
+                      opt->hopm_max_iter, opt->hopm_tol, opt->max_peaks, out_pos, out_count, out_quat,
+                      out_lambda, out_flags, out_C, nullptr, stream));
+  return TTM_OK;
+}
+
+size_t tm_classical_workspace_bytes(ttm_dims N, ttm_dims L, int32_t n_rot) {
+  if (!dims_ok(N) || !dims_ok(L) || n_rot < 1) return 0;
+  Carve c(nullptr);
+  class_layout(c, make_geo(N, L), n_rot);
+  return c.size();
+}
+
+ttm_status tm_classical(const float* image, ttm_dims N, const float* tmpl, const float* mask, ttm_dims L,
+                        const float* quats_host, int32_t n_rot, const ttm_options* opt, float* out_best_ncc,
+                        int32_t* out_best_rot, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!image || !tmpl || !mask || !quats_host || !opt || !out_best_ncc || !out_best_rot) return TTM_E_ARG;
+  if (n_rot < 1 || !(opt->eps_v >= 0.0f)) return TTM_E_ARG;
+  for (int j = 0; j < n_rot; ++j) {
+    const float* q = quats_host + 4 * j;
+    const double nq = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3];
+    if (!std::isfinite(nq) || nq <= 0.0) return TTM_E_ARG;
+  }
+  if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
+  if (!ws || ws_bytes < tm_classical_workspace_bytes(N, L, n_rot)) return TTM_E_WORKSPACE;
+  const Geo g = make_geo(N, L);
+  Carve c(ws);
+  ClassWs w = class_layout(c, g, n_rot);
+  const long half = g.half();
+  TTM_TRY(hipMemcpyAsync(w.quats, quats_host, sizeof(float) * 4 * (size_t)n_rot, hipMemcpyHostToDevice, stream));
+  TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream));
+  // w(x) from the two masked moments
+  TTM_CALL(bank_forward(g, mask, 1, w.bbank, stream));
+  TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, w.bbank, g.bank_slab(), 1, w.H, half, stream));
+  TTM_PROF(PC_PASS1, launch_pass1(g, w.Xg, w.bbank, g.bank_slab(), 1, w.H + half, half, stream));
+  TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.h2, g.h2, (long)g.n1 * g.h2, g.h2, g.n1, g.c1, 2, half,
+                         stream));
+  Pass3Args a;
+  std::memset(&a, 0, sizeof(a));
+  a.H = w.H;
+  a.pstride = half;
+  a.mode = P3_W;
+  a.stats = w.stats;
+  a.eps_v = opt->eps_v;
+  a.out_w = w.w;
+  TTM_PROF(PC_PASS3, launch_pass3(g, a, stream));
+  // rotation loop in batches
+  TTM_PROF(PC_BUILD, launch_rot_stats(tmpl, mask, L.n0, L.n1, L.n2, w.quats, n_rot, w.rstats, stream));
+  const int B = n_rot < kClassicalBatch ? n_rot : kClassicalBatch;
+  for (int j0 = 0; j0 < n_rot; j0 += B) {
+    const int nb = (n_rot - j0) < B ? (n_rot - j0) : B;
+    TTM_PROF(PC_BUILD, launch_rot_write(tmpl, mask, L.n0, L.n1, L.n2, w.quats, w.rstats, j0, nb, w.tbatch, stream));
+    TTM_CALL(bank_forward(g, w.tbatch, nb, w.bbank, stream));
+    TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, w.bbank, g.bank_slab(), nb, w.H, half, stream));
+    TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.h2, g.h2, (long)g.n1 * g.h2, g.h2, g.n1, g.c1, nb,
+                           half, stream));
+    Pass3Args m;
+    std::memset(&m, 0, sizeof(m));
+    m.H = w.H;
+    m.pstride = half;
+    m.npairs = nb;
+    m.mode = P3_MAX;
+    m.best = out_best_ncc;
+    m.best_idx = out_best_rot;
+    m.first_index = j0;
+    m.init = j0 == 0 ? 1 : 0;
+    TTM_PROF(PC_PASS3, launch_pass3(g, m, stream));
+  }
+  TTM_PROF(PC_EPI, launch_classical_final(g, w.w, out_best_ncc, out_best_rot, stream));
+  return TTM_OK;
+}
+
+void ttm_profile_enable(int32_t on) {
+  Prof& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.on = on != 0;
+}
+
+int32_t ttm_profile_read(double* ms_out, int64_t* launches_out, int32_t n) {
+  Prof& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  double ms[PC_COUNT] = {0};
+  int64_t cnt[PC_COUNT] = {0};
+  int32_t status = PC_COUNT;
+  for (const auto& u : p.used) {
+    const auto& ev = p.pool[u.second];
+    if (hipEventSynchronize(ev.second) != hipSuccess) {
+      status = TTM_E_HIP;
+      continue;
+    }
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, ev.first, ev.second) != hipSuccess) {
+      status = TTM_E_HIP;
+      continue;
+    }
+    ms[u.first] += t;
+    cnt[u.first] += 1;
+  }
+  p.used.clear();
+  for (int i = 0; i < n && i < PC_COUNT; ++i) {
+    if (ms_out) ms_out[i] = ms[i];
+    if (launches_out) launches_out[i] = cnt[i];
+  }
+  return status;
+}
+
+const char* ttm_profile_class_name(int32_t cls) {
+  return (cls >= 0 && cls < PC_COUNT) ? kProfNames[cls] : "unknown";
+}
+
+}  // extern "C"

@@ -1,0 +1,244 @@
+// Tensor template construction (Section 3.2) and the rotated, normalised
+// templates of classical matching (Algorithm 1).
+//
+//   s_j(u) = m(u) (g_j(u) - mean_j) scale_j,  g_j(u) = t(c + R_j^-1 (u - c))
+//   mean_j = <g_j, m> / m_sum,  scale_j = 1 / sqrt(<g_j^2, m> - <g_j, m>^2 / m_sum)
+//   T_alpha(u) = sum_j omega_j Q_j^alpha s_j(u)
+//
+// Rotation R(Q) of Q = (a,b,c,d): the active Hamilton rotation v -> Q v Q*,
+// vector part on axes (0,1,2).  Sampling is trilinear with zero outside the
+// box.  Masked sums and the tensor accumulation are float64.
+#include "ttm_device.h"
+#include "ttm_internal.h"
+
+namespace ttm {
+
+struct Rot {
+  float r[9];   // row-major R
+};
+
+__device__ __forceinline__ Rot quat_rot(const float* q4) {
+  double a = q4[0], b = q4[1], c = q4[2], d = q4[3];
+  const double nrm = sqrt(a * a + b * b + c * c + d * d);
+  a /= nrm; b /= nrm; c /= nrm; d /= nrm;
+  Rot R;
+  R.r[0] = (float)(a * a + b * b - c * c - d * d);
+  R.r[1] = (float)(2.0 * (b * c - a * d));
+  R.r[2] = (float)(2.0 * (b * d + a * c));
+  R.r[3] = (float)(2.0 * (b * c + a * d));
+  R.r[4] = (float)(a * a - b * b + c * c - d * d);
+  R.r[5] = (float)(2.0 * (c * d - a * b));
+  R.r[6] = (float)(2.0 * (b * d - a * c));
+  R.r[7] = (float)(2.0 * (c * d + a * b));
+  R.r[8] = (float)(a * a - b * b - c * c + d * d);
+  return R;
+}
+
+// t(c + R^-1 (u - c)) with R^-1 = R^T, trilinear, zero outside [0, L)
+__device__ __forceinline__ float sample_rotated(const float* __restrict__ t, int L0, int L1, int L2,
+                                                const Rot& R, int u0, int u1, int u2) {
+  const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;
+  const float v0 = (float)(u0 - c0), v1 = (float)(u1 - c1), v2 = (float)(u2 - c2);
+  const float p0 = c0 + R.r[0] * v0 + R.r[3] * v1 + R.r[6] * v2;
+  const float p1 = c1 + R.r[1] * v0 + R.r[4] * v1 + R.r[7] * v2;
+  const float p2 = c2 + R.r[2] * v0 + R.r[5] * v1 + R.r[8] * v2;
+  const float f0 = floorf(p0), f1 = floorf(p1), f2 = floorf(p2);
+  const int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
+  const float w0 = p0 - f0, w1 = p1 - f1, w2 = p2 - f2;
+  float acc = 0.0f;
+#pragma unroll
+  for (int d0 = 0; d0 < 2; ++d0) {
+    const int j0 = i0 + d0;
+    if (j0 < 0 || j0 >= L0) continue;
+    const float a0 = d0 ? w0 : 1.0f - w0;
+#pragma unroll
+    for (int d1 = 0; d1 < 2; ++d1) {
+      const int j1 = i1 + d1;
+      if (j1 < 0 || j1 >= L1) continue;
+      const float a1 = a0 * (d1 ? w1 : 1.0f - w1);
+#pragma unroll
+      for (int d2 = 0; d2 < 2; ++d2) {
+        const int j2 = i2 + d2;
+        if (j2 < 0 || j2 >= L2) continue;
+        acc += a1 * (d2 ? w2 : 1.0f - w2) * t[((long)j0 * L1 + j1) * L2 + j2];
+      }
+    }
+  }
+  return acc;
+}
+
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rot_stats(const float* __restrict__ t, const float* __restrict__ m,
+                                                   int L0, int L1, int L2, const float* __restrict__ quats,
+                                                   double* __restrict__ rstats) {
+  __shared__ double sh[3 * 256];
+  const int j = blockIdx.x;
+  const Rot R = quat_rot(quats + 4 * j);
+  const int n = L0 * L1 * L2;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int u = threadIdx.x; u < n; u += blockDim.x) {
+    const float mv = m[u];
+    if (mv == 0.0f) continue;
+    const int u2 = u % L2, u1 = (u / L2) % L1, u0 = u / (L1 * L2);
+    const double gv = sample_rotated(t, L0, L1, L2, R, u0, u1, u2);
+    s0 += mv;
+    s1 += mv * gv;
+    s2 += mv * gv * gv;
+  }
+  const int tid = threadIdx.x;
+  sh[tid] = s0; sh[256 + tid] = s1; sh[512 + tid] = s2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      sh[tid] += sh[tid + s];
+      sh[256 + tid] += sh[256 + tid + s];
+      sh[512 + tid] += sh[512 + tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double msum = sh[0], a1 = sh[256], a2 = sh[512];
+    const double mean = msum > 0.0 ? a1 / msum : 0.0;
+    const double var = msum > 0.0 ? a2 - a1 * a1 / msum : 0.0;
+    rstats[2 * j] = mean;
+    rstats[2 * j + 1] = (var > 1e-12 * (a2 > 0.0 ? a2 : 1.0)) ? 1.0 / sqrt(var) : 0.0;
+  }
+}
+
+hipError_t launch_rot_stats(const float* tmpl, const float* mask, int L0, int L1, int L2,
+                            const float* quats, int nrot, double* rstats, hipStream_t s) {
+  hipLaunchKernelGGL(k_rot_stats, dim3(nrot), dim3(256), 0, s, tmpl, mask, L0, L1, L2, quats, rstats);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double ipow(double x, int e) {
+  double r = 1.0;
+  for (int i = 0; i < e; ++i) r *= x;
+  return r;
+}
+
+__global__ void k_build_coef(const float* __restrict__ quats, const double* __restrict__ weights,
+                             const double* __restrict__ rstats, int nrot, int order_n, int K,
+                             double* __restrict__ coef) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)nrot * K) return;
+  const int j = (int)(i / K), k = (int)(i % K);
+  int al[4];
+  alpha_of_dev(order_n, k, al);
+  double q[4] = {quats[4 * j], quats[4 * j + 1], quats[4 * j + 2], quats[4 * j + 3]};
+  const double nrm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  double mono = 1.0;
+  for (int d = 0; d < 4; ++d) mono *= ipow(q[d] / nrm, al[d]);
+  coef[i] = weights[j] * mono * rstats[2 * j + 1];
+}
+
+hipError_t launch_build_coef(const float* quats, const double* weights, const double* rstats,
+                             int nrot, int order_n, double* coef, hipStream_t s) {
+  const int K = num_components(order_n);
+  const long n = (long)nrot * K;
+  hipLaunchKernelGGL(k_build_coef, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, quats, weights,
+                     rstats, nrot, order_n, K, coef);
+  return hipGetLastError();
+}
+
+__global__ void k_multiplicities(int order_n, int K, float* mu) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  int al[4];
+  alpha_of_dev(order_n, k, al);
+  double f = 1.0;
+  for (int i = 2; i <= order_n; ++i) f *= i;
+  for (int d = 0; d < 4; ++d)
+    for (int i = 2; i <= al[d]; ++i) f /= i;
+  mu[k] = (float)f;
+}
+
+hipError_t launch_multiplicities(int order_n, float* mu, hipStream_t s) {
+  const int K = num_components(order_n);
+  hipLaunchKernelGGL(k_multiplicities, dim3((K + 255) / 256), dim3(256), 0, s, order_n, K, mu);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// T_alpha(u) for a chunk of KC components (blockIdx.y selects the chunk)
+constexpr int kKC = 36;
+
+__global__ void __launch_bounds__(256) k_build_accum(const float* __restrict__ t, const float* __restrict__ m,
+                                                     int L0, int L1, int L2, const float* __restrict__ quats,
+                                                     const double* __restrict__ rstats,
+                                                     const double* __restrict__ coef, int nrot, int K,
+                                                     float* __restrict__ comps) {
+  const int n = L0 * L1 * L2;
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k0 = blockIdx.y * kKC;
+  const int kc = min(kKC, K - k0);
+  double acc[kKC];
+#pragma unroll
+  for (int i = 0; i < kKC; ++i) acc[i] = 0.0;
+  float mv = 0.0f;
+  int u0 = 0, u1 = 0, u2 = 0;
+  if (u < n) {
+    mv = m[u];
+    u2 = u % L2; u1 = (u / L2) % L1; u0 = u / (L1 * L2);
+  }
+  if (mv != 0.0f) {
+#pragma unroll 1
+    for (int j = 0; j < nrot; ++j) {
+      const Rot R = quat_rot(quats + 4 * j);
+      const double g = sample_rotated(t, L0, L1, L2, R, u0, u1, u2);
+      const double sv = (double)mv * (g - rstats[2 * j]);
+      const double* cj = coef + (long)j * K + k0;
+#pragma unroll
+      for (int i = 0; i < kKC; ++i)
+        if (i < kc) acc[i] += cj[i] * sv;
+    }
+  }
+  if (u < n) {
+#pragma unroll
+    for (int i = 0; i < kKC; ++i)
+      if (i < kc) comps[(long)(k0 + i) * n + u] = (float)acc[i];
+  }
+}
+
+hipError_t launch_build_accum(const float* tmpl, const float* mask, int L0, int L1, int L2,
+                              const float* quats, const double* rstats, const double* coef,
+                              int nrot, int K, float* comps, hipStream_t s) {
+  const int n = L0 * L1 * L2;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)((K + kKC - 1) / kKC));
+  hipLaunchKernelGGL(k_build_accum, grid, dim3(256), 0, s, tmpl, mask, L0, L1, L2, quats, rstats, coef,
+                     nrot, K, comps);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rot_write(const float* __restrict__ t, const float* __restrict__ m,
+                                                   int L0, int L1, int L2, const float* __restrict__ quats,
+                                                   const double* __restrict__ rstats, int j0,
+                                                   float* __restrict__ out) {
+  const int n = L0 * L1 * L2;
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  const int j = j0 + b;
+  if (u >= n) return;
+  const float mv = m[u];
+  float v = 0.0f;
+  if (mv != 0.0f) {
+    const Rot R = quat_rot(quats + 4 * j);
+    const int u2 = u % L2, u1 = (u / L2) % L1, u0 = u / (L1 * L2);
+    const double g = sample_rotated(t, L0, L1, L2, R, u0, u1, u2);
+    v = (float)((double)mv * (g - rstats[2 * j]) * rstats[2 * j + 1]);
+  }
+  out[(long)b * n + u] = v;
+}
+
+hipError_t launch_rot_write(const float* tmpl, const float* mask, int L0, int L1, int L2,
+                            const float* quats, const double* rstats, int j0, int nb, float* out,
+                            hipStream_t s) {
+  const int n = L0 * L1 * L2;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)nb);
+  hipLaunchKernelGGL(k_rot_write, grid, dim3(256), 0, s, tmpl, mask, L0, L1, L2, quats, rstats, j0, out);
+  return hipGetLastError();
+}
+
+}  // namespace ttm

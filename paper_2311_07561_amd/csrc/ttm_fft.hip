@@ -1,0 +1,608 @@
+// FFT passes of the correlation path (Section 2, FFT inner products; Algorithm
+// 1; Section 3.2).  Transforms are unnormalised; the 1/(n0 n1 n2) factor is
+// applied once, in the last inverse pass.
+//
+// Layout of a half spectrum: [n0][n1][h2] complex float, h2 = n2/2 + 1.
+// Forward path of the image: axis-2 R2C (rows), then axis 1 (pencils, in
+// place); the axis-0 forward transform is done on the fly inside pass 1.
+// Inverse path per (image spectrum, template entry) pair: pass 1 = axis 0
+// (fused with the forward axis-0 transform of the pruned template block and
+// the conjugate product), pass 2 = axis 1 (pencils, in place), pass 3 =
+// axis-2 C2R fused with the per-voxel reduction.
+#include "ttm_device.h"
+#include "ttm_internal.h"
+
+namespace ttm {
+
+// ----------------------------------------------------------------------------
+// image and mask moments (float64, deterministic two-level reduction)
+// ----------------------------------------------------------------------------
+constexpr int kStatBlocks = 512;
+
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = a;
+  sh[tid + 256] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      sh[tid] += sh[tid + s];
+      sh[tid + 256] += sh[tid + 256 + s];
+    }
+    __syncthreads();
+  }
+  a = sh[0];
+  b = sh[256];
+}
+
+__global__ void __launch_bounds__(256) k_stats_partial(const float* __restrict__ x, long n,
+                                                       double* __restrict__ partials) {
+  __shared__ double sh[512];
+  double s1 = 0.0, s2 = 0.0;
+  const long n4 = n / 4;
+  const float4* x4 = reinterpret_cast<const float4*>(x);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (long)gridDim.x * blockDim.x) {
+    const float4 v = x4[i];
+    s1 += (double)v.x + (double)v.y + (double)v.z + (double)v.w;
+    s2 += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+  }
+  for (long i = n4 * 4 + (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double v = x[i];
+    s1 += v;
+    s2 += v * v;
+  }
+  block_sum2(s1, s2, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = s1;
+    partials[2 * blockIdx.x + 1] = s2;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_stats_final(const double* __restrict__ partials, int nb,
+                                                     long n, double* __restrict__ stats) {
+  __shared__ double sh[512];
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    s1 += partials[2 * i];
+    s2 += partials[2 * i + 1];
+  }
+  block_sum2(s1, s2, sh);
+  if (threadIdx.x == 0) {
+    const double mean = s1 / (double)n;
+    double var = s2 / (double)n - mean * mean;
+    stats[0] = mean;
+    stats[1] = var > 0.0 ? var : 0.0;
+  }
+}
+
+hipError_t launch_image_stats(const float* img, long n, double* partials, double* stats,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_partial, dim3(kStatBlocks), dim3(256), 0, s, img, n, partials);
+  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(256), 0, s, partials, kStatBlocks, n, stats);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_mask_sum(const float* __restrict__ m, long n,
+                                                  double* __restrict__ out) {
+  __shared__ double sh[512];
+  double s1 = 0.0, s2 = 0.0;
+  for (long i = threadIdx.x; i < n; i += blockDim.x) s1 += (double)m[i];
+  block_sum2(s1, s2, sh);
+  if (threadIdx.x == 0) out[0] = s1;
+}
+
+hipError_t launch_mask_sum(const float* mask, long n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_sum, dim3(1), dim3(256), 0, s, mask, n, out);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// axis-2 R2C of real rows through a half-length complex FFT:
+// z(m) = x(2m) + i x(2m+1), Z = FFT_M(z),
+// X(k) = (Z(k) + conj Z(M-k))/2 - (i/2) W_N^k (Z(k) - conj Z(M-k)), k = 0..M
+// ----------------------------------------------------------------------------
+template <int M>
+struct RowCfg {
+  static constexpr int R1 = Plan<M>::R1, R2 = Plan<M>::R2;
+  static constexpr int RW = 256 / R1;          // rows per block
+  static constexpr int SP = M + 1;             // stage pitch (complex)
+};
+
+template <int M, int MODE>
+__global__ void __launch_bounds__(256) k_r2c_rows(const float* __restrict__ src, long src_stride,
+                                                  int len_valid, long nrows, float2* __restrict__ dst0,
+                                                  float2* __restrict__ dst1, long grp, long grp_stride,
+                                                  const double* __restrict__ stats) {
+  using C = RowCfg<M>;
+  constexpr int R1 = C::R1, R2 = C::R2, RW = C::RW, SP = C::SP;
+  constexpr int N2 = 2 * M, H2 = M + 1;
+  __shared__ float2 stage[RW * SP];
+  __shared__ float2 twM[M];
+  __shared__ float2 tw2[N2];
+  const int tid = threadIdx.x;
+  fill_twiddles(twM, M, tid, 256);
+  fill_twiddles(tw2, N2, tid, 256);
+  const long r0 = (long)blockIdx.x * RW;
+  const int p = tid % RW, a = tid / RW;
+  const float mean = MODE == 1 ? (float)stats[0] : 0.0f;
+
+#pragma unroll 1
+  for (int sq = 0; sq < (MODE == 1 ? 2 : 1); ++sq) {
+    float2* dst = sq ? dst1 : dst0;
+    __syncthreads();
+    for (int e = tid; e < RW * M; e += 256) {
+      const int rr = e / M, m = e % M;
+      const long r = r0 + rr;
+      float v0 = 0.0f, v1 = 0.0f;
+      if (r < nrows) {
+        const float* row = src + r * src_stride;
+        if (2 * m < len_valid) v0 = row[2 * m];
+        if (2 * m + 1 < len_valid) v1 = row[2 * m + 1];
+        if (MODE == 1) {
+          v0 -= mean;
+          v1 -= mean;
+          if (sq) {
+            v0 *= v0;
+            v1 *= v1;
+          }
+        }
+      }
+      stage[rr * SP + m] = make_float2(v0, v1);
+    }
+    __syncthreads();
+    float2 x[R2], o[R2];
+#pragma unroll
+    for (int b = 0; b < R2; ++b) x[b] = stage[p * SP + a + R1 * b];
+    // the engine's exchange buffer aliases the stage: all stage reads above
+    // complete before the engine's first barrier
+    engineA<M, RW, false>(x, o, stage, twM, p, a);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < R2 / R1; ++k)
+#pragma unroll
+      for (int d = 0; d < R1; ++d) stage[p * SP + (a + R1 * k) + R2 * d] = o[k * R1 + d];
+    __syncthreads();
+    for (int e = tid; e < RW * H2; e += 256) {
+      const int rr = e / H2, k = e % H2;
+      const long r = r0 + rr;
+      if (r >= nrows) continue;
+      const float2 zk = stage[rr * SP + (k % M)];
+      const float2 zm = cconj(stage[rr * SP + ((M - k) % M)]);
+      const float2 ev = cscale(cadd(zk, zm), 0.5f);
+      const float2 pw = cmul(tw2[k], csub(zk, zm));
+      const float2 X = make_float2(ev.x + 0.5f * pw.y, ev.y - 0.5f * pw.x);
+      const long drow = (r / grp) * grp_stride + (r % grp);
+      dst[drow * H2 + k] = X;
+    }
+  }
+}
+
+template <int M>
+static hipError_t r2c_rows_m(const float* src, long src_stride, int len_valid, long nrows,
+                             float2* dst0, float2* dst1, long grp, long grp_stride, int mode,
+                             const double* stats, hipStream_t s) {
+  constexpr int RW = RowCfg<M>::RW;
+  dim3 grid((unsigned)((nrows + RW - 1) / RW));
+  if (mode == 1)
+    hipLaunchKernelGGL((k_r2c_rows<M, 1>), grid, dim3(256), 0, s, src, src_stride, len_valid, nrows,
+                       dst0, dst1, grp, grp_stride, stats);
+  else
+    hipLaunchKernelGGL((k_r2c_rows<M, 0>), grid, dim3(256), 0, s, src, src_stride, len_valid, nrows,
+                       dst0, dst1, grp, grp_stride, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_r2c_rows(int n2, const float* src, long src_stride, int len_valid, long nrows,
+                           float2* dst0, float2* dst1, long grp, long grp_stride, int mode,
+                           const double* stats, hipStream_t s) {
+  switch (n2) {
+    case 16: return r2c_rows_m<8>(src, src_stride, len_valid, nrows, dst0, dst1, grp, grp_stride, mode, stats, s);
+    case 32: return r2c_rows_m<16>(src, src_stride, len_valid, nrows, dst0, dst1, grp, grp_stride, mode, stats, s);
+    case 64: return r2c_rows_m<32>(src, src_stride, len_valid, nrows, dst0, dst1, grp, grp_stride, mode, stats, s);
+    case 128: return r2c_rows_m<64>(src, src_stride, len_valid, nrows, dst0, dst1, grp, grp_stride, mode, stats, s);
+    case 256: return r2c_rows_m<128>(src, src_stride, len_valid, nrows, dst0, dst1, grp, grp_stride, mode, stats, s);
+    case 512: return r2c_rows_m<256>(src, src_stride, len_valid, nrows, dst0, dst1, grp, grp_stride, mode, stats, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// strided pencils along one axis (in place)
+// ----------------------------------------------------------------------------
+template <int N>
+struct PenCfg {
+  static constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
+  static constexpr int PW = 256 / R1;    // pencils per block
+};
+
+template <int N, bool INV>
+__global__ void __launch_bounds__(256) k_pencils(float2* __restrict__ data, long npencils, long Q,
+                                                 long S_outer, long S_axis, int nin, int shift,
+                                                 long batch_stride) {
+  using C = PenCfg<N>;
+  constexpr int R1 = C::R1, R2 = C::R2, PW = C::PW;
+  __shared__ float2 lds[PW * N];
+  __shared__ float2 tw[N];
+  const int tid = threadIdx.x;
+  fill_twiddles(tw, N, tid, 256);
+  const int pl = tid % PW, a = tid / PW;
+  const long p = (long)blockIdx.x * PW + pl;
+  const bool valid = p < npencils;
+  float2* base = data + (long)blockIdx.y * batch_stride + (valid ? (p / Q) * S_outer + (p % Q) : 0);
+  float2 x[R2], o[R2];
+#pragma unroll
+  for (int b = 0; b < R2; ++b) {
+    const int j = a + R1 * b;
+    x[b] = (valid && j < nin) ? base[j * S_axis] : make_float2(0.0f, 0.0f);
+  }
+  engineA<N, PW, INV>(x, o, lds, tw, pl, a);
+  if (!valid) return;
+#pragma unroll
+  for (int k = 0; k < R2 / R1; ++k)
+#pragma unroll
+    for (int d = 0; d < R1; ++d) {
+      const int j = (a + R1 * k) + R2 * d;
+      base[((j + shift) & (N - 1)) * S_axis] = o[k * R1 + d];
+    }
+}
+
+template <int N>
+static hipError_t pencils_n(bool inverse, float2* data, long npencils, long Q, long S_outer,
+                            long S_axis, int nin, int shift, int nbatch, long batch_stride,
+                            hipStream_t s) {
+  constexpr int PW = PenCfg<N>::PW;
+  dim3 grid((unsigned)((npencils + PW - 1) / PW), (unsigned)nbatch);
+  if (inverse)
+    hipLaunchKernelGGL((k_pencils<N, true>), grid, dim3(256), 0, s, data, npencils, Q, S_outer,
+                       S_axis, nin, shift, batch_stride);
+  else
+    hipLaunchKernelGGL((k_pencils<N, false>), grid, dim3(256), 0, s, data, npencils, Q, S_outer,
+                       S_axis, nin, shift, batch_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long Q, long S_outer,
+                          long S_axis, int nin, int shift, int nbatch, long batch_stride,
+                          hipStream_t s) {
+  switch (N) {
+    case 16: return pencils_n<16>(inverse, data, npencils, Q, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
+    case 32: return pencils_n<32>(inverse, data, npencils, Q, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
+    case 64: return pencils_n<64>(inverse, data, npencils, Q, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
+    case 128: return pencils_n<128>(inverse, data, npencils, Q, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
+    case 256: return pencils_n<256>(inverse, data, npencils, Q, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
+    case 512: return pencils_n<512>(inverse, data, npencils, Q, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// pass 1: axis 0, fused fan-out (Section 2: <f,g> = F^-1(F(f) conj F(g)))
+// ----------------------------------------------------------------------------
+template <int N0>
+__global__ void __launch_bounds__(256) k_pass1(const float2* __restrict__ src, long P, int L0,
+                                               const float2* __restrict__ tmpl, long tmpl_stride, int nt,
+                                               float2* __restrict__ out, long out_stride, int shift0) {
+  using C = PenCfg<N0>;
+  constexpr int R1 = C::R1, R2 = C::R2, PW = C::PW;
+  __shared__ float2 lds[PW * N0];
+  __shared__ float2 tw[N0];
+  const int tid = threadIdx.x;
+  fill_twiddles(tw, N0, tid, 256);
+  const int pl = tid % PW, a = tid / PW;
+  const long p = (long)blockIdx.x * PW + pl;
+  const bool valid = p < P;
+  const long pp = valid ? p : 0;
+  float2 x[R2], F[R2], T[R2], y[R2];
+#pragma unroll
+  for (int b = 0; b < R2; ++b) x[b] = valid ? src[(long)(a + R1 * b) * P + pp] : make_float2(0.0f, 0.0f);
+  engineA<N0, PW, false>(x, F, lds, tw, pl, a);
+#pragma unroll 1
+  for (int i = 0; i < nt; ++i) {
+    const float2* tb = tmpl + (long)i * tmpl_stride;
+#pragma unroll
+    for (int b = 0; b < R2; ++b) {
+      const int j = a + R1 * b;
+      x[b] = (valid && j < L0) ? tb[(long)j * P + pp] : make_float2(0.0f, 0.0f);
+    }
+    engineA<N0, PW, false>(x, T, lds, tw, pl, a);
+#pragma unroll
+    for (int j = 0; j < R2; ++j) T[j] = cmulc(F[j], T[j]);
+    engineB<N0, PW, true>(T, y, lds, tw, pl, a);
+    if (valid) {
+      float2* ob = out + (long)i * out_stride;
+#pragma unroll
+      for (int g = 0; g < R2; ++g) {
+        const int j = a + R1 * g;
+        ob[(long)((j + shift0) & (N0 - 1)) * P + p] = y[g];
+      }
+    }
+  }
+}
+
+template <int N0>
+static hipError_t pass1_n(const Geo& g, const float2* src, const float2* tmpl, long tmpl_stride,
+                          int nt, float2* out, long out_stride, hipStream_t s) {
+  constexpr int PW = PenCfg<N0>::PW;
+  const long P = (long)g.n1 * g.h2;
+  dim3 grid((unsigned)((P + PW - 1) / PW));
+  hipLaunchKernelGGL((k_pass1<N0>), grid, dim3(256), 0, s, src, P, g.L0, tmpl, tmpl_stride, nt, out,
+                     out_stride, g.c0);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass1(const Geo& g, const float2* src, const float2* tmpl, long tmpl_stride,
+                        int nt, float2* out, long out_stride, hipStream_t s) {
+  switch (g.n0) {
+    case 16: return pass1_n<16>(g, src, tmpl, tmpl_stride, nt, out, out_stride, s);
+    case 32: return pass1_n<32>(g, src, tmpl, tmpl_stride, nt, out, out_stride, s);
+    case 64: return pass1_n<64>(g, src, tmpl, tmpl_stride, nt, out, out_stride, s);
+    case 128: return pass1_n<128>(g, src, tmpl, tmpl_stride, nt, out, out_stride, s);
+    case 256: return pass1_n<256>(g, src, tmpl, tmpl_stride, nt, out, out_stride, s);
+    case 512: return pass1_n<512>(g, src, tmpl, tmpl_stride, nt, out, out_stride, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// pass 3: axis-2 C2R fused with the reduction over pair arrays.
+// 2 Z(k) = (X(k) + conj X(M-k)) + i (X(k) - conj X(M-k)) e^{+2 pi i k/N},
+// IDFT_M(2Z)(m) = N (x(2m) + i x(2m+1)).
+// ----------------------------------------------------------------------------
+struct P3Geo {
+  int n0, n1, n2, h2;
+  int lo0, hi0, lo1, hi1, lo2, hi2;   // valid region, inclusive bounds
+  int c2;
+  double inv_vol;
+};
+
+template <int M, int MODE>
+__global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
+  using C = RowCfg<M>;
+  constexpr int R1 = C::R1, R2 = C::R2, RW = C::RW, SP = C::SP;
+  constexpr int N2 = 2 * M, H2 = M + 1;
+  __shared__ float2 stage[RW * SP];
+  __shared__ float ostage[RW * N2];
+  __shared__ float2 twM[M];
+  __shared__ float2 tw2[N2];
+  const int tid = threadIdx.x;
+  fill_twiddles(twM, M, tid, 256);
+  fill_twiddles(tw2, N2, tid, 256);
+  const long nrows = (long)g.n0 * g.n1;
+  const long r0 = (long)blockIdx.x * RW;
+  const int p = tid % RW, a = tid / RW;
+  const long myrow = r0 + p;
+
+  // per-thread element values: e[k*R1+d] holds (x(2n), x(2n+1)), n = (a + R1 k) + R2 d
+  float2 wv[R2];     // w (P3_SCORE) or running best (P3_MAX)
+  float2 acc[R2];    // sum mu G^2 (P3_SCORE)
+  int2 bidx[R2];     // running argmax (P3_MAX)
+  double msum = 0.0, floor_v = 0.0;
+  if (MODE != P3_MAX) {
+    msum = A.stats[2];
+    floor_v = (double)A.eps_v * msum * A.stats[1];
+  }
+#pragma unroll
+  for (int j = 0; j < R2; ++j) {
+    wv[j] = make_float2(0.0f, 0.0f);
+    acc[j] = make_float2(0.0f, 0.0f);
+    bidx[j] = make_int2(0, 0);
+  }
+  if (MODE == P3_MAX) {
+#pragma unroll
+    for (int k = 0; k < R2 / R1; ++k)
+#pragma unroll
+      for (int d = 0; d < R1; ++d) {
+        const int n = (a + R1 * k) + R2 * d;
+        const int j = k * R1 + d;
+        if (A.init || myrow >= nrows) {
+          wv[j] = make_float2(-INFINITY, -INFINITY);
+          bidx[j] = make_int2(0, 0);
+        } else {
+          const long o0 = myrow * g.n2 + ((2 * n + g.c2) & (N2 - 1));
+          const long o1 = myrow * g.n2 + ((2 * n + 1 + g.c2) & (N2 - 1));
+          wv[j] = make_float2(A.best[o0], A.best[o1]);
+          bidx[j] = make_int2(A.best_idx[o0], A.best_idx[o1]);
+        }
+      }
+  }
+
+  const int npass = MODE == P3_SCORE ? A.npairs + 2 : (MODE == P3_W ? 2 : A.npairs);
+#pragma unroll 1
+  for (int it = 0; it < npass; ++it) {
+    // pair order: P3_SCORE does M1 (index npairs), M2 (npairs+1), then components
+    int pair = it;
+    if (MODE == P3_SCORE) pair = it < 2 ? A.npairs + it : it - 2;
+    const float2* H = A.H + (long)pair * A.pstride + r0 * H2;
+    __syncthreads();
+    for (int e = tid; e < RW * H2; e += 256) {
+      const int rr = e / H2, k = e % H2;
+      stage[rr * SP + k] = (r0 + rr < nrows) ? H[e] : make_float2(0.0f, 0.0f);
+    }
+    __syncthreads();
+    float2 z[R2], o[R2];
+#pragma unroll
+    for (int b = 0; b < R2; ++b) {
+      const int k = a + R1 * b;
+      const float2 xk = stage[p * SP + k];
+      const float2 xm = cconj(stage[p * SP + (M - k)]);
+      const float2 s = cadd(xk, xm);
+      const float2 q = cmul(csub(xk, xm), cconj(tw2[k]));
+      z[b] = make_float2(s.x - q.y, s.y + q.x);
+    }
+    engineA<M, RW, true>(z, o, stage, twM, p, a);
+    if (MODE == P3_SCORE || MODE == P3_W) {
+      if (it == 0) {
+#pragma unroll
+        for (int j = 0; j < R2; ++j) wv[j] = o[j];               // M1 (unscaled)
+      } else if (it == 1) {
+#pragma unroll
+        for (int j = 0; j < R2; ++j) {
+          const double m1x = (double)wv[j].x * g.inv_vol, m1y = (double)wv[j].y * g.inv_vol;
+          const double m2x = (double)o[j].x * g.inv_vol, m2y = (double)o[j].y * g.inv_vol;
+          const double vx = m2x - m1x * m1x / msum, vy = m2y - m1y * m1y / msum;
+          wv[j] = make_float2(vx > floor_v ? (float)(1.0 / sqrt(vx)) : 0.0f,
+                              vy > floor_v ? (float)(1.0 / sqrt(vy)) : 0.0f);
+        }
+      } else {
+        const float mu = A.mu[pair];
+#pragma unroll
+        for (int j = 0; j < R2; ++j) {
+          acc[j].x += mu * o[j].x * o[j].x;
+          acc[j].y += mu * o[j].y * o[j].y;
+        }
+      }
+    } else {
+      const int idx = A.first_index + pair;
+#pragma unroll
+      for (int j = 0; j < R2; ++j) {
+        if (o[j].x > wv[j].x) { wv[j].x = o[j].x; bidx[j].x = idx; }
+        if (o[j].y > wv[j].y) { wv[j].y = o[j].y; bidx[j].y = idx; }
+      }
+    }
+  }
+
+  if (MODE == P3_MAX) {
+    if (myrow < nrows) {
+#pragma unroll
+      for (int k = 0; k < R2 / R1; ++k)
+#pragma unroll
+        for (int d = 0; d < R1; ++d) {
+          const int n = (a + R1 * k) + R2 * d;
+          const int j = k * R1 + d;
+          const long o0 = myrow * g.n2 + ((2 * n + g.c2) & (N2 - 1));
+          const long o1 = myrow * g.n2 + ((2 * n + 1 + g.c2) & (N2 - 1));
+          A.best[o0] = wv[j].x;
+          A.best[o1] = wv[j].y;
+          A.best_idx[o0] = bidx[j].x;
+          A.best_idx[o1] = bidx[j].y;
+        }
+    }
+    return;
+  }
+
+  // stage the outputs in LDS with the axis-2 centre shift, then store rows
+  const float fscale = (float)g.inv_vol;
+#pragma unroll 1
+  for (int outk = 0; outk < 2; ++outk) {
+    float* dst = outk == 0 ? (MODE == P3_SCORE ? A.out_score : A.out_w) : (MODE == P3_SCORE ? A.out_w : nullptr);
+    if (dst == nullptr) break;
+    const bool is_w = (MODE == P3_W) || outk == 1;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < R2 / R1; ++k)
+#pragma unroll
+      for (int d = 0; d < R1; ++d) {
+        const int n = (a + R1 * k) + R2 * d;
+        const int j = k * R1 + d;
+        float v0, v1;
+        if (is_w) {
+          v0 = wv[j].x;
+          v1 = wv[j].y;
+        } else {
+          v0 = wv[j].x * sqrtf(acc[j].x) * fscale;
+          v1 = wv[j].y * sqrtf(acc[j].y) * fscale;
+        }
+        ostage[p * N2 + ((2 * n + g.c2) & (N2 - 1))] = v0;
+        ostage[p * N2 + ((2 * n + 1 + g.c2) & (N2 - 1))] = v1;
+      }
+    __syncthreads();
+    for (int e = tid; e < RW * N2; e += 256) {
+      const int rr = e / N2, x2 = e % N2;
+      const long r = r0 + rr;
+      if (r >= nrows) continue;
+      const int x0 = (int)(r / g.n1), x1 = (int)(r % g.n1);
+      const bool ok = x0 >= g.lo0 && x0 <= g.hi0 && x1 >= g.lo1 && x1 <= g.hi1 && x2 >= g.lo2 && x2 <= g.hi2;
+      dst[r * g.n2 + x2] = ok ? ostage[e] : 0.0f;
+    }
+  }
+}
+
+static P3Geo make_p3geo(const Geo& g) {
+  P3Geo q;
+  q.n0 = g.n0; q.n1 = g.n1; q.n2 = g.n2; q.h2 = g.h2;
+  q.lo0 = g.c0; q.hi0 = g.n0 - g.L0 + g.c0;
+  q.lo1 = g.c1; q.hi1 = g.n1 - g.L1 + g.c1;
+  q.lo2 = g.c2; q.hi2 = g.n2 - g.L2 + g.c2;
+  q.c2 = g.c2;
+  q.inv_vol = 1.0 / (double)g.vol();
+  return q;
+}
+
+template <int M>
+static hipError_t pass3_m(const Geo& g, const Pass3Args& a, hipStream_t s) {
+  constexpr int RW = RowCfg<M>::RW;
+  const long nrows = (long)g.n0 * g.n1;
+  dim3 grid((unsigned)((nrows + RW - 1) / RW));
+  const P3Geo q = make_p3geo(g);
+  switch (a.mode) {
+    case P3_SCORE: hipLaunchKernelGGL((k_pass3<M, P3_SCORE>), grid, dim3(256), 0, s, q, a); break;
+    case P3_W: hipLaunchKernelGGL((k_pass3<M, P3_W>), grid, dim3(256), 0, s, q, a); break;
+    case P3_MAX: hipLaunchKernelGGL((k_pass3<M, P3_MAX>), grid, dim3(256), 0, s, q, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pass3(const Geo& g, const Pass3Args& a, hipStream_t s) {
+  switch (g.n2) {
+    case 16: return pass3_m<8>(g, a, s);
+    case 32: return pass3_m<16>(g, a, s);
+    case 64: return pass3_m<32>(g, a, s);
+    case 128: return pass3_m<64>(g, a, s);
+    case 256: return pass3_m<128>(g, a, s);
+    case 512: return pass3_m<256>(g, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// classical epilogue and fills
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_classical_final(P3Geo g, const float* __restrict__ w,
+                                                         float* __restrict__ best, int* __restrict__ idx) {
+  const long n = (long)g.n0 * g.n1 * g.n2;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int x2 = (int)(i % g.n2);
+    const long r = i / g.n2;
+    const int x1 = (int)(r % g.n1), x0 = (int)(r / g.n1);
+    const bool ok = x0 >= g.lo0 && x0 <= g.hi0 && x1 >= g.lo1 && x1 <= g.hi1 && x2 >= g.lo2 && x2 <= g.hi2;
+    if (!ok) {
+      best[i] = 0.0f;
+      idx[i] = -1;
+    } else {
+      const float wi = w[i];
+      if (wi > 0.0f) {
+        best[i] = (float)((double)best[i] * (double)wi * g.inv_vol);
+      } else {
+        best[i] = 0.0f;
+        idx[i] = 0;
+      }
+    }
+  }
+}
+
+hipError_t launch_classical_final(const Geo& g, const float* w, float* best, int* idx,
+                                  hipStream_t s) {
+  const P3Geo q = make_p3geo(g);
+  hipLaunchKernelGGL(k_classical_final, dim3(2048), dim3(256), 0, s, q, w, best, idx);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_f32(float* p, long n, float v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_i32(int* p, long n, int v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+hipError_t launch_fill_f32(float* p, long n, float v, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_f32, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int* p, long n, int v, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_i32, dim3(nb > 0 ? nb : 1), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace ttm

@@ -1,0 +1,114 @@
+// Host-side internal interface between the libttm translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ttm.h"
+
+namespace ttm {
+
+constexpr int kMaxOrder = 8;
+constexpr int kMaxK = 165;          // C(8+3, 3)
+
+inline int num_components(int n) { return (n + 1) * (n + 2) * (n + 3) / 6; }
+inline bool supported_len(int n) { return n >= 16 && n <= 512 && (n & (n - 1)) == 0; }
+
+// Reduction modes of the last inverse pass (axis-2 C2R).
+enum Pass3Mode { P3_SCORE = 0, P3_W = 1, P3_MAX = 2 };
+
+struct Geo {
+  int n0, n1, n2;      // image extents
+  int h2;              // n2 / 2 + 1
+  int L0, L1, L2;      // template extents
+  int c0, c1, c2;      // template centre (L / 2)
+  long vol() const { return (long)n0 * n1 * n2; }
+  long half() const { return (long)n0 * n1 * h2; }     // complex elements of a half spectrum
+  long bank_slab() const { return (long)L0 * n1 * h2; } // complex elements per bank entry
+};
+
+// --- FFT passes (ttm_fft.hip) -------------------------------------------------
+// image moments: stats[0] = mean, stats[1] = population variance (float64)
+hipError_t launch_image_stats(const float* img, long n, double* partials, double* stats,
+                              hipStream_t s);
+// mask sum: stats[0] = m_sum
+hipError_t launch_mask_sum(const float* mask, long n, double* out, hipStream_t s);
+// axis-2 R2C of rows.  mode 0: src rows (len_valid <= n2 values, rest zero)
+// -> dst0; mode 1: image rows, (f - mean) -> dst0 and (f - mean)^2 -> dst1.
+// dst row of source row r: (r / grp) * grp_stride + r % grp (rows of h2).
+hipError_t launch_r2c_rows(int n2, const float* src, long src_stride, int len_valid, long nrows,
+                           float2* dst0, float2* dst1, long grp, long grp_stride, int mode,
+                           const double* stats, hipStream_t s);
+// strided pencil FFT along one axis, in place: pencil p has base
+// (p / Q) * S_outer + p % Q and element j at base + j * S_axis; only j < nin is
+// read (the rest is zero); output index j is written at (j + shift) mod N.
+// blockIdx.y walks nbatch arrays batch_stride apart.
+hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long Q, long S_outer,
+                          long S_axis, int nin, int shift, int nbatch, long batch_stride,
+                          hipStream_t s);
+// first inverse pass, fused: forward axis-0 FFT of the image pencils in src,
+// then for each of nt template entries (bank layout [L0][n1][h2]): pruned
+// forward axis-0 FFT, product with conj, inverse axis-0 FFT, store into
+// out + i * out_stride with the centre shift.
+hipError_t launch_pass1(const Geo& g, const float2* src, const float2* tmpl, long tmpl_stride,
+                        int nt, float2* out, long out_stride, hipStream_t s);
+// last inverse pass (axis-2 C2R) fused with the per-voxel reduction.
+struct Pass3Args {
+  const float2* H;     // pair arrays [n0][n1][h2]
+  long pstride;        // complex elements between pair arrays
+  int npairs;          // arrays to reduce (components / rotations)
+  int mode;            // Pass3Mode
+  const float* mu;     // P3_SCORE: multiplicities (npairs)
+  const double* stats; // [0] mean [1] var(f); msum at stats[2]
+  float eps_v;
+  float* out_score;    // P3_SCORE
+  float* out_w;        // P3_SCORE (optional) / P3_W
+  float* best;         // P3_MAX running maximum of G (unscaled)
+  int* best_idx;       // P3_MAX
+  int first_index;     // P3_MAX index of pair 0
+  int init;            // P3_MAX: 1 = first batch (ignore best/best_idx contents)
+};
+hipError_t launch_pass3(const Geo& g, const Pass3Args& a, hipStream_t s);
+// classical epilogue: ncc = best * w / V inside the valid region where w > 0
+hipError_t launch_classical_final(const Geo& g, const float* w, float* best, int* idx,
+                                  hipStream_t s);
+hipError_t launch_fill_f32(float* p, long n, float v, hipStream_t s);
+hipError_t launch_fill_i32(int* p, long n, int v, hipStream_t s);
+
+// --- template build (ttm_build.hip) -------------------------------------------
+// per-rotation masked statistics of the rotated raw template:
+// stats[j] = (mean_j, scale_j) with scale = 1/sqrt(masked variance) (0 if none)
+hipError_t launch_rot_stats(const float* tmpl, const float* mask, int L0, int L1, int L2,
+                            const float* quats, int nrot, double* rstats, hipStream_t s);
+// coef[j*K + alpha] = omega_j * Q_j^alpha * scale_j
+hipError_t launch_build_coef(const float* quats, const double* weights, const double* rstats,
+                             int nrot, int order_n, double* coef, hipStream_t s);
+// components[alpha][u] = sum_j coef[j][alpha] * m(u) (g_j(u) - mean_j)
+hipError_t launch_build_accum(const float* tmpl, const float* mask, int L0, int L1, int L2,
+                              const float* quats, const double* rstats, const double* coef,
+                              int nrot, int K, float* comps, hipStream_t s);
+// normalised rotated templates s_j for j in [j0, j0+nb) -> out[nb][L0][L1][L2]
+hipError_t launch_rot_write(const float* tmpl, const float* mask, int L0, int L1, int L2,
+                            const float* quats, const double* rstats, int j0, int nb,
+                            float* out, hipStream_t s);
+hipError_t launch_multiplicities(int order_n, float* mu, hipStream_t s);
+
+// --- peaks and pose (ttm_pose.hip) --------------------------------------------
+struct PeakWs {
+  unsigned* hist;      // 32768 bins
+  unsigned* ctrl;      // [0] candidate count [1] threshold key [2] overflow
+  unsigned long long* cand;  // capacity kCandCap
+};
+constexpr int kHistBins = 32768;
+constexpr int kCandCap = 16384;
+hipError_t launch_peaks(const Geo& g, const float* score, float threshold, float min_dist,
+                        int max_peaks, const PeakWs& w, int* out_pos, float* out_score,
+                        int* out_count, hipStream_t s);
+hipError_t launch_pose(const Geo& g, const float* image, const float* comps, const float* mask,
+                       int order_n, const double* img_stats, float eps_v, int n_seeds,
+                       int max_iter, double tol, int max_peaks, const int* pos,
+                       const int* count, float* out_quat, double* out_lambda, int* out_flags,
+                       double* out_C, double* Cbuf, hipStream_t s);
+
+}  // namespace ttm

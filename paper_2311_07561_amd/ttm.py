@@ -1,0 +1,319 @@
+"""Python binding of libttm (ctypes).  Argument marshalling only: every step of
+the matching path runs in the HIP kernels of libttm.so; PyTorch provides device
+memory and the stream.  There is no fallback: if the library is missing or the
+tensors are not on a GPU, the calls raise.
+
+Functions mirror the C ABI in include/ttm.h:
+
+* ``build_tensor_template(tmpl, mask, order, quats, weights, image_shape)``
+* ``correlate(image, bank, mask, order, opt)``
+* ``recover_pose(score, image, components, mask, order, opt)``
+* ``tm_classical(image, tmpl, mask, quats, opt)``
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libttm.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "ttm.h")
+
+TTM_OK = 0
+STATUS = {0: "TTM_OK", -1: "TTM_E_ARG", -2: "TTM_E_SIZE", -3: "TTM_E_WORKSPACE",
+          -4: "TTM_E_HIP", -5: "TTM_E_NONFINITE"}
+POSE_NOT_CONVERGED = 1
+POSE_ZERO_NORM = 2
+PEAKS_TRUNCATED = 4
+
+
+class TTMError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)}")
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_int32), ("n1", ctypes.c_int32), ("n2", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("eps_v", ctypes.c_float), ("threshold", ctypes.c_float),
+                ("min_dist", ctypes.c_float), ("max_peaks", ctypes.c_int32),
+                ("n_seeds", ctypes.c_int32), ("hopm_max_iter", ctypes.c_int32),
+                ("hopm_tol", ctypes.c_double)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_SZ = ctypes.c_size_t
+_I32 = ctypes.c_int32
+_DIMS = Dims
+_OPTP = ctypes.POINTER(Options)
+
+_SIGS = {
+    "ttm_default_options": (None, [_OPTP]),
+    "ttm_num_components": (_I32, [_I32]),
+    "ttm_supported_length": (_I32, [_I32]),
+    "ttm_status_string": (ctypes.c_char_p, [_I32]),
+    "ttm_bank_bytes": (_SZ, [_DIMS, _DIMS, _I32]),
+    "ttm_build_workspace_bytes": (_SZ, [_DIMS, _I32, _I32, _DIMS]),
+    "ttm_build_tensor_template": (_I32, [_P, _P, _DIMS, _I32, _P, _P, _I32, _P, _DIMS, _P, _P, _SZ, _P]),
+    "ttm_correlate_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32]),
+    "ttm_correlate": (_I32, [_P, _DIMS, _P, _DIMS, _I32, _P, _OPTP, _P, _P, _P, _SZ, _P]),
+    "ttm_pose_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32, _OPTP]),
+    "ttm_recover_pose": (_I32, [_P, _P, _P, _P, _DIMS, _DIMS, _I32, _OPTP, _P, _P, _P, _P, _P, _P, _P,
+                                _P, _SZ, _P]),
+    "tm_classical_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32]),
+    "tm_classical": (_I32, [_P, _DIMS, _P, _P, _DIMS, _P, _I32, _OPTP, _P, _P, _P, _SZ, _P]),
+    "ttm_profile_enable": (None, [_I32]),
+    "ttm_profile_read": (_I32, [_P, _P, _I32]),
+    "ttm_profile_class_name": (ctypes.c_char_p, [_I32]),
+}
+
+PROFILE_CLASSES = 10
+
+
+def profile_enable(on: bool = True):
+    """Record HIP event pairs around every kernel group (instrumentation)."""
+    lib().ttm_profile_enable(1 if on else 0)
+
+
+def profile_read() -> dict:
+    """Summed milliseconds and launch counts per kernel class since the last
+    read (waits for the recorded events)."""
+    ms = (ctypes.c_double * PROFILE_CLASSES)()
+    cnt = (ctypes.c_int64 * PROFILE_CLASSES)()
+    st = lib().ttm_profile_read(ctypes.cast(ms, ctypes.c_void_p), ctypes.cast(cnt, ctypes.c_void_p),
+                                PROFILE_CLASSES)
+    if st < 0:
+        raise TTMError(st, "ttm_profile_read")
+    return {lib().ttm_profile_class_name(i).decode(): (ms[i], cnt[i]) for i in range(PROFILE_CLASSES)}
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions declared in include/ttm.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"\b((?:ttm|tm)_[a-z_0-9]+)\s*\(", text)
+
+
+def lib(path: str | None = None) -> ctypes.CDLL:
+    """Load libttm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libttm.so not found at {p}: build it with "
+                           "`python -m paper_2311_07561_amd.build_lib`")
+    L = ctypes.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = L
+    return L
+
+
+def _check(status: int, what: str):
+    if status != TTM_OK:
+        raise TTMError(status, what)
+
+
+def _dims(shape) -> Dims:
+    s = tuple(int(v) for v in shape)
+    if len(s) != 3:
+        raise ValueError("expected a 3-D shape")
+    return Dims(*s)
+
+
+def _dev(t: torch.Tensor, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 tensor")
+    return t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().ttm_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def num_components(order: int) -> int:
+    k = lib().ttm_num_components(order)
+    if k < 0:
+        raise TTMError(k, "num_components")
+    return k
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def build_tensor_template(tmpl: torch.Tensor, mask: torch.Tensor, order: int, quats, weights,
+                          image_shape=None):
+    """Tensor template components (K, L0, L1, L2) and, if ``image_shape`` is
+    given, the correlation bank for images of that shape."""
+    dev = tmpl.device
+    K = num_components(order)
+    L = _dims(tmpl.shape)
+    q = torch.as_tensor(quats, dtype=torch.float32).contiguous().cpu()
+    w = torch.as_tensor(weights, dtype=torch.float64).contiguous().cpu()
+    nrot = q.shape[0]
+    if q.shape != (nrot, 4) or w.shape != (nrot,):
+        raise ValueError("quats must be (J, 4) and weights (J,)")
+    comps = torch.empty((K,) + tuple(tmpl.shape), dtype=torch.float32, device=dev)
+    N = _dims(image_shape) if image_shape is not None else Dims(0, 0, 0)
+    bank = None
+    if image_shape is not None:
+        nb = lib().ttm_bank_bytes(N, L, K)
+        bank = torch.empty(nb, dtype=torch.uint8, device=dev)
+    nws = lib().ttm_build_workspace_bytes(L, order, nrot, N)
+    ws = _workspace(nws, dev)
+    st = lib().ttm_build_tensor_template(
+        _dev(tmpl, "tmpl"), _dev(mask, "mask"), L, order, q.data_ptr(), w.data_ptr(), nrot,
+        comps.data_ptr(), N, bank.data_ptr() if bank is not None else None, ws.data_ptr(), nws,
+        _stream(dev))
+    _check(st, "ttm_build_tensor_template")
+    return comps, bank
+
+
+def correlate(image: torch.Tensor, bank: torch.Tensor, mask: torch.Tensor, order: int,
+              opt: Options | None = None, want_w: bool = True, workspace: torch.Tensor | None = None,
+              out=None):
+    """Frobenius score map F(x) and local normaliser w(x).  ``out`` may give
+    preallocated (score, w) tensors (w may be None)."""
+    dev = image.device
+    K = num_components(order)
+    N = _dims(image.shape)
+    L = _dims(mask.shape)
+    opt = opt or default_options()
+    if out is not None:
+        score, w = out
+        _dev(score, "score")
+        if w is not None:
+            _dev(w, "w")
+    else:
+        score = torch.empty_like(image)
+        w = torch.empty_like(image) if want_w else None
+    nws = lib().ttm_correlate_workspace_bytes(N, L, K)
+    ws = workspace if workspace is not None and workspace.numel() >= nws else _workspace(nws, dev)
+    st = lib().ttm_correlate(_dev(image, "image"), N, bank.data_ptr(), L, order, _dev(mask, "mask"),
+                             ctypes.byref(opt), score.data_ptr(),
+                             w.data_ptr() if w is not None else None, ws.data_ptr(), ws.numel(),
+                             _stream(dev))
+    _check(st, "ttm_correlate")
+    return score, w
+
+
+def correlate_workspace(image_shape, L, order, device) -> torch.Tensor:
+    K = num_components(order)
+    return _workspace(lib().ttm_correlate_workspace_bytes(_dims(image_shape), _dims(L), K), device)
+
+
+def recover_pose(score: torch.Tensor, image: torch.Tensor, components: torch.Tensor,
+                 mask: torch.Tensor, order: int, opt: Options | None = None, want_C: bool = True):
+    """Peaks of F and the dominant Z-eigenpair of C_n at each.  Returns a dict
+    of device tensors trimmed to the number of peaks found (one sync)."""
+    dev = score.device
+    K = num_components(order)
+    N = _dims(score.shape)
+    L = _dims(mask.shape)
+    opt = opt or default_options()
+    P = int(opt.max_peaks)
+    pos = torch.zeros((P, 3), dtype=torch.int32, device=dev)
+    quat = torch.zeros((P, 4), dtype=torch.float32, device=dev)
+    lam = torch.zeros((P,), dtype=torch.float64, device=dev)
+    pscore = torch.zeros((P,), dtype=torch.float32, device=dev)
+    flags = torch.zeros((P,), dtype=torch.int32, device=dev)
+    C = torch.zeros((P, K), dtype=torch.float64, device=dev) if want_C else None
+    count = torch.zeros((2,), dtype=torch.int32, device=dev)
+    nws = lib().ttm_pose_workspace_bytes(N, L, order, ctypes.byref(opt))
+    ws = _workspace(nws, dev)
+    st = lib().ttm_recover_pose(_dev(score, "score"), _dev(image, "image"), _dev(components, "components"),
+                                _dev(mask, "mask"), N, L, order, ctypes.byref(opt), pos.data_ptr(),
+                                quat.data_ptr(), lam.data_ptr(), pscore.data_ptr(), flags.data_ptr(),
+                                C.data_ptr() if C is not None else None, count.data_ptr(), ws.data_ptr(),
+                                nws, _stream(dev))
+    _check(st, "ttm_recover_pose")
+    cnt = count.cpu()
+    n = int(cnt[0])
+    out = dict(pos=pos[:n], quat=quat[:n], lam=lam[:n], score=pscore[:n], flags=flags[:n],
+               truncated=bool(int(cnt[1]) & PEAKS_TRUNCATED), count=n)
+    if C is not None:
+        out["C"] = C[:n]
+    return out
+
+
+class PoseBuffers:
+    """Preallocated outputs and workspace of ``recover_pose_async``."""
+
+    def __init__(self, opt: Options, K: int, device):
+        P = int(opt.max_peaks)
+        self.pos = torch.zeros((P, 3), dtype=torch.int32, device=device)
+        self.quat = torch.zeros((P, 4), dtype=torch.float32, device=device)
+        self.lam = torch.zeros((P,), dtype=torch.float64, device=device)
+        self.score = torch.zeros((P,), dtype=torch.float32, device=device)
+        self.flags = torch.zeros((P,), dtype=torch.int32, device=device)
+        self.C = torch.zeros((P, K), dtype=torch.float64, device=device)
+        self.count = torch.zeros((2,), dtype=torch.int32, device=device)
+        self.ws = _workspace(1 << 20, device)
+
+    def result(self) -> dict:
+        cnt = self.count.cpu()
+        n = int(cnt[0])
+        return dict(pos=self.pos[:n], quat=self.quat[:n], lam=self.lam[:n], score=self.score[:n],
+                    flags=self.flags[:n], C=self.C[:n], count=n,
+                    truncated=bool(int(cnt[1]) & PEAKS_TRUNCATED))
+
+
+def recover_pose_async(score: torch.Tensor, image: torch.Tensor, components: torch.Tensor,
+                       mask: torch.Tensor, order: int, opt: Options, bufs: PoseBuffers):
+    """``recover_pose`` into preallocated buffers, without synchronising."""
+    dev = score.device
+    N = _dims(score.shape)
+    L = _dims(mask.shape)
+    nws = lib().ttm_pose_workspace_bytes(N, L, order, ctypes.byref(opt))
+    if bufs.ws.numel() < nws:
+        bufs.ws = _workspace(nws, dev)
+    st = lib().ttm_recover_pose(_dev(score, "score"), _dev(image, "image"), _dev(components, "components"),
+                                _dev(mask, "mask"), N, L, order, ctypes.byref(opt), bufs.pos.data_ptr(),
+                                bufs.quat.data_ptr(), bufs.lam.data_ptr(), bufs.score.data_ptr(),
+                                bufs.flags.data_ptr(), bufs.C.data_ptr(), bufs.count.data_ptr(),
+                                bufs.ws.data_ptr(), bufs.ws.numel(), _stream(dev))
+    _check(st, "ttm_recover_pose")
+
+
+def tm_classical(image: torch.Tensor, tmpl: torch.Tensor, mask: torch.Tensor, quats,
+                 opt: Options | None = None):
+    """Best NCC over the rotation list and its index, per voxel."""
+    dev = image.device
+    N = _dims(image.shape)
+    L = _dims(tmpl.shape)
+    q = torch.as_tensor(quats, dtype=torch.float32).contiguous().cpu()
+    nrot = q.shape[0]
+    opt = opt or default_options()
+    best = torch.empty_like(image)
+    idx = torch.empty(image.shape, dtype=torch.int32, device=dev)
+    nws = lib().tm_classical_workspace_bytes(N, L, nrot)
+    ws = _workspace(nws, dev)
+    st = lib().tm_classical(_dev(image, "image"), N, _dev(tmpl, "tmpl"), _dev(mask, "mask"), L,
+                            q.data_ptr(), nrot, ctypes.byref(opt), best.data_ptr(), idx.data_ptr(),
+                            ws.data_ptr(), nws, _stream(dev))
+    _check(st, "tm_classical")
+    return best, idx

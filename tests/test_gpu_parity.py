@@ -1,0 +1,230 @@
+"""Parity of the HIP path (called through the C ABI) with the FP64 oracle.
+
+Tolerances: score F abs <= 1e-4 (float32 FFT path against float64 direct
+sums); components and w relative 1e-5 / 1e-4; peak positions bit-exact when
+the oracle's peak picking runs on the GPU's own float32 score map (so that both
+sides take the local-maximum decisions on the same values); recovered rotation
+<= 1 degree except where the dominant eigenvalue is ambiguous.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ttm_oracle as O
+from paper_2311_07561_amd import synth, ttm
+
+pytestmark = pytest.mark.gpu
+
+SCORE_TOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ttm.lib()   # raises if the library is missing: no fallback
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def box_mask(L, r):
+    c = np.array(L) // 2
+    g = np.meshgrid(*[np.arange(l) - c[i] for i, l in enumerate(L)], indexing="ij")
+    return (np.sqrt(g[0] ** 2 + g[1] ** 2 + g[2] ** 2) < r).astype(np.float32)
+
+
+def rand_setup(seed, N, L, r, nrot):
+    rng = np.random.default_rng(seed)
+    img = rng.standard_normal(N).astype(np.float32)
+    tm = synth.make_blob_template(rng, max(L), 4, min(L) / 2)
+    c = np.array(L) // 2
+    g = np.meshgrid(*[np.arange(l, dtype=np.float64) - c[i] for i, l in enumerate(L)], indexing="ij")
+    tmpl = tm.evaluate(np.stack(g, axis=-1)).astype(np.float32)
+    mask = box_mask(L, r)
+    q = synth.random_quaternions(rng, nrot).astype(np.float32)
+    w = rng.uniform(0.5, 1.5, nrot)
+    w /= w.sum()
+    return img, tmpl, mask, q, w
+
+
+def oracle_T(tmpl, mask, n, q, w):
+    return O.tensor_template(tmpl.astype(np.float64), mask.astype(np.float64), n,
+                             q.astype(np.float64), w)
+
+
+@pytest.mark.parametrize("n,L", [(2, (9, 8, 10)), (4, (8, 8, 8)), (6, (7, 6, 7))])
+def test_components_match_oracle(n, L):
+    img, tmpl, mask, q, w = rand_setup(100 + n, (32, 32, 32), L, 3.2, 40)
+    comps, _ = ttm.build_tensor_template(dev(tmpl), dev(mask), n, q, w)
+    T = oracle_T(tmpl, mask, n, q, w)
+    got = comps.cpu().numpy().astype(np.float64)
+    assert got.shape == T.shape
+    assert np.abs(got - T).max() <= 1e-5 * max(1.0, np.abs(T).max()), np.abs(got - T).max()
+
+
+@pytest.mark.parametrize("N,L,n,r", [
+    ((32, 32, 32), (8, 8, 8), 4, 4.0),
+    ((16, 64, 32), (9, 7, 10), 2, 3.5),
+    ((32, 16, 64), (7, 12, 5), 2, 2.6),
+    ((64, 32, 16), (11, 6, 9), 6, 3.0),
+])
+def test_correlate_full_map(N, L, n, r):
+    img, tmpl, mask, q, w = rand_setup(7 + n, N, L, r, 24)
+    # structure: plant a rotated template copy so that scores are not all noise
+    s = O.rotated_template(tmpl, mask, q[3])
+    c = np.array(L) // 2
+    x0 = np.array(N) // 2
+    sl = tuple(slice(x0[i] - c[i], x0[i] - c[i] + L[i]) for i in range(3))
+    img[sl] += 3.0 * np.sqrt(mask.sum()) * s.astype(np.float32)
+    comps, bank = ttm.build_tensor_template(dev(tmpl), dev(mask), n, q, w, image_shape=N)
+    score, wv = ttm.correlate(dev(img), bank, dev(mask), n)
+    T = oracle_T(tmpl, mask, n, q, w)
+    F_ref = O.score_map(img.astype(np.float64), T, mask.astype(np.float64), n)
+    w_ref = O.w_map(img.astype(np.float64), mask.astype(np.float64))
+    F = score.cpu().numpy()
+    W = wv.cpu().numpy()
+    assert np.abs(F - F_ref).max() <= SCORE_TOL, np.abs(F - F_ref).max()
+    assert np.allclose(W, w_ref, rtol=1e-4, atol=0), np.abs(W - w_ref).max()
+    vm = O.valid_mask(N, L)
+    assert np.all(F[~vm] == 0) and np.all(W[~vm] == 0)
+    assert F[tuple(x0)] > 0.5 * F.max()
+
+
+def test_single_valid_voxel_and_longest_axis():
+    # N = L: exactly one valid position; and a 512-long axis
+    img, tmpl, mask, q, w = rand_setup(3, (16, 16, 16), (16, 16, 16), 7.5, 10)
+    comps, bank = ttm.build_tensor_template(dev(tmpl), dev(mask), 2, q, w, image_shape=(16, 16, 16))
+    score, wv = ttm.correlate(dev(img), bank, dev(mask), 2)
+    T = oracle_T(tmpl, mask, 2, q, w)
+    F_ref = O.score_map(img.astype(np.float64), T, mask.astype(np.float64), 2)
+    F = score.cpu().numpy()
+    assert (F != 0).sum() == 1 and F[8, 8, 8] > 0
+    assert abs(F[8, 8, 8] - F_ref[8, 8, 8]) <= SCORE_TOL
+    img, tmpl, mask, q, w = rand_setup(4, (512, 16, 32), (5, 6, 7), 2.6, 8)
+    comps, bank = ttm.build_tensor_template(dev(tmpl), dev(mask), 2, q, w, image_shape=(512, 16, 32))
+    score, _ = ttm.correlate(dev(img), bank, dev(mask), 2)
+    T = oracle_T(tmpl, mask, 2, q, w)
+    rng = np.random.default_rng(5)
+    lo, hi = O.valid_region((512, 16, 32), (5, 6, 7))
+    xs = np.stack([rng.integers(lo[i], hi[i], 300) for i in range(3)], axis=1)
+    C = O.tensor_field_at(img.astype(np.float64), T, mask.astype(np.float64), xs)
+    ref = O.score_from_field(C, 2)
+    got = score.cpu().numpy()[xs[:, 0], xs[:, 1], xs[:, 2]]
+    assert np.abs(got - ref).max() <= SCORE_TOL
+
+
+def test_classical_matches_oracle():
+    img, tmpl, mask, q, w = rand_setup(21, (32, 32, 32), (8, 8, 8), 4.0, 40)
+    k = 17
+    s = O.rotated_template(tmpl, mask, q[k])
+    sl = tuple(slice(16 - 4, 16 + 4) for _ in range(3))
+    img[sl] += 4.0 * np.sqrt(mask.sum()) * s.astype(np.float32)
+    best, idx = ttm.tm_classical(dev(img), dev(tmpl), dev(mask), q)
+    vm = O.valid_mask((32, 32, 32), (8, 8, 8))
+    xs = np.argwhere(vm)
+    c = O.classical_ncc_at(img.astype(np.float64), tmpl.astype(np.float64), mask.astype(np.float64),
+                           q.astype(np.float64), xs)
+    ref_best = c.max(axis=1)
+    ref_idx = c.argmax(axis=1)
+    srt = np.sort(c, axis=1)
+    gap = srt[:, -1] - srt[:, -2]
+    B = best.cpu().numpy()
+    I = idx.cpu().numpy()
+    assert np.abs(B[vm] - ref_best).max() <= SCORE_TOL
+    clear = gap > 1e-4
+    assert np.array_equal(I[vm][clear], ref_idx[clear])
+    assert np.all(B[~vm] == 0) and np.all(I[~vm] == -1)
+    assert I[16, 16, 16] == k and B[16, 16, 16] > 0.9
+    assert np.all(np.abs(B) <= 1 + 1e-5)
+
+
+def test_small_workload_end_to_end():
+    """64^3 image, 16^3 template, order 2: full score map, peaks, C at the
+    peaks and the recovered rotations against the oracle."""
+    wl = synth.workload_small()
+    n = wl.order
+    q = synth.super_fibonacci(500).astype(np.float32)
+    wts = np.full(len(q), 1.0 / len(q))
+    comps, bank = ttm.build_tensor_template(dev(wl.template), dev(wl.mask), n, q, wts,
+                                            image_shape=wl.image.shape)
+    score, _ = ttm.correlate(dev(wl.image), bank, dev(wl.mask), n)
+    T = oracle_T(wl.template, wl.mask, n, q, wts)
+    f64 = wl.image.astype(np.float64)
+    F_ref = O.score_map(f64, T, wl.mask.astype(np.float64), n)
+    F = score.cpu().numpy()
+    assert np.abs(F - F_ref).max() <= SCORE_TOL
+    opt = ttm.default_options(max_peaks=8, min_dist=8.0, threshold=0.0)
+    res = ttm.recover_pose(score, dev(wl.image), comps, dev(wl.mask), n, opt)
+    # peaks: the oracle's picking on the same float32 map
+    ref_peaks = O.find_peaks_fast(F, wl.template.shape, 0.0, 8.0, 8)
+    got_peaks = res["pos"].cpu().numpy()
+    assert np.array_equal(got_peaks, ref_peaks)
+    # and on its own float64 map, away from near-ties
+    own = O.find_peaks_fast(F_ref, wl.template.shape, 0.0, 8.0, 3)
+    assert np.array_equal(own, got_peaks[:3])
+    # the three planted copies are the top three peaks
+    planted = {tuple(p) for p in wl.positions}
+    assert {tuple(p) for p in got_peaks[:3]} == planted
+    # tensor at the peaks
+    C_ref = O.tensor_field_at(f64, T, wl.mask.astype(np.float64), got_peaks)
+    C = res["C"].cpu().numpy()
+    assert np.abs(C - C_ref).max() <= 1e-5 * np.abs(C_ref).max()
+    # rotations: GPU eigenvector vs the oracle's dominant Z-eigenpair
+    quats = res["quat"].cpu().numpy()
+    lam = res["lam"].cpu().numpy()
+    for i in range(len(got_peaks)):
+        qo, lo, second = O.dominant_z_eigenpair(C_ref[i], n, n_brute=100000)
+        assert abs(lam[i] - lo) <= 1e-6 * abs(lo) + 1e-9
+        if second > lo - 1e-3 * abs(lo):
+            continue        # ambiguous: a second maximum as high as the first
+        assert O.rotation_angle_deg(quats[i], qo) <= 1.0
+    assert np.all((res["flags"].cpu().numpy() & ttm.POSE_NOT_CONVERGED) == 0)
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_pose_high_order(n):
+    img, tmpl, mask, q, w = rand_setup(40 + n, (32, 32, 32), (8, 8, 8), 4.0, 64)
+    s = O.rotated_template(tmpl, mask, q[5])
+    sl = tuple(slice(14 - 4, 14 + 4) for _ in range(3))
+    img[sl] += 3.0 * np.sqrt(mask.sum()) * s.astype(np.float32)
+    comps, bank = ttm.build_tensor_template(dev(tmpl), dev(mask), n, q, w, image_shape=(32, 32, 32))
+    score, _ = ttm.correlate(dev(img), bank, dev(mask), n)
+    opt = ttm.default_options(max_peaks=3, min_dist=6.0)
+    res = ttm.recover_pose(score, dev(img), comps, dev(mask), n, opt)
+    pos = res["pos"].cpu().numpy()
+    assert tuple(pos[0]) == (14, 14, 14)
+    T = oracle_T(tmpl, mask, n, q, w)
+    C_ref = O.tensor_field_at(img.astype(np.float64), T, mask.astype(np.float64), pos)
+    assert np.abs(res["C"].cpu().numpy() - C_ref).max() <= 1e-5 * np.abs(C_ref).max()
+    qo, lo, second = O.dominant_z_eigenpair(C_ref[0], n, n_brute=100000)
+    lam = res["lam"].cpu().numpy()[0]
+    assert abs(lam - lo) <= 1e-6 * abs(lo) + 1e-9
+    if second < lo - 1e-3 * abs(lo):
+        assert O.rotation_angle_deg(res["quat"].cpu().numpy()[0], qo) <= 1.0
+
+
+def test_tomogram_sampled_parity():
+    """The benchmarked size: 256^3, 32^3 template, order 4 (35 components),
+    checked at the planted centres and at random valid voxels."""
+    wl = synth.workload_tomogram()
+    n = wl.order
+    q = synth.super_fibonacci(300).astype(np.float32)
+    wts = np.full(len(q), 1.0 / len(q))
+    comps, bank = ttm.build_tensor_template(dev(wl.template), dev(wl.mask), n, q, wts,
+                                            image_shape=wl.image.shape)
+    score, wv = ttm.correlate(dev(wl.image), bank, dev(wl.mask), n)
+    T = oracle_T(wl.template, wl.mask, n, q, wts)
+    rng = np.random.default_rng(9)
+    lo, hi = O.valid_region(wl.image.shape, wl.template.shape)
+    xs = np.concatenate([wl.positions,
+                         np.stack([rng.integers(lo[i], hi[i], 200) for i in range(3)], axis=1)])
+    f64 = wl.image.astype(np.float64)
+    C = O.tensor_field_at(f64, T, wl.mask.astype(np.float64), xs)
+    ref = O.score_from_field(C, n)
+    got = score.cpu().numpy()[xs[:, 0], xs[:, 1], xs[:, 2]]
+    assert np.abs(got - ref).max() <= SCORE_TOL, np.abs(got - ref).max()
+    wref = O.local_norm_at(f64, wl.mask.astype(np.float64), xs)
+    wgot = wv.cpu().numpy()[xs[:, 0], xs[:, 1], xs[:, 2]]
+    assert np.allclose(wgot, wref, rtol=1e-4)
