@@ -150,20 +150,23 @@ def tensor_apply(A: np.ndarray, n: int, q: np.ndarray) -> float:
     return float(np.dot(multiplicities(n) * A, monomials(q, n)))
 
 
+def _safe_pow(q: np.ndarray, e: np.ndarray) -> np.ndarray:
+    """prod_d q_d^e_d per row of exponents, with negative exponents giving 0
+    (they only occur with a zero coefficient)."""
+    return np.prod(np.where(e >= 0, q[None, :] ** np.maximum(e, 0), 0.0), axis=1)
+
+
 def tensor_apply_nm1(A: np.ndarray, n: int, q: np.ndarray) -> np.ndarray:
     """``A x^{n-1}``: the vector with ``(A x^{n-1})_i = (1/n) d(A x^n)/dx_i``
     (Section 3.1, the gradient identity)."""
     q = np.asarray(q, dtype=np.float64)
     al = multi_indices(n)
-    mu = multiplicities(n)
+    c = multiplicities(n) * np.asarray(A, dtype=np.float64)
     out = np.zeros(4)
-    for k, a in enumerate(al):
-        for i in range(4):
-            if a[i] == 0:
-                continue
-            e = a.copy()
-            e[i] -= 1
-            out[i] += mu[k] * A[k] * a[i] / n * np.prod(q ** e)
+    for i in range(4):
+        e = al.copy()
+        e[:, i] -= 1
+        out[i] = np.sum(c * al[:, i] / n * _safe_pow(q, e))
     return out
 
 
@@ -171,18 +174,15 @@ def tensor_apply_nm2(A: np.ndarray, n: int, q: np.ndarray) -> np.ndarray:
     """``A x^{n-2}``: the 4x4 matrix with Hessian ``n (n-1) A x^{n-2}``."""
     q = np.asarray(q, dtype=np.float64)
     al = multi_indices(n)
-    mu = multiplicities(n)
+    c = multiplicities(n) * np.asarray(A, dtype=np.float64)
     out = np.zeros((4, 4))
-    for k, a in enumerate(al):
-        for i in range(4):
-            for j in range(4):
-                e = a.copy()
-                e[i] -= 1
-                e[j] -= 1
-                coef = a[i] * (a[j] - (1 if i == j else 0))
-                if coef == 0 or np.any(e < 0):
-                    continue
-                out[i, j] += mu[k] * A[k] * coef / (n * (n - 1)) * np.prod(q ** e)
+    for i in range(4):
+        for j in range(4):
+            e = al.copy()
+            e[:, i] -= 1
+            e[:, j] -= 1
+            coef = al[:, i] * (al[:, j] - (1 if i == j else 0))
+            out[i, j] = np.sum(c * coef / (n * (n - 1)) * _safe_pow(q, e))
     return out
 
 
