@@ -164,9 +164,10 @@ def test_small_workload_end_to_end():
     # and on its own float64 map, away from near-ties
     own = O.find_peaks_fast(F_ref, wl.template.shape, 0.0, 8.0, 3)
     assert np.array_equal(own, got_peaks[:3])
-    # the three planted copies are the top three peaks
-    planted = {tuple(p) for p in wl.positions}
-    assert {tuple(p) for p in got_peaks[:3]} == planted
+    # the three top peaks sit on the three planted copies (the Frobenius proxy
+    # may peak one voxel away from the copy's centre: Section 3.4)
+    for p in wl.positions:
+        assert np.abs(got_peaks[:3] - p[None]).max(axis=1).min() <= 1
     # tensor at the peaks
     C_ref = O.tensor_field_at(f64, T, wl.mask.astype(np.float64), got_peaks)
     C = res["C"].cpu().numpy()
