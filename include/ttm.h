@@ -64,6 +64,11 @@ typedef struct {
   int32_t n_seeds;       /* S^3 seed points scanned before SS-HOPM (64..65536) */
   int32_t hopm_max_iter; /* SS-HOPM iteration cap                              */
   double hopm_tol;       /* stop when |d lambda| <= tol * max(1, |lambda|)     */
+  int32_t refine;        /* 0: pose at each candidate as found; 1: move each
+                            candidate to the voxel of its 3x3x3 neighbourhood
+                            with the largest dominant Z-eigenvalue (the
+                            spectral norm the Frobenius score stands in for,
+                            Section 3.4); default 0                            */
 } ttm_options;
 
 /* Pose flags (bit set in out_flags). */
@@ -73,7 +78,7 @@ typedef struct {
                                       than max_peaks may have been accepted   */
 
 /* Fills *opt with the defaults (eps_v 1e-5, threshold 0, min_dist 8,
- * max_peaks 64, n_seeds 4096, hopm_max_iter 1000, hopm_tol 1e-12). */
+ * max_peaks 64, n_seeds 4096, hopm_max_iter 1000, hopm_tol 1e-12, refine 0). */
 void ttm_default_options(ttm_options* opt);
 
 /* Number of independent components of a symmetric tensor of order n on R^4:
@@ -160,8 +165,11 @@ ttm_status ttm_correlate(
  * At each peak the tensor C_n(x) is recomputed directly in float64 from the
  * image window and the components (two-pass local variance), and its dominant
  * Z-eigenpair (max C Q^n on |Q| = 1, eq. "Zeigen") is found by a scan of
- * n_seeds S^3 points followed by SS-HOPM from the 4 best (adaptive shift); by
- * Theorem "main" the eigenvector is the rotation of the match.
+ * n_seeds S^3 points, each of 64 lanes polishing its own best seed with
+ * Newton steps on the sphere that fall back to a shifted power step (SS-HOPM)
+ * whenever they do not increase lambda; by Theorem "main" the eigenvector is
+ * the rotation of the match.  With opt->refine = 1 this is done at the 27
+ * voxels around each peak and the one with the largest lambda is reported.
  *
  *   score            [n0][n1][n2] float32 from ttm_correlate
  *   image            the correlated image; components: K x [L0][L1][L2] float32
@@ -180,10 +188,41 @@ ttm_status ttm_correlate(
  * ------------------------------------------------------------------------- */
 size_t ttm_pose_workspace_bytes(ttm_dims N, ttm_dims L, int32_t order_n,
                                 const ttm_options* opt);
+/* Pose at caller-given positions (no peak search): the same tensor and
+ * eigenpair computation as ttm_recover_pose at n_pos positions
+ * (positions: n_pos x 3 int32 device array, each inside the valid region, else
+ * its lambda is -inf and its flags TTM_POSE_ZERO_NORM), with opt->refine as
+ * there.  out_pos receives the (refined) positions; out_C may be NULL.
+ * n_pos <= opt->max_peaks; workspace from ttm_pose_workspace_bytes. */
+ttm_status ttm_pose_at(
+    const float* image, const float* components, const float* mask,
+    ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt,
+    const int32_t* positions, int32_t n_pos, int32_t* out_pos,
+    float* out_quat, double* out_lambda, int32_t* out_flags, double* out_C,
+    void* ws, size_t ws_bytes, hipStream_t stream);
 ttm_status ttm_recover_pose(
     const float* score, const float* image, const float* components,
     const float* mask, ttm_dims N, ttm_dims L, int32_t order_n,
     const ttm_options* opt, int32_t* out_pos, float* out_quat,
+    double* out_lambda, float* out_peak_score, int32_t* out_flags,
+    double* out_C, int32_t* out_count, void* ws, size_t ws_bytes,
+    hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * The whole per-tomogram path in one call (Sections 2, 3.2-3.4): the
+ * correlation of ttm_correlate, the peaks of ttm_recover_pose, and the pose at
+ * each peak with C_n(x) taken from the correlated tensor field itself (the K
+ * transformed arrays are evaluated at the candidate voxels by a point inverse
+ * DFT of their last axis, times w(x)) instead of being recomputed from the
+ * image window.  Arguments as in ttm_correlate and ttm_recover_pose; out_w
+ * and out_C may be NULL.  Workspace from ttm_match_workspace_bytes.
+ * ------------------------------------------------------------------------- */
+size_t ttm_match_workspace_bytes(ttm_dims N, ttm_dims L, int32_t order_n,
+                                 const ttm_options* opt);
+ttm_status ttm_match(
+    const float* image, ttm_dims N, const void* bank, ttm_dims L,
+    int32_t order_n, const float* mask, const ttm_options* opt,
+    float* out_score, float* out_w, int32_t* out_pos, float* out_quat,
     double* out_lambda, float* out_peak_score, int32_t* out_flags,
     double* out_C, int32_t* out_count, void* ws, size_t ws_bytes,
     hipStream_t stream);

@@ -559,3 +559,36 @@ def dominant_z_eigenpair(A: np.ndarray, n: int, n_brute: int = 200000,
         if rotation_angle_deg(q, best_q) > 5.0:
             second = max(second, lam)
     return best_q, best_lam, second
+
+
+def neighbourhood_offsets() -> np.ndarray:
+    """The 27 offsets of a 3x3x3 neighbourhood, index k = 9 (d0+1) + 3 (d1+1) + (d2+1)."""
+    return np.array([(k // 9 - 1, (k // 3) % 3 - 1, k % 3 - 1) for k in range(27)], dtype=np.int64)
+
+
+def refine_by_eigenvalue(f, T, m, n: int, x, eps_v: float = EPS_V_DEFAULT,
+                         n_brute: int = 100000):
+    """Reading of Section 3.4: the Frobenius norm stands in for the spectral
+    norm ``||C_n(x)||_sigma = max_Q |C_n(x) Q^n|``; a candidate position is moved
+    to the voxel of its 3x3x3 neighbourhood (inside the valid region) whose
+    dominant Z-eigenvalue is largest (the centre first on ties, then the lower
+    neighbour index).  Returns (position, q, lambda, lambdas of the 27 voxels)."""
+    N = np.shape(f)
+    L = np.shape(T)[1:]
+    lo, hi = valid_region(N, L)
+    offs = neighbourhood_offsets()
+    lams = np.full(27, -np.inf)
+    qs = np.zeros((27, 4))
+    for k, o in enumerate(offs):
+        y = np.asarray(x) + o
+        if np.any(y < lo) or np.any(y >= hi):
+            continue
+        C = tensor_field_at(f, T, m, y[None], eps_v)[0]
+        q, lam, _ = dominant_z_eigenpair(C, n, n_brute=n_brute)
+        lams[k] = lam
+        qs[k] = q
+    best = 13
+    for k in range(27):
+        if lams[k] > lams[best]:
+            best = k
+    return np.asarray(x) + offs[best], qs[best], lams[best], lams

@@ -98,10 +98,11 @@ struct ProfScope {
 
 // ---- layouts ----------------------------------------------------------------
 struct BuildWs {
-  float* quats; double* weights; double* rstats; double* coef;
+  float* quats; double* weights; double* rstats; double* coef; float* rtab;
 };
 static BuildWs build_layout(Carve& c, int nrot, int K) {
   BuildWs w;
+  w.rtab = c.take<float>((size_t)nrot * 9);
   w.quats = c.take<float>((size_t)nrot * 4);
   w.weights = c.take<double>((size_t)nrot);
   w.rstats = c.take<double>((size_t)nrot * 2);
@@ -124,15 +125,27 @@ static CorrWs corr_layout(Carve& c, const Geo& g, int K) {
 }
 
 struct PoseWs {
-  unsigned* hist; unsigned* ctrl; unsigned long long* cand; double* stats; double* partials;
+  unsigned* hist; unsigned* ctrl; unsigned long long* allc; unsigned long long* cand; double* stats;
+  double* partials; int* cand_pos; double* seeds; PoseScratch ps;
 };
-static PoseWs pose_layout(Carve& c) {
+static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refine, int n_seeds) {
   PoseWs w;
+  const size_t nb = (size_t)max_peaks * (refine ? 27 : 1);
   w.hist = c.take<unsigned>(kHistBins);
-  w.ctrl = c.take<unsigned>(4);
+  w.ctrl = c.take<unsigned>(16);
+  w.allc = c.take<unsigned long long>((size_t)peaks_bigcap(g));
   w.cand = c.take<unsigned long long>(kCandCap);
+  w.seeds = c.take<double>((size_t)n_seeds * 4);
+  w.ps.seeds = w.seeds;
   w.stats = c.take<double>(4);
   w.partials = c.take<double>(2 * 512);
+  w.cand_pos = c.take<int>((size_t)max_peaks * 3);
+  w.ps.C = c.take<double>(nb * (size_t)K);
+  w.ps.w = c.take<double>(nb);
+  w.ps.ok = c.take<int>(nb);
+  w.ps.q = c.take<float>(nb * 4);
+  w.ps.lam = c.take<double>(nb);
+  w.ps.flags = c.take<int>(nb);
   return w;
 }
 
@@ -202,6 +215,7 @@ void ttm_default_options(ttm_options* o) {
   o->n_seeds = 4096;
   o->hopm_max_iter = 1000;
   o->hopm_tol = 1e-12;
+  o->refine = 0;
 }
 
 int32_t ttm_num_components(int32_t n) {
@@ -267,7 +281,7 @@ ttm_status ttm_build_tensor_template(const float* tmpl, const float* mask, ttm_d
   TTM_PROF(PC_BUILD, launch_rot_stats(tmpl, mask, L.n0, L.n1, L.n2, w.quats, n_rot, w.rstats, stream));
   TTM_PROF(PC_BUILD, launch_build_coef(w.quats, w.weights, w.rstats, n_rot, order_n, w.coef, stream));
   TTM_PROF(PC_BUILD, launch_build_accum(tmpl, mask, L.n0, L.n1, L.n2, w.quats, w.rstats, w.coef, n_rot, K, out_components,
-                             stream));
+                             w.rtab, stream));
   if (out_bank) {
     const Geo g = make_geo(N, L);
     float2* bank = static_cast<float2*>(out_bank);
@@ -284,6 +298,32 @@ size_t ttm_correlate_workspace_bytes(ttm_dims N, ttm_dims L, int32_t K) {
   return c.size();
 }
 
+static ttm_status correlate_into(const Geo& g, int order_n, int K, const float* image, const float2* bk,
+                                 const float* mask, float eps_v, float* out_score, float* out_w, CorrWs& w,
+                                 hipStream_t stream) {
+  const long half = g.half();
+  TTM_PROF(PC_STATS, launch_multiplicities(order_n, w.mu, stream));
+  TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream));
+  TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, bk, g.bank_slab(), K + 1, w.H, half, stream));
+  TTM_PROF(PC_PASS1, launch_pass1(g, w.Xg, bk + (long)K * g.bank_slab(), g.bank_slab(), 1,
+                                  w.H + (long)(K + 1) * half, half, stream));
+  TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.h2, g.h2, (long)g.n1 * g.h2, g.h2, g.n1,
+                                      g.c1, K + 2, half, stream));
+  Pass3Args a;
+  std::memset(&a, 0, sizeof(a));
+  a.H = w.H;
+  a.pstride = half;
+  a.npairs = K;
+  a.mode = P3_SCORE;
+  a.mu = w.mu;
+  a.stats = w.stats;
+  a.eps_v = eps_v;
+  a.out_score = out_score;
+  a.out_w = out_w;
+  TTM_PROF(PC_PASS3, launch_pass3(g, a, stream));
+  return TTM_OK;
+}
+
 ttm_status ttm_correlate(const float* image, ttm_dims N, const void* bank, ttm_dims L, int32_t order_n,
                          const float* mask, const ttm_options* opt, float* out_score, float* out_w, void* ws,
                          size_t ws_bytes, hipStream_t stream) {
@@ -296,34 +336,25 @@ ttm_status ttm_correlate(const float* image, ttm_dims N, const void* bank, ttm_d
   const Geo g = make_geo(N, L);
   Carve c(ws);
   CorrWs w = corr_layout(c, g, K);
-  const float2* bk = static_cast<const float2*>(bank);
-  const long half = g.half();
-  TTM_PROF(PC_STATS, launch_multiplicities(order_n, w.mu, stream));
-  TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream));
-  TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, bk, g.bank_slab(), K + 1, w.H, half, stream));
-  TTM_PROF(PC_PASS1, launch_pass1(g, w.Xg, bk + (long)K * g.bank_slab(), g.bank_slab(), 1, w.H + (long)(K + 1) * half, half,
-                       stream));
-  TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.h2, g.h2, (long)g.n1 * g.h2, g.h2, g.n1, g.c1, K + 2,
-                         half, stream));
-  Pass3Args a;
-  std::memset(&a, 0, sizeof(a));
-  a.H = w.H;
-  a.pstride = half;
-  a.npairs = K;
-  a.mode = P3_SCORE;
-  a.mu = w.mu;
-  a.stats = w.stats;
-  a.eps_v = opt->eps_v;
-  a.out_score = out_score;
-  a.out_w = out_w;
-  TTM_PROF(PC_PASS3, launch_pass3(g, a, stream));
-  return TTM_OK;
+  return correlate_into(g, order_n, K, image, static_cast<const float2*>(bank), mask, opt->eps_v, out_score,
+                        out_w, w, stream);
+}
+
+static bool pose_opts_ok(const ttm_options* opt) {
+  if (opt->max_peaks < 1 || opt->max_peaks > 4096) return false;
+  if (opt->n_seeds < 64 || opt->n_seeds > 65536) return false;
+  if (opt->hopm_max_iter < 1 || !(opt->hopm_tol > 0.0)) return false;
+  if (!(opt->threshold >= 0.0f) || !(opt->min_dist >= 0.0f) || !(opt->eps_v >= 0.0f)) return false;
+  if (opt->refine != 0 && opt->refine != 1) return false;
+  return true;
 }
 
 size_t ttm_pose_workspace_bytes(ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt) {
-  (void)N; (void)L; (void)order_n; (void)opt;
+  (void)N; (void)L;
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || !opt || !pose_opts_ok(opt)) return 0;
   Carve c(nullptr);
-  pose_layout(c);
+  pose_layout(c, make_geo(N, L), opt->max_peaks, K, opt->refine, opt->n_seeds);
   return c.size();
 }
 
@@ -335,23 +366,89 @@ ttm_status ttm_recover_pose(const float* score, const float* image, const float*
       !out_peak_score || !out_flags || !out_count)
     return TTM_E_ARG;
   const int K = ttm_num_components(order_n);
-  if (K < 0) return TTM_E_ARG;
-  if (opt->max_peaks < 1 || opt->max_peaks > 4096) return TTM_E_ARG;
-  if (opt->n_seeds < 64 || opt->n_seeds > 65536) return TTM_E_ARG;
-  if (opt->hopm_max_iter < 1 || !(opt->hopm_tol > 0.0)) return TTM_E_ARG;
-  if (!(opt->threshold >= 0.0f) || !(opt->min_dist >= 0.0f) || !(opt->eps_v >= 0.0f)) return TTM_E_ARG;
+  if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
   if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
   if (!ws || ws_bytes < ttm_pose_workspace_bytes(N, L, order_n, opt)) return TTM_E_WORKSPACE;
   const Geo g = make_geo(N, L);
   Carve c(ws);
-  PoseWs w = pose_layout(c);
+  PoseWs w = pose_layout(c, g, opt->max_peaks, K, opt->refine, opt->n_seeds);
   TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), w.partials, w.stats, stream));
-  PeakWs pw{w.hist, w.ctrl, w.cand};
-  TTM_PROF(PC_PEAKS, launch_peaks(g, score, opt->threshold, opt->min_dist, opt->max_peaks, pw, out_pos, out_peak_score,
-                       out_count, stream));
-  TTM_PROF(PC_POSE, launch_pose(g, image, components, mask, order_n, w.stats, opt->eps_v, opt->n_seeds,
-                      opt->hopm_max_iter, opt->hopm_tol, opt->max_peaks, out_pos, out_count, out_quat,
-                      out_lambda, out_flags, out_C, nullptr, stream));
+  PeakWs pw{w.hist, w.ctrl, w.allc, w.cand};
+  float* cand_score = reinterpret_cast<float*>(w.ps.w);   // overwritten later by the pose scratch
+  TTM_PROF(PC_PEAKS, launch_peaks(g, score, opt->threshold, opt->min_dist, opt->max_peaks, pw, w.cand_pos,
+                                  cand_score, out_count, stream));
+  TTM_PROF(PC_POSE, launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v,
+                                       opt->max_peaks, opt->refine, w.cand_pos, out_count, 0, w.ps, stream));
+  TTM_PROF(PC_POSE, launch_pose_solve(g, score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
+                                      opt->max_peaks, opt->refine, w.cand_pos, out_count, 0, out_pos, out_quat,
+                                      out_lambda, out_peak_score, out_flags, out_C, w.ps, stream));
+  return TTM_OK;
+}
+
+ttm_status ttm_pose_at(const float* image, const float* components, const float* mask, ttm_dims N, ttm_dims L,
+                       int32_t order_n, const ttm_options* opt, const int32_t* positions, int32_t n_pos,
+                       int32_t* out_pos, float* out_quat, double* out_lambda, int32_t* out_flags, double* out_C,
+                       void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!image || !components || !mask || !opt || !positions || !out_pos || !out_quat || !out_lambda ||
+      !out_flags)
+    return TTM_E_ARG;
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
+  if (n_pos < 0 || n_pos > opt->max_peaks) return TTM_E_ARG;
+  if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
+  if (!ws || ws_bytes < ttm_pose_workspace_bytes(N, L, order_n, opt)) return TTM_E_WORKSPACE;
+  if (n_pos == 0) return TTM_OK;
+  const Geo g = make_geo(N, L);
+  Carve c(ws);
+  PoseWs w = pose_layout(c, g, opt->max_peaks, K, opt->refine, opt->n_seeds);
+  TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), w.partials, w.stats, stream));
+  TTM_PROF(PC_POSE, launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, n_pos,
+                                       opt->refine, positions, nullptr, n_pos, w.ps, stream));
+  TTM_PROF(PC_POSE, launch_pose_solve(g, nullptr, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol, n_pos,
+                                      opt->refine, positions, nullptr, n_pos, out_pos, out_quat, out_lambda,
+                                      nullptr, out_flags, out_C, w.ps, stream));
+  return TTM_OK;
+}
+
+size_t ttm_match_workspace_bytes(ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt) {
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || !opt || !pose_opts_ok(opt) || !dims_ok(N) || !dims_ok(L)) return 0;
+  const Geo g = make_geo(N, L);
+  Carve c(nullptr);
+  corr_layout(c, g, K);
+  pose_layout(c, make_geo(N, L), opt->max_peaks, K, opt->refine, opt->n_seeds);
+  c.take<float>(g.vol());
+  return c.size();
+}
+
+ttm_status ttm_match(const float* image, ttm_dims N, const void* bank, ttm_dims L, int32_t order_n,
+                     const float* mask, const ttm_options* opt, float* out_score, float* out_w, int32_t* out_pos,
+                     float* out_quat, double* out_lambda, float* out_peak_score, int32_t* out_flags,
+                     double* out_C, int32_t* out_count, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!image || !bank || !mask || !opt || !out_score || !out_pos || !out_quat || !out_lambda ||
+      !out_peak_score || !out_flags || !out_count)
+    return TTM_E_ARG;
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
+  if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
+  if (!ws || ws_bytes < ttm_match_workspace_bytes(N, L, order_n, opt)) return TTM_E_WORKSPACE;
+  const Geo g = make_geo(N, L);
+  Carve c(ws);
+  CorrWs cw = corr_layout(c, g, K);
+  PoseWs pw = pose_layout(c, g, opt->max_peaks, K, opt->refine, opt->n_seeds);
+  float* wmap = c.take<float>(g.vol());
+  float* wout = out_w ? out_w : wmap;
+  TTM_CALL(correlate_into(g, order_n, K, image, static_cast<const float2*>(bank), mask, opt->eps_v, out_score,
+                          wout, cw, stream));
+  PeakWs pk{pw.hist, pw.ctrl, pw.allc, pw.cand};
+  float* cand_score = reinterpret_cast<float*>(pw.ps.w);
+  TTM_PROF(PC_PEAKS, launch_peaks(g, out_score, opt->threshold, opt->min_dist, opt->max_peaks, pk, pw.cand_pos,
+                                  cand_score, out_count, stream));
+  TTM_PROF(PC_POSE, launch_field_at(g, cw.H, g.half(), K, wout, opt->max_peaks, opt->refine, pw.cand_pos,
+                                    out_count, 0, pw.ps, stream));
+  TTM_PROF(PC_POSE, launch_pose_solve(g, out_score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
+                                      opt->max_peaks, opt->refine, pw.cand_pos, out_count, 0, out_pos, out_quat,
+                                      out_lambda, out_peak_score, out_flags, out_C, pw.ps, stream));
   return TTM_OK;
 }
 

@@ -164,8 +164,15 @@ hipError_t launch_multiplicities(int order_n, float* mu, hipStream_t s) {
 // T_alpha(u) for a chunk of KC components (blockIdx.y selects the chunk)
 constexpr int kKC = 36;
 
+__global__ void k_rot_table(const float* __restrict__ quats, int nrot, float* __restrict__ rtab) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nrot) return;
+  const Rot R = quat_rot(quats + 4 * j);
+  for (int i = 0; i < 9; ++i) rtab[9 * j + i] = R.r[i];
+}
+
 __global__ void __launch_bounds__(256) k_build_accum(const float* __restrict__ t, const float* __restrict__ m,
-                                                     int L0, int L1, int L2, const float* __restrict__ quats,
+                                                     int L0, int L1, int L2, const float* __restrict__ rtab,
                                                      const double* __restrict__ rstats,
                                                      const double* __restrict__ coef, int nrot, int K,
                                                      float* __restrict__ comps) {
@@ -185,7 +192,9 @@ __global__ void __launch_bounds__(256) k_build_accum(const float* __restrict__ t
   if (mv != 0.0f) {
 #pragma unroll 1
     for (int j = 0; j < nrot; ++j) {
-      const Rot R = quat_rot(quats + 4 * j);
+      Rot R;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) R.r[i] = rtab[9 * j + i];
       const double g = sample_rotated(t, L0, L1, L2, R, u0, u1, u2);
       const double sv = (double)mv * (g - rstats[2 * j]);
       const double* cj = coef + (long)j * K + k0;
@@ -203,10 +212,11 @@ __global__ void __launch_bounds__(256) k_build_accum(const float* __restrict__ t
 
 hipError_t launch_build_accum(const float* tmpl, const float* mask, int L0, int L1, int L2,
                               const float* quats, const double* rstats, const double* coef,
-                              int nrot, int K, float* comps, hipStream_t s) {
+                              int nrot, int K, float* comps, float* rtab, hipStream_t s) {
   const int n = L0 * L1 * L2;
+  hipLaunchKernelGGL(k_rot_table, dim3((nrot + 255) / 256), dim3(256), 0, s, quats, nrot, rtab);
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)((K + kKC - 1) / kKC));
-  hipLaunchKernelGGL(k_build_accum, grid, dim3(256), 0, s, tmpl, mask, L0, L1, L2, quats, rstats, coef,
+  hipLaunchKernelGGL(k_build_accum, grid, dim3(256), 0, s, tmpl, mask, L0, L1, L2, rtab, rstats, coef,
                      nrot, K, comps);
   return hipGetLastError();
 }

@@ -407,18 +407,40 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
   }
 
   const int npass = MODE == P3_SCORE ? A.npairs + 2 : (MODE == P3_W ? 2 : A.npairs);
+  // pair order: P3_SCORE does M1 (index npairs), M2 (npairs+1), then components
+  auto pair_of = [&](int it) { return MODE == P3_SCORE ? (it < 2 ? A.npairs + it : it - 2) : it; };
+  // software pipeline: the rows of the next pair are fetched into registers
+  // while the current pair is transformed (each thread owns a fixed slice of
+  // the block's contiguous RW x H2 tile)
+  constexpr int PF = (RW * H2 + 255) / 256;
+  const long nvalid = (nrows - r0 < RW ? nrows - r0 : RW) * (long)H2;
+  float2 pf[PF];
+  {
+    const float2* Hn = A.H + (long)pair_of(0) * A.pstride + r0 * H2;
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = tid + 256 * i;
+      pf[i] = (e < nvalid) ? Hn[e] : make_float2(0.0f, 0.0f);
+    }
+  }
 #pragma unroll 1
   for (int it = 0; it < npass; ++it) {
-    // pair order: P3_SCORE does M1 (index npairs), M2 (npairs+1), then components
-    int pair = it;
-    if (MODE == P3_SCORE) pair = it < 2 ? A.npairs + it : it - 2;
-    const float2* H = A.H + (long)pair * A.pstride + r0 * H2;
+    const int pair = pair_of(it);
     __syncthreads();
-    for (int e = tid; e < RW * H2; e += 256) {
-      const int rr = e / H2, k = e % H2;
-      stage[rr * SP + k] = (r0 + rr < nrows) ? H[e] : make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = tid + 256 * i;
+      if (e < RW * H2) stage[(e / H2) * SP + (e % H2)] = pf[i];
     }
     __syncthreads();
+    if (it + 1 < npass) {
+      const float2* Hn = A.H + (long)pair_of(it + 1) * A.pstride + r0 * H2;
+#pragma unroll
+      for (int i = 0; i < PF; ++i) {
+        const int e = tid + 256 * i;
+        pf[i] = (e < nvalid) ? Hn[e] : make_float2(0.0f, 0.0f);
+      }
+    }
     float2 z[R2], o[R2];
 #pragma unroll
     for (int b = 0; b < R2; ++b) {
@@ -553,6 +575,82 @@ hipError_t launch_pass3(const Geo& g, const Pass3Args& a, hipStream_t s) {
     case 512: return pass3_m<256>(g, a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ----------------------------------------------------------------------------
+// the correlated tensor field at candidate voxels, read from the K arrays
+// after their axis-0 and axis-1 inverse passes: for the row (x0, x1) of array
+// alpha, G(y) = Re Y(0) + (-1)^y Re Y(M) + 2 sum_{k=1}^{M-1} Re(Y(k) e^{2 pi i k y / n2})
+// (unnormalised inverse real DFT at one point), y = x2 - c2 mod n2;
+// C_alpha(x) = w(x) G / (n0 n1 n2).  One block per (candidate, neighbour row).
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_field_at(P3Geo g, const float2* __restrict__ H, long pstride, int K,
+                                                  const float* __restrict__ wmap, int refine,
+                                                  const int* __restrict__ pos, const int* __restrict__ count_dev,
+                                                  int count_host, double* __restrict__ Cbuf,
+                                                  double* __restrict__ wbuf, int* __restrict__ okbuf) {
+  extern __shared__ float2 twf[];            // n2 entries: (cos, sin)(2 pi j / n2)
+  const int rows = refine ? 9 : 1;
+  const int NB = refine ? 27 : 1;
+  const int b = blockIdx.x;
+  const int p = b / rows, r = b % rows;
+  const int count = count_dev ? count_dev[0] : count_host;
+  if (p >= count) return;
+  const int tid = threadIdx.x;
+  for (int j = tid; j < g.n2; j += 256) {
+    float sn, cs;
+    sincospif(2.0f * (float)j / (float)g.n2, &sn, &cs);
+    twf[j] = make_float2(cs, sn);
+  }
+  __syncthreads();
+  const int o0 = refine ? r / 3 - 1 : 0, o1 = refine ? r % 3 - 1 : 0;
+  const int x0 = pos[3 * p] + o0, x1 = pos[3 * p + 1] + o1;
+  const int npt = refine ? 3 : 1;
+  const int M = g.n2 / 2;
+  const bool row_ok = x0 >= g.lo0 && x0 <= g.hi0 && x1 >= g.lo1 && x1 <= g.hi1;
+  for (int pr = tid; pr < K * npt; pr += 256) {
+    const int alpha = pr / npt, pt = pr % npt;
+    const int o2 = refine ? pt - 1 : 0;
+    const int x2 = pos[3 * p + 2] + o2;
+    const int k = refine ? (o0 + 1) * 9 + (o1 + 1) * 3 + (o2 + 1) : 0;
+    const long cb = (long)p * NB + k;
+    const bool ok = row_ok && x2 >= g.lo2 && x2 <= g.hi2;
+    if (!ok) {
+      Cbuf[cb * K + alpha] = 0.0;
+      if (alpha == 0) {
+        okbuf[cb] = 0;
+        wbuf[cb] = 0.0;
+      }
+      continue;
+    }
+    const int y = ((x2 - g.c2) % g.n2 + g.n2) % g.n2;
+    const float2* row = H + (long)alpha * pstride + ((long)x0 * g.n1 + x1) * g.h2;
+    double acc = (double)row[0].x + ((y & 1) ? -(double)row[M].x : (double)row[M].x);
+    double s2 = 0.0;
+    int ph = y;
+    for (int kk = 1; kk < M; ++kk, ph += y) {
+      const float2 v = row[kk];
+      const float2 w = twf[ph & (g.n2 - 1)];
+      s2 += (double)v.x * w.x - (double)v.y * w.y;
+    }
+    acc += 2.0 * s2;
+    const double wv = (double)wmap[((long)x0 * g.n1 + x1) * g.n2 + x2];
+    Cbuf[cb * K + alpha] = wv * acc * g.inv_vol;
+    if (alpha == 0) {
+      okbuf[cb] = 1;
+      wbuf[cb] = wv;
+    }
+  }
+}
+
+hipError_t launch_field_at(const Geo& gg, const float2* H, long pstride, int K, const float* wmap,
+                           int max_peaks, int refine, const int* pos_in, const int* count_dev, int count_host,
+                           const PoseScratch& ps, hipStream_t s) {
+  const P3Geo q = make_p3geo(gg);
+  const unsigned nblk = (unsigned)(max_peaks * (refine ? 9 : 1));
+  hipLaunchKernelGGL(k_field_at, dim3(nblk), dim3(256), sizeof(float2) * gg.n2, s, q, H, pstride, K, wmap,
+                     refine, pos_in, count_dev, count_host, ps.C, ps.w, ps.ok);
+  return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------

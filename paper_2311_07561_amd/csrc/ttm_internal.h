@@ -87,7 +87,7 @@ hipError_t launch_build_coef(const float* quats, const double* weights, const do
 // components[alpha][u] = sum_j coef[j][alpha] * m(u) (g_j(u) - mean_j)
 hipError_t launch_build_accum(const float* tmpl, const float* mask, int L0, int L1, int L2,
                               const float* quats, const double* rstats, const double* coef,
-                              int nrot, int K, float* comps, hipStream_t s);
+                              int nrot, int K, float* comps, float* rtab, hipStream_t s);
 // normalised rotated templates s_j for j in [j0, j0+nb) -> out[nb][L0][L1][L2]
 hipError_t launch_rot_write(const float* tmpl, const float* mask, int L0, int L1, int L2,
                             const float* quats, const double* rstats, int j0, int nb,
@@ -96,19 +96,44 @@ hipError_t launch_multiplicities(int order_n, float* mu, hipStream_t s);
 
 // --- peaks and pose (ttm_pose.hip) --------------------------------------------
 struct PeakWs {
-  unsigned* hist;      // 32768 bins
-  unsigned* ctrl;      // [0] candidate count [1] threshold key [2] overflow
-  unsigned long long* cand;  // capacity kCandCap
+  unsigned* hist;                 // kHistBins bins of the candidates' key top bits
+  unsigned* ctrl;                 // 16 control words
+  unsigned long long* allc;       // every strict local maximum (peaks_bigcap entries)
+  unsigned long long* cand;       // the sorted list of a round (kCandCap entries)
 };
+long peaks_bigcap(const Geo& g);  // V/8 + 1024 >= the number of strict 26-neighbour maxima
 constexpr int kHistBins = 32768;
 constexpr int kCandCap = 16384;
 hipError_t launch_peaks(const Geo& g, const float* score, float threshold, float min_dist,
                         int max_peaks, const PeakWs& w, int* out_pos, float* out_score,
                         int* out_count, hipStream_t s);
-hipError_t launch_pose(const Geo& g, const float* image, const float* comps, const float* mask,
-                       int order_n, const double* img_stats, float eps_v, int n_seeds,
-                       int max_iter, double tol, int max_peaks, const int* pos,
-                       const int* count, float* out_quat, double* out_lambda, int* out_flags,
-                       double* out_C, double* Cbuf, hipStream_t s);
+struct PoseScratch {
+  double* seeds;  // n_seeds * 4: the S^3 seed points
+  double* C;      // max_peaks * NB * K
+  double* w;      // max_peaks * NB
+  int* ok;        // max_peaks * NB
+  float* q;       // max_peaks * NB * 4
+  double* lam;    // max_peaks * NB
+  int* flags;     // max_peaks * NB
+};
+// C_n(x) in float64 by direct window sums at max_peaks candidates (count from
+// count_dev if non-null, else count_host), at the 27 neighbours if refine
+hipError_t launch_pose_tensor(const Geo& g, const float* image, const float* comps, const float* mask,
+                              int order_n, const double* img_stats, float eps_v, int max_peaks, int refine,
+                              const int* pos_in, const int* count_dev, int count_host, const PoseScratch& ps,
+                              hipStream_t s);
+// C_n(x) read from the correlated field: the K inverse-transformed arrays
+// before their last (axis-2) pass, evaluated at the (neighbour) voxels by a
+// direct inverse real DFT of their rows, times w(x)/V
+hipError_t launch_field_at(const Geo& g, const float2* H, long pstride, int K, const float* wmap,
+                           int max_peaks, int refine, const int* pos_in, const int* count_dev, int count_host,
+                           const PoseScratch& ps, hipStream_t s);
+// dominant Z-eigenpairs of the tensors in ps and, per candidate, the
+// neighbour with the largest lambda
+hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int n_seeds, int max_iter,
+                             double tol, int max_peaks, int refine, const int* pos_in, const int* count_dev,
+                             int count_host, int* out_pos, float* out_quat, double* out_lambda,
+                             float* out_score, int* out_flags, double* out_C, const PoseScratch& ps,
+                             hipStream_t s);
 
 }  // namespace ttm

@@ -23,88 +23,117 @@ struct PeakGeo {
   int lo0, hi0, lo1, hi1, lo2, hi2;
 };
 
-__device__ __forceinline__ bool strict_local_max(const float* __restrict__ F, const PeakGeo& g, int x0,
-                                                 int x1, int x2, float v) {
-  for (int d0 = -1; d0 <= 1; ++d0) {
-    const int y0 = x0 + d0;
-    if (y0 < 0 || y0 >= g.n0) continue;
-    for (int d1 = -1; d1 <= 1; ++d1) {
-      const int y1 = x1 + d1;
-      if (y1 < 0 || y1 >= g.n1) continue;
-      const float* row = F + ((long)y0 * g.n1 + y1) * g.n2;
-      for (int d2 = -1; d2 <= 1; ++d2) {
-        const int y2 = x2 + d2;
-        if (y2 < 0 || y2 >= g.n2) continue;
-        if (d0 == 0 && d1 == 0 && d2 == 0) continue;
-        if (!(v > row[y2])) return false;
-      }
-    }
-  }
-  return true;
+// control words of the peak search
+enum PeakCtrl { PK_TOTAL = 0, PK_B1 = 1, PK_MORE1 = 2, PK_CNT1 = 3, PK_B2 = 4, PK_MORE2 = 5, PK_CNT2 = 6,
+                PK_REDO = 7, PK_OVER = 8 };
+
+__device__ __forceinline__ unsigned long long peak_key(float v, long lin) {
+  // ascending key order = F descending, then linear index ascending
+  return ((unsigned long long)(0xFFFFFFFFu - __float_as_uint(v)) << 32) | (unsigned long long)lin;
 }
 
-// pass 0: histogram of candidate keys; pass 1: compaction of keys >= ctrl[1]
-template <int PASS>
+// One pass over the valid region in 4 x 8 x 64 tiles staged (with a one-voxel
+// halo) in LDS: every strict local maximum above the threshold is appended to
+// the full candidate list and counted in the histogram of its key's top bits.
+// Out-of-image neighbours are not compared (they hold -inf in the tile).
+constexpr int PT0 = 4, PT1 = 8, PT2 = 64;
 __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F, PeakGeo g, float threshold,
                                                     unsigned* __restrict__ hist, unsigned* __restrict__ ctrl,
-                                                    unsigned long long* __restrict__ cand) {
-  const int e0 = g.hi0 - g.lo0 + 1, e1 = g.hi1 - g.lo1 + 1, e2 = g.hi2 - g.lo2 + 1;
-  const long nvalid = (long)e0 * e1 * e2;
-  const unsigned kmin = PASS == 1 ? ctrl[1] : 0u;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nvalid; i += (long)gridDim.x * blockDim.x) {
-    const int x2 = g.lo2 + (int)(i % e2);
-    const long r = i / e2;
-    const int x1 = g.lo1 + (int)(r % e1);
-    const int x0 = g.lo0 + (int)(r / e1);
-    const long lin = ((long)x0 * g.n1 + x1) * g.n2 + x2;
-    const float v = F[lin];
+                                                    unsigned long long* __restrict__ allc, long bigcap) {
+  constexpr int H0 = PT0 + 2, H1 = PT1 + 2, H2 = PT2 + 2;
+  __shared__ float tile[H0 * H1 * H2];
+  const int tid = threadIdx.x;
+  const int b0 = g.lo0 + blockIdx.z * PT0, b1 = g.lo1 + blockIdx.y * PT1, b2 = g.lo2 + blockIdx.x * PT2;
+  for (int e = tid; e < H0 * H1 * H2; e += 256) {
+    const int t2 = e % H2, t1 = (e / H2) % H1, t0 = e / (H1 * H2);
+    const int y0 = b0 - 1 + t0, y1 = b1 - 1 + t1, y2 = b2 - 1 + t2;
+    float v = -INFINITY;
+    if (y0 >= 0 && y0 < g.n0 && y1 >= 0 && y1 < g.n1 && y2 >= 0 && y2 < g.n2)
+      v = F[((long)y0 * g.n1 + y1) * g.n2 + y2];
+    tile[e] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < PT0 * PT1 * PT2; e += 256) {
+    const int t2 = e % PT2, t1 = (e / PT2) % PT1, t0 = e / (PT1 * PT2);
+    const int x0 = b0 + t0, x1 = b1 + t1, x2 = b2 + t2;
+    if (x0 > g.hi0 || x1 > g.hi1 || x2 > g.hi2) continue;
+    const int c = ((t0 + 1) * H1 + (t1 + 1)) * H2 + (t2 + 1);
+    const float v = tile[c];
     if (!(v > threshold)) continue;
-    if (!strict_local_max(F, g, x0, x1, x2, v)) continue;
-    const unsigned key = __float_as_uint(v) >> 16;
-    if (PASS == 0) {
-      atomicAdd(&hist[key], 1u);
-    } else if (key >= kmin) {
-      const unsigned slot = atomicAdd(&ctrl[0], 1u);
-      if (slot < (unsigned)kCandCap)
-        cand[slot] = ((unsigned long long)(0xFFFFFFFFu - __float_as_uint(v)) << 32) | (unsigned long long)lin;
-    }
+    bool ok = true;
+#pragma unroll
+    for (int d0 = -1; d0 <= 1; ++d0)
+#pragma unroll
+      for (int d1 = -1; d1 <= 1; ++d1)
+#pragma unroll
+        for (int d2 = -1; d2 <= 1; ++d2) {
+          if (d0 == 0 && d1 == 0 && d2 == 0) continue;
+          ok = ok && (v > tile[c + (d0 * H1 + d1) * H2 + d2]);
+        }
+    if (!ok) continue;
+    const long lin = ((long)x0 * g.n1 + x1) * g.n2 + x2;
+    atomicAdd(&hist[__float_as_uint(v) >> 16], 1u);
+    const unsigned slot = atomicAdd(&ctrl[PK_TOTAL], 1u);
+    if ((long)slot < bigcap)
+      allc[slot] = peak_key(v, lin);
+    else
+      ctrl[PK_OVER] = 1u;
   }
 }
 
-// smallest key b with sum_{k >= b} hist[k] <= kCandCap
+// round r: the smallest bin b with sum_{k >= b} hist[k] <= cap
 __global__ void __launch_bounds__(1024) k_peaks_select(const unsigned* __restrict__ hist,
-                                                       unsigned* __restrict__ ctrl) {
+                                                       unsigned* __restrict__ ctrl, int round, unsigned cap) {
+  if (round == 2 && ctrl[PK_REDO] == 0u) return;
   __shared__ unsigned part[1024];
   constexpr int per = kHistBins / 1024;
   const int tid = threadIdx.x;
+  const int base = round == 1 ? PK_B1 : PK_B2;
   unsigned s = 0;
   for (int i = 0; i < per; ++i) s += hist[tid * per + i];
   part[tid] = s;
   __syncthreads();
-  // inclusive suffix sums over threads (Hillis-Steele)
   for (int off = 1; off < 1024; off <<= 1) {
     const unsigned v = (tid + off < 1024) ? part[tid + off] : 0u;
     __syncthreads();
     part[tid] += v;
     __syncthreads();
   }
-  // part[tid] = sum of bins from tid*per to the end
-  const unsigned above = (tid + 1 < 1024) ? part[tid + 1] : 0u;   // bins after this chunk
-  if (part[tid] > (unsigned)kCandCap && above <= (unsigned)kCandCap) {
+  const unsigned above = (tid + 1 < 1024) ? part[tid + 1] : 0u;
+  if (part[tid] > cap && above <= cap) {
     unsigned run = above;
     int b = tid * per + per;
     for (int i = per - 1; i >= 0; --i) {
       const unsigned h = hist[tid * per + i];
-      if (run + h > (unsigned)kCandCap) break;
+      if (run + h > cap) break;
       run += h;
       b = tid * per + i;
     }
-    ctrl[1] = (unsigned)b;
-    ctrl[2] = 1u;   // the total exceeds the capacity: candidates below b exist
+    ctrl[base] = (unsigned)b;
+    ctrl[base + 1] = 1u;           // candidates below b exist
   }
-  if (tid == 0 && part[0] <= (unsigned)kCandCap) {
-    ctrl[1] = 0u;
-    ctrl[2] = 0u;
+  if (tid == 0 && part[0] <= cap) {
+    ctrl[base] = 0u;
+    ctrl[base + 1] = 0u;
+  }
+}
+
+// round r: the candidates whose key bin is >= the round's bin
+__global__ void __launch_bounds__(256) k_peaks_gather(unsigned* __restrict__ ctrl,
+                                                      const unsigned long long* __restrict__ allc, long bigcap,
+                                                      unsigned long long* __restrict__ cand, int round,
+                                                      unsigned cap) {
+  if (round == 2 && ctrl[PK_REDO] == 0u) return;
+  const unsigned bmin = ctrl[round == 1 ? PK_B1 : PK_B2];
+  unsigned* cnt = &ctrl[round == 1 ? PK_CNT1 : PK_CNT2];
+  const long total = min((long)ctrl[PK_TOTAL], bigcap);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const unsigned long long k = allc[i];
+    const unsigned bits = 0xFFFFFFFFu - (unsigned)(k >> 32);
+    if ((bits >> 16) >= bmin) {
+      const unsigned slot = atomicAdd(cnt, 1u);
+      if (slot < cap) cand[slot] = k;
+    }
   }
 }
 
@@ -116,13 +145,14 @@ __device__ __forceinline__ void decode_lin(unsigned long long key, int n1, int n
   x0 = (int)(r / n1);
 }
 
-// one block: bitonic sort of the candidate keys (ascending key = F descending,
-// then linear index ascending), written back in place
+// one block: bitonic sort of the round's candidate keys in LDS, in place
+template <int CAP>
 __global__ void __launch_bounds__(1024) k_peaks_sort(const unsigned* __restrict__ ctrl,
-                                                     unsigned long long* __restrict__ cand) {
-  __shared__ unsigned long long keys[kCandCap];
+                                                     unsigned long long* __restrict__ cand, int round) {
+  if (round == 2 && ctrl[PK_REDO] == 0u) return;
+  __shared__ unsigned long long keys[CAP];
   const int tid = threadIdx.x;
-  const unsigned nc = min(ctrl[0], (unsigned)kCandCap);
+  const unsigned nc = min(ctrl[round == 1 ? PK_CNT1 : PK_CNT2], (unsigned)CAP);
   int np2 = 1;
   while (np2 < (int)nc) np2 <<= 1;
   for (int i = tid; i < np2; i += 1024) keys[i] = (i < (int)nc) ? cand[i] : ~0ull;
@@ -148,14 +178,20 @@ __global__ void __launch_bounds__(1024) k_peaks_sort(const unsigned* __restrict_
 
 // one wavefront: greedy suppression over the sorted candidates, 64 at a time.
 // Each lane tests its candidate against the accepted list; conflicts inside
-// the chunk are resolved in candidate order with lane broadcasts.
-__global__ void __launch_bounds__(64) k_peaks_nms(PeakGeo g, const unsigned* __restrict__ ctrl,
-                                                  const unsigned long long* __restrict__ cand,
-                                                  float min_dist, int max_peaks, int* __restrict__ out_pos,
-                                                  float* __restrict__ out_score, int* __restrict__ out_count) {
+// the chunk are resolved in candidate order with lane broadcasts.  Round 1
+// asks for round 2 (a larger candidate list) when its list ran out before
+// max_peaks peaks were accepted while lower candidates exist.
+__global__ void __launch_bounds__(64) k_peaks_nms(PeakGeo g, unsigned* __restrict__ ctrl,
+                                                  const unsigned long long* __restrict__ cand, int round,
+                                                  unsigned cap, float min_dist, int max_peaks,
+                                                  int* __restrict__ out_pos, float* __restrict__ out_score,
+                                                  int* __restrict__ out_count) {
+  if (round == 2 && ctrl[PK_REDO] == 0u) return;
   __shared__ int acc_pos[3 * 4096];
   const int lane = threadIdx.x;
-  const unsigned nc = min(ctrl[0], (unsigned)kCandCap);
+  const unsigned ncount = ctrl[round == 1 ? PK_CNT1 : PK_CNT2];
+  const unsigned nc = min(ncount, cap);
+  const bool more_below = ctrl[round == 1 ? PK_MORE1 : PK_MORE2] != 0u || ncount > cap;
   const float d2min = min_dist * min_dist;
   int nacc = 0;
   bool exhausted = true;
@@ -166,7 +202,7 @@ __global__ void __launch_bounds__(64) k_peaks_nms(PeakGeo g, const unsigned* __r
     }
     const int i = base + lane;
     const bool have = i < (int)nc;
-    unsigned long long key = have ? cand[i] : ~0ull;
+    const unsigned long long key = have ? cand[i] : ~0ull;
     int x0 = 0, x1 = 0, x2 = 0;
     if (have) decode_lin(key, g.n1, g.n2, x0, x1, x2);
     bool sup = !have;
@@ -193,7 +229,6 @@ __global__ void __launch_bounds__(64) k_peaks_nms(PeakGeo g, const unsigned* __r
         ++nacc;
       }
     }
-    // lane m writes its own accepted entry at its rank among the accepted lanes
     if ((accepted >> lane) & 1ull) {
       const int rank = nacc0 + __popcll(accepted & ((1ull << lane) - 1ull));
       acc_pos[3 * rank] = x0;
@@ -207,12 +242,14 @@ __global__ void __launch_bounds__(64) k_peaks_nms(PeakGeo g, const unsigned* __r
     __syncthreads();
   }
   if (lane == 0) {
+    const bool short_list = nacc < max_peaks && exhausted && more_below;
     out_count[0] = nacc;
-    const bool more_below = ctrl[2] != 0u;
-    out_count[1] = ((nacc < max_peaks && exhausted && more_below) || ctrl[0] > (unsigned)kCandCap)
-                       ? TTM_PEAKS_TRUNCATED : 0;
+    out_count[1] = (round == 2 && short_list) || ctrl[PK_OVER] ? TTM_PEAKS_TRUNCATED : 0;
+    if (round == 1 && short_list) ctrl[PK_REDO] = 1u;
   }
 }
+
+long peaks_bigcap(const Geo& g) { return g.vol() / 8 + 1024; }
 
 hipError_t launch_peaks(const Geo& gg, const float* score, float threshold, float min_dist,
                         int max_peaks, const PeakWs& w, int* out_pos, float* out_score,
@@ -222,15 +259,25 @@ hipError_t launch_peaks(const Geo& gg, const float* score, float threshold, floa
   g.lo0 = gg.c0; g.hi0 = gg.n0 - gg.L0 + gg.c0;
   g.lo1 = gg.c1; g.hi1 = gg.n1 - gg.L1 + gg.c1;
   g.lo2 = gg.c2; g.hi2 = gg.n2 - gg.L2 + gg.c2;
+  const long bigcap = peaks_bigcap(gg);
   hipError_t e;
   if ((e = launch_fill_i32(reinterpret_cast<int*>(w.hist), kHistBins, 0, s)) != hipSuccess) return e;
-  if ((e = launch_fill_i32(reinterpret_cast<int*>(w.ctrl), 4, 0, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_peaks_scan<0>), dim3(2048), dim3(256), 0, s, score, g, threshold, w.hist, w.ctrl, w.cand);
-  hipLaunchKernelGGL(k_peaks_select, dim3(1), dim3(1024), 0, s, w.hist, w.ctrl);
-  hipLaunchKernelGGL((k_peaks_scan<1>), dim3(2048), dim3(256), 0, s, score, g, threshold, w.hist, w.ctrl, w.cand);
-  hipLaunchKernelGGL(k_peaks_sort, dim3(1), dim3(1024), 0, s, w.ctrl, w.cand);
-  hipLaunchKernelGGL(k_peaks_nms, dim3(1), dim3(64), 0, s, g, w.ctrl, w.cand, min_dist, max_peaks,
-                     out_pos, out_score, out_count);
+  if ((e = launch_fill_i32(reinterpret_cast<int*>(w.ctrl), 16, 0, s)) != hipSuccess) return e;
+  const int e0 = g.hi0 - g.lo0 + 1, e1 = g.hi1 - g.lo1 + 1, e2 = g.hi2 - g.lo2 + 1;
+  dim3 sgrid((e2 + PT2 - 1) / PT2, (e1 + PT1 - 1) / PT1, (e0 + PT0 - 1) / PT0);
+  hipLaunchKernelGGL(k_peaks_scan, sgrid, dim3(256), 0, s, score, g, threshold, w.hist, w.ctrl, w.allc, bigcap);
+  constexpr unsigned cap1 = 2048, cap2 = kCandCap;
+  for (int round = 1; round <= 2; ++round) {
+    const unsigned cap = round == 1 ? cap1 : cap2;
+    hipLaunchKernelGGL(k_peaks_select, dim3(1), dim3(1024), 0, s, w.hist, w.ctrl, round, cap);
+    hipLaunchKernelGGL(k_peaks_gather, dim3(256), dim3(256), 0, s, w.ctrl, w.allc, bigcap, w.cand, round, cap);
+    if (round == 1)
+      hipLaunchKernelGGL(k_peaks_sort<cap1>, dim3(1), dim3(1024), 0, s, w.ctrl, w.cand, round);
+    else
+      hipLaunchKernelGGL(k_peaks_sort<cap2>, dim3(1), dim3(1024), 0, s, w.ctrl, w.cand, round);
+    hipLaunchKernelGGL(k_peaks_nms, dim3(1), dim3(64), 0, s, g, w.ctrl, w.cand, round, cap, min_dist, max_peaks,
+                       out_pos, out_score, out_count);
+  }
   return hipGetLastError();
 }
 
@@ -239,46 +286,16 @@ hipError_t launch_peaks(const Geo& gg, const float* score, float threshold, floa
 // ----------------------------------------------------------------------------
 struct PoseGeo {
   int n0, n1, n2, L0, L1, L2;
+  int lo0, hi0, lo1, hi1, lo2, hi2;
 };
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  const int tid = threadIdx.x;
-  __syncthreads();
-  sh[tid] = v;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) sh[tid] += sh[tid + s];
-    __syncthreads();
-  }
-  return sh[0];
-}
+constexpr int kTensorChunk = 36;
 
-// wavefront sum (64 lanes); the butterfly leaves each lane with a sum in a
-// different association order, so lane 0's value is broadcast to keep every
-// lane's control flow identical
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return __shfl(v, 0);
-}
-
-constexpr int kPoseChunk = 8;
-constexpr int kMaxTerms = kMaxK;
-
-// Evaluate phi(Q) = sum_alpha mu_alpha A_alpha Q^alpha (A pre-multiplied by mu)
-__device__ __forceinline__ double phi_eval(const double* muA, const int* al, int K, int n, const double* q) {
-  double pw[4][kMaxOrder + 1];
-  for (int d = 0; d < 4; ++d) {
-    pw[d][0] = 1.0;
-    for (int e = 1; e <= n; ++e) pw[d][e] = pw[d][e - 1] * q[d];
-  }
-  double s = 0.0;
-  for (int k = 0; k < K; ++k) s += muA[k] * pw[0][al[4 * k]] * pw[1][al[4 * k + 1]] * pw[2][al[4 * k + 2]] * pw[3][al[4 * k + 3]];
-  return s;
-}
-
+// point i of the n-point super-Fibonacci spiral on S^3 (Alexa, CVPR 2022):
+// phi = sqrt(2), psi the real root of psi^4 = psi + 4
 __device__ __forceinline__ void seed_point(int i, int n, double* q) {
-  const double phi = 1.4142135623730950488;      // sqrt(2)
-  const double psi = 1.533751168755204288118041; // real root of psi^4 = psi + 4
+  const double phi = 1.4142135623730950488;
+  const double psi = 1.533751168755204288118041;
   const double s = i + 0.5;
   const double r = sqrt(s / n), R = sqrt(1.0 - s / n);
   const double al = 6.283185307179586477 * s / phi, be = 6.283185307179586477 * s / psi;
@@ -288,14 +305,26 @@ __device__ __forceinline__ void seed_point(int i, int n, double* q) {
   q[3] = R * cos(be);
 }
 
-// Solve the 4x4 system H xi = rhs by Gaussian elimination with partial pivoting.
-__device__ __forceinline__ bool solve4(double H[4][4], double* rhs) {
+__global__ void k_seed_table(int n, double* __restrict__ seeds) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) seed_point(i, n, seeds + 4 * i);
+}
+
+// Solve H xi = rhs (4x4) by Gaussian elimination with partial pivoting.
+__device__ __forceinline__ bool solve4(double (&H)[4][4], double* rhs) {
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
     int piv = c;
+    double best = fabs(H[c][c]);
+#pragma unroll
     for (int r = c + 1; r < 4; ++r)
-      if (fabs(H[r][c]) > fabs(H[piv][c])) piv = r;
-    if (fabs(H[piv][c]) < 1e-300) return false;
+      if (fabs(H[r][c]) > best) {
+        best = fabs(H[r][c]);
+        piv = r;
+      }
+    if (!(best > 1e-300)) return false;
     if (piv != c) {
+#pragma unroll
       for (int k = 0; k < 4; ++k) {
         const double t = H[c][k];
         H[c][k] = H[piv][k];
@@ -305,88 +334,97 @@ __device__ __forceinline__ bool solve4(double H[4][4], double* rhs) {
       rhs[c] = rhs[piv];
       rhs[piv] = t;
     }
+#pragma unroll
     for (int r = c + 1; r < 4; ++r) {
       const double f = H[r][c] / H[c][c];
+#pragma unroll
       for (int k = c; k < 4; ++k) H[r][k] -= f * H[c][k];
       rhs[r] -= f * rhs[c];
     }
   }
+#pragma unroll
   for (int c = 3; c >= 0; --c) {
     double s = rhs[c];
+#pragma unroll
     for (int k = c + 1; k < 4; ++k) s -= H[c][k] * rhs[k];
     rhs[c] = s / H[c][c];
   }
   return true;
 }
 
-// lambda, gradient term A x^{n-1} and matrix A x^{n-2} (times n(n-1) later),
-// accumulated across the wavefront: each lane owns components k = lane + 64 i.
-__device__ __forceinline__ void tensor_terms(const double* muA, const int* al, int K, int n, const double* x,
-                                             int lane, double& lam, double* g, double* Hm) {
-  double pw[4][kMaxOrder + 1];
-  for (int d = 0; d < 4; ++d) {
-    pw[d][0] = 1.0;
-    for (int e = 1; e <= n; ++e) pw[d][e] = pw[d][e - 1] * x[d];
-  }
-  double l = 0.0, gg[4] = {0, 0, 0, 0}, hh[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int k = lane; k < K; k += 64) {
-    const int e[4] = {al[4 * k], al[4 * k + 1], al[4 * k + 2], al[4 * k + 3]};
-    const double c = muA[k];
-    l += c * pw[0][e[0]] * pw[1][e[1]] * pw[2][e[2]] * pw[3][e[3]];
-    for (int i = 0; i < 4; ++i) {
-      if (e[i] == 0) continue;
-      double t = c * e[i];
-      for (int d = 0; d < 4; ++d) t *= pw[d][d == i ? e[d] - 1 : e[d]];
-      gg[i] += t;
+// 256-thread sum of kTensorChunk values per thread (wave shuffles, then LDS)
+__device__ __forceinline__ void block_sum_chunk(double* v, int kc, double* sh /* 4 * kTensorChunk */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < kTensorChunk; ++i) {
+    if (i < kc) {
+      double t = v[i];
+      for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+      if (lane == 0) sh[wave * kTensorChunk + i] = t;
     }
-    int h = 0;
-    for (int i = 0; i < 4; ++i)
-      for (int j = i; j < 4; ++j, ++h) {
-        const int ci = e[i] * (e[j] - (i == j ? 1 : 0));
-        if (ci == 0) continue;
-        double t = c * ci;
-        for (int d = 0; d < 4; ++d) {
-          int ex = e[d] - (d == i ? 1 : 0) - (d == j ? 1 : 0);
-          t *= pw[d][ex];
-        }
-        hh[h] += t;
-      }
   }
-  lam = wave_sum(l);
-  for (int i = 0; i < 4; ++i) g[i] = wave_sum(gg[i]) / n;                 // A x^{n-1}
-  for (int h = 0; h < 10; ++h) Hm[h] = wave_sum(hh[h]) / (n * (n - 1));   // A x^{n-2}
+  __syncthreads();
+  if (threadIdx.x < kc)
+    v[0] = sh[threadIdx.x] + sh[kTensorChunk + threadIdx.x] + sh[2 * kTensorChunk + threadIdx.x] +
+           sh[3 * kTensorChunk + threadIdx.x];
+  __syncthreads();
 }
 
-__global__ void __launch_bounds__(256) k_pose(PoseGeo g, const float* __restrict__ image,
-                                              const float* __restrict__ comps, const float* __restrict__ mask,
-                                              int order_n, const double* __restrict__ img_stats, float eps_v,
-                                              int n_seeds, int max_iter, double tol, const int* __restrict__ pos,
-                                              const int* __restrict__ count, float* __restrict__ out_quat,
-                                              double* __restrict__ out_lambda, int* __restrict__ out_flags,
-                                              double* __restrict__ out_C) {
-  __shared__ double sh[256];
-  __shared__ double muA[kMaxTerms];
-  __shared__ int al[4 * kMaxTerms];
-  __shared__ double sel[4][4];
-  __shared__ double wres[4][6];    // per wave: lambda, q0..q3, flags
-  __shared__ int shi[256];
-  const int peak = blockIdx.x;
-  if (peak >= count[0]) return;
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  double a[kTensorChunk];
+  a[0] = v;
+  block_sum_chunk(a, 1, sh);
+  if (threadIdx.x == 0) sh[0] = a[0];
+  __syncthreads();
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ void neighbour_offset(int k, int NB, int& o0, int& o1, int& o2) {
+  if (NB == 27) {
+    o0 = k / 9 - 1;
+    o1 = (k / 3) % 3 - 1;
+    o2 = k % 3 - 1;
+  } else {
+    o0 = o1 = o2 = 0;
+  }
+}
+
+// C_alpha(x) = w(x) <tau_x f, T_alpha> in float64 at x = pos[p] + offset(k), with
+// w(x) from the two-pass masked mean and variance of the window (Section 2).
+__global__ void __launch_bounds__(256) k_pose_tensor(PoseGeo g, const float* __restrict__ image,
+                                                     const float* __restrict__ comps,
+                                                     const float* __restrict__ mask, int K,
+                                                     const double* __restrict__ img_stats, float eps_v,
+                                                     const int* __restrict__ pos, const int* __restrict__ count_dev,
+                                                     int count_host, int NB, double* __restrict__ Cbuf,
+                                                     double* __restrict__ wbuf, int* __restrict__ okbuf) {
+  __shared__ double sh[4 * kTensorChunk];
+  const int b = blockIdx.x;
+  const int p = b / NB, k = b % NB;
+  const int count = count_dev ? count_dev[0] : count_host;
+  if (p >= count) return;
   const int tid = threadIdx.x;
-  const int n = order_n;
-  const int K = num_components_dev(n);
+  int o0, o1, o2;
+  neighbour_offset(k, NB, o0, o1, o2);
+  const int x0 = pos[3 * p] + o0, x1 = pos[3 * p + 1] + o1, x2 = pos[3 * p + 2] + o2;
+  const bool inside = x0 >= g.lo0 && x0 <= g.hi0 && x1 >= g.lo1 && x1 <= g.hi1 && x2 >= g.lo2 && x2 <= g.hi2;
+  if (!inside) {
+    if (tid == 0) {
+      okbuf[b] = 0;
+      wbuf[b] = 0.0;
+    }
+    return;
+  }
   const int L0 = g.L0, L1 = g.L1, L2 = g.L2, nL = L0 * L1 * L2;
-  const int x0 = pos[3 * peak], x1 = pos[3 * peak + 1], x2 = pos[3 * peak + 2];
   const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;
+  // the window lies inside the image (valid region), no wrap needed
+  const float* base = image + ((long)(x0 - c0) * g.n1 + (x1 - c1)) * g.n2 + (x2 - c2);
   auto img_at = [&](int u) -> double {
     const int u2 = u % L2, u1 = (u / L2) % L1, u0 = u / (L1 * L2);
-    int y0 = x0 + u0 - c0, y1 = x1 + u1 - c1, y2 = x2 + u2 - c2;
-    y0 = ((y0 % g.n0) + g.n0) % g.n0;
-    y1 = ((y1 % g.n1) + g.n1) % g.n1;
-    y2 = ((y2 % g.n2) + g.n2) % g.n2;
-    return (double)image[((long)y0 * g.n1 + y1) * g.n2 + y2];
+    return (double)base[((long)u0 * g.n1 + u1) * g.n2 + u2];
   };
-  // two-pass masked mean and variance of the window
   double s0 = 0.0, s1 = 0.0;
   for (int u = tid; u < nL; u += 256) {
     const double mv = mask[u];
@@ -408,202 +446,399 @@ __global__ void __launch_bounds__(256) k_pose(PoseGeo g, const float* __restrict
   const double var = block_sum(s2, sh);
   const double floor_v = (double)eps_v * msum * img_stats[1];
   const double w = var > floor_v ? 1.0 / sqrt(var) : 0.0;
-
-  // packed exponents and multiplicities
-  if (tid < K) {
-    int e[4];
-    alpha_of_dev(n, tid, e);
-    for (int d = 0; d < 4; ++d) al[4 * tid + d] = e[d];
-  }
-  __syncthreads();
-
-  // C_alpha = w <tau_x f, T_alpha>, in chunks of kPoseChunk components
-  for (int k0 = 0; k0 < K; k0 += kPoseChunk) {
-    double acc[kPoseChunk];
-    for (int i = 0; i < kPoseChunk; ++i) acc[i] = 0.0;
+  for (int k0 = 0; k0 < K; k0 += kTensorChunk) {
+    const int kc = min(kTensorChunk, K - k0);
+    double acc[kTensorChunk];
+#pragma unroll
+    for (int i = 0; i < kTensorChunk; ++i) acc[i] = 0.0;
     for (int u = tid; u < nL; u += 256) {
       const double v = img_at(u);
-      for (int i = 0; i < kPoseChunk; ++i)
-        if (k0 + i < K) acc[i] += v * (double)comps[(long)(k0 + i) * nL + u];
+      const float* cu = comps + (long)k0 * nL + u;
+#pragma unroll
+      for (int i = 0; i < kTensorChunk; ++i)
+        if (i < kc) acc[i] += v * (double)cu[(long)i * nL];
     }
-    for (int i = 0; i < kPoseChunk; ++i) {
-      if (k0 + i >= K) break;
-      const double c = block_sum(acc[i], sh) * w;
-      if (tid == 0) {
-        if (out_C) out_C[(long)peak * K + k0 + i] = c;
-        const int* e = &al[4 * (k0 + i)];
-        double mu = 1.0;
-        for (int j = 2; j <= n; ++j) mu *= j;
-        for (int d = 0; d < 4; ++d)
-          for (int j = 2; j <= e[d]; ++j) mu /= j;
-        muA[k0 + i] = mu * c;
-      }
+    block_sum_chunk(acc, kc, sh);
+    if (tid < kc) Cbuf[(long)b * K + k0 + tid] = acc[0] * w;
+  }
+  if (tid == 0) {
+    okbuf[b] = 1;
+    wbuf[b] = w;
+  }
+}
+
+constexpr int hidx(int i, int j) { return i * 4 - i * (i - 1) / 2 + (j - i); }   // upper triangle, i <= j
+
+// Per-wave LDS tables of the eigen-solver: packed exponents and mu*A of the K
+// terms, and each lane's powers x_d^e stored lane-fastest (conflict free).
+struct EigLds {
+  double muA[kMaxK];
+  int ex[kMaxK];                          // alpha_1..alpha_4 in 4 bytes
+  double pw[4 * (kMaxOrder + 1) * 64];    // [(d * 9 + e) * 64 + lane]
+};
+
+__device__ __forceinline__ double PW(const EigLds& t, int d, int e, int lane) {
+  return t.pw[(d * (kMaxOrder + 1) + e) * 64 + lane];
+}
+
+// lambda = sum_alpha muA_alpha x^alpha; with DERIV also g = A x^{n-1} and the
+// upper triangle H of A x^{n-2}, from the products of all-but-one and
+// all-but-two factors of each monomial.
+template <bool DERIV>
+__device__ __forceinline__ void eval_terms(EigLds& t, int n, int K, const double* x, int lane, double& lam,
+                                           double* g, double* H) {
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    double v = 1.0;
+    t.pw[(d * (kMaxOrder + 1)) * 64 + lane] = 1.0;
+    for (int e = 1; e <= n; ++e) {
+      v *= x[d];
+      t.pw[(d * (kMaxOrder + 1) + e) * 64 + lane] = v;
     }
   }
-  __syncthreads();
-
-  // seed scan: 4 rounds of block argmax, each excluding seeds within 10 degrees
-  // (|<q, s>| > cos 5 deg) of the seeds already selected
-  const double cosx = 0.99619469809174553;   // cos(5 deg)
-  for (int r = 0; r < 4; ++r) {
-    double best = -INFINITY;
-    int bi = -1;
-    for (int i = tid; i < n_seeds; i += 256) {
-      double q[4];
-      seed_point(i, n_seeds, q);
-      bool skip = false;
-      for (int t = 0; t < r; ++t) {
-        const double dp = q[0] * sel[t][0] + q[1] * sel[t][1] + q[2] * sel[t][2] + q[3] * sel[t][3];
-        if (fabs(dp) > cosx) skip = true;
+  double l = 0.0, gg[4] = {0.0, 0.0, 0.0, 0.0}, hh[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < K; ++k) {
+    const int ex = t.ex[k];
+    const int e[4] = {ex & 255, (ex >> 8) & 255, (ex >> 16) & 255, (ex >> 24) & 255};
+    const double c = t.muA[k];
+    double p[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) p[d] = PW(t, d, e[d], lane);
+    l += c * p[0] * p[1] * p[2] * p[3];
+    if (DERIV) {
+      double pm[4], pmm[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        pm[d] = e[d] >= 1 ? PW(t, d, e[d] - 1, lane) : 0.0;
+        pmm[d] = e[d] >= 2 ? PW(t, d, e[d] - 2, lane) : 0.0;
       }
-      if (skip) continue;
-      const double v = phi_eval(muA, al, K, n, q);
-      if (v > best) {
-        best = v;
-        bi = i;
-      }
-    }
-    // block argmax (value, then lower index)
-    __syncthreads();
-    sh[tid] = best;
-    shi[tid] = bi;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double a = sh[tid], b = sh[tid + s];
-        const int ia = shi[tid], ib = shi[tid + s];
-        if (b > a || (b == a && ib >= 0 && (ia < 0 || ib < ia))) {
-          sh[tid] = b;
-          shi[tid] = ib;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        double rest = 1.0;
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+          if (d != i) rest *= p[d];
+        gg[i] += c * e[i] * pm[i] * rest;
+        hh[hidx(i, i)] += c * e[i] * (e[i] - 1) * pmm[i] * rest;
+#pragma unroll
+        for (int j = i + 1; j < 4; ++j) {
+          double r2 = 1.0;
+#pragma unroll
+          for (int d = 0; d < 4; ++d)
+            if (d != i && d != j) r2 *= p[d];
+          hh[hidx(i, j)] += c * e[i] * e[j] * pm[i] * pm[j] * r2;
         }
       }
-      __syncthreads();
     }
-    if (tid == 0) {
-      double q[4] = {1.0, 0.0, 0.0, 0.0};
-      if (shi[0] >= 0) seed_point(shi[0], n_seeds, q);
-      for (int d = 0; d < 4; ++d) sel[r][d] = q[d];
-    }
-    __syncthreads();
   }
+  lam = l;
+  if (DERIV) {
+    const double in = 1.0 / n, inn = 1.0 / (n * (n - 1));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g[i] = gg[i] * in;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) H[i] = hh[i] * inn;
+  }
+}
 
-  // per wave: polish from sel[wave]
-  const int wave = tid / 64, lane = tid % 64;
-  double x[4] = {sel[wave][0], sel[wave][1], sel[wave][2], sel[wave][3]};
-  double lam, gv[4], Hm[10];
-  tensor_terms(muA, al, K, n, x, lane, lam, gv, Hm);
-  int it = 0;
+__device__ __forceinline__ double fact_d(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+
+// Dominant Z-eigenpair of one packed tensor per wavefront: every lane scans a
+// strided share of the S^3 seed points; the 4 best mutually distant lane seeds
+// are polished by SS-HOPM (shifted power iteration) accelerated with Newton
+// steps on the sphere: a Newton step is taken when it is an ascent direction
+// and a backtracking search along it raises lambda, otherwise the shifted
+// power step; the wave keeps the best lambda.
+__global__ void __launch_bounds__(64) k_pose_eig(int n, const double* __restrict__ seeds,
+                                                 const double* __restrict__ Cbuf,
+                                                 const int* __restrict__ okbuf, const int* __restrict__ count_dev,
+                                                 int count_host, int NB, int n_seeds, int max_iter, double tol,
+                                                 float* __restrict__ qbuf, double* __restrict__ lambuf,
+                                                 int* __restrict__ flagbuf) {
+  __shared__ EigLds t;
+  __shared__ double red[64 * 6];
+  const int K = num_components_dev(n);
+  const int b = blockIdx.x;
+  const int p = b / NB;
+  const int count = count_dev ? count_dev[0] : count_host;
+  if (p >= count) return;
+  const int lane = threadIdx.x;
+  if (!okbuf[b]) {
+    if (lane == 0) {
+      lambuf[b] = -INFINITY;
+      flagbuf[b] = 0;
+    }
+    return;
+  }
+  for (int k = lane; k < K; k += 64) {
+    int al[4];
+    alpha_of_dev(n, k, al);
+    double mu = fact_d(n);
+    for (int d = 0; d < 4; ++d) mu /= fact_d(al[d]);
+    t.muA[k] = mu * Cbuf[(long)b * K + k];
+    t.ex[k] = al[0] | (al[1] << 8) | (al[2] << 16) | (al[3] << 24);
+  }
+  __syncthreads();
+  // seed scan: every lane keeps the best of its strided share
+  double best = -INFINITY;
+  int bseed = 0;
+  for (int sd = lane; sd < n_seeds; sd += 64) {
+    const double q[4] = {seeds[4 * sd], seeds[4 * sd + 1], seeds[4 * sd + 2], seeds[4 * sd + 3]};
+    double v;
+    eval_terms<false>(t, n, K, q, lane, v, nullptr, nullptr);
+    if (v > best) {
+      best = v;
+      bseed = sd;
+    }
+  }
+  // the 4 best lane seeds that are mutually more than 10 degrees apart
+  // (|<q, q'>| < cos 5 deg) start the polish
+  red[lane * 6 + 0] = best;
+  red[lane * 6 + 1] = (double)bseed;
+  __syncthreads();
+  __shared__ int starts[4];
+  __shared__ int nstart;
+  __shared__ double sel[4][4];
+  if (lane == 0) {
+    const double cosx = 0.99619469809174553;
+    unsigned long long used = 0ull;
+    int ns = 0;
+    while (ns < 4) {
+      int bl = -1;
+      for (int l = 0; l < 64; ++l)
+        if (!((used >> l) & 1ull) && (bl < 0 || red[l * 6] > red[bl * 6])) bl = l;
+      if (bl < 0 || !(red[bl * 6] > -INFINITY)) break;
+      used |= 1ull << bl;
+      const int si = (int)red[bl * 6 + 1];
+      const double q[4] = {seeds[4 * si], seeds[4 * si + 1], seeds[4 * si + 2], seeds[4 * si + 3]};
+      bool far = true;
+      for (int i = 0; i < ns; ++i) {
+        const double dp = q[0] * sel[i][0] + q[1] * sel[i][1] + q[2] * sel[i][2] + q[3] * sel[i][3];
+        if (fabs(dp) > cosx) far = false;
+      }
+      if (!far) continue;
+      for (int d = 0; d < 4; ++d) sel[ns][d] = q[d];
+      starts[ns++] = (int)red[bl * 6 + 1];
+    }
+    nstart = ns;
+  }
+  __syncthreads();
+  double lam = -INFINITY;
+  double x[4] = {1.0, 0.0, 0.0, 0.0};
   bool conv = false;
-  for (it = 1; it <= max_iter; ++it) {
-    // Newton step on the sphere: (P M P - n lam P + x x^T) xi = -n (A x^{n-1} - lam x)
-    double M[4][4];
-    {
-      int h = 0;
+  // the best seed may iterate up to max_iter; the runner-up seeds, kept for
+  // near-degenerate tensors with competing maxima, stop after 30 iterations
+  const int lane_iters = lane == 0 ? max_iter : min(max_iter, 30);
+  if (lane < nstart) {
+    for (int d = 0; d < 4; ++d) x[d] = seeds[4 * starts[lane] + d];
+    double gv[4], Hm[10];
+    eval_terms<true>(t, n, K, x, lane, lam, gv, Hm);
+    const double nn1 = (double)(n * (n - 1));
+    for (int it = 1; it <= lane_iters; ++it) {
+      double M[4][4];
+#pragma unroll
       for (int i = 0; i < 4; ++i)
-        for (int j = i; j < 4; ++j, ++h) {
-          M[i][j] = n * (n - 1) * Hm[h];
+#pragma unroll
+        for (int j = i; j < 4; ++j) {
+          M[i][j] = nn1 * Hm[hidx(i, j)];
           M[j][i] = M[i][j];
         }
-    }
-    double grad[4];
-    for (int i = 0; i < 4; ++i) grad[i] = n * (gv[i] - lam * x[i]);
-    double PMP[4][4], Mx[4];
-    double xMx = 0.0;
-    for (int i = 0; i < 4; ++i) {
-      Mx[i] = 0.0;
-      for (int j = 0; j < 4; ++j) Mx[i] += M[i][j] * x[j];
-      xMx += x[i] * Mx[i];
-    }
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j)
-        PMP[i][j] = M[i][j] - x[i] * Mx[j] - Mx[i] * x[j] + x[i] * x[j] * xMx
-                    - n * lam * ((i == j ? 1.0 : 0.0) - x[i] * x[j]) + x[i] * x[j];
-    double xi[4] = {-grad[0], -grad[1], -grad[2], -grad[3]};
-    double y[4];
-    bool newton_ok = solve4(PMP, xi);
-    double ny = 0.0;
-    if (newton_ok) {
-      for (int i = 0; i < 4; ++i) { y[i] = x[i] + xi[i]; ny += y[i] * y[i]; }
-      newton_ok = ny > 0.0;
-    }
-    double lam_new = -INFINITY, gv2[4], Hm2[10];
-    if (newton_ok) {
-      ny = sqrt(ny);
-      for (int i = 0; i < 4; ++i) y[i] /= ny;
-      tensor_terms(muA, al, K, n, y, lane, lam_new, gv2, Hm2);
-    }
-    if (!(lam_new >= lam)) {
-      // shifted power step: y = A x^{n-1} + alpha x, alpha keeping the shifted
-      // objective locally convex (Gershgorin bound on lambda_min(A x^{n-2}))
-      double gmin = INFINITY;
-      double Hf[4][4];
-      int h = 0;
-      for (int i = 0; i < 4; ++i)
-        for (int j = i; j < 4; ++j, ++h) { Hf[i][j] = Hm[h]; Hf[j][i] = Hm[h]; }
+      double grad[4], Mx[4], xMx = 0.0, gnorm = 0.0;
+#pragma unroll
       for (int i = 0; i < 4; ++i) {
-        double r = Hf[i][i];
-        for (int j = 0; j < 4; ++j)
-          if (j != i) r -= fabs(Hf[i][j]);
-        gmin = fmin(gmin, r);
+        grad[i] = n * (gv[i] - lam * x[i]);
+        gnorm += grad[i] * grad[i];
+        Mx[i] = M[i][0] * x[0] + M[i][1] * x[1] + M[i][2] * x[2] + M[i][3] * x[3];
+        xMx += x[i] * Mx[i];
       }
-      const double alpha = fmax(0.0, 1e-6 - (n - 1) * gmin);
-      ny = 0.0;
-      for (int i = 0; i < 4; ++i) { y[i] = gv[i] + alpha * x[i]; ny += y[i] * y[i]; }
-      ny = sqrt(ny);
-      for (int i = 0; i < 4; ++i) y[i] /= ny;
-      tensor_terms(muA, al, K, n, y, lane, lam_new, gv2, Hm2);
-    }
-    const double dl = fabs(lam_new - lam);
-    double gnorm = 0.0;
-    for (int i = 0; i < 4; ++i) gnorm += grad[i] * grad[i];
-    for (int i = 0; i < 4; ++i) x[i] = y[i];
-    for (int i = 0; i < 4; ++i) gv[i] = gv2[i];
-    for (int hh = 0; hh < 10; ++hh) Hm[hh] = Hm2[hh];
-    const double lam_prev = lam;
-    lam = lam_new;
-    if (dl <= tol * fmax(1.0, fabs(lam)) && sqrt(gnorm) <= 1e-6 * fmax(1.0, fabs(lam_prev))) {
-      conv = true;
-      break;
+      gnorm = sqrt(gnorm);
+      const double scale = fmax(1.0, fabs(lam));
+      if (gnorm <= 1e-10 * scale) {
+        conv = true;
+        break;
+      }
+      // Newton direction on the sphere: (P M P - n lam P + x x^T) xi = -grad
+      double R[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          R[i][j] = M[i][j] - x[i] * Mx[j] - Mx[i] * x[j] + x[i] * x[j] * xMx -
+                    n * lam * ((i == j ? 1.0 : 0.0) - x[i] * x[j]) + x[i] * x[j];
+      double dir[4] = {-grad[0], -grad[1], -grad[2], -grad[3]};
+      const bool newton = solve4(R, dir);
+      double slope = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) slope += dir[i] * grad[i];
+      double y[4], lam_new = -INFINITY, gv2[4], Hm2[10];
+      bool moved = false;
+      if (newton && slope > 0.0) {
+        // Newton ascent direction with backtracking: 1, 1/2, 1/4, ...
+        double step = 1.0;
+        for (int bt = 0; bt < 8; ++bt, step *= 0.5) {
+          double ny = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            y[i] = x[i] + step * dir[i];
+            ny += y[i] * y[i];
+          }
+          ny = 1.0 / sqrt(ny);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) y[i] *= ny;
+          eval_terms<true>(t, n, K, y, lane, lam_new, gv2, Hm2);
+          if (lam_new >= lam) {
+            moved = true;
+            break;
+          }
+        }
+      }
+      if (!moved) {
+        // shifted power step (SS-HOPM): y = A x^{n-1} + alpha x, with alpha
+        // keeping (1/n) A x^n + alpha/2 |x|^2 locally convex (Gershgorin
+        // bound on the smallest eigenvalue of A x^{n-2}); it never lowers lambda
+        double gmin = INFINITY;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          double r = Hm[hidx(i, i)];
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (j != i) r -= fabs(Hm[i < j ? hidx(i, j) : hidx(j, i)]);
+          gmin = fmin(gmin, r);
+        }
+        const double alpha = fmax(0.0, 1e-6 - (n - 1) * gmin);
+        double ny = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          y[i] = gv[i] + alpha * x[i];
+          ny += y[i] * y[i];
+        }
+        ny = 1.0 / sqrt(ny);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[i] *= ny;
+        eval_terms<true>(t, n, K, y, lane, lam_new, gv2, Hm2);
+      }
+      const double dl = fabs(lam_new - lam);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        x[i] = y[i];
+        gv[i] = gv2[i];
+      }
+#pragma unroll
+      for (int i = 0; i < 10; ++i) Hm[i] = Hm2[i];
+      lam = lam_new;
+      if (dl <= tol * fmax(1.0, fabs(lam)) && gnorm <= 1e-7 * scale) {
+        conv = true;
+        break;
+      }
     }
   }
-  if (lane == 0) {
-    wres[wave][0] = lam;
-    for (int d = 0; d < 4; ++d) wres[wave][1 + d] = x[d];
-    wres[wave][5] = conv ? 0.0 : 1.0;
-  }
+  // wave argmax of lambda (lowest lane on ties)
   __syncthreads();
-  if (tid == 0) {
-    int b = 0;
-    for (int wv = 1; wv < 4; ++wv)
-      if (wres[wv][0] > wres[b][0]) b = wv;
-    double q[4] = {wres[b][1], wres[b][2], wres[b][3], wres[b][4]};
+  red[lane * 6 + 0] = lam;
+  red[lane * 6 + 1] = x[0];
+  red[lane * 6 + 2] = x[1];
+  red[lane * 6 + 3] = x[2];
+  red[lane * 6 + 4] = x[3];
+  red[lane * 6 + 5] = conv ? 0.0 : 1.0;
+  __syncthreads();
+  if (lane == 0) {
+    int bl = 0;
+    for (int l = 1; l < 64; ++l)
+      if (red[l * 6] > red[bl * 6]) bl = l;
+    double q[4] = {red[bl * 6 + 1], red[bl * 6 + 2], red[bl * 6 + 3], red[bl * 6 + 4]};
     const double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     double sgn = 1.0;
-    for (int d = 0; d < 4; ++d) {
+    for (int d = 0; d < 4; ++d)
       if (q[d] != 0.0) {
         sgn = q[d] > 0.0 ? 1.0 : -1.0;
         break;
       }
-    }
-    for (int d = 0; d < 4; ++d) out_quat[4 * peak + d] = (float)(sgn * q[d] / nq);
-    out_lambda[peak] = wres[b][0];
-    int flags = 0;
-    if (wres[b][5] != 0.0) flags |= TTM_POSE_NOT_CONVERGED;
-    if (w == 0.0) flags |= TTM_POSE_ZERO_NORM;
-    out_flags[peak] = flags;
+    for (int d = 0; d < 4; ++d) qbuf[4 * b + d] = (float)(sgn * q[d] / nq);
+    lambuf[b] = red[bl * 6];
+    flagbuf[b] = red[bl * 6 + 5] != 0.0 ? TTM_POSE_NOT_CONVERGED : 0;
   }
 }
 
-hipError_t launch_pose(const Geo& gg, const float* image, const float* comps, const float* mask,
-                       int order_n, const double* img_stats, float eps_v, int n_seeds, int max_iter,
-                       double tol, int max_peaks, const int* pos, const int* count, float* out_quat,
-                       double* out_lambda, int* out_flags, double* out_C, double* /*Cbuf*/,
-                       hipStream_t s) {
+// per candidate: the neighbour with the largest dominant Z-eigenvalue (the
+// centre first on ties, then the lower neighbour index)
+__global__ void k_pose_pick(PoseGeo g, const float* __restrict__ score, int K, const int* __restrict__ pos_in,
+                            const int* __restrict__ count_dev, int count_host, int NB,
+                            const double* __restrict__ Cbuf, const double* __restrict__ wbuf,
+                            const float* __restrict__ qbuf, const double* __restrict__ lambuf,
+                            const int* __restrict__ flagbuf, int* __restrict__ out_pos,
+                            float* __restrict__ out_quat, double* __restrict__ out_lambda,
+                            float* __restrict__ out_score, int* __restrict__ out_flags,
+                            double* __restrict__ out_C) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int count = count_dev ? count_dev[0] : count_host;
+  if (p >= count) return;
+  const int centre = NB == 27 ? 13 : 0;
+  int bk = centre;
+  double bl = lambuf[(long)p * NB + centre];
+  for (int k = 0; k < NB; ++k) {
+    const double v = lambuf[(long)p * NB + k];
+    if (v > bl) {
+      bl = v;
+      bk = k;
+    }
+  }
+  const long b = (long)p * NB + bk;
+  int o0, o1, o2;
+  neighbour_offset(bk, NB, o0, o1, o2);
+  const int x0 = pos_in[3 * p] + o0, x1 = pos_in[3 * p + 1] + o1, x2 = pos_in[3 * p + 2] + o2;
+  out_pos[3 * p] = x0;
+  out_pos[3 * p + 1] = x1;
+  out_pos[3 * p + 2] = x2;
+  for (int d = 0; d < 4; ++d) out_quat[4 * p + d] = qbuf[4 * b + d];
+  out_lambda[p] = bl;
+  int flags = flagbuf[b];
+  if (!(wbuf[b] > 0.0)) flags |= TTM_POSE_ZERO_NORM;
+  out_flags[p] = flags;
+  if (out_score) out_score[p] = score ? score[((long)x0 * g.n1 + x1) * g.n2 + x2] : 0.0f;
+  if (out_C)
+    for (int k = 0; k < K; ++k) out_C[(long)p * K + k] = Cbuf[b * K + k];
+}
+
+static PoseGeo make_posegeo(const Geo& gg) {
   PoseGeo g;
   g.n0 = gg.n0; g.n1 = gg.n1; g.n2 = gg.n2;
   g.L0 = gg.L0; g.L1 = gg.L1; g.L2 = gg.L2;
-  hipLaunchKernelGGL(k_pose, dim3(max_peaks), dim3(256), 0, s, g, image, comps, mask, order_n, img_stats,
-                     eps_v, n_seeds, max_iter, tol, pos, count, out_quat, out_lambda, out_flags, out_C);
+  g.lo0 = gg.c0; g.hi0 = gg.n0 - gg.L0 + gg.c0;
+  g.lo1 = gg.c1; g.hi1 = gg.n1 - gg.L1 + gg.c1;
+  g.lo2 = gg.c2; g.hi2 = gg.n2 - gg.L2 + gg.c2;
+  return g;
+}
+
+hipError_t launch_pose_tensor(const Geo& gg, const float* image, const float* comps, const float* mask,
+                              int order_n, const double* img_stats, float eps_v, int max_peaks, int refine,
+                              const int* pos_in, const int* count_dev, int count_host, const PoseScratch& ps,
+                              hipStream_t s) {
+  const PoseGeo g = make_posegeo(gg);
+  const int K = num_components(order_n);
+  const int NB = refine ? 27 : 1;
+  hipLaunchKernelGGL(k_pose_tensor, dim3((unsigned)(max_peaks * NB)), dim3(256), 0, s, g, image, comps, mask, K,
+                     img_stats, eps_v, pos_in, count_dev, count_host, NB, ps.C, ps.w, ps.ok);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int n_seeds, int max_iter,
+                             double tol, int max_peaks, int refine, const int* pos_in, const int* count_dev,
+                             int count_host, int* out_pos, float* out_quat, double* out_lambda,
+                             float* out_score, int* out_flags, double* out_C, const PoseScratch& ps,
+                             hipStream_t s) {
+  const PoseGeo g = make_posegeo(gg);
+  const int K = num_components(order_n);
+  const int NB = refine ? 27 : 1;
+  hipLaunchKernelGGL(k_seed_table, dim3((n_seeds + 255) / 256), dim3(256), 0, s, n_seeds, ps.seeds);
+  hipLaunchKernelGGL(k_pose_eig, dim3((unsigned)(max_peaks * NB)), dim3(64), 0, s, order_n, ps.seeds, ps.C, ps.ok,
+                     count_dev, count_host, NB, n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags);
+  hipLaunchKernelGGL(k_pose_pick, dim3((max_peaks + 63) / 64), dim3(64), 0, s, g, score, K, pos_in, count_dev,
+                     count_host, NB, ps.C, ps.w, ps.q, ps.lam, ps.flags, out_pos, out_quat, out_lambda,
+                     out_score, out_flags, out_C);
   return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
     _fields_ = [("eps_v", ctypes.c_float), ("threshold", ctypes.c_float),
                 ("min_dist", ctypes.c_float), ("max_peaks", ctypes.c_int32),
                 ("n_seeds", ctypes.c_int32), ("hopm_max_iter", ctypes.c_int32),
-                ("hopm_tol", ctypes.c_double)]
+                ("hopm_tol", ctypes.c_double), ("refine", ctypes.c_int32)]
 
 
 _lib = None
@@ -67,6 +67,10 @@ _SIGS = {
     "ttm_pose_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32, _OPTP]),
     "ttm_recover_pose": (_I32, [_P, _P, _P, _P, _DIMS, _DIMS, _I32, _OPTP, _P, _P, _P, _P, _P, _P, _P,
                                 _P, _SZ, _P]),
+    "ttm_pose_at": (_I32, [_P, _P, _P, _DIMS, _DIMS, _I32, _OPTP, _P, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "ttm_match_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32, _OPTP]),
+    "ttm_match": (_I32, [_P, _DIMS, _P, _DIMS, _I32, _P, _OPTP, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ,
+                         _P]),
     "tm_classical_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32]),
     "tm_classical": (_I32, [_P, _DIMS, _P, _P, _DIMS, _P, _I32, _OPTP, _P, _P, _P, _SZ, _P]),
     "ttm_profile_enable": (None, [_I32]),
@@ -260,6 +264,37 @@ def recover_pose(score: torch.Tensor, image: torch.Tensor, components: torch.Ten
     return out
 
 
+def pose_at(image: torch.Tensor, components: torch.Tensor, mask: torch.Tensor, order: int, positions,
+            opt: Options | None = None, want_C: bool = True) -> dict:
+    """Dominant Z-eigenpair of C_n at caller-given positions (P, 3)."""
+    dev = image.device
+    K = num_components(order)
+    N = _dims(image.shape)
+    L = _dims(mask.shape)
+    pos = torch.as_tensor(positions, dtype=torch.int32).reshape(-1, 3).contiguous().to(dev)
+    P = pos.shape[0]
+    opt = opt or default_options()
+    if P > opt.max_peaks:
+        opt = Options.from_buffer_copy(opt)
+        opt.max_peaks = P
+    out_pos = torch.zeros((P, 3), dtype=torch.int32, device=dev)
+    quat = torch.zeros((P, 4), dtype=torch.float32, device=dev)
+    lam = torch.zeros((P,), dtype=torch.float64, device=dev)
+    flags = torch.zeros((P,), dtype=torch.int32, device=dev)
+    C = torch.zeros((P, K), dtype=torch.float64, device=dev) if want_C else None
+    nws = lib().ttm_pose_workspace_bytes(N, L, order, ctypes.byref(opt))
+    ws = _workspace(nws, dev)
+    st = lib().ttm_pose_at(_dev(image, "image"), _dev(components, "components"), _dev(mask, "mask"), N, L,
+                           order, ctypes.byref(opt), pos.data_ptr(), P, out_pos.data_ptr(), quat.data_ptr(),
+                           lam.data_ptr(), flags.data_ptr(), C.data_ptr() if C is not None else None,
+                           ws.data_ptr(), nws, _stream(dev))
+    _check(st, "ttm_pose_at")
+    out = dict(pos=out_pos, quat=quat, lam=lam, flags=flags)
+    if C is not None:
+        out["C"] = C
+    return out
+
+
 class PoseBuffers:
     """Preallocated outputs and workspace of ``recover_pose_async``."""
 
@@ -297,6 +332,41 @@ def recover_pose_async(score: torch.Tensor, image: torch.Tensor, components: tor
                                 bufs.flags.data_ptr(), bufs.C.data_ptr(), bufs.count.data_ptr(),
                                 bufs.ws.data_ptr(), bufs.ws.numel(), _stream(dev))
     _check(st, "ttm_recover_pose")
+
+
+class MatchBuffers(PoseBuffers):
+    """Preallocated outputs and workspace of ``match``."""
+
+    def __init__(self, image_shape, L, order: int, opt: Options, device):
+        K = num_components(order)
+        super().__init__(opt, K, device)
+        self.score = torch.empty(tuple(image_shape), dtype=torch.float32, device=device)
+        self.w = torch.empty(tuple(image_shape), dtype=torch.float32, device=device)
+        self.peak_score = torch.zeros((int(opt.max_peaks),), dtype=torch.float32, device=device)
+        nws = lib().ttm_match_workspace_bytes(_dims(image_shape), _dims(L), order, ctypes.byref(opt))
+        self.ws = _workspace(nws, device)
+
+    def result(self) -> dict:
+        cnt = self.count.cpu()
+        n = int(cnt[0])
+        return dict(pos=self.pos[:n], quat=self.quat[:n], lam=self.lam[:n], score=self.peak_score[:n],
+                    flags=self.flags[:n], C=self.C[:n], count=n,
+                    truncated=bool(int(cnt[1]) & PEAKS_TRUNCATED))
+
+
+def match(image: torch.Tensor, bank: torch.Tensor, mask: torch.Tensor, order: int, opt: Options,
+          bufs: MatchBuffers):
+    """Correlation, peaks and poses in one asynchronous call (ttm_match);
+    results land in ``bufs`` (score map in bufs.score, w in bufs.w)."""
+    dev = image.device
+    N = _dims(image.shape)
+    L = _dims(mask.shape)
+    st = lib().ttm_match(_dev(image, "image"), N, bank.data_ptr(), L, order, _dev(mask, "mask"),
+                         ctypes.byref(opt), bufs.score.data_ptr(), bufs.w.data_ptr(), bufs.pos.data_ptr(),
+                         bufs.quat.data_ptr(), bufs.lam.data_ptr(), bufs.peak_score.data_ptr(),
+                         bufs.flags.data_ptr(), bufs.C.data_ptr(), bufs.count.data_ptr(), bufs.ws.data_ptr(),
+                         bufs.ws.numel(), _stream(dev))
+    _check(st, "ttm_match")
 
 
 def tm_classical(image: torch.Tensor, tmpl: torch.Tensor, mask: torch.Tensor, quats,

@@ -87,6 +87,15 @@ def test_argument_validation_without_gpu():
     bad = _opt(threshold=-1.0)
     args[7] = ctypes.byref(bad)
     assert L.ttm_recover_pose(*args) == -1
+    bad = _opt(refine=2)
+    args[7] = ctypes.byref(bad)
+    assert L.ttm_recover_pose(*args) == -1
+    # pose at given positions: more positions than max_peaks
+    ok = _opt(max_peaks=2)
+    assert L.ttm_pose_at(fake, fake, fake, N, T, 4, ctypes.byref(ok), fake, 3, fake, fake, fake, fake, None,
+                         fake, big, None) == -1
+    assert L.ttm_pose_at(fake, fake, fake, N, T, 4, ctypes.byref(ok), fake, 2, fake, fake, fake, fake, None,
+                         fake, 16, None) == -3
     # classical
     assert L.tm_classical(fake, N, fake, fake, T, q, 0, ctypes.byref(o), fake, fake, fake, big, None) == -1
     assert L.tm_classical(fake, N, fake, fake, T, q0, 2, ctypes.byref(o), fake, fake, fake, big, None) == -1

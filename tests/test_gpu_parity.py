@@ -229,3 +229,103 @@ def test_tomogram_sampled_parity():
     wref = O.local_norm_at(f64, wl.mask.astype(np.float64), xs)
     wgot = wv.cpu().numpy()[xs[:, 0], xs[:, 1], xs[:, 2]]
     assert np.allclose(wgot, wref, rtol=1e-4)
+
+
+def test_pose_at_given_positions_and_refinement():
+    """ttm_pose_at at planted centres and one voxel off, with and without the
+    3x3x3 refinement by the dominant Z-eigenvalue, against the oracle."""
+    img, tmpl, mask, q, w = rand_setup(61, (32, 32, 32), (8, 8, 8), 4.0, 64)
+    n = 4
+    s = O.rotated_template(tmpl, mask, q[9])
+    sl = tuple(slice(15 - 4, 15 + 4) for _ in range(3))
+    img[sl] += 1.5 * np.sqrt(mask.sum()) * s.astype(np.float32)
+    comps, _ = ttm.build_tensor_template(dev(tmpl), dev(mask), n, q, w)
+    T = oracle_T(tmpl, mask, n, q, w)
+    f64 = img.astype(np.float64)
+    m64 = mask.astype(np.float64)
+    xs = np.array([[15, 15, 15], [16, 15, 14], [10, 20, 12], [4, 4, 4]], dtype=np.int32)
+    res = ttm.pose_at(dev(img), comps, dev(mask), n, xs, ttm.default_options(max_peaks=4))
+    C_ref = O.tensor_field_at(f64, T, m64, xs)
+    assert np.abs(res["C"].cpu().numpy() - C_ref).max() <= 1e-5 * np.abs(C_ref).max()
+    assert np.array_equal(res["pos"].cpu().numpy(), xs)
+    for i in range(len(xs)):
+        qo, lo, second = O.dominant_z_eigenpair(C_ref[i], n, n_brute=100000)
+        assert abs(res["lam"].cpu().numpy()[i] - lo) <= 1e-6 * abs(lo) + 1e-9
+        if second < lo - 1e-3 * abs(lo):
+            assert O.rotation_angle_deg(res["quat"].cpu().numpy()[i], qo) <= 1.0
+    # refinement: the chosen neighbour maximises lambda
+    opt = ttm.default_options(max_peaks=4, refine=1)
+    rr = ttm.pose_at(dev(img), comps, dev(mask), n, xs[:2], opt)
+    for i in range(2):
+        pos, qo, lo, lams = O.refine_by_eigenvalue(f64, T, m64, n, xs[i], n_brute=50000)
+        got = rr["pos"].cpu().numpy()[i]
+        srt = np.sort(lams)[::-1]
+        if srt[0] - srt[1] > 1e-6 * abs(srt[0]):
+            assert np.array_equal(got, pos)
+        k = int(np.argmax([(np.asarray(got) - xs[i] == o).all() for o in O.neighbourhood_offsets()]))
+        assert abs(rr["lam"].cpu().numpy()[i] - lams[k]) <= 1e-6 * abs(lams[k]) + 1e-9
+
+
+@pytest.mark.parametrize("refine", [0, 1])
+def test_match_uses_the_correlated_field(refine):
+    """ttm_match: the same score map and peaks as ttm_correlate + peak picking,
+    C_n at the peaks read from the correlated field (float32 FFT precision)
+    against the oracle's direct float64 sums, and the oracle's rotation."""
+    wl = synth.workload_small()
+    n = 4
+    q = synth.super_fibonacci(400).astype(np.float32)
+    wts = np.full(len(q), 1.0 / len(q))
+    comps, bank = ttm.build_tensor_template(dev(wl.template), dev(wl.mask), n, q, wts,
+                                            image_shape=wl.image.shape)
+    img = dev(wl.image)
+    opt = ttm.default_options(max_peaks=6, min_dist=8.0, refine=refine)
+    bufs = ttm.MatchBuffers(wl.image.shape, wl.template.shape, n, opt, "cuda")
+    ttm.match(img, bank, dev(wl.mask), n, opt, bufs)
+    res = bufs.result()
+    score, _ = ttm.correlate(img, bank, dev(wl.mask), n)
+    assert torch.equal(score, bufs.score)
+    F = score.cpu().numpy()
+    cand = O.find_peaks_fast(F, wl.template.shape, 0.0, 8.0, 6)
+    got = res["pos"].cpu().numpy()
+    assert len(got) == len(cand)
+    T = oracle_T(wl.template, wl.mask, n, q, wts)
+    f64 = wl.image.astype(np.float64)
+    m64 = wl.mask.astype(np.float64)
+    C_ref = O.tensor_field_at(f64, T, m64, got)
+    C = res["C"].cpu().numpy()
+    assert np.abs(C - C_ref).max() <= 2e-4 * np.abs(C_ref).max(), np.abs(C - C_ref).max() / np.abs(C_ref).max()
+    if refine == 0:
+        assert np.array_equal(got, cand)
+    else:
+        assert np.all(np.abs(got - cand).max(axis=1) <= 1)
+    lam = res["lam"].cpu().numpy()
+    quats = res["quat"].cpu().numpy()
+    for i in range(len(got)):
+        qo, lo, second = O.dominant_z_eigenpair(C_ref[i], n, n_brute=100000)
+        assert abs(lam[i] - lo) <= 2e-4 * abs(lo)
+        if second < lo - 1e-2 * abs(lo):
+            assert O.rotation_angle_deg(quats[i], qo) <= 1.0
+    if refine:
+        # the reported neighbour maximises the eigenvalue among the 27 (oracle,
+        # up to the float32 field precision)
+        for i in range(min(3, len(got))):
+            pos, _, lo, lams = O.refine_by_eigenvalue(f64, T, m64, n, cand[i], n_brute=50000)
+            assert lam[i] >= np.max(lams) - 2e-4 * abs(np.max(lams))
+
+
+@pytest.mark.parametrize("min_dist,max_peaks", [(12.0, 40), (4.0, 300), (30.0, 8)])
+def test_peak_search_rounds_match_oracle(min_dist, max_peaks):
+    """Random score maps with dense local maxima: the bounded candidate lists
+    of the GPU search (a first round of 2048 keys, a second of 16384 when the
+    first runs out) give exactly the oracle's greedy result."""
+    rng = np.random.default_rng(int(min_dist * 7 + max_peaks))
+    N, L = (64, 64, 64), (8, 8, 8)
+    F = rng.random(N).astype(np.float32)
+    img = rng.standard_normal(N).astype(np.float32)
+    comps = dev(rng.standard_normal((10,) + L).astype(np.float32))
+    mask = dev(box_mask(L, 4.0))
+    opt = ttm.default_options(max_peaks=max_peaks, min_dist=min_dist, threshold=0.0, n_seeds=256)
+    res = ttm.recover_pose(dev(F), dev(img), comps, mask, 2, opt, want_C=False)
+    ref = O.find_peaks_fast(F, L, 0.0, min_dist, max_peaks)
+    assert np.array_equal(res["pos"].cpu().numpy(), ref)
+    assert not res["truncated"]
