@@ -47,6 +47,8 @@ def parse():
                    help="target CPU time of the oracle baseline sample (0 = skip)")
     p.add_argument("--seed", type=int, default=2000)
     p.add_argument("--profile-json", default="", help="also write the full result here")
+    p.add_argument("--copy-calibration", type=int, default=0,
+                   help="only copy this many MiB device-to-device (counter calibration) and exit")
     return p.parse_args()
 
 
@@ -159,6 +161,16 @@ def main():
                                    "would shard", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 4}), flush=True)
+        return
 
     from oracle.ttm_oracle import rotation_angle_deg as angle   # reporting only: angle between quaternions
     from paper_2311_07561_amd import synth, ttm

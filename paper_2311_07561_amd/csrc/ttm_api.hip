@@ -37,7 +37,7 @@ static bool fits(const ttm_dims& L, const ttm_dims& N) {
 
 static Geo make_geo(const ttm_dims& N, const ttm_dims& L) {
   Geo g;
-  g.n0 = N.n0; g.n1 = N.n1; g.n2 = N.n2; g.h2 = N.n2 / 2 + 1;
+  g.n0 = N.n0; g.n1 = N.n1; g.n2 = N.n2; g.h2 = N.n2 / 2 + 1; g.p2 = row_pitch(N.n2);
   g.L0 = L.n0; g.L1 = L.n1; g.L2 = L.n2;
   g.c0 = L.n0 / 2; g.c1 = L.n1 / 2; g.c2 = L.n2 / 2;
   return g;
@@ -180,8 +180,8 @@ static ttm_status image_forward(const Geo& g, const float* image, float2* Xf, fl
   TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), partials, stats, stream));
   TTM_PROF(PC_STATS, launch_mask_sum(mask, L3, stats + 2, stream));
   TTM_PROF(PC_ROWS, launch_r2c_rows(g.n2, image, g.n2, g.n2, rows, Xf, Xg, rows, 0, 1, stats, stream));
-  TTM_PROF(PC_PEN_FWD, launch_pencils(g.n1, false, Xf, (long)g.n0 * g.h2, g.h2, (long)g.n1 * g.h2, g.h2, g.n1,
-                                      0, 2, (long)(Xg - Xf), stream));
+  TTM_PROF(PC_PEN_FWD, launch_pencils(g.n1, false, Xf, (long)g.n0 * g.p2, g.p2, g.h2, (long)g.n1 * g.p2, g.p2,
+                                      g.n1, 0, 2, (long)(Xg - Xf), stream));
   return TTM_OK;
 }
 
@@ -189,8 +189,8 @@ static ttm_status image_forward(const Geo& g, const float* image, float2* Xf, fl
 static ttm_status bank_forward(const Geo& g, const float* src, int nent, float2* bank, hipStream_t stream) {
   const long rows = (long)nent * g.L0 * g.L1;
   TTM_PROF(PC_ROWS, launch_r2c_rows(g.n2, src, g.L2, g.L2, rows, bank, nullptr, g.L1, g.n1, 0, nullptr, stream));
-  TTM_PROF(PC_PEN_FWD, launch_pencils(g.n1, false, bank, (long)nent * g.L0 * g.h2, g.h2, (long)g.n1 * g.h2,
-                                      g.h2, g.L1, 0, 1, 0, stream));
+  TTM_PROF(PC_PEN_FWD, launch_pencils(g.n1, false, bank, (long)nent * g.L0 * g.p2, g.p2, g.h2,
+                                      (long)g.n1 * g.p2, g.p2, g.L1, 0, 1, 0, stream));
   return TTM_OK;
 }
 
@@ -239,7 +239,7 @@ const char* ttm_status_string(int32_t s) {
 
 size_t ttm_bank_bytes(ttm_dims N, ttm_dims L, int32_t K) {
   if (!dims_ok(N) || !dims_ok(L) || K < 1) return 0;
-  return (size_t)(K + 1) * L.n0 * N.n1 * (N.n2 / 2 + 1) * sizeof(float2);
+  return (size_t)(K + 1) * L.n0 * N.n1 * row_pitch(N.n2) * sizeof(float2);
 }
 
 size_t ttm_build_workspace_bytes(ttm_dims L, int32_t order_n, int32_t n_rot, ttm_dims N) {
@@ -307,7 +307,7 @@ static ttm_status correlate_into(const Geo& g, int order_n, int K, const float* 
   TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, bk, g.bank_slab(), K + 1, w.H, half, stream));
   TTM_PROF(PC_PASS1, launch_pass1(g, w.Xg, bk + (long)K * g.bank_slab(), g.bank_slab(), 1,
                                   w.H + (long)(K + 1) * half, half, stream));
-  TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.h2, g.h2, (long)g.n1 * g.h2, g.h2, g.n1,
+  TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.p2, g.p2, g.h2, (long)g.n1 * g.p2, g.p2, g.n1,
                                       g.c1, K + 2, half, stream));
   Pass3Args a;
   std::memset(&a, 0, sizeof(a));
@@ -481,7 +481,7 @@ ttm_status tm_classical(const float* image, ttm_dims N, const float* tmpl, const
   TTM_CALL(bank_forward(g, mask, 1, w.bbank, stream));
   TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, w.bbank, g.bank_slab(), 1, w.H, half, stream));
   TTM_PROF(PC_PASS1, launch_pass1(g, w.Xg, w.bbank, g.bank_slab(), 1, w.H + half, half, stream));
-  TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.h2, g.h2, (long)g.n1 * g.h2, g.h2, g.n1, g.c1, 2, half,
+  TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.p2, g.p2, g.h2, (long)g.n1 * g.p2, g.p2, g.n1, g.c1, 2, half,
                          stream));
   Pass3Args a;
   std::memset(&a, 0, sizeof(a));
@@ -500,7 +500,7 @@ ttm_status tm_classical(const float* image, ttm_dims N, const float* tmpl, const
     TTM_PROF(PC_BUILD, launch_rot_write(tmpl, mask, L.n0, L.n1, L.n2, w.quats, w.rstats, j0, nb, w.tbatch, stream));
     TTM_CALL(bank_forward(g, w.tbatch, nb, w.bbank, stream));
     TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, w.bbank, g.bank_slab(), nb, w.H, half, stream));
-    TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.h2, g.h2, (long)g.n1 * g.h2, g.h2, g.n1, g.c1, nb,
+    TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.p2, g.p2, g.h2, (long)g.n1 * g.p2, g.p2, g.n1, g.c1, nb,
                            half, stream));
     Pass3Args m;
     std::memset(&m, 0, sizeof(m));

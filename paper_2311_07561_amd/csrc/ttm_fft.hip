@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(256) k_r2c_rows(const float* __restrict__ src,
                                                   const double* __restrict__ stats) {
   using C = RowCfg<M>;
   constexpr int R1 = C::R1, R2 = C::R2, RW = C::RW, SP = C::SP;
-  constexpr int N2 = 2 * M, H2 = M + 1;
+  constexpr int N2 = 2 * M, H2 = M + 1, P2 = (H2 + 15) / 16 * 16;
   __shared__ float2 stage[RW * SP];
   __shared__ float2 twM[M];
   __shared__ float2 tw2[N2];
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(256) k_r2c_rows(const float* __restrict__ src,
       const float2 pw = cmul(tw2[k], csub(zk, zm));
       const float2 X = make_float2(ev.x + 0.5f * pw.y, ev.y - 0.5f * pw.x);
       const long drow = (r / grp) * grp_stride + (r % grp);
-      dst[drow * H2 + k] = X;
+      dst[drow * P2 + k] = X;
     }
   }
 }
@@ -215,10 +215,13 @@ struct PenCfg {
   static constexpr int PW = 256 / R1;    // pencils per block
 };
 
-template <int N, bool INV>
-__global__ void __launch_bounds__(256) k_pencils(float2* __restrict__ data, long npencils, long Q,
-                                                 long S_outer, long S_axis, int nin, int shift,
-                                                 long batch_stride) {
+// One block transforms PW pencils.  Pencils in the row padding
+// (p % Q >= qvalid) are transformed too: the padding columns hold no data
+// and are never read as data, so this only saves branches.  Element offsets
+// are 32-bit from the block's array base (one array holds < 2^31 elements).
+template <int N, bool INV, bool PRUNED>
+__global__ void __launch_bounds__(256) k_pencils(float2* __restrict__ data, int npencils, int Q, long S_outer,
+                                                 int S_axis, int nin, int shift, long batch_stride) {
   using C = PenCfg<N>;
   constexpr int R1 = C::R1, R2 = C::R2, PW = C::PW;
   __shared__ float2 lds[PW * N];
@@ -226,51 +229,67 @@ __global__ void __launch_bounds__(256) k_pencils(float2* __restrict__ data, long
   const int tid = threadIdx.x;
   fill_twiddles(tw, N, tid, 256);
   const int pl = tid % PW, a = tid / PW;
-  const long p = (long)blockIdx.x * PW + pl;
+  const int p = blockIdx.x * PW + pl;
   const bool valid = p < npencils;
-  float2* base = data + (long)blockIdx.y * batch_stride + (valid ? (p / Q) * S_outer + (p % Q) : 0);
+  float2* __restrict__ arr = data + (long)blockIdx.y * batch_stride;
+  const unsigned toff = valid ? (unsigned)((long)(p / Q) * S_outer + (p % Q)) + (unsigned)(a * S_axis) : 0u;
+  const unsigned step = (unsigned)(R1 * S_axis);
   float2 x[R2], o[R2];
 #pragma unroll
   for (int b = 0; b < R2; ++b) {
-    const int j = a + R1 * b;
-    x[b] = (valid && j < nin) ? base[j * S_axis] : make_float2(0.0f, 0.0f);
+    if (PRUNED)
+      x[b] = (valid && a + R1 * b < nin) ? arr[toff + b * step] : make_float2(0.0f, 0.0f);
+    else
+      x[b] = arr[toff + b * step];
   }
   engineA<N, PW, INV>(x, o, lds, tw, pl, a);
   if (!valid) return;
+  const unsigned base = toff - (unsigned)(a * S_axis);
 #pragma unroll
   for (int k = 0; k < R2 / R1; ++k)
 #pragma unroll
     for (int d = 0; d < R1; ++d) {
       const int j = (a + R1 * k) + R2 * d;
-      base[((j + shift) & (N - 1)) * S_axis] = o[k * R1 + d];
+      arr[base + (unsigned)(((j + shift) & (N - 1)) * S_axis)] = o[k * R1 + d];
     }
 }
 
 template <int N>
-static hipError_t pencils_n(bool inverse, float2* data, long npencils, long Q, long S_outer,
+static hipError_t pencils_n(bool inverse, float2* data, long npencils, long Q, long qvalid, long S_outer,
                             long S_axis, int nin, int shift, int nbatch, long batch_stride,
                             hipStream_t s) {
+  (void)qvalid;
   constexpr int PW = PenCfg<N>::PW;
   dim3 grid((unsigned)((npencils + PW - 1) / PW), (unsigned)nbatch);
-  if (inverse)
-    hipLaunchKernelGGL((k_pencils<N, true>), grid, dim3(256), 0, s, data, npencils, Q, S_outer,
-                       S_axis, nin, shift, batch_stride);
-  else
-    hipLaunchKernelGGL((k_pencils<N, false>), grid, dim3(256), 0, s, data, npencils, Q, S_outer,
-                       S_axis, nin, shift, batch_stride);
+  const bool pruned = nin < N;
+  if (inverse) {
+    if (pruned)
+      hipLaunchKernelGGL((k_pencils<N, true, true>), grid, dim3(256), 0, s, data, (int)npencils, (int)Q, S_outer,
+                         (int)S_axis, nin, shift, batch_stride);
+    else
+      hipLaunchKernelGGL((k_pencils<N, true, false>), grid, dim3(256), 0, s, data, (int)npencils, (int)Q, S_outer,
+                         (int)S_axis, nin, shift, batch_stride);
+  } else {
+    if (pruned)
+      hipLaunchKernelGGL((k_pencils<N, false, true>), grid, dim3(256), 0, s, data, (int)npencils, (int)Q, S_outer,
+                         (int)S_axis, nin, shift, batch_stride);
+    else
+      hipLaunchKernelGGL((k_pencils<N, false, false>), grid, dim3(256), 0, s, data, (int)npencils, (int)Q, S_outer,
+                         (int)S_axis, nin, shift, batch_stride);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long Q, long S_outer,
-                          long S_axis, int nin, int shift, int nbatch, long batch_stride,
+hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long Q, long qvalid,
+                          long S_outer, long S_axis, int nin, int shift, int nbatch, long batch_stride,
                           hipStream_t s) {
   switch (N) {
-    case 16: return pencils_n<16>(inverse, data, npencils, Q, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
-    case 32: return pencils_n<32>(inverse, data, npencils, Q, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
-    case 64: return pencils_n<64>(inverse, data, npencils, Q, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
-    case 128: return pencils_n<128>(inverse, data, npencils, Q, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
-    case 256: return pencils_n<256>(inverse, data, npencils, Q, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
-    case 512: return pencils_n<512>(inverse, data, npencils, Q, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
+    case 16: return pencils_n<16>(inverse, data, npencils, Q, qvalid, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
+    case 32: return pencils_n<32>(inverse, data, npencils, Q, qvalid, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
+    case 64: return pencils_n<64>(inverse, data, npencils, Q, qvalid, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
+    case 128: return pencils_n<128>(inverse, data, npencils, Q, qvalid, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
+    case 256: return pencils_n<256>(inverse, data, npencils, Q, qvalid, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
+    case 512: return pencils_n<512>(inverse, data, npencils, Q, qvalid, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -279,7 +298,7 @@ hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long
 // pass 1: axis 0, fused fan-out (Section 2: <f,g> = F^-1(F(f) conj F(g)))
 // ----------------------------------------------------------------------------
 template <int N0>
-__global__ void __launch_bounds__(256) k_pass1(const float2* __restrict__ src, long P, int L0,
+__global__ void __launch_bounds__(256) k_pass1(const float2* __restrict__ src, long P, int p2, int h2, int L0,
                                                const float2* __restrict__ tmpl, long tmpl_stride, int nt,
                                                float2* __restrict__ out, long out_stride, int shift0) {
   using C = PenCfg<N0>;
@@ -289,31 +308,48 @@ __global__ void __launch_bounds__(256) k_pass1(const float2* __restrict__ src, l
   const int tid = threadIdx.x;
   fill_twiddles(tw, N0, tid, 256);
   const int pl = tid % PW, a = tid / PW;
-  const long p = (long)blockIdx.x * PW + pl;
-  const bool valid = p < P;
-  const long pp = valid ? p : 0;
+  const int p = blockIdx.x * PW + pl;
+  // pencils in the row padding (column >= h2) carry no data: they are
+  // transformed as zeros and not stored
+  const bool valid = p < P && (p % p2) < h2;
+  const unsigned pu = valid ? (unsigned)p : 0u;
+  const unsigned P32 = (unsigned)P;
+  const unsigned step = (unsigned)R1 * P32;
   float2 x[R2], F[R2], T[R2], y[R2];
+  {
+    const unsigned off = (unsigned)a * P32 + pu;
 #pragma unroll
-  for (int b = 0; b < R2; ++b) x[b] = valid ? src[(long)(a + R1 * b) * P + pp] : make_float2(0.0f, 0.0f);
+    for (int b = 0; b < R2; ++b) x[b] = src[off + b * step];
+    if (!valid) {
+#pragma unroll
+      for (int b = 0; b < R2; ++b) x[b] = make_float2(0.0f, 0.0f);
+    }
+  }
   engineA<N0, PW, false>(x, F, lds, tw, pl, a);
+  const int bmax = (L0 + R1 - 1) / R1;      // the template block has L0 rows along axis 0
 #pragma unroll 1
   for (int i = 0; i < nt; ++i) {
-    const float2* tb = tmpl + (long)i * tmpl_stride;
+    const float2* __restrict__ tb = tmpl + (long)i * tmpl_stride;
+    const unsigned off = (unsigned)a * P32 + pu;
 #pragma unroll
     for (int b = 0; b < R2; ++b) {
-      const int j = a + R1 * b;
-      x[b] = (valid && j < L0) ? tb[(long)j * P + pp] : make_float2(0.0f, 0.0f);
+      x[b] = make_float2(0.0f, 0.0f);
+      if (b < bmax && a + R1 * b < L0) x[b] = tb[off + b * step];
+    }
+    if (!valid) {
+#pragma unroll
+      for (int b = 0; b < R2; ++b) x[b] = make_float2(0.0f, 0.0f);
     }
     engineA<N0, PW, false>(x, T, lds, tw, pl, a);
 #pragma unroll
     for (int j = 0; j < R2; ++j) T[j] = cmulc(F[j], T[j]);
     engineB<N0, PW, true>(T, y, lds, tw, pl, a);
     if (valid) {
-      float2* ob = out + (long)i * out_stride;
+      float2* __restrict__ ob = out + (long)i * out_stride;
 #pragma unroll
       for (int g = 0; g < R2; ++g) {
-        const int j = a + R1 * g;
-        ob[(long)((j + shift0) & (N0 - 1)) * P + p] = y[g];
+        const unsigned j = (unsigned)((a + R1 * g + shift0) & (N0 - 1));
+        ob[j * P32 + pu] = y[g];
       }
     }
   }
@@ -323,9 +359,9 @@ template <int N0>
 static hipError_t pass1_n(const Geo& g, const float2* src, const float2* tmpl, long tmpl_stride,
                           int nt, float2* out, long out_stride, hipStream_t s) {
   constexpr int PW = PenCfg<N0>::PW;
-  const long P = (long)g.n1 * g.h2;
+  const long P = (long)g.n1 * g.p2;
   dim3 grid((unsigned)((P + PW - 1) / PW));
-  hipLaunchKernelGGL((k_pass1<N0>), grid, dim3(256), 0, s, src, P, g.L0, tmpl, tmpl_stride, nt, out,
+  hipLaunchKernelGGL((k_pass1<N0>), grid, dim3(256), 0, s, src, P, g.p2, g.h2, g.L0, tmpl, tmpl_stride, nt, out,
                      out_stride, g.c0);
   return hipGetLastError();
 }
@@ -349,7 +385,7 @@ hipError_t launch_pass1(const Geo& g, const float2* src, const float2* tmpl, lon
 // IDFT_M(2Z)(m) = N (x(2m) + i x(2m+1)).
 // ----------------------------------------------------------------------------
 struct P3Geo {
-  int n0, n1, n2, h2;
+  int n0, n1, n2, h2, p2;
   int lo0, hi0, lo1, hi1, lo2, hi2;   // valid region, inclusive bounds
   int c2;
   double inv_vol;
@@ -376,9 +412,10 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
   float2 wv[R2];     // w (P3_SCORE) or running best (P3_MAX)
   float2 acc[R2];    // sum mu G^2 (P3_SCORE)
   int2 bidx[R2];     // running argmax (P3_MAX)
-  double msum = 0.0, floor_v = 0.0;
+  double msum = 0.0, floor_v = 0.0, inv_msum = 0.0;
   if (MODE != P3_MAX) {
     msum = A.stats[2];
+    inv_msum = 1.0 / msum;
     floor_v = (double)A.eps_v * msum * A.stats[1];
   }
 #pragma unroll
@@ -413,14 +450,15 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
   // while the current pair is transformed (each thread owns a fixed slice of
   // the block's contiguous RW x H2 tile)
   constexpr int PF = (RW * H2 + 255) / 256;
+  constexpr int P2 = (H2 + 15) / 16 * 16;       // row pitch of the arrays
   const long nvalid = (nrows - r0 < RW ? nrows - r0 : RW) * (long)H2;
   float2 pf[PF];
   {
-    const float2* Hn = A.H + (long)pair_of(0) * A.pstride + r0 * H2;
+    const float2* Hn = A.H + (long)pair_of(0) * A.pstride + r0 * P2;
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int e = tid + 256 * i;
-      pf[i] = (e < nvalid) ? Hn[e] : make_float2(0.0f, 0.0f);
+      pf[i] = (e < nvalid) ? Hn[(e / H2) * P2 + (e % H2)] : make_float2(0.0f, 0.0f);
     }
   }
 #pragma unroll 1
@@ -434,11 +472,11 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
     }
     __syncthreads();
     if (it + 1 < npass) {
-      const float2* Hn = A.H + (long)pair_of(it + 1) * A.pstride + r0 * H2;
+      const float2* Hn = A.H + (long)pair_of(it + 1) * A.pstride + r0 * P2;
 #pragma unroll
       for (int i = 0; i < PF; ++i) {
         const int e = tid + 256 * i;
-        pf[i] = (e < nvalid) ? Hn[e] : make_float2(0.0f, 0.0f);
+        pf[i] = (e < nvalid) ? Hn[(e / H2) * P2 + (e % H2)] : make_float2(0.0f, 0.0f);
       }
     }
     float2 z[R2], o[R2];
@@ -461,9 +499,10 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
         for (int j = 0; j < R2; ++j) {
           const double m1x = (double)wv[j].x * g.inv_vol, m1y = (double)wv[j].y * g.inv_vol;
           const double m2x = (double)o[j].x * g.inv_vol, m2y = (double)o[j].y * g.inv_vol;
-          const double vx = m2x - m1x * m1x / msum, vy = m2y - m1y * m1y / msum;
-          wv[j] = make_float2(vx > floor_v ? (float)(1.0 / sqrt(vx)) : 0.0f,
-                              vy > floor_v ? (float)(1.0 / sqrt(vy)) : 0.0f);
+          // the cancelling subtraction in float64, the reciprocal root in float32
+          const double vx = m2x - m1x * m1x * inv_msum, vy = m2y - m1y * m1y * inv_msum;
+          wv[j] = make_float2(vx > floor_v ? rsqrtf((float)vx) : 0.0f,
+                              vy > floor_v ? rsqrtf((float)vy) : 0.0f);
         }
       } else {
         const float mu = A.mu[pair];
@@ -541,7 +580,7 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
 
 static P3Geo make_p3geo(const Geo& g) {
   P3Geo q;
-  q.n0 = g.n0; q.n1 = g.n1; q.n2 = g.n2; q.h2 = g.h2;
+  q.n0 = g.n0; q.n1 = g.n1; q.n2 = g.n2; q.h2 = g.h2; q.p2 = g.p2;
   q.lo0 = g.c0; q.hi0 = g.n0 - g.L0 + g.c0;
   q.lo1 = g.c1; q.hi1 = g.n1 - g.L1 + g.c1;
   q.lo2 = g.c2; q.hi2 = g.n2 - g.L2 + g.c2;
@@ -624,7 +663,7 @@ __global__ void __launch_bounds__(256) k_field_at(P3Geo g, const float2* __restr
       continue;
     }
     const int y = ((x2 - g.c2) % g.n2 + g.n2) % g.n2;
-    const float2* row = H + (long)alpha * pstride + ((long)x0 * g.n1 + x1) * g.h2;
+    const float2* row = H + (long)alpha * pstride + ((long)x0 * g.n1 + x1) * g.p2;
     double acc = (double)row[0].x + ((y & 1) ? -(double)row[M].x : (double)row[M].x);
     double s2 = 0.0;
     int ph = y;

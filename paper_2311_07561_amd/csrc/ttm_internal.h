@@ -20,13 +20,17 @@ enum Pass3Mode { P3_SCORE = 0, P3_W = 1, P3_MAX = 2 };
 
 struct Geo {
   int n0, n1, n2;      // image extents
-  int h2;              // n2 / 2 + 1
+  int h2;              // n2 / 2 + 1 columns of a half spectrum
+  int p2;              // row pitch of a half spectrum: h2 rounded up to 16
+                       // complex (128 bytes), so that every 16-column tile
+                       // row is one aligned cache line
   int L0, L1, L2;      // template extents
   int c0, c1, c2;      // template centre (L / 2)
   long vol() const { return (long)n0 * n1 * n2; }
-  long half() const { return (long)n0 * n1 * h2; }     // complex elements of a half spectrum
-  long bank_slab() const { return (long)L0 * n1 * h2; } // complex elements per bank entry
+  long half() const { return (long)n0 * n1 * p2; }     // complex elements of a half spectrum
+  long bank_slab() const { return (long)L0 * n1 * p2; } // complex elements per bank entry
 };
+inline int row_pitch(int n2) { return ((n2 / 2 + 1) + 15) / 16 * 16; }
 
 // --- FFT passes (ttm_fft.hip) -------------------------------------------------
 // image moments: stats[0] = mean, stats[1] = population variance (float64)
@@ -39,13 +43,14 @@ hipError_t launch_mask_sum(const float* mask, long n, double* out, hipStream_t s
 // dst row of source row r: (r / grp) * grp_stride + r % grp (rows of h2).
 hipError_t launch_r2c_rows(int n2, const float* src, long src_stride, int len_valid, long nrows,
                            float2* dst0, float2* dst1, long grp, long grp_stride, int mode,
-                           const double* stats, hipStream_t s);
+                           const double* stats, hipStream_t s);   // rows of pitch row_pitch(n2)
 // strided pencil FFT along one axis, in place: pencil p has base
-// (p / Q) * S_outer + p % Q and element j at base + j * S_axis; only j < nin is
-// read (the rest is zero); output index j is written at (j + shift) mod N.
-// blockIdx.y walks nbatch arrays batch_stride apart.
-hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long Q, long S_outer,
-                          long S_axis, int nin, int shift, int nbatch, long batch_stride,
+// (p / Q) * S_outer + p % Q and element j at base + j * S_axis; pencils with
+// p % Q >= qvalid (row padding) are skipped; only j < nin is read (the rest is
+// zero); output index j is written at (j + shift) mod N.  blockIdx.y walks
+// nbatch arrays batch_stride apart.
+hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long Q, long qvalid,
+                          long S_outer, long S_axis, int nin, int shift, int nbatch, long batch_stride,
                           hipStream_t s);
 // first inverse pass, fused: forward axis-0 FFT of the image pencils in src,
 // then for each of nt template entries (bank layout [L0][n1][h2]): pruned

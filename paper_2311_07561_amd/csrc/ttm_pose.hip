@@ -52,6 +52,9 @@ __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F,
       v = F[((long)y0 * g.n1 + y1) * g.n2 + y2];
     tile[e] = v;
   }
+  __shared__ unsigned long long lkeys[PT0 * PT1 * PT2 / 8];   // strict maxima: at most one per 2x2x2 cell
+  __shared__ unsigned lcount, lbase;
+  if (tid == 0) lcount = 0u;
   __syncthreads();
   for (int e = tid; e < PT0 * PT1 * PT2; e += 256) {
     const int t2 = e % PT2, t1 = (e / PT2) % PT1, t0 = e / (PT1 * PT2);
@@ -73,9 +76,18 @@ __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F,
     if (!ok) continue;
     const long lin = ((long)x0 * g.n1 + x1) * g.n2 + x2;
     atomicAdd(&hist[__float_as_uint(v) >> 16], 1u);
-    const unsigned slot = atomicAdd(&ctrl[PK_TOTAL], 1u);
-    if ((long)slot < bigcap)
-      allc[slot] = peak_key(v, lin);
+    const unsigned ls = atomicAdd(&lcount, 1u);
+    lkeys[ls] = peak_key(v, lin);
+  }
+  __syncthreads();
+  const unsigned nl = lcount;
+  if (tid == 0 && nl > 0u) lbase = atomicAdd(&ctrl[PK_TOTAL], nl);
+  __syncthreads();
+  if (nl == 0u) return;
+  for (unsigned i = tid; i < nl; i += 256) {
+    const long slot = (long)lbase + i;
+    if (slot < bigcap)
+      allc[slot] = lkeys[i];
     else
       ctrl[PK_OVER] = 1u;
   }
@@ -471,14 +483,66 @@ constexpr int hidx(int i, int j) { return i * 4 - i * (i - 1) / 2 + (j - i); }  
 
 // Per-wave LDS tables of the eigen-solver: packed exponents and mu*A of the K
 // terms, and each lane's powers x_d^e stored lane-fastest (conflict free).
+constexpr int kPolishLanes = 4;
 struct EigLds {
   double muA[kMaxK];
-  int ex[kMaxK];                          // alpha_1..alpha_4 in 4 bytes
-  double pw[4 * (kMaxOrder + 1) * 64];    // [(d * 9 + e) * 64 + lane]
+  int ex[kMaxK];                                   // alpha_1..alpha_4 in 4 bytes
+  double pw[4 * (kMaxOrder + 1) * kPolishLanes];   // [(d * 9 + e) * 4 + lane], polishing lanes only
 };
 
 __device__ __forceinline__ double PW(const EigLds& t, int d, int e, int lane) {
-  return t.pw[(d * (kMaxOrder + 1) + e) * 64 + lane];
+  return t.pw[(d * (kMaxOrder + 1) + e) * kPolishLanes + lane];
+}
+
+// compile-time packed multi-indices, in the order of alpha_of_dev
+struct Alpha {
+  int a[4];
+};
+constexpr Alpha alpha_c(int n, int k) {
+  int idx = 0;
+  for (int a1 = n; a1 >= 0; --a1)
+    for (int a2 = n - a1; a2 >= 0; --a2)
+      for (int a3 = n - a1 - a2; a3 >= 0; --a3) {
+        if (idx == k) return Alpha{{a1, a2, a3, n - a1 - a2 - a3}};
+        ++idx;
+      }
+  return Alpha{{0, 0, 0, 0}};
+}
+
+// lambda(q) = sum_alpha muA_alpha q^alpha with compile-time exponents and the
+// powers of q in registers (the seed scan)
+template <int N>
+__device__ __forceinline__ double eval_lambda(const double* __restrict__ muA, const double* q) {
+  constexpr int K = (N + 1) * (N + 2) * (N + 3) / 6;
+  double pw[4][N + 1];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    pw[d][0] = 1.0;
+#pragma unroll
+    for (int e = 1; e <= N; ++e) pw[d][e] = pw[d][e - 1] * q[d];
+  }
+  double l = 0.0;
+  static_for<0, K>([&](auto kk) {
+    constexpr Alpha A = alpha_c(N, decltype(kk)::value);
+    l += muA[decltype(kk)::value] * (pw[0][A.a[0]] * pw[1][A.a[1]]) * (pw[2][A.a[2]] * pw[3][A.a[3]]);
+  });
+  return l;
+}
+
+// every lane scans a strided share of the seed table; returns the lane's best
+template <int N>
+__device__ __forceinline__ void seed_scan(const double* __restrict__ muA, const double* __restrict__ seeds,
+                                          int n_seeds, int lane, double& best, int& bseed) {
+  best = -INFINITY;
+  bseed = 0;
+  for (int sd = lane; sd < n_seeds; sd += 64) {
+    const double q[4] = {seeds[4 * sd], seeds[4 * sd + 1], seeds[4 * sd + 2], seeds[4 * sd + 3]};
+    const double v = eval_lambda<N>(muA, q);
+    if (v > best) {
+      best = v;
+      bseed = sd;
+    }
+  }
 }
 
 // lambda = sum_alpha muA_alpha x^alpha; with DERIV also g = A x^{n-1} and the
@@ -490,13 +554,14 @@ __device__ __forceinline__ void eval_terms(EigLds& t, int n, int K, const double
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
     double v = 1.0;
-    t.pw[(d * (kMaxOrder + 1)) * 64 + lane] = 1.0;
+    t.pw[(d * (kMaxOrder + 1)) * kPolishLanes + lane] = 1.0;
     for (int e = 1; e <= n; ++e) {
       v *= x[d];
-      t.pw[(d * (kMaxOrder + 1) + e) * 64 + lane] = v;
+      t.pw[(d * (kMaxOrder + 1) + e) * kPolishLanes + lane] = v;
     }
   }
   double l = 0.0, gg[4] = {0.0, 0.0, 0.0, 0.0}, hh[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
   for (int k = 0; k < K; ++k) {
     const int ex = t.ex[k];
     const int e[4] = {ex & 255, (ex >> 8) & 255, (ex >> 16) & 255, (ex >> 24) & 255};
@@ -553,12 +618,14 @@ __device__ __forceinline__ double fact_d(int n) {
 // steps on the sphere: a Newton step is taken when it is an ascent direction
 // and a backtracking search along it raises lambda, otherwise the shifted
 // power step; the wave keeps the best lambda.
-__global__ void __launch_bounds__(64) k_pose_eig(int n, const double* __restrict__ seeds,
+template <int N>
+__global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seeds,
                                                  const double* __restrict__ Cbuf,
                                                  const int* __restrict__ okbuf, const int* __restrict__ count_dev,
                                                  int count_host, int NB, int n_seeds, int max_iter, double tol,
                                                  float* __restrict__ qbuf, double* __restrict__ lambuf,
                                                  int* __restrict__ flagbuf) {
+  constexpr int n = N;
   __shared__ EigLds t;
   __shared__ double red[64 * 6];
   const int K = num_components_dev(n);
@@ -584,17 +651,9 @@ __global__ void __launch_bounds__(64) k_pose_eig(int n, const double* __restrict
   }
   __syncthreads();
   // seed scan: every lane keeps the best of its strided share
-  double best = -INFINITY;
-  int bseed = 0;
-  for (int sd = lane; sd < n_seeds; sd += 64) {
-    const double q[4] = {seeds[4 * sd], seeds[4 * sd + 1], seeds[4 * sd + 2], seeds[4 * sd + 3]};
-    double v;
-    eval_terms<false>(t, n, K, q, lane, v, nullptr, nullptr);
-    if (v > best) {
-      best = v;
-      bseed = sd;
-    }
-  }
+  double best;
+  int bseed;
+  seed_scan<N>(t.muA, seeds, n_seeds, lane, best, bseed);
   // the 4 best lane seeds that are mutually more than 10 degrees apart
   // (|<q, q'>| < cos 5 deg) start the polish
   red[lane * 6 + 0] = best;
@@ -834,8 +893,18 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
   const int K = num_components(order_n);
   const int NB = refine ? 27 : 1;
   hipLaunchKernelGGL(k_seed_table, dim3((n_seeds + 255) / 256), dim3(256), 0, s, n_seeds, ps.seeds);
-  hipLaunchKernelGGL(k_pose_eig, dim3((unsigned)(max_peaks * NB)), dim3(64), 0, s, order_n, ps.seeds, ps.C, ps.ok,
-                     count_dev, count_host, NB, n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags);
+  const dim3 eg((unsigned)(max_peaks * NB));
+  switch (order_n) {
+    case 2: hipLaunchKernelGGL(k_pose_eig<2>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                               n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags); break;
+    case 4: hipLaunchKernelGGL(k_pose_eig<4>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                               n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags); break;
+    case 6: hipLaunchKernelGGL(k_pose_eig<6>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                               n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags); break;
+    case 8: hipLaunchKernelGGL(k_pose_eig<8>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                               n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags); break;
+    default: return hipErrorInvalidValue;
+  }
   hipLaunchKernelGGL(k_pose_pick, dim3((max_peaks + 63) / 64), dim3(64), 0, s, g, score, K, pos_in, count_dev,
                      count_host, NB, ps.C, ps.w, ps.q, ps.lam, ps.flags, out_pos, out_quat, out_lambda,
                      out_score, out_flags, out_C);
