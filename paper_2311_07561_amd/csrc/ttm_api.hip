@@ -180,8 +180,8 @@ static ttm_status image_forward(const Geo& g, const float* image, float2* Xf, fl
   TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), partials, stats, stream));
   TTM_PROF(PC_STATS, launch_mask_sum(mask, L3, stats + 2, stream));
   TTM_PROF(PC_ROWS, launch_r2c_rows(g.n2, image, g.n2, g.n2, rows, Xf, Xg, rows, 0, 1, stats, stream));
-  TTM_PROF(PC_PEN_FWD, launch_pencils(g.n1, false, Xf, (long)g.n0 * g.p2, g.p2, g.h2, (long)g.n1 * g.p2, g.p2,
-                                      g.n1, 0, 2, (long)(Xg - Xf), stream));
+  TTM_PROF(PC_PEN_FWD, launch_pencils(g.n1, false, Xf, (long)g.n0 * g.p2, g.p2, (long)g.n1 * g.p2, g.p2, g.n1, 0,
+                                      0, g.n1 - 1, 2, (long)(Xg - Xf), stream));
   return TTM_OK;
 }
 
@@ -189,9 +189,18 @@ static ttm_status image_forward(const Geo& g, const float* image, float2* Xf, fl
 static ttm_status bank_forward(const Geo& g, const float* src, int nent, float2* bank, hipStream_t stream) {
   const long rows = (long)nent * g.L0 * g.L1;
   TTM_PROF(PC_ROWS, launch_r2c_rows(g.n2, src, g.L2, g.L2, rows, bank, nullptr, g.L1, g.n1, 0, nullptr, stream));
-  TTM_PROF(PC_PEN_FWD, launch_pencils(g.n1, false, bank, (long)nent * g.L0 * g.p2, g.p2, g.h2,
-                                      (long)g.n1 * g.p2, g.p2, g.L1, 0, 1, 0, stream));
+  TTM_PROF(PC_PEN_FWD, launch_pencils(g.n1, false, bank, (long)nent * g.L0 * g.p2, g.p2, (long)g.n1 * g.p2, g.p2,
+                                      g.L1, 0, 0, g.n1 - 1, 1, 0, stream));
   return TTM_OK;
+}
+
+// axis-1 inverse of nb arrays (half elements apart) after pass 1: only the
+// planes x0 of the valid region hold data, only rows x1 of the valid region
+// are stored (with the axis-1 centre shift)
+static hipError_t pencils_inverse_valid(const Geo& g, float2* H, int nb, long half, hipStream_t stream) {
+  const long plane = (long)g.n1 * g.p2;
+  return launch_pencils(g.n1, true, H + (long)g.lo0() * plane, (long)(g.hi0() - g.lo0() + 1) * g.p2, g.p2, plane,
+                        g.p2, g.n1, g.c1, g.lo1(), g.hi1(), nb, half, stream);
 }
 
 #define TTM_CALL(expr)                     \
@@ -307,8 +316,7 @@ static ttm_status correlate_into(const Geo& g, int order_n, int K, const float* 
   TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, bk, g.bank_slab(), K + 1, w.H, half, stream));
   TTM_PROF(PC_PASS1, launch_pass1(g, w.Xg, bk + (long)K * g.bank_slab(), g.bank_slab(), 1,
                                   w.H + (long)(K + 1) * half, half, stream));
-  TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.p2, g.p2, g.h2, (long)g.n1 * g.p2, g.p2, g.n1,
-                                      g.c1, K + 2, half, stream));
+  TTM_PROF(PC_PEN_INV, pencils_inverse_valid(g, w.H, K + 2, half, stream));
   Pass3Args a;
   std::memset(&a, 0, sizeof(a));
   a.H = w.H;
@@ -481,8 +489,7 @@ ttm_status tm_classical(const float* image, ttm_dims N, const float* tmpl, const
   TTM_CALL(bank_forward(g, mask, 1, w.bbank, stream));
   TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, w.bbank, g.bank_slab(), 1, w.H, half, stream));
   TTM_PROF(PC_PASS1, launch_pass1(g, w.Xg, w.bbank, g.bank_slab(), 1, w.H + half, half, stream));
-  TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.p2, g.p2, g.h2, (long)g.n1 * g.p2, g.p2, g.n1, g.c1, 2, half,
-                         stream));
+  TTM_PROF(PC_PEN_INV, pencils_inverse_valid(g, w.H, 2, half, stream));
   Pass3Args a;
   std::memset(&a, 0, sizeof(a));
   a.H = w.H;
@@ -500,8 +507,7 @@ ttm_status tm_classical(const float* image, ttm_dims N, const float* tmpl, const
     TTM_PROF(PC_BUILD, launch_rot_write(tmpl, mask, L.n0, L.n1, L.n2, w.quats, w.rstats, j0, nb, w.tbatch, stream));
     TTM_CALL(bank_forward(g, w.tbatch, nb, w.bbank, stream));
     TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, w.bbank, g.bank_slab(), nb, w.H, half, stream));
-    TTM_PROF(PC_PEN_INV, launch_pencils(g.n1, true, w.H, (long)g.n0 * g.p2, g.p2, g.h2, (long)g.n1 * g.p2, g.p2, g.n1, g.c1, nb,
-                           half, stream));
+    TTM_PROF(PC_PEN_INV, pencils_inverse_valid(g, w.H, nb, half, stream));
     Pass3Args m;
     std::memset(&m, 0, sizeof(m));
     m.H = w.H;

@@ -192,6 +192,15 @@ __device__ __forceinline__ void engineB(float2 (&o)[Plan<N>::R2], float2 (&y)[Pl
 }
 
 // number of packed components of S^n(R^4): C(n+3, 3)
+// Workgroups of a launch are dealt to the 8 XCDs round-robin (block b runs on
+// XCD b mod 8).  This maps block b to a tile index so that each XCD receives
+// one contiguous range of tiles: neighbouring tiles that share cache lines
+// then share one L2.  A bijection on [0, nb).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, rem = nb & 7, x = b & 7, slot = b >> 3;
+  return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + slot;
+}
+
 __device__ __forceinline__ int num_components_dev(int n) { return (n + 1) * (n + 2) * (n + 3) / 6; }
 
 // packed multi-index alpha of position k for order n (alpha1 from n down to

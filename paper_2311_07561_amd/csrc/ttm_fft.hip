@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(256) k_r2c_rows(const float* __restrict__ src,
                                                   const double* __restrict__ stats) {
   using C = RowCfg<M>;
   constexpr int R1 = C::R1, R2 = C::R2, RW = C::RW, SP = C::SP;
-  constexpr int N2 = 2 * M, H2 = M + 1, P2 = (H2 + 15) / 16 * 16;
+  constexpr int N2 = 2 * M, H2 = M + 1, P2 = row_pitch(N2);
   __shared__ float2 stage[RW * SP];
   __shared__ float2 twM[M];
   __shared__ float2 tw2[N2];
@@ -215,13 +215,12 @@ struct PenCfg {
   static constexpr int PW = 256 / R1;    // pencils per block
 };
 
-// One block transforms PW pencils.  Pencils in the row padding
-// (p % Q >= qvalid) are transformed too: the padding columns hold no data
-// and are never read as data, so this only saves branches.  Element offsets
-// are 32-bit from the block's array base (one array holds < 2^31 elements).
+// One block transforms PW pencils.  Element offsets are 32-bit from the
+// block's array base (one array holds < 2^31 elements).
 template <int N, bool INV, bool PRUNED>
 __global__ void __launch_bounds__(256) k_pencils(float2* __restrict__ data, int npencils, int Q, long S_outer,
-                                                 int S_axis, int nin, int shift, long batch_stride) {
+                                                 int S_axis, int nin, int shift, int slo, int shi,
+                                                 long batch_stride) {
   using C = PenCfg<N>;
   constexpr int R1 = C::R1, R2 = C::R2, PW = C::PW;
   __shared__ float2 lds[PW * N];
@@ -229,7 +228,7 @@ __global__ void __launch_bounds__(256) k_pencils(float2* __restrict__ data, int 
   const int tid = threadIdx.x;
   fill_twiddles(tw, N, tid, 256);
   const int pl = tid % PW, a = tid / PW;
-  const int p = blockIdx.x * PW + pl;
+  const int p = xcd_tile(blockIdx.x, gridDim.x) * PW + pl;
   const bool valid = p < npencils;
   float2* __restrict__ arr = data + (long)blockIdx.y * batch_stride;
   const unsigned toff = valid ? (unsigned)((long)(p / Q) * S_outer + (p % Q)) + (unsigned)(a * S_axis) : 0u;
@@ -250,46 +249,39 @@ __global__ void __launch_bounds__(256) k_pencils(float2* __restrict__ data, int 
 #pragma unroll
     for (int d = 0; d < R1; ++d) {
       const int j = (a + R1 * k) + R2 * d;
-      arr[base + (unsigned)(((j + shift) & (N - 1)) * S_axis)] = o[k * R1 + d];
+      const int x = (j + shift) & (N - 1);
+      if ((unsigned)(x - slo) <= (unsigned)(shi - slo)) arr[base + (unsigned)(x * S_axis)] = o[k * R1 + d];
     }
 }
 
 template <int N>
-static hipError_t pencils_n(bool inverse, float2* data, long npencils, long Q, long qvalid, long S_outer,
-                            long S_axis, int nin, int shift, int nbatch, long batch_stride,
-                            hipStream_t s) {
-  (void)qvalid;
+static hipError_t pencils_n(bool inverse, float2* data, long npencils, long Q, long S_outer, long S_axis, int nin,
+                            int shift, int slo, int shi, int nbatch, long batch_stride, hipStream_t s) {
   constexpr int PW = PenCfg<N>::PW;
+  if (npencils <= 0 || nbatch <= 0) return hipSuccess;
   dim3 grid((unsigned)((npencils + PW - 1) / PW), (unsigned)nbatch);
   const bool pruned = nin < N;
+#define TTM_PENCILS(I, PR)                                                                                  \
+  hipLaunchKernelGGL((k_pencils<N, I, PR>), grid, dim3(256), 0, s, data, (int)npencils, (int)Q, S_outer, \
+                     (int)S_axis, nin, shift, slo, shi, batch_stride)
   if (inverse) {
-    if (pruned)
-      hipLaunchKernelGGL((k_pencils<N, true, true>), grid, dim3(256), 0, s, data, (int)npencils, (int)Q, S_outer,
-                         (int)S_axis, nin, shift, batch_stride);
-    else
-      hipLaunchKernelGGL((k_pencils<N, true, false>), grid, dim3(256), 0, s, data, (int)npencils, (int)Q, S_outer,
-                         (int)S_axis, nin, shift, batch_stride);
+    if (pruned) TTM_PENCILS(true, true);
+    else TTM_PENCILS(true, false);
   } else {
-    if (pruned)
-      hipLaunchKernelGGL((k_pencils<N, false, true>), grid, dim3(256), 0, s, data, (int)npencils, (int)Q, S_outer,
-                         (int)S_axis, nin, shift, batch_stride);
-    else
-      hipLaunchKernelGGL((k_pencils<N, false, false>), grid, dim3(256), 0, s, data, (int)npencils, (int)Q, S_outer,
-                         (int)S_axis, nin, shift, batch_stride);
+    if (pruned) TTM_PENCILS(false, true);
+    else TTM_PENCILS(false, false);
   }
+#undef TTM_PENCILS
   return hipGetLastError();
 }
 
-hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long Q, long qvalid,
-                          long S_outer, long S_axis, int nin, int shift, int nbatch, long batch_stride,
-                          hipStream_t s) {
+hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long Q, long S_outer, long S_axis,
+                          int nin, int shift, int slo, int shi, int nbatch, long batch_stride, hipStream_t s) {
   switch (N) {
-    case 16: return pencils_n<16>(inverse, data, npencils, Q, qvalid, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
-    case 32: return pencils_n<32>(inverse, data, npencils, Q, qvalid, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
-    case 64: return pencils_n<64>(inverse, data, npencils, Q, qvalid, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
-    case 128: return pencils_n<128>(inverse, data, npencils, Q, qvalid, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
-    case 256: return pencils_n<256>(inverse, data, npencils, Q, qvalid, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
-    case 512: return pencils_n<512>(inverse, data, npencils, Q, qvalid, S_outer, S_axis, nin, shift, nbatch, batch_stride, s);
+#define TTM_CASE(n) \
+  case n: return pencils_n<n>(inverse, data, npencils, Q, S_outer, S_axis, nin, shift, slo, shi, nbatch, batch_stride, s)
+    TTM_CASE(16); TTM_CASE(32); TTM_CASE(64); TTM_CASE(128); TTM_CASE(256); TTM_CASE(512);
+#undef TTM_CASE
     default: return hipErrorInvalidValue;
   }
 }
@@ -300,7 +292,8 @@ hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long
 template <int N0>
 __global__ void __launch_bounds__(256) k_pass1(const float2* __restrict__ src, long P, int p2, int h2, int L0,
                                                const float2* __restrict__ tmpl, long tmpl_stride, int nt,
-                                               float2* __restrict__ out, long out_stride, int shift0) {
+                                               float2* __restrict__ out, long out_stride, int shift0, int lo0,
+                                               int hi0) {
   using C = PenCfg<N0>;
   constexpr int R1 = C::R1, R2 = C::R2, PW = C::PW;
   __shared__ float2 lds[PW * N0];
@@ -308,9 +301,8 @@ __global__ void __launch_bounds__(256) k_pass1(const float2* __restrict__ src, l
   const int tid = threadIdx.x;
   fill_twiddles(tw, N0, tid, 256);
   const int pl = tid % PW, a = tid / PW;
-  const int p = blockIdx.x * PW + pl;
-  // pencils in the row padding (column >= h2) carry no data: they are
-  // transformed as zeros and not stored
+  const int p = xcd_tile(blockIdx.x, gridDim.x) * PW + pl;
+  // pencils past the last tile's end are transformed as zeros and not stored
   const bool valid = p < P && (p % p2) < h2;
   const unsigned pu = valid ? (unsigned)p : 0u;
   const unsigned P32 = (unsigned)P;
@@ -348,8 +340,8 @@ __global__ void __launch_bounds__(256) k_pass1(const float2* __restrict__ src, l
       float2* __restrict__ ob = out + (long)i * out_stride;
 #pragma unroll
       for (int g = 0; g < R2; ++g) {
-        const unsigned j = (unsigned)((a + R1 * g + shift0) & (N0 - 1));
-        ob[j * P32 + pu] = y[g];
+        const int j = (a + R1 * g + shift0) & (N0 - 1);
+        if ((unsigned)(j - lo0) <= (unsigned)(hi0 - lo0)) ob[(unsigned)j * P32 + pu] = y[g];
       }
     }
   }
@@ -362,7 +354,7 @@ static hipError_t pass1_n(const Geo& g, const float2* src, const float2* tmpl, l
   const long P = (long)g.n1 * g.p2;
   dim3 grid((unsigned)((P + PW - 1) / PW));
   hipLaunchKernelGGL((k_pass1<N0>), grid, dim3(256), 0, s, src, P, g.p2, g.h2, g.L0, tmpl, tmpl_stride, nt, out,
-                     out_stride, g.c0);
+                     out_stride, g.c0, g.lo0(), g.hi0());
   return hipGetLastError();
 }
 
@@ -388,7 +380,12 @@ struct P3Geo {
   int n0, n1, n2, h2, p2;
   int lo0, hi0, lo1, hi1, lo2, hi2;   // valid region, inclusive bounds
   int c2;
+  int l1;                             // log2(n1)
   double inv_vol;
+  __device__ bool row_valid(long r) const {
+    const int x0 = (int)(r >> l1), x1 = (int)(r & (n1 - 1));
+    return (unsigned)(x0 - lo0) <= (unsigned)(hi0 - lo0) && (unsigned)(x1 - lo1) <= (unsigned)(hi1 - lo1);
+  }
 };
 
 template <int M, int MODE>
@@ -407,6 +404,7 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
   const long r0 = (long)blockIdx.x * RW;
   const int p = tid % RW, a = tid / RW;
   const long myrow = r0 + p;
+  const bool myrow_ok = myrow < nrows && g.row_valid(myrow);
 
   // per-thread element values: e[k*R1+d] holds (x(2n), x(2n+1)), n = (a + R1 k) + R2 d
   float2 wv[R2];     // w (P3_SCORE) or running best (P3_MAX)
@@ -431,7 +429,7 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
       for (int d = 0; d < R1; ++d) {
         const int n = (a + R1 * k) + R2 * d;
         const int j = k * R1 + d;
-        if (A.init || myrow >= nrows) {
+        if (A.init || !myrow_ok) {
           wv[j] = make_float2(-INFINITY, -INFINITY);
           bidx[j] = make_int2(0, 0);
         } else {
@@ -443,6 +441,22 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
       }
   }
 
+  // a tile with no row in the valid region reads nothing: its outputs are zero
+  if (!__syncthreads_or(tid < RW && r0 + tid < nrows && g.row_valid(r0 + tid))) {
+    if (MODE == P3_MAX) return;
+    for (int e = tid; e < RW * N2; e += 256) {
+      const long r = r0 + e / N2;
+      if (r >= nrows) continue;
+      if (MODE == P3_SCORE) {
+        A.out_score[r * g.n2 + e % N2] = 0.0f;
+        if (A.out_w) A.out_w[r * g.n2 + e % N2] = 0.0f;
+      } else {
+        A.out_w[r * g.n2 + e % N2] = 0.0f;
+      }
+    }
+    return;
+  }
+
   const int npass = MODE == P3_SCORE ? A.npairs + 2 : (MODE == P3_W ? 2 : A.npairs);
   // pair order: P3_SCORE does M1 (index npairs), M2 (npairs+1), then components
   auto pair_of = [&](int it) { return MODE == P3_SCORE ? (it < 2 ? A.npairs + it : it - 2) : it; };
@@ -450,15 +464,22 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
   // while the current pair is transformed (each thread owns a fixed slice of
   // the block's contiguous RW x H2 tile)
   constexpr int PF = (RW * H2 + 255) / 256;
-  constexpr int P2 = (H2 + 15) / 16 * 16;       // row pitch of the arrays
+  constexpr int P2 = row_pitch(N2);             // row pitch of the arrays
   const long nvalid = (nrows - r0 < RW ? nrows - r0 : RW) * (long)H2;
+  // rows outside the valid region are not read (transformed as zeros)
+  bool ld_ok[PF];
+#pragma unroll
+  for (int i = 0; i < PF; ++i) {
+    const int e = tid + 256 * i;
+    ld_ok[i] = e < nvalid && g.row_valid(r0 + e / H2);
+  }
   float2 pf[PF];
   {
     const float2* Hn = A.H + (long)pair_of(0) * A.pstride + r0 * P2;
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int e = tid + 256 * i;
-      pf[i] = (e < nvalid) ? Hn[(e / H2) * P2 + (e % H2)] : make_float2(0.0f, 0.0f);
+      pf[i] = ld_ok[i] ? Hn[(e / H2) * P2 + (e % H2)] : make_float2(0.0f, 0.0f);
     }
   }
 #pragma unroll 1
@@ -476,7 +497,7 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
 #pragma unroll
       for (int i = 0; i < PF; ++i) {
         const int e = tid + 256 * i;
-        pf[i] = (e < nvalid) ? Hn[(e / H2) * P2 + (e % H2)] : make_float2(0.0f, 0.0f);
+        pf[i] = ld_ok[i] ? Hn[(e / H2) * P2 + (e % H2)] : make_float2(0.0f, 0.0f);
       }
     }
     float2 z[R2], o[R2];
@@ -523,7 +544,7 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
   }
 
   if (MODE == P3_MAX) {
-    if (myrow < nrows) {
+    if (myrow_ok) {
 #pragma unroll
       for (int k = 0; k < R2 / R1; ++k)
 #pragma unroll
@@ -585,6 +606,8 @@ static P3Geo make_p3geo(const Geo& g) {
   q.lo1 = g.c1; q.hi1 = g.n1 - g.L1 + g.c1;
   q.lo2 = g.c2; q.hi2 = g.n2 - g.L2 + g.c2;
   q.c2 = g.c2;
+  q.l1 = 0;
+  while ((1 << q.l1) < g.n1) ++q.l1;
   q.inv_vol = 1.0 / (double)g.vol();
   return q;
 }

@@ -21,16 +21,23 @@ enum Pass3Mode { P3_SCORE = 0, P3_W = 1, P3_MAX = 2 };
 struct Geo {
   int n0, n1, n2;      // image extents
   int h2;              // n2 / 2 + 1 columns of a half spectrum
-  int p2;              // row pitch of a half spectrum: h2 rounded up to 16
-                       // complex (128 bytes), so that every 16-column tile
-                       // row is one aligned cache line
+  int p2;              // row pitch of a half spectrum (= h2, unpadded: a
+                       // plane of n1 rows is a whole number of 128-byte
+                       // lines, so axis-0 tiles of 16 pencils are aligned;
+                       // axis-1 tiles straddle lines shared with the next
+                       // tile, which the XCD-aware tile order keeps in one L2)
   int L0, L1, L2;      // template extents
   int c0, c1, c2;      // template centre (L / 2)
   long vol() const { return (long)n0 * n1 * n2; }
   long half() const { return (long)n0 * n1 * p2; }     // complex elements of a half spectrum
   long bank_slab() const { return (long)L0 * n1 * p2; } // complex elements per bank entry
+  // valid region (window inside the image), inclusive bounds per axis
+  int lo0() const { return c0; }
+  int hi0() const { return n0 - L0 + c0; }
+  int lo1() const { return c1; }
+  int hi1() const { return n1 - L1 + c1; }
 };
-inline int row_pitch(int n2) { return ((n2 / 2 + 1) + 15) / 16 * 16; }
+__host__ __device__ constexpr int row_pitch(int n2) { return n2 / 2 + 1; }
 
 // --- FFT passes (ttm_fft.hip) -------------------------------------------------
 // image moments: stats[0] = mean, stats[1] = population variance (float64)
@@ -45,20 +52,23 @@ hipError_t launch_r2c_rows(int n2, const float* src, long src_stride, int len_va
                            float2* dst0, float2* dst1, long grp, long grp_stride, int mode,
                            const double* stats, hipStream_t s);   // rows of pitch row_pitch(n2)
 // strided pencil FFT along one axis, in place: pencil p has base
-// (p / Q) * S_outer + p % Q and element j at base + j * S_axis; pencils with
-// p % Q >= qvalid (row padding) are skipped; only j < nin is read (the rest is
-// zero); output index j is written at (j + shift) mod N.  blockIdx.y walks
-// nbatch arrays batch_stride apart.
-hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long Q, long qvalid,
-                          long S_outer, long S_axis, int nin, int shift, int nbatch, long batch_stride,
-                          hipStream_t s);
+// (p / Q) * S_outer + p % Q and element j at base + j * S_axis; only j < nin
+// is read (the rest is zero); output index j goes to position
+// x = (j + shift) mod N, and is stored only if slo <= x <= shi.  Pencils in
+// the row padding are transformed too (they hold no data and are never read
+// as data).  blockIdx.y walks nbatch arrays batch_stride apart.
+hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long Q, long S_outer, long S_axis,
+                          int nin, int shift, int slo, int shi, int nbatch, long batch_stride, hipStream_t s);
 // first inverse pass, fused: forward axis-0 FFT of the image pencils in src,
-// then for each of nt template entries (bank layout [L0][n1][h2]): pruned
+// then for each of nt template entries (bank layout [L0][n1][p2]): pruned
 // forward axis-0 FFT, product with conj, inverse axis-0 FFT, store into
-// out + i * out_stride with the centre shift.
+// out + i * out_stride with the centre shift; only the planes x0 of the
+// valid region are stored.
 hipError_t launch_pass1(const Geo& g, const float2* src, const float2* tmpl, long tmpl_stride,
                         int nt, float2* out, long out_stride, hipStream_t s);
-// last inverse pass (axis-2 C2R) fused with the per-voxel reduction.
+// last inverse pass (axis-2 C2R) fused with the per-voxel reduction.  Only
+// rows (x0, x1) of the valid region are read; outputs outside it are zero
+// (P3_SCORE, P3_W) or left untouched (P3_MAX).
 struct Pass3Args {
   const float2* H;     // pair arrays [n0][n1][h2]
   long pstride;        // complex elements between pair arrays

@@ -37,8 +37,8 @@ def test_host_only_functions():
 def test_sizes():
     L = ttm.lib()
     N, T = ttm.Dims(256, 256, 256), ttm.Dims(32, 32, 32)
-    assert L.ttm_bank_bytes(N, T, 35) == 36 * 32 * 256 * 144 * 8
-    half = 256 * 256 * 144 * 8
+    assert L.ttm_bank_bytes(N, T, 35) == 36 * 32 * 256 * 129 * 8
+    half = 256 * 256 * 129 * 8
     ws = L.ttm_correlate_workspace_bytes(N, T, 35)
     assert ws >= (2 + 37) * half and ws < (2 + 37) * half + (1 << 20)
     assert L.ttm_correlate_workspace_bytes(ttm.Dims(0, 1, 1), T, 35) == 0
