@@ -481,18 +481,12 @@ __global__ void __launch_bounds__(256) k_pose_tensor(PoseGeo g, const float* __r
 
 constexpr int hidx(int i, int j) { return i * 4 - i * (i - 1) / 2 + (j - i); }   // upper triangle, i <= j
 
-// Per-wave LDS tables of the eigen-solver: packed exponents and mu*A of the K
-// terms, and each lane's powers x_d^e stored lane-fastest (conflict free).
-constexpr int kPolishLanes = 4;
+// Per-wave LDS tables of the eigen-solver: the packed tensor entries C and
+// mu * C (mu the multiplicities).
 struct EigLds {
+  double C[kMaxK];
   double muA[kMaxK];
-  int ex[kMaxK];                                   // alpha_1..alpha_4 in 4 bytes
-  double pw[4 * (kMaxOrder + 1) * kPolishLanes];   // [(d * 9 + e) * 4 + lane], polishing lanes only
 };
-
-__device__ __forceinline__ double PW(const EigLds& t, int d, int e, int lane) {
-  return t.pw[(d * (kMaxOrder + 1) + e) * kPolishLanes + lane];
-}
 
 // compile-time packed multi-indices, in the order of alpha_of_dev
 struct Alpha {
@@ -508,6 +502,28 @@ constexpr Alpha alpha_c(int n, int k) {
       }
   return Alpha{{0, 0, 0, 0}};
 }
+// packed index of the multi-index (a1, a2, a3, n - a1 - a2 - a3)
+constexpr int alpha_pos(int n, int a1, int a2, int a3) {
+  int idx = 0;
+  for (int b1 = n; b1 >= 0; --b1)
+    for (int b2 = n - b1; b2 >= 0; --b2)
+      for (int b3 = n - b1 - b2; b3 >= 0; --b3) {
+        if (b1 == a1 && b2 == a2 && b3 == a3) return idx;
+        ++idx;
+      }
+  return -1;
+}
+constexpr double fact_c(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+// multinomial multiplicity n! / (a1! a2! a3! a4!)
+constexpr double mult_c(int n, Alpha a) {
+  return fact_c(n) / (fact_c(a.a[0]) * fact_c(a.a[1]) * fact_c(a.a[2]) * fact_c(a.a[3]));
+}
+constexpr int pair_i(int k) { return k < 4 ? 0 : k < 7 ? 1 : k < 9 ? 2 : 3; }
+constexpr int pair_j(int k) { return k < 4 ? k : k < 7 ? k - 3 : k < 9 ? k - 5 : 3; }
 
 // lambda(q) = sum_alpha muA_alpha q^alpha with compile-time exponents and the
 // powers of q in registers (the seed scan)
@@ -545,64 +561,60 @@ __device__ __forceinline__ void seed_scan(const double* __restrict__ muA, const 
   }
 }
 
-// lambda = sum_alpha muA_alpha x^alpha; with DERIV also g = A x^{n-1} and the
-// upper triangle H of A x^{n-2}, from the products of all-but-one and
-// all-but-two factors of each monomial.
-template <bool DERIV>
-__device__ __forceinline__ void eval_terms(EigLds& t, int n, int K, const double* x, int lane, double& lam,
-                                           double* g, double* H) {
+// H = A x^{n-2} (upper triangle), g = A x^{n-1} = H x and lambda = A x^n = x . g
+// for the symmetric tensor with packed entries C: (A x^{n-2})_ij is the sum over
+// the multi-indices b of degree n - 2 of mult(b) C[b + e_i + e_j] x^b.  The
+// weighted monomials mult(b) x^b are formed first; then each entry C[c] is
+// read once and added into every H_ij with c - e_i - e_j >= 0.  Every index is
+// a compile-time constant, so all lanes run one instruction stream.
+template <int N>
+__device__ __forceinline__ void eval_H(const double* __restrict__ C, const double* x, double& lam, double* g,
+                                       double* H) {
+  constexpr int NM = N - 2;
+  constexpr int KB = (NM + 1) * (NM + 2) * (NM + 3) / 6;
+  constexpr int K = (N + 1) * (N + 2) * (N + 3) / 6;
+  double pw[4][NM + 1];
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
-    double v = 1.0;
-    t.pw[(d * (kMaxOrder + 1)) * kPolishLanes + lane] = 1.0;
-    for (int e = 1; e <= n; ++e) {
-      v *= x[d];
-      t.pw[(d * (kMaxOrder + 1) + e) * kPolishLanes + lane] = v;
-    }
+    pw[d][0] = 1.0;
+#pragma unroll
+    for (int e = 1; e <= NM; ++e) pw[d][e] = pw[d][e - 1] * x[d];
   }
-  double l = 0.0, gg[4] = {0.0, 0.0, 0.0, 0.0}, hh[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-  for (int k = 0; k < K; ++k) {
-    const int ex = t.ex[k];
-    const int e[4] = {ex & 255, (ex >> 8) & 255, (ex >> 16) & 255, (ex >> 24) & 255};
-    const double c = t.muA[k];
-    double p[4];
+  double m[KB];
+  static_for<0, KB>([&](auto bb) {
+    constexpr Alpha B = alpha_c(NM, decltype(bb)::value);
+    constexpr double mb = mult_c(NM, B);
+    m[decltype(bb)::value] = mb * (pw[0][B.a[0]] * pw[1][B.a[1]]) * (pw[2][B.a[2]] * pw[3][B.a[3]]);
+  });
+  double h[10];
 #pragma unroll
-    for (int d = 0; d < 4; ++d) p[d] = PW(t, d, e[d], lane);
-    l += c * p[0] * p[1] * p[2] * p[3];
-    if (DERIV) {
-      double pm[4], pmm[4];
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        pm[d] = e[d] >= 1 ? PW(t, d, e[d] - 1, lane) : 0.0;
-        pmm[d] = e[d] >= 2 ? PW(t, d, e[d] - 2, lane) : 0.0;
+  for (int k = 0; k < 10; ++k) h[k] = 0.0;
+  // the entries are re-read from LDS on every call rather than held in
+  // registers across the solver's iterations
+  asm volatile("" ::: "memory");
+  static_for<0, K>([&](auto cc) {
+    constexpr Alpha G = alpha_c(N, decltype(cc)::value);
+    const double c = C[decltype(cc)::value];
+    static_for<0, 10>([&](auto kk) {
+      constexpr int i = pair_i(decltype(kk)::value), j = pair_j(decltype(kk)::value);
+      constexpr int b0 = G.a[0] - (i == 0) - (j == 0), b1 = G.a[1] - (i == 1) - (j == 1);
+      constexpr int b2 = G.a[2] - (i == 2) - (j == 2), b3 = G.a[3] - (i == 3) - (j == 3);
+      if constexpr (b0 >= 0 && b1 >= 0 && b2 >= 0 && b3 >= 0) {
+        constexpr int bi = alpha_pos(NM, b0, b1, b2);
+        h[decltype(kk)::value] += c * m[bi];
       }
+    });
+  });
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        double rest = 1.0;
+  for (int k = 0; k < 10; ++k) H[k] = h[k];
+  lam = 0.0;
 #pragma unroll
-        for (int d = 0; d < 4; ++d)
-          if (d != i) rest *= p[d];
-        gg[i] += c * e[i] * pm[i] * rest;
-        hh[hidx(i, i)] += c * e[i] * (e[i] - 1) * pmm[i] * rest;
+  for (int i = 0; i < 4; ++i) {
+    double gi = 0.0;
 #pragma unroll
-        for (int j = i + 1; j < 4; ++j) {
-          double r2 = 1.0;
-#pragma unroll
-          for (int d = 0; d < 4; ++d)
-            if (d != i && d != j) r2 *= p[d];
-          hh[hidx(i, j)] += c * e[i] * e[j] * pm[i] * pm[j] * r2;
-        }
-      }
-    }
-  }
-  lam = l;
-  if (DERIV) {
-    const double in = 1.0 / n, inn = 1.0 / (n * (n - 1));
-#pragma unroll
-    for (int i = 0; i < 4; ++i) g[i] = gg[i] * in;
-#pragma unroll
-    for (int i = 0; i < 10; ++i) H[i] = hh[i] * inn;
+    for (int j = 0; j < 4; ++j) gi += h[i <= j ? hidx(i, j) : hidx(j, i)] * x[j];
+    g[i] = gi;
+    lam += x[i] * gi;
   }
 }
 
@@ -613,11 +625,12 @@ __device__ __forceinline__ double fact_d(int n) {
 }
 
 // Dominant Z-eigenpair of one packed tensor per wavefront: every lane scans a
-// strided share of the S^3 seed points; the 4 best mutually distant lane seeds
+// strided share of the S^3 seed points; the kStarts best mutually distant lane seeds
 // are polished by SS-HOPM (shifted power iteration) accelerated with Newton
 // steps on the sphere: a Newton step is taken when it is an ascent direction
 // and a backtracking search along it raises lambda, otherwise the shifted
 // power step; the wave keeps the best lambda.
+constexpr int kStarts = 8;
 template <int N>
 __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seeds,
                                                  const double* __restrict__ Cbuf,
@@ -646,27 +659,28 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
     alpha_of_dev(n, k, al);
     double mu = fact_d(n);
     for (int d = 0; d < 4; ++d) mu /= fact_d(al[d]);
-    t.muA[k] = mu * Cbuf[(long)b * K + k];
-    t.ex[k] = al[0] | (al[1] << 8) | (al[2] << 16) | (al[3] << 24);
+    const double c = Cbuf[(long)b * K + k];
+    t.C[k] = c;
+    t.muA[k] = mu * c;
   }
   __syncthreads();
   // seed scan: every lane keeps the best of its strided share
   double best;
   int bseed;
   seed_scan<N>(t.muA, seeds, n_seeds, lane, best, bseed);
-  // the 4 best lane seeds that are mutually more than 10 degrees apart
+  // the kStarts best lane seeds that are mutually more than 10 degrees apart
   // (|<q, q'>| < cos 5 deg) start the polish
   red[lane * 6 + 0] = best;
   red[lane * 6 + 1] = (double)bseed;
   __syncthreads();
-  __shared__ int starts[4];
+  __shared__ int starts[kStarts];
   __shared__ int nstart;
-  __shared__ double sel[4][4];
+  __shared__ double sel[kStarts][4];
   if (lane == 0) {
     const double cosx = 0.99619469809174553;
     unsigned long long used = 0ull;
     int ns = 0;
-    while (ns < 4) {
+    while (ns < kStarts) {
       int bl = -1;
       for (int l = 0; l < 64; ++l)
         if (!((used >> l) & 1ull) && (bl < 0 || red[l * 6] > red[bl * 6])) bl = l;
@@ -695,7 +709,7 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
   if (lane < nstart) {
     for (int d = 0; d < 4; ++d) x[d] = seeds[4 * starts[lane] + d];
     double gv[4], Hm[10];
-    eval_terms<true>(t, n, K, x, lane, lam, gv, Hm);
+    eval_H<N>(t.C, x, lam, gv, Hm);
     const double nn1 = (double)(n * (n - 1));
     for (int it = 1; it <= lane_iters; ++it) {
       double M[4][4];
@@ -748,7 +762,7 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
           ny = 1.0 / sqrt(ny);
 #pragma unroll
           for (int i = 0; i < 4; ++i) y[i] *= ny;
-          eval_terms<true>(t, n, K, y, lane, lam_new, gv2, Hm2);
+          eval_H<N>(t.C, y, lam_new, gv2, Hm2);
           if (lam_new >= lam) {
             moved = true;
             break;
@@ -778,7 +792,7 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
         ny = 1.0 / sqrt(ny);
 #pragma unroll
         for (int i = 0; i < 4; ++i) y[i] *= ny;
-        eval_terms<true>(t, n, K, y, lane, lam_new, gv2, Hm2);
+        eval_H<N>(t.C, y, lam_new, gv2, Hm2);
       }
       const double dl = fabs(lam_new - lam);
 #pragma unroll
