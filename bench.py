@@ -16,6 +16,7 @@ Prints one JSON line on stdout (progress goes to stderr).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +29,42 @@ sys.path.insert(0, ROOT)
 
 METRIC = "TTM tomogram voxels/s & HBM GB/s vs classical TM@10k rotations, same pose accuracy"
 HBM_PEAK_GBPS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2311_07561_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def source_digest():
+    """Digest of the HIP sources: counter summaries taken from other sources
+    do not describe the kernels that run now."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel_class, workload):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary of this workload (each counter scaled by
+    its reading for a plain copy of known size), or None when there is no
+    summary or the sources changed since it was taken."""
+    path = os.path.join(PROFILES, f"{kernel_class}__{workload}__pmc.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -52,25 +89,31 @@ def parse():
     return p.parse_args()
 
 
-def class_bytes(n0, n1, n2, L0, K):
-    """Algorithmic HBM bytes per step of each kernel class of ttm_correlate,
-    from the units U_c (a half spectrum, complex64: 8 n0 n1 (n2/2+1) bytes),
-    U_r (a real float32 field: 4 n0 n1 n2 bytes) and B_e (one bank entry:
-    8 L0 n1 (n2/2+1) bytes)."""
+def class_bytes(n0, n1, n2, L0, L1, K):
+    """Algorithmic HBM bytes per step of each kernel class of ttm_match, from
+    the units U_c (a half spectrum, complex64: 8 n0 n1 (n2/2+1) bytes), U_r (a
+    real float32 field: 4 n0 n1 n2 bytes) and B_e (one bank entry: 8 L0 n1
+    (n2/2+1) bytes).  Only outputs in the valid region (the window inside the
+    image: v0 = n0 - L0 + 1 planes along axis 0, v1 = n1 - L1 + 1 rows along
+    axis 1) are carried through the inverse passes, so those passes move the
+    fractions r0 = v0 / n0 and r01 = v0 v1 / (n0 n1) of each array."""
     h2 = n2 // 2 + 1
     Uc = 8.0 * n0 * n1 * h2
     Ur = 4.0 * n0 * n1 * n2
     Be = 8.0 * L0 * n1 * h2
+    r0 = (n0 - L0 + 1) / n0
+    r01 = r0 * (n1 - L1 + 1) / n1
+    E = K + 2                                             # K components, mask vs f, mask vs f^2
     return {
-        "image_moments": 2 * Ur,                          # f read by correlate and by recover_pose
+        "image_moments": 2 * Ur,                          # f read twice (mean, then variance)
         "r2c_rows": Ur + 2 * Uc,                          # read f; write F2(f), F2(f^2)
         "pencils_fwd": 2 * 2 * Uc,                        # two arrays, read + write
-        "pass1_fanout": 2 * Uc + (K + 2) * Be + (K + 2) * Uc,   # F1(f), F1(f^2); K+2 bank reads; K+2 outputs
-        "pencils_inv": 2 * (K + 2) * Uc,                  # K+2 arrays, read + write
-        "pass3_c2r_reduce": (K + 2) * Uc + 2 * Ur,        # read K+2 arrays; write F and w
-        "peaks": 2 * Ur,                                  # two scans of F
+        "pass1_fanout": 2 * Uc + E * Be + E * r0 * Uc,    # F1(f), F1(f^2); E bank reads; E outputs
+        "pencils_inv": E * r0 * Uc + E * r01 * Uc,        # E arrays: read v0 planes, write v0 x v1 rows
+        "pass3_c2r_reduce": E * r01 * Uc + 2 * Ur,        # read v0 x v1 rows of E arrays; write F and w
+        "peaks": Ur,                                      # one scan of F
         "pose": 0.0,
-        "units": {"U_c": Uc, "U_r": Ur, "B_e": Be},
+        "units": {"U_c": Uc, "U_r": Ur, "B_e": Be, "r0": r0, "r01": r01, "arrays": E},
     }
 
 
@@ -193,7 +236,7 @@ def main():
     K = main_run["components"]
 
     # per-kernel roofline from the live event pairs of the timed steps
-    cb = class_bytes(N[0], N[1], N[2], L[0], K)
+    cb = class_bytes(N[0], N[1], N[2], L[0], L[1], K)
     kernels = {}
     for name, (ms, cnt) in main_run["_prof"].items():
         if cnt == 0:
@@ -208,7 +251,8 @@ def main():
     dom = max(fft_classes, key=lambda k: kernels[k]["ms_per_step"])
     achieved = kernels[dom]["model_GBps"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": counter_traffic(dom, wl.name),
+                "bytes_per_launch": kernels[dom]["model_bytes_per_step"] / kernels[dom]["launches_per_step"],
                 "bytes_per_step": kernels[dom]["model_bytes_per_step"],
                 "avg_launch_ms": kernels[dom]["avg_launch_ms"],
                 "launches_per_step": kernels[dom]["launches_per_step"]}

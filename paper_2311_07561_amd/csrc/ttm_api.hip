@@ -119,7 +119,7 @@ static CorrWs corr_layout(Carve& c, const Geo& g, int K) {
   w.Xg = c.take<float2>(g.half());
   w.H = c.take<float2>(g.half() * (size_t)(K + 2));
   w.stats = c.take<double>(4);
-  w.partials = c.take<double>(2 * 512);
+  w.partials = c.take<double>(3 * kStatPartials);
   w.mu = c.take<float>(kMaxK);
   return w;
 }
@@ -138,7 +138,7 @@ static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refi
   w.seeds = c.take<double>((size_t)n_seeds * 4);
   w.ps.seeds = w.seeds;
   w.stats = c.take<double>(4);
-  w.partials = c.take<double>(2 * 512);
+  w.partials = c.take<double>(3 * kStatPartials);
   w.cand_pos = c.take<int>((size_t)max_peaks * 3);
   w.ps.C = c.take<double>(nb * (size_t)K);
   w.ps.w = c.take<double>(nb);
@@ -168,7 +168,7 @@ static ClassWs class_layout(Carve& c, const Geo& g, int nrot) {
   w.bbank = c.take<float2>(g.bank_slab() * (size_t)(B > 1 ? B : 1));
   w.w = c.take<float>(g.vol());
   w.stats = c.take<double>(4);
-  w.partials = c.take<double>(2 * 512);
+  w.partials = c.take<double>(3 * kStatPartials);
   return w;
 }
 
@@ -177,8 +177,7 @@ static ttm_status image_forward(const Geo& g, const float* image, float2* Xf, fl
                                 double* stats, double* partials, const float* mask, hipStream_t stream) {
   const long L3 = (long)g.L0 * g.L1 * g.L2;
   const long rows = (long)g.n0 * g.n1;
-  TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), partials, stats, stream));
-  TTM_PROF(PC_STATS, launch_mask_sum(mask, L3, stats + 2, stream));
+  TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), mask, L3, partials, stats, stream));
   TTM_PROF(PC_ROWS, launch_r2c_rows(g.n2, image, g.n2, g.n2, rows, Xf, Xg, rows, 0, 1, stats, stream));
   TTM_PROF(PC_PEN_FWD, launch_pencils(g.n1, false, Xf, (long)g.n0 * g.p2, g.p2, (long)g.n1 * g.p2, g.p2, g.n1, 0,
                                       0, g.n1 - 1, 2, (long)(Xg - Xf), stream));
@@ -313,9 +312,9 @@ static ttm_status correlate_into(const Geo& g, int order_n, int K, const float* 
   const long half = g.half();
   TTM_PROF(PC_STATS, launch_multiplicities(order_n, w.mu, stream));
   TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream));
-  TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, bk, g.bank_slab(), K + 1, w.H, half, stream));
-  TTM_PROF(PC_PASS1, launch_pass1(g, w.Xg, bk + (long)K * g.bank_slab(), g.bank_slab(), 1,
-                                  w.H + (long)(K + 1) * half, half, stream));
+  // K components and the mask against f, then the mask against f^2
+  const Pass1Args p1{w.Xf, bk, K + 1, w.Xg, bk + (long)K * g.bank_slab(), 1, g.bank_slab(), w.H, half};
+  TTM_PROF(PC_PASS1, launch_pass1(g, p1, stream));
   TTM_PROF(PC_PEN_INV, pencils_inverse_valid(g, w.H, K + 2, half, stream));
   Pass3Args a;
   std::memset(&a, 0, sizeof(a));
@@ -380,7 +379,7 @@ ttm_status ttm_recover_pose(const float* score, const float* image, const float*
   const Geo g = make_geo(N, L);
   Carve c(ws);
   PoseWs w = pose_layout(c, g, opt->max_peaks, K, opt->refine, opt->n_seeds);
-  TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), w.partials, w.stats, stream));
+  TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), nullptr, 0, w.partials, w.stats, stream));
   PeakWs pw{w.hist, w.ctrl, w.allc, w.cand};
   float* cand_score = reinterpret_cast<float*>(w.ps.w);   // overwritten later by the pose scratch
   TTM_PROF(PC_PEAKS, launch_peaks(g, score, opt->threshold, opt->min_dist, opt->max_peaks, pw, w.cand_pos,
@@ -409,7 +408,7 @@ ttm_status ttm_pose_at(const float* image, const float* components, const float*
   const Geo g = make_geo(N, L);
   Carve c(ws);
   PoseWs w = pose_layout(c, g, opt->max_peaks, K, opt->refine, opt->n_seeds);
-  TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), w.partials, w.stats, stream));
+  TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), nullptr, 0, w.partials, w.stats, stream));
   TTM_PROF(PC_POSE, launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, n_pos,
                                        opt->refine, positions, nullptr, n_pos, w.ps, stream));
   TTM_PROF(PC_POSE, launch_pose_solve(g, nullptr, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol, n_pos,
@@ -487,8 +486,8 @@ ttm_status tm_classical(const float* image, ttm_dims N, const float* tmpl, const
   TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream));
   // w(x) from the two masked moments
   TTM_CALL(bank_forward(g, mask, 1, w.bbank, stream));
-  TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, w.bbank, g.bank_slab(), 1, w.H, half, stream));
-  TTM_PROF(PC_PASS1, launch_pass1(g, w.Xg, w.bbank, g.bank_slab(), 1, w.H + half, half, stream));
+  const Pass1Args p1{w.Xf, w.bbank, 1, w.Xg, w.bbank, 1, g.bank_slab(), w.H, half};
+  TTM_PROF(PC_PASS1, launch_pass1(g, p1, stream));
   TTM_PROF(PC_PEN_INV, pencils_inverse_valid(g, w.H, 2, half, stream));
   Pass3Args a;
   std::memset(&a, 0, sizeof(a));
@@ -506,7 +505,8 @@ ttm_status tm_classical(const float* image, ttm_dims N, const float* tmpl, const
     const int nb = (n_rot - j0) < B ? (n_rot - j0) : B;
     TTM_PROF(PC_BUILD, launch_rot_write(tmpl, mask, L.n0, L.n1, L.n2, w.quats, w.rstats, j0, nb, w.tbatch, stream));
     TTM_CALL(bank_forward(g, w.tbatch, nb, w.bbank, stream));
-    TTM_PROF(PC_PASS1, launch_pass1(g, w.Xf, w.bbank, g.bank_slab(), nb, w.H, half, stream));
+    const Pass1Args p1{w.Xf, w.bbank, nb, nullptr, nullptr, 0, g.bank_slab(), w.H, half};
+    TTM_PROF(PC_PASS1, launch_pass1(g, p1, stream));
     TTM_PROF(PC_PEN_INV, pencils_inverse_valid(g, w.H, nb, half, stream));
     Pass3Args m;
     std::memset(&m, 0, sizeof(m));

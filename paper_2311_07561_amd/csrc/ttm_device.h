@@ -112,6 +112,21 @@ __device__ __forceinline__ void fft_reg(float2 (&x)[R]) {
   }
 }
 
+// fft_reg for an input whose entries b >= BM are zero: y(k) = sum_{b < BM}
+// x(b) W_R^{bk}, evaluated directly for BM <= 2 (the first stage of a
+// zero-padded transform), else the full transform.
+template <int R, int BM, bool INV>
+__device__ __forceinline__ void fft_reg_pruned(float2 (&x)[R]) {
+  if constexpr (BM == 1) {
+    static_for<1, R>([&](auto k) { x[k] = x[0]; });
+  } else if constexpr (BM == 2 && R >= 2) {
+    const float2 x0 = x[0], x1 = x[1];
+    static_for<0, R>([&](auto k) { x[k] = cadd(x0, twmul32<decltype(k)::value * (32 / R), INV>(x1)); });
+  } else {
+    fft_reg<R, INV>(x);
+  }
+}
+
 // ----------------------------------------------------------------------------
 // FFT plans: N = R1 * R2 with R1 <= R2, R2 % R1 == 0
 // ----------------------------------------------------------------------------
@@ -144,11 +159,13 @@ __device__ __forceinline__ float2 twiddle(float2 v, const float2* tw, int idx) {
 // Engine A.  in: x[b] = x(a + R1 b), b < R2.  out: o[k*R1 + d] = X(c + R2 d),
 // c = a + R1 k, k < R2/R1, d < R1.  tw: the length-N table.  Starts with a
 // barrier (protects lds from earlier readers).
-template <int N, int PW, bool INV>
+// BM < R2: x[b] is zero for b >= BM (a zero-padded input of at most BM * R1
+// leading entries).
+template <int N, int PW, bool INV, int BM = Plan<N>::R2>
 __device__ __forceinline__ void engineA(float2 (&x)[Plan<N>::R2], float2 (&o)[Plan<N>::R2],
                                         float2* lds, const float2* tw, int p, int a) {
   constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
-  fft_reg<R2, INV>(x);
+  fft_reg_pruned<R2, (BM < R2 ? BM : R2), INV>(x);
 #pragma unroll
   for (int c = 1; c < R2; ++c) x[c] = twiddle<INV>(x[c], tw, (a * c) & (N - 1));
   __syncthreads();
@@ -191,7 +208,6 @@ __device__ __forceinline__ void engineB(float2 (&o)[Plan<N>::R2], float2 (&y)[Pl
   fft_reg<R2, INV>(y);
 }
 
-// number of packed components of S^n(R^4): C(n+3, 3)
 // Workgroups of a launch are dealt to the 8 XCDs round-robin (block b runs on
 // XCD b mod 8).  This maps block b to a tile index so that each XCD receives
 // one contiguous range of tiles: neighbouring tiles that share cache lines
@@ -201,6 +217,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + slot;
 }
 
+// number of packed components of S^n(R^4): C(n+3, 3)
 __device__ __forceinline__ int num_components_dev(int n) { return (n + 1) * (n + 2) * (n + 3) / 6; }
 
 // packed multi-index alpha of position k for order n (alpha1 from n down to

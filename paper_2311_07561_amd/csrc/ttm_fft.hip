@@ -17,82 +17,80 @@ namespace ttm {
 // ----------------------------------------------------------------------------
 // image and mask moments (float64, deterministic two-level reduction)
 // ----------------------------------------------------------------------------
-constexpr int kStatBlocks = 512;
+constexpr int kStatBlocks = kStatPartials;
 
-__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh /* 768 */) {
   const int tid = threadIdx.x;
   sh[tid] = a;
   sh[tid + 256] = b;
+  sh[tid + 512] = c;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (tid < s) {
       sh[tid] += sh[tid + s];
       sh[tid + 256] += sh[tid + 256 + s];
+      sh[tid + 512] += sh[tid + 512 + s];
     }
     __syncthreads();
   }
   a = sh[0];
   b = sh[256];
+  c = sh[512];
 }
 
+// per block: sum f, sum f^2 over a grid-stride share of the image and, if
+// mask is given, sum m over a share of the mask
 __global__ void __launch_bounds__(256) k_stats_partial(const float* __restrict__ x, long n,
+                                                       const float* __restrict__ mask, long nm,
                                                        double* __restrict__ partials) {
-  __shared__ double sh[512];
-  double s1 = 0.0, s2 = 0.0;
+  __shared__ double sh[768];
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
   const long n4 = n / 4;
+  const long gs = (long)gridDim.x * blockDim.x, t0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const float4* x4 = reinterpret_cast<const float4*>(x);
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (long)gridDim.x * blockDim.x) {
+  for (long i = t0; i < n4; i += gs) {
     const float4 v = x4[i];
     s1 += (double)v.x + (double)v.y + (double)v.z + (double)v.w;
     s2 += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
   }
-  for (long i = n4 * 4 + (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+  for (long i = n4 * 4 + t0; i < n; i += gs) {
     const double v = x[i];
     s1 += v;
     s2 += v * v;
   }
-  block_sum2(s1, s2, sh);
+  if (mask)
+    for (long i = t0; i < nm; i += gs) s3 += (double)mask[i];
+  block_sum3(s1, s2, s3, sh);
   if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = s1;
-    partials[2 * blockIdx.x + 1] = s2;
+    partials[3 * blockIdx.x] = s1;
+    partials[3 * blockIdx.x + 1] = s2;
+    partials[3 * blockIdx.x + 2] = s3;
   }
 }
 
-__global__ void __launch_bounds__(256) k_stats_final(const double* __restrict__ partials, int nb,
-                                                     long n, double* __restrict__ stats) {
-  __shared__ double sh[512];
-  double s1 = 0.0, s2 = 0.0;
+__global__ void __launch_bounds__(256) k_stats_final(const double* __restrict__ partials, int nb, long n,
+                                                     int with_mask, double* __restrict__ stats) {
+  __shared__ double sh[768];
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    s1 += partials[2 * i];
-    s2 += partials[2 * i + 1];
+    s1 += partials[3 * i];
+    s2 += partials[3 * i + 1];
+    s3 += partials[3 * i + 2];
   }
-  block_sum2(s1, s2, sh);
+  block_sum3(s1, s2, s3, sh);
   if (threadIdx.x == 0) {
     const double mean = s1 / (double)n;
     double var = s2 / (double)n - mean * mean;
     stats[0] = mean;
     stats[1] = var > 0.0 ? var : 0.0;
+    if (with_mask) stats[2] = s3;
   }
 }
 
-hipError_t launch_image_stats(const float* img, long n, double* partials, double* stats,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_stats_partial, dim3(kStatBlocks), dim3(256), 0, s, img, n, partials);
-  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(256), 0, s, partials, kStatBlocks, n, stats);
-  return hipGetLastError();
-}
-
-__global__ void __launch_bounds__(256) k_mask_sum(const float* __restrict__ m, long n,
-                                                  double* __restrict__ out) {
-  __shared__ double sh[512];
-  double s1 = 0.0, s2 = 0.0;
-  for (long i = threadIdx.x; i < n; i += blockDim.x) s1 += (double)m[i];
-  block_sum2(s1, s2, sh);
-  if (threadIdx.x == 0) out[0] = s1;
-}
-
-hipError_t launch_mask_sum(const float* mask, long n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_mask_sum, dim3(1), dim3(256), 0, s, mask, n, out);
+hipError_t launch_image_stats(const float* img, long n, const float* mask, long nm, double* partials,
+                              double* stats, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_partial, dim3(kStatBlocks), dim3(256), 0, s, img, n, mask, nm, partials);
+  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(256), 0, s, partials, kStatBlocks, n, mask ? 1 : 0, stats);
   return hipGetLastError();
 }
 
@@ -289,10 +287,10 @@ hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long
 // ----------------------------------------------------------------------------
 // pass 1: axis 0, fused fan-out (Section 2: <f,g> = F^-1(F(f) conj F(g)))
 // ----------------------------------------------------------------------------
-template <int N0>
-__global__ void __launch_bounds__(256) k_pass1(const float2* __restrict__ src, long P, int p2, int h2, int L0,
-                                               const float2* __restrict__ tmpl, long tmpl_stride, int nt,
-                                               float2* __restrict__ out, long out_stride, int shift0, int lo0,
+// BM: the template block's L0 rows occupy the first BM of each thread's R2
+// elements (BM = R2: no pruning)
+template <int N0, int BM>
+__global__ void __launch_bounds__(256) k_pass1(Pass1Args A, long P, int p2, int h2, int L0, int shift0, int lo0,
                                                int hi0) {
   using C = PenCfg<N0>;
   constexpr int R1 = C::R1, R2 = C::R2, PW = C::PW;
@@ -307,37 +305,35 @@ __global__ void __launch_bounds__(256) k_pass1(const float2* __restrict__ src, l
   const unsigned pu = valid ? (unsigned)p : 0u;
   const unsigned P32 = (unsigned)P;
   const unsigned step = (unsigned)R1 * P32;
+  const unsigned off = (unsigned)a * P32 + pu;
   float2 x[R2], F[R2], T[R2], y[R2];
-  {
-    const unsigned off = (unsigned)a * P32 + pu;
-#pragma unroll
-    for (int b = 0; b < R2; ++b) x[b] = src[off + b * step];
-    if (!valid) {
-#pragma unroll
-      for (int b = 0; b < R2; ++b) x[b] = make_float2(0.0f, 0.0f);
-    }
-  }
-  engineA<N0, PW, false>(x, F, lds, tw, pl, a);
-  const int bmax = (L0 + R1 - 1) / R1;      // the template block has L0 rows along axis 0
+  const int nt = A.nt0 + A.nt1;
 #pragma unroll 1
   for (int i = 0; i < nt; ++i) {
-    const float2* __restrict__ tb = tmpl + (long)i * tmpl_stride;
-    const unsigned off = (unsigned)a * P32 + pu;
+    if (i == 0 || i == A.nt0) {
+      // forward axis-0 transform of the image tile of this group of entries
+      const float2* __restrict__ src = i == 0 ? A.src0 : A.src1;
+#pragma unroll
+      for (int b = 0; b < R2; ++b) x[b] = src[off + b * step];
+      if (!valid) {
+#pragma unroll
+        for (int b = 0; b < R2; ++b) x[b] = make_float2(0.0f, 0.0f);
+      }
+      engineA<N0, PW, false>(x, F, lds, tw, pl, a);
+    }
+    const float2* __restrict__ tb = i < A.nt0 ? A.tmpl0 + (long)i * A.tmpl_stride
+                                              : A.tmpl1 + (long)(i - A.nt0) * A.tmpl_stride;
 #pragma unroll
     for (int b = 0; b < R2; ++b) {
       x[b] = make_float2(0.0f, 0.0f);
-      if (b < bmax && a + R1 * b < L0) x[b] = tb[off + b * step];
+      if (b < BM && valid && a + R1 * b < L0) x[b] = tb[off + b * step];
     }
-    if (!valid) {
-#pragma unroll
-      for (int b = 0; b < R2; ++b) x[b] = make_float2(0.0f, 0.0f);
-    }
-    engineA<N0, PW, false>(x, T, lds, tw, pl, a);
+    engineA<N0, PW, false, BM>(x, T, lds, tw, pl, a);
 #pragma unroll
     for (int j = 0; j < R2; ++j) T[j] = cmulc(F[j], T[j]);
     engineB<N0, PW, true>(T, y, lds, tw, pl, a);
     if (valid) {
-      float2* __restrict__ ob = out + (long)i * out_stride;
+      float2* __restrict__ ob = A.out + (long)i * A.out_stride;
 #pragma unroll
       for (int g = 0; g < R2; ++g) {
         const int j = (a + R1 * g + shift0) & (N0 - 1);
@@ -348,25 +344,29 @@ __global__ void __launch_bounds__(256) k_pass1(const float2* __restrict__ src, l
 }
 
 template <int N0>
-static hipError_t pass1_n(const Geo& g, const float2* src, const float2* tmpl, long tmpl_stride,
-                          int nt, float2* out, long out_stride, hipStream_t s) {
-  constexpr int PW = PenCfg<N0>::PW;
+static hipError_t pass1_n(const Geo& g, const Pass1Args& a, hipStream_t s) {
+  constexpr int PW = PenCfg<N0>::PW, R1 = PenCfg<N0>::R1, R2 = PenCfg<N0>::R2;
   const long P = (long)g.n1 * g.p2;
   dim3 grid((unsigned)((P + PW - 1) / PW));
-  hipLaunchKernelGGL((k_pass1<N0>), grid, dim3(256), 0, s, src, P, g.p2, g.h2, g.L0, tmpl, tmpl_stride, nt, out,
-                     out_stride, g.c0, g.lo0(), g.hi0());
+  const int bm = (g.L0 + R1 - 1) / R1;
+  if (bm == 1)
+    hipLaunchKernelGGL((k_pass1<N0, 1>), grid, dim3(256), 0, s, a, P, g.p2, g.h2, g.L0, g.c0, g.lo0(), g.hi0());
+  else if (bm == 2)
+    hipLaunchKernelGGL((k_pass1<N0, 2>), grid, dim3(256), 0, s, a, P, g.p2, g.h2, g.L0, g.c0, g.lo0(), g.hi0());
+  else
+    hipLaunchKernelGGL((k_pass1<N0, R2>), grid, dim3(256), 0, s, a, P, g.p2, g.h2, g.L0, g.c0, g.lo0(), g.hi0());
   return hipGetLastError();
 }
 
-hipError_t launch_pass1(const Geo& g, const float2* src, const float2* tmpl, long tmpl_stride,
-                        int nt, float2* out, long out_stride, hipStream_t s) {
+hipError_t launch_pass1(const Geo& g, const Pass1Args& a, hipStream_t s) {
+  if (a.nt0 < 1 || a.nt1 < 0) return hipErrorInvalidValue;
   switch (g.n0) {
-    case 16: return pass1_n<16>(g, src, tmpl, tmpl_stride, nt, out, out_stride, s);
-    case 32: return pass1_n<32>(g, src, tmpl, tmpl_stride, nt, out, out_stride, s);
-    case 64: return pass1_n<64>(g, src, tmpl, tmpl_stride, nt, out, out_stride, s);
-    case 128: return pass1_n<128>(g, src, tmpl, tmpl_stride, nt, out, out_stride, s);
-    case 256: return pass1_n<256>(g, src, tmpl, tmpl_stride, nt, out, out_stride, s);
-    case 512: return pass1_n<512>(g, src, tmpl, tmpl_stride, nt, out, out_stride, s);
+    case 16: return pass1_n<16>(g, a, s);
+    case 32: return pass1_n<32>(g, a, s);
+    case 64: return pass1_n<64>(g, a, s);
+    case 128: return pass1_n<128>(g, a, s);
+    case 256: return pass1_n<256>(g, a, s);
+    case 512: return pass1_n<512>(g, a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -394,7 +394,11 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
   constexpr int R1 = C::R1, R2 = C::R2, RW = C::RW, SP = C::SP;
   constexpr int N2 = 2 * M, H2 = M + 1;
   __shared__ float2 stage[RW * SP];
-  __shared__ float ostage[RW * N2];
+  // output stage (pitch N2 + 1: rows on distinct banks), aliasing the input
+  // stage, which is free once the last pair has been transformed
+  constexpr int OP = N2 + 1;
+  static_assert(RW * OP <= 2 * RW * SP, "output stage exceeds the input stage");
+  float* const ostage = reinterpret_cast<float*>(stage);
   __shared__ float2 twM[M];
   __shared__ float2 tw2[N2];
   const int tid = threadIdx.x;
@@ -584,8 +588,8 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
           v0 = wv[j].x * sqrtf(acc[j].x) * fscale;
           v1 = wv[j].y * sqrtf(acc[j].y) * fscale;
         }
-        ostage[p * N2 + ((2 * n + g.c2) & (N2 - 1))] = v0;
-        ostage[p * N2 + ((2 * n + 1 + g.c2) & (N2 - 1))] = v1;
+        ostage[p * OP + ((2 * n + g.c2) & (N2 - 1))] = v0;
+        ostage[p * OP + ((2 * n + 1 + g.c2) & (N2 - 1))] = v1;
       }
     __syncthreads();
     for (int e = tid; e < RW * N2; e += 256) {
@@ -594,7 +598,7 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
       if (r >= nrows) continue;
       const int x0 = (int)(r / g.n1), x1 = (int)(r % g.n1);
       const bool ok = x0 >= g.lo0 && x0 <= g.hi0 && x1 >= g.lo1 && x1 <= g.hi1 && x2 >= g.lo2 && x2 <= g.hi2;
-      dst[r * g.n2 + x2] = ok ? ostage[e] : 0.0f;
+      dst[r * g.n2 + x2] = ok ? ostage[rr * OP + x2] : 0.0f;
     }
   }
 }

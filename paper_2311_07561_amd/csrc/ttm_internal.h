@@ -40,11 +40,12 @@ struct Geo {
 __host__ __device__ constexpr int row_pitch(int n2) { return n2 / 2 + 1; }
 
 // --- FFT passes (ttm_fft.hip) -------------------------------------------------
-// image moments: stats[0] = mean, stats[1] = population variance (float64)
-hipError_t launch_image_stats(const float* img, long n, double* partials, double* stats,
-                              hipStream_t s);
-// mask sum: stats[0] = m_sum
-hipError_t launch_mask_sum(const float* mask, long n, double* out, hipStream_t s);
+// image moments in float64: stats[0] = mean, stats[1] = population variance
+// and, if mask is given, stats[2] = m_sum over its nm values; partials holds
+// 3 * kStatPartials doubles
+constexpr int kStatPartials = 512;
+hipError_t launch_image_stats(const float* img, long n, const float* mask, long nm, double* partials,
+                              double* stats, hipStream_t s);
 // axis-2 R2C of rows.  mode 0: src rows (len_valid <= n2 values, rest zero)
 // -> dst0; mode 1: image rows, (f - mean) -> dst0 and (f - mean)^2 -> dst1.
 // dst row of source row r: (r / grp) * grp_stride + r % grp (rows of h2).
@@ -59,13 +60,24 @@ hipError_t launch_r2c_rows(int n2, const float* src, long src_stride, int len_va
 // as data).  blockIdx.y walks nbatch arrays batch_stride apart.
 hipError_t launch_pencils(int N, bool inverse, float2* data, long npencils, long Q, long S_outer, long S_axis,
                           int nin, int shift, int slo, int shi, int nbatch, long batch_stride, hipStream_t s);
-// first inverse pass, fused: forward axis-0 FFT of the image pencils in src,
-// then for each of nt template entries (bank layout [L0][n1][p2]): pruned
-// forward axis-0 FFT, product with conj, inverse axis-0 FFT, store into
-// out + i * out_stride with the centre shift; only the planes x0 of the
-// valid region are stored.
-hipError_t launch_pass1(const Geo& g, const float2* src, const float2* tmpl, long tmpl_stride,
-                        int nt, float2* out, long out_stride, hipStream_t s);
+// first inverse pass, fused: forward axis-0 FFT of the image pencils in src0,
+// then for each of nt0 template entries from tmpl0 (bank layout
+// [L0][n1][p2], tmpl_stride apart): pruned forward axis-0 FFT, product with
+// conj, inverse axis-0 FFT, store into out + i * out_stride with the centre
+// shift; then the same for src1 with nt1 entries from tmpl1 (outputs
+// nt0 .. nt0 + nt1 - 1).  Only the planes x0 of the valid region are stored.
+struct Pass1Args {
+  const float2* src0;
+  const float2* tmpl0;
+  int nt0;
+  const float2* src1;
+  const float2* tmpl1;
+  int nt1;
+  long tmpl_stride;
+  float2* out;
+  long out_stride;
+};
+hipError_t launch_pass1(const Geo& g, const Pass1Args& a, hipStream_t s);
 // last inverse pass (axis-2 C2R) fused with the per-voxel reduction.  Only
 // rows (x0, x1) of the valid region are read; outputs outside it are zero
 // (P3_SCORE, P3_W) or left untouched (P3_MAX).
