@@ -592,3 +592,35 @@ def refine_by_eigenvalue(f, T, m, n: int, x, eps_v: float = EPS_V_DEFAULT,
         if lams[k] > lams[best]:
             best = k
     return np.asarray(x) + offs[best], qs[best], lams[best], lams
+
+
+def refine_by_ncc(f, t, m, T, n: int, x, eps_v: float = EPS_V_DEFAULT,
+                  n_brute: int = 100000):
+    """A second reading of Section 3.4's position selection: each voxel y of the
+    3x3x3 neighbourhood of a candidate (inside the valid region) gets its own
+    rotation, the dominant Z-eigenvector q_y of C_n(y) (Theorem "main"), and the
+    classical NCC at that rotation, c(y, R(q_y)) (Section 2, the normalised
+    correlation of Algorithm 1).  The candidate moves to the voxel with the
+    largest such NCC (the centre first on ties, then the lower neighbour
+    index).  Returns (position, q, lambda, ncc, the 27 NCC values)."""
+    N = np.shape(f)
+    L = np.shape(T)[1:]
+    lo, hi = valid_region(N, L)
+    offs = neighbourhood_offsets()
+    nccs = np.full(27, -np.inf)
+    qs = np.zeros((27, 4))
+    lams = np.full(27, -np.inf)
+    for k, o in enumerate(offs):
+        y = np.asarray(x) + o
+        if np.any(y < lo) or np.any(y >= hi):
+            continue
+        C = tensor_field_at(f, T, m, y[None], eps_v)[0]
+        q, lam, _ = dominant_z_eigenpair(C, n, n_brute=n_brute)
+        qs[k] = q
+        lams[k] = lam
+        nccs[k] = classical_ncc_at(f, t, m, q[None], y[None], eps_v)[0, 0]
+    best = 13
+    for k in range(27):
+        if nccs[k] > nccs[best]:
+            best = k
+    return np.asarray(x) + offs[best], qs[best], lams[best], nccs[best], nccs

@@ -440,3 +440,30 @@ def test_find_peaks_fast_matches_loops():
         a = O.find_peaks(F, (5, 4, 6), thr, d, 7)
         b = O.find_peaks_fast(F, (5, 4, 6), thr, d, 7)
         assert np.array_equal(a, b)
+
+
+def test_refinement_returns_to_a_noiseless_copy():
+    # a nearly noiseless analytic copy at x0 with a random pose: started one
+    # voxel away along a corner diagonal, the NCC-verified refinement moves to
+    # x0, where the NCC at the recovered rotation is near 1 (the copy is exact
+    # up to the rotation's quadrature error: Section 2, NCC = 1 at an exact
+    # copy; Theorem "main" for the rotation).  Choosing by the largest
+    # eigenvalue instead stays off the copy here, so this pins the NCC rule.
+    L, n = 12, 4
+    tm = synth.make_blob_template(_rng(60), L, 5, L / 2)
+    t = tm.grid()
+    m = synth.ball_mask(L, L / 2)
+    qs = synth.super_fibonacci(3000)
+    T = O.tensor_template(t, m, n, qs, np.full(len(qs), 1.0 / len(qs)))
+    qtrue = synth.random_quaternions(_rng(61), 1)[0]
+    x0 = np.array([12, 12, 12])
+    f = synth.render_copies((24, 24, 24), tm, x0[None], qtrue[None])
+    f = f + 0.01 * _rng(62).standard_normal(f.shape)
+    for start in (x0 + np.array([-1, 1, -1]),):
+        pos, q, lam, ncc, nccs = O.refine_by_ncc(f, t, m, T, n, start, n_brute=20000)
+        assert np.array_equal(pos, x0), (start, pos, nccs)
+        assert ncc > 0.95, ncc
+        assert O.rotation_angle_deg(q, qtrue) < 3.0
+        # the neighbour values that exist are finite and below the chosen one
+        fin = nccs[np.isfinite(nccs)]
+        assert len(fin) == 27 and fin.max() == ncc
