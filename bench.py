@@ -5,9 +5,10 @@ rotation-sampled NCC template matching at 10^4 rotations on the same GPU.
 A step is one ttm_match call over the resident tomogram: image moments, R2C
 of f and f^2, K+2 fanned-out spectral products, batched C2R inverses, local
 normalisation and Frobenius score, then peak picking and the dominant
-Z-eigenpair of the correlated tensor field at every peak (at its 27
-neighbours, keeping the largest eigenvalue, unless --refine 0).  The tensor-template build (once per template) is timed
-separately.
+Z-eigenpair of the correlated tensor field at every peak and its 26
+neighbours; the reported voxel is the one whose NCC at its own rotation is
+largest (--refine 2, the default; 1 keeps the largest eigenvalue, 0 the peak
+itself).  The tensor-template build (once per template) is timed separately.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 
@@ -78,7 +79,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--build-rotations", type=int, default=10000)
     p.add_argument("--classical-rotations", type=int, default=10000)
-    p.add_argument("--refine", type=int, default=1)
+    p.add_argument("--refine", type=int, default=2,
+                   help="0: pose at each peak; 1: best eigenvalue of the 3x3x3 neighbourhood; "
+                        "2: best NCC at each neighbour's own rotation")
     p.add_argument("--order6", type=int, default=1, help="also time and score tensor order 6")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU time of the oracle baseline sample (0 = skip)")
@@ -174,7 +177,7 @@ def run_order(order, wl, img, tmpl, mask, args, ttm, synth, torch, dev, angle, w
     score = bufs.score
 
     def step():
-        ttm.match(img, bank, mask, order, opt, bufs)
+        ttm.match(img, bank, mask, order, opt, bufs, tmpl=tmpl)
 
     ms, prof = time_steps(step, args.steps, args.warmup, ttm, torch)
     log(f"order {order}: step {ms:.3f} ms")
@@ -182,11 +185,14 @@ def run_order(order, wl, img, tmpl, mask, args, ttm, synth, torch, dev, angle, w
     det = match_errors(res["pos"].cpu().numpy(), res["quat"].cpu().numpy(), wl.positions, wl.true_quats, angle)
     out = {"order": order, "components": K, "ms_per_step": ms, "build_ms": round(build_ms, 1),
            "pose_detected": dict(err_stats(det), recall=len(det) / len(wl.positions), refine=args.refine)}
-    if args.refine:
-        opt0 = ttm.default_options(max_peaks=len(wl.positions), min_dist=float(L[0]) / 2, threshold=0.0)
-        r0 = ttm.recover_pose(score, img, comps, mask, order, opt0, want_C=False)
+    for rf in (0, 1, 2):
+        if rf == args.refine:
+            continue
+        opt0 = ttm.default_options(max_peaks=len(wl.positions), min_dist=float(L[0]) / 2, threshold=0.0,
+                                   refine=rf)
+        r0 = ttm.recover_pose(score, img, comps, mask, order, opt0, want_C=False, tmpl=tmpl)
         d0 = match_errors(r0["pos"].cpu().numpy(), r0["quat"].cpu().numpy(), wl.positions, wl.true_quats, angle)
-        out["pose_detected_no_refine"] = dict(err_stats(d0), recall=len(d0) / len(wl.positions))
+        out[f"pose_detected_refine{rf}"] = dict(err_stats(d0), recall=len(d0) / len(wl.positions))
     pa = ttm.pose_at(img, comps, mask, order, wl.positions,
                      ttm.default_options(max_peaks=len(wl.positions)), want_C=False)
     at = [angle(q, t) for q, t in zip(pa["quat"].cpu().numpy(), wl.true_quats)]

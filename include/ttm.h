@@ -68,7 +68,9 @@ typedef struct {
                             candidate to the voxel of its 3x3x3 neighbourhood
                             with the largest dominant Z-eigenvalue (the
                             spectral norm the Frobenius score stands in for,
-                            Section 3.4); default 0                            */
+                            Section 3.4); 2: move it to the voxel whose NCC
+                            c(y, R(q_y)) at its own dominant rotation q_y is
+                            largest (needs the raw template); default 0       */
 } ttm_options;
 
 /* Pose flags (bit set in out_flags). */
@@ -170,10 +172,18 @@ ttm_status ttm_correlate(
  * whenever they do not increase lambda; by Theorem "main" the eigenvector is
  * the rotation of the match.  With opt->refine = 1 this is done at the 27
  * voxels around each peak and the one with the largest lambda is reported.
+ * With opt->refine = 2 each of the 27 voxels y is scored by the classical
+ * normalised correlation at its own rotation, c(y, R(q_y)) = w(y) <tau_y f,
+ * s_R> with s_R the raw template rotated by R(q_y) and normalised under the
+ * mask (Section 2, Algorithm 1; float64 sums), and the voxel with the largest
+ * NCC is reported (ties: the centre, then the lower neighbour index).
  *
  *   score            [n0][n1][n2] float32 from ttm_correlate
  *   image            the correlated image; components: K x [L0][L1][L2] float32
  *   mask             the mask used for the components
+ *   tmpl             the raw template [L0][L1][L2] float32 the components were
+ *                    built from; read only when opt->refine = 2 (else may be
+ *                    NULL; NULL with refine = 2 is TTM_E_ARG)
  *   out_pos          max_peaks x 3 int32 (i0,i1,i2)
  *   out_quat         max_peaks x 4 float32, canonical (a > 0)
  *   out_lambda       max_peaks float64 dominant Z-eigenvalue C Q^n
@@ -196,14 +206,15 @@ size_t ttm_pose_workspace_bytes(ttm_dims N, ttm_dims L, int32_t order_n,
  * n_pos <= opt->max_peaks; workspace from ttm_pose_workspace_bytes. */
 ttm_status ttm_pose_at(
     const float* image, const float* components, const float* mask,
-    ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt,
+    const float* tmpl, ttm_dims N, ttm_dims L, int32_t order_n,
+    const ttm_options* opt,
     const int32_t* positions, int32_t n_pos, int32_t* out_pos,
     float* out_quat, double* out_lambda, int32_t* out_flags, double* out_C,
     void* ws, size_t ws_bytes, hipStream_t stream);
 ttm_status ttm_recover_pose(
     const float* score, const float* image, const float* components,
-    const float* mask, ttm_dims N, ttm_dims L, int32_t order_n,
-    const ttm_options* opt, int32_t* out_pos, float* out_quat,
+    const float* mask, const float* tmpl, ttm_dims N, ttm_dims L,
+    int32_t order_n, const ttm_options* opt, int32_t* out_pos, float* out_quat,
     double* out_lambda, float* out_peak_score, int32_t* out_flags,
     double* out_C, int32_t* out_count, void* ws, size_t ws_bytes,
     hipStream_t stream);
@@ -221,7 +232,8 @@ size_t ttm_match_workspace_bytes(ttm_dims N, ttm_dims L, int32_t order_n,
                                  const ttm_options* opt);
 ttm_status ttm_match(
     const float* image, ttm_dims N, const void* bank, ttm_dims L,
-    int32_t order_n, const float* mask, const ttm_options* opt,
+    int32_t order_n, const float* mask, const float* tmpl,
+    const ttm_options* opt,
     float* out_score, float* out_w, int32_t* out_pos, float* out_quat,
     double* out_lambda, float* out_peak_score, int32_t* out_flags,
     double* out_C, int32_t* out_count, void* ws, size_t ws_bytes,

@@ -146,6 +146,10 @@ static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refi
   w.ps.q = c.take<float>(nb * 4);
   w.ps.lam = c.take<double>(nb);
   w.ps.flags = c.take<int>(nb);
+  w.ps.ncc = c.take<double>(nb);
+  w.ps.mlist = c.take<unsigned>((size_t)g.L0 * g.L1 * g.L2);
+  w.ps.mval = c.take<float>((size_t)g.L0 * g.L1 * g.L2);
+  w.ps.mcount = c.take<int>(1);
   return w;
 }
 
@@ -352,7 +356,7 @@ static bool pose_opts_ok(const ttm_options* opt) {
   if (opt->n_seeds < 64 || opt->n_seeds > 65536) return false;
   if (opt->hopm_max_iter < 1 || !(opt->hopm_tol > 0.0)) return false;
   if (!(opt->threshold >= 0.0f) || !(opt->min_dist >= 0.0f) || !(opt->eps_v >= 0.0f)) return false;
-  if (opt->refine != 0 && opt->refine != 1) return false;
+  if (opt->refine < 0 || opt->refine > 2) return false;
   return true;
 }
 
@@ -366,12 +370,14 @@ size_t ttm_pose_workspace_bytes(ttm_dims N, ttm_dims L, int32_t order_n, const t
 }
 
 ttm_status ttm_recover_pose(const float* score, const float* image, const float* components, const float* mask,
-                            ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt, int32_t* out_pos,
-                            float* out_quat, double* out_lambda, float* out_peak_score, int32_t* out_flags,
-                            double* out_C, int32_t* out_count, void* ws, size_t ws_bytes, hipStream_t stream) {
+                            const float* tmpl, ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt,
+                            int32_t* out_pos, float* out_quat, double* out_lambda, float* out_peak_score,
+                            int32_t* out_flags, double* out_C, int32_t* out_count, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
   if (!score || !image || !components || !mask || !opt || !out_pos || !out_quat || !out_lambda ||
       !out_peak_score || !out_flags || !out_count)
     return TTM_E_ARG;
+  if (opt->refine == 2 && !tmpl) return TTM_E_ARG;
   const int K = ttm_num_components(order_n);
   if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
   if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
@@ -387,18 +393,20 @@ ttm_status ttm_recover_pose(const float* score, const float* image, const float*
   TTM_PROF(PC_POSE, launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v,
                                        opt->max_peaks, opt->refine, w.cand_pos, out_count, 0, w.ps, stream));
   TTM_PROF(PC_POSE, launch_pose_solve(g, score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
-                                      opt->max_peaks, opt->refine, w.cand_pos, out_count, 0, out_pos, out_quat,
-                                      out_lambda, out_peak_score, out_flags, out_C, w.ps, stream));
+                                      opt->max_peaks, opt->refine, w.cand_pos, out_count, 0, image, tmpl, mask,
+                                      out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, w.ps,
+                                      stream));
   return TTM_OK;
 }
 
-ttm_status ttm_pose_at(const float* image, const float* components, const float* mask, ttm_dims N, ttm_dims L,
-                       int32_t order_n, const ttm_options* opt, const int32_t* positions, int32_t n_pos,
-                       int32_t* out_pos, float* out_quat, double* out_lambda, int32_t* out_flags, double* out_C,
-                       void* ws, size_t ws_bytes, hipStream_t stream) {
+ttm_status ttm_pose_at(const float* image, const float* components, const float* mask, const float* tmpl,
+                       ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt, const int32_t* positions,
+                       int32_t n_pos, int32_t* out_pos, float* out_quat, double* out_lambda, int32_t* out_flags,
+                       double* out_C, void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!image || !components || !mask || !opt || !positions || !out_pos || !out_quat || !out_lambda ||
       !out_flags)
     return TTM_E_ARG;
+  if (opt->refine == 2 && !tmpl) return TTM_E_ARG;
   const int K = ttm_num_components(order_n);
   if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
   if (n_pos < 0 || n_pos > opt->max_peaks) return TTM_E_ARG;
@@ -412,8 +420,8 @@ ttm_status ttm_pose_at(const float* image, const float* components, const float*
   TTM_PROF(PC_POSE, launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, n_pos,
                                        opt->refine, positions, nullptr, n_pos, w.ps, stream));
   TTM_PROF(PC_POSE, launch_pose_solve(g, nullptr, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol, n_pos,
-                                      opt->refine, positions, nullptr, n_pos, out_pos, out_quat, out_lambda,
-                                      nullptr, out_flags, out_C, w.ps, stream));
+                                      opt->refine, positions, nullptr, n_pos, image, tmpl, mask, out_pos, out_quat,
+                                      out_lambda, nullptr, out_flags, out_C, w.ps, stream));
   return TTM_OK;
 }
 
@@ -429,12 +437,14 @@ size_t ttm_match_workspace_bytes(ttm_dims N, ttm_dims L, int32_t order_n, const 
 }
 
 ttm_status ttm_match(const float* image, ttm_dims N, const void* bank, ttm_dims L, int32_t order_n,
-                     const float* mask, const ttm_options* opt, float* out_score, float* out_w, int32_t* out_pos,
-                     float* out_quat, double* out_lambda, float* out_peak_score, int32_t* out_flags,
-                     double* out_C, int32_t* out_count, void* ws, size_t ws_bytes, hipStream_t stream) {
+                     const float* mask, const float* tmpl, const ttm_options* opt, float* out_score, float* out_w,
+                     int32_t* out_pos, float* out_quat, double* out_lambda, float* out_peak_score,
+                     int32_t* out_flags, double* out_C, int32_t* out_count, void* ws, size_t ws_bytes,
+                     hipStream_t stream) {
   if (!image || !bank || !mask || !opt || !out_score || !out_pos || !out_quat || !out_lambda ||
       !out_peak_score || !out_flags || !out_count)
     return TTM_E_ARG;
+  if (opt->refine == 2 && !tmpl) return TTM_E_ARG;
   const int K = ttm_num_components(order_n);
   if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
   if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
@@ -454,8 +464,9 @@ ttm_status ttm_match(const float* image, ttm_dims N, const void* bank, ttm_dims 
   TTM_PROF(PC_POSE, launch_field_at(g, cw.H, g.half(), K, wout, opt->max_peaks, opt->refine, pw.cand_pos,
                                     out_count, 0, pw.ps, stream));
   TTM_PROF(PC_POSE, launch_pose_solve(g, out_score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
-                                      opt->max_peaks, opt->refine, pw.cand_pos, out_count, 0, out_pos, out_quat,
-                                      out_lambda, out_peak_score, out_flags, out_C, pw.ps, stream));
+                                      opt->max_peaks, opt->refine, pw.cand_pos, out_count, 0, image, tmpl, mask,
+                                      out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, pw.ps,
+                                      stream));
   return TTM_OK;
 }
 

@@ -10,62 +10,9 @@
 // box.  Masked sums and the tensor accumulation are float64.
 #include "ttm_device.h"
 #include "ttm_internal.h"
+#include "ttm_rotate.h"
 
 namespace ttm {
-
-struct Rot {
-  float r[9];   // row-major R
-};
-
-__device__ __forceinline__ Rot quat_rot(const float* q4) {
-  double a = q4[0], b = q4[1], c = q4[2], d = q4[3];
-  const double nrm = sqrt(a * a + b * b + c * c + d * d);
-  a /= nrm; b /= nrm; c /= nrm; d /= nrm;
-  Rot R;
-  R.r[0] = (float)(a * a + b * b - c * c - d * d);
-  R.r[1] = (float)(2.0 * (b * c - a * d));
-  R.r[2] = (float)(2.0 * (b * d + a * c));
-  R.r[3] = (float)(2.0 * (b * c + a * d));
-  R.r[4] = (float)(a * a - b * b + c * c - d * d);
-  R.r[5] = (float)(2.0 * (c * d - a * b));
-  R.r[6] = (float)(2.0 * (b * d - a * c));
-  R.r[7] = (float)(2.0 * (c * d + a * b));
-  R.r[8] = (float)(a * a - b * b - c * c + d * d);
-  return R;
-}
-
-// t(c + R^-1 (u - c)) with R^-1 = R^T, trilinear, zero outside [0, L)
-__device__ __forceinline__ float sample_rotated(const float* __restrict__ t, int L0, int L1, int L2,
-                                                const Rot& R, int u0, int u1, int u2) {
-  const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;
-  const float v0 = (float)(u0 - c0), v1 = (float)(u1 - c1), v2 = (float)(u2 - c2);
-  const float p0 = c0 + R.r[0] * v0 + R.r[3] * v1 + R.r[6] * v2;
-  const float p1 = c1 + R.r[1] * v0 + R.r[4] * v1 + R.r[7] * v2;
-  const float p2 = c2 + R.r[2] * v0 + R.r[5] * v1 + R.r[8] * v2;
-  const float f0 = floorf(p0), f1 = floorf(p1), f2 = floorf(p2);
-  const int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
-  const float w0 = p0 - f0, w1 = p1 - f1, w2 = p2 - f2;
-  float acc = 0.0f;
-#pragma unroll
-  for (int d0 = 0; d0 < 2; ++d0) {
-    const int j0 = i0 + d0;
-    if (j0 < 0 || j0 >= L0) continue;
-    const float a0 = d0 ? w0 : 1.0f - w0;
-#pragma unroll
-    for (int d1 = 0; d1 < 2; ++d1) {
-      const int j1 = i1 + d1;
-      if (j1 < 0 || j1 >= L1) continue;
-      const float a1 = a0 * (d1 ? w1 : 1.0f - w1);
-#pragma unroll
-      for (int d2 = 0; d2 < 2; ++d2) {
-        const int j2 = i2 + d2;
-        if (j2 < 0 || j2 >= L2) continue;
-        acc += a1 * (d2 ? w2 : 1.0f - w2) * t[((long)j0 * L1 + j1) * L2 + j2];
-      }
-    }
-  }
-  return acc;
-}
 
 // ----------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_rot_stats(const float* __restrict__ t, const float* __restrict__ m,

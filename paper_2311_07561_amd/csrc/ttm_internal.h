@@ -142,6 +142,10 @@ struct PoseScratch {
   float* q;       // max_peaks * NB * 4
   double* lam;    // max_peaks * NB
   int* flags;     // max_peaks * NB
+  double* ncc;    // max_peaks * NB: NCC at the voxel's own rotation (refine 2)
+  unsigned* mlist;  // L0 L1 L2: packed coordinates of the mask voxels (refine 2)
+  float* mval;      // L0 L1 L2: their mask values
+  int* mcount;      // 1: their number
 };
 // C_n(x) in float64 by direct window sums at max_peaks candidates (count from
 // count_dev if non-null, else count_host), at the 27 neighbours if refine
@@ -156,11 +160,13 @@ hipError_t launch_field_at(const Geo& g, const float2* H, long pstride, int K, c
                            int max_peaks, int refine, const int* pos_in, const int* count_dev, int count_host,
                            const PoseScratch& ps, hipStream_t s);
 // dominant Z-eigenpairs of the tensors in ps and, per candidate, the
-// neighbour with the largest lambda
+// neighbour with the largest lambda (refine 1) or with the largest NCC of the
+// image window against the template rotated by the voxel's own eigenvector
+// (refine 2: image, tmpl and mask are read)
 hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int n_seeds, int max_iter,
                              double tol, int max_peaks, int refine, const int* pos_in, const int* count_dev,
-                             int count_host, int* out_pos, float* out_quat, double* out_lambda,
-                             float* out_score, int* out_flags, double* out_C, const PoseScratch& ps,
-                             hipStream_t s);
+                             int count_host, const float* image, const float* tmpl, const float* mask,
+                             int* out_pos, float* out_quat, double* out_lambda, float* out_score, int* out_flags,
+                             double* out_C, const PoseScratch& ps, hipStream_t s);
 
 }  // namespace ttm

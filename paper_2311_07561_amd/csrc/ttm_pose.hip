@@ -15,6 +15,7 @@
 // on the sphere, from the 4 best mutually distant seeds.
 #include "ttm_device.h"
 #include "ttm_internal.h"
+#include "ttm_rotate.h"
 
 namespace ttm {
 
@@ -836,30 +837,293 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
   }
 }
 
-// per candidate: the neighbour with the largest dominant Z-eigenvalue (the
-// centre first on ties, then the lower neighbour index)
+// The voxels of the mask box with m(u) != 0, packed as u0 | u1 << 10 | u2 << 20
+// (extents <= 512), their mask values and their count.  Order: 4x4x4 bricks
+// in C order, the voxels of a brick in C order within it, so that the 64
+// lanes of a wave sample a compact region (fewer LDS bank conflicts in the
+// rotated gathers).  The order is fixed, so the float sums over it are
+// deterministic.  One block.
+__global__ void __launch_bounds__(1024) k_mask_list(const float* __restrict__ mask, int L0, int L1, int L2,
+                                                    unsigned* __restrict__ list, float* __restrict__ mval,
+                                                    int* __restrict__ count) {
+  __shared__ int wsum[16];
+  __shared__ int base;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int B0 = (L0 + 3) / 4, B1 = (L1 + 3) / 4, B2 = (L2 + 3) / 4, nB = B0 * B1 * B2;
+  if (tid == 0) base = 0;
+  __syncthreads();
+  for (int t0 = 0; t0 < nB; t0 += 1024) {
+    const int br = t0 + tid;
+    unsigned long long bits = 0ull;
+    int b0 = 0, b1 = 0, b2 = 0;
+    if (br < nB) {
+      b2 = br % B2;
+      b1 = (br / B2) % B1;
+      b0 = br / (B1 * B2);
+      for (int j = 0; j < 64; ++j) {
+        const int u0 = 4 * b0 + (j >> 4), u1 = 4 * b1 + ((j >> 2) & 3), u2 = 4 * b2 + (j & 3);
+        if (u0 < L0 && u1 < L1 && u2 < L2 && mask[(u0 * L1 + u1) * L2 + u2] != 0.0f) bits |= 1ull << j;
+      }
+    }
+    const int cnt = __popcll(bits);
+    int incl = cnt;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off);
+      if (lane >= off) incl += v;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int off = base + incl - cnt;
+    for (int w = 0; w < wave; ++w) off += wsum[w];
+    for (int j = 0; j < 64; ++j) {
+      if ((bits >> j) & 1ull) {
+        const int u0 = 4 * b0 + (j >> 4), u1 = 4 * b1 + ((j >> 2) & 3), u2 = 4 * b2 + (j & 3);
+        list[off] = (unsigned)u0 | ((unsigned)u1 << 10) | ((unsigned)u2 << 20);
+        mval[off] = mask[(u0 * L1 + u1) * L2 + u2];
+        ++off;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int tot = 0;
+      for (int w = 0; w < 16; ++w) tot += wsum[w];
+      base += tot;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) count[0] = base;
+}
+
+// c(y, R(q_y)) = w(y) <tau_y f, s_R> for the rotation q_y found at voxel y
+// (Section 2, the normalised correlation of Algorithm 1, with s_R the raw
+// template rotated by R and normalised under the mask):
+//   <tau_y f, s_R> = (sum m g f - mu sum m f) / sqrt(sum m g^2 - mu sum m g),
+//   g = t_R sampled trilinearly (zero outside the box), mu = sum m g / sum m,
+//   f the image window.
+// Per-thread partial sums in float32 over the compacted mask voxels, the block
+// reduction and the normalisation in float64.  -inf outside the valid region;
+// 0 where w(y) = 0 or the rotated template has no masked variance.  One block
+// per (candidate, neighbour).
+__global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __restrict__ image,
+                                                  const float* __restrict__ tmpl, const unsigned* __restrict__ mlist,
+                                                  const float* __restrict__ mval,
+                                                  const int* __restrict__ mcount, const int* __restrict__ pos,
+                                                  const int* __restrict__ count_dev, int count_host, int NB,
+                                                  const double* __restrict__ wbuf, const int* __restrict__ okbuf,
+                                                  const float* __restrict__ qbuf, double* __restrict__ nccbuf) {
+  __shared__ double red[4][5];
+  const int b = blockIdx.x;
+  const int p = b / NB, k = b % NB;
+  const int count = count_dev ? count_dev[0] : count_host;
+  if (p >= count) return;
+  const int tid = threadIdx.x;
+  if (!okbuf[b]) {
+    if (tid == 0) nccbuf[b] = -INFINITY;
+    return;
+  }
+  const double w = wbuf[b];
+  if (!(w > 0.0)) {
+    if (tid == 0) nccbuf[b] = 0.0;
+    return;
+  }
+  int o0, o1, o2;
+  neighbour_offset(k, NB, o0, o1, o2);
+  const int x0 = pos[3 * p] + o0, x1 = pos[3 * p + 1] + o1, x2 = pos[3 * p + 2] + o2;
+  const int L0 = g.L0, L1 = g.L1, L2 = g.L2;
+  const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;
+  // okbuf: the window lies inside the image (valid region), no wrap needed
+  const float* __restrict__ base = image + ((long)(x0 - c0) * g.n1 + (x1 - c1)) * g.n2 + (x2 - c2);
+  const int rs1 = g.n2, rs0 = g.n1 * g.n2;       // window strides (< 2^31 elements)
+  const Rot R = quat_rot(qbuf + 4 * (long)b);
+  const int nm = mcount[0];
+  float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, v3 = 0.0f, v4 = 0.0f;   // m, m g, m g^2, m f, m g f
+  for (int i = tid; i < nm; i += 256) {
+    const unsigned pk = mlist[i];
+    const int u0 = (int)(pk & 1023u), u1 = (int)((pk >> 10) & 1023u), u2 = (int)(pk >> 20);
+    const float mv = mval[i];
+    const float gv = sample_rotated(tmpl, L0, L1, L2, R, u0, u1, u2);
+    const float fv = base[u0 * rs0 + u1 * rs1 + u2];
+    const float mg = mv * gv;
+    v0 += mv;
+    v1 += mg;
+    v2 += mg * gv;
+    v3 += mv * fv;
+    v4 += mg * fv;
+  }
+  double v[5] = {v0, v1, v2, v3, v4};
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+    for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off);
+  const int lane = tid & 63, wave = tid >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < 5; ++i) red[wave][i] = v[i];
+  __syncthreads();
+  if (tid == 0) {
+    double t[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) t[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+    const double mu = t[0] > 0.0 ? t[1] / t[0] : 0.0;
+    const double var = t[2] - mu * t[1];
+    nccbuf[b] = var > 1e-6 * (t[2] > 0.0 ? t[2] : 1.0) ? w * (t[4] - mu * t[3]) / sqrt(var) : 0.0;
+  }
+}
+
+// The same NCC with the template held in LDS: one 1024-thread block per
+// (candidate, group of kNccGroup neighbours) loads the template once and
+// evaluates the group's neighbours one after another, sampling trilinearly
+// from LDS without branches (corners outside the box get weight 0 and read
+// element 0).  LDS layout: row pitch P2 = L2 + 3 and plane pitch
+// P01 = L1 P2 + 5 (for L = 32 the banks see j2 + 35 j1 + 37 j0 mod 64 rather
+// than only j2 and the parity of j1); with the 4x4x4 brick order of the mask
+// voxels this cuts the distinct addresses per bank of a wave's gather about
+// fourfold.  The layout must fit kNccLdsCap floats.
+constexpr int kNccLdsCap = 36864;
+constexpr int kNccGroup = 9;
+__host__ __device__ constexpr long ncc_lds_floats(int L0, int L1, int L2) {
+  return (long)L0 * ((long)L1 * (L2 + 3) + 5);
+}
+__device__ __forceinline__ float sample_rotated_lds(const float* t, int L0, int L1, int L2, int P2, int P01,
+                                                    const Rot& R, int u0, int u1, int u2) {
+  const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;
+  const float v0 = (float)(u0 - c0), v1 = (float)(u1 - c1), v2 = (float)(u2 - c2);
+  const float p0 = c0 + R.r[0] * v0 + R.r[3] * v1 + R.r[6] * v2;
+  const float p1 = c1 + R.r[1] * v0 + R.r[4] * v1 + R.r[7] * v2;
+  const float p2 = c2 + R.r[2] * v0 + R.r[5] * v1 + R.r[8] * v2;
+  const float f0 = floorf(p0), f1 = floorf(p1), f2 = floorf(p2);
+  const int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
+  const float w0 = p0 - f0, w1 = p1 - f1, w2 = p2 - f2;
+  float a[2], b[2], c[2];
+  int j0[2], j1[2], j2[2];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    const bool ok0 = (unsigned)(i0 + d) < (unsigned)L0, ok1 = (unsigned)(i1 + d) < (unsigned)L1,
+               ok2 = (unsigned)(i2 + d) < (unsigned)L2;
+    a[d] = ok0 ? (d ? w0 : 1.0f - w0) : 0.0f;
+    b[d] = ok1 ? (d ? w1 : 1.0f - w1) : 0.0f;
+    c[d] = ok2 ? (d ? w2 : 1.0f - w2) : 0.0f;
+    j0[d] = ok0 ? (i0 + d) * P01 : 0;
+    j1[d] = ok1 ? (i1 + d) * P2 : 0;
+    j2[d] = ok2 ? i2 + d : 0;
+  }
+  float acc = 0.0f;
+#pragma unroll
+  for (int d0 = 0; d0 < 2; ++d0)
+#pragma unroll
+    for (int d1 = 0; d1 < 2; ++d1) {
+      const float ab = a[d0] * b[d1];
+      const int r = j0[d0] + j1[d1];
+      acc += ab * (c[0] * t[r + j2[0]] + c[1] * t[r + j2[1]]);
+    }
+  return acc;
+}
+
+__global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, const float* __restrict__ image,
+                                                       const float* __restrict__ tmpl,
+                                                       const unsigned* __restrict__ mlist,
+                                                       const float* __restrict__ mval,
+                                                       const int* __restrict__ mcount, const int* __restrict__ pos,
+                                                       const int* __restrict__ count_dev, int count_host,
+                                                       const double* __restrict__ wbuf,
+                                                       const int* __restrict__ okbuf, const float* __restrict__ qbuf,
+                                                       double* __restrict__ nccbuf) {
+  __shared__ float tl[kNccLdsCap];
+  __shared__ double red[16][5];
+  constexpr int NB = 27;
+  const int ngroups = NB / kNccGroup;
+  const int p = blockIdx.x / ngroups, grp = blockIdx.x % ngroups;
+  const int count = count_dev ? count_dev[0] : count_host;
+  if (p >= count) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int L0 = g.L0, L1 = g.L1, L2 = g.L2, nL = L0 * L1 * L2;
+  const int P2 = L2 + 3, P01 = L1 * P2 + 5;
+  for (int i = tid; i < nL; i += 1024) {
+    const int i2 = i % L2, i1 = (i / L2) % L1, i0 = i / (L1 * L2);
+    tl[i0 * P01 + i1 * P2 + i2] = tmpl[i];
+  }
+  __syncthreads();
+  const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;
+  const int rs1 = g.n2, rs0 = g.n1 * g.n2;
+  const int nm = mcount[0];
+  for (int kk = 0; kk < kNccGroup; ++kk) {
+    const int k = grp * kNccGroup + kk;
+    const long b = (long)p * NB + k;
+    // block-uniform: the neighbour's validity and w
+    if (!okbuf[b]) {
+      if (tid == 0) nccbuf[b] = -INFINITY;
+      continue;
+    }
+    const double w = wbuf[b];
+    if (!(w > 0.0)) {
+      if (tid == 0) nccbuf[b] = 0.0;
+      continue;
+    }
+    int o0, o1, o2;
+    neighbour_offset(k, NB, o0, o1, o2);
+    const int x0 = pos[3 * p] + o0, x1 = pos[3 * p + 1] + o1, x2 = pos[3 * p + 2] + o2;
+    const float* __restrict__ base = image + ((long)(x0 - c0) * g.n1 + (x1 - c1)) * g.n2 + (x2 - c2);
+    const Rot R = quat_rot(qbuf + 4 * b);
+    float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, v3 = 0.0f, v4 = 0.0f;
+    for (int i = tid; i < nm; i += 1024) {
+      const unsigned pk = mlist[i];
+      const int u0 = (int)(pk & 1023u), u1 = (int)((pk >> 10) & 1023u), u2 = (int)(pk >> 20);
+      const float mv = mval[i];
+      const float gv = sample_rotated_lds(tl, L0, L1, L2, P2, P01, R, u0, u1, u2);
+      const float fv = base[u0 * rs0 + u1 * rs1 + u2];
+      const float mg = mv * gv;
+      v0 += mv;
+      v1 += mg;
+      v2 += mg * gv;
+      v3 += mv * fv;
+      v4 += mg * fv;
+    }
+    double v[5] = {v0, v1, v2, v3, v4};
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+      for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off);
+    if (lane == 0)
+#pragma unroll
+      for (int i = 0; i < 5; ++i) red[wave][i] = v[i];
+    __syncthreads();
+    if (tid == 0) {
+      double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int wv = 0; wv < 16; ++wv)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) t[i] += red[wv][i];
+      const double mu = t[0] > 0.0 ? t[1] / t[0] : 0.0;
+      const double var = t[2] - mu * t[1];
+      nccbuf[b] = var > 1e-6 * (t[2] > 0.0 ? t[2] : 1.0) ? w * (t[4] - mu * t[3]) / sqrt(var) : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+// per candidate: the neighbour with the largest dominant Z-eigenvalue
+// (refine 1) or with the largest NCC at its own dominant rotation (refine 2);
+// the centre first on ties, then the lower neighbour index
 __global__ void k_pose_pick(PoseGeo g, const float* __restrict__ score, int K, const int* __restrict__ pos_in,
                             const int* __restrict__ count_dev, int count_host, int NB,
                             const double* __restrict__ Cbuf, const double* __restrict__ wbuf,
                             const float* __restrict__ qbuf, const double* __restrict__ lambuf,
-                            const int* __restrict__ flagbuf, int* __restrict__ out_pos,
-                            float* __restrict__ out_quat, double* __restrict__ out_lambda,
-                            float* __restrict__ out_score, int* __restrict__ out_flags,
-                            double* __restrict__ out_C) {
+                            const double* __restrict__ keybuf, const int* __restrict__ flagbuf,
+                            int* __restrict__ out_pos, float* __restrict__ out_quat,
+                            double* __restrict__ out_lambda, float* __restrict__ out_score,
+                            int* __restrict__ out_flags, double* __restrict__ out_C) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int count = count_dev ? count_dev[0] : count_host;
   if (p >= count) return;
   const int centre = NB == 27 ? 13 : 0;
   int bk = centre;
-  double bl = lambuf[(long)p * NB + centre];
+  double bv = keybuf[(long)p * NB + centre];
   for (int k = 0; k < NB; ++k) {
-    const double v = lambuf[(long)p * NB + k];
-    if (v > bl) {
-      bl = v;
+    const double v = keybuf[(long)p * NB + k];
+    if (v > bv) {
+      bv = v;
       bk = k;
     }
   }
   const long b = (long)p * NB + bk;
+  const double bl = lambuf[b];
   int o0, o1, o2;
   neighbour_offset(bk, NB, o0, o1, o2);
   const int x0 = pos_in[3 * p] + o0, x1 = pos_in[3 * p + 1] + o1, x2 = pos_in[3 * p + 2] + o2;
@@ -900,9 +1164,9 @@ hipError_t launch_pose_tensor(const Geo& gg, const float* image, const float* co
 
 hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int n_seeds, int max_iter,
                              double tol, int max_peaks, int refine, const int* pos_in, const int* count_dev,
-                             int count_host, int* out_pos, float* out_quat, double* out_lambda,
-                             float* out_score, int* out_flags, double* out_C, const PoseScratch& ps,
-                             hipStream_t s) {
+                             int count_host, const float* image, const float* tmpl, const float* mask,
+                             int* out_pos, float* out_quat, double* out_lambda, float* out_score, int* out_flags,
+                             double* out_C, const PoseScratch& ps, hipStream_t s) {
   const PoseGeo g = make_posegeo(gg);
   const int K = num_components(order_n);
   const int NB = refine ? 27 : 1;
@@ -919,9 +1183,20 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
                                n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags); break;
     default: return hipErrorInvalidValue;
   }
+  if (refine == 2) {
+    hipLaunchKernelGGL(k_mask_list, dim3(1), dim3(1024), 0, s, mask, g.L0, g.L1, g.L2, ps.mlist, ps.mval,
+                       ps.mcount);
+    if (ncc_lds_floats(g.L0, g.L1, g.L2) <= kNccLdsCap)
+      hipLaunchKernelGGL(k_pose_ncc_lds, dim3((unsigned)(max_peaks * (27 / kNccGroup))), dim3(1024), 0, s, g,
+                         image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in, count_dev, count_host, ps.w, ps.ok,
+                         ps.q, ps.ncc);
+    else
+      hipLaunchKernelGGL(k_pose_ncc, eg, dim3(256), 0, s, g, image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in,
+                         count_dev, count_host, NB, ps.w, ps.ok, ps.q, ps.ncc);
+  }
   hipLaunchKernelGGL(k_pose_pick, dim3((max_peaks + 63) / 64), dim3(64), 0, s, g, score, K, pos_in, count_dev,
-                     count_host, NB, ps.C, ps.w, ps.q, ps.lam, ps.flags, out_pos, out_quat, out_lambda,
-                     out_score, out_flags, out_C);
+                     count_host, NB, ps.C, ps.w, ps.q, ps.lam, refine == 2 ? ps.ncc : ps.lam, ps.flags, out_pos,
+                     out_quat, out_lambda, out_score, out_flags, out_C);
   return hipGetLastError();
 }
 

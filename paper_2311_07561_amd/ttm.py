@@ -65,12 +65,13 @@ _SIGS = {
     "ttm_correlate_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32]),
     "ttm_correlate": (_I32, [_P, _DIMS, _P, _DIMS, _I32, _P, _OPTP, _P, _P, _P, _SZ, _P]),
     "ttm_pose_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32, _OPTP]),
-    "ttm_recover_pose": (_I32, [_P, _P, _P, _P, _DIMS, _DIMS, _I32, _OPTP, _P, _P, _P, _P, _P, _P, _P,
+    "ttm_recover_pose": (_I32, [_P, _P, _P, _P, _P, _DIMS, _DIMS, _I32, _OPTP, _P, _P, _P, _P, _P, _P, _P,
                                 _P, _SZ, _P]),
-    "ttm_pose_at": (_I32, [_P, _P, _P, _DIMS, _DIMS, _I32, _OPTP, _P, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "ttm_pose_at": (_I32, [_P, _P, _P, _P, _DIMS, _DIMS, _I32, _OPTP, _P, _I32, _P, _P, _P, _P, _P, _P, _SZ,
+                           _P]),
     "ttm_match_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32, _OPTP]),
-    "ttm_match": (_I32, [_P, _DIMS, _P, _DIMS, _I32, _P, _OPTP, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ,
-                         _P]),
+    "ttm_match": (_I32, [_P, _DIMS, _P, _DIMS, _I32, _P, _P, _OPTP, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                         _SZ, _P]),
     "tm_classical_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32]),
     "tm_classical": (_I32, [_P, _DIMS, _P, _P, _DIMS, _P, _I32, _OPTP, _P, _P, _P, _SZ, _P]),
     "ttm_profile_enable": (None, [_I32]),
@@ -230,10 +231,16 @@ def correlate_workspace(image_shape, L, order, device) -> torch.Tensor:
     return _workspace(lib().ttm_correlate_workspace_bytes(_dims(image_shape), _dims(L), K), device)
 
 
+def _opt_dev(t, name):
+    return None if t is None else _dev(t, name)
+
+
 def recover_pose(score: torch.Tensor, image: torch.Tensor, components: torch.Tensor,
-                 mask: torch.Tensor, order: int, opt: Options | None = None, want_C: bool = True):
+                 mask: torch.Tensor, order: int, opt: Options | None = None, want_C: bool = True,
+                 tmpl: torch.Tensor | None = None):
     """Peaks of F and the dominant Z-eigenpair of C_n at each.  Returns a dict
-    of device tensors trimmed to the number of peaks found (one sync)."""
+    of device tensors trimmed to the number of peaks found (one sync).  The raw
+    template ``tmpl`` is needed with ``opt.refine == 2``."""
     dev = score.device
     K = num_components(order)
     N = _dims(score.shape)
@@ -250,7 +257,8 @@ def recover_pose(score: torch.Tensor, image: torch.Tensor, components: torch.Ten
     nws = lib().ttm_pose_workspace_bytes(N, L, order, ctypes.byref(opt))
     ws = _workspace(nws, dev)
     st = lib().ttm_recover_pose(_dev(score, "score"), _dev(image, "image"), _dev(components, "components"),
-                                _dev(mask, "mask"), N, L, order, ctypes.byref(opt), pos.data_ptr(),
+                                _dev(mask, "mask"), _opt_dev(tmpl, "tmpl"), N, L, order, ctypes.byref(opt),
+                                pos.data_ptr(),
                                 quat.data_ptr(), lam.data_ptr(), pscore.data_ptr(), flags.data_ptr(),
                                 C.data_ptr() if C is not None else None, count.data_ptr(), ws.data_ptr(),
                                 nws, _stream(dev))
@@ -265,7 +273,7 @@ def recover_pose(score: torch.Tensor, image: torch.Tensor, components: torch.Ten
 
 
 def pose_at(image: torch.Tensor, components: torch.Tensor, mask: torch.Tensor, order: int, positions,
-            opt: Options | None = None, want_C: bool = True) -> dict:
+            opt: Options | None = None, want_C: bool = True, tmpl: torch.Tensor | None = None) -> dict:
     """Dominant Z-eigenpair of C_n at caller-given positions (P, 3)."""
     dev = image.device
     K = num_components(order)
@@ -284,8 +292,8 @@ def pose_at(image: torch.Tensor, components: torch.Tensor, mask: torch.Tensor, o
     C = torch.zeros((P, K), dtype=torch.float64, device=dev) if want_C else None
     nws = lib().ttm_pose_workspace_bytes(N, L, order, ctypes.byref(opt))
     ws = _workspace(nws, dev)
-    st = lib().ttm_pose_at(_dev(image, "image"), _dev(components, "components"), _dev(mask, "mask"), N, L,
-                           order, ctypes.byref(opt), pos.data_ptr(), P, out_pos.data_ptr(), quat.data_ptr(),
+    st = lib().ttm_pose_at(_dev(image, "image"), _dev(components, "components"), _dev(mask, "mask"),
+                           _opt_dev(tmpl, "tmpl"), N, L, order, ctypes.byref(opt), pos.data_ptr(), P, out_pos.data_ptr(), quat.data_ptr(),
                            lam.data_ptr(), flags.data_ptr(), C.data_ptr() if C is not None else None,
                            ws.data_ptr(), nws, _stream(dev))
     _check(st, "ttm_pose_at")
@@ -318,7 +326,8 @@ class PoseBuffers:
 
 
 def recover_pose_async(score: torch.Tensor, image: torch.Tensor, components: torch.Tensor,
-                       mask: torch.Tensor, order: int, opt: Options, bufs: PoseBuffers):
+                       mask: torch.Tensor, order: int, opt: Options, bufs: PoseBuffers,
+                       tmpl: torch.Tensor | None = None):
     """``recover_pose`` into preallocated buffers, without synchronising."""
     dev = score.device
     N = _dims(score.shape)
@@ -327,7 +336,8 @@ def recover_pose_async(score: torch.Tensor, image: torch.Tensor, components: tor
     if bufs.ws.numel() < nws:
         bufs.ws = _workspace(nws, dev)
     st = lib().ttm_recover_pose(_dev(score, "score"), _dev(image, "image"), _dev(components, "components"),
-                                _dev(mask, "mask"), N, L, order, ctypes.byref(opt), bufs.pos.data_ptr(),
+                                _dev(mask, "mask"), _opt_dev(tmpl, "tmpl"), N, L, order, ctypes.byref(opt),
+                                bufs.pos.data_ptr(),
                                 bufs.quat.data_ptr(), bufs.lam.data_ptr(), bufs.score.data_ptr(),
                                 bufs.flags.data_ptr(), bufs.C.data_ptr(), bufs.count.data_ptr(),
                                 bufs.ws.data_ptr(), bufs.ws.numel(), _stream(dev))
@@ -355,14 +365,15 @@ class MatchBuffers(PoseBuffers):
 
 
 def match(image: torch.Tensor, bank: torch.Tensor, mask: torch.Tensor, order: int, opt: Options,
-          bufs: MatchBuffers):
+          bufs: MatchBuffers, tmpl: torch.Tensor | None = None):
     """Correlation, peaks and poses in one asynchronous call (ttm_match);
-    results land in ``bufs`` (score map in bufs.score, w in bufs.w)."""
+    results land in ``bufs`` (score map in bufs.score, w in bufs.w).  The raw
+    template ``tmpl`` is needed with ``opt.refine == 2``."""
     dev = image.device
     N = _dims(image.shape)
     L = _dims(mask.shape)
     st = lib().ttm_match(_dev(image, "image"), N, bank.data_ptr(), L, order, _dev(mask, "mask"),
-                         ctypes.byref(opt), bufs.score.data_ptr(), bufs.w.data_ptr(), bufs.pos.data_ptr(),
+                         _opt_dev(tmpl, "tmpl"), ctypes.byref(opt), bufs.score.data_ptr(), bufs.w.data_ptr(), bufs.pos.data_ptr(),
                          bufs.quat.data_ptr(), bufs.lam.data_ptr(), bufs.peak_score.data_ptr(),
                          bufs.flags.data_ptr(), bufs.C.data_ptr(), bufs.count.data_ptr(), bufs.ws.data_ptr(),
                          bufs.ws.numel(), _stream(dev))

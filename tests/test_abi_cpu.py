@@ -79,23 +79,34 @@ def test_argument_validation_without_gpu():
     assert L.ttm_build_tensor_template(fake, fake, T, 2, q, w2, 2, fake, N, None, None, 0, None) == -3
     # pose options
     bad = _opt(max_peaks=0)
-    args = [fake] * 4 + [N, T, 4, ctypes.byref(bad)] + [fake] * 7 + [fake, big, None]
+    args = [fake] * 5 + [N, T, 4, ctypes.byref(bad)] + [fake] * 7 + [fake, big, None]
     assert L.ttm_recover_pose(*args) == -1
     bad = _opt(n_seeds=8)
-    args[7] = ctypes.byref(bad)
+    args[8] = ctypes.byref(bad)
     assert L.ttm_recover_pose(*args) == -1
     bad = _opt(threshold=-1.0)
-    args[7] = ctypes.byref(bad)
+    args[8] = ctypes.byref(bad)
     assert L.ttm_recover_pose(*args) == -1
+    bad = _opt(refine=3)
+    args[8] = ctypes.byref(bad)
+    assert L.ttm_recover_pose(*args) == -1
+    # refine 2 needs the raw template
     bad = _opt(refine=2)
-    args[7] = ctypes.byref(bad)
+    args[8] = ctypes.byref(bad)
+    args[4] = None
     assert L.ttm_recover_pose(*args) == -1
     # pose at given positions: more positions than max_peaks
     ok = _opt(max_peaks=2)
-    assert L.ttm_pose_at(fake, fake, fake, N, T, 4, ctypes.byref(ok), fake, 3, fake, fake, fake, fake, None,
-                         fake, big, None) == -1
-    assert L.ttm_pose_at(fake, fake, fake, N, T, 4, ctypes.byref(ok), fake, 2, fake, fake, fake, fake, None,
-                         fake, 16, None) == -3
+    assert L.ttm_pose_at(fake, fake, fake, None, N, T, 4, ctypes.byref(ok), fake, 3, fake, fake, fake, fake,
+                         None, fake, big, None) == -1
+    assert L.ttm_pose_at(fake, fake, fake, None, N, T, 4, ctypes.byref(ok), fake, 2, fake, fake, fake, fake,
+                         None, fake, 16, None) == -3
+    r2 = _opt(max_peaks=2, refine=2)
+    assert L.ttm_pose_at(fake, fake, fake, None, N, T, 4, ctypes.byref(r2), fake, 2, fake, fake, fake, fake,
+                         None, fake, big, None) == -1
+    # match: refine 2 without the template
+    assert L.ttm_match(fake, N, fake, T, 4, fake, None, ctypes.byref(r2), fake, None, fake, fake, fake, fake,
+                       fake, None, fake, fake, big, None) == -1
     # classical
     assert L.tm_classical(fake, N, fake, fake, T, q, 0, ctypes.byref(o), fake, fake, fake, big, None) == -1
     assert L.tm_classical(fake, N, fake, fake, T, q0, 2, ctypes.byref(o), fake, fake, fake, big, None) == -1

@@ -266,7 +266,43 @@ def test_pose_at_given_positions_and_refinement():
         assert abs(rr["lam"].cpu().numpy()[i] - lams[k]) <= 1e-6 * abs(lams[k]) + 1e-9
 
 
-@pytest.mark.parametrize("refine", [0, 1])
+def test_pose_at_refinement_by_ncc():
+    """refine = 2: each of the 27 voxels gets its own dominant rotation and the
+    NCC of the image window against the template rotated by it; the voxel with
+    the largest NCC is reported (oracle: refine_by_ncc)."""
+    img, tmpl, mask, q, w = rand_setup(61, (32, 32, 32), (8, 8, 8), 4.0, 64)
+    n = 4
+    s = O.rotated_template(tmpl, mask, q[9])
+    sl = tuple(slice(15 - 4, 15 + 4) for _ in range(3))
+    img[sl] += 1.5 * np.sqrt(mask.sum()) * s.astype(np.float32)
+    comps, _ = ttm.build_tensor_template(dev(tmpl), dev(mask), n, q, w)
+    T = oracle_T(tmpl, mask, n, q, w)
+    f64, t64, m64 = img.astype(np.float64), tmpl.astype(np.float64), mask.astype(np.float64)
+    xs = np.array([[16, 15, 14], [10, 20, 12]], dtype=np.int32)
+    opt = ttm.default_options(max_peaks=2, refine=2)
+    with pytest.raises(ttm.TTMError):
+        ttm.pose_at(dev(img), comps, dev(mask), n, xs, opt)          # refine 2 needs the template
+    rr = ttm.pose_at(dev(img), comps, dev(mask), n, xs, opt, tmpl=dev(tmpl))
+    offs = O.neighbourhood_offsets()
+    for i in range(len(xs)):
+        pos, qo, lo, ncc, nccs = O.refine_by_ncc(f64, t64, m64, T, n, xs[i], n_brute=30000)
+        got = rr["pos"].cpu().numpy()[i]
+        k = int(np.argmax([(np.asarray(got) - xs[i] == o).all() for o in offs]))
+        srt = np.sort(nccs)[::-1]
+        if srt[0] - srt[1] > 1e-4:
+            assert np.array_equal(got, pos), (i, got, pos, srt[:3])
+        # the reported voxel's NCC (oracle, at the oracle's rotation there) is the largest
+        assert nccs[k] >= srt[0] - 1e-4
+        C_k = O.tensor_field_at(f64, T, m64, np.asarray(got)[None])[0]
+        qk, lk, second = O.dominant_z_eigenpair(C_k, n, n_brute=30000)
+        assert abs(rr["lam"].cpu().numpy()[i] - lk) <= 1e-6 * abs(lk) + 1e-9
+        if second < lk - 1e-3 * abs(lk):
+            assert O.rotation_angle_deg(rr["quat"].cpu().numpy()[i], qk) <= 1.0
+    # the planted copy is found from one voxel off
+    assert np.array_equal(rr["pos"].cpu().numpy()[0], [15, 15, 15])
+
+
+@pytest.mark.parametrize("refine", [0, 1, 2])
 def test_match_uses_the_correlated_field(refine):
     """ttm_match: the same score map and peaks as ttm_correlate + peak picking,
     C_n at the peaks read from the correlated field (float32 FFT precision)
@@ -280,7 +316,7 @@ def test_match_uses_the_correlated_field(refine):
     img = dev(wl.image)
     opt = ttm.default_options(max_peaks=6, min_dist=8.0, refine=refine)
     bufs = ttm.MatchBuffers(wl.image.shape, wl.template.shape, n, opt, "cuda")
-    ttm.match(img, bank, dev(wl.mask), n, opt, bufs)
+    ttm.match(img, bank, dev(wl.mask), n, opt, bufs, tmpl=dev(wl.template))
     res = bufs.result()
     score, _ = ttm.correlate(img, bank, dev(wl.mask), n)
     assert torch.equal(score, bufs.score)
@@ -305,12 +341,21 @@ def test_match_uses_the_correlated_field(refine):
         assert abs(lam[i] - lo) <= 2e-4 * abs(lo)
         if second < lo - 1e-2 * abs(lo):
             assert O.rotation_angle_deg(quats[i], qo) <= 1.0
-    if refine:
+    if refine == 1:
         # the reported neighbour maximises the eigenvalue among the 27 (oracle,
         # up to the float32 field precision)
         for i in range(min(3, len(got))):
             pos, _, lo, lams = O.refine_by_eigenvalue(f64, T, m64, n, cand[i], n_brute=50000)
             assert lam[i] >= np.max(lams) - 2e-4 * abs(np.max(lams))
+    if refine == 2:
+        # the reported neighbour maximises the NCC at its own rotation (oracle,
+        # up to the float32 field precision of the rotations)
+        t64 = wl.template.astype(np.float64)
+        offs = O.neighbourhood_offsets()
+        for i in range(min(2, len(got))):
+            pos, _, _, ncc, nccs = O.refine_by_ncc(f64, t64, m64, T, n, cand[i], n_brute=30000)
+            k = int(np.argmax([(got[i] - cand[i] == o).all() for o in offs]))
+            assert nccs[k] >= ncc - 2e-3, (i, got[i], pos, nccs[k], ncc)
 
 
 @pytest.mark.parametrize("min_dist,max_peaks", [(12.0, 40), (4.0, 300), (30.0, 8)])
