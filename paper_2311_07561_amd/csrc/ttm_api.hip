@@ -150,6 +150,8 @@ static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refi
   w.ps.mlist = c.take<unsigned>((size_t)g.L0 * g.L1 * g.L2);
   w.ps.mval = c.take<float>((size_t)g.L0 * g.L1 * g.L2);
   w.ps.mcount = c.take<int>(1);
+  w.ps.sbest = c.take<double>(nb * 64);
+  w.ps.sidx = c.take<int>(nb * 64);
   return w;
 }
 

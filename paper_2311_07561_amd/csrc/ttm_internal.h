@@ -146,6 +146,8 @@ struct PoseScratch {
   unsigned* mlist;  // L0 L1 L2: packed coordinates of the mask voxels (refine 2)
   float* mval;      // L0 L1 L2: their mask values
   int* mcount;      // 1: their number
+  double* sbest;    // max_peaks * NB * 64: seed scan, best lambda per slot
+  int* sidx;        // max_peaks * NB * 64: and its seed index
 };
 // C_n(x) in float64 by direct window sums at max_peaks candidates (count from
 // count_dev if non-null, else count_host), at the 27 neighbours if refine

@@ -13,6 +13,8 @@
 // (eq. "Zeigen"; Theorem "main") is found from a scan of S^3 seed points and
 // a shifted power iteration (SS-HOPM) accelerated by safeguarded Newton steps
 // on the sphere, from the 4 best mutually distant seeds.
+#include <algorithm>
+
 #include "ttm_device.h"
 #include "ttm_internal.h"
 #include "ttm_rotate.h"
@@ -323,48 +325,6 @@ __global__ void k_seed_table(int n, double* __restrict__ seeds) {
   if (i < n) seed_point(i, n, seeds + 4 * i);
 }
 
-// Solve H xi = rhs (4x4) by Gaussian elimination with partial pivoting.
-__device__ __forceinline__ bool solve4(double (&H)[4][4], double* rhs) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    int piv = c;
-    double best = fabs(H[c][c]);
-#pragma unroll
-    for (int r = c + 1; r < 4; ++r)
-      if (fabs(H[r][c]) > best) {
-        best = fabs(H[r][c]);
-        piv = r;
-      }
-    if (!(best > 1e-300)) return false;
-    if (piv != c) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double t = H[c][k];
-        H[c][k] = H[piv][k];
-        H[piv][k] = t;
-      }
-      const double t = rhs[c];
-      rhs[c] = rhs[piv];
-      rhs[piv] = t;
-    }
-#pragma unroll
-    for (int r = c + 1; r < 4; ++r) {
-      const double f = H[r][c] / H[c][c];
-#pragma unroll
-      for (int k = c; k < 4; ++k) H[r][k] -= f * H[c][k];
-      rhs[r] -= f * rhs[c];
-    }
-  }
-#pragma unroll
-  for (int c = 3; c >= 0; --c) {
-    double s = rhs[c];
-#pragma unroll
-    for (int k = c + 1; k < 4; ++k) s -= H[c][k] * rhs[k];
-    rhs[c] = s / H[c][c];
-  }
-  return true;
-}
-
 // 256-thread sum of kTensorChunk values per thread (wave shuffles, then LDS)
 __device__ __forceinline__ void block_sum_chunk(double* v, int kc, double* sh /* 4 * kTensorChunk */) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -482,11 +442,9 @@ __global__ void __launch_bounds__(256) k_pose_tensor(PoseGeo g, const float* __r
 
 constexpr int hidx(int i, int j) { return i * 4 - i * (i - 1) / 2 + (j - i); }   // upper triangle, i <= j
 
-// Per-wave LDS tables of the eigen-solver: the packed tensor entries C and
-// mu * C (mu the multiplicities).
+// Per-wave LDS table of the eigen-solver: the packed tensor entries C.
 struct EigLds {
   double C[kMaxK];
-  double muA[kMaxK];
 };
 
 // compile-time packed multi-indices, in the order of alpha_of_dev
@@ -544,22 +502,6 @@ __device__ __forceinline__ double eval_lambda(const double* __restrict__ muA, co
     l += muA[decltype(kk)::value] * (pw[0][A.a[0]] * pw[1][A.a[1]]) * (pw[2][A.a[2]] * pw[3][A.a[3]]);
   });
   return l;
-}
-
-// every lane scans a strided share of the seed table; returns the lane's best
-template <int N>
-__device__ __forceinline__ void seed_scan(const double* __restrict__ muA, const double* __restrict__ seeds,
-                                          int n_seeds, int lane, double& best, int& bseed) {
-  best = -INFINITY;
-  bseed = 0;
-  for (int sd = lane; sd < n_seeds; sd += 64) {
-    const double q[4] = {seeds[4 * sd], seeds[4 * sd + 1], seeds[4 * sd + 2], seeds[4 * sd + 3]};
-    const double v = eval_lambda<N>(muA, q);
-    if (v > best) {
-      best = v;
-      bseed = sd;
-    }
-  }
 }
 
 // H = A x^{n-2} (upper triangle), g = A x^{n-1} = H x and lambda = A x^n = x . g
@@ -625,8 +567,65 @@ __device__ __forceinline__ double fact_d(int n) {
   return f;
 }
 
-// Dominant Z-eigenpair of one packed tensor per wavefront: every lane scans a
-// strided share of the S^3 seed points; the kStarts best mutually distant lane seeds
+// Seed scan of the eigen-solver, one 256-thread block per tensor: lambda(s) =
+// sum_alpha mu_alpha C_alpha s^alpha at every S^3 seed point s; for each of
+// 64 slots l the largest value over the seeds s = l mod 64 and its seed index
+// (the lowest index on ties).  Thread t scans the seeds t, t + 256, ...; the
+// four threads t = l mod 64 are then merged.
+template <int N>
+__global__ void __launch_bounds__(256) k_seed_scan(const double* __restrict__ seeds,
+                                                   const double* __restrict__ Cbuf,
+                                                   const int* __restrict__ okbuf, const int* __restrict__ count_dev,
+                                                   int count_host, int NB, int n_seeds,
+                                                   double* __restrict__ slot_best, int* __restrict__ slot_idx) {
+  constexpr int K = (N + 1) * (N + 2) * (N + 3) / 6;
+  __shared__ double muA[K];
+  __shared__ double rb[256];
+  __shared__ int ri[256];
+  const int b = blockIdx.x;
+  const int p = b / NB;
+  const int count = count_dev ? count_dev[0] : count_host;
+  if (p >= count || !okbuf[b]) return;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < K; k += 256) {
+    int al[4];
+    alpha_of_dev(N, k, al);
+    double mu = fact_d(N);
+    for (int d = 0; d < 4; ++d) mu /= fact_d(al[d]);
+    muA[k] = mu * Cbuf[(long)b * K + k];
+  }
+  __syncthreads();
+  double best = -INFINITY;
+  int bseed = 0;
+  for (int sd = tid; sd < n_seeds; sd += 256) {
+    const double q[4] = {seeds[4 * sd], seeds[4 * sd + 1], seeds[4 * sd + 2], seeds[4 * sd + 3]};
+    const double v = eval_lambda<N>(muA, q);
+    if (v > best) {
+      best = v;
+      bseed = sd;
+    }
+  }
+  rb[tid] = best;
+  ri[tid] = bseed;
+  __syncthreads();
+  if (tid < 64) {
+    double bv = rb[tid];
+    int bi = ri[tid];
+    for (int j = 1; j < 4; ++j) {
+      const double v = rb[tid + 64 * j];
+      const int i = ri[tid + 64 * j];
+      if (v > bv || (v == bv && v > -INFINITY && i < bi)) {
+        bv = v;
+        bi = i;
+      }
+    }
+    slot_best[(long)b * 64 + tid] = bv;
+    slot_idx[(long)b * 64 + tid] = bi;
+  }
+}
+
+// Dominant Z-eigenpair of one packed tensor per wavefront: lane l takes the
+// best seed of slot l from the seed scan; the kStarts best mutually distant lane seeds
 // are polished by SS-HOPM (shifted power iteration) accelerated with Newton
 // steps on the sphere: a Newton step is taken when it is an ascent direction
 // and a backtracking search along it raises lambda, otherwise the shifted
@@ -636,7 +635,8 @@ template <int N>
 __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seeds,
                                                  const double* __restrict__ Cbuf,
                                                  const int* __restrict__ okbuf, const int* __restrict__ count_dev,
-                                                 int count_host, int NB, int n_seeds, int max_iter, double tol,
+                                                 int count_host, int NB, const double* __restrict__ slot_best,
+                                                 const int* __restrict__ slot_idx, int max_iter, double tol,
                                                  float* __restrict__ qbuf, double* __restrict__ lambuf,
                                                  int* __restrict__ flagbuf) {
   constexpr int n = N;
@@ -655,20 +655,11 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
     }
     return;
   }
-  for (int k = lane; k < K; k += 64) {
-    int al[4];
-    alpha_of_dev(n, k, al);
-    double mu = fact_d(n);
-    for (int d = 0; d < 4; ++d) mu /= fact_d(al[d]);
-    const double c = Cbuf[(long)b * K + k];
-    t.C[k] = c;
-    t.muA[k] = mu * c;
-  }
+  for (int k = lane; k < K; k += 64) t.C[k] = Cbuf[(long)b * K + k];
   __syncthreads();
-  // seed scan: every lane keeps the best of its strided share
-  double best;
-  int bseed;
-  seed_scan<N>(t.muA, seeds, n_seeds, lane, best, bseed);
+  // the seed scan's best seed of this lane's slot
+  const double best = slot_best[(long)b * 64 + lane];
+  const int bseed = slot_idx[(long)b * 64 + lane];
   // the kStarts best lane seeds that are mutually more than 10 degrees apart
   // (|<q, q'>| < cos 5 deg) start the polish
   red[lane * 6 + 0] = best;
@@ -721,13 +712,11 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
           M[i][j] = nn1 * Hm[hidx(i, j)];
           M[j][i] = M[i][j];
         }
-      double grad[4], Mx[4], xMx = 0.0, gnorm = 0.0;
+      double gnorm = 0.0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        grad[i] = n * (gv[i] - lam * x[i]);
-        gnorm += grad[i] * grad[i];
-        Mx[i] = M[i][0] * x[0] + M[i][1] * x[1] + M[i][2] * x[2] + M[i][3] * x[3];
-        xMx += x[i] * Mx[i];
+        const double gr = n * (gv[i] - lam * x[i]);
+        gnorm += gr * gr;
       }
       gnorm = sqrt(gnorm);
       const double scale = fmax(1.0, fabs(lam));
@@ -735,19 +724,78 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
         conv = true;
         break;
       }
-      // Newton direction on the sphere: (P M P - n lam P + x x^T) xi = -grad
-      double R[4][4];
+      // Newton step in the tangent space of S^3 at x, spanned by the unit
+      // quaternions x i, x j, x k (orthonormal, orthogonal to x): with the
+      // Riemannian Hessian S = n(n-1) B^T H B - n lambda I_3 and gradient
+      // gs = n B^T g of lambda(x) = A x^n on the sphere, xi = -S^-1 gs and the
+      // direction is B xi.  Where S is not negative definite it is shifted
+      // by its Gershgorin bound, which keeps the step an ascent direction.
+      const double Bt[3][4] = {{-x[1], x[0], x[3], -x[2]},
+                               {-x[2], -x[3], x[0], x[1]},
+                               {-x[3], x[2], -x[1], x[0]}};
+      double HB[3][4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int k = 0; k < 3; ++k)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          R[i][j] = M[i][j] - x[i] * Mx[j] - Mx[i] * x[j] + x[i] * x[j] * xMx -
-                    n * lam * ((i == j ? 1.0 : 0.0) - x[i] * x[j]) + x[i] * x[j];
-      double dir[4] = {-grad[0], -grad[1], -grad[2], -grad[3]};
-      const bool newton = solve4(R, dir);
+        for (int i = 0; i < 4; ++i) {
+          double v = 0.0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v += M[i][j] * Bt[k][j];
+          HB[k][i] = v;
+        }
+      double S[3][3], gs[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int l = k; l < 3; ++l) {
+          double v = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v += Bt[k][i] * HB[l][i];
+          S[k][l] = v - (k == l ? n * lam : 0.0);
+          S[l][k] = S[k][l];
+        }
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v += Bt[k][i] * gv[i];
+        gs[k] = n * v;
+      }
+      auto det3 = [&]() {
+        return S[0][0] * (S[1][1] * S[2][2] - S[1][2] * S[1][2]) - S[0][1] * (S[0][1] * S[2][2] - S[1][2] * S[0][2]) +
+               S[0][2] * (S[0][1] * S[1][2] - S[1][1] * S[0][2]);
+      };
+      double D = det3();
+      const bool nd = S[0][0] < 0.0 && S[0][0] * S[1][1] - S[0][1] * S[0][1] > 0.0 && D < 0.0;
+      if (!nd) {
+        double mu = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          double r = S[k][k];
+#pragma unroll
+          for (int l = 0; l < 3; ++l)
+            if (l != k) r += fabs(S[k][l]);
+          mu = fmax(mu, r);
+        }
+        mu += 1e-6 * scale;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) S[k][k] -= mu;
+        D = det3();
+      }
+      double dir[4] = {0.0, 0.0, 0.0, 0.0};
       double slope = 0.0;
+      const bool newton = D != 0.0 && isfinite(D);
+      if (newton) {
+        // xi = -S^-1 gs by the adjugate of the symmetric S
+        const double a00 = S[1][1] * S[2][2] - S[1][2] * S[1][2], a01 = S[0][2] * S[1][2] - S[0][1] * S[2][2],
+                     a02 = S[0][1] * S[1][2] - S[0][2] * S[1][1], a11 = S[0][0] * S[2][2] - S[0][2] * S[0][2],
+                     a12 = S[0][1] * S[0][2] - S[0][0] * S[1][2], a22 = S[0][0] * S[1][1] - S[0][1] * S[0][1];
+        const double iD = -1.0 / D;
+        const double xi[3] = {iD * (a00 * gs[0] + a01 * gs[1] + a02 * gs[2]),
+                              iD * (a01 * gs[0] + a11 * gs[1] + a12 * gs[2]),
+                              iD * (a02 * gs[0] + a12 * gs[1] + a22 * gs[2])};
 #pragma unroll
-      for (int i = 0; i < 4; ++i) slope += dir[i] * grad[i];
+        for (int i = 0; i < 4; ++i) dir[i] = Bt[0][i] * xi[0] + Bt[1][i] * xi[1] + Bt[2][i] * xi[2];
+        slope = xi[0] * gs[0] + xi[1] * gs[1] + xi[2] * gs[2];
+      }
       double y[4], lam_new = -INFINITY, gv2[4], Hm2[10];
       bool moved = false;
       if (newton && slope > 0.0) {
@@ -846,47 +894,68 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
 __global__ void __launch_bounds__(1024) k_mask_list(const float* __restrict__ mask, int L0, int L1, int L2,
                                                     unsigned* __restrict__ list, float* __restrict__ mval,
                                                     int* __restrict__ count) {
-  __shared__ int wsum[16];
+  // bricks are handled in chunks of kChunk: one wave per brick (lane j holds
+  // voxel j of the brick), the brick counts are scanned across the chunk in
+  // LDS, then each wave writes its bricks' voxels
+  constexpr int kChunk = 2048;
+  __shared__ unsigned long long bits_s[kChunk];
+  __shared__ int off_s[kChunk + 1];
+  __shared__ int wpart[16];
   __shared__ int base;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int B0 = (L0 + 3) / 4, B1 = (L1 + 3) / 4, B2 = (L2 + 3) / 4, nB = B0 * B1 * B2;
+  const int j0 = lane >> 4, j1 = (lane >> 2) & 3, j2 = lane & 3;
   if (tid == 0) base = 0;
-  __syncthreads();
-  for (int t0 = 0; t0 < nB; t0 += 1024) {
-    const int br = t0 + tid;
-    unsigned long long bits = 0ull;
-    int b0 = 0, b1 = 0, b2 = 0;
-    if (br < nB) {
-      b2 = br % B2;
-      b1 = (br / B2) % B1;
-      b0 = br / (B1 * B2);
-      for (int j = 0; j < 64; ++j) {
-        const int u0 = 4 * b0 + (j >> 4), u1 = 4 * b1 + ((j >> 2) & 3), u2 = 4 * b2 + (j & 3);
-        if (u0 < L0 && u1 < L1 && u2 < L2 && mask[(u0 * L1 + u1) * L2 + u2] != 0.0f) bits |= 1ull << j;
+  for (int c0 = 0; c0 < nB; c0 += kChunk) {
+    const int nc = min(kChunk, nB - c0);
+    for (int i = wave; i < nc; i += 16) {
+      const int br = c0 + i;
+      const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
+      const int u0 = 4 * b0 + j0, u1 = 4 * b1 + j1, u2 = 4 * b2 + j2;
+      const bool on = u0 < L0 && u1 < L1 && u2 < L2 && mask[(u0 * L1 + u1) * L2 + u2] != 0.0f;
+      const unsigned long long bl = __ballot(on);
+      if (lane == 0) bits_s[i] = bl;
+    }
+    __syncthreads();
+    // exclusive scan of the brick counts: each thread sums a run of 2 bricks
+    const int per = (nc + 1023) / 1024;
+    int run = 0;
+    for (int k = 0; k < per; ++k) {
+      const int i = tid * per + k;
+      if (i < nc) run += __popcll(bits_s[i]);
+    }
+    int incl = run;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o);
+      if (lane >= o) incl += v;
+    }
+    if (lane == 63) wpart[wave] = incl;
+    __syncthreads();
+    int pre = base + incl - run;
+    for (int w = 0; w < wave; ++w) pre += wpart[w];
+    for (int k = 0; k < per; ++k) {
+      const int i = tid * per + k;
+      if (i < nc) {
+        off_s[i] = pre;
+        pre += __popcll(bits_s[i]);
       }
     }
-    const int cnt = __popcll(bits);
-    int incl = cnt;
-    for (int off = 1; off < 64; off <<= 1) {
-      const int v = __shfl_up(incl, off);
-      if (lane >= off) incl += v;
-    }
-    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    int off = base + incl - cnt;
-    for (int w = 0; w < wave; ++w) off += wsum[w];
-    for (int j = 0; j < 64; ++j) {
-      if ((bits >> j) & 1ull) {
-        const int u0 = 4 * b0 + (j >> 4), u1 = 4 * b1 + ((j >> 2) & 3), u2 = 4 * b2 + (j & 3);
-        list[off] = (unsigned)u0 | ((unsigned)u1 << 10) | ((unsigned)u2 << 20);
-        mval[off] = mask[(u0 * L1 + u1) * L2 + u2];
-        ++off;
+    for (int i = wave; i < nc; i += 16) {
+      const unsigned long long bl = bits_s[i];
+      if ((bl >> lane) & 1ull) {
+        const int br = c0 + i;
+        const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
+        const int u0 = 4 * b0 + j0, u1 = 4 * b1 + j1, u2 = 4 * b2 + j2;
+        const int o = off_s[i] + __popcll(bl & ((1ull << lane) - 1ull));
+        list[o] = (unsigned)u0 | ((unsigned)u1 << 10) | ((unsigned)u2 << 20);
+        mval[o] = mask[(u0 * L1 + u1) * L2 + u2];
       }
     }
     __syncthreads();
     if (tid == 0) {
       int tot = 0;
-      for (int w = 0; w < 16; ++w) tot += wsum[w];
+      for (int w = 0; w < 16; ++w) tot += wpart[w];
       base += tot;
     }
     __syncthreads();
@@ -970,7 +1039,7 @@ __global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __rest
 }
 
 // The same NCC with the template held in LDS: one 1024-thread block per
-// (candidate, group of kNccGroup neighbours) loads the template once and
+// (candidate, group of its neighbours) loads the template once and
 // evaluates the group's neighbours one after another, sampling trilinearly
 // from LDS without branches (corners outside the box get weight 0 and read
 // element 0).  LDS layout: row pitch P2 = L2 + 3 and plane pitch
@@ -979,7 +1048,6 @@ __global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __rest
 // voxels this cuts the distinct addresses per bank of a wave's gather about
 // fourfold.  The layout must fit kNccLdsCap floats.
 constexpr int kNccLdsCap = 36864;
-constexpr int kNccGroup = 9;
 __host__ __device__ constexpr long ncc_lds_floats(int L0, int L1, int L2) {
   return (long)L0 * ((long)L1 * (L2 + 3) + 5);
 }
@@ -1018,7 +1086,7 @@ __device__ __forceinline__ float sample_rotated_lds(const float* t, int L0, int 
   return acc;
 }
 
-__global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, const float* __restrict__ image,
+__global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, int ngroups, const float* __restrict__ image,
                                                        const float* __restrict__ tmpl,
                                                        const unsigned* __restrict__ mlist,
                                                        const float* __restrict__ mval,
@@ -1030,8 +1098,9 @@ __global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, const float* _
   __shared__ float tl[kNccLdsCap];
   __shared__ double red[16][5];
   constexpr int NB = 27;
-  const int ngroups = NB / kNccGroup;
   const int p = blockIdx.x / ngroups, grp = blockIdx.x % ngroups;
+  const int gsize = (NB + ngroups - 1) / ngroups;
+  const int k_lo = grp * gsize, k_hi = min(NB, k_lo + gsize);
   const int count = count_dev ? count_dev[0] : count_host;
   if (p >= count) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1045,8 +1114,7 @@ __global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, const float* _
   const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;
   const int rs1 = g.n2, rs0 = g.n1 * g.n2;
   const int nm = mcount[0];
-  for (int kk = 0; kk < kNccGroup; ++kk) {
-    const int k = grp * kNccGroup + kk;
+  for (int k = k_lo; k < k_hi; ++k) {
     const long b = (long)p * NB + k;
     // block-uniform: the neighbour's validity and w
     if (!okbuf[b]) {
@@ -1173,23 +1241,43 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
   hipLaunchKernelGGL(k_seed_table, dim3((n_seeds + 255) / 256), dim3(256), 0, s, n_seeds, ps.seeds);
   const dim3 eg((unsigned)(max_peaks * NB));
   switch (order_n) {
-    case 2: hipLaunchKernelGGL(k_pose_eig<2>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                               n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags); break;
-    case 4: hipLaunchKernelGGL(k_pose_eig<4>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                               n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags); break;
-    case 6: hipLaunchKernelGGL(k_pose_eig<6>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                               n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags); break;
-    case 8: hipLaunchKernelGGL(k_pose_eig<8>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                               n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags); break;
+    case 2:
+      hipLaunchKernelGGL(k_seed_scan<2>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                         n_seeds, ps.sbest, ps.sidx);
+      hipLaunchKernelGGL(k_pose_eig<2>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_seed_scan<4>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                         n_seeds, ps.sbest, ps.sidx);
+      hipLaunchKernelGGL(k_pose_eig<4>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags);
+      break;
+    case 6:
+      hipLaunchKernelGGL(k_seed_scan<6>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                         n_seeds, ps.sbest, ps.sidx);
+      hipLaunchKernelGGL(k_pose_eig<6>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_seed_scan<8>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                         n_seeds, ps.sbest, ps.sidx);
+      hipLaunchKernelGGL(k_pose_eig<8>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags);
+      break;
     default: return hipErrorInvalidValue;
   }
   if (refine == 2) {
     hipLaunchKernelGGL(k_mask_list, dim3(1), dim3(1024), 0, s, mask, g.L0, g.L1, g.L2, ps.mlist, ps.mval,
                        ps.mcount);
-    if (ncc_lds_floats(g.L0, g.L1, g.L2) <= kNccLdsCap)
-      hipLaunchKernelGGL(k_pose_ncc_lds, dim3((unsigned)(max_peaks * (27 / kNccGroup))), dim3(1024), 0, s, g,
+    if (ncc_lds_floats(g.L0, g.L1, g.L2) <= kNccLdsCap) {
+      // one block per CU (the template fills most of the LDS); each block
+      // loads the template once for 9 neighbours of a candidate
+      const int ngroups = 3;
+      hipLaunchKernelGGL(k_pose_ncc_lds, dim3((unsigned)(max_peaks * ngroups)), dim3(1024), 0, s, g, ngroups,
                          image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in, count_dev, count_host, ps.w, ps.ok,
                          ps.q, ps.ncc);
+    }
     else
       hipLaunchKernelGGL(k_pose_ncc, eg, dim3(256), 0, s, g, image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in,
                          count_dev, count_host, NB, ps.w, ps.ok, ps.q, ps.ncc);
