@@ -624,3 +624,117 @@ def refine_by_ncc(f, t, m, T, n: int, x, eps_v: float = EPS_V_DEFAULT,
         if nccs[k] > nccs[best]:
             best = k
     return np.asarray(x) + offs[best], qs[best], lams[best], nccs[best], nccs
+
+
+# ----------------------------------------------------------------------------
+# gradient of the Frobenius score at fixed positions: the adjoint of the whole
+# forward path (rotation, masked normalisation, tensor accumulation, window
+# correlation, local normalisation, Frobenius norm), written out by the chain
+# rule in float64
+# ----------------------------------------------------------------------------
+
+def rotate_trilinear_adjoint(h: np.ndarray, q, L) -> np.ndarray:
+    """Adjoint of :func:`rotate_trilinear` in its template argument: the array
+    ``a`` with ``<rotate_trilinear(t, q), h> = <t, a>`` for every ``t`` (each
+    sample's weight scattered back to its eight corners)."""
+    h = np.asarray(h, dtype=np.float64)
+    L = np.array(L)
+    c = template_centre(L).astype(np.float64)
+    r_inv = quat_to_matrix(q).T
+    grids = np.meshgrid(*[np.arange(l, dtype=np.float64) for l in L], indexing="ij")
+    u = np.stack(grids, axis=-1) - c
+    p = u @ r_inv.T + c
+    p0 = np.floor(p)
+    fr = p - p0
+    p0 = p0.astype(np.int64)
+    out = np.zeros(tuple(L))
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                idx = p0 + np.array([dz, dy, dx])
+                wgt = ((fr[..., 0] if dz else 1 - fr[..., 0]) *
+                       (fr[..., 1] if dy else 1 - fr[..., 1]) *
+                       (fr[..., 2] if dx else 1 - fr[..., 2]))
+                inside = np.all((idx >= 0) & (idx < L), axis=-1)
+                ii = idx[inside]
+                np.add.at(out, (ii[:, 0], ii[:, 1], ii[:, 2]), (wgt * h)[inside])
+    return out
+
+
+def score_at(f, t, m, n: int, quats, weights, xs, eps_v: float = EPS_V_DEFAULT) -> np.ndarray:
+    """``F(x)`` at the positions ``xs`` from the raw template: tensor template
+    (Section 3.2), tensor field and Frobenius norm (Section 3.4)."""
+    T = tensor_template(t, m, n, quats, weights)
+    return score_from_field(tensor_field_at(f, T, m, xs, eps_v), n)
+
+
+def score_grad(f, t, m, n: int, quats, weights, xs, grad_F, eps_v: float = EPS_V_DEFAULT):
+    """Gradient of ``sum_p grad_F[p] F(x_p)`` with respect to the raw template
+    ``t`` and the image ``f``.  With ``C = w G``, ``G_alpha = <tau_x f,
+    T_alpha>``, ``F = sqrt(sum mu C^2)``:
+
+    * ``dF/dC_alpha = mu_alpha C_alpha / F``;
+    * ``d/dT_alpha(u) = sum_p dC_alpha(p) w_p (tau_{x_p} f)(u)``;
+    * ``d/df`` on each window: ``w_p sum_alpha dC_alpha T_alpha(u)
+      - w_p^3 m(u) (f - mu_p) sum_alpha dC_alpha G_alpha`` (from
+      ``dw/df = -w^3 m (f - mu)``, Section 2's local norm);
+    * through ``T_alpha = sum_j omega_j Q_j^alpha s_j``, ``s = m (g - mu)/sigma``
+      of the rotated template ``g``: ``dg = (m/sigma)(h - H1/M - (g - mu)
+      H2/sigma^2)`` with ``h = omega_j sum_alpha Q_j^alpha dT_alpha``,
+      ``H1 = sum m h``, ``H2 = sum m h (g - mu)``, ``M = sum m``; then the
+      adjoint of the trilinear rotation.
+
+    Where ``w = 0`` (the variance floor) or ``F = 0`` the position contributes
+    nothing.  Returns (grad_t, grad_f)."""
+    f = np.asarray(f, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    m = np.asarray(m, dtype=np.float64)
+    quats = np.asarray(quats, dtype=np.float64)
+    weights = np.asarray(weights, dtype=np.float64)
+    xs = np.asarray(xs, dtype=np.int64).reshape(-1, 3)
+    grad_F = np.asarray(grad_F, dtype=np.float64).reshape(-1)
+    L = np.shape(t)
+    N = np.shape(f)
+    c = template_centre(L)
+    mu_n = multiplicities(n)
+    T = tensor_template(t, m, n, quats, weights)
+    K = T.shape[0]
+    Tf = T.reshape(K, -1)
+    W = windows(f, xs, L).reshape(len(xs), -1)
+    mv = m.reshape(-1)
+    msum = mv.sum()
+    mean = (W * mv).sum(axis=1) / msum
+    var = ((W - mean[:, None]) ** 2 * mv).sum(axis=1)
+    floor = eps_v * msum * float(f.var())
+    w = np.where(var > floor, 1.0 / np.sqrt(np.maximum(var, 1e-300)), 0.0)
+    G = W @ Tf.T
+    C = G * w[:, None]
+    F = np.sqrt(C ** 2 @ mu_n)
+    ok = (w > 0) & (F > 0)
+    dC = np.where(ok[:, None], grad_F[:, None] * mu_n[None] * C / np.where(F > 0, F, 1.0)[:, None], 0.0)
+    # template tensor
+    dT = (dC * w[:, None]).T @ W                                   # (K, L^3)
+    # image: each window's gradient scattered back
+    grad_f = np.zeros(N)
+    a = (dC * G).sum(axis=1)
+    b = dC @ Tf
+    dW = w[:, None] * b - (w ** 3)[:, None] * mv[None] * (W - mean[:, None]) * a[:, None]
+    for p, x in enumerate(xs):
+        i0 = (x[0] + np.arange(L[0]) - c[0]) % N[0]
+        i1 = (x[1] + np.arange(L[1]) - c[1]) % N[1]
+        i2 = (x[2] + np.arange(L[2]) - c[2]) % N[2]
+        grad_f[np.ix_(i0, i1, i2)] += dW[p].reshape(L)
+    # raw template through the rotations and the masked normalisation
+    mono = monomials(quats / np.linalg.norm(quats, axis=1, keepdims=True), n)
+    grad_t = np.zeros(L)
+    for j, q in enumerate(quats):
+        g = rotate_trilinear(t, q).reshape(-1)
+        s1 = (mv * g).sum()
+        mu_j = s1 / msum
+        sig = math.sqrt((mv * g * g).sum() - s1 * s1 / msum)
+        h = weights[j] * (mono[j] @ dT)
+        H1 = (mv * h).sum()
+        H2 = (mv * h * (g - mu_j)).sum()
+        dg = mv / sig * (h - H1 / msum - (g - mu_j) * H2 / sig ** 2)
+        grad_t += rotate_trilinear_adjoint(dg.reshape(L), q, L)
+    return grad_t, grad_f

@@ -467,3 +467,56 @@ def test_refinement_returns_to_a_noiseless_copy():
         # the neighbour values that exist are finite and below the chosen one
         fin = nccs[np.isfinite(nccs)]
         assert len(fin) == 27 and fin.max() == ncc
+
+
+# --------------------------------------------------------------------------
+# gradient of the score (adjoint) against central finite differences
+# --------------------------------------------------------------------------
+
+def test_rotation_adjoint_is_the_transpose():
+    rng = _rng(70)
+    L = (7, 6, 8)
+    q = synth.random_quaternions(rng, 1)[0]
+    t = rng.standard_normal(L)
+    h = rng.standard_normal(L)
+    lhs = float((O.rotate_trilinear(t, q) * h).sum())
+    rhs = float((t * O.rotate_trilinear_adjoint(h, q, L)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+def test_score_gradient_matches_central_differences():
+    # L = sum_p g_p F(x_p) on a noisy image with a planted copy; central
+    # differences (h = 1e-3) of the oracle's own forward pin the analytic
+    # adjoint for template voxels (inside and outside the mask) and image
+    # voxels (inside windows, in two overlapping windows, and outside all)
+    rng = _rng(71)
+    L, n = 8, 4
+    tm = synth.make_blob_template(rng, L, 4, L / 2)
+    t = tm.grid()
+    m = synth.ball_mask(L, 3.6)
+    qs = synth.random_quaternions(rng, 30)
+    wts = rng.uniform(0.5, 1.5, 30)
+    wts /= wts.sum()
+    f = rng.standard_normal((20, 20, 20))
+    f += 2.0 * synth.render_copies((20, 20, 20), tm, np.array([[10, 10, 10]]), qs[:1])
+    xs = np.array([[10, 10, 10], [11, 9, 10], [6, 13, 8]])
+    gF = np.array([1.0, -0.5, 0.7])
+    gt, gf = O.score_grad(f, t, m, n, qs, wts, xs, gF)
+
+    def loss(tt, ff):
+        return float(gF @ O.score_at(ff, tt, m, n, qs, wts, xs))
+
+    h = 1e-3
+    for idx in [(4, 4, 4), (1, 4, 5), (0, 0, 0), (6, 2, 3), (3, 7, 4)]:
+        tp, tq = t.copy(), t.copy()
+        tp[idx] += h
+        tq[idx] -= h
+        fd = (loss(tp, f) - loss(tq, f)) / (2 * h)
+        assert abs(fd - gt[idx]) <= 1e-6 + 1e-5 * abs(fd), (idx, fd, gt[idx])
+    for idx in [(10, 10, 10), (8, 11, 12), (11, 10, 9), (7, 12, 8), (1, 1, 18)]:
+        fp, fq = f.copy(), f.copy()
+        fp[idx] += h
+        fq[idx] -= h
+        fd = (loss(t, fp) - loss(t, fq)) / (2 * h)
+        assert abs(fd - gf[idx]) <= 1e-6 + 1e-5 * abs(fd), (idx, fd, gf[idx])
+    assert gf[1, 1, 18] == 0.0          # outside every window
