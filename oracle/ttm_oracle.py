@@ -738,3 +738,60 @@ def score_grad(f, t, m, n: int, quats, weights, xs, grad_F, eps_v: float = EPS_V
         dg = mv / sig * (h - H1 / msum - (g - mu_j) * H2 / sig ** 2)
         grad_t += rotate_trilinear_adjoint(dg.reshape(L), q, L)
     return grad_t, grad_f
+
+
+# ----------------------------------------------------------------------------
+# isotropic low-pass filter and soft mask (Section 2: matching is applied to
+# f * h and t * h for an isotropic low-pass h with h * 1 = 1, under a
+# rotationally symmetric mask that is 1 inside one radius and 0 outside a
+# slightly larger one)
+# ----------------------------------------------------------------------------
+
+def lowpass_kernel(sigma: float) -> np.ndarray:
+    """Reading of the unspecified filter: a sampled Gaussian of standard
+    deviation ``sigma`` voxels on ``k = -R..R``, ``R = ceil(3 sigma)``,
+    normalised to unit sum (so ``h * 1 = 1``); ``sigma = 0`` is the identity.
+    The 3-D filter is its product along the three axes."""
+    if sigma < 0:
+        raise ValueError("sigma must be >= 0")
+    if sigma == 0:
+        return np.ones(1)
+    R = int(math.ceil(3.0 * sigma))
+    k = np.arange(-R, R + 1, dtype=np.float64)
+    h = np.exp(-0.5 * (k / sigma) ** 2)
+    return h / h.sum()
+
+
+def lowpass(f: np.ndarray, sigma: float, periodic: bool = True) -> np.ndarray:
+    """``f * h`` with the filter of :func:`lowpass_kernel`, one axis at a
+    time: ``out(x) = sum_k h(k) f(x - k)``, indices taken modulo the extent
+    (``periodic``, as the FFT correlation treats the image) or with ``f = 0``
+    outside the array (the template box)."""
+    h = lowpass_kernel(sigma)
+    R = (len(h) - 1) // 2
+    out = np.asarray(f, dtype=np.float64)
+    for axis in range(out.ndim):
+        n = out.shape[axis]
+        acc = np.zeros_like(out)
+        for i, k in enumerate(range(-R, R + 1)):
+            src = np.arange(n) - k
+            if periodic:
+                acc += h[i] * np.take(out, src % n, axis=axis)
+            else:
+                ok = (src >= 0) & (src < n)
+                shape = [1] * out.ndim
+                shape[axis] = n
+                acc += h[i] * np.take(out, np.clip(src, 0, n - 1), axis=axis) * ok.reshape(shape)
+        out = acc
+    return out
+
+
+def soft_mask(L, r_in: float, r_out: float) -> np.ndarray:
+    """Rotationally symmetric mask about the template centre: 1 for
+    ``||u - c|| <= r_in``, 0 for ``>= r_out``, a raised cosine in between."""
+    L = (L, L, L) if np.isscalar(L) else tuple(L)
+    c = template_centre(L)
+    g = np.meshgrid(*[np.arange(l) - c[i] for i, l in enumerate(L)], indexing="ij")
+    r = np.sqrt(g[0] ** 2 + g[1] ** 2 + g[2] ** 2)
+    t = np.clip((r - r_in) / (r_out - r_in), 0.0, 1.0)
+    return 0.5 * (1.0 + np.cos(np.pi * t))

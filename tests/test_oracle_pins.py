@@ -520,3 +520,56 @@ def test_score_gradient_matches_central_differences():
         fd = (loss(t, fp) - loss(t, fq)) / (2 * h)
         assert abs(fd - gf[idx]) <= 1e-6 + 1e-5 * abs(fd), (idx, fd, gf[idx])
     assert gf[1, 1, 18] == 0.0          # outside every window
+
+
+# --------------------------------------------------------------------------
+# low-pass filter and soft mask
+# --------------------------------------------------------------------------
+
+def test_lowpass_pins():
+    rng = _rng(90)
+    # unit DC gain: a constant image is unchanged (h * 1 = 1)
+    c = np.full((9, 10, 11), 3.25)
+    assert np.allclose(O.lowpass(c, 1.3), c, atol=1e-13)
+    # sigma 0 is the identity
+    f = rng.standard_normal((12, 9, 10))
+    assert np.array_equal(O.lowpass(f, 0.0), f)
+    # separable filter = brute-force 3-D circular convolution with the outer product
+    sigma = 0.8
+    h = O.lowpass_kernel(sigma)
+    R = (len(h) - 1) // 2
+    g = rng.standard_normal((7, 8, 9))
+    ref = np.zeros_like(g)
+    N = g.shape
+    for k0 in range(-R, R + 1):
+        for k1 in range(-R, R + 1):
+            for k2 in range(-R, R + 1):
+                ref += h[k0 + R] * h[k1 + R] * h[k2 + R] * np.roll(g, (k0, k1, k2), axis=(0, 1, 2))
+    assert np.allclose(O.lowpass(g, sigma), ref, atol=1e-12)
+    # the same as multiplying the spectrum by the transfer function of h
+    ker = np.zeros(N)
+    for k0 in range(-R, R + 1):
+        for k1 in range(-R, R + 1):
+            for k2 in range(-R, R + 1):
+                ker[k0 % N[0], k1 % N[1], k2 % N[2]] += h[k0 + R] * h[k1 + R] * h[k2 + R]
+    fft = np.real(np.fft.ifftn(np.fft.fftn(g) * np.fft.fftn(ker)))
+    assert np.allclose(O.lowpass(g, sigma), fft, atol=1e-12)
+    # isotropic on the grid: commutes with a 90-degree turn
+    cube = rng.standard_normal((8, 8, 8))
+    assert np.allclose(O.lowpass(np.rot90(cube, axes=(1, 2)), 1.1), np.rot90(O.lowpass(cube, 1.1), axes=(1, 2)),
+                       atol=1e-12)
+    # zero extension = periodic filtering of the zero-padded box, cropped
+    pad = np.pad(g, R + 1)
+    crop = O.lowpass(pad, sigma)[R + 1:-R - 1, R + 1:-R - 1, R + 1:-R - 1]
+    assert np.allclose(O.lowpass(g, sigma, periodic=False), crop, atol=1e-12)
+
+
+def test_soft_mask_shape():
+    m = O.soft_mask(16, 5.0, 7.0)
+    c = O.template_centre((16, 16, 16))
+    assert m[tuple(c)] == 1.0 and m[c[0], c[1], c[2] + 5] == 1.0
+    assert m[c[0], c[1], c[2] + 7] == 0.0 and m[0, 0, 0] == 0.0
+    assert abs(m[c[0], c[1], c[2] + 6] - 0.5) < 1e-12
+    # rotationally symmetric on the grid (odd box: its centre is the array's)
+    m15 = O.soft_mask(15, 4.5, 6.5)
+    assert np.allclose(m15, np.rot90(m15, axes=(0, 2))) and np.allclose(m15, np.transpose(m15, (2, 0, 1)))
