@@ -258,6 +258,56 @@ ttm_status tm_classical(
     void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Isotropic low-pass filter (Section 2: the matching is applied to f * h and
+ * t * h for an isotropic low-pass h with h * 1 = 1).  h is a sampled Gaussian
+ * of standard deviation sigma voxels on k = -R..R, R = ceil(3 sigma) <= 32,
+ * normalised to unit sum, applied along each axis:
+ *   out(x) = sum_k h(k) in(x - k)
+ * with indices modulo the extent (periodic = 1, for images: the correlation
+ * is circular) or zero outside the array (periodic = 0, for the template
+ * box).  sigma = 0 copies.  in and out are [n0][n1][n2] float32 device arrays
+ * and may be the same.
+ * Errors: TTM_E_ARG (NULL, sigma < 0 or too large, periodic not 0/1),
+ * TTM_E_SIZE, TTM_E_WORKSPACE, TTM_E_HIP.
+ * ------------------------------------------------------------------------- */
+size_t ttm_lowpass_workspace_bytes(ttm_dims N);
+ttm_status ttm_lowpass(const float* in, ttm_dims N, float sigma,
+                       int32_t periodic, float* out, void* ws,
+                       size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Gradient of the score at fixed positions (the adjoint of the tensor build,
+ * Section 3.2, the window correlation and local normalisation, Section 2, and
+ * the Frobenius norm, Section 3.4): for L = sum_p grad_score[p] F(x_p), with
+ * F evaluated as ttm_correlate does (in float64 window sums here), writes
+ * dL/dt (the raw template) and dL/df (the image).  The tensor components are
+ * not differentiated through storage: the rotations are re-sampled from the
+ * template, so the components only supply T_alpha for the image gradient.
+ *
+ *   image [n0][n1][n2]; tmpl, mask [L0][L1][L2]; quats_host, weights_host,
+ *   n_rot       the quadrature of the tensor build (same checks)
+ *   components  K x [L0][L1][L2] from ttm_build_tensor_template with them
+ *   positions   n_pos x 3 int32 device; positions outside the valid region,
+ *               or where w = 0 or F = 0, contribute nothing
+ *   grad_score  n_pos float32 device
+ *   opt         eps_v is used
+ *   out_grad_tmpl   [L0][L1][L2] float32 (written), or NULL; needs
+ *                   L0 L1 L2 <= 32768 (TTM_E_SIZE otherwise)
+ *   out_grad_image  [n0][n1][n2] float32 (written: zero outside the
+ *                   positions' windows), or NULL
+ * Errors: TTM_E_ARG, TTM_E_SIZE, TTM_E_WORKSPACE, TTM_E_HIP.
+ * ------------------------------------------------------------------------- */
+size_t ttm_score_backward_workspace_bytes(ttm_dims L, int32_t order_n,
+                                          int32_t n_rot, int32_t n_pos);
+ttm_status ttm_score_backward(
+    const float* image, ttm_dims N, const float* tmpl, const float* mask,
+    ttm_dims L, int32_t order_n, const float* quats_host,
+    const double* weights_host, int32_t n_rot, const float* components,
+    const int32_t* positions, int32_t n_pos, const float* grad_score,
+    const ttm_options* opt, float* out_grad_tmpl, float* out_grad_image,
+    void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Instrumentation (not part of the method).  When enabled, every call records
  * a HIP event pair on its stream around each kernel group, by class:
  *   0 image moments, 1 axis-2 R2C rows, 2 axis-1 forward pencils,

@@ -472,6 +472,124 @@ ttm_status ttm_match(const float* image, ttm_dims N, const void* bank, ttm_dims 
   return TTM_OK;
 }
 
+// --- low-pass filter -----------------------------------------------------------
+size_t ttm_lowpass_workspace_bytes(ttm_dims N) {
+  if (!dims_ok(N)) return 0;
+  return 2 * sizeof(float) * (size_t)N.n0 * N.n1 * N.n2 + 512;
+}
+
+ttm_status ttm_lowpass(const float* in, ttm_dims N, float sigma, int32_t periodic, float* out, void* ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  if (!in || !out || !std::isfinite(sigma) || sigma < 0.0f || (periodic != 0 && periodic != 1)) return TTM_E_ARG;
+  if (!dims_ok(N)) return TTM_E_SIZE;
+  const int R = sigma > 0.0f ? (int)std::ceil(3.0 * (double)sigma) : 0;
+  if (R > kMaxFilterRadius) return TTM_E_ARG;
+  const size_t vol = (size_t)N.n0 * N.n1 * N.n2;
+  if (sigma == 0.0f) {
+    if (in != out) TTM_TRY(hipMemcpyAsync(out, in, sizeof(float) * vol, hipMemcpyDeviceToDevice, stream));
+    return TTM_OK;
+  }
+  if (!ws || ws_bytes < ttm_lowpass_workspace_bytes(N)) return TTM_E_WORKSPACE;
+  // the sampled Gaussian, normalised to unit sum in float64
+  FilterTaps taps;
+  taps.R = R;
+  double h[2 * kMaxFilterRadius + 1], sum = 0.0;
+  for (int k = -R; k <= R; ++k) {
+    h[k + R] = std::exp(-0.5 * ((double)k / sigma) * ((double)k / sigma));
+    sum += h[k + R];
+  }
+  for (int k = 0; k <= 2 * R; ++k) taps.h[k] = (float)(h[k] / sum);
+  Carve c(ws);
+  float* a = c.take<float>(vol);
+  float* b = c.take<float>(vol);
+  TTM_TRY(launch_lowpass(in, out, a, b, N.n0, N.n1, N.n2, periodic, taps, stream));
+  return TTM_OK;
+}
+
+// --- gradient of the score at fixed positions ----------------------------------
+struct GradLayout {
+  BuildWs b;
+  GradWs g;
+  double* stats;
+  double* partials;
+};
+static GradLayout grad_layout(Carve& c, ttm_dims L, int K, int n_rot, int n_pos) {
+  GradLayout w;
+  w.b = build_layout(c, n_rot, K);
+  const long nL = (long)L.n0 * L.n1 * L.n2;
+  const long ntiles = (nL + 255) / 256;
+  w.g.wv = c.take<double>((size_t)n_pos);
+  w.g.mean = c.take<double>((size_t)n_pos);
+  w.g.dC = c.take<double>((size_t)n_pos * K);
+  w.g.a = c.take<double>((size_t)n_pos);
+  w.g.dT = c.take<float>((size_t)K * nL);
+  w.g.part = c.take<double>((size_t)ntiles * n_rot * 2);
+  w.g.H = c.take<double>((size_t)n_rot * 2);
+  w.stats = c.take<double>(4);
+  w.partials = c.take<double>(3 * kStatPartials);
+  return w;
+}
+
+size_t ttm_score_backward_workspace_bytes(ttm_dims L, int32_t order_n, int32_t n_rot, int32_t n_pos) {
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || n_rot < 1 || n_pos < 1 || !dims_ok(L)) return 0;
+  Carve c(nullptr);
+  grad_layout(c, L, K, n_rot, n_pos);
+  return c.size();
+}
+
+ttm_status ttm_score_backward(const float* image, ttm_dims N, const float* tmpl, const float* mask, ttm_dims L,
+                              int32_t order_n, const float* quats_host, const double* weights_host, int32_t n_rot,
+                              const float* components, const int32_t* positions, int32_t n_pos,
+                              const float* grad_score, const ttm_options* opt, float* out_grad_tmpl,
+                              float* out_grad_image, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!image || !tmpl || !mask || !quats_host || !weights_host || !components || !positions || !grad_score ||
+      !opt)
+    return TTM_E_ARG;
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || n_rot < 1 || n_pos < 1 || !(opt->eps_v >= 0.0f)) return TTM_E_ARG;
+  double wsum = 0.0;
+  for (int j = 0; j < n_rot; ++j) {
+    const float* q = quats_host + 4 * j;
+    const double nq = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3];
+    if (!std::isfinite(nq) || nq <= 0.0) return TTM_E_ARG;
+    if (!std::isfinite(weights_host[j])) return TTM_E_ARG;
+    wsum += weights_host[j];
+  }
+  if (std::fabs(wsum - 1.0) > 1e-6) return TTM_E_ARG;
+  if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
+  if (out_grad_tmpl && (long)L.n0 * L.n1 * L.n2 > kGradMaxTemplate) return TTM_E_SIZE;
+  if (!ws || ws_bytes < ttm_score_backward_workspace_bytes(L, order_n, n_rot, n_pos)) return TTM_E_WORKSPACE;
+  Carve c(ws);
+  GradLayout w = grad_layout(c, L, K, n_rot, n_pos);
+  const Geo geo = make_geo(N, L);
+  GradGeo g;
+  g.n0 = N.n0; g.n1 = N.n1; g.n2 = N.n2; g.L0 = L.n0; g.L1 = L.n1; g.L2 = L.n2;
+  g.lo0 = geo.lo0(); g.hi0 = geo.hi0(); g.lo1 = geo.lo1(); g.hi1 = geo.hi1();
+  g.lo2 = geo.c2; g.hi2 = N.n2 - L.n2 + geo.c2;
+  const long nL = (long)L.n0 * L.n1 * L.n2;
+  TTM_PROF(PC_STATS, launch_image_stats(image, geo.vol(), mask, nL, w.partials, w.stats, stream));
+  TTM_PROF(PC_POSE, launch_grad_field(g, image, components, mask, order_n, w.stats, opt->eps_v, positions, n_pos,
+                                      grad_score, w.g, stream));
+  if (out_grad_image) {
+    TTM_PROF(PC_POSE, launch_fill_f32(out_grad_image, geo.vol(), 0.0f, stream));
+    TTM_PROF(PC_POSE, launch_grad_image(g, image, components, mask, order_n, positions, n_pos, w.g,
+                                        out_grad_image, stream));
+  }
+  if (out_grad_tmpl) {
+    TTM_TRY(hipMemcpyAsync(w.b.quats, quats_host, sizeof(float) * 4 * (size_t)n_rot, hipMemcpyHostToDevice,
+                           stream));
+    TTM_TRY(hipMemcpyAsync(w.b.weights, weights_host, sizeof(double) * (size_t)n_rot, hipMemcpyHostToDevice,
+                           stream));
+    TTM_PROF(PC_BUILD, launch_rot_stats(tmpl, mask, L.n0, L.n1, L.n2, w.b.quats, n_rot, w.b.rstats, stream));
+    TTM_PROF(PC_BUILD, launch_build_coef(w.b.quats, w.b.weights, w.b.rstats, n_rot, order_n, w.b.coef, stream));
+    TTM_PROF(PC_BUILD, launch_fill_f32(out_grad_tmpl, nL, 0.0f, stream));
+    TTM_PROF(PC_BUILD, launch_grad_tmpl(g, image, tmpl, mask, order_n, w.b.quats, n_rot, w.b.coef, w.b.rstats,
+                                        w.stats, positions, n_pos, w.g, out_grad_tmpl, stream));
+  }
+  return TTM_OK;
+}
+
 size_t tm_classical_workspace_bytes(ttm_dims N, ttm_dims L, int32_t n_rot) {
   if (!dims_ok(N) || !dims_ok(L) || n_rot < 1) return 0;
   Carve c(nullptr);

@@ -171,4 +171,45 @@ hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int 
                              int* out_pos, float* out_quat, double* out_lambda, float* out_score, int* out_flags,
                              double* out_C, const PoseScratch& ps, hipStream_t s);
 
+// --- isotropic low-pass filter (ttm_filter.hip) -----------------------------
+constexpr int kMaxFilterRadius = 32;
+struct FilterTaps {
+  int R;                               // taps k = -R..R
+  float h[2 * kMaxFilterRadius + 1];   // h[k + R]
+};
+// out = in * h along axes 2, 1, 0 (through tmp_a, tmp_b; out may equal in)
+hipError_t launch_lowpass(const float* in, float* out, float* tmp_a, float* tmp_b, int n0, int n1, int n2,
+                          int periodic, const FilterTaps& taps, hipStream_t s);
+
+// --- gradient of the score at fixed positions (ttm_grad.hip) ---------------
+struct GradGeo {
+  int n0, n1, n2, L0, L1, L2;
+  int lo0, hi0, lo1, hi1, lo2, hi2;   // valid region, inclusive
+};
+struct GradWs {
+  double* wv;      // n_pos: w at the position (0 where it contributes nothing)
+  double* mean;    // n_pos: masked window mean
+  double* dC;      // n_pos * K: gF mu_alpha C_alpha / F
+  double* a;       // n_pos: sum_alpha dC_alpha G_alpha
+  float* dT;       // K * L^3: gradient with respect to the tensor components
+  double* part;    // ceil(L^3 / 256) * n_rot * 2: per-tile rotation sums
+  double* H;       // n_rot * 2: H1_j, H2_j
+};
+// per position: window statistics, G, F, dC and a (stats[1] = var(f))
+hipError_t launch_grad_field(const GradGeo& g, const float* image, const float* comps, const float* mask,
+                             int order_n, const double* img_stats, float eps_v, const int* pos, int n_pos,
+                             const float* grad_F, const GradWs& w, hipStream_t s);
+// the image gradient added onto grad_image (zeroed by the caller)
+hipError_t launch_grad_image(const GradGeo& g, const float* image, const float* comps, const float* mask,
+                             int order_n, const int* pos, int n_pos, const GradWs& w, float* grad_image,
+                             hipStream_t s);
+// dT, then the template gradient through the rotations (coef, rstats of the
+// tensor build; stats[2] = m_sum) added onto grad_tmpl (zeroed by the caller);
+// needs L0 L1 L2 <= 32768
+hipError_t launch_grad_tmpl(const GradGeo& g, const float* image, const float* tmpl, const float* mask,
+                            int order_n, const float* quats, int nrot, const double* coef, const double* rstats,
+                            const double* stats, const int* pos, int n_pos, const GradWs& w, float* grad_tmpl,
+                            hipStream_t s);
+constexpr int kGradMaxTemplate = 32768;
+
 }  // namespace ttm

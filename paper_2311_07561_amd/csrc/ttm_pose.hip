@@ -37,11 +37,11 @@ __device__ __forceinline__ unsigned long long peak_key(float v, long lin) {
 
 // One pass over the valid region in 4 x 8 x 64 tiles staged (with a one-voxel
 // halo) in LDS: every strict local maximum above the threshold is appended to
-// the full candidate list and counted in the histogram of its key's top bits.
-// Out-of-image neighbours are not compared (they hold -inf in the tile).
+// the full candidate list.  Out-of-image neighbours are not compared (they
+// hold -inf in the tile).
 constexpr int PT0 = 4, PT1 = 8, PT2 = 64;
 __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F, PeakGeo g, float threshold,
-                                                    unsigned* __restrict__ hist, unsigned* __restrict__ ctrl,
+                                                    unsigned* __restrict__ ctrl,
                                                     unsigned long long* __restrict__ allc, long bigcap) {
   constexpr int H0 = PT0 + 2, H1 = PT1 + 2, H2 = PT2 + 2;
   __shared__ float tile[H0 * H1 * H2];
@@ -78,7 +78,6 @@ __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F,
         }
     if (!ok) continue;
     const long lin = ((long)x0 * g.n1 + x1) * g.n2 + x2;
-    atomicAdd(&hist[__float_as_uint(v) >> 16], 1u);
     const unsigned ls = atomicAdd(&lcount, 1u);
     lkeys[ls] = peak_key(v, lin);
   }
@@ -93,6 +92,29 @@ __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F,
       allc[slot] = lkeys[i];
     else
       ctrl[PK_OVER] = 1u;
+  }
+}
+
+// Histogram of the candidates' key top bits (the float bits of F >> 16): each
+// block counts a grid-strided share of the list in LDS, then adds its
+// non-zero bins to the global histogram.
+constexpr int kHistBlocks = 64;
+__global__ void __launch_bounds__(1024) k_peaks_hist(const unsigned* __restrict__ ctrl,
+                                                     const unsigned long long* __restrict__ allc, long bigcap,
+                                                     unsigned* __restrict__ hist) {
+  __shared__ unsigned lh[kHistBins];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kHistBins; i += 1024) lh[i] = 0u;
+  __syncthreads();
+  const long total = min((long)ctrl[PK_TOTAL], bigcap);
+  for (long i = (long)blockIdx.x * 1024 + tid; i < total; i += (long)gridDim.x * 1024) {
+    const unsigned bits = 0xFFFFFFFFu - (unsigned)(allc[i] >> 32);
+    atomicAdd(&lh[bits >> 16], 1u);
+  }
+  __syncthreads();
+  for (int i = tid; i < kHistBins; i += 1024) {
+    const unsigned v = lh[i];
+    if (v) atomicAdd(&hist[i], v);
   }
 }
 
@@ -280,7 +302,8 @@ hipError_t launch_peaks(const Geo& gg, const float* score, float threshold, floa
   if ((e = launch_fill_i32(reinterpret_cast<int*>(w.ctrl), 16, 0, s)) != hipSuccess) return e;
   const int e0 = g.hi0 - g.lo0 + 1, e1 = g.hi1 - g.lo1 + 1, e2 = g.hi2 - g.lo2 + 1;
   dim3 sgrid((e2 + PT2 - 1) / PT2, (e1 + PT1 - 1) / PT1, (e0 + PT0 - 1) / PT0);
-  hipLaunchKernelGGL(k_peaks_scan, sgrid, dim3(256), 0, s, score, g, threshold, w.hist, w.ctrl, w.allc, bigcap);
+  hipLaunchKernelGGL(k_peaks_scan, sgrid, dim3(256), 0, s, score, g, threshold, w.ctrl, w.allc, bigcap);
+  hipLaunchKernelGGL(k_peaks_hist, dim3(kHistBlocks), dim3(1024), 0, s, w.ctrl, w.allc, bigcap, w.hist);
   constexpr unsigned cap1 = 2048, cap2 = kCandCap;
   for (int round = 1; round <= 2; ++round) {
     const unsigned cap = round == 1 ? cap1 : cap2;
@@ -1061,6 +1084,16 @@ __device__ __forceinline__ float sample_rotated_lds(const float* t, int L0, int 
   const float f0 = floorf(p0), f1 = floorf(p1), f2 = floorf(p2);
   const int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
   const float w0 = p0 - f0, w1 = p1 - f1, w2 = p2 - f2;
+  if ((unsigned)i0 < (unsigned)(L0 - 1) && (unsigned)i1 < (unsigned)(L1 - 1) && (unsigned)i2 < (unsigned)(L2 - 1)) {
+    // all eight corners inside the box (the common case)
+    const float* q = t + i0 * P01 + i1 * P2 + i2;
+    const float c00 = q[0] + w2 * (q[1] - q[0]);
+    const float c01 = q[P2] + w2 * (q[P2 + 1] - q[P2]);
+    const float c10 = q[P01] + w2 * (q[P01 + 1] - q[P01]);
+    const float c11 = q[P01 + P2] + w2 * (q[P01 + P2 + 1] - q[P01 + P2]);
+    const float c0 = c00 + w1 * (c01 - c00), c1 = c10 + w1 * (c11 - c10);
+    return c0 + w0 * (c1 - c0);
+  }
   float a[2], b[2], c[2];
   int j0[2], j1[2], j2[2];
 #pragma unroll
@@ -1106,9 +1139,9 @@ __global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, int ngroups, c
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int L0 = g.L0, L1 = g.L1, L2 = g.L2, nL = L0 * L1 * L2;
   const int P2 = L2 + 3, P01 = L1 * P2 + 5;
-  for (int i = tid; i < nL; i += 1024) {
-    const int i2 = i % L2, i1 = (i / L2) % L1, i0 = i / (L1 * L2);
-    tl[i0 * P01 + i1 * P2 + i2] = tmpl[i];
+  for (int r = wave; r < L0 * L1; r += 16) {
+    const int i0 = r / L1, i1 = r % L1;
+    for (int i2 = lane; i2 < L2; i2 += 64) tl[i0 * P01 + i1 * P2 + i2] = tmpl[r * L2 + i2];
   }
   __syncthreads();
   const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;

@@ -74,6 +74,11 @@ _SIGS = {
                          _SZ, _P]),
     "tm_classical_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32]),
     "tm_classical": (_I32, [_P, _DIMS, _P, _P, _DIMS, _P, _I32, _OPTP, _P, _P, _P, _SZ, _P]),
+    "ttm_score_backward_workspace_bytes": (_SZ, [_DIMS, _I32, _I32, _I32]),
+    "ttm_score_backward": (_I32, [_P, _DIMS, _P, _P, _DIMS, _I32, _P, _P, _I32, _P, _P, _I32, _P, _OPTP, _P, _P,
+                                  _P, _SZ, _P]),
+    "ttm_lowpass_workspace_bytes": (_SZ, [_DIMS]),
+    "ttm_lowpass": (_I32, [_P, _DIMS, ctypes.c_float, _I32, _P, _P, _SZ, _P]),
     "ttm_profile_enable": (None, [_I32]),
     "ttm_profile_read": (_I32, [_P, _P, _I32]),
     "ttm_profile_class_name": (ctypes.c_char_p, [_I32]),
@@ -378,6 +383,78 @@ def match(image: torch.Tensor, bank: torch.Tensor, mask: torch.Tensor, order: in
                          bufs.flags.data_ptr(), bufs.C.data_ptr(), bufs.count.data_ptr(), bufs.ws.data_ptr(),
                          bufs.ws.numel(), _stream(dev))
     _check(st, "ttm_match")
+
+
+def lowpass(x: torch.Tensor, sigma: float, periodic: bool = True, out: torch.Tensor | None = None):
+    """``x * h`` for the isotropic low-pass filter (ttm_lowpass): periodic for
+    images, zero-extended for template boxes."""
+    dev = x.device
+    N = _dims(x.shape)
+    out = torch.empty_like(x) if out is None else out
+    nws = lib().ttm_lowpass_workspace_bytes(N)
+    ws = _workspace(nws, dev)
+    st = lib().ttm_lowpass(_dev(x, "x"), N, float(sigma), 1 if periodic else 0, _dev(out, "out"), ws.data_ptr(),
+                           nws, _stream(dev))
+    _check(st, "ttm_lowpass")
+    return out
+
+
+def score_backward(image: torch.Tensor, tmpl: torch.Tensor, mask: torch.Tensor, order: int, quats, weights,
+                   components: torch.Tensor, positions, grad_score: torch.Tensor, opt: Options | None = None,
+                   want_tmpl: bool = True, want_image: bool = True):
+    """Gradient of ``sum_p grad_score[p] F(x_p)`` with respect to the raw
+    template and the image (ttm_score_backward).  Returns (grad_tmpl,
+    grad_image); either is None when not requested."""
+    dev = image.device
+    N = _dims(image.shape)
+    L = _dims(tmpl.shape)
+    q = torch.as_tensor(quats, dtype=torch.float32).contiguous().cpu()
+    w = torch.as_tensor(weights, dtype=torch.float64).contiguous().cpu()
+    nrot = q.shape[0]
+    pos = torch.as_tensor(positions, dtype=torch.int32).reshape(-1, 3).contiguous().to(dev)
+    P = pos.shape[0]
+    gs = grad_score.to(device=dev, dtype=torch.float32).contiguous()
+    if gs.numel() != P:
+        raise ValueError("grad_score needs one value per position")
+    opt = opt or default_options()
+    gt = torch.empty_like(tmpl) if want_tmpl else None
+    gi = torch.empty_like(image) if want_image else None
+    nws = lib().ttm_score_backward_workspace_bytes(L, order, nrot, P)
+    ws = _workspace(nws, dev)
+    st = lib().ttm_score_backward(_dev(image, "image"), N, _dev(tmpl, "tmpl"), _dev(mask, "mask"), L, order,
+                                  q.data_ptr(), w.data_ptr(), nrot, _dev(components, "components"),
+                                  pos.data_ptr(), P, gs.data_ptr(), ctypes.byref(opt),
+                                  gt.data_ptr() if gt is not None else None,
+                                  gi.data_ptr() if gi is not None else None, ws.data_ptr(), nws, _stream(dev))
+    _check(st, "ttm_score_backward")
+    return gt, gi
+
+
+class TTMScore(torch.autograd.Function):
+    """F(x_p) at fixed positions as a differentiable function of the raw
+    template and the image.  Forward: the tensor template and its spectra are
+    rebuilt from the template (ttm_build_tensor_template) and the image is
+    correlated (ttm_correlate); F is read at the positions.  Backward:
+    ttm_score_backward.  Use ``TTMScore.apply(tmpl, image, mask, order,
+    quats, weights, positions, opt)``."""
+
+    @staticmethod
+    def forward(ctx, tmpl, image, mask, order, quats, weights, positions, opt=None):
+        comps, bank = build_tensor_template(tmpl, mask, order, quats, weights, image_shape=image.shape)
+        score, _ = correlate(image, bank, mask, order, opt, want_w=False)
+        pos = torch.as_tensor(positions, dtype=torch.long).reshape(-1, 3).to(image.device)
+        F = score[pos[:, 0], pos[:, 1], pos[:, 2]]
+        ctx.save_for_backward(tmpl, image, mask, comps)
+        ctx.args = (order, quats, weights, pos.to(torch.int32), opt)
+        return F
+
+    @staticmethod
+    def backward(ctx, grad_F):
+        tmpl, image, mask, comps = ctx.saved_tensors
+        order, quats, weights, pos, opt = ctx.args
+        gt, gi = score_backward(image, tmpl, mask, order, quats, weights, comps, pos, grad_F, opt,
+                                want_tmpl=ctx.needs_input_grad[0], want_image=ctx.needs_input_grad[1])
+        return gt, gi, None, None, None, None, None, None
 
 
 def tm_classical(image: torch.Tensor, tmpl: torch.Tensor, mask: torch.Tensor, quats,

@@ -117,3 +117,18 @@ def test_binding_refuses_cpu_tensors():
     t = torch.zeros((16, 16, 16))
     with pytest.raises(ValueError):
         ttm.correlate(t, t, t, 2)
+
+
+def test_lowpass_validation_without_gpu():
+    L = ttm.lib()
+    N = ttm.Dims(16, 16, 16)
+    fake = ctypes.c_void_p(256)
+    big = 1 << 40
+    assert L.ttm_lowpass(None, N, 1.0, 1, fake, fake, big, None) == -1
+    assert L.ttm_lowpass(fake, N, -0.5, 1, fake, fake, big, None) == -1
+    assert L.ttm_lowpass(fake, N, 11.0, 1, fake, fake, big, None) == -1     # radius 33 > 32
+    assert L.ttm_lowpass(fake, N, 1.0, 2, fake, fake, big, None) == -1
+    assert L.ttm_lowpass(fake, ttm.Dims(0, 4, 4), 1.0, 1, fake, fake, big, None) == -2
+    assert L.ttm_lowpass(fake, N, 1.0, 1, fake, fake, 16, None) == -3
+    assert L.ttm_lowpass_workspace_bytes(N) >= 2 * 4 * 16 ** 3
+
