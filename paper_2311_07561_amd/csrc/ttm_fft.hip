@@ -469,6 +469,9 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
   // the block's contiguous RW x H2 tile)
   constexpr int PF = (RW * H2 + 255) / 256;
   constexpr int P2 = row_pitch(N2);             // row pitch of the arrays
+  // rows are unpadded in memory and in the stage: element e of the block's
+  // tile sits at offset e in both
+  static_assert(P2 == H2 && SP == H2, "the tile is contiguous in memory and in LDS");
   const long nvalid = (nrows - r0 < RW ? nrows - r0 : RW) * (long)H2;
   // rows outside the valid region are not read (transformed as zeros)
   bool ld_ok[PF];
@@ -483,7 +486,7 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int e = tid + 256 * i;
-      pf[i] = ld_ok[i] ? Hn[(e / H2) * P2 + (e % H2)] : make_float2(0.0f, 0.0f);
+      pf[i] = ld_ok[i] ? Hn[e] : make_float2(0.0f, 0.0f);
     }
   }
 #pragma unroll 1
@@ -493,7 +496,7 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int e = tid + 256 * i;
-      if (e < RW * H2) stage[(e / H2) * SP + (e % H2)] = pf[i];
+      if (e < RW * H2) stage[e] = pf[i];
     }
     __syncthreads();
     if (it + 1 < npass) {
@@ -501,7 +504,7 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
 #pragma unroll
       for (int i = 0; i < PF; ++i) {
         const int e = tid + 256 * i;
-        pf[i] = ld_ok[i] ? Hn[(e / H2) * P2 + (e % H2)] : make_float2(0.0f, 0.0f);
+        pf[i] = ld_ok[i] ? Hn[e] : make_float2(0.0f, 0.0f);
       }
     }
     float2 z[R2], o[R2];
