@@ -284,7 +284,8 @@ ttm_status ttm_lowpass(const float* in, ttm_dims N, float sigma,
  * not differentiated through storage: the rotations are re-sampled from the
  * template, so the components only supply T_alpha for the image gradient.
  *
- *   image [n0][n1][n2]; tmpl, mask [L0][L1][L2]; quats_host, weights_host,
+ *   image [n0][n1][n2] (any extents: no FFT is involved); tmpl, mask
+ *               [L0][L1][L2]; quats_host, weights_host,
  *   n_rot       the quadrature of the tensor build (same checks)
  *   components  K x [L0][L1][L2] from ttm_build_tensor_template with them
  *   positions   n_pos x 3 int32 device; positions outside the valid region,

@@ -663,9 +663,13 @@ def rotate_trilinear_adjoint(h: np.ndarray, q, L) -> np.ndarray:
 
 def score_at(f, t, m, n: int, quats, weights, xs, eps_v: float = EPS_V_DEFAULT) -> np.ndarray:
     """``F(x)`` at the positions ``xs`` from the raw template: tensor template
-    (Section 3.2), tensor field and Frobenius norm (Section 3.4)."""
+    (Section 3.2), tensor field and Frobenius norm (Section 3.4); 0 outside
+    the valid region, where the score is not defined."""
     T = tensor_template(t, m, n, quats, weights)
-    return score_from_field(tensor_field_at(f, T, m, xs, eps_v), n)
+    xs = np.asarray(xs, dtype=np.int64).reshape(-1, 3)
+    lo, hi = valid_region(np.shape(f), np.shape(t))
+    inside = np.all((xs >= lo) & (xs < hi), axis=1)
+    return np.where(inside, score_from_field(tensor_field_at(f, T, m, xs, eps_v), n), 0.0)
 
 
 def score_grad(f, t, m, n: int, quats, weights, xs, grad_F, eps_v: float = EPS_V_DEFAULT):
@@ -684,8 +688,9 @@ def score_grad(f, t, m, n: int, quats, weights, xs, grad_F, eps_v: float = EPS_V
       ``H1 = sum m h``, ``H2 = sum m h (g - mu)``, ``M = sum m``; then the
       adjoint of the trilinear rotation.
 
-    Where ``w = 0`` (the variance floor) or ``F = 0`` the position contributes
-    nothing.  Returns (grad_t, grad_f)."""
+    Positions outside the valid region (where F is 0 by definition), or where
+    ``w = 0`` (the variance floor) or ``F = 0``, contribute nothing.  Returns
+    (grad_t, grad_f)."""
     f = np.asarray(f, dtype=np.float64)
     t = np.asarray(t, dtype=np.float64)
     m = np.asarray(m, dtype=np.float64)
@@ -710,7 +715,10 @@ def score_grad(f, t, m, n: int, quats, weights, xs, grad_F, eps_v: float = EPS_V
     G = W @ Tf.T
     C = G * w[:, None]
     F = np.sqrt(C ** 2 @ mu_n)
-    ok = (w > 0) & (F > 0)
+    lo, hi = valid_region(N, L)
+    inside = np.all((xs >= lo) & (xs < hi), axis=1)
+    ok = inside & (w > 0) & (F > 0)
+    w = np.where(ok, w, 0.0)
     dC = np.where(ok[:, None], grad_F[:, None] * mu_n[None] * C / np.where(F > 0, F, 1.0)[:, None], 0.0)
     # template tensor
     dT = (dC * w[:, None]).T @ W                                   # (K, L^3)

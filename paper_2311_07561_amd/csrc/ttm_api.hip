@@ -557,7 +557,8 @@ ttm_status ttm_score_backward(const float* image, ttm_dims N, const float* tmpl,
     wsum += weights_host[j];
   }
   if (std::fabs(wsum - 1.0) > 1e-6) return TTM_E_ARG;
-  if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
+  // direct window sums: any image extent holds (no FFT)
+  if (!dims_ok(L) || !dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
   if (out_grad_tmpl && (long)L.n0 * L.n1 * L.n2 > kGradMaxTemplate) return TTM_E_SIZE;
   if (!ws || ws_bytes < ttm_score_backward_workspace_bytes(L, order_n, n_rot, n_pos)) return TTM_E_WORKSPACE;
   Carve c(ws);

@@ -499,8 +499,10 @@ def test_score_gradient_matches_central_differences():
     wts /= wts.sum()
     f = rng.standard_normal((20, 20, 20))
     f += 2.0 * synth.render_copies((20, 20, 20), tm, np.array([[10, 10, 10]]), qs[:1])
-    xs = np.array([[10, 10, 10], [11, 9, 10], [6, 13, 8]])
-    gF = np.array([1.0, -0.5, 0.7])
+    # the last position is outside the valid region: F is 0 there by
+    # definition and it must not contribute
+    xs = np.array([[10, 10, 10], [11, 9, 10], [6, 13, 8], [1, 2, 18]])
+    gF = np.array([1.0, -0.5, 0.7, 2.0])
     gt, gf = O.score_grad(f, t, m, n, qs, wts, xs, gF)
 
     def loss(tt, ff):
@@ -519,7 +521,8 @@ def test_score_gradient_matches_central_differences():
         fq[idx] -= h
         fd = (loss(t, fp) - loss(t, fq)) / (2 * h)
         assert abs(fd - gf[idx]) <= 1e-6 + 1e-5 * abs(fd), (idx, fd, gf[idx])
-    assert gf[1, 1, 18] == 0.0          # outside every window
+    assert gf[1, 1, 18] == 0.0          # outside every valid window
+    assert O.score_at(f, t, m, n, qs, wts, xs)[3] == 0.0
 
 
 # --------------------------------------------------------------------------
