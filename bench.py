@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "TTM tomogram voxels/s & HBM GB/s vs classical TM@10k rotations, same pose accuracy"
 HBM_PEAK_GBPS = 8000.0
+MFMA_F16_PEAK_TFLOPS = 2500.0     # dense fp16 matrix cores
 CSRC = os.path.join(ROOT, "paper_2311_07561_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -83,6 +84,9 @@ def parse():
                    help="0: pose at each peak; 1: best eigenvalue of the 3x3x3 neighbourhood; "
                         "2: best NCC at each neighbour's own rotation")
     p.add_argument("--order6", type=int, default=1, help="also time and score tensor order 6")
+    p.add_argument("--rmap-seeds", type=int, default=10016,
+                   help="also time the all-voxel rotation map with this many seeds (0 = skip)")
+    p.add_argument("--rmap-steps", type=int, default=3)
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU time of the oracle baseline sample (0 = skip)")
     p.add_argument("--seed", type=int, default=2000)
@@ -200,7 +204,43 @@ def run_order(order, wl, img, tmpl, mask, args, ttm, synth, torch, dev, angle, w
     out["_prof"] = prof
     out["_score"] = score
     out["_comps"] = comps
+    out["_bank"] = bank
     return out
+
+
+def run_rotation_map(wl, img, mask, bank, K, args, ttm, synth, torch, dev, angle):
+    """The all-voxel rotation map at the same workload: the correlation with
+    the field kept, the fp16 MFMA seed scan (dominant kernel: 2 V_valid J K
+    flops per launch, K = 35 useful components) and the float64 polish."""
+    N = wl.image.shape
+    L = wl.template.shape
+    J = args.rmap_seeds
+    seeds = torch.as_tensor(synth.super_fibonacci(J).astype(np.float32), device=dev)
+    ws = ttm.rotation_map_workspace(N, L, 4, J, dev)
+    out = ttm.rotation_map(img, bank, mask, 4, seeds, workspace=ws)
+
+    def step():
+        ttm.rotation_map(img, bank, mask, 4, seeds, workspace=ws, out=out)
+
+    ms, prof = time_steps(step, args.rmap_steps, 1, ttm, torch)
+    Vv = (N[0] - L[0] + 1) * (N[1] - L[1] + 1) * (N[2] - L[2] + 1)
+    stages = {k: round(v[0] / args.rmap_steps, 4) for k, v in prof.items() if v[1]}
+    scan_ms = prof["rmap_scan"][0] / prof["rmap_scan"][1]
+    flops = 2.0 * Vv * J * K
+    achieved = flops / (scan_ms / 1e3) / 1e12
+    pos = torch.as_tensor(wl.positions, dtype=torch.long, device=dev)
+    qp = out["quat"][pos[:, 0], pos[:, 1], pos[:, 2]].cpu().numpy()
+    at = [angle(a, q) for a, q in zip(qp, wl.true_quats)]
+    unconv = int(out["unconverged"].cpu()[0])
+    log(f"rotation map ({J} seeds): {ms:.3f} ms, scan {scan_ms:.3f} ms = {achieved:.0f} TFLOP/s")
+    del out, ws
+    return {"n_seeds": J, "ms": round(ms, 4), "voxels_per_s": float(np.prod(N)) / (ms / 1e3),
+            "valid_voxels_per_s": Vv / (ms / 1e3), "stages_ms": stages, "unconverged": unconv,
+            "roofline": {"bound": "mfma", "kernel": "rmap_scan", "dtype": "f16 (f32 accumulate)",
+                         "achieved": round(achieved, 1), "peak": MFMA_F16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(achieved / MFMA_F16_PEAK_TFLOPS, 4),
+                         "flops_per_launch": flops, "avg_launch_ms": round(scan_ms, 4), "traffic": None},
+            "pose_at_planted": err_stats(at)}
 
 
 def main():
@@ -269,6 +309,10 @@ def main():
            "step_model_GBps": round(sum(k["model_bytes_per_step"] for k in kernels.values()) /
                                     (ms_per_step / 1e3) / 1e9, 1)}
 
+    rmap = None
+    if args.rmap_seeds > 0:
+        rmap = run_rotation_map(wl, img, mask, main_run["_bank"], K, args, ttm, synth, torch, dev, angle)
+
     order6 = None
     if args.order6:
         r6 = run_order(6, wl, img, tmpl, mask, args, ttm, synth, torch, dev, angle, False)
@@ -325,6 +369,7 @@ def main():
         "cpu_baseline": cpu,
         "ttm_order4": ttm4,
         "ttm_order6": order6,
+        "rotation_map": rmap,
         "classical": classical,
         "kernels": kernels,
     }

@@ -240,6 +240,52 @@ ttm_status ttm_match(
     hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * All-voxel rotation map (Section 3.4 with Theorem "main"): the rotation at
+ * every voxel of the valid region, not only at peaks, as the dominant
+ * Z-eigenpair of C_n(x) (eq. "Zeigen": max over unit Q of C_n(x) Q^n):
+ *   1. the correlation of ttm_correlate, keeping C_alpha(x) for every valid
+ *      voxel (float32, K planes over the valid box, in the workspace);
+ *   2. a seed scan: phi(x, Q_j) = sum_alpha mu_alpha C_alpha(x) Q_j^alpha at
+ *      every seed Q_j, a [V x K] . [K x J] product on the matrix cores in
+ *      fp16 with float32 accumulation, keeping per voxel the group of 16
+ *      seeds holding the largest value;
+ *   3. a float64 polish per voxel: lambda at those 16 seeds, then the
+ *      safeguarded Newton / shifted power iteration of ttm_recover_pose from
+ *      the best of them.
+ * The seed scan decides only the starting basin: where two local maxima of
+ * phi are within the fp16 rounding of each other the map may hold the
+ * second; elsewhere it is the global maximiser.
+ *
+ *   image, bank, mask, N, L, order_n   as in ttm_correlate
+ *   opt         eps_v, hopm_max_iter, hopm_tol are used
+ *   seeds       n_seeds x 4 float32 device array of quaternions (normalised
+ *               here; sign irrelevant: the order is even); n_seeds a
+ *               multiple of 32 in [32, 131072]
+ *   out_score   [n0][n1][n2] F = |C_n(x)|_F as ttm_correlate, here summed in
+ *               float64 from the stored float32 C_alpha
+ *   out_w       [n0][n1][n2] w, or NULL
+ *   out_quat    [n0][n1][n2][4] float32: the dominant rotation (unit, first
+ *               nonzero component positive); zero outside the valid region;
+ *               the identity where C_n(x) = 0 (w(x) = 0)
+ *   out_lambda  [n0][n1][n2] float32: its Z-eigenvalue C_n(x) q^n; zero
+ *               outside the valid region and where C_n(x) = 0
+ *   out_unconverged  one int32 (device), or NULL: the number of voxels whose
+ *               polish stopped at hopm_max_iter
+ * All outputs are device arrays written on `stream`; the workspace holds
+ * K float32 values per valid voxel (ttm_rotation_map_workspace_bytes).
+ * Errors: TTM_E_ARG (NULL, order, n_seeds, options), TTM_E_SIZE,
+ * TTM_E_WORKSPACE, TTM_E_HIP.
+ * ------------------------------------------------------------------------- */
+size_t ttm_rotation_map_workspace_bytes(ttm_dims N, ttm_dims L,
+                                        int32_t order_n, int32_t n_seeds);
+ttm_status ttm_rotation_map(
+    const float* image, ttm_dims N, const void* bank, ttm_dims L,
+    int32_t order_n, const float* mask, const ttm_options* opt,
+    const float* seeds, int32_t n_seeds, float* out_score, float* out_w,
+    float* out_quat, float* out_lambda, int32_t* out_unconverged, void* ws,
+    size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Classical template matching with rotations (Algorithm 1 with a loop over
  * the rotation list): for every valid voxel
  *   out_best_ncc(x) = max_j c(x, R_j),  c(x,R) = w(x) (f * s_R)(x)
@@ -313,13 +359,14 @@ ttm_status ttm_score_backward(
  * a HIP event pair on its stream around each kernel group, by class:
  *   0 image moments, 1 axis-2 R2C rows, 2 axis-1 forward pencils,
  *   3 pass 1 (axis-0 fan-out), 4 axis-1 inverse pencils, 5 pass 3 (axis-2 C2R
- *   + reduction), 6 peaks, 7 pose, 8 tensor build, 9 classical epilogue.
+ *   + reduction), 6 peaks, 7 pose, 8 tensor build, 9 classical epilogue,
+ *   10 rotation-map seed scan, 11 rotation-map seed table, fills and polish.
  * ttm_profile_read waits for the recorded events, writes the summed
  * milliseconds and launch counts of the first n classes, clears the record
  * and returns the number of classes (or TTM_E_HIP).  Event pairs are created
  * on first use and reused; with profiling off nothing is recorded.
  * ------------------------------------------------------------------------- */
-#define TTM_PROFILE_CLASSES 10
+#define TTM_PROFILE_CLASSES 12
 void ttm_profile_enable(int32_t on);
 int32_t ttm_profile_read(double* ms_out, int64_t* launches_out, int32_t n);
 const char* ttm_profile_class_name(int32_t cls);

@@ -561,6 +561,27 @@ def dominant_z_eigenpair(A: np.ndarray, n: int, n_brute: int = 200000,
     return best_q, best_lam, second
 
 
+def rotation_map_at(f, T, m, n: int, xs, eps_v: float = EPS_V_DEFAULT,
+                    n_brute: int = 100000):
+    """The rotation at each listed voxel rather than only at peaks (Section
+    3.4 read at every position, with Theorem "main"): the dominant
+    Z-eigenpair of ``C_n(x)`` (eq. "Zeigen").  Returns (q (P, 4) canonical,
+    lambda (P,), second (P,)) with ``second`` as in ``dominant_z_eigenpair``.
+    Where ``C_n(x) = 0`` (``w(x) = 0``) every ``Q`` attains ``phi = 0``: the map
+    holds the identity with ``lambda = 0`` (and ``second = 0``)."""
+    C = tensor_field_at(f, T, m, np.asarray(xs), eps_v)
+    P = len(C)
+    qs = np.zeros((P, 4))
+    lams = np.zeros(P)
+    secs = np.zeros(P)
+    for p in range(P):
+        if not np.any(C[p]):
+            qs[p] = (1.0, 0.0, 0.0, 0.0)
+            continue
+        qs[p], lams[p], secs[p] = dominant_z_eigenpair(C[p], n, n_brute=n_brute)
+    return qs, lams, secs
+
+
 def neighbourhood_offsets() -> np.ndarray:
     """The 27 offsets of a 3x3x3 neighbourhood, index k = 9 (d0+1) + 3 (d1+1) + (d2+1)."""
     return np.array([(k // 9 - 1, (k // 3) % 3 - 1, k % 3 - 1) for k in range(27)], dtype=np.int64)

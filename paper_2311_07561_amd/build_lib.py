@@ -20,10 +20,13 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libttm.so")
-SOURCES = ["ttm_fft.hip", "ttm_build.hip", "ttm_pose.hip", "ttm_grad.hip", "ttm_filter.hip", "ttm_api.hip"]
+SOURCES = ["ttm_fft.hip", "ttm_build.hip", "ttm_pose.hip", "ttm_grad.hip", "ttm_filter.hip", "ttm_rmap.hip", "ttm_api.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", f"-I{INCLUDE}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# per-source additions: the matrix-core seed scan keeps its MFMA accumulators
+# in ordinary VGPRs (read directly by the max reduction, no accumulator moves)
+EXTRA = {"ttm_rmap.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def hipcc() -> str:
@@ -35,7 +38,7 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr}")

@@ -50,10 +50,10 @@ static Geo make_geo(const ttm_dims& N, const ttm_dims& L) {
 
 // ---- optional event-pair instrumentation --------------------------------------
 enum ProfClass { PC_STATS = 0, PC_ROWS, PC_PEN_FWD, PC_PASS1, PC_PEN_INV, PC_PASS3, PC_PEAKS, PC_POSE,
-                 PC_BUILD, PC_EPI, PC_COUNT };
+                 PC_BUILD, PC_EPI, PC_RMAP_SCAN, PC_RMAP_POLISH, PC_COUNT };
 static const char* kProfNames[PC_COUNT] = {"image_moments", "r2c_rows", "pencils_fwd", "pass1_fanout",
                                            "pencils_inv", "pass3_c2r_reduce", "peaks", "pose",
-                                           "tensor_build", "classical_epilogue"};
+                                           "tensor_build", "classical_epilogue", "rmap_scan", "rmap_polish"};
 struct Prof {
   std::mutex mu;
   bool on = false;
@@ -312,9 +312,11 @@ size_t ttm_correlate_workspace_bytes(ttm_dims N, ttm_dims L, int32_t K) {
   return c.size();
 }
 
+// out_C (optional): C_alpha over the valid box, [K][W0][W1][W2]; then only w
+// is written here (out_score is not touched)
 static ttm_status correlate_into(const Geo& g, int order_n, int K, const float* image, const float2* bk,
                                  const float* mask, float eps_v, float* out_score, float* out_w, CorrWs& w,
-                                 hipStream_t stream) {
+                                 hipStream_t stream, float* out_C = nullptr) {
   const long half = g.half();
   TTM_PROF(PC_STATS, launch_multiplicities(order_n, w.mu, stream));
   TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream));
@@ -327,7 +329,9 @@ static ttm_status correlate_into(const Geo& g, int order_n, int K, const float* 
   a.H = w.H;
   a.pstride = half;
   a.npairs = K;
-  a.mode = P3_SCORE;
+  a.mode = out_C ? P3_FIELD : P3_SCORE;
+  a.out_C = out_C;
+  a.c_plane = (long)(g.hi0() - g.lo0() + 1) * (g.hi1() - g.lo1() + 1) * (g.n2 - g.L2 + 1);
   a.mu = w.mu;
   a.stats = w.stats;
   a.eps_v = eps_v;
@@ -469,6 +473,64 @@ ttm_status ttm_match(const float* image, ttm_dims N, const void* bank, ttm_dims 
                                       opt->max_peaks, opt->refine, pw.cand_pos, out_count, 0, image, tmpl, mask,
                                       out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, pw.ps,
                                       stream));
+  return TTM_OK;
+}
+
+// --- all-voxel rotation map --------------------------------------------------------
+static long valid_voxels(const Geo& g) {
+  return (long)(g.hi0() - g.lo0() + 1) * (g.hi1() - g.lo1() + 1) * (g.n2 - g.L2 + 1);
+}
+static bool rmap_seeds_ok(int n_seeds) { return n_seeds >= 32 && n_seeds <= kRmapMaxSeeds && n_seeds % 32 == 0; }
+
+struct RmapWs {
+  float* planes; uint4* table; int* group; float* wmap;
+};
+static RmapWs rmap_layout(Carve& c, const Geo& g, int order_n, int K, int n_seeds) {
+  RmapWs w;
+  const long V = valid_voxels(g);
+  w.planes = c.take<float>((size_t)K * V);
+  w.table = c.take<uint4>((size_t)rmap_table_uint4(order_n, n_seeds));
+  w.group = c.take<int>((size_t)V);
+  w.wmap = c.take<float>(g.vol());
+  return w;
+}
+
+size_t ttm_rotation_map_workspace_bytes(ttm_dims N, ttm_dims L, int32_t order_n, int32_t n_seeds) {
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || !dims_ok(N) || !dims_ok(L) || !fits(L, N) || !rmap_seeds_ok(n_seeds)) return 0;
+  const Geo g = make_geo(N, L);
+  Carve c(nullptr);
+  corr_layout(c, g, K);
+  rmap_layout(c, g, order_n, K, n_seeds);
+  return c.size();
+}
+
+ttm_status ttm_rotation_map(const float* image, ttm_dims N, const void* bank, ttm_dims L, int32_t order_n,
+                            const float* mask, const ttm_options* opt, const float* seeds, int32_t n_seeds,
+                            float* out_score, float* out_w, float* out_quat, float* out_lambda,
+                            int32_t* out_unconverged, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!image || !bank || !mask || !opt || !seeds || !out_score || !out_quat || !out_lambda) return TTM_E_ARG;
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || !rmap_seeds_ok(n_seeds)) return TTM_E_ARG;
+  if (!(opt->eps_v >= 0.0f) || opt->hopm_max_iter < 1 || !(opt->hopm_tol > 0.0)) return TTM_E_ARG;
+  if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
+  if (!ws || ws_bytes < ttm_rotation_map_workspace_bytes(N, L, order_n, n_seeds)) return TTM_E_WORKSPACE;
+  const Geo g = make_geo(N, L);
+  Carve c(ws);
+  CorrWs cw = corr_layout(c, g, K);
+  RmapWs rw = rmap_layout(c, g, order_n, K, n_seeds);
+  float* wout = out_w ? out_w : rw.wmap;
+  TTM_CALL(correlate_into(g, order_n, K, image, static_cast<const float2*>(bank), mask, opt->eps_v, out_score,
+                          wout, cw, stream, rw.planes));
+  TTM_PROF(PC_RMAP_POLISH, launch_rmap_table(order_n, seeds, n_seeds, rw.table, stream));
+  TTM_PROF(PC_RMAP_SCAN, launch_rmap_scan(g, order_n, rw.planes, rw.table, n_seeds, rw.group, stream));
+  TTM_PROF(PC_RMAP_POLISH, launch_fill_f32(out_score, g.vol(), 0.0f, stream));
+  TTM_PROF(PC_RMAP_POLISH, launch_fill_f32(out_quat, 4 * g.vol(), 0.0f, stream));
+  TTM_PROF(PC_RMAP_POLISH, launch_fill_f32(out_lambda, g.vol(), 0.0f, stream));
+  if (out_unconverged) TTM_PROF(PC_RMAP_POLISH, launch_fill_i32(out_unconverged, 1, 0, stream));
+  TTM_PROF(PC_RMAP_POLISH, launch_rmap_polish(g, order_n, rw.planes, seeds, rw.group, opt->hopm_max_iter,
+                                              opt->hopm_tol, out_score, out_quat, out_lambda, out_unconverged,
+                                              stream));
   return TTM_OK;
 }
 

@@ -390,6 +390,8 @@ struct P3Geo {
 
 template <int M, int MODE>
 __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
+  constexpr bool SC = MODE == P3_SCORE;                        // score (and optional w) outputs
+  constexpr bool MOM = SC || MODE == P3_FIELD;                  // moment pairs first, then components
   using C = RowCfg<M>;
   constexpr int R1 = C::R1, R2 = C::R2, RW = C::RW, SP = C::SP;
   constexpr int N2 = 2 * M, H2 = M + 1;
@@ -451,7 +453,7 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
     for (int e = tid; e < RW * N2; e += 256) {
       const long r = r0 + e / N2;
       if (r >= nrows) continue;
-      if (MODE == P3_SCORE) {
+      if (SC) {
         A.out_score[r * g.n2 + e % N2] = 0.0f;
         if (A.out_w) A.out_w[r * g.n2 + e % N2] = 0.0f;
       } else {
@@ -461,9 +463,10 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
     return;
   }
 
-  const int npass = MODE == P3_SCORE ? A.npairs + 2 : (MODE == P3_W ? 2 : A.npairs);
-  // pair order: P3_SCORE does M1 (index npairs), M2 (npairs+1), then components
-  auto pair_of = [&](int it) { return MODE == P3_SCORE ? (it < 2 ? A.npairs + it : it - 2) : it; };
+  const int npass = MOM ? A.npairs + 2 : (MODE == P3_W ? 2 : A.npairs);
+  // pair order: P3_SCORE and P3_FIELD do M1 (index npairs), M2 (npairs+1),
+  // then the components
+  auto pair_of = [&](int it) { return MOM ? (it < 2 ? A.npairs + it : it - 2) : it; };
   // software pipeline: the rows of the next pair are fetched into registers
   // while the current pair is transformed (each thread owns a fixed slice of
   // the block's contiguous RW x H2 tile)
@@ -518,7 +521,7 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
       z[b] = make_float2(s.x - q.y, s.y + q.x);
     }
     engineA<M, RW, true>(z, o, stage, twM, p, a);
-    if (MODE == P3_SCORE || MODE == P3_W) {
+    if (MOM || MODE == P3_W) {
       if (it == 0) {
 #pragma unroll
         for (int j = 0; j < R2; ++j) wv[j] = o[j];               // M1 (unscaled)
@@ -533,11 +536,40 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
                               vy > floor_v ? rsqrtf((float)vy) : 0.0f);
         }
       } else {
-        const float mu = A.mu[pair];
+        if (SC) {
+          const float mu = A.mu[pair];
 #pragma unroll
-        for (int j = 0; j < R2; ++j) {
-          acc[j].x += mu * o[j].x * o[j].x;
-          acc[j].y += mu * o[j].y * o[j].y;
+          for (int j = 0; j < R2; ++j) {
+            acc[j].x += mu * o[j].x * o[j].x;
+            acc[j].y += mu * o[j].y * o[j].y;
+          }
+        }
+        if (MODE == P3_FIELD) {
+          // C_alpha = w G_alpha staged with the axis-2 centre shift, then the
+          // valid part of each row stored contiguously in the plane of alpha
+          const float fs = (float)g.inv_vol;
+          __syncthreads();
+#pragma unroll
+          for (int k = 0; k < R2 / R1; ++k)
+#pragma unroll
+            for (int d = 0; d < R1; ++d) {
+              const int n = (a + R1 * k) + R2 * d;
+              const int j = k * R1 + d;
+              ostage[p * OP + ((2 * n + g.c2) & (N2 - 1))] = wv[j].x * o[j].x * fs;
+              ostage[p * OP + ((2 * n + 1 + g.c2) & (N2 - 1))] = wv[j].y * o[j].y * fs;
+            }
+          __syncthreads();
+          const int W1 = g.hi1 - g.lo1 + 1, W2 = g.hi2 - g.lo2 + 1;
+          float* __restrict__ plane = A.out_C + (long)pair * A.c_plane;
+          // row by row (uniform validity), each thread a strided set of columns
+#pragma unroll 1
+          for (int rr = 0; rr < RW; ++rr) {
+            const long r = r0 + rr;
+            if (r >= nrows || !g.row_valid(r)) continue;
+            const int x0 = (int)(r >> g.l1), x1 = (int)(r & (g.n1 - 1));
+            float* __restrict__ prow = plane + ((long)(x0 - g.lo0) * W1 + (x1 - g.lo1)) * W2 - g.lo2;
+            for (int x2 = g.lo2 + tid; x2 <= g.hi2; x2 += 256) prow[x2] = ostage[rr * OP + x2];
+          }
         }
       }
     } else {
@@ -573,9 +605,9 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
   const float fscale = (float)g.inv_vol;
 #pragma unroll 1
   for (int outk = 0; outk < 2; ++outk) {
-    float* dst = outk == 0 ? (MODE == P3_SCORE ? A.out_score : A.out_w) : (MODE == P3_SCORE ? A.out_w : nullptr);
+    float* dst = outk == 0 ? (SC ? A.out_score : A.out_w) : (SC ? A.out_w : nullptr);
     if (dst == nullptr) break;
-    const bool is_w = (MODE == P3_W) || outk == 1;
+    const bool is_w = !SC || outk == 1;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < R2 / R1; ++k)
@@ -629,6 +661,7 @@ static hipError_t pass3_m(const Geo& g, const Pass3Args& a, hipStream_t s) {
     case P3_SCORE: hipLaunchKernelGGL((k_pass3<M, P3_SCORE>), grid, dim3(256), 0, s, q, a); break;
     case P3_W: hipLaunchKernelGGL((k_pass3<M, P3_W>), grid, dim3(256), 0, s, q, a); break;
     case P3_MAX: hipLaunchKernelGGL((k_pass3<M, P3_MAX>), grid, dim3(256), 0, s, q, a); break;
+    case P3_FIELD: hipLaunchKernelGGL((k_pass3<M, P3_FIELD>), grid, dim3(256), 0, s, q, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -16,7 +16,8 @@ inline int num_components(int n) { return (n + 1) * (n + 2) * (n + 3) / 6; }
 inline bool supported_len(int n) { return n >= 16 && n <= 512 && (n & (n - 1)) == 0; }
 
 // Reduction modes of the last inverse pass (axis-2 C2R).
-enum Pass3Mode { P3_SCORE = 0, P3_W = 1, P3_MAX = 2 };
+// P3_FIELD: w (as P3_W) and C_alpha(x) = w(x) G_alpha(x) per component
+enum Pass3Mode { P3_SCORE = 0, P3_W = 1, P3_MAX = 2, P3_FIELD = 3 };
 
 struct Geo {
   int n0, n1, n2;      // image extents
@@ -95,6 +96,8 @@ struct Pass3Args {
   int* best_idx;       // P3_MAX
   int first_index;     // P3_MAX index of pair 0
   int init;            // P3_MAX: 1 = first batch (ignore best/best_idx contents)
+  float* out_C;        // P3_FIELD: planes [npairs][W0][W1][W2] over the valid box
+  long c_plane;        // P3_FIELD: W0 W1 W2
 };
 hipError_t launch_pass3(const Geo& g, const Pass3Args& a, hipStream_t s);
 // classical epilogue: ncc = best * w / V inside the valid region where w > 0
@@ -211,5 +214,20 @@ hipError_t launch_grad_tmpl(const GradGeo& g, const float* image, const float* t
                             const double* stats, const int* pos, int n_pos, const GradWs& w, float* grad_tmpl,
                             hipStream_t s);
 constexpr int kGradMaxTemplate = 32768;
+
+// --- all-voxel rotation map (ttm_rmap.hip) ------------------------------------
+// planes: C_alpha over the valid box, [K][W0][W1][W2] (pass 3 in P3_FIELD mode).
+// n_seeds is a multiple of 32; the table holds rmap_table_uint4 entries.
+constexpr int kRmapMaxSeeds = 131072;
+long rmap_table_uint4(int order_n, int n_seeds);
+hipError_t launch_rmap_table(int order_n, const float* seeds, int n_seeds, uint4* table, hipStream_t s);
+// per valid voxel: the winning group of 16 seeds (2 tile + lane half)
+hipError_t launch_rmap_scan(const Geo& g, int order_n, const float* planes, const uint4* table, int n_seeds,
+                            int* group, hipStream_t s);
+// per valid voxel: the score |C_n(x)|_F, the quaternion and lambda written at
+// the voxel's image index
+hipError_t launch_rmap_polish(const Geo& g, int order_n, const float* planes, const float* seeds,
+                              const int* group, int max_iter, double tol, float* out_score, float* out_quat,
+                              float* out_lambda, int* unconv, hipStream_t s);
 
 }  // namespace ttm

@@ -8,6 +8,7 @@ Functions mirror the C ABI in include/ttm.h:
 * ``build_tensor_template(tmpl, mask, order, quats, weights, image_shape)``
 * ``correlate(image, bank, mask, order, opt)``
 * ``recover_pose(score, image, components, mask, order, opt)``
+* ``rotation_map(image, bank, mask, order, seeds, opt)``
 * ``tm_classical(image, tmpl, mask, quats, opt)``
 """
 from __future__ import annotations
@@ -77,6 +78,9 @@ _SIGS = {
     "ttm_score_backward_workspace_bytes": (_SZ, [_DIMS, _I32, _I32, _I32]),
     "ttm_score_backward": (_I32, [_P, _DIMS, _P, _P, _DIMS, _I32, _P, _P, _I32, _P, _P, _I32, _P, _OPTP, _P, _P,
                                   _P, _SZ, _P]),
+    "ttm_rotation_map_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32, _I32]),
+    "ttm_rotation_map": (_I32, [_P, _DIMS, _P, _DIMS, _I32, _P, _OPTP, _P, _I32, _P, _P, _P, _P, _P, _P, _SZ,
+                                _P]),
     "ttm_lowpass_workspace_bytes": (_SZ, [_DIMS]),
     "ttm_lowpass": (_I32, [_P, _DIMS, ctypes.c_float, _I32, _P, _P, _SZ, _P]),
     "ttm_profile_enable": (None, [_I32]),
@@ -84,7 +88,7 @@ _SIGS = {
     "ttm_profile_class_name": (ctypes.c_char_p, [_I32]),
 }
 
-PROFILE_CLASSES = 10
+PROFILE_CLASSES = 12
 
 
 def profile_enable(on: bool = True):
@@ -147,6 +151,14 @@ def _dev(t: torch.Tensor, name: str) -> int:
         raise ValueError(f"{name} must be a CUDA (HIP) tensor")
     if t.dtype != torch.float32 or not t.is_contiguous():
         raise ValueError(f"{name} must be a contiguous float32 tensor")
+    return t.data_ptr()
+
+
+def _i32_dev(t, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous int32 CUDA (HIP) tensor")
     return t.data_ptr()
 
 
@@ -383,6 +395,50 @@ def match(image: torch.Tensor, bank: torch.Tensor, mask: torch.Tensor, order: in
                          bufs.flags.data_ptr(), bufs.C.data_ptr(), bufs.count.data_ptr(), bufs.ws.data_ptr(),
                          bufs.ws.numel(), _stream(dev))
     _check(st, "ttm_match")
+
+
+def rotation_map_workspace(image_shape, L, order, n_seeds, device) -> torch.Tensor:
+    n = lib().ttm_rotation_map_workspace_bytes(_dims(image_shape), _dims(L), order, int(n_seeds))
+    if n == 0:
+        raise TTMError(-1, "ttm_rotation_map_workspace_bytes")
+    return _workspace(n, device)
+
+
+def rotation_map(image: torch.Tensor, bank: torch.Tensor, mask: torch.Tensor, order: int, seeds,
+                 opt: Options | None = None, want_w: bool = False, workspace: torch.Tensor | None = None,
+                 out: dict | None = None) -> dict:
+    """Dominant rotation and Z-eigenvalue of C_n(x) at every valid voxel.
+    ``seeds`` (n_seeds x 4 quaternions, n_seeds a multiple of 32) is a device
+    tensor or array-like.  Returns (or fills ``out``, a dict of preallocated
+    tensors with the same keys) score [N], w [N] or None, quat [N + (4,)],
+    lam [N] and unconverged (one int32), all device tensors; nothing is
+    synchronised."""
+    dev = image.device
+    N = _dims(image.shape)
+    L = _dims(mask.shape)
+    opt = opt or default_options()
+    if not torch.is_tensor(seeds):
+        seeds = torch.as_tensor(seeds, dtype=torch.float32, device=dev)
+    sd = seeds.to(device=dev, dtype=torch.float32).contiguous()
+    if sd.dim() != 2 or sd.shape[1] != 4:
+        raise ValueError("seeds must be an (n_seeds, 4) array of quaternions")
+    J = int(sd.shape[0])
+    if out is None:
+        shape = tuple(image.shape)
+        out = dict(score=torch.empty(shape, dtype=torch.float32, device=dev),
+                   w=torch.empty(shape, dtype=torch.float32, device=dev) if want_w else None,
+                   quat=torch.empty(shape + (4,), dtype=torch.float32, device=dev),
+                   lam=torch.empty(shape, dtype=torch.float32, device=dev),
+                   unconverged=torch.zeros((1,), dtype=torch.int32, device=dev))
+    ws = workspace if workspace is not None else rotation_map_workspace(image.shape, mask.shape, order, J, dev)
+    w = out.get("w")
+    st = lib().ttm_rotation_map(_dev(image, "image"), N, bank.data_ptr(), L, order, _dev(mask, "mask"),
+                                ctypes.byref(opt), _dev(sd, "seeds"), J, _dev(out["score"], "score"),
+                                _opt_dev(w, "w"), _dev(out["quat"], "quat"), _dev(out["lam"], "lam"),
+                                _i32_dev(out.get("unconverged"), "unconverged"), ws.data_ptr(), ws.numel(),
+                                _stream(dev))
+    _check(st, "ttm_rotation_map")
+    return out
 
 
 def lowpass(x: torch.Tensor, sigma: float, periodic: bool = True, out: torch.Tensor | None = None):

@@ -132,3 +132,30 @@ def test_lowpass_validation_without_gpu():
     assert L.ttm_lowpass(fake, N, 1.0, 1, fake, fake, 16, None) == -3
     assert L.ttm_lowpass_workspace_bytes(N) >= 2 * 4 * 16 ** 3
 
+
+
+def test_rotation_map_validation_without_gpu():
+    L = ttm.lib()
+    N, T = ttm.Dims(64, 64, 64), ttm.Dims(16, 16, 16)
+    o = _opt()
+    fake = ctypes.c_void_p(256)
+    big = 1 << 40
+
+    def call(n_seeds=64, order=4, opt=o, seeds=fake, ws=big, dims=N):
+        return L.ttm_rotation_map(fake, dims, fake, T, order, fake, ctypes.byref(opt), seeds, n_seeds, fake,
+                                  None, fake, fake, None, fake, ws, None)
+
+    assert call(n_seeds=48) == -1            # not a multiple of 32
+    assert call(n_seeds=0) == -1
+    assert call(n_seeds=131072 + 32) == -1
+    assert call(order=3) == -1
+    assert call(seeds=None) == -1
+    assert call(opt=_opt(hopm_max_iter=0)) == -1
+    assert call(dims=ttm.Dims(64, 64, 96)) == -2
+    assert call(ws=1024) == -3
+    assert L.ttm_rotation_map_workspace_bytes(N, T, 4, 48) == 0
+    # workspace: the correlation's, plus K float32 planes over the valid box
+    # (49^3 voxels), the fp16 seed table and one group index per valid voxel
+    V = 49 ** 3
+    need = L.ttm_rotation_map_workspace_bytes(N, T, 4, 64)
+    assert need >= L.ttm_correlate_workspace_bytes(N, T, 35) + 35 * 4 * V + 4 * V + 64 * 48 * 2

@@ -388,17 +388,22 @@ def test_sshopm_reaches_brute_force_maximum():
             assert lam == pytest.approx(np.linalg.eigvalsh(O.unpack_symmetric(A, 2))[-1], abs=1e-10)
 
 
-def test_theorem_main_recovers_planted_rotation():
-    # a noiseless analytic copy at x0 rotated by R*: phi peaks at R* (Theorem "main")
+@pytest.fixture(scope="module")
+def planted_setup():
     # the quadrature must resolve c(x, R) over SO(3): 10^4 rotations (~5 degree
     # spacing) bring the recovered pose within a fraction of a degree
     L, n = 12, 4
     tm = synth.make_blob_template(_rng(50), L, 5, L / 2)
-    t = tm.grid()
     m = synth.ball_mask(L, L / 2)
     qs = synth.super_fibonacci(10000)
     wts = np.full(len(qs), 1.0 / len(qs))
-    T = O.tensor_template(t, m, n, qs, wts)
+    T = O.tensor_template(tm.grid(), m, n, qs, wts)
+    return L, n, tm, m, T
+
+
+def test_theorem_main_recovers_planted_rotation(planted_setup):
+    # a noiseless analytic copy at x0 rotated by R*: phi peaks at R* (Theorem "main")
+    L, n, tm, m, T = planted_setup
     errs = []
     for k, qtrue in enumerate(synth.random_quaternions(_rng(51), 3)):
         x0 = np.array([[12, 12, 12]])
@@ -407,6 +412,28 @@ def test_theorem_main_recovers_planted_rotation():
         q, lam, second = O.dominant_z_eigenpair(C, n, n_brute=60000)
         errs.append(O.rotation_angle_deg(q, qtrue))
     assert max(errs) < 1.0, errs
+
+
+def test_rotation_map_at_planted_copies_flat_window_and_bound(planted_setup):
+    # two noiseless copies with different rotations in one image: at each
+    # copy's centre the map holds that copy's rotation, not the other's
+    # (Theorem "main" position by position); a window in a flat region (w = 0)
+    # holds the identity with lambda = 0; and |lambda| <= F = |C_n(x)|_F at
+    # every voxel (Cauchy-Schwarz with |Q^{(.)n}|_F = 1)
+    L, n, tm, m, T = planted_setup
+    qtrue = synth.random_quaternions(_rng(52), 2)
+    assert O.rotation_angle_deg(qtrue[0], qtrue[1]) > 20.0
+    centres = np.array([[12, 12, 12], [12, 12, 30]])
+    f = synth.render_copies((24, 24, 60), tm, centres, qtrue)
+    xs = np.array([[12, 12, 12], [12, 12, 30], [12, 12, 48], [11, 13, 21]])
+    q, lam, _ = O.rotation_map_at(f, T, m, n, xs, n_brute=60000)
+    assert O.rotation_angle_deg(q[0], qtrue[0]) < 1.0
+    assert O.rotation_angle_deg(q[1], qtrue[1]) < 1.0
+    assert np.array_equal(q[2], [1.0, 0.0, 0.0, 0.0]) and lam[2] == 0.0
+    F = O.score_from_field(O.tensor_field_at(f, T, m, xs), n)
+    assert F[2] == 0.0
+    assert np.all(np.abs(lam) <= F + 1e-12)
+    assert lam[0] > 0.0 and lam[1] > 0.0
 
 
 # --------------------------------------------------------------------------
