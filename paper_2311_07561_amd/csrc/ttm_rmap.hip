@@ -15,6 +15,8 @@
 // 2. Polish in float64, one lane per voxel: lambda at the 16 seeds of the
 //    winning group, then the safeguarded Newton / shifted power iteration
 //    from the best of them.
+#include <cfloat>
+
 #include "ttm_device.h"
 #include "ttm_eig.h"
 #include "ttm_internal.h"
@@ -68,7 +70,7 @@ __global__ void __launch_bounds__(256) k_rmap_table(const float* __restrict__ se
 // operands in registers for the whole scan.  The seed table streams through
 // two LDS chunks of CT tiles (global loads of the next chunk are in flight
 // while the current one is multiplied).  Output per voxel: the winning group
-// 2 t + h (tile t, lane half h), ties to the lower group.
+// 2 t + h (tile t, lane half h).
 template <int KS>
 struct ScanCfg {
   static constexpr int KG = 2 * KS;                 // 8-element groups per seed row
@@ -82,7 +84,7 @@ struct ScanCfg {
 
 template <int KS>
 __global__ void __launch_bounds__(256) k_rmap_scan(const float* __restrict__ planes, long Vv, int K,
-                                                   const uint4* __restrict__ table, int ntiles,
+                                                   const uint4* __restrict__ table, int ntiles, int tbits,
                                                    int* __restrict__ group_out) {
   using S = ScanCfg<KS>;
   constexpr int VT = S::VT, TILE16 = S::TILE16, CT = S::CT, CH16 = S::CH16, PFN = S::PFN;
@@ -124,13 +126,14 @@ __global__ void __launch_bounds__(256) k_rmap_scan(const float* __restrict__ pla
       for (int e = 0; e < 8; ++e) b[v][s][e] = (_Float16)(cv[s][e] * sc);
   }
 
+  // running best per voxel tile as a key: the tile's maximum with its low
+  // tbits mantissa bits replaced by the tile index, so that one maximum keeps
+  // both (the keys order as the maxima do up to 2^(tbits - 24) relative, far
+  // below the fp16 rounding of the products)
+  const unsigned tmask = (1u << tbits) - 1u;
   float best[VT];
-  int bt[VT];
 #pragma unroll
-  for (int v = 0; v < VT; ++v) {
-    best[v] = -INFINITY;
-    bt[v] = 0;
-  }
+  for (int v = 0; v < VT; ++v) best[v] = -FLT_MAX;
   const int nch = (ntiles + CT - 1) / CT;
   const long tab16 = (long)ntiles * TILE16;
   uint4 pf[PFN];
@@ -171,27 +174,27 @@ __global__ void __launch_bounds__(256) k_rmap_scan(const float* __restrict__ pla
         f32x16 acc = {};
 #pragma unroll
         for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[s], b[v][s], acc, 0, 0, 0);
-        float m = fmaxf(fmaxf(acc[0], acc[1]), acc[2]);
+        float m = __builtin_elementwise_maximum(__builtin_elementwise_maximum(acc[0], acc[1]), acc[2]);
 #pragma unroll
-        for (int r = 3; r < 15; r += 2) m = fmaxf(fmaxf(m, acc[r]), acc[r + 1]);
-        m = fmaxf(m, acc[15]);
-        if (m > best[v]) {
-          best[v] = m;
-          bt[v] = tile;
-        }
+        for (int r = 3; r < 15; r += 2)
+          m = __builtin_elementwise_maximum(__builtin_elementwise_maximum(m, acc[r]), acc[r + 1]);
+        m = __builtin_elementwise_maximum(m, acc[15]);
+        const float key = __uint_as_float((__float_as_uint(m) & ~tmask) | (unsigned)tile);
+        best[v] = __builtin_elementwise_maximum(best[v], key);
       }
     }
   }
-  // merge the two lane halves of each voxel: the larger maximum, then the
-  // lower tile, then half 0
+  // merge the two lane halves of each voxel: the larger key, half 0 on equal
+  // keys (the tile index is clamped in case a non-finite input made the key
+  // NaN)
 #pragma unroll
   for (int v = 0; v < VT; ++v) {
     const float ob = __shfl_xor(best[v], 32);
-    const int ot = __shfl_xor(bt[v], 32);
     const long vox = vbase + v * 32 + j;
     if (h == 0 && vox < Vv) {
-      const bool mine = best[v] > ob || (best[v] == ob && bt[v] <= ot) || !(ob == ob);
-      group_out[vox] = mine ? 2 * bt[v] : 2 * ot + 1;
+      const bool mine = !(ob > best[v]);
+      const int t = (int)(__float_as_uint(mine ? best[v] : ob) & tmask);
+      group_out[vox] = 2 * (t < ntiles ? t : ntiles - 1) + (mine ? 0 : 1);
     }
   }
 }
@@ -320,7 +323,9 @@ template <int KS>
 static void scan_ks(long Vv, int K, const float* planes, const uint4* table, int ntiles, int* group,
                     hipStream_t s) {
   const dim3 sg((unsigned)((Vv + ScanCfg<KS>::VOX - 1) / ScanCfg<KS>::VOX));
-  hipLaunchKernelGGL(k_rmap_scan<KS>, sg, dim3(256), 0, s, planes, Vv, K, table, ntiles, group);
+  int tbits = 1;
+  while ((1 << tbits) < ntiles) ++tbits;
+  hipLaunchKernelGGL(k_rmap_scan<KS>, sg, dim3(256), 0, s, planes, Vv, K, table, ntiles, tbits, group);
 }
 
 hipError_t launch_rmap_scan(const Geo& gg, int order_n, const float* planes, const uint4* table, int n_seeds,
