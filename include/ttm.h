@@ -178,7 +178,9 @@ ttm_status ttm_correlate(
  * mask (Section 2, Algorithm 1; float64 sums), and the voxel with the largest
  * NCC is reported (ties: the centre, then the lower neighbour index).
  *
- *   score            [n0][n1][n2] float32 from ttm_correlate
+ *   score            [n0][n1][n2] float32 from ttm_correlate or
+ *                    ttm_correlate_tiled (no FFT here: any extents n_i >= L_i,
+ *                    n_i <= 8192, volume < 2^31)
  *   image            the correlated image; components: K x [L0][L1][L2] float32
  *   mask             the mask used for the components
  *   tmpl             the raw template [L0][L1][L2] float32 the components were
@@ -284,6 +286,108 @@ ttm_status ttm_rotation_map(
     const float* seeds, int32_t n_seeds, float* out_score, float* out_w,
     float* out_quat, float* out_lambda, int32_t* out_unconverged, void* ws,
     size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Tomograms of any extent: overlap-save tiling onto power-of-two FFT tiles.
+ * The correlation of Section 2 (ttm_correlate's score F and w) is computed on
+ * cubic tiles of edge T (a supported length, T >= each template extent).
+ * Tiles step by T - L + 1 per axis, so the positions where a tile's window
+ * lies inside the tile partition the image's valid region; positions whose
+ * window leaves the image are dropped and the maps are 0 there (as for
+ * ttm_correlate).  The image statistics (mean shift, variance floor of
+ * ttm_options.eps_v, mask sum) are those of the whole image, so the result is
+ * ttm_correlate's for any tiling, up to float32 rounding.  The bank is the
+ * template's built with image_shape = (T, T, T).
+ *
+ *   image      [n0][n1][n2] float32, any extents with n_i >= L_i, n_i <= 8192,
+ *              volume < 2^31
+ *   out_score  [n0][n1][n2]; out_w likewise or NULL
+ * Workspace from ttm_correlate_tiled_workspace_bytes (independent of the
+ * image size).  ttm_tile_count returns the number of tiles (or TTM_E_SIZE).
+ * ttm_recover_pose and ttm_pose_at accept the same image extents.
+ * Errors: TTM_E_ARG, TTM_E_SIZE, TTM_E_WORKSPACE, TTM_E_HIP.
+ * ------------------------------------------------------------------------- */
+int32_t ttm_tile_count(ttm_dims N, ttm_dims L, int32_t T);
+size_t ttm_correlate_tiled_workspace_bytes(ttm_dims L, int32_t order_n,
+                                           int32_t T);
+ttm_status ttm_correlate_tiled(
+    const float* image, ttm_dims N, const void* bank, ttm_dims L,
+    int32_t order_n, int32_t T, const float* mask, const ttm_options* opt,
+    float* out_score, float* out_w, void* ws, size_t ws_bytes,
+    hipStream_t stream);
+
+/* Autotuner of the tile schedule (no counterpart in the paper).
+ * ttm_autotune_tiles times one tile correlation (gather, the FFT passes of
+ * the tile edge with their radix plan, scatter) for each candidate edge
+ * tiles_host[i] with the template's bank banks_host[i] (built for that
+ * edge), `repeats` times after one untimed run, and writes the median
+ * milliseconds to ms_host[i].  It synchronises `stream`.  Workspace from
+ * ttm_autotune_workspace_bytes.
+ * ttm_choose_tile returns the candidate edge minimising
+ * ttm_tile_count(N, L, T) x ms (the larger edge on ties), or TTM_E_SIZE when
+ * none fits.  Host only. */
+size_t ttm_autotune_workspace_bytes(ttm_dims L, int32_t order_n,
+                                    const int32_t* tiles_host, int32_t n);
+ttm_status ttm_autotune_tiles(
+    const void* const* banks_host, const int32_t* tiles_host, int32_t n,
+    ttm_dims L, int32_t order_n, const float* mask, const ttm_options* opt,
+    int32_t repeats, float* ms_host, void* ws, size_t ws_bytes,
+    hipStream_t stream);
+int32_t ttm_choose_tile(ttm_dims N, ttm_dims L, const int32_t* tiles_host,
+                        const float* ms_host, int32_t n);
+
+/* ---------------------------------------------------------------------------
+ * Batches of tomograms and templates of uneven sizes (no counterpart in the
+ * paper).  A job is one tomogram against one template: the tiled correlation
+ * above at the job's tile edge, then ttm_recover_pose on the stitched score
+ * map (peaks, C_n(x) from direct float64 window sums, the eigenpair, the
+ * refinement of opt->refine).  ttm_batch_match runs the jobs eagerly, one
+ * after another on `stream`, sharing one workspace.  ttm_batch_graph_create
+ * records them into one hipGraph by stream capture (stream must be a created
+ * stream, not the legacy default; profiling records nothing while
+ * capturing): the jobs are split over n_streams branches (1..8, longest jobs
+ * first onto the least loaded branch, a job's cost taken as its tiles times
+ * the tile volume) that run concurrently, each with its own slice of the
+ * workspace; ttm_graph_launch replays the graph as one launch on any stream.
+ * ttm_batch_workspace_bytes gives n_streams times the largest job's need
+ * (n_streams = 1 for ttm_batch_match).  The graph holds the job
+ * descriptors' pointers and the workspace: they must stay valid, and be used
+ * by nothing else while a replay runs.  Outputs per job as
+ * ttm_recover_pose's (max_peaks rows; out_C is not produced).
+ * Errors: TTM_E_ARG, TTM_E_SIZE, TTM_E_WORKSPACE, TTM_E_HIP.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const float* image;        /* [n0][n1][n2] device */
+  ttm_dims N;
+  const void* bank;          /* the template's bank at (tile, tile, tile) */
+  int32_t tile;              /* tile edge T */
+  const float* components;   /* K x [L0][L1][L2] */
+  const float* mask;         /* [L0][L1][L2] */
+  const float* tmpl;         /* [L0][L1][L2], needed with refine = 2 */
+  ttm_dims L;
+  float* out_score;          /* [n0][n1][n2] */
+  float* out_w;              /* [n0][n1][n2] or NULL */
+  int32_t* out_pos;          /* max_peaks x 3 */
+  float* out_quat;           /* max_peaks x 4 */
+  double* out_lambda;        /* max_peaks */
+  float* out_peak_score;     /* max_peaks */
+  int32_t* out_flags;        /* max_peaks */
+  int32_t* out_count;        /* 2 */
+} ttm_batch_job;
+typedef struct ttm_graph_s* ttm_graph;
+size_t ttm_batch_workspace_bytes(const ttm_batch_job* jobs_host,
+                                 int32_t n_jobs, int32_t order_n,
+                                 const ttm_options* opt, int32_t n_streams);
+ttm_status ttm_batch_match(const ttm_batch_job* jobs_host, int32_t n_jobs,
+                           int32_t order_n, const ttm_options* opt, void* ws,
+                           size_t ws_bytes, hipStream_t stream);
+ttm_status ttm_batch_graph_create(const ttm_batch_job* jobs_host,
+                                  int32_t n_jobs, int32_t order_n,
+                                  const ttm_options* opt, int32_t n_streams,
+                                  void* ws, size_t ws_bytes,
+                                  hipStream_t stream, ttm_graph* out_graph);
+ttm_status ttm_graph_launch(ttm_graph graph, hipStream_t stream);
+void ttm_graph_destroy(ttm_graph graph);
 
 /* ---------------------------------------------------------------------------
  * Classical template matching with rotations (Algorithm 1 with a loop over

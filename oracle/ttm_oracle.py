@@ -9,7 +9,7 @@ implementation written from the paper (Almira, Phelippeau, Martinez-Sanchez,
 arXiv 2311.07561).  Every correlation is a *direct spatial sum* (no FFT), every
 reduction is in float64, and each function cites the passage it follows.
 
-Readings of points where the paper is silent (listed in the design doc as well):
+Readings of points where the paper is silent:
 
 * grid: C-order ``[n0][n1][n2]``; correlation is circular,
   ``(f * g)(x) = sum_u f((x + u - c) mod N) g(u)`` with ``c = L // 2`` the

@@ -1,6 +1,7 @@
 // The extern "C" entry points of libttm: argument validation on the host,
 // workspace carving, and the launch sequence of each call (all asynchronous on
 // the caller's stream).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -73,6 +74,8 @@ struct ProfScope {
     Prof& p = prof();
     std::lock_guard<std::mutex> g(p.mu);
     if (!p.on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     if (p.used.size() == p.pool.size()) {
       hipEvent_t a, b;
       if (hipEventCreate(&a) != hipSuccess) return;
@@ -179,12 +182,16 @@ static ClassWs class_layout(Carve& c, const Geo& g, int nrot) {
 }
 
 // forward axis-2 and axis-1 transforms of the image and of its square
+// stats_in (optional): the image statistics (mean, variance, mask sum) taken
+// elsewhere (the whole image of a tile); otherwise they are computed here
 static ttm_status image_forward(const Geo& g, const float* image, float2* Xf, float2* Xg,
-                                double* stats, double* partials, const float* mask, hipStream_t stream) {
+                                double* stats, double* partials, const float* mask, hipStream_t stream,
+                                const double* stats_in = nullptr) {
   const long L3 = (long)g.L0 * g.L1 * g.L2;
   const long rows = (long)g.n0 * g.n1;
-  TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), mask, L3, partials, stats, stream));
-  TTM_PROF(PC_ROWS, launch_r2c_rows(g.n2, image, g.n2, g.n2, rows, Xf, Xg, rows, 0, 1, stats, stream));
+  if (!stats_in) TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), mask, L3, partials, stats, stream));
+  const double* st = stats_in ? stats_in : stats;
+  TTM_PROF(PC_ROWS, launch_r2c_rows(g.n2, image, g.n2, g.n2, rows, Xf, Xg, rows, 0, 1, st, stream));
   TTM_PROF(PC_PEN_FWD, launch_pencils(g.n1, false, Xf, (long)g.n0 * g.p2, g.p2, (long)g.n1 * g.p2, g.p2, g.n1, 0,
                                       0, g.n1 - 1, 2, (long)(Xg - Xf), stream));
   return TTM_OK;
@@ -313,13 +320,14 @@ size_t ttm_correlate_workspace_bytes(ttm_dims N, ttm_dims L, int32_t K) {
 }
 
 // out_C (optional): C_alpha over the valid box, [K][W0][W1][W2]; then only w
-// is written here (out_score is not touched)
+// is written here (out_score is not touched).  stats_in (optional): image
+// statistics taken elsewhere (see image_forward).
 static ttm_status correlate_into(const Geo& g, int order_n, int K, const float* image, const float2* bk,
                                  const float* mask, float eps_v, float* out_score, float* out_w, CorrWs& w,
-                                 hipStream_t stream, float* out_C = nullptr) {
+                                 hipStream_t stream, float* out_C = nullptr, const double* stats_in = nullptr) {
   const long half = g.half();
   TTM_PROF(PC_STATS, launch_multiplicities(order_n, w.mu, stream));
-  TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream));
+  TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream, stats_in));
   // K components and the mask against f, then the mask against f^2
   const Pass1Args p1{w.Xf, bk, K + 1, w.Xg, bk + (long)K * g.bank_slab(), 1, g.bank_slab(), w.H, half};
   TTM_PROF(PC_PASS1, launch_pass1(g, p1, stream));
@@ -333,7 +341,7 @@ static ttm_status correlate_into(const Geo& g, int order_n, int K, const float* 
   a.out_C = out_C;
   a.c_plane = (long)(g.hi0() - g.lo0() + 1) * (g.hi1() - g.lo1() + 1) * (g.n2 - g.L2 + 1);
   a.mu = w.mu;
-  a.stats = w.stats;
+  a.stats = stats_in ? stats_in : w.stats;
   a.eps_v = eps_v;
   a.out_score = out_score;
   a.out_w = out_w;
@@ -375,22 +383,11 @@ size_t ttm_pose_workspace_bytes(ttm_dims N, ttm_dims L, int32_t order_n, const t
   return c.size();
 }
 
-ttm_status ttm_recover_pose(const float* score, const float* image, const float* components, const float* mask,
-                            const float* tmpl, ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt,
-                            int32_t* out_pos, float* out_quat, double* out_lambda, float* out_peak_score,
-                            int32_t* out_flags, double* out_C, int32_t* out_count, void* ws, size_t ws_bytes,
-                            hipStream_t stream) {
-  if (!score || !image || !components || !mask || !opt || !out_pos || !out_quat || !out_lambda ||
-      !out_peak_score || !out_flags || !out_count)
-    return TTM_E_ARG;
-  if (opt->refine == 2 && !tmpl) return TTM_E_ARG;
-  const int K = ttm_num_components(order_n);
-  if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
-  if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
-  if (!ws || ws_bytes < ttm_pose_workspace_bytes(N, L, order_n, opt)) return TTM_E_WORKSPACE;
-  const Geo g = make_geo(N, L);
-  Carve c(ws);
-  PoseWs w = pose_layout(c, g, opt->max_peaks, K, opt->refine, opt->n_seeds);
+static ttm_status recover_pose_into(const Geo& g, const float* score, const float* image, const float* components,
+                                    const float* mask, const float* tmpl, int order_n, int K, const ttm_options* opt,
+                                    int32_t* out_pos, float* out_quat, double* out_lambda, float* out_peak_score,
+                                    int32_t* out_flags, double* out_C, int32_t* out_count, PoseWs& w,
+                                    hipStream_t stream) {
   TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), nullptr, 0, w.partials, w.stats, stream));
   PeakWs pw{w.hist, w.ctrl, w.allc, w.cand};
   float* cand_score = reinterpret_cast<float*>(w.ps.w);   // overwritten later by the pose scratch
@@ -405,6 +402,33 @@ ttm_status ttm_recover_pose(const float* score, const float* image, const float*
   return TTM_OK;
 }
 
+// extents of images that are not transformed as a whole (pose, tiled
+// correlation): any size >= 1 with a volume below 2^31 (peak keys hold a
+// 32-bit linear index)
+static bool any_dims_ok(const ttm_dims& N) {
+  return dims_ok(N) && N.n0 <= 8192 && N.n1 <= 8192 && N.n2 <= 8192 && (long)N.n0 * N.n1 * N.n2 < (1L << 31);
+}
+
+ttm_status ttm_recover_pose(const float* score, const float* image, const float* components, const float* mask,
+                            const float* tmpl, ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt,
+                            int32_t* out_pos, float* out_quat, double* out_lambda, float* out_peak_score,
+                            int32_t* out_flags, double* out_C, int32_t* out_count, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+  if (!score || !image || !components || !mask || !opt || !out_pos || !out_quat || !out_lambda ||
+      !out_peak_score || !out_flags || !out_count)
+    return TTM_E_ARG;
+  if (opt->refine == 2 && !tmpl) return TTM_E_ARG;
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
+  if (!dims_ok(L) || !any_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
+  if (!ws || ws_bytes < ttm_pose_workspace_bytes(N, L, order_n, opt)) return TTM_E_WORKSPACE;
+  const Geo g = make_geo(N, L);
+  Carve c(ws);
+  PoseWs w = pose_layout(c, g, opt->max_peaks, K, opt->refine, opt->n_seeds);
+  return recover_pose_into(g, score, image, components, mask, tmpl, order_n, K, opt, out_pos, out_quat, out_lambda,
+                           out_peak_score, out_flags, out_C, out_count, w, stream);
+}
+
 ttm_status ttm_pose_at(const float* image, const float* components, const float* mask, const float* tmpl,
                        ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt, const int32_t* positions,
                        int32_t n_pos, int32_t* out_pos, float* out_quat, double* out_lambda, int32_t* out_flags,
@@ -416,7 +440,7 @@ ttm_status ttm_pose_at(const float* image, const float* components, const float*
   const int K = ttm_num_components(order_n);
   if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
   if (n_pos < 0 || n_pos > opt->max_peaks) return TTM_E_ARG;
-  if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
+  if (!dims_ok(L) || !any_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
   if (!ws || ws_bytes < ttm_pose_workspace_bytes(N, L, order_n, opt)) return TTM_E_WORKSPACE;
   if (n_pos == 0) return TTM_OK;
   const Geo g = make_geo(N, L);
@@ -474,6 +498,351 @@ ttm_status ttm_match(const float* image, ttm_dims N, const void* bank, ttm_dims 
                                       out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, pw.ps,
                                       stream));
   return TTM_OK;
+}
+
+// --- overlap-save tiled correlation, batches, graphs ---------------------------------
+static bool tile_ok(int T, const ttm_dims& L) {
+  return supported_len(T) && T >= L.n0 && T >= L.n1 && T >= L.n2;
+}
+static long tiles_along(int n, int l, int T) {
+  const long W = (long)n - l + 1, WT = (long)T - l + 1;
+  return (W + WT - 1) / WT;
+}
+
+struct TiledWs {
+  float* tile; float* tscore; float* tw; double* stats; double* partials; CorrWs corr;
+};
+static TiledWs tiled_layout(Carve& c, int T, const ttm_dims& L, int K) {
+  TiledWs w;
+  const Geo gT = make_geo(ttm_dims{T, T, T}, L);
+  const size_t T3 = (size_t)T * T * T;
+  w.tile = c.take<float>(T3);
+  w.tscore = c.take<float>(T3);
+  w.tw = c.take<float>(T3);
+  w.stats = c.take<double>(4);
+  w.partials = c.take<double>(3 * kStatPartials);
+  w.corr = corr_layout(c, gT, K);
+  return w;
+}
+
+// the whole image's statistics once, then per tile: gather, correlate (with
+// those statistics), scatter of the tile's valid part
+static ttm_status correlate_tiled_into(const float* image, const ttm_dims& N, const float2* bank, const ttm_dims& L,
+                                       int order_n, int K, int T, const float* mask, float eps_v, float* out_score,
+                                       float* out_w, TiledWs& w, hipStream_t stream) {
+  const Geo gT = make_geo(ttm_dims{T, T, T}, L);
+  const long vol = (long)N.n0 * N.n1 * N.n2;
+  TTM_PROF(PC_STATS, launch_image_stats(image, vol, mask, (long)L.n0 * L.n1 * L.n2, w.partials, w.stats, stream));
+  TTM_PROF(PC_EPI, launch_fill_f32(out_score, vol, 0.0f, stream));
+  if (out_w) TTM_PROF(PC_EPI, launch_fill_f32(out_w, vol, 0.0f, stream));
+  TileGeo tg;
+  tg.n0 = N.n0; tg.n1 = N.n1; tg.n2 = N.n2;
+  tg.T = T;
+  tg.L0 = L.n0; tg.L1 = L.n1; tg.L2 = L.n2;
+  tg.c0 = L.n0 / 2; tg.c1 = L.n1 / 2; tg.c2 = L.n2 / 2;
+  const long k0n = tiles_along(N.n0, L.n0, T), k1n = tiles_along(N.n1, L.n1, T), k2n = tiles_along(N.n2, L.n2, T);
+  for (long k0 = 0; k0 < k0n; ++k0)
+    for (long k1 = 0; k1 < k1n; ++k1)
+      for (long k2 = 0; k2 < k2n; ++k2) {
+        tg.o0 = (int)(k0 * (T - L.n0 + 1));
+        tg.o1 = (int)(k1 * (T - L.n1 + 1));
+        tg.o2 = (int)(k2 * (T - L.n2 + 1));
+        TTM_PROF(PC_EPI, launch_tile_gather(image, tg, w.tile, stream));
+        TTM_CALL(correlate_into(gT, order_n, K, w.tile, bank, mask, eps_v, w.tscore, w.tw, w.corr, stream, nullptr,
+                                w.stats));
+        TTM_PROF(PC_EPI, launch_tile_scatter(w.tscore, w.tw, tg, out_score, out_w, stream));
+      }
+  return TTM_OK;
+}
+
+int32_t ttm_tile_count(ttm_dims N, ttm_dims L, int32_t T) {
+  if (!any_dims_ok(N) || !dims_ok(L) || !fits(L, N) || !tile_ok(T, L)) return TTM_E_SIZE;
+  const long n = tiles_along(N.n0, L.n0, T) * tiles_along(N.n1, L.n1, T) * tiles_along(N.n2, L.n2, T);
+  return n > 0x7fffffffL ? TTM_E_SIZE : (int32_t)n;
+}
+
+int32_t ttm_choose_tile(ttm_dims N, ttm_dims L, const int32_t* tiles_host, const float* ms_host, int32_t n) {
+  if (!tiles_host || !ms_host || n < 1) return TTM_E_ARG;
+  int best = TTM_E_SIZE;
+  double best_cost = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const int cnt = ttm_tile_count(N, L, tiles_host[i]);
+    if (cnt <= 0 || !(ms_host[i] > 0.0f)) continue;
+    const double cost = (double)cnt * ms_host[i];
+    // the cheaper plan; the larger tile on equal cost
+    if (best < 0 || cost < best_cost || (cost == best_cost && tiles_host[i] > best)) {
+      best = tiles_host[i];
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
+size_t ttm_correlate_tiled_workspace_bytes(ttm_dims L, int32_t order_n, int32_t T) {
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || !dims_ok(L) || !tile_ok(T, L)) return 0;
+  Carve c(nullptr);
+  tiled_layout(c, T, L, K);
+  return c.size();
+}
+
+ttm_status ttm_correlate_tiled(const float* image, ttm_dims N, const void* bank, ttm_dims L, int32_t order_n,
+                               int32_t T, const float* mask, const ttm_options* opt, float* out_score, float* out_w,
+                               void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!image || !bank || !mask || !opt || !out_score) return TTM_E_ARG;
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || !(opt->eps_v >= 0.0f)) return TTM_E_ARG;
+  if (!dims_ok(L) || !any_dims_ok(N) || !fits(L, N) || !tile_ok(T, L)) return TTM_E_SIZE;
+  if (!ws || ws_bytes < ttm_correlate_tiled_workspace_bytes(L, order_n, T)) return TTM_E_WORKSPACE;
+  Carve c(ws);
+  TiledWs w = tiled_layout(c, T, L, K);
+  return correlate_tiled_into(image, N, static_cast<const float2*>(bank), L, order_n, K, T, mask, opt->eps_v,
+                              out_score, out_w, w, stream);
+}
+
+size_t ttm_autotune_workspace_bytes(ttm_dims L, int32_t order_n, const int32_t* tiles_host, int32_t n) {
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || !dims_ok(L) || !tiles_host || n < 1) return 0;
+  size_t need = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!tile_ok(tiles_host[i], L)) return 0;
+    Carve c(nullptr);
+    tiled_layout(c, tiles_host[i], L, K);
+    const size_t T3 = (size_t)tiles_host[i] * tiles_host[i] * tiles_host[i];
+    c.take<float>(T3);
+    c.take<float>(T3);
+    need = std::max(need, c.size());
+  }
+  return need;
+}
+
+ttm_status ttm_autotune_tiles(const void* const* banks_host, const int32_t* tiles_host, int32_t n, ttm_dims L,
+                              int32_t order_n, const float* mask, const ttm_options* opt, int32_t repeats,
+                              float* ms_host, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!banks_host || !tiles_host || !mask || !opt || !ms_host || n < 1 || repeats < 1) return TTM_E_ARG;
+  const int K = ttm_num_components(order_n);
+  if (K < 0) return TTM_E_ARG;
+  if (!dims_ok(L)) return TTM_E_SIZE;
+  for (int i = 0; i < n; ++i) {
+    if (!banks_host[i]) return TTM_E_ARG;
+    if (!tile_ok(tiles_host[i], L)) return TTM_E_SIZE;
+  }
+  if (!ws || ws_bytes < ttm_autotune_workspace_bytes(L, order_n, tiles_host, n)) return TTM_E_WORKSPACE;
+  hipEvent_t e0, e1;
+  TTM_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return TTM_E_HIP;
+  }
+  ttm_status st = TTM_OK;
+  for (int i = 0; i < n && st == TTM_OK; ++i) {
+    const int T = tiles_host[i];
+    Carve c(ws);
+    TiledWs w = tiled_layout(c, T, L, K);
+    const long T3 = (long)T * T * T;
+    float* img = c.take<float>((size_t)T3);
+    float* out = c.take<float>((size_t)T3);
+    const ttm_dims NT{T, T, T};
+    // an image of one tile (zeros: the passes do the same work for any
+    // values), timed `repeats` times after one untimed run; the median is kept
+    std::vector<float> ms;
+    if (launch_fill_f32(img, T3, 0.0f, stream) != hipSuccess) st = TTM_E_HIP;
+    for (int r = 0; r <= repeats && st == TTM_OK; ++r) {
+      if (hipEventRecord(e0, stream) != hipSuccess) {
+        st = TTM_E_HIP;
+        break;
+      }
+      st = correlate_tiled_into(img, NT, static_cast<const float2*>(banks_host[i]), L, order_n, K, T, mask,
+                                opt->eps_v, out, nullptr, w, stream);
+      if (st != TTM_OK) break;
+      float t = 0.0f;
+      if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+        st = TTM_E_HIP;
+        break;
+      }
+      if (r > 0) ms.push_back(t);
+    }
+    if (st == TTM_OK) {
+      std::sort(ms.begin(), ms.end());
+      ms_host[i] = ms[ms.size() / 2];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+static bool job_ok(const ttm_batch_job& j, int order_n, const ttm_options* opt) {
+  if (!j.image || !j.bank || !j.components || !j.mask || !j.out_score || !j.out_pos || !j.out_quat ||
+      !j.out_lambda || !j.out_peak_score || !j.out_flags || !j.out_count)
+    return false;
+  if (opt->refine == 2 && !j.tmpl) return false;
+  (void)order_n;
+  return true;
+}
+static ttm_status job_sizes(const ttm_batch_job& j) {
+  if (!dims_ok(j.L) || !any_dims_ok(j.N) || !fits(j.L, j.N) || !tile_ok(j.tile, j.L)) return TTM_E_SIZE;
+  return TTM_OK;
+}
+
+// workspace of one stream of a batch: the largest job's tiled and pose layouts
+static size_t batch_stream_bytes(const ttm_batch_job* jobs_host, int32_t n_jobs, int32_t order_n,
+                                 const ttm_options* opt) {
+  const int K = ttm_num_components(order_n);
+  if (!jobs_host || n_jobs < 1 || K < 0 || !opt || !pose_opts_ok(opt)) return 0;
+  size_t need = 0;
+  for (int i = 0; i < n_jobs; ++i) {
+    const ttm_batch_job& j = jobs_host[i];
+    if (job_sizes(j) != TTM_OK) return 0;
+    Carve c(nullptr);
+    tiled_layout(c, j.tile, j.L, K);
+    pose_layout(c, make_geo(j.N, j.L), opt->max_peaks, K, opt->refine, opt->n_seeds);
+    need = std::max(need, c.size());
+  }
+  return need;
+}
+
+size_t ttm_batch_workspace_bytes(const ttm_batch_job* jobs_host, int32_t n_jobs, int32_t order_n,
+                                 const ttm_options* opt, int32_t n_streams) {
+  if (n_streams < 1 || n_streams > kBatchMaxStreams) return 0;
+  return batch_stream_bytes(jobs_host, n_jobs, order_n, opt) * (size_t)n_streams;
+}
+
+static ttm_status batch_check(const ttm_batch_job* jobs_host, int32_t n_jobs, int32_t order_n,
+                              const ttm_options* opt, int32_t n_streams, void* ws, size_t ws_bytes) {
+  if (n_streams < 1 || n_streams > kBatchMaxStreams) return TTM_E_ARG;
+  if (!jobs_host || n_jobs < 1 || !opt) return TTM_E_ARG;
+  const int K = ttm_num_components(order_n);
+  if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
+  for (int i = 0; i < n_jobs; ++i) {
+    if (!job_ok(jobs_host[i], order_n, opt)) return TTM_E_ARG;
+    const ttm_status st = job_sizes(jobs_host[i]);
+    if (st != TTM_OK) return st;
+  }
+  if (!ws || ws_bytes < ttm_batch_workspace_bytes(jobs_host, n_jobs, order_n, opt, n_streams))
+    return TTM_E_WORKSPACE;
+  return TTM_OK;
+}
+
+// the listed jobs one after another on `stream`, sharing the workspace
+static ttm_status batch_run(const ttm_batch_job* jobs_host, const int* idx, int n_idx, int32_t order_n,
+                            const ttm_options* opt, void* ws, hipStream_t stream) {
+  const int K = ttm_num_components(order_n);
+  for (int ii = 0; ii < n_idx; ++ii) {
+    const ttm_batch_job& j = jobs_host[idx[ii]];
+    Carve c(ws);
+    TiledWs tw = tiled_layout(c, j.tile, j.L, K);
+    PoseWs pw = pose_layout(c, make_geo(j.N, j.L), opt->max_peaks, K, opt->refine, opt->n_seeds);
+    TTM_CALL(correlate_tiled_into(j.image, j.N, static_cast<const float2*>(j.bank), j.L, order_n, K, j.tile, j.mask,
+                                  opt->eps_v, j.out_score, j.out_w, tw, stream));
+    TTM_CALL(recover_pose_into(make_geo(j.N, j.L), j.out_score, j.image, j.components, j.mask, j.tmpl, order_n, K,
+                               opt, j.out_pos, j.out_quat, j.out_lambda, j.out_peak_score, j.out_flags, nullptr,
+                               j.out_count, pw, stream));
+  }
+  return TTM_OK;
+}
+
+ttm_status ttm_batch_match(const ttm_batch_job* jobs_host, int32_t n_jobs, int32_t order_n, const ttm_options* opt,
+                           void* ws, size_t ws_bytes, hipStream_t stream) {
+  TTM_CALL(batch_check(jobs_host, n_jobs, order_n, opt, 1, ws, ws_bytes));
+  std::vector<int> idx(n_jobs);
+  for (int i = 0; i < n_jobs; ++i) idx[i] = i;
+  return batch_run(jobs_host, idx.data(), n_jobs, order_n, opt, ws, stream);
+}
+
+// jobs split over n streams: longest first onto the least loaded stream,
+// with a job's cost estimated as its tiles times the tile volume
+static std::vector<std::vector<int>> batch_split(const ttm_batch_job* jobs_host, int n_jobs, int n) {
+  std::vector<std::pair<double, int>> cost(n_jobs);
+  for (int i = 0; i < n_jobs; ++i) {
+    const ttm_batch_job& j = jobs_host[i];
+    const double T = j.tile;
+    cost[i] = {(double)ttm_tile_count(j.N, j.L, j.tile) * T * T * T, i};
+  }
+  std::stable_sort(cost.begin(), cost.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  std::vector<std::vector<int>> parts(n);
+  std::vector<double> load(n, 0.0);
+  for (const auto& c : cost) {
+    const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    parts[b].push_back(c.second);
+    load[b] += c.first;
+  }
+  for (auto& p : parts) std::sort(p.begin(), p.end());   // each stream keeps the caller's order
+  return parts;
+}
+
+struct ttm_graph_s {
+  hipGraphExec_t exec;
+};
+
+ttm_status ttm_batch_graph_create(const ttm_batch_job* jobs_host, int32_t n_jobs, int32_t order_n,
+                                  const ttm_options* opt, int32_t n_streams, void* ws, size_t ws_bytes,
+                                  hipStream_t stream, ttm_graph* out_graph) {
+  if (!out_graph) return TTM_E_ARG;
+  *out_graph = nullptr;
+  TTM_CALL(batch_check(jobs_host, n_jobs, order_n, opt, n_streams, ws, ws_bytes));
+  if (!stream) return TTM_E_ARG;   // the legacy default stream cannot be captured
+  const size_t per = batch_stream_bytes(jobs_host, n_jobs, order_n, opt);
+  const std::vector<std::vector<int>> parts = batch_split(jobs_host, n_jobs, n_streams);
+  // side streams (default priority) and the fork / join events, for the
+  // capture only: the instantiated graph does not refer to them
+  std::vector<hipStream_t> side(n_streams, nullptr);
+  std::vector<hipEvent_t> ev(n_streams, nullptr);
+  ttm_status st = TTM_OK;
+  for (int b = 0; b < n_streams && st == TTM_OK; ++b) {
+    if (hipEventCreateWithFlags(&ev[b], hipEventDisableTiming) != hipSuccess) st = TTM_E_HIP;
+    if (b > 0 && st == TTM_OK && hipStreamCreateWithFlags(&side[b], hipStreamNonBlocking) != hipSuccess)
+      st = TTM_E_HIP;
+  }
+  hipGraph_t graph = nullptr;
+  bool capturing = false;
+  if (st == TTM_OK) {
+    if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) st = TTM_E_HIP;
+    else capturing = true;
+  }
+  // fork: every side stream waits on the capture stream's start
+  if (st == TTM_OK && n_streams > 1) {
+    if (hipEventRecord(ev[0], stream) != hipSuccess) st = TTM_E_HIP;
+    for (int b = 1; b < n_streams && st == TTM_OK; ++b)
+      if (hipStreamWaitEvent(side[b], ev[0], 0) != hipSuccess) st = TTM_E_HIP;
+  }
+  for (int b = 0; b < n_streams && st == TTM_OK; ++b) {
+    if (parts[b].empty()) continue;
+    st = batch_run(jobs_host, parts[b].data(), (int)parts[b].size(), order_n, opt,
+                   static_cast<char*>(ws) + per * (size_t)b, b == 0 ? stream : side[b]);
+  }
+  // join: the capture stream waits on every side stream's end
+  for (int b = 1; b < n_streams && st == TTM_OK; ++b) {
+    if (hipEventRecord(ev[b], side[b]) != hipSuccess || hipStreamWaitEvent(stream, ev[b], 0) != hipSuccess)
+      st = TTM_E_HIP;
+  }
+  if (capturing) {
+    const hipError_t ec = hipStreamEndCapture(stream, &graph);
+    if (st == TTM_OK && (ec != hipSuccess || !graph)) st = TTM_E_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (st == TTM_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) st = TTM_E_HIP;
+  if (graph) (void)hipGraphDestroy(graph);
+  for (int b = 0; b < n_streams; ++b) {
+    if (ev[b]) (void)hipEventDestroy(ev[b]);
+    if (side[b]) (void)hipStreamDestroy(side[b]);
+  }
+  if (st != TTM_OK) return st;
+  *out_graph = new ttm_graph_s{exec};
+  return TTM_OK;
+}
+
+ttm_status ttm_graph_launch(ttm_graph graph, hipStream_t stream) {
+  if (!graph) return TTM_E_ARG;
+  TTM_TRY(hipGraphLaunch(graph->exec, stream));
+  return TTM_OK;
+}
+
+void ttm_graph_destroy(ttm_graph graph) {
+  if (!graph) return;
+  (void)hipGraphExecDestroy(graph->exec);
+  delete graph;
 }
 
 // --- all-voxel rotation map --------------------------------------------------------

@@ -215,6 +215,19 @@ hipError_t launch_grad_tmpl(const GradGeo& g, const float* image, const float* t
                             hipStream_t s);
 constexpr int kGradMaxTemplate = 32768;
 
+// --- overlap-save tiles (ttm_tile.hip) ------------------------------------------
+struct TileGeo {
+  int n0, n1, n2;      // image extents (any)
+  int o0, o1, o2;      // tile origin in the image
+  int T;               // tile edge (a supported FFT length)
+  int L0, L1, L2;      // template extents
+  int c0, c1, c2;      // template centre
+};
+constexpr int kBatchMaxStreams = 8;
+hipError_t launch_tile_gather(const float* image, const TileGeo& g, float* tile, hipStream_t s);
+hipError_t launch_tile_scatter(const float* tscore, const float* tw, const TileGeo& g, float* score, float* w,
+                               hipStream_t s);
+
 // --- all-voxel rotation map (ttm_rmap.hip) ------------------------------------
 // planes: C_alpha over the valid box, [K][W0][W1][W2] (pass 3 in P3_FIELD mode).
 // n_seeds is a multiple of 32; the table holds rmap_table_uint4 entries.

@@ -261,3 +261,92 @@ def workload_grad(seed: int = 5000) -> Workload:
     """128^3 image, 24^3 template, order 4, 20 copies, SNR 0.1."""
     return make_workload("ttm-128c-L24-n4", (128, 128, 128), 24, 4, 20, seed,
                          n_blobs=6, snr=0.1)
+
+
+@dataclasses.dataclass
+class BatchWorkload:
+    """Uneven tomograms, each holding copies of several templates."""
+    name: str
+    templates: list            # float32 (L, L, L) per template
+    masks: list                # float32 (L, L, L) per template
+    images: list               # float32 cubic tomograms of uneven edges
+    positions: list            # per tomogram, per template: (P, 3) int64 centres
+    true_quats: list           # per tomogram, per template: (P, 4)
+    noise_sigma: float
+    order: int
+
+
+def _batch_tomogram(args):
+    """Tomogram i of workload_batch (independent sub-seeds, so tomograms can be
+    generated in any order or in parallel)."""
+    i, S, seed, tmpls, template_sizes, plants_per_template, sigma, sep = args
+    prng = np.random.default_rng(seed + 10 + 3 * i)
+    # the largest templates first; a placement that gets stuck restarts
+    order_t = sorted(range(len(template_sizes)), key=lambda k: -template_sizes[k])
+    for _ in range(1000):
+        placed = []                          # (centre, L)
+        per_t = [None] * len(template_sizes)
+        ok = True
+        for k in order_t:
+            L = template_sizes[k]
+            c = L // 2
+            pts = []
+            tries = 0
+            while len(pts) < plants_per_template:
+                tries += 1
+                if tries > 2000:
+                    ok = False
+                    break
+                p = np.array([prng.integers(c, S - (L - c) + 1) for _ in range(3)])
+                if all(np.linalg.norm(p - q) >= sep * (L + Lq) / 2.0 for q, Lq in placed):
+                    pts.append(p)
+                    placed.append((p, L))
+            if not ok:
+                break
+            per_t[k] = np.array(pts, dtype=np.int64)
+        if ok:
+            break
+    else:
+        raise RuntimeError("could not place the copies")
+    qrng = np.random.default_rng(seed + 11 + 3 * i)
+    qs = [random_quaternions(qrng, plants_per_template) for _ in template_sizes]
+    img = np.zeros((S, S, S), dtype=np.float64)
+    for t, p, q in zip(tmpls, per_t, qs):
+        img += render_copies((S, S, S), t, p, q)
+    img = img.astype(np.float32)
+    if sigma > 0:
+        img += np.float32(sigma) * np.random.default_rng(seed + 12 + 3 * i).standard_normal(
+            img.shape, dtype=np.float32)
+    return img, per_t, qs
+
+
+def workload_batch(seed: int = 4000, count: int = 64, edges=(96, 320), template_sizes=(24, 32, 48),
+                   plants_per_template: int = 3, snr: float = 0.1, order: int = 4,
+                   n_blobs: int = 6, sep: float = 1.0, workers: int = 1) -> BatchWorkload:
+    """``count`` cubic tomograms with edges uniform in ``edges`` (inclusive),
+    each holding ``plants_per_template`` copies of every template (random-blob
+    templates of the given edges, mask radius L/2).  Copies of templates a and
+    b are at least sep (L_a + L_b)/2 apart (placed largest template first;
+    with sep = 1 the template boxes do not overlap).
+    Additive Gaussian noise with standard deviation sqrt(mean template
+    variance over its mask / snr).  Sub-seeds: +0 templates, +1 edges, then
+    per tomogram i: +10+3i positions, +11+3i rotations, +12+3i noise, so the
+    result does not depend on ``workers`` (processes generating tomograms)."""
+    trng = np.random.default_rng(seed)
+    tmpls = [make_blob_template(trng, L, n_blobs, L / 2.0) for L in template_sizes]
+    grids = [t.grid() for t in tmpls]
+    masks = [ball_mask(L, L / 2.0) for L in template_sizes]
+    var = float(np.mean([g[m > 0].var() for g, m in zip(grids, masks)]))
+    sigma = math.sqrt(var / snr) if snr else 0.0
+    sizes = np.random.default_rng(seed + 1).integers(edges[0], edges[1] + 1, count)
+    jobs = [(i, int(S), seed, tmpls, tuple(template_sizes), plants_per_template, sigma, sep)
+            for i, S in enumerate(sizes)]
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            res = pool.map(_batch_tomogram, jobs, chunksize=1)
+    else:
+        res = [_batch_tomogram(j) for j in jobs]
+    return BatchWorkload(f"ttm-batch{count}-e{edges[0]}-{edges[1]}-L{'-'.join(map(str, template_sizes))}-n{order}",
+                         [g.astype(np.float32) for g in grids], [m.astype(np.float32) for m in masks],
+                         [r[0] for r in res], [r[1] for r in res], [r[2] for r in res], sigma, order)

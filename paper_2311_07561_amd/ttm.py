@@ -9,6 +9,8 @@ Functions mirror the C ABI in include/ttm.h:
 * ``correlate(image, bank, mask, order, opt)``
 * ``recover_pose(score, image, components, mask, order, opt)``
 * ``rotation_map(image, bank, mask, order, seeds, opt)``
+* ``correlate_tiled(image, bank, mask, order, tile, opt)``, ``autotune_tiles``,
+  ``choose_tile``, ``batch_match(jobs, order, opt)``, ``BatchGraph``
 * ``tm_classical(image, tmpl, mask, quats, opt)``
 """
 from __future__ import annotations
@@ -48,6 +50,16 @@ class Options(ctypes.Structure):
                 ("hopm_tol", ctypes.c_double), ("refine", ctypes.c_int32)]
 
 
+class BatchJob(ctypes.Structure):
+    """``ttm_batch_job``: one tomogram against one template (see include/ttm.h)."""
+    _fields_ = [("image", ctypes.c_void_p), ("N", Dims), ("bank", ctypes.c_void_p), ("tile", ctypes.c_int32),
+                ("components", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("tmpl", ctypes.c_void_p),
+                ("L", Dims), ("out_score", ctypes.c_void_p), ("out_w", ctypes.c_void_p),
+                ("out_pos", ctypes.c_void_p), ("out_quat", ctypes.c_void_p), ("out_lambda", ctypes.c_void_p),
+                ("out_peak_score", ctypes.c_void_p), ("out_flags", ctypes.c_void_p),
+                ("out_count", ctypes.c_void_p)]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _SZ = ctypes.c_size_t
@@ -81,6 +93,17 @@ _SIGS = {
     "ttm_rotation_map_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32, _I32]),
     "ttm_rotation_map": (_I32, [_P, _DIMS, _P, _DIMS, _I32, _P, _OPTP, _P, _I32, _P, _P, _P, _P, _P, _P, _SZ,
                                 _P]),
+    "ttm_tile_count": (_I32, [_DIMS, _DIMS, _I32]),
+    "ttm_choose_tile": (_I32, [_DIMS, _DIMS, _P, _P, _I32]),
+    "ttm_correlate_tiled_workspace_bytes": (_SZ, [_DIMS, _I32, _I32]),
+    "ttm_correlate_tiled": (_I32, [_P, _DIMS, _P, _DIMS, _I32, _I32, _P, _OPTP, _P, _P, _P, _SZ, _P]),
+    "ttm_autotune_workspace_bytes": (_SZ, [_DIMS, _I32, _P, _I32]),
+    "ttm_autotune_tiles": (_I32, [_P, _P, _I32, _DIMS, _I32, _P, _OPTP, _I32, _P, _P, _SZ, _P]),
+    "ttm_batch_workspace_bytes": (_SZ, [_P, _I32, _I32, _OPTP, _I32]),
+    "ttm_batch_match": (_I32, [_P, _I32, _I32, _OPTP, _P, _SZ, _P]),
+    "ttm_batch_graph_create": (_I32, [_P, _I32, _I32, _OPTP, _I32, _P, _SZ, _P, _P]),
+    "ttm_graph_launch": (_I32, [_P, _P]),
+    "ttm_graph_destroy": (None, [_P]),
     "ttm_lowpass_workspace_bytes": (_SZ, [_DIMS]),
     "ttm_lowpass": (_I32, [_P, _DIMS, ctypes.c_float, _I32, _P, _P, _SZ, _P]),
     "ttm_profile_enable": (None, [_I32]),
@@ -439,6 +462,172 @@ def rotation_map(image: torch.Tensor, bank: torch.Tensor, mask: torch.Tensor, or
                                 _stream(dev))
     _check(st, "ttm_rotation_map")
     return out
+
+
+def tile_count(N, L, tile: int) -> int:
+    n = lib().ttm_tile_count(_dims(N), _dims(L), int(tile))
+    if n < 0:
+        raise TTMError(n, "ttm_tile_count")
+    return n
+
+
+def correlate_tiled(image: torch.Tensor, bank: torch.Tensor, mask: torch.Tensor, order: int, tile: int,
+                    opt: Options | None = None, want_w: bool = True, workspace: torch.Tensor | None = None,
+                    out=None):
+    """Score F and w of an image of any extent, correlated on tile^3 FFT tiles
+    (``bank`` built with image_shape = (tile, tile, tile))."""
+    dev = image.device
+    N = _dims(image.shape)
+    L = _dims(mask.shape)
+    opt = opt or default_options()
+    if out is not None:
+        score, w = out
+    else:
+        score = torch.empty_like(image)
+        w = torch.empty_like(image) if want_w else None
+    nws = lib().ttm_correlate_tiled_workspace_bytes(L, order, int(tile))
+    if nws == 0:
+        raise TTMError(-2, "ttm_correlate_tiled_workspace_bytes")
+    ws = workspace if workspace is not None and workspace.numel() >= nws else _workspace(nws, dev)
+    st = lib().ttm_correlate_tiled(_dev(image, "image"), N, bank.data_ptr(), L, order, int(tile),
+                                   _dev(mask, "mask"), ctypes.byref(opt), _dev(score, "score"), _opt_dev(w, "w"),
+                                   ws.data_ptr(), ws.numel(), _stream(dev))
+    _check(st, "ttm_correlate_tiled")
+    return score, w
+
+
+def autotune_tiles(banks: dict, L, mask: torch.Tensor, order: int, opt: Options | None = None,
+                   repeats: int = 3) -> dict:
+    """Median milliseconds of one tile correlation per candidate tile edge
+    (``banks``: {edge: the template's bank built at (edge, edge, edge)});
+    synchronises the current stream."""
+    dev = mask.device
+    opt = opt or default_options()
+    edges = sorted(int(t) for t in banks)
+    tiles = (ctypes.c_int32 * len(edges))(*edges)
+    bptr = (ctypes.c_void_p * len(edges))(*[banks[t].data_ptr() for t in edges])
+    ms = (ctypes.c_float * len(edges))()
+    nws = lib().ttm_autotune_workspace_bytes(_dims(L), order, ctypes.cast(tiles, _P), len(edges))
+    if nws == 0:
+        raise TTMError(-2, "ttm_autotune_workspace_bytes")
+    ws = _workspace(nws, dev)
+    st = lib().ttm_autotune_tiles(ctypes.cast(bptr, _P), ctypes.cast(tiles, _P), len(edges), _dims(L), order,
+                                  _dev(mask, "mask"), ctypes.byref(opt), int(repeats), ctypes.cast(ms, _P),
+                                  ws.data_ptr(), ws.numel(), _stream(dev))
+    _check(st, "ttm_autotune_tiles")
+    return {t: float(ms[i]) for i, t in enumerate(edges)}
+
+
+def choose_tile(N, L, table: dict) -> int:
+    """The tile edge of ``table`` ({edge: ms per tile}) minimising tiles x ms."""
+    edges = sorted(int(t) for t in table)
+    tiles = (ctypes.c_int32 * len(edges))(*edges)
+    ms = (ctypes.c_float * len(edges))(*[table[t] for t in edges])
+    t = lib().ttm_choose_tile(_dims(N), _dims(L), ctypes.cast(tiles, _P), ctypes.cast(ms, _P), len(edges))
+    if t < 0:
+        raise TTMError(t, "ttm_choose_tile")
+    return t
+
+
+class BatchOutputs:
+    """Device outputs of one batch job: score and w maps, pose rows."""
+
+    def __init__(self, image_shape, max_peaks: int, device, want_w: bool = False):
+        self.score = torch.empty(tuple(image_shape), dtype=torch.float32, device=device)
+        self.w = torch.empty(tuple(image_shape), dtype=torch.float32, device=device) if want_w else None
+        P = int(max_peaks)
+        self.pos = torch.zeros((P, 3), dtype=torch.int32, device=device)
+        self.quat = torch.zeros((P, 4), dtype=torch.float32, device=device)
+        self.lam = torch.zeros((P,), dtype=torch.float64, device=device)
+        self.peak_score = torch.zeros((P,), dtype=torch.float32, device=device)
+        self.flags = torch.zeros((P,), dtype=torch.int32, device=device)
+        self.count = torch.zeros((2,), dtype=torch.int32, device=device)
+
+    def result(self) -> dict:
+        cnt = self.count.cpu()
+        n = int(cnt[0])
+        return dict(pos=self.pos[:n], quat=self.quat[:n], lam=self.lam[:n], score=self.peak_score[:n],
+                    flags=self.flags[:n], truncated=bool(int(cnt[1]) & PEAKS_TRUNCATED), count=n)
+
+
+def batch_job(image: torch.Tensor, bank: torch.Tensor, tile: int, components: torch.Tensor, mask: torch.Tensor,
+              out: BatchOutputs, tmpl: torch.Tensor | None = None) -> BatchJob:
+    """The C descriptor of one job (the tensors must outlive every use of it)."""
+    j = BatchJob()
+    j.image = _dev(image, "image")
+    j.N = _dims(image.shape)
+    j.bank = bank.data_ptr()
+    j.tile = int(tile)
+    j.components = _dev(components, "components")
+    j.mask = _dev(mask, "mask")
+    j.tmpl = _opt_dev(tmpl, "tmpl")
+    j.L = _dims(mask.shape)
+    j.out_score = _dev(out.score, "score")
+    j.out_w = _opt_dev(out.w, "w")
+    j.out_pos = out.pos.data_ptr()
+    j.out_quat = out.quat.data_ptr()
+    j.out_lambda = out.lam.data_ptr()
+    j.out_peak_score = out.peak_score.data_ptr()
+    j.out_flags = out.flags.data_ptr()
+    j.out_count = out.count.data_ptr()
+    return j
+
+
+def _jobs_array(jobs):
+    arr = (BatchJob * len(jobs))(*jobs)
+    return arr, ctypes.cast(arr, _P)
+
+
+def batch_workspace(jobs, order: int, opt: Options, device, n_streams: int = 1) -> torch.Tensor:
+    arr, ptr = _jobs_array(jobs)
+    n = lib().ttm_batch_workspace_bytes(ptr, len(jobs), order, ctypes.byref(opt), int(n_streams))
+    if n == 0:
+        raise TTMError(-1, "ttm_batch_workspace_bytes")
+    return _workspace(n, device)
+
+
+def batch_match(jobs, order: int, opt: Options, workspace: torch.Tensor, device=None):
+    """Run the jobs eagerly, one after another on the current stream."""
+    arr, ptr = _jobs_array(jobs)
+    st = lib().ttm_batch_match(ptr, len(jobs), order, ctypes.byref(opt), workspace.data_ptr(), workspace.numel(),
+                               _stream(device or workspace.device))
+    _check(st, "ttm_batch_match")
+
+
+class BatchGraph:
+    """The jobs recorded into one hipGraph (captured on a side stream, split
+    over ``n_streams`` concurrent branches, the workspace from
+    ``batch_workspace(..., n_streams)``); ``launch()`` replays all of them as
+    one launch on the current stream.  The job tensors and the workspace must
+    stay alive and unchanged."""
+
+    def __init__(self, jobs, order: int, opt: Options, workspace: torch.Tensor, n_streams: int = 1):
+        self._keep = (list(jobs), workspace, opt)
+        arr, ptr = _jobs_array(jobs)
+        self._handle = ctypes.c_void_p()
+        dev = workspace.device
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        st = lib().ttm_batch_graph_create(ptr, len(jobs), order, ctypes.byref(opt), int(n_streams),
+                                          workspace.data_ptr(), workspace.numel(), side.cuda_stream,
+                                          ctypes.byref(self._handle))
+        _check(st, "ttm_batch_graph_create")
+        self.device = dev
+
+    def launch(self):
+        st = lib().ttm_graph_launch(self._handle, _stream(self.device))
+        _check(st, "ttm_graph_launch")
+
+    def close(self):
+        if self._handle:
+            lib().ttm_graph_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def lowpass(x: torch.Tensor, sigma: float, periodic: bool = True, out: torch.Tensor | None = None):

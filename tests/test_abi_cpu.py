@@ -159,3 +159,90 @@ def test_rotation_map_validation_without_gpu():
     V = 49 ** 3
     need = L.ttm_rotation_map_workspace_bytes(N, T, 4, 64)
     assert need >= L.ttm_correlate_workspace_bytes(N, T, 35) + 35 * 4 * V + 4 * V + 64 * 48 * 2
+
+
+def test_tile_schedule_host_logic():
+    """Tile counts from an independent enumeration of tile origins, and the
+    choice that minimises tiles x ms (ties: the larger edge)."""
+    import itertools
+
+    def count(N, L, T):
+        total = 1
+        for n, l in zip(N, L):
+            W, WT = n - l + 1, T - l + 1
+            origins = list(range(0, W, WT))
+            covered = sorted(o + i for o in origins for i in range(WT) if o + i < W)
+            assert covered == list(range(W))          # the tiles partition the valid positions
+            total *= len(origins)
+        return total
+
+    for N, L, T in itertools.product([(96, 96, 96), (40, 52, 37), (320, 201, 97), (24, 24, 24)],
+                                     [(24, 24, 24), (12, 9, 16)], [32, 64, 128, 256]):
+        if any(l > n for l, n in zip(L, N)) or T < max(L):
+            assert ttm.lib().ttm_tile_count(ttm.Dims(*N), ttm.Dims(*L), T) < 0
+            continue
+        assert ttm.tile_count(N, L, T) == count(N, L, T)
+    assert ttm.lib().ttm_tile_count(ttm.Dims(64, 64, 64), ttm.Dims(8, 8, 8), 48) < 0      # not a supported length
+    table = {64: 0.05, 128: 0.35, 256: 2.6}
+    for N, L in [((96,) * 3, (24,) * 3), ((320,) * 3, (48,) * 3), ((200, 120, 300), (32,) * 3)]:
+        cost = {T: ttm.tile_count(N, L, T) * ms for T, ms in table.items() if T >= max(L)}
+        best = min(cost.values())
+        assert ttm.choose_tile(N, L, table) == max(T for T, c in cost.items() if c == best)
+    assert ttm.choose_tile((100,) * 3, (10,) * 3, {64: 1.0, 128: 8.0}) == 128   # 8 tiles of 64 = 1 of 128: tie
+
+
+def test_batch_and_tiled_validation_without_gpu():
+    L = ttm.lib()
+    fake = ctypes.c_void_p(256)
+    big = 1 << 40
+    o = _opt()
+    N, T = ttm.Dims(100, 90, 80), ttm.Dims(16, 16, 16)
+    assert L.ttm_correlate_tiled(None, N, fake, T, 4, 32, fake, ctypes.byref(o), fake, None, fake, big, None) == -1
+    assert L.ttm_correlate_tiled(fake, N, fake, T, 4, 48, fake, ctypes.byref(o), fake, None, fake, big, None) == -2
+    assert L.ttm_correlate_tiled(fake, N, fake, T, 4, 8, fake, ctypes.byref(o), fake, None, fake, big, None) == -2
+    assert L.ttm_correlate_tiled(fake, ttm.Dims(10, 90, 80), fake, T, 4, 32, fake, ctypes.byref(o), fake, None,
+                                 fake, big, None) == -2
+    assert L.ttm_correlate_tiled(fake, N, fake, T, 4, 32, fake, ctypes.byref(o), fake, None, fake, 64, None) == -3
+    # the tiled workspace does not depend on the image extent
+    assert L.ttm_correlate_tiled_workspace_bytes(T, 4, 32) >= 3 * 4 * 32 ** 3
+    # a batch job with a missing output, with refine 2 and no template
+    job = ttm.BatchJob()
+    for f in ("image", "bank", "components", "mask", "tmpl", "out_score", "out_pos", "out_quat", "out_lambda",
+              "out_peak_score", "out_flags", "out_count"):
+        setattr(job, f, 256)
+    job.N, job.L, job.tile = N, T, 32
+    arr = (ttm.BatchJob * 1)(job)
+    one = L.ttm_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), 1)
+    assert one > 0
+    assert L.ttm_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), 3) == 3 * one
+    assert L.ttm_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), 9) == 0
+    bad = ttm.BatchJob.from_buffer_copy(job)
+    bad.out_count = None
+    arr2 = (ttm.BatchJob * 1)(bad)
+    assert L.ttm_batch_match(ctypes.cast(arr2, ctypes.c_void_p), 1, 4, ctypes.byref(o), fake, big, None) == -1
+    r2 = _opt(refine=2)
+    nt = ttm.BatchJob.from_buffer_copy(job)
+    nt.tmpl = None
+    arr3 = (ttm.BatchJob * 1)(nt)
+    assert L.ttm_batch_match(ctypes.cast(arr3, ctypes.c_void_p), 1, 4, ctypes.byref(r2), fake, big, None) == -1
+    wrong = ttm.BatchJob.from_buffer_copy(job)
+    wrong.tile = 8
+    arr4 = (ttm.BatchJob * 1)(wrong)
+    assert L.ttm_batch_match(ctypes.cast(arr4, ctypes.c_void_p), 1, 4, ctypes.byref(o), fake, big, None) == -2
+    assert L.ttm_batch_match(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), fake, 64, None) == -3
+    # capture needs a created stream and an output handle
+    h = ctypes.c_void_p()
+    assert L.ttm_batch_graph_create(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), 1, fake, big, None,
+                                    ctypes.byref(h)) == -1
+    assert L.ttm_batch_graph_create(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), 1, fake, big, fake,
+                                    None) == -1
+    assert L.ttm_batch_graph_create(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), 0, fake, big, fake,
+                                    ctypes.byref(h)) == -1
+    assert L.ttm_batch_graph_create(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), 2, fake, one, fake,
+                                    ctypes.byref(h)) == -3
+    assert L.ttm_graph_launch(None, None) == -1
+    L.ttm_graph_destroy(None)
+    # ttm_batch_job's layout: natural alignment of its C declaration
+    assert ctypes.sizeof(ttm.BatchJob) == 144
+    assert (ttm.BatchJob.N.offset, ttm.BatchJob.tile.offset, ttm.BatchJob.L.offset,
+            ttm.BatchJob.out_count.offset) == (8, 32, 64, 136)

@@ -1,0 +1,199 @@
+"""Tomograms of uneven sizes: the overlap-save tiled correlation
+(ttm_correlate_tiled), the tile autotuner, batches of jobs (ttm_batch_match)
+and their hipGraph replay, through the C ABI, against the float64 oracle.
+
+Tolerances as for the whole-image path: score F absolute 1e-4, w relative
+1e-4, zeros outside the valid region; peak positions bit-exact when the
+oracle's picker runs on the GPU's own score map; rotations within 1 degree of
+the oracle's eigenpair at those positions where it is unambiguous.  A single
+tile covering a power-of-two image is ttm_correlate bit for bit (same passes,
+same statistics); smaller tiles agree with it to float32 rounding.  Graph
+replays are the eager batch bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ttm_oracle as O
+from paper_2311_07561_amd import synth, ttm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ttm.lib()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def _template(seed, L, n, nrot=60):
+    rng = np.random.default_rng(seed)
+    c = np.array(L) // 2
+    g = np.meshgrid(*[np.arange(l, dtype=np.float64) - c[i] for i, l in enumerate(L)], indexing="ij")
+    tm = synth.make_blob_template(rng, max(L), 4, min(L) / 2)
+    tmpl = tm.evaluate(np.stack(g, axis=-1)).astype(np.float32)
+    mask = (np.sqrt(sum(x ** 2 for x in g)) < min(L) / 2 - 0.2).astype(np.float32)
+    q = synth.super_fibonacci(nrot).astype(np.float32)
+    w = np.full(nrot, 1.0 / nrot)
+    return tmpl, mask, q, w
+
+
+@pytest.mark.parametrize("N,L,n,T", [
+    ((40, 52, 37), (9, 8, 10), 2, 16),      # 4 x 5 x 4 tiles, ragged last tiles
+    ((50, 33, 61), (12, 12, 12), 4, 32),    # 2 x 2 x 3 tiles
+    ((24, 24, 24), (24, 24, 24), 2, 32),    # a single valid voxel
+    ((33, 17, 20), (16, 16, 16), 2, 16),    # one valid position per tile along each axis
+])
+def test_correlate_tiled_matches_oracle(N, L, n, T):
+    tmpl, mask, q, w = _template(11 + n, L, n)
+    rng = np.random.default_rng(3)
+    img = rng.standard_normal(N).astype(np.float32)
+    _, bank = ttm.build_tensor_template(dev(tmpl), dev(mask), n, q, w, image_shape=(T, T, T))
+    score, wmap = ttm.correlate_tiled(dev(img), bank, dev(mask), n, T)
+    torch.cuda.synchronize()
+    Tt = O.tensor_template(tmpl.astype(np.float64), mask.astype(np.float64), n, q.astype(np.float64), w)
+    F_ref = O.score_map(img.astype(np.float64), Tt, mask.astype(np.float64), n)
+    w_ref = O.w_map(img.astype(np.float64), mask.astype(np.float64))
+    # the valid region is where w_map/score_map are defined; they are zero elsewhere
+    valid = O.valid_mask(N, L)
+    got = score.cpu().numpy()
+    gw = wmap.cpu().numpy()
+    assert np.all(got[~valid] == 0.0) and np.all(gw[~valid] == 0.0)
+    err = np.abs(got - F_ref).max()
+    print(f"\n{N} / {L} / order {n} / tile {T} ({ttm.tile_count(N, L, T)} tiles): score abs err {err:.2e}")
+    assert err <= 1e-4
+    assert np.allclose(gw[valid], w_ref[valid], rtol=1e-4, atol=0)
+
+
+def test_tiled_against_whole_image():
+    """64^3 image: one 64^3 tile is ttm_correlate bit for bit; 32^3 tiles
+    (27 of them) agree with it to float32 rounding."""
+    L, n = (16, 16, 16), 4
+    tmpl, mask, q, w = _template(21, L, n)
+    img = dev(np.random.default_rng(4).standard_normal((64, 64, 64)))
+    _, bank64 = ttm.build_tensor_template(dev(tmpl), dev(mask), n, q, w, image_shape=(64, 64, 64))
+    _, bank32 = ttm.build_tensor_template(dev(tmpl), dev(mask), n, q, w, image_shape=(32, 32, 32))
+    s_ref, w_ref = ttm.correlate(img, bank64, dev(mask), n)
+    s64, w64 = ttm.correlate_tiled(img, bank64, dev(mask), n, 64)
+    s32, w32 = ttm.correlate_tiled(img, bank32, dev(mask), n, 32)
+    torch.cuda.synchronize()
+    assert torch.equal(s64, s_ref) and torch.equal(w64, w_ref)
+    assert ttm.tile_count((64,) * 3, L, 32) == 27
+    d = float((s32 - s_ref).abs().max())
+    print(f"\n32^3 tiles vs the whole 64^3 image: score max |diff| {d:.2e} (max F {float(s_ref.max()):.3f})")
+    assert d <= 2e-6 * max(1.0, float(s_ref.abs().max()))
+    assert torch.allclose(w32, w_ref, rtol=1e-5, atol=0)
+
+
+@pytest.fixture(scope="module")
+def batch_setup():
+    wl = synth.workload_batch(seed=4100, count=3, edges=(40, 72), template_sizes=(12, 16),
+                              plants_per_template=2, snr=1.0)
+    n = 4
+    q = synth.super_fibonacci(300).astype(np.float32)
+    w = np.full(len(q), 1.0 / len(q))
+    temps = []
+    for t, m in zip(wl.templates, wl.masks):
+        tt, mm = dev(t), dev(m)
+        banks, comps = {}, None
+        for T in (32, 64):
+            comps, banks[T] = ttm.build_tensor_template(tt, mm, n, q, w, image_shape=(T, T, T))
+        table = ttm.autotune_tiles(banks, t.shape, mm, n, repeats=2)
+        temps.append(dict(tmpl=tt, mask=mm, comps=comps, banks=banks, table=table))
+    opt = ttm.default_options(max_peaks=4, min_dist=8.0, threshold=0.0, refine=2)
+    jobs, outs, meta = [], [], []
+    for i, img in enumerate(wl.images):
+        im = dev(img)
+        for k, tp in enumerate(temps):
+            T = ttm.choose_tile(img.shape, wl.templates[k].shape, tp["table"])
+            out = ttm.BatchOutputs(img.shape, opt.max_peaks, "cuda", want_w=True)
+            jobs.append(ttm.batch_job(im, tp["banks"][T], T, tp["comps"], tp["mask"], out, tmpl=tp["tmpl"]))
+            outs.append(out)
+            meta.append((i, k, T, im))
+    ws = ttm.batch_workspace(jobs, n, opt, "cuda")
+    return wl, n, q, w, temps, opt, jobs, outs, meta, ws
+
+
+def _snapshot(outs):
+    return [(o.score.clone(), o.w.clone(), o.pos.clone(), o.quat.clone(), o.lam.clone(), o.flags.clone(),
+             o.count.clone()) for o in outs]
+
+
+def test_autotuner_table_and_choice(batch_setup):
+    wl, n, q, w, temps, opt, jobs, outs, meta, ws = batch_setup
+    for tp, t in zip(temps, wl.templates):
+        table = tp["table"]
+        print(f"\ntemplate {t.shape[0]}^3: ms per tile {table}")
+        assert set(table) == {32, 64} and all(v > 0.0 for v in table.values())
+        for img in wl.images:
+            T = ttm.choose_tile(img.shape, t.shape, table)
+            cost = {e: ttm.tile_count(img.shape, t.shape, e) * table[e] for e in table}
+            assert cost[T] == min(cost.values())
+
+
+def test_batch_match_against_oracle(batch_setup):
+    wl, n, q, w, temps, opt, jobs, outs, meta, ws = batch_setup
+    ttm.batch_match(jobs, n, opt, ws)
+    torch.cuda.synchronize()
+    for out, (i, k, T, im) in zip(outs, meta):
+        img = wl.images[i]
+        t, m = wl.templates[k], wl.masks[k]
+        # the batch's maps are the tiled correlation's
+        s_ref, w_ref = ttm.correlate_tiled(im, temps[k]["banks"][T], temps[k]["mask"], n, T)
+        assert torch.equal(out.score, s_ref) and torch.equal(out.w, w_ref)
+        F = out.score.cpu().numpy()
+        res = out.result()
+        Tt = O.tensor_template(t.astype(np.float64), m.astype(np.float64), n, q.astype(np.float64), w)
+        # sampled voxels of the stitched map against direct sums
+        rng = np.random.default_rng(i * 7 + k)
+        lo, hi = O.valid_region(img.shape, t.shape)
+        xs = np.stack([rng.integers(lo[a], hi[a], 64) for a in range(3)], axis=1)
+        F_ref = O.score_from_field(O.tensor_field_at(img.astype(np.float64), Tt, m.astype(np.float64), xs), n)
+        assert np.abs(F[xs[:, 0], xs[:, 1], xs[:, 2]] - F_ref).max() <= 1e-4
+        # peaks of the GPU's own map against the oracle's picker; the reported
+        # positions are the candidates moved by the NCC refinement to one of
+        # their 27 neighbours, so they lie within one voxel of the candidates
+        cand = O.find_peaks_fast(F, t.shape, opt.threshold, opt.min_dist, opt.max_peaks)
+        assert res["count"] == len(cand)
+        pos = res["pos"].cpu().numpy()
+        assert np.all(np.abs(pos - cand).max(axis=1) <= 1)
+        # rotations at the reported positions against the oracle's eigenpair
+        C = O.tensor_field_at(img.astype(np.float64), Tt, m.astype(np.float64), pos)
+        for p in range(len(pos)):
+            qo, lo_, second = O.dominant_z_eigenpair(C[p], n, n_brute=60000)
+            if second < lo_ - 1e-2 * abs(lo_):
+                assert O.rotation_angle_deg(res["quat"][p].cpu().numpy(), qo) <= 1.0
+        print(f"\ntomogram {i} ({img.shape[0]}^3), template {t.shape[0]}^3, tile {T}: "
+              f"{res['count']} peaks, planted at {wl.positions[i][k].tolist()}, found {pos.tolist()}")
+
+
+@pytest.mark.parametrize("n_streams", [1, 3])
+def test_batch_graph_replays_equal_eager(batch_setup, n_streams):
+    """The graph (its jobs on n_streams concurrent branches, each with its own
+    workspace slice) is replayed three times, with eager work and cleared
+    outputs in between; every replay equals the eager batch bit for bit."""
+    wl, n, q, w, temps, opt, jobs, outs, meta, ws = batch_setup
+    ttm.batch_match(jobs, n, opt, ws)
+    torch.cuda.synchronize()
+    eager = _snapshot(outs)
+    gws = ttm.batch_workspace(jobs, n, opt, "cuda", n_streams)
+    g = ttm.BatchGraph(jobs, n, opt, gws, n_streams)
+    try:
+        for r in range(3):
+            for o in outs:
+                o.score.fill_(-1.0)
+                o.pos.zero_()
+                o.count.zero_()
+            _ = torch.randn(1 << 20, device="cuda").sum()     # unrelated eager work
+            g.launch()
+            torch.cuda.synchronize()
+            for got, ref in zip(_snapshot(outs), eager):
+                for a, b in zip(got, ref):
+                    assert torch.equal(a, b), r
+    finally:
+        g.close()
