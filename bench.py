@@ -7,8 +7,9 @@ of f and f^2, K+2 fanned-out spectral products, batched C2R inverses, local
 normalisation and Frobenius score, then peak picking and the dominant
 Z-eigenpair of the correlated tensor field at every peak and its 26
 neighbours; the reported voxel is the one whose NCC at its own rotation is
-largest (--refine 2, the default; 1 keeps the largest eigenvalue, 0 the peak
-itself).  The tensor-template build (once per template) is timed separately.
+largest, repeated from the moved peaks until none moves (--refine 3, the
+default, at most 4 rounds; 2 stops after one round, 1 keeps the largest
+eigenvalue, 0 the peak itself).  The tensor-template build (once per template) is timed separately.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 
@@ -80,9 +81,10 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--build-rotations", type=int, default=10000)
     p.add_argument("--classical-rotations", type=int, default=10000)
-    p.add_argument("--refine", type=int, default=2,
+    p.add_argument("--refine", type=int, default=3,
                    help="0: pose at each peak; 1: best eigenvalue of the 3x3x3 neighbourhood; "
-                        "2: best NCC at each neighbour's own rotation")
+                        "2: best NCC at each neighbour's own rotation; 3: 2 repeated until no peak moves "
+                        "(at most 4 rounds)")
     p.add_argument("--order6", type=int, default=1, help="also time and score tensor order 6")
     p.add_argument("--rmap-seeds", type=int, default=10016,
                    help="also time the all-voxel rotation map with this many seeds (0 = skip)")
@@ -194,7 +196,15 @@ def run_order(order, wl, img, tmpl, mask, args, ttm, synth, torch, dev, angle, w
     det = match_errors(res["pos"].cpu().numpy(), res["quat"].cpu().numpy(), wl.positions, wl.true_quats, angle)
     out = {"order": order, "components": K, "ms_per_step": ms, "build_ms": round(build_ms, 1),
            "pose_detected": dict(err_stats(det), recall=len(det) / len(wl.positions), refine=args.refine)}
-    for rf in (0, 1, 2):
+    if args.refine == 3:
+        # the single-round refinement's step time, for comparison
+        opt2 = ttm.default_options(max_peaks=len(wl.positions), min_dist=float(L[0]) / 2, threshold=0.0, refine=2)
+        bufs2 = ttm.MatchBuffers(N, L, order, opt2, dev)
+        ms2, _ = time_steps(lambda: ttm.match(img, bank, mask, order, opt2, bufs2, tmpl=tmpl), args.steps,
+                            args.warmup, ttm, torch)
+        out["ms_per_step_refine2"] = round(ms2, 4)
+        del bufs2
+    for rf in (0, 1, 2, 3):
         if rf == args.refine:
             continue
         opt0 = ttm.default_options(max_peaks=len(wl.positions), min_dist=float(L[0]) / 2, threshold=0.0,
@@ -271,7 +281,7 @@ def run_batch(bwl, args, ttm, synth, torch, dev, angle):
     # as many peaks per job as the tomogram holds copies of all templates
     copies = sum(len(p) for p in bwl.positions[0])
     opt = ttm.default_options(max_peaks=copies, min_dist=float(min(t.shape[0] for t in bwl.templates)) / 2,
-                              threshold=0.0, refine=2)
+                              threshold=0.0, refine=args.refine)
     images = [torch.as_tensor(im, device=dev) for im in bwl.images]
     jobs, outs, meta = [], [], []
     choice = {}

@@ -70,7 +70,11 @@ typedef struct {
                             spectral norm the Frobenius score stands in for,
                             Section 3.4); 2: move it to the voxel whose NCC
                             c(y, R(q_y)) at its own dominant rotation q_y is
-                            largest (needs the raw template); default 0       */
+                            largest (needs the raw template); 3: repeat 2 from
+                            the moved positions until no candidate moves, at
+                            most 4 rounds in all (only moving candidates are
+                            recomputed; two candidates may end on the same
+                            voxel); default 0                                 */
 } ttm_options;
 
 /* Pose flags (bit set in out_flags). */
@@ -184,8 +188,8 @@ ttm_status ttm_correlate(
  *   image            the correlated image; components: K x [L0][L1][L2] float32
  *   mask             the mask used for the components
  *   tmpl             the raw template [L0][L1][L2] float32 the components were
- *                    built from; read only when opt->refine = 2 (else may be
- *                    NULL; NULL with refine = 2 is TTM_E_ARG)
+ *                    built from; read only when opt->refine >= 2 (else may be
+ *                    NULL; NULL with refine >= 2 is TTM_E_ARG)
  *   out_pos          max_peaks x 3 int32 (i0,i1,i2)
  *   out_quat         max_peaks x 4 float32, canonical (a > 0)
  *   out_lambda       max_peaks float64 dominant Z-eigenvalue C Q^n
@@ -363,7 +367,7 @@ typedef struct {
   int32_t tile;              /* tile edge T */
   const float* components;   /* K x [L0][L1][L2] */
   const float* mask;         /* [L0][L1][L2] */
-  const float* tmpl;         /* [L0][L1][L2], needed with refine = 2 */
+  const float* tmpl;         /* [L0][L1][L2], needed with refine >= 2 */
   ttm_dims L;
   float* out_score;          /* [n0][n1][n2] */
   float* out_w;              /* [n0][n1][n2] or NULL */
@@ -379,8 +383,9 @@ size_t ttm_batch_workspace_bytes(const ttm_batch_job* jobs_host,
                                  int32_t n_jobs, int32_t order_n,
                                  const ttm_options* opt, int32_t n_streams);
 ttm_status ttm_batch_match(const ttm_batch_job* jobs_host, int32_t n_jobs,
-                           int32_t order_n, const ttm_options* opt, void* ws,
-                           size_t ws_bytes, hipStream_t stream);
+                           int32_t order_n, const ttm_options* opt,
+                           int32_t n_streams, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
 ttm_status ttm_batch_graph_create(const ttm_batch_job* jobs_host,
                                   int32_t n_jobs, int32_t order_n,
                                   const ttm_options* opt, int32_t n_streams,

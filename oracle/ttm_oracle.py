@@ -647,6 +647,22 @@ def refine_by_ncc(f, t, m, T, n: int, x, eps_v: float = EPS_V_DEFAULT,
     return np.asarray(x) + offs[best], qs[best], lams[best], nccs[best], nccs
 
 
+def refine_by_ncc_iterated(f, t, m, T, n: int, x, eps_v: float = EPS_V_DEFAULT,
+                           n_brute: int = 100000, max_rounds: int = 4):
+    """The NCC refinement of :func:`refine_by_ncc` repeated from its own result
+    until the position no longer moves, at most ``max_rounds`` times (a hill
+    climb on the NCC at each voxel's own rotation, for Frobenius-score peaks
+    more than one voxel from the copy's centre).  Returns (position, q,
+    lambda, ncc, rounds taken)."""
+    x = np.asarray(x)
+    for r in range(1, max_rounds + 1):
+        pos, q, lam, ncc, _ = refine_by_ncc(f, t, m, T, n, x, eps_v, n_brute)
+        if np.array_equal(pos, x) or r == max_rounds:
+            return pos, q, lam, ncc, r
+        x = pos
+    raise ValueError("max_rounds must be >= 1")
+
+
 # ----------------------------------------------------------------------------
 # gradient of the Frobenius score at fixed positions: the adjoint of the whole
 # forward path (rotation, masked normalisation, tensor accumulation, window

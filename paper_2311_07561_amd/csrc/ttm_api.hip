@@ -130,6 +130,8 @@ static CorrWs corr_layout(Carve& c, const Geo& g, int K) {
 struct PoseWs {
   unsigned* hist; unsigned* ctrl; unsigned long long* allc; unsigned long long* cand; double* stats;
   double* partials; int* cand_pos; double* seeds; PoseScratch ps;
+  // refine 3: per-candidate moved flags, the compact list of a round, its outputs
+  int* moved; int* act_pos; int* act_idx; int* act_count; RefineTmp tmp;
 };
 static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refine, int n_seeds) {
   PoseWs w;
@@ -155,7 +157,48 @@ static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refi
   w.ps.mcount = c.take<int>(1);
   w.ps.sbest = c.take<double>(nb * 64);
   w.ps.sidx = c.take<int>(nb * 64);
+  w.moved = w.act_pos = w.act_idx = w.act_count = nullptr;
+  w.tmp = RefineTmp{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (refine == 3) {
+    const size_t P = (size_t)max_peaks;
+    w.moved = c.take<int>(P);
+    w.act_pos = c.take<int>(P * 3);
+    w.act_idx = c.take<int>(P);
+    w.act_count = c.take<int>(1);
+    w.tmp.pos = c.take<int>(P * 3);
+    w.tmp.quat = c.take<float>(P * 4);
+    w.tmp.lam = c.take<double>(P);
+    w.tmp.score = c.take<float>(P);
+    w.tmp.flags = c.take<int>(P);
+    w.tmp.C = c.take<double>(P * (size_t)K);
+  }
   return w;
+}
+
+// refine 3: after the first round (the refinement of refine 2, already
+// written to the outputs from the start positions), rounds on the candidates
+// whose position changed, until none moves or kRefineRounds rounds in all.
+// tensor(pos, count_dev) fills the pose scratch with C_n at the 27
+// neighbours of the listed candidates.
+template <class TensorFn>
+static ttm_status refine_rounds(const Geo& g, const float* score, int order_n, int K, const ttm_options* opt,
+                                int max_peaks, const int* count_dev, int count_host, const int* start,
+                                const float* image, const float* tmpl, const float* mask, int32_t* out_pos,
+                                float* out_quat, double* out_lambda, float* out_score, int32_t* out_flags,
+                                double* out_C, PoseWs& w, TensorFn tensor, hipStream_t stream) {
+  TTM_PROF(PC_POSE, launch_refine_init(count_dev, count_host, start, out_pos, w.moved, max_peaks, stream));
+  for (int r = 1; r < kRefineRounds; ++r) {
+    TTM_PROF(PC_POSE, launch_refine_compact(count_dev, count_host, w.moved, out_pos, w.act_pos, w.act_idx,
+                                            w.act_count, stream));
+    TTM_PROF(PC_POSE, tensor(w.act_pos, w.act_count));
+    TTM_PROF(PC_POSE, launch_pose_solve(g, score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
+                                        max_peaks, 2, w.act_pos, w.act_count, 0, image, tmpl, mask, w.tmp.pos,
+                                        w.tmp.quat, w.tmp.lam, out_score ? w.tmp.score : nullptr, w.tmp.flags,
+                                        out_C ? w.tmp.C : nullptr, w.ps, stream, true, 27));
+    TTM_PROF(PC_POSE, launch_refine_scatter(w.act_count, w.act_idx, K, w.tmp, out_pos, out_quat, out_lambda,
+                                            out_score, out_flags, out_C, w.moved, max_peaks, stream));
+  }
+  return TTM_OK;
 }
 
 constexpr int kClassicalBatch = 32;
@@ -370,7 +413,7 @@ static bool pose_opts_ok(const ttm_options* opt) {
   if (opt->n_seeds < 64 || opt->n_seeds > 65536) return false;
   if (opt->hopm_max_iter < 1 || !(opt->hopm_tol > 0.0)) return false;
   if (!(opt->threshold >= 0.0f) || !(opt->min_dist >= 0.0f) || !(opt->eps_v >= 0.0f)) return false;
-  if (opt->refine < 0 || opt->refine > 2) return false;
+  if (opt->refine < 0 || opt->refine > 3) return false;
   return true;
 }
 
@@ -393,12 +436,21 @@ static ttm_status recover_pose_into(const Geo& g, const float* score, const floa
   float* cand_score = reinterpret_cast<float*>(w.ps.w);   // overwritten later by the pose scratch
   TTM_PROF(PC_PEAKS, launch_peaks(g, score, opt->threshold, opt->min_dist, opt->max_peaks, pw, w.cand_pos,
                                   cand_score, out_count, stream));
+  const int rf = opt->refine == 3 ? 2 : opt->refine;   // each round of refine 3 is a refine-2 round
   TTM_PROF(PC_POSE, launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v,
-                                       opt->max_peaks, opt->refine, w.cand_pos, out_count, 0, w.ps, stream));
+                                       opt->max_peaks, rf, w.cand_pos, out_count, 0, w.ps, stream));
   TTM_PROF(PC_POSE, launch_pose_solve(g, score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
-                                      opt->max_peaks, opt->refine, w.cand_pos, out_count, 0, image, tmpl, mask,
+                                      opt->max_peaks, rf, w.cand_pos, out_count, 0, image, tmpl, mask,
                                       out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, w.ps,
                                       stream));
+  if (opt->refine == 3) {
+    auto tensor = [&](const int* pos, const int* cnt) {
+      return launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, opt->max_peaks, 2, pos,
+                                cnt, 0, w.ps, stream);
+    };
+    TTM_CALL(refine_rounds(g, score, order_n, K, opt, opt->max_peaks, out_count, 0, w.cand_pos, image, tmpl, mask,
+                           out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, w, tensor, stream));
+  }
   return TTM_OK;
 }
 
@@ -417,7 +469,7 @@ ttm_status ttm_recover_pose(const float* score, const float* image, const float*
   if (!score || !image || !components || !mask || !opt || !out_pos || !out_quat || !out_lambda ||
       !out_peak_score || !out_flags || !out_count)
     return TTM_E_ARG;
-  if (opt->refine == 2 && !tmpl) return TTM_E_ARG;
+  if (opt->refine >= 2 && !tmpl) return TTM_E_ARG;
   const int K = ttm_num_components(order_n);
   if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
   if (!dims_ok(L) || !any_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
@@ -436,7 +488,7 @@ ttm_status ttm_pose_at(const float* image, const float* components, const float*
   if (!image || !components || !mask || !opt || !positions || !out_pos || !out_quat || !out_lambda ||
       !out_flags)
     return TTM_E_ARG;
-  if (opt->refine == 2 && !tmpl) return TTM_E_ARG;
+  if (opt->refine >= 2 && !tmpl) return TTM_E_ARG;
   const int K = ttm_num_components(order_n);
   if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
   if (n_pos < 0 || n_pos > opt->max_peaks) return TTM_E_ARG;
@@ -447,11 +499,20 @@ ttm_status ttm_pose_at(const float* image, const float* components, const float*
   Carve c(ws);
   PoseWs w = pose_layout(c, g, opt->max_peaks, K, opt->refine, opt->n_seeds);
   TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), nullptr, 0, w.partials, w.stats, stream));
+  const int rf = opt->refine == 3 ? 2 : opt->refine;
   TTM_PROF(PC_POSE, launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, n_pos,
-                                       opt->refine, positions, nullptr, n_pos, w.ps, stream));
+                                       rf, positions, nullptr, n_pos, w.ps, stream));
   TTM_PROF(PC_POSE, launch_pose_solve(g, nullptr, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol, n_pos,
-                                      opt->refine, positions, nullptr, n_pos, image, tmpl, mask, out_pos, out_quat,
+                                      rf, positions, nullptr, n_pos, image, tmpl, mask, out_pos, out_quat,
                                       out_lambda, nullptr, out_flags, out_C, w.ps, stream));
+  if (opt->refine == 3) {
+    auto tensor = [&](const int* pos, const int* cnt) {
+      return launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, n_pos, 2, pos, cnt, 0,
+                                w.ps, stream);
+    };
+    TTM_CALL(refine_rounds(g, nullptr, order_n, K, opt, n_pos, nullptr, n_pos, positions, image, tmpl, mask, out_pos,
+                           out_quat, out_lambda, nullptr, out_flags, out_C, w, tensor, stream));
+  }
   return TTM_OK;
 }
 
@@ -474,7 +535,7 @@ ttm_status ttm_match(const float* image, ttm_dims N, const void* bank, ttm_dims 
   if (!image || !bank || !mask || !opt || !out_score || !out_pos || !out_quat || !out_lambda ||
       !out_peak_score || !out_flags || !out_count)
     return TTM_E_ARG;
-  if (opt->refine == 2 && !tmpl) return TTM_E_ARG;
+  if (opt->refine >= 2 && !tmpl) return TTM_E_ARG;
   const int K = ttm_num_components(order_n);
   if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
   if (!dims_ok(L) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
@@ -491,12 +552,21 @@ ttm_status ttm_match(const float* image, ttm_dims N, const void* bank, ttm_dims 
   float* cand_score = reinterpret_cast<float*>(pw.ps.w);
   TTM_PROF(PC_PEAKS, launch_peaks(g, out_score, opt->threshold, opt->min_dist, opt->max_peaks, pk, pw.cand_pos,
                                   cand_score, out_count, stream));
-  TTM_PROF(PC_POSE, launch_field_at(g, cw.H, g.half(), K, wout, opt->max_peaks, opt->refine, pw.cand_pos,
+  const int rf = opt->refine == 3 ? 2 : opt->refine;
+  TTM_PROF(PC_POSE, launch_field_at(g, cw.H, g.half(), K, wout, opt->max_peaks, rf, pw.cand_pos,
                                     out_count, 0, pw.ps, stream));
   TTM_PROF(PC_POSE, launch_pose_solve(g, out_score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
-                                      opt->max_peaks, opt->refine, pw.cand_pos, out_count, 0, image, tmpl, mask,
+                                      opt->max_peaks, rf, pw.cand_pos, out_count, 0, image, tmpl, mask,
                                       out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, pw.ps,
                                       stream));
+  if (opt->refine == 3) {
+    auto tensor = [&](const int* pos, const int* cnt) {
+      return launch_field_at(g, cw.H, g.half(), K, wout, opt->max_peaks, 2, pos, cnt, 0, pw.ps, stream);
+    };
+    TTM_CALL(refine_rounds(g, out_score, order_n, K, opt, opt->max_peaks, out_count, 0, pw.cand_pos, image, tmpl,
+                           mask, out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, pw, tensor,
+                           stream));
+  }
   return TTM_OK;
 }
 
@@ -677,7 +747,7 @@ static bool job_ok(const ttm_batch_job& j, int order_n, const ttm_options* opt) 
   if (!j.image || !j.bank || !j.components || !j.mask || !j.out_score || !j.out_pos || !j.out_quat ||
       !j.out_lambda || !j.out_peak_score || !j.out_flags || !j.out_count)
     return false;
-  if (opt->refine == 2 && !j.tmpl) return false;
+  if (opt->refine >= 2 && !j.tmpl) return false;
   (void)order_n;
   return true;
 }
@@ -706,7 +776,9 @@ static size_t batch_stream_bytes(const ttm_batch_job* jobs_host, int32_t n_jobs,
 size_t ttm_batch_workspace_bytes(const ttm_batch_job* jobs_host, int32_t n_jobs, int32_t order_n,
                                  const ttm_options* opt, int32_t n_streams) {
   if (n_streams < 1 || n_streams > kBatchMaxStreams) return 0;
-  return batch_stream_bytes(jobs_host, n_jobs, order_n, opt) * (size_t)n_streams;
+  const size_t per = batch_stream_bytes(jobs_host, n_jobs, order_n, opt);
+  // the slices, plus one 256-byte block for the graph's root and sink nodes
+  return per == 0 ? 0 : per * (size_t)n_streams + 256;
 }
 
 static ttm_status batch_check(const ttm_batch_job* jobs_host, int32_t n_jobs, int32_t order_n,
@@ -743,14 +815,6 @@ static ttm_status batch_run(const ttm_batch_job* jobs_host, const int* idx, int 
   return TTM_OK;
 }
 
-ttm_status ttm_batch_match(const ttm_batch_job* jobs_host, int32_t n_jobs, int32_t order_n, const ttm_options* opt,
-                           void* ws, size_t ws_bytes, hipStream_t stream) {
-  TTM_CALL(batch_check(jobs_host, n_jobs, order_n, opt, 1, ws, ws_bytes));
-  std::vector<int> idx(n_jobs);
-  for (int i = 0; i < n_jobs; ++i) idx[i] = i;
-  return batch_run(jobs_host, idx.data(), n_jobs, order_n, opt, ws, stream);
-}
-
 // jobs split over n streams: longest first onto the least loaded stream,
 // with a job's cost estimated as its tiles times the tile volume
 static std::vector<std::vector<int>> batch_split(const ttm_batch_job* jobs_host, int n_jobs, int n) {
@@ -776,17 +840,15 @@ struct ttm_graph_s {
   hipGraphExec_t exec;
 };
 
-ttm_status ttm_batch_graph_create(const ttm_batch_job* jobs_host, int32_t n_jobs, int32_t order_n,
-                                  const ttm_options* opt, int32_t n_streams, void* ws, size_t ws_bytes,
-                                  hipStream_t stream, ttm_graph* out_graph) {
-  if (!out_graph) return TTM_E_ARG;
-  *out_graph = nullptr;
-  TTM_CALL(batch_check(jobs_host, n_jobs, order_n, opt, n_streams, ws, ws_bytes));
-  if (!stream) return TTM_E_ARG;   // the legacy default stream cannot be captured
+// the jobs split over n_streams branches on `stream` and side streams forked
+// from it and joined back to it (recorded into a graph when `capture`)
+static ttm_status batch_dispatch(const ttm_batch_job* jobs_host, int32_t n_jobs, int32_t order_n,
+                                 const ttm_options* opt, int32_t n_streams, void* ws, hipStream_t stream,
+                                 bool capture, hipGraph_t* graph_out) {
   const size_t per = batch_stream_bytes(jobs_host, n_jobs, order_n, opt);
   const std::vector<std::vector<int>> parts = batch_split(jobs_host, n_jobs, n_streams);
-  // side streams (default priority) and the fork / join events, for the
-  // capture only: the instantiated graph does not refer to them
+  // side streams (default priority) and the fork / join events, created and
+  // destroyed by this call: a captured graph does not refer to them
   std::vector<hipStream_t> side(n_streams, nullptr);
   std::vector<hipEvent_t> ev(n_streams, nullptr);
   ttm_status st = TTM_OK;
@@ -795,15 +857,17 @@ ttm_status ttm_batch_graph_create(const ttm_batch_job* jobs_host, int32_t n_jobs
     if (b > 0 && st == TTM_OK && hipStreamCreateWithFlags(&side[b], hipStreamNonBlocking) != hipSuccess)
       st = TTM_E_HIP;
   }
-  hipGraph_t graph = nullptr;
   bool capturing = false;
-  if (st == TTM_OK) {
+  if (st == TTM_OK && capture) {
     if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) st = TTM_E_HIP;
     else capturing = true;
   }
-  // fork: every side stream waits on the capture stream's start
+  int* marker = reinterpret_cast<int*>(static_cast<char*>(ws) + per * (size_t)n_streams);
+  // fork: every side stream waits on the start, one kernel node that all
+  // branches descend from
   if (st == TTM_OK && n_streams > 1) {
-    if (hipEventRecord(ev[0], stream) != hipSuccess) st = TTM_E_HIP;
+    if (launch_fill_i32(marker, 1, 0, stream) != hipSuccess || hipEventRecord(ev[0], stream) != hipSuccess)
+      st = TTM_E_HIP;
     for (int b = 1; b < n_streams && st == TTM_OK; ++b)
       if (hipStreamWaitEvent(side[b], ev[0], 0) != hipSuccess) st = TTM_E_HIP;
   }
@@ -812,23 +876,53 @@ ttm_status ttm_batch_graph_create(const ttm_batch_job* jobs_host, int32_t n_jobs
     st = batch_run(jobs_host, parts[b].data(), (int)parts[b].size(), order_n, opt,
                    static_cast<char*>(ws) + per * (size_t)b, b == 0 ? stream : side[b]);
   }
-  // join: the capture stream waits on every side stream's end
+  // join: `stream` waits on every side stream's end, then one kernel node
   for (int b = 1; b < n_streams && st == TTM_OK; ++b) {
     if (hipEventRecord(ev[b], side[b]) != hipSuccess || hipStreamWaitEvent(stream, ev[b], 0) != hipSuccess)
       st = TTM_E_HIP;
   }
+  if (st == TTM_OK && n_streams > 1 && launch_fill_i32(marker, 1, 0, stream) != hipSuccess) st = TTM_E_HIP;
   if (capturing) {
+    hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(stream, &graph);
     if (st == TTM_OK && (ec != hipSuccess || !graph)) st = TTM_E_HIP;
+    if (st == TTM_OK) *graph_out = graph;
+    else if (graph) (void)hipGraphDestroy(graph);
   }
-  hipGraphExec_t exec = nullptr;
-  if (st == TTM_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) st = TTM_E_HIP;
-  if (graph) (void)hipGraphDestroy(graph);
+  // an eager dispatch's side streams are destroyed only after their work is
+  // ordered before `stream`'s later work (the join above); destroying a
+  // stream with pending work is allowed and does not wait for it
   for (int b = 0; b < n_streams; ++b) {
     if (ev[b]) (void)hipEventDestroy(ev[b]);
     if (side[b]) (void)hipStreamDestroy(side[b]);
   }
-  if (st != TTM_OK) return st;
+  return st;
+}
+
+ttm_status ttm_batch_match(const ttm_batch_job* jobs_host, int32_t n_jobs, int32_t order_n, const ttm_options* opt,
+                           int32_t n_streams, void* ws, size_t ws_bytes, hipStream_t stream) {
+  TTM_CALL(batch_check(jobs_host, n_jobs, order_n, opt, n_streams, ws, ws_bytes));
+  if (n_streams == 1) {
+    std::vector<int> idx(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) idx[i] = i;
+    return batch_run(jobs_host, idx.data(), n_jobs, order_n, opt, ws, stream);
+  }
+  return batch_dispatch(jobs_host, n_jobs, order_n, opt, n_streams, ws, stream, false, nullptr);
+}
+
+ttm_status ttm_batch_graph_create(const ttm_batch_job* jobs_host, int32_t n_jobs, int32_t order_n,
+                                  const ttm_options* opt, int32_t n_streams, void* ws, size_t ws_bytes,
+                                  hipStream_t stream, ttm_graph* out_graph) {
+  if (!out_graph) return TTM_E_ARG;
+  *out_graph = nullptr;
+  TTM_CALL(batch_check(jobs_host, n_jobs, order_n, opt, n_streams, ws, ws_bytes));
+  if (!stream) return TTM_E_ARG;   // the legacy default stream cannot be captured
+  hipGraph_t graph = nullptr;
+  TTM_CALL(batch_dispatch(jobs_host, n_jobs, order_n, opt, n_streams, ws, stream, true, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return TTM_E_HIP;
   *out_graph = new ttm_graph_s{exec};
   return TTM_OK;
 }

@@ -225,6 +225,9 @@ __global__ void __launch_bounds__(256) k_pencils(float2* __restrict__ data, int 
   __shared__ float2 tw[N];
   const int tid = threadIdx.x;
   fill_twiddles(tw, N, tid, 256);
+  // the table is written by several waves and read (by the engine's first
+  // twiddle step) before any other barrier
+  __syncthreads();
   const int pl = tid % PW, a = tid / PW;
   const int p = xcd_tile(blockIdx.x, gridDim.x) * PW + pl;
   const bool valid = p < npencils;
@@ -298,6 +301,7 @@ __global__ void __launch_bounds__(256) k_pass1(Pass1Args A, long P, int p2, int 
   __shared__ float2 tw[N0];
   const int tid = threadIdx.x;
   fill_twiddles(tw, N0, tid, 256);
+  __syncthreads();   // the table is read by the first engine call before its first barrier
   const int pl = tid % PW, a = tid / PW;
   const int p = xcd_tile(blockIdx.x, gridDim.x) * PW + pl;
   // pencils past the last tile's end are transformed as zeros and not stored

@@ -152,6 +152,20 @@ struct PoseScratch {
   double* sbest;    // max_peaks * NB * 64: seed scan, best lambda per slot
   int* sidx;        // max_peaks * NB * 64: and its seed index
 };
+// iterated refinement (refine 3): the rounds after the first (few candidates
+// still move there, so the NCC kernel spreads each candidate's 27 neighbours
+// over 27 blocks instead of 3, trading template loads for latency)
+constexpr int kRefineRounds = 4;
+struct RefineTmp {            // one round's outputs, in compact order
+  int* pos; float* quat; double* lam; float* score; int* flags; double* C;
+};
+hipError_t launch_refine_init(const int* count_dev, int count_host, const int* start, const int* pos, int* moved,
+                              int max_peaks, hipStream_t s);
+hipError_t launch_refine_compact(const int* count_dev, int count_host, int* moved, const int* pos, int* act_pos,
+                                 int* act_idx, int* act_count, hipStream_t s);
+hipError_t launch_refine_scatter(const int* act_count, const int* act_idx, int K, const RefineTmp& t,
+                                 int* out_pos, float* out_quat, double* out_lambda, float* out_score,
+                                 int* out_flags, double* out_C, int* moved, int max_peaks, hipStream_t s);
 // C_n(x) in float64 by direct window sums at max_peaks candidates (count from
 // count_dev if non-null, else count_host), at the 27 neighbours if refine
 hipError_t launch_pose_tensor(const Geo& g, const float* image, const float* comps, const float* mask,
@@ -172,7 +186,8 @@ hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int 
                              double tol, int max_peaks, int refine, const int* pos_in, const int* count_dev,
                              int count_host, const float* image, const float* tmpl, const float* mask,
                              int* out_pos, float* out_quat, double* out_lambda, float* out_score, int* out_flags,
-                             double* out_C, const PoseScratch& ps, hipStream_t s);
+                             double* out_C, const PoseScratch& ps, hipStream_t s, bool reuse_tables = false,
+                             int ncc_groups = 3);
 
 // --- isotropic low-pass filter (ttm_filter.hip) -----------------------------
 constexpr int kMaxFilterRadius = 32;

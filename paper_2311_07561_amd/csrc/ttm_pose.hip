@@ -964,6 +964,106 @@ __global__ void k_pose_pick(PoseGeo g, const float* __restrict__ score, int K, c
     for (int k = 0; k < K; ++k) out_C[(long)p * K + k] = Cbuf[b * K + k];
 }
 
+// ----------------------------------------------------------------------------
+// iterated refinement (refine 3): after the first refinement, the candidates
+// that moved are compacted into a list that the next round refines again
+// ----------------------------------------------------------------------------
+__global__ void k_refine_init(const int* __restrict__ count_dev, int count_host, const int* __restrict__ start,
+                              const int* __restrict__ pos, int* __restrict__ moved) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = count_dev ? count_dev[0] : count_host;
+  if (p >= n) return;
+  moved[p] = (pos[3 * p] != start[3 * p] || pos[3 * p + 1] != start[3 * p + 1] ||
+              pos[3 * p + 2] != start[3 * p + 2]) ? 1 : 0;
+}
+
+// one block: the moving candidates in index order (an LDS prefix sum per
+// chunk of 1024); their flags are cleared for the round
+__global__ void __launch_bounds__(1024) k_refine_compact(const int* __restrict__ count_dev, int count_host,
+                                                         int* __restrict__ moved, const int* __restrict__ pos,
+                                                         int* __restrict__ act_pos, int* __restrict__ act_idx,
+                                                         int* __restrict__ act_count) {
+  __shared__ int sh[1024];
+  __shared__ int base;
+  const int tid = threadIdx.x;
+  const int n = count_dev ? count_dev[0] : count_host;
+  if (tid == 0) base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < n; c0 += 1024) {
+    const int p = c0 + tid;
+    const int f = (p < n && moved[p]) ? 1 : 0;
+    sh[tid] = f;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int v = tid >= off ? sh[tid - off] : 0;
+      __syncthreads();
+      sh[tid] += v;
+      __syncthreads();
+    }
+    if (f) {
+      const int j = base + sh[tid] - 1;
+      act_idx[j] = p;
+      act_pos[3 * j] = pos[3 * p];
+      act_pos[3 * j + 1] = pos[3 * p + 1];
+      act_pos[3 * j + 2] = pos[3 * p + 2];
+      moved[p] = 0;
+    }
+    __syncthreads();
+    if (tid == 1023) base += sh[1023];
+    __syncthreads();
+  }
+  if (tid == 0) act_count[0] = base;
+}
+
+// the round's results written back to the candidates' rows; a candidate moves
+// on to the next round if its position changed
+__global__ void k_refine_scatter(const int* __restrict__ act_count, const int* __restrict__ act_idx, int K,
+                                 const int* __restrict__ t_pos, const float* __restrict__ t_quat,
+                                 const double* __restrict__ t_lam, const float* __restrict__ t_score,
+                                 const int* __restrict__ t_flags, const double* __restrict__ t_C,
+                                 int* __restrict__ out_pos, float* __restrict__ out_quat,
+                                 double* __restrict__ out_lambda, float* __restrict__ out_score,
+                                 int* __restrict__ out_flags, double* __restrict__ out_C, int* __restrict__ moved) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= act_count[0]) return;
+  const int p = act_idx[j];
+  bool mv = false;
+  for (int d = 0; d < 3; ++d) {
+    mv = mv || t_pos[3 * j + d] != out_pos[3 * p + d];
+    out_pos[3 * p + d] = t_pos[3 * j + d];
+  }
+  moved[p] = mv ? 1 : 0;
+  for (int d = 0; d < 4; ++d) out_quat[4 * p + d] = t_quat[4 * j + d];
+  out_lambda[p] = t_lam[j];
+  if (out_score) out_score[p] = t_score[j];
+  out_flags[p] = t_flags[j];
+  if (out_C)
+    for (int k = 0; k < K; ++k) out_C[(long)p * K + k] = t_C[(long)j * K + k];
+}
+
+hipError_t launch_refine_init(const int* count_dev, int count_host, const int* start, const int* pos, int* moved,
+                              int max_peaks, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_init, dim3((max_peaks + 255) / 256), dim3(256), 0, s, count_dev, count_host, start,
+                     pos, moved);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_compact(const int* count_dev, int count_host, int* moved, const int* pos, int* act_pos,
+                                 int* act_idx, int* act_count, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_compact, dim3(1), dim3(1024), 0, s, count_dev, count_host, moved, pos, act_pos,
+                     act_idx, act_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_scatter(const int* act_count, const int* act_idx, int K, const RefineTmp& t,
+                                 int* out_pos, float* out_quat, double* out_lambda, float* out_score,
+                                 int* out_flags, double* out_C, int* moved, int max_peaks, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_scatter, dim3((max_peaks + 255) / 256), dim3(256), 0, s, act_count, act_idx, K,
+                     t.pos, t.quat, t.lam, t.score, t.flags, t.C, out_pos, out_quat, out_lambda, out_score,
+                     out_flags, out_C, moved);
+  return hipGetLastError();
+}
+
 static PoseGeo make_posegeo(const Geo& gg) {
   PoseGeo g;
   g.n0 = gg.n0; g.n1 = gg.n1; g.n2 = gg.n2;
@@ -990,11 +1090,13 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
                              double tol, int max_peaks, int refine, const int* pos_in, const int* count_dev,
                              int count_host, const float* image, const float* tmpl, const float* mask,
                              int* out_pos, float* out_quat, double* out_lambda, float* out_score, int* out_flags,
-                             double* out_C, const PoseScratch& ps, hipStream_t s) {
+                             double* out_C, const PoseScratch& ps, hipStream_t s, bool reuse_tables,
+                             int ncc_groups) {
   const PoseGeo g = make_posegeo(gg);
   const int K = num_components(order_n);
   const int NB = refine ? 27 : 1;
-  hipLaunchKernelGGL(k_seed_table, dim3((n_seeds + 255) / 256), dim3(256), 0, s, n_seeds, ps.seeds);
+  if (!reuse_tables)
+    hipLaunchKernelGGL(k_seed_table, dim3((n_seeds + 255) / 256), dim3(256), 0, s, n_seeds, ps.seeds);
   const dim3 eg((unsigned)(max_peaks * NB));
   switch (order_n) {
     case 2:
@@ -1024,12 +1126,13 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
     default: return hipErrorInvalidValue;
   }
   if (refine == 2) {
-    hipLaunchKernelGGL(k_mask_list, dim3(1), dim3(1024), 0, s, mask, g.L0, g.L1, g.L2, ps.mlist, ps.mval,
-                       ps.mcount);
+    if (!reuse_tables)
+      hipLaunchKernelGGL(k_mask_list, dim3(1), dim3(1024), 0, s, mask, g.L0, g.L1, g.L2, ps.mlist, ps.mval,
+                         ps.mcount);
     if (ncc_lds_floats(g.L0, g.L1, g.L2) <= kNccLdsCap) {
       // one block per CU (the template fills most of the LDS); each block
-      // loads the template once for 9 neighbours of a candidate
-      const int ngroups = 3;
+      // loads the template once for 27 / ngroups neighbours of a candidate
+      const int ngroups = ncc_groups;
       hipLaunchKernelGGL(k_pose_ncc_lds, dim3((unsigned)(max_peaks * ngroups)), dim3(1024), 0, s, g, ngroups,
                          image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in, count_dev, count_host, ps.w, ps.ok,
                          ps.q, ps.ncc);

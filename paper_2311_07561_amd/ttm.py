@@ -100,7 +100,7 @@ _SIGS = {
     "ttm_autotune_workspace_bytes": (_SZ, [_DIMS, _I32, _P, _I32]),
     "ttm_autotune_tiles": (_I32, [_P, _P, _I32, _DIMS, _I32, _P, _OPTP, _I32, _P, _P, _SZ, _P]),
     "ttm_batch_workspace_bytes": (_SZ, [_P, _I32, _I32, _OPTP, _I32]),
-    "ttm_batch_match": (_I32, [_P, _I32, _I32, _OPTP, _P, _SZ, _P]),
+    "ttm_batch_match": (_I32, [_P, _I32, _I32, _OPTP, _I32, _P, _SZ, _P]),
     "ttm_batch_graph_create": (_I32, [_P, _I32, _I32, _OPTP, _I32, _P, _SZ, _P, _P]),
     "ttm_graph_launch": (_I32, [_P, _P]),
     "ttm_graph_destroy": (None, [_P]),
@@ -280,7 +280,7 @@ def recover_pose(score: torch.Tensor, image: torch.Tensor, components: torch.Ten
                  tmpl: torch.Tensor | None = None):
     """Peaks of F and the dominant Z-eigenpair of C_n at each.  Returns a dict
     of device tensors trimmed to the number of peaks found (one sync).  The raw
-    template ``tmpl`` is needed with ``opt.refine == 2``."""
+    template ``tmpl`` is needed with ``opt.refine >= 2``."""
     dev = score.device
     K = num_components(order)
     N = _dims(score.shape)
@@ -408,7 +408,7 @@ def match(image: torch.Tensor, bank: torch.Tensor, mask: torch.Tensor, order: in
           bufs: MatchBuffers, tmpl: torch.Tensor | None = None):
     """Correlation, peaks and poses in one asynchronous call (ttm_match);
     results land in ``bufs`` (score map in bufs.score, w in bufs.w).  The raw
-    template ``tmpl`` is needed with ``opt.refine == 2``."""
+    template ``tmpl`` is needed with ``opt.refine >= 2``."""
     dev = image.device
     N = _dims(image.shape)
     L = _dims(mask.shape)
@@ -586,11 +586,13 @@ def batch_workspace(jobs, order: int, opt: Options, device, n_streams: int = 1) 
     return _workspace(n, device)
 
 
-def batch_match(jobs, order: int, opt: Options, workspace: torch.Tensor, device=None):
-    """Run the jobs eagerly, one after another on the current stream."""
+def batch_match(jobs, order: int, opt: Options, workspace: torch.Tensor, device=None, n_streams: int = 1):
+    """Run the jobs eagerly on the current stream (split over ``n_streams``
+    concurrent branches forked from it and joined back to it when > 1; the
+    workspace from ``batch_workspace(..., n_streams)``)."""
     arr, ptr = _jobs_array(jobs)
-    st = lib().ttm_batch_match(ptr, len(jobs), order, ctypes.byref(opt), workspace.data_ptr(), workspace.numel(),
-                               _stream(device or workspace.device))
+    st = lib().ttm_batch_match(ptr, len(jobs), order, ctypes.byref(opt), int(n_streams), workspace.data_ptr(),
+                               workspace.numel(), _stream(device or workspace.device))
     _check(st, "ttm_batch_match")
 
 

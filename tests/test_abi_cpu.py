@@ -87,9 +87,14 @@ def test_argument_validation_without_gpu():
     bad = _opt(threshold=-1.0)
     args[8] = ctypes.byref(bad)
     assert L.ttm_recover_pose(*args) == -1
-    bad = _opt(refine=3)
+    bad = _opt(refine=4)
     args[8] = ctypes.byref(bad)
     assert L.ttm_recover_pose(*args) == -1
+    bad = _opt(refine=3)        # refine 3 needs the raw template like 2
+    args[8] = ctypes.byref(bad)
+    args[4] = None
+    assert L.ttm_recover_pose(*args) == -1
+    args[4] = fake
     # refine 2 needs the raw template
     bad = _opt(refine=2)
     args[8] = ctypes.byref(bad)
@@ -214,22 +219,22 @@ def test_batch_and_tiled_validation_without_gpu():
     arr = (ttm.BatchJob * 1)(job)
     one = L.ttm_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), 1)
     assert one > 0
-    assert L.ttm_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), 3) == 3 * one
+    assert L.ttm_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), 3) == 3 * one - 512
     assert L.ttm_batch_workspace_bytes(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), 9) == 0
     bad = ttm.BatchJob.from_buffer_copy(job)
     bad.out_count = None
     arr2 = (ttm.BatchJob * 1)(bad)
-    assert L.ttm_batch_match(ctypes.cast(arr2, ctypes.c_void_p), 1, 4, ctypes.byref(o), fake, big, None) == -1
+    assert L.ttm_batch_match(ctypes.cast(arr2, ctypes.c_void_p), 1, 4, ctypes.byref(o), 1, fake, big, None) == -1
     r2 = _opt(refine=2)
     nt = ttm.BatchJob.from_buffer_copy(job)
     nt.tmpl = None
     arr3 = (ttm.BatchJob * 1)(nt)
-    assert L.ttm_batch_match(ctypes.cast(arr3, ctypes.c_void_p), 1, 4, ctypes.byref(r2), fake, big, None) == -1
+    assert L.ttm_batch_match(ctypes.cast(arr3, ctypes.c_void_p), 1, 4, ctypes.byref(r2), 1, fake, big, None) == -1
     wrong = ttm.BatchJob.from_buffer_copy(job)
     wrong.tile = 8
     arr4 = (ttm.BatchJob * 1)(wrong)
-    assert L.ttm_batch_match(ctypes.cast(arr4, ctypes.c_void_p), 1, 4, ctypes.byref(o), fake, big, None) == -2
-    assert L.ttm_batch_match(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), fake, 64, None) == -3
+    assert L.ttm_batch_match(ctypes.cast(arr4, ctypes.c_void_p), 1, 4, ctypes.byref(o), 1, fake, big, None) == -2
+    assert L.ttm_batch_match(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), 1, fake, 64, None) == -3
     # capture needs a created stream and an output handle
     h = ctypes.c_void_p()
     assert L.ttm_batch_graph_create(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(o), 1, fake, big, None,

@@ -374,3 +374,85 @@ def test_peak_search_rounds_match_oracle(min_dist, max_peaks):
     ref = O.find_peaks_fast(F, L, 0.0, min_dist, max_peaks)
     assert np.array_equal(res["pos"].cpu().numpy(), ref)
     assert not res["truncated"]
+
+
+def _iterate_refine2(img, comps, mask, n, xs, tmpl, rounds=4, **kw):
+    """refine = 2 applied from its own result until nothing moves (at most
+    `rounds` applications): the definition of refine = 3."""
+    opt = ttm.default_options(max_peaks=len(xs), refine=2, **kw)
+    cur = np.asarray(xs, dtype=np.int32)
+    res = None
+    active = np.ones(len(cur), dtype=bool)
+    out = {}
+    for r in range(rounds):
+        idx = np.nonzero(active)[0]
+        if len(idx) == 0:
+            break
+        res = ttm.pose_at(img, comps, mask, n, cur[idx], opt, tmpl=tmpl)
+        npos = res["pos"].cpu().numpy()
+        for j, i in enumerate(idx):
+            out[i] = (npos[j].copy(), res["quat"].cpu().numpy()[j].copy(), float(res["lam"].cpu().numpy()[j]),
+                      int(res["flags"].cpu().numpy()[j]))
+            active[i] = not np.array_equal(npos[j], cur[i])
+            cur[i] = npos[j]
+    return out
+
+
+def test_iterated_refinement_is_refine2_repeated():
+    """refine = 3 (pose_at): two copies, started two voxels off along corner
+    diagonals, reach their centres; positions, rotations and lambdas equal
+    those of refine = 2 applied from its own result until nothing moves."""
+    img, tmpl, mask, _, _ = rand_setup(62, (48, 48, 48), (10, 10, 10), 4.6, 8)
+    img *= 0.05
+    n = 4
+    # a quadrature fine enough to resolve the rotation at the copies (the
+    # climb stalls where the recovered rotation is off)
+    q = synth.super_fibonacci(2000).astype(np.float32)
+    w = np.full(len(q), 1.0 / len(q))
+    planted = synth.random_quaternions(np.random.default_rng(63), 2)
+    for qp, c in ((planted[0], 15), (planted[1], 32)):
+        s = O.rotated_template(tmpl, mask, qp)
+        sl = tuple(slice(c - 5, c + 5) for _ in range(3))
+        img[sl] += (2.0 * s).astype(np.float32)
+    comps, _ = ttm.build_tensor_template(dev(tmpl), dev(mask), n, q, w)
+    xs = np.array([[17, 13, 17], [30, 34, 30], [24, 20, 27]], dtype=np.int32)
+    opt = ttm.default_options(max_peaks=len(xs), refine=3)
+    rr = ttm.pose_at(dev(img), comps, dev(mask), n, xs, opt, tmpl=dev(tmpl))
+    ref = _iterate_refine2(dev(img), comps, dev(mask), n, xs, dev(tmpl))
+    pos, quat = rr["pos"].cpu().numpy(), rr["quat"].cpu().numpy()
+    lam, flags = rr["lam"].cpu().numpy(), rr["flags"].cpu().numpy()
+    for i in range(len(xs)):
+        p, qq, ll, ff = ref[i]
+        assert np.array_equal(pos[i], p) and np.array_equal(quat[i], qq) and lam[i] == ll and flags[i] == ff, i
+    assert np.array_equal(pos[0], [15, 15, 15]) and np.array_equal(pos[1], [32, 32, 32])
+    print(f"\nrefine 3 from two voxels off: {pos.tolist()}")
+
+
+def test_match_iterated_refinement():
+    """ttm_match with refine = 3 on the 256^3 workload: the same peaks as
+    refine = 2, each then moved as refine = 2 repeated (pose_at from the match's
+    refine = 2 positions); rotations agree to 0.01 degree (the match reads
+    C_n from the correlated float32 field, pose_at sums it in float64)."""
+    wl = synth.workload_tomogram()
+    n = wl.order
+    q = synth.super_fibonacci(2000).astype(np.float32)
+    w = np.full(len(q), 1.0 / len(q))
+    img, mk, tm = dev(wl.image), dev(wl.mask), dev(wl.template)
+    comps, bank = ttm.build_tensor_template(tm, mk, n, q, w, image_shape=wl.image.shape)
+    res = {}
+    for rf in (2, 3):
+        opt = ttm.default_options(max_peaks=len(wl.positions), min_dist=16.0, threshold=0.0, refine=rf)
+        bufs = ttm.MatchBuffers(wl.image.shape, wl.template.shape, n, opt, "cuda")
+        ttm.match(img, bank, mk, n, opt, bufs, tmpl=tm)
+        res[rf] = bufs.result()
+    p2 = res[2]["pos"].cpu().numpy()
+    ref = _iterate_refine2(img, comps, mk, n, p2, tm, rounds=3)
+    p3, q3 = res[3]["pos"].cpu().numpy(), res[3]["quat"].cpu().numpy()
+    moved = 0
+    for i in range(len(p2)):
+        # round 1 of refine 3 is refine 2: rounds 2.. are pose_at's rounds 1..
+        pi, qi, li, fi = ref[i]
+        assert np.array_equal(p3[i], pi), (i, p3[i], pi)
+        assert O.rotation_angle_deg(q3[i], qi) <= 0.01
+        moved += int(not np.array_equal(pi, p2[i]))
+    print(f"\nrefine 3 moved {moved} of {len(p2)} candidates further than refine 2")

@@ -496,6 +496,31 @@ def test_refinement_returns_to_a_noiseless_copy():
         assert len(fin) == 27 and fin.max() == ncc
 
 
+def test_iterated_refinement_climbs_to_a_noiseless_copy():
+    # the same nearly noiseless copy, started two voxels away along a corner
+    # diagonal: one NCC refinement step moves one voxel; repeated from its own
+    # result it reaches the copy and stops there (the copy is a fixed point:
+    # its NCC is the largest of its neighbourhood), in three rounds
+    L, n = 12, 4
+    tm = synth.make_blob_template(_rng(60), L, 5, L / 2)
+    t = tm.grid()
+    m = synth.ball_mask(L, L / 2)
+    qs = synth.super_fibonacci(3000)
+    T = O.tensor_template(t, m, n, qs, np.full(len(qs), 1.0 / len(qs)))
+    qtrue = synth.random_quaternions(_rng(61), 1)[0]
+    x0 = np.array([12, 12, 12])
+    f = synth.render_copies((24, 24, 24), tm, x0[None], qtrue[None])
+    f = f + 0.01 * _rng(62).standard_normal(f.shape)
+    start = x0 + np.array([2, -2, 2])
+    # a cap of one round is the single step
+    one, _, _, _, r1 = O.refine_by_ncc_iterated(f, t, m, T, n, start, n_brute=4000, max_rounds=1)
+    assert np.abs(one - x0).max() == 1 and r1 == 1, one
+    pos, q, lam, ncc, rounds = O.refine_by_ncc_iterated(f, t, m, T, n, start, n_brute=4000)
+    assert np.array_equal(pos, x0), pos
+    assert rounds == 3, rounds
+    assert ncc > 0.95 and O.rotation_angle_deg(q, qtrue) < 3.0
+
+
 # --------------------------------------------------------------------------
 # gradient of the score (adjoint) against central finite differences
 # --------------------------------------------------------------------------
