@@ -840,3 +840,82 @@ def soft_mask(L, r_in: float, r_out: float) -> np.ndarray:
     r = np.sqrt(g[0] ** 2 + g[1] ** 2 + g[2] ** 2)
     t = np.clip((r - r_in) / (r_out - r_in), 0.0, 1.0)
     return 0.5 * (1.0 + np.cos(np.pi * t))
+
+
+# ----------------------------------------------------------------------------
+# S'-consistent normalisation (Section 3.4, the false-positive discussion;
+# S_2 and S' = S_2 S from the proof of Theorem "main")
+# ----------------------------------------------------------------------------
+#
+# The tensor correlation is an inner product under S' = S_2 S, where S_2 is the
+# convolution on SO(3) with the kernel K(P) = (P . I)^n = a_P^n of the
+# polynomial features Q^{(.)n}, but it is normalised under S.  The
+# S'-consistent score divides lambda by the S'-norms of the (S-normalised)
+# window and template.  The paper states the quantity and no algorithm; the
+# SO(3) integral of S_2 is taken with the tensor template's own quadrature
+# {(Q_j, omega_j)}, and every rotated copy is re-normalised under the mask,
+# as the rotated templates of the tensor template are:
+#
+#   D(h) = sum_j omega_j a_j^n <h~, N_m(I_{R_j} h~)>,
+#   h~ = P_S h / ||P_S h||_S,  P_S h = h - <h,m>/m_sum,
+#
+# with I_R the trilinear rotation about the box centre and N_m the masked
+# normalisation.  In the continuum D(h) = ||h~||^2_{S'}.  The S'-normalised
+# score at a candidate x with dominant eigenvalue lambda(x) is
+#
+#   rho'(x) = lambda(x) / sqrt(D(tau_x f) D(t)),
+#
+# which lies in [-1, 1] where the discrete S' form is positive semidefinite
+# (exactly so for a quadrature that is a finite rotation group with equal
+# weights and grid-exact rotations) and is 1 at a noiseless copy.
+
+SNORM_FLAT_REL = 1e-6
+
+
+def s_prime_norm2(h, m, n: int, quats, weights) -> float:
+    """``D(h)``: the squared S'-norm of the S-normalised box ``h`` (see the
+    section comment).  A window whose masked variance is at most
+    ``1e-6 sum m h^2`` is flat: NaN.  A rotated copy whose masked variance is at
+    most ``1e-6`` of its masked second moment contributes 0."""
+    h = np.asarray(h, dtype=np.float64)
+    m = np.asarray(m, dtype=np.float64)
+    msum = m.sum()
+    mu = float((m * h).sum()) / msum
+    g = h - mu
+    v = float((m * g * g).sum())
+    if not v > SNORM_FLAT_REL * float((m * h * h).sum()):
+        return math.nan
+    ht = g / math.sqrt(v)
+    quats = np.asarray(quats, dtype=np.float64)
+    quats = quats / np.linalg.norm(quats, axis=1, keepdims=True)
+    D = 0.0
+    for q, om in zip(quats, np.asarray(weights, dtype=np.float64)):
+        r = rotate_trilinear(ht, q)
+        s1 = float((m * r).sum())
+        s2 = float((m * r * r).sum())
+        var = s2 - s1 * s1 / msum
+        if not var > SNORM_FLAT_REL * s2:
+            continue
+        nr = m * (r - s1 / msum) / math.sqrt(var)          # N_m(I_R h~)
+        D += om * q[0] ** n * float((ht * nr).sum())
+    return D
+
+
+def s_prime_norms_at(f, t, m, n: int, quats, weights, xs):
+    """``D`` of the image window ``tau_x f`` at each position of ``xs`` (which
+    must lie in the valid region) and of the template: (Dx (P,), Dt)."""
+    L = np.shape(t)
+    W = windows(f, np.asarray(xs, dtype=np.int64).reshape(-1, 3), L)
+    Dx = np.array([s_prime_norm2(W[p], m, n, quats, weights) for p in range(len(W))])
+    return Dx, s_prime_norm2(t, m, n, quats, weights)
+
+
+def s_prime_score(lam, Dx, Dt):
+    """``rho' = lambda / sqrt(Dx Dt)``; 0 where either norm is not positive
+    (a flat window, or a quadrature whose discrete S' form is not positive
+    there)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    Dx = np.asarray(Dx, dtype=np.float64)
+    ok = (Dx > 0) & (Dt > 0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(ok, lam / np.sqrt(np.where(ok, Dx * Dt, 1.0)), 0.0)

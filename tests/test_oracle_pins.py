@@ -628,3 +628,99 @@ def test_soft_mask_shape():
     # rotationally symmetric on the grid (odd box: its centre is the array's)
     m15 = O.soft_mask(15, 4.5, 6.5)
     assert np.allclose(m15, np.rot90(m15, axes=(0, 2))) and np.allclose(m15, np.transpose(m15, (2, 0, 1)))
+
+
+# --------------------------------------------------------------------------
+# S'-consistent normalisation (Section 3.4, false positives; S' = S_2 S from
+# the proof of Theorem "main")
+# --------------------------------------------------------------------------
+
+def _cube_rotations():
+    """The 24 rotations of the cube, one quaternion per rotation."""
+    g = synth.binary_octahedral()
+    keep = [q for q in g if q[np.nonzero(q)[0][0]] > 0]
+    assert len(keep) == 24
+    return np.array(keep)
+
+
+def _ball(L, radius):
+    c = L // 2
+    g = np.meshgrid(*[np.arange(L) - c] * 3, indexing="ij")
+    r2 = g[0] ** 2 + g[1] ** 2 + g[2] ** 2
+    return (np.sqrt(r2) < radius).astype(np.float64), r2
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 8])
+def test_s_prime_norm_closed_form_on_the_cube_group(n):
+    """A window invariant under the cube's rotations, the 24 rotations as the
+    quadrature (grid-exact, equal weights): every rotated copy is the window,
+    so D = (1/24) sum_R a_R^n.  The classes of the group: the identity (a = 1),
+    three half-turns about the axes and six about the edge diagonals (a = 0),
+    six quarter-turns (a = 1/sqrt 2) and eight third-turns about the body
+    diagonals (a = 1/2)."""
+    m, r2 = _ball(11, 4.6)
+    h = 3.0 + 2.0 * np.exp(-r2 / 8.0)          # radial, with an offset and a scale
+    D = O.s_prime_norm2(h, m, n, _cube_rotations(), np.full(24, 1 / 24))
+    closed = (1.0 + 6.0 * 2.0 ** (-n / 2) + 8.0 * 2.0 ** (-n)) / 24.0
+    assert abs(D - closed) < 1e-12
+
+
+def test_s_prime_score_bounded_and_one_at_a_copy_on_the_cube_group():
+    """With the cube group as the quadrature the discrete S' form is a group
+    convolution with the positive-definite kernel a^n, so the S'-normalised
+    score obeys Cauchy-Schwarz at every position and every group rotation,
+    with equality at a noiseless copy (affinely changed) rotated by a group
+    element."""
+    G, w, n = _cube_rotations(), np.full(24, 1 / 24), 4
+    L, c = 11, 5
+    m, _ = _ball(L, 4.6)
+    rng = _rng(41)
+    t = rng.standard_normal((L, L, L))
+    f = rng.standard_normal((40, 40, 40))
+    T = O.tensor_template(t, m, n, G, w)
+    xs = np.array([[10, 12, 20], [20, 20, 20], [30, 15, 8], [7, 33, 25]])
+    C = O.tensor_field_at(f, T, m, xs)
+    Dx, Dt = O.s_prime_norms_at(f, t, m, n, G, w, xs)
+    assert Dt > 0 and np.all(Dx > 0)
+    for p in range(len(xs)):
+        lam = np.array([O.tensor_apply(C[p], n, q) for q in G])
+        rho = O.s_prime_score(lam, np.full(24, Dx[p]), Dt)
+        assert np.all(np.abs(rho) <= 1.0 + 1e-12)
+    # the copy: rotate by a group element with numpy index operations only
+    # (a quarter-turn about axis 0 is rot90 over axes (1, 2))
+    q0 = np.array([math.cos(math.pi / 4), math.sin(math.pi / 4), 0.0, 0.0])
+    x0 = np.array([20, 20, 20])
+    f2 = f.copy()
+    f2[x0[0] - c:x0[0] - c + L, x0[1] - c:x0[1] - c + L, x0[2] - c:x0[2] - c + L] = \
+        2.5 * np.rot90(t, 1, axes=(1, 2)) + 1.0
+    C2 = O.tensor_field_at(f2, T, m, x0[None])
+    Dx2, _ = O.s_prime_norms_at(f2, t, m, n, G, w, x0[None])
+    assert abs(Dx2[0] - Dt) < 1e-12 * Dt
+    rho = O.s_prime_score([O.tensor_apply(C2[0], n, q0)], Dx2, Dt)[0]
+    assert abs(rho - 1.0) < 1e-12
+
+
+def test_s_prime_norm_continuum_value_for_a_radial_window():
+    """In the continuum, a rotation-invariant window is its own rotated copy,
+    so ||h~||^2_{S'} = int_{SO(3)} a_P^n dP = E[a^n] over the unit sphere of
+    R^4 = Gamma((n+1)/2) / (sqrt(pi) Gamma((n+4)/2)) (1/4, 1/8, 5/64 for
+    n = 2, 4, 6).  A smooth radial blob with a dense quadrature reaches it to
+    the quadrature and interpolation error."""
+    q = synth.super_fibonacci(2000)
+    w = np.full(len(q), 1.0 / len(q))
+    m, r2 = _ball(15, 6.5)
+    h = np.exp(-r2 / (2 * 3.0 ** 2))
+    n = 4
+    D = O.s_prime_norm2(h, m, n, q, w)
+    E = math.gamma((n + 1) / 2) / (math.sqrt(math.pi) * math.gamma((n + 4) / 2))
+    assert abs(E - 0.125) < 1e-15
+    assert abs(D / E - 1.0) < 2e-3
+
+
+def test_s_prime_norm_flat_window_and_zero_score():
+    L = 9
+    m, _ = _ball(L, 3.6)
+    G = _cube_rotations()
+    assert math.isnan(O.s_prime_norm2(np.full((L, L, L), 2.0), m, 4, G, np.full(24, 1 / 24)))
+    rho = O.s_prime_score([0.5, 0.5, 0.5], [math.nan, -1.0, 0.04], 0.04)
+    assert rho[0] == 0.0 and rho[1] == 0.0 and abs(rho[2] - 12.5) < 1e-12
