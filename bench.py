@@ -94,6 +94,8 @@ def parse():
     p.add_argument("--batch-replays", type=int, default=2)
     p.add_argument("--batch-streams", type=int, default=4, help="concurrent branches of the batch graph")
     p.add_argument("--batch-workers", type=int, default=16, help="processes generating the batch tomograms")
+    p.add_argument("--snorm-steps", type=int, default=3,
+                   help="timed runs of the S'-normalisation of the peaks (0: skip)")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU time of the oracle baseline sample (0 = skip)")
     p.add_argument("--seed", type=int, default=2000)
@@ -170,6 +172,57 @@ def match_errors(pos, quats, planted, truth, angle, radius=2.0):
     return errs
 
 
+def run_snorm(wl, img, tmpl, mask, order, qb, wb, bank, bufs, opt, args, ttm, synth, torch):
+    """S'-normalised scores (ttm_snorm, with the device count): the time per
+    call on the match's peaks, then how the Frobenius score F, the eigenvalue
+    lambda and rho' rank copies against smooth decoys: the same tomogram with
+    25 smooth radial bumps added, matched with room for 75 peaks."""
+    def call(b):
+        return ttm.snorm(img if b is bufs else dimg, tmpl, mask, order, qb, wb, b.pos, b.lam, count=b.count)
+
+    ms, prof = time_steps(lambda: call(bufs), args.snorm_steps, 1, ttm, torch)
+    kern = prof.get("snorm", (0.0, 0))
+    cnt = int(bufs.count[0])
+    nm = int((wl.mask != 0).sum())
+    out = {"ms": round(ms, 4), "windows": cnt + 1, "rotations": len(qb), "mask_voxels": nm,
+           "voxel_rotations_per_s": (cnt + 1) * len(qb) * nm / (ms / 1e3),
+           "kernel_ms": round(kern[0] / args.snorm_steps, 4)}
+
+    dwl, decoys = synth.add_smooth_decoys(wl, args.seed + 4, 25)
+    dimg = torch.as_tensor(dwl.image, device=img.device)
+    P = len(wl.positions) + len(decoys)
+    dopt = ttm.default_options(max_peaks=P, min_dist=opt.min_dist, threshold=0.0, refine=opt.refine)
+    dbufs = ttm.MatchBuffers(dwl.image.shape, dwl.template.shape, order, dopt, img.device)
+    ttm.match(dimg, bank, mask, order, dopt, dbufs, tmpl=tmpl)
+    rho, D, flags = call(dbufs)
+    torch.cuda.synchronize()
+    n = int(dbufs.count[0])
+    pos = dbufs.pos[:n].cpu().numpy()
+    near = lambda pts: np.array([np.min(np.linalg.norm(pts - x[None], axis=1)) <= 2.0 for x in pos])
+    on_copy, on_decoy = near(wl.positions), near(decoys)
+    keys = {"F": dbufs.peak_score[:n].cpu().numpy(), "lambda": dbufs.lam[:n].cpu().numpy(),
+            "rho": rho[:n].cpu().numpy()}
+    k = len(wl.positions)
+    ranks = {}
+    for name, v in keys.items():
+        top = np.argsort(-v, kind="stable")[:k]
+        ranks[name] = {"copies": int(on_copy[top].sum()), "decoys": int(on_decoy[top].sum())}
+
+    def med(v):
+        return round(float(np.median(v)), 4) if v.size else None
+
+    out["decoys"] = {"workload": dwl.name, "peaks": n, "copies_found": int(on_copy.sum()),
+                     "decoys_found": int(on_decoy.sum()), "flags": int(np.count_nonzero(flags[:n].cpu().numpy())),
+                     f"top{k}": ranks,
+                     "median_on_copies": {nm_: med(v[on_copy]) for nm_, v in keys.items()},
+                     "median_on_decoys": {nm_: med(v[on_decoy]) for nm_, v in keys.items()}}
+    log(f"S'-normalisation: {ms:.3f} ms for {cnt} peaks + template, {len(qb)} rotations; decoys: "
+        f"{n} peaks ({int(on_copy.sum())} copies, {int(on_decoy.sum())} decoys), top {k} by F / lambda / rho': "
+        f"{ranks['F']} / {ranks['lambda']} / {ranks['rho']}")
+    del dbufs, dimg
+    return out
+
+
 def run_order(order, wl, img, tmpl, mask, args, ttm, synth, torch, dev, angle, with_profile):
     N = wl.image.shape
     L = wl.template.shape
@@ -196,6 +249,8 @@ def run_order(order, wl, img, tmpl, mask, args, ttm, synth, torch, dev, angle, w
     det = match_errors(res["pos"].cpu().numpy(), res["quat"].cpu().numpy(), wl.positions, wl.true_quats, angle)
     out = {"order": order, "components": K, "ms_per_step": ms, "build_ms": round(build_ms, 1),
            "pose_detected": dict(err_stats(det), recall=len(det) / len(wl.positions), refine=args.refine)}
+    if args.snorm_steps > 0:
+        out["snorm"] = run_snorm(wl, img, tmpl, mask, order, qb, wb, bank, bufs, opt, args, ttm, synth, torch)
     if args.refine == 3:
         # the single-round refinement's step time, for comparison
         opt2 = ttm.default_options(max_peaks=len(wl.positions), min_dist=float(L[0]) / 2, threshold=0.0, refine=2)

@@ -292,6 +292,56 @@ ttm_status ttm_rotation_map(
     size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * S'-consistent normalisation of peak scores (Section 3.4, the discussion of
+ * false positives; S_2 and S' = S_2 S from the proof of Theorem 1).
+ * The tensor correlation lambda(x) = w(x) <tau_x f, t_Q>_{S'} is an inner
+ * product under S' normalised under S, so it is not bounded by 1 and favours
+ * smooth windows.  The paper states the quantity and no algorithm; here the
+ * SO(3) convolution S_2 (kernel a^n of the identity's features) takes the
+ * tensor template's own rotation quadrature.  Per window h (the image box of
+ * each position, and the template):
+ *   D(h) = sum_j omega_j a_j^n <h~, N_m(I_{R_j} h~)>,
+ *   h~ = (h - <h,m>/m_sum) / ||h - <h,m>/m_sum||_S,
+ * with I_R the trilinear rotation about the box centre (zero outside the box)
+ * and N_m the masked normalisation of the tensor build; then
+ *   rho'(x) = lambda(x) / sqrt(D(tau_x f) D(t)),
+ * which is 1 at a noiseless copy and lies in [-1, 1] wherever the discrete S'
+ * form is positive semidefinite.
+ *
+ *   image, N     [n0][n1][n2] float32 (any extents, n_i <= 8192, volume < 2^31)
+ *   tmpl, mask, L, order_n, quats_host, weights_host, n_rot
+ *                as given to ttm_build_tensor_template (the same quadrature)
+ *   pos          max_pos x 3 int32 device positions (e.g. ttm_recover_pose's
+ *                out_pos); a window that leaves the image is flagged
+ *   lambda       max_pos float64 device: lambda at each position (e.g.
+ *                ttm_recover_pose's out_lambda)
+ *   count        one int32 on the device, the number of positions used
+ *                (clamped to [0, max_pos]), or NULL for max_pos
+ *   out_rho      max_pos float32: rho' (0 where flagged)
+ *   out_D        max_pos + 1 float64: D of each window, then D of the
+ *                template (NaN for a flat or outside window)
+ *   out_flags    max_pos int32 TTM_SNORM_* bits
+ * Entries past count are not written.  Masked variance at most 1e-6 of the
+ * masked second moment marks a window flat; a rotated copy with as little
+ * variance adds nothing to D.  The mask's nonzero voxels must lie in the box
+ * (each extent of L at most 1023).  Workspace from
+ * ttm_snorm_workspace_bytes.  Errors: TTM_E_ARG (NULL pointers, order,
+ * quadrature, max_pos), TTM_E_SIZE, TTM_E_WORKSPACE, TTM_E_HIP.
+ * ------------------------------------------------------------------------- */
+#define TTM_SNORM_FLAT      1   /* the window's masked variance vanishes    */
+#define TTM_SNORM_NONPOS    2   /* D(window) <= 0 in this quadrature        */
+#define TTM_SNORM_OUTSIDE   4   /* the window leaves the image              */
+#define TTM_SNORM_TEMPLATE  8   /* D(template) is not positive              */
+size_t ttm_snorm_workspace_bytes(ttm_dims L, int32_t n_rot, int32_t max_pos);
+ttm_status ttm_snorm(
+    const float* image, ttm_dims N, const float* tmpl, const float* mask,
+    ttm_dims L, int32_t order_n, const float* quats_host,
+    const double* weights_host, int32_t n_rot, const int32_t* pos,
+    const double* lambda, const int32_t* count, int32_t max_pos,
+    float* out_rho, double* out_D, int32_t* out_flags, void* ws,
+    size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Tomograms of any extent: overlap-save tiling onto power-of-two FFT tiles.
  * The correlation of Section 2 (ttm_correlate's score F and w) is computed on
  * cubic tiles of edge T (a supported length, T >= each template extent).
@@ -469,13 +519,14 @@ ttm_status ttm_score_backward(
  *   0 image moments, 1 axis-2 R2C rows, 2 axis-1 forward pencils,
  *   3 pass 1 (axis-0 fan-out), 4 axis-1 inverse pencils, 5 pass 3 (axis-2 C2R
  *   + reduction), 6 peaks, 7 pose, 8 tensor build, 9 classical epilogue,
- *   10 rotation-map seed scan, 11 rotation-map seed table, fills and polish.
+ *   10 rotation-map seed scan, 11 rotation-map seed table, fills and polish,
+ *   12 S'-normalisation.
  * ttm_profile_read waits for the recorded events, writes the summed
  * milliseconds and launch counts of the first n classes, clears the record
  * and returns the number of classes (or TTM_E_HIP).  Event pairs are created
  * on first use and reused; with profiling off nothing is recorded.
  * ------------------------------------------------------------------------- */
-#define TTM_PROFILE_CLASSES 12
+#define TTM_PROFILE_CLASSES 13
 void ttm_profile_enable(int32_t on);
 int32_t ttm_profile_read(double* ms_out, int64_t* launches_out, int32_t n);
 const char* ttm_profile_class_name(int32_t cls);

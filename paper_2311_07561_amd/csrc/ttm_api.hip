@@ -51,10 +51,11 @@ static Geo make_geo(const ttm_dims& N, const ttm_dims& L) {
 
 // ---- optional event-pair instrumentation --------------------------------------
 enum ProfClass { PC_STATS = 0, PC_ROWS, PC_PEN_FWD, PC_PASS1, PC_PEN_INV, PC_PASS3, PC_PEAKS, PC_POSE,
-                 PC_BUILD, PC_EPI, PC_RMAP_SCAN, PC_RMAP_POLISH, PC_COUNT };
+                 PC_BUILD, PC_EPI, PC_RMAP_SCAN, PC_RMAP_POLISH, PC_SNORM, PC_COUNT };
 static const char* kProfNames[PC_COUNT] = {"image_moments", "r2c_rows", "pencils_fwd", "pass1_fanout",
                                            "pencils_inv", "pass3_c2r_reduce", "peaks", "pose",
-                                           "tensor_build", "classical_epilogue", "rmap_scan", "rmap_polish"};
+                                           "tensor_build", "classical_epilogue", "rmap_scan", "rmap_polish",
+                                           "snorm"};
 struct Prof {
   std::mutex mu;
   bool on = false;
@@ -994,6 +995,72 @@ ttm_status ttm_rotation_map(const float* image, ttm_dims N, const void* bank, tt
   TTM_PROF(PC_RMAP_POLISH, launch_rmap_polish(g, order_n, rw.planes, seeds, rw.group, opt->hopm_max_iter,
                                               opt->hopm_tol, out_score, out_quat, out_lambda, out_unconverged,
                                               stream));
+  return TTM_OK;
+}
+
+// --- S'-consistent normalisation ------------------------------------------------
+constexpr int kSnormMaxPos = 1 << 16;
+
+static SnormWs snorm_layout(Carve& c, const ttm_dims& L, int n_rot, int max_pos) {
+  SnormWs w;
+  const int n_pad = snorm_pad(n_rot);
+  const size_t nL = (size_t)L.n0 * L.n1 * L.n2;
+  const int n_win = max_pos + 1;
+  w.quats = c.take<float>(4 * (size_t)n_rot);
+  w.weights = c.take<double>((size_t)n_rot);
+  w.rtab = c.take<float>(12 * (size_t)n_pad);
+  w.kap = c.take<double>((size_t)n_pad);
+  w.mlist = c.take<unsigned>(nL);
+  w.mval = c.take<float>(nL);
+  w.mcount = c.take<int>(1);
+  w.slabs = c.take<float>((size_t)n_win * nL);
+  w.stat = c.take<double>(4 * (size_t)n_win);
+  w.partial = c.take<double>((size_t)n_win * snorm_chunks(n_win, n_pad));
+  return w;
+}
+
+static bool snorm_box_ok(const ttm_dims& L) {
+  return dims_ok(L) && L.n0 <= 1023 && L.n1 <= 1023 && L.n2 <= 1023 && (long)L.n0 * L.n1 * L.n2 <= (1L << 24);
+}
+
+size_t ttm_snorm_workspace_bytes(ttm_dims L, int32_t n_rot, int32_t max_pos) {
+  if (!snorm_box_ok(L) || n_rot < 1 || max_pos < 1 || max_pos > kSnormMaxPos) return 0;
+  Carve c(nullptr);
+  snorm_layout(c, L, n_rot, max_pos);
+  return c.size();
+}
+
+ttm_status ttm_snorm(const float* image, ttm_dims N, const float* tmpl, const float* mask, ttm_dims L,
+                     int32_t order_n, const float* quats_host, const double* weights_host, int32_t n_rot,
+                     const int32_t* pos, const double* lambda, const int32_t* count, int32_t max_pos,
+                     float* out_rho, double* out_D, int32_t* out_flags, void* ws, size_t ws_bytes,
+                     hipStream_t stream) {
+  if (!image || !tmpl || !mask || !quats_host || !weights_host || !pos || !lambda || !out_rho || !out_D ||
+      !out_flags)
+    return TTM_E_ARG;
+  if (ttm_num_components(order_n) < 0 || n_rot < 1 || max_pos < 1 || max_pos > kSnormMaxPos) return TTM_E_ARG;
+  double wsum = 0.0;
+  for (int j = 0; j < n_rot; ++j) {
+    const float* q = quats_host + 4 * j;
+    const double nq = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3];
+    if (!std::isfinite(nq) || nq <= 0.0) return TTM_E_ARG;
+    if (!std::isfinite(weights_host[j])) return TTM_E_ARG;
+    wsum += weights_host[j];
+  }
+  if (std::fabs(wsum - 1.0) > 1e-6) return TTM_E_ARG;
+  if (!snorm_box_ok(L) || !any_dims_ok(N)) return TTM_E_SIZE;
+  if (!ws || ws_bytes < ttm_snorm_workspace_bytes(L, n_rot, max_pos)) return TTM_E_WORKSPACE;
+  Carve c(ws);
+  SnormWs w = snorm_layout(c, L, n_rot, max_pos);
+  SnormGeo g;
+  g.n0 = N.n0; g.n1 = N.n1; g.n2 = N.n2;
+  g.L0 = L.n0; g.L1 = L.n1; g.L2 = L.n2;
+  g.max_pos = max_pos;
+  g.n_pad = snorm_pad(n_rot);
+  TTM_TRY(hipMemcpyAsync(w.quats, quats_host, sizeof(float) * 4 * (size_t)n_rot, hipMemcpyHostToDevice, stream));
+  TTM_TRY(hipMemcpyAsync(w.weights, weights_host, sizeof(double) * (size_t)n_rot, hipMemcpyHostToDevice, stream));
+  TTM_PROF(PC_SNORM, launch_snorm(g, image, tmpl, mask, w.quats, w.weights, n_rot, order_n, pos, count, lambda, w,
+                                  out_rho, out_D, out_flags, stream));
   return TTM_OK;
 }
 

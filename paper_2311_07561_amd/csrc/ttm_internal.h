@@ -189,6 +189,34 @@ hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int 
                              double* out_C, const PoseScratch& ps, hipStream_t s, bool reuse_tables = false,
                              int ncc_groups = 3);
 
+// the mask voxels with m != 0 (packed u0 | u1 << 10 | u2 << 20), their
+// values and their count; one block
+hipError_t launch_mask_list(const float* mask, int L0, int L1, int L2, unsigned* list, float* mval, int* count,
+                            hipStream_t s);
+
+// --- S'-consistent normalisation (ttm_snorm.hip) ------------------------------
+constexpr double kSnormFlatRel = 1e-6;
+struct SnormGeo {
+  int n0, n1, n2;      // image
+  int L0, L1, L2;      // template box
+  int max_pos;         // windows 0..max_pos-1 are image boxes, max_pos the template
+  int n_pad;           // rotations padded to a multiple of 8
+};
+struct SnormWs {
+  float* quats; double* weights;   // n_rot: the caller's quadrature
+  float* rtab; double* kap;        // n_pad: rotation table, omega_j a_j^n
+  unsigned* mlist; float* mval; int* mcount;
+  float* slabs;                    // (max_pos + 1) L0 L1 L2: h~ per window
+  double* stat;                    // (max_pos + 1) x 4
+  double* partial;                 // (max_pos + 1) x chunks
+};
+int snorm_pad(int n_rot);
+int snorm_chunks(int n_win, int n_pad);
+hipError_t launch_snorm(const SnormGeo& g, const float* image, const float* tmpl, const float* mask,
+                        const float* quats, const double* weights, int n_rot, int order_n, const int* pos,
+                        const int* count_dev, const double* lambda, const SnormWs& w, float* out_rho, double* out_D,
+                        int* out_flags, hipStream_t s);
+
 // --- isotropic low-pass filter (ttm_filter.hip) -----------------------------
 constexpr int kMaxFilterRadius = 32;
 struct FilterTaps {

@@ -709,6 +709,12 @@ __global__ void __launch_bounds__(1024) k_mask_list(const float* __restrict__ ma
   if (tid == 0) count[0] = base;
 }
 
+hipError_t launch_mask_list(const float* mask, int L0, int L1, int L2, unsigned* list, float* mval, int* count,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_list, dim3(1), dim3(1024), 0, s, mask, L0, L1, L2, list, mval, count);
+  return hipGetLastError();
+}
+
 // c(y, R(q_y)) = w(y) <tau_y f, s_R> for the rotation q_y found at voxel y
 // (Section 2, the normalised correlation of Algorithm 1, with s_R the raw
 // template rotated by R and normalised under the mask):
@@ -793,55 +799,6 @@ __global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __rest
 // than only j2 and the parity of j1); with the 4x4x4 brick order of the mask
 // voxels this cuts the distinct addresses per bank of a wave's gather about
 // fourfold.  The layout must fit kNccLdsCap floats.
-constexpr int kNccLdsCap = 36864;
-__host__ __device__ constexpr long ncc_lds_floats(int L0, int L1, int L2) {
-  return (long)L0 * ((long)L1 * (L2 + 3) + 5);
-}
-__device__ __forceinline__ float sample_rotated_lds(const float* t, int L0, int L1, int L2, int P2, int P01,
-                                                    const Rot& R, int u0, int u1, int u2) {
-  const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;
-  const float v0 = (float)(u0 - c0), v1 = (float)(u1 - c1), v2 = (float)(u2 - c2);
-  const float p0 = c0 + R.r[0] * v0 + R.r[3] * v1 + R.r[6] * v2;
-  const float p1 = c1 + R.r[1] * v0 + R.r[4] * v1 + R.r[7] * v2;
-  const float p2 = c2 + R.r[2] * v0 + R.r[5] * v1 + R.r[8] * v2;
-  const float f0 = floorf(p0), f1 = floorf(p1), f2 = floorf(p2);
-  const int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
-  const float w0 = p0 - f0, w1 = p1 - f1, w2 = p2 - f2;
-  if ((unsigned)i0 < (unsigned)(L0 - 1) && (unsigned)i1 < (unsigned)(L1 - 1) && (unsigned)i2 < (unsigned)(L2 - 1)) {
-    // all eight corners inside the box (the common case)
-    const float* q = t + i0 * P01 + i1 * P2 + i2;
-    const float c00 = q[0] + w2 * (q[1] - q[0]);
-    const float c01 = q[P2] + w2 * (q[P2 + 1] - q[P2]);
-    const float c10 = q[P01] + w2 * (q[P01 + 1] - q[P01]);
-    const float c11 = q[P01 + P2] + w2 * (q[P01 + P2 + 1] - q[P01 + P2]);
-    const float c0 = c00 + w1 * (c01 - c00), c1 = c10 + w1 * (c11 - c10);
-    return c0 + w0 * (c1 - c0);
-  }
-  float a[2], b[2], c[2];
-  int j0[2], j1[2], j2[2];
-#pragma unroll
-  for (int d = 0; d < 2; ++d) {
-    const bool ok0 = (unsigned)(i0 + d) < (unsigned)L0, ok1 = (unsigned)(i1 + d) < (unsigned)L1,
-               ok2 = (unsigned)(i2 + d) < (unsigned)L2;
-    a[d] = ok0 ? (d ? w0 : 1.0f - w0) : 0.0f;
-    b[d] = ok1 ? (d ? w1 : 1.0f - w1) : 0.0f;
-    c[d] = ok2 ? (d ? w2 : 1.0f - w2) : 0.0f;
-    j0[d] = ok0 ? (i0 + d) * P01 : 0;
-    j1[d] = ok1 ? (i1 + d) * P2 : 0;
-    j2[d] = ok2 ? i2 + d : 0;
-  }
-  float acc = 0.0f;
-#pragma unroll
-  for (int d0 = 0; d0 < 2; ++d0)
-#pragma unroll
-    for (int d1 = 0; d1 < 2; ++d1) {
-      const float ab = a[d0] * b[d1];
-      const int r = j0[d0] + j1[d1];
-      acc += ab * (c[0] * t[r + j2[0]] + c[1] * t[r + j2[1]]);
-    }
-  return acc;
-}
-
 __global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, int ngroups, const float* __restrict__ image,
                                                        const float* __restrict__ tmpl,
                                                        const unsigned* __restrict__ mlist,
@@ -1127,8 +1084,7 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
   }
   if (refine == 2) {
     if (!reuse_tables)
-      hipLaunchKernelGGL(k_mask_list, dim3(1), dim3(1024), 0, s, mask, g.L0, g.L1, g.L2, ps.mlist, ps.mval,
-                         ps.mcount);
+      (void)launch_mask_list(mask, g.L0, g.L1, g.L2, ps.mlist, ps.mval, ps.mcount, s);
     if (ncc_lds_floats(g.L0, g.L1, g.L2) <= kNccLdsCap) {
       // one block per CU (the template fills most of the LDS); each block
       // loads the template once for 27 / ngroups neighbours of a candidate

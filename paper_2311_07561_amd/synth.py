@@ -251,6 +251,44 @@ def workload_tomogram(seed: int = 2000) -> Workload:
                          n_blobs=6, snr=0.1)
 
 
+def add_smooth_decoys(wl: Workload, seed: int, count: int, sigma: float = 5.0,
+                      amplitude: float = 3.0) -> tuple:
+    """The workload's image with ``count`` smooth radial decoys added:
+    Gaussian bumps of width ``sigma`` voxels and peak height ``amplitude``
+    times the noise standard deviation, centred in the region where a whole
+    template box fits, at least one template extent from every copy and from
+    each other.  Such windows are smooth where the copies are noisy: the
+    situation in which an S-normalised tensor score can rank a non-match above
+    a match.  Returns (Workload with the new image and name, decoy centres)."""
+    L = wl.template.shape[0]
+    rng = np.random.default_rng(seed)
+    c = L // 2
+    shape = wl.image.shape
+    lo = np.array([c, c, c])
+    hi = np.array(shape) - (L - c)
+    taken = [np.asarray(p) for p in wl.positions]
+    pts = []
+    tries = 0
+    while len(pts) < count:
+        tries += 1
+        if tries > 200000:
+            raise RuntimeError("could not place the requested number of decoys")
+        p = np.array([rng.integers(lo[i], hi[i] + 1) for i in range(3)])
+        if all(np.linalg.norm(p - q) >= L for q in taken + pts):
+            pts.append(p)
+    img = wl.image.astype(np.float64)
+    amp = amplitude * (wl.noise_sigma if wl.noise_sigma > 0 else 1.0)
+    ext = int(math.ceil(4.0 * sigma))
+    for x in pts:
+        a = [max(int(x[i]) - ext, 0) for i in range(3)]
+        b = [min(int(x[i]) + ext + 1, shape[i]) for i in range(3)]
+        ax = [np.arange(a[i], b[i], dtype=np.float64) - x[i] for i in range(3)]
+        r2 = ax[0][:, None, None] ** 2 + ax[1][None, :, None] ** 2 + ax[2][None, None, :] ** 2
+        img[a[0]:b[0], a[1]:b[1], a[2]:b[2]] += amp * np.exp(-r2 / (2.0 * sigma * sigma))
+    out = dataclasses.replace(wl, name=wl.name + f"-decoys{count}", image=img.astype(np.float32))
+    return out, np.array(pts, dtype=np.int64)
+
+
 def workload_precision(seed: int = 3000) -> Workload:
     """512x512x256 tomogram, 40^3 template, tensor order 6, SNR 0.1."""
     return make_workload("ttm-512x512x256-L40-n6", (512, 512, 256), 40, 6, 40,

@@ -93,6 +93,8 @@ _SIGS = {
     "ttm_rotation_map_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32, _I32]),
     "ttm_rotation_map": (_I32, [_P, _DIMS, _P, _DIMS, _I32, _P, _OPTP, _P, _I32, _P, _P, _P, _P, _P, _P, _SZ,
                                 _P]),
+    "ttm_snorm_workspace_bytes": (_SZ, [_DIMS, _I32, _I32]),
+    "ttm_snorm": (_I32, [_P, _DIMS, _P, _P, _DIMS, _I32, _P, _P, _I32, _P, _P, _P, _I32, _P, _P, _P, _P, _SZ, _P]),
     "ttm_tile_count": (_I32, [_DIMS, _DIMS, _I32]),
     "ttm_choose_tile": (_I32, [_DIMS, _DIMS, _P, _P, _I32]),
     "ttm_correlate_tiled_workspace_bytes": (_SZ, [_DIMS, _I32, _I32]),
@@ -111,7 +113,7 @@ _SIGS = {
     "ttm_profile_class_name": (ctypes.c_char_p, [_I32]),
 }
 
-PROFILE_CLASSES = 12
+PROFILE_CLASSES = 13
 
 
 def profile_enable(on: bool = True):
@@ -418,6 +420,48 @@ def match(image: torch.Tensor, bank: torch.Tensor, mask: torch.Tensor, order: in
                          bufs.flags.data_ptr(), bufs.C.data_ptr(), bufs.count.data_ptr(), bufs.ws.data_ptr(),
                          bufs.ws.numel(), _stream(dev))
     _check(st, "ttm_match")
+
+
+SNORM_FLAT, SNORM_NONPOS, SNORM_OUTSIDE, SNORM_TEMPLATE = 1, 2, 4, 8
+
+
+def snorm(image: torch.Tensor, tmpl: torch.Tensor, mask: torch.Tensor, order: int, quats, weights,
+          pos: torch.Tensor, lam: torch.Tensor, count: torch.Tensor | None = None,
+          workspace: torch.Tensor | None = None):
+    """S'-consistent normalisation (ttm_snorm): ``rho' = lambda / sqrt(D(window)
+    D(template))`` at the positions ``pos`` (P, 3) int32 with their
+    eigenvalues ``lam`` (P,) float64, using the tensor template's quadrature
+    ``(quats, weights)``.  ``count`` (device int32, one element) limits the
+    positions used.  Returns (rho (P,) float32, D (P + 1,) float64 with the
+    template's last, flags (P,) int32); entries past ``count`` are zero."""
+    dev = image.device
+    N = _dims(image.shape)
+    L = _dims(tmpl.shape)
+    q = torch.as_tensor(quats, dtype=torch.float32).contiguous().cpu()
+    w = torch.as_tensor(weights, dtype=torch.float64).contiguous().cpu()
+    nrot = q.shape[0]
+    if q.shape != (nrot, 4) or w.shape != (nrot,):
+        raise ValueError("quats must be (J, 4) and weights (J,)")
+    P = int(pos.shape[0])
+    if tuple(pos.shape) != (P, 3) or tuple(lam.shape) != (P,):
+        raise ValueError("pos must be (P, 3) and lam (P,)")
+    _i32_dev(pos, "pos")
+    _i32_dev(count, "count")
+    if not lam.is_cuda or lam.dtype != torch.float64 or not lam.is_contiguous():
+        raise ValueError("lam must be a contiguous float64 CUDA (HIP) tensor")
+    rho = torch.zeros(P, dtype=torch.float32, device=dev)
+    D = torch.zeros(P + 1, dtype=torch.float64, device=dev)
+    flags = torch.zeros(P, dtype=torch.int32, device=dev)
+    nws = lib().ttm_snorm_workspace_bytes(L, nrot, P)
+    if nws == 0:
+        raise TTMError(-2, "ttm_snorm_workspace_bytes")
+    ws = workspace if workspace is not None and workspace.numel() >= nws else _workspace(nws, dev)
+    st = lib().ttm_snorm(_dev(image, "image"), N, _dev(tmpl, "tmpl"), _dev(mask, "mask"), L, order,
+                         q.data_ptr(), w.data_ptr(), nrot, pos.data_ptr(), lam.data_ptr(),
+                         count.data_ptr() if count is not None else None, P, rho.data_ptr(), D.data_ptr(),
+                         flags.data_ptr(), ws.data_ptr(), nws, _stream(dev))
+    _check(st, "ttm_snorm")
+    return rho, D, flags
 
 
 def rotation_map_workspace(image_shape, L, order, n_seeds, device) -> torch.Tensor:

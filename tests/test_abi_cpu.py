@@ -4,6 +4,8 @@ reaches the GPU: invalid arguments return before anything is enqueued)."""
 import ctypes
 import os
 
+import numpy as np
+
 import pytest
 
 from paper_2311_07561_amd import ttm
@@ -251,3 +253,39 @@ def test_batch_and_tiled_validation_without_gpu():
     assert ctypes.sizeof(ttm.BatchJob) == 144
     assert (ttm.BatchJob.N.offset, ttm.BatchJob.tile.offset, ttm.BatchJob.L.offset,
             ttm.BatchJob.out_count.offset) == (8, 32, 64, 136)
+
+
+def test_snorm_validation_without_gpu():
+    """ttm_snorm rejects bad arguments before any device work; the workspace
+    holds at least the per-window slabs of h~ (one L-box per position plus the
+    template) and the rotation table."""
+    L = ttm.lib()
+    N, T = ttm.Dims(64, 64, 64), ttm.Dims(16, 16, 16)
+    fake = ctypes.c_void_p(256)
+    big = 1 << 40
+    q = np.array([[1.0, 0.0, 0.0, 0.0], [0.0, 1.0, 0.0, 0.0]], dtype=np.float32)
+    w = np.array([0.5, 0.5])
+    qp, wp = q.ctypes.data, w.ctypes.data
+
+    def call(order=4, n_rot=2, max_pos=8, ws=big, dims=N, box=T, wts=wp, pos=fake, quats=qp):
+        return L.ttm_snorm(fake, dims, fake, fake, box, order, quats, wts, n_rot, pos, fake, None, max_pos,
+                           fake, fake, fake, fake, ws, None)
+
+    assert call(order=3) == -1
+    assert call(order=0) == -1
+    assert call(n_rot=0) == -1
+    assert call(max_pos=0) == -1
+    assert call(max_pos=(1 << 16) + 1) == -1
+    assert call(pos=None) == -1
+    assert call(quats=None) == -1
+    bad_w = np.array([0.5, 0.4])
+    assert call(wts=bad_w.ctypes.data) == -1          # weights must sum to 1
+    zero_q = np.zeros((2, 4), dtype=np.float32)
+    assert call(quats=zero_q.ctypes.data) == -1
+    assert call(box=ttm.Dims(1024, 4, 4)) == -2
+    assert call(dims=ttm.Dims(9000, 4, 4)) == -2
+    assert call(ws=1024) == -3
+    assert L.ttm_snorm_workspace_bytes(T, 0, 8) == 0
+    assert L.ttm_snorm_workspace_bytes(T, 2, 0) == 0
+    need = L.ttm_snorm_workspace_bytes(T, 10000, 64)
+    assert need >= 65 * 16 ** 3 * 4 + 10000 * (12 * 4 + 8)
