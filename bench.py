@@ -201,10 +201,12 @@ def run_snorm(wl, img, tmpl, mask, order, qb, wb, bank, bufs, opt, args, ttm, sy
     near = lambda pts: np.array([np.min(np.linalg.norm(pts - x[None], axis=1)) <= 2.0 for x in pos])
     on_copy, on_decoy = near(wl.positions), near(decoys)
     keys = {"F": dbufs.peak_score[:n].cpu().numpy(), "lambda": dbufs.lam[:n].cpu().numpy(),
-            "rho": rho[:n].cpu().numpy()}
+            "rho": rho[:n].cpu().numpy(), "D": D[:n].cpu().numpy()}
     k = len(wl.positions)
     ranks = {}
     for name, v in keys.items():
+        if name == "D":
+            continue
         top = np.argsort(-v, kind="stable")[:k]
         ranks[name] = {"copies": int(on_copy[top].sum()), "decoys": int(on_decoy[top].sum())}
 
