@@ -919,3 +919,219 @@ def s_prime_score(lam, Dx, Dt):
     ok = (Dx > 0) & (Dt > 0)
     with np.errstate(invalid="ignore", divide="ignore"):
         return np.where(ok, lam / np.sqrt(np.where(ok, Dx * Dt, 1.0)), 0.0)
+
+
+# ----------------------------------------------------------------------------
+# two-dimensional TTM (Sections 2 and 3 with d = 2)
+# ----------------------------------------------------------------------------
+#
+# Readings for d = 2 (Theorem "main" is stated for R^3 only):
+# * a rotation R(z) of the plane is described by a unit complex number
+#   z = (a, b) = e^{i theta / 2}, the half angle (the planar analogue of the
+#   unit quaternion: z and -z give the same rotation, and an even order n makes
+#   them equivalent); R(z) = [[a^2 - b^2, -2ab], [2ab, a^2 - b^2]] is the
+#   rotation by theta = 2 atan2(b, a).  With the full angle (cos theta,
+#   sin theta) instead, an even power of z . z' could not tell theta from
+#   theta + pi;
+# * C_n(x) in S^n(R^2), stored as its n + 1 entries C_k with multi-index
+#   (n - k, k), multiplicity mu_k = C(n, k);
+# * the image is C-order [n1][n2], the template box [L1][L2] with centre
+#   c = L // 2 per axis, the SO(2) integral a quadrature {(z_j, omega_j)}.
+
+
+def rot2_matrix(z) -> np.ndarray:
+    """Rotation of the plane described by the unit complex number ``z``."""
+    a, b = np.asarray(z, dtype=np.float64) / np.linalg.norm(z)
+    return np.array([[a * a - b * b, -2 * a * b], [2 * a * b, a * a - b * b]])
+
+
+def rotate_bilinear(t: np.ndarray, z) -> np.ndarray:
+    """``t_R(u) = t(c + R^-1 (u - c))`` sampled bilinearly, zero outside the
+    box (Section 2, ``t_R = O_{R^-1}(t)``, in the plane)."""
+    t = np.asarray(t, dtype=np.float64)
+    L = np.array(t.shape)
+    c = np.array([int(l) // 2 for l in L], dtype=np.float64)
+    r_inv = rot2_matrix(z).T
+    g = np.meshgrid(*[np.arange(l, dtype=np.float64) for l in L], indexing="ij")
+    u = np.stack(g, axis=-1) - c
+    p = u @ r_inv.T + c
+    p0 = np.floor(p)
+    fr = p - p0
+    p0 = p0.astype(np.int64)
+    out = np.zeros(t.shape)
+    for dy in (0, 1):
+        for dx in (0, 1):
+            idx = p0 + np.array([dy, dx])
+            wgt = (fr[..., 0] if dy else 1 - fr[..., 0]) * (fr[..., 1] if dx else 1 - fr[..., 1])
+            inside = np.all((idx >= 0) & (idx < L), axis=-1)
+            vals = np.zeros(t.shape)
+            ii = idx[inside]
+            vals[inside] = t[ii[:, 0], ii[:, 1]]
+            out += wgt * vals
+    return out
+
+
+def planar_multiplicities(n: int) -> np.ndarray:
+    return np.array([math.comb(n, k) for k in range(n + 1)], dtype=np.float64)
+
+
+def planar_monomials(zs: np.ndarray, n: int) -> np.ndarray:
+    """``a^(n-k) b^k`` for k = 0..n per unit complex number: (J, n + 1)."""
+    zs = np.asarray(zs, dtype=np.float64).reshape(-1, 2)
+    zs = zs / np.linalg.norm(zs, axis=1, keepdims=True)
+    k = np.arange(n + 1)
+    return zs[:, :1] ** (n - k)[None] * zs[:, 1:] ** k[None]
+
+
+def tensor_template_2d(t, m, n: int, zs, weights) -> np.ndarray:
+    """``T_k(u) = sum_j omega_j a_j^(n-k) b_j^k s_{R_j}(u)``, k = 0..n, with
+    ``s_R`` the raw template rotated by ``R(z_j)`` and normalised under ``m``
+    (Section 3.2 with d = 2)."""
+    if n < 2 or n % 2:
+        raise ValueError("tensor order must be even and >= 2")
+    mono = planar_monomials(zs, n)
+    T = np.zeros((n + 1,) + tuple(np.shape(t)))
+    for j, z in enumerate(np.asarray(zs, dtype=np.float64).reshape(-1, 2)):
+        s = masked_normalize(rotate_bilinear(t, z), m)
+        T += (weights[j] * mono[j])[:, None, None] * s[None]
+    return T
+
+
+def windows_2d(f: np.ndarray, xs: np.ndarray, L) -> np.ndarray:
+    """``W[p, u] = f((x_p + u - c) mod N)`` in the plane: (P, L1, L2)."""
+    f = np.asarray(f, dtype=np.float64)
+    N = np.array(f.shape)
+    c = [int(l) // 2 for l in L]
+    xs = np.asarray(xs, dtype=np.int64).reshape(-1, 2)
+    i0 = (xs[:, 0, None] + np.arange(L[0]) - c[0]) % N[0]
+    i1 = (xs[:, 1, None] + np.arange(L[1]) - c[1]) % N[1]
+    return f[i0[:, :, None], i1[:, None, :]]
+
+
+def local_norm_at_2d(f, m, xs, eps_v: float = EPS_V_DEFAULT) -> np.ndarray:
+    """``w(x) = 1 / ||P_S tau_x f||_S`` by the two-pass definition, with the
+    floor of the 3-D case (``w = 0`` where ``v <= eps_v m_sum var(f)``)."""
+    f = np.asarray(f, dtype=np.float64)
+    m = np.asarray(m, dtype=np.float64)
+    msum = m.sum()
+    floor = eps_v * msum * float(f.var())
+    W = windows_2d(f, xs, m.shape).reshape(len(np.reshape(xs, (-1, 2))), -1)
+    mv = m.reshape(-1)
+    mu = (W @ mv) / msum
+    v = ((W - mu[:, None]) ** 2) @ mv
+    return np.where(v > floor, 1.0 / np.sqrt(np.maximum(v, 1e-300)), 0.0)
+
+
+def tensor_field_at_2d(f, T, m, xs, eps_v: float = EPS_V_DEFAULT) -> np.ndarray:
+    """``C_k(x) = w(x) <tau_x f, T_k>``: (P, n + 1)."""
+    T = np.asarray(T, dtype=np.float64)
+    W = windows_2d(f, xs, T.shape[1:]).reshape(-1, T[0].size)
+    return (W @ T.reshape(len(T), -1).T) * local_norm_at_2d(f, m, xs, eps_v)[:, None]
+
+
+def score_from_field_2d(C: np.ndarray, n: int) -> np.ndarray:
+    """Frobenius norm over all 2^n entries: ``sqrt(sum_k C(n,k) C_k^2)``."""
+    C = np.asarray(C, dtype=np.float64)
+    return np.sqrt((C * C) @ planar_multiplicities(n))
+
+
+def tensor_apply_2d(C: np.ndarray, n: int, z) -> float:
+    """``C z^n = sum_k C(n,k) C_k a^(n-k) b^k``."""
+    return float(planar_monomials(np.asarray(z)[None], n)[0] @ (planar_multiplicities(n) * C))
+
+
+def score_map_2d(f, T, m, n: int, eps_v: float = EPS_V_DEFAULT) -> np.ndarray:
+    """``F(x)`` over the image's valid region (zero elsewhere)."""
+    N = np.shape(f)
+    L = np.shape(T)[1:]
+    c = [l // 2 for l in L]
+    out = np.zeros(N)
+    g = np.meshgrid(np.arange(c[0], N[0] - L[0] + c[0] + 1), np.arange(c[1], N[1] - L[1] + c[1] + 1),
+                    indexing="ij")
+    xs = np.stack([g[0].reshape(-1), g[1].reshape(-1)], axis=1)
+    out[xs[:, 0], xs[:, 1]] = score_from_field_2d(tensor_field_at_2d(f, T, m, xs, eps_v), n)
+    return out
+
+
+def classical_ncc_at_2d(f, t, m, zs, xs, eps_v: float = EPS_V_DEFAULT) -> np.ndarray:
+    """``c(x, R_j) = w(x) <tau_x f, s_{R_j}>`` in the plane: (P, J)."""
+    s = np.stack([masked_normalize(rotate_bilinear(t, z), m) for z in np.asarray(zs).reshape(-1, 2)])
+    W = windows_2d(f, xs, np.shape(t)).reshape(-1, s[0].size)
+    return (W @ s.reshape(len(s), -1).T) * local_norm_at_2d(f, m, xs, eps_v)[:, None]
+
+
+def dominant_eigen_2d(C: np.ndarray, n: int, n_brute: int = 20000):
+    """Global maximiser of ``phi(z) = C z^n`` on the unit circle: a brute-force
+    scan of z = (cos psi, sin psi), psi in [0, pi) (z and -z are equivalent),
+    then golden-section refinement around the best point.  Returns
+    (z with a > 0 (or a = 0, b > 0), lambda, the best value at least 5 degrees
+    of rotation away)."""
+    mu = planar_multiplicities(n) * np.asarray(C, dtype=np.float64)
+    k = np.arange(n + 1)
+
+    def phi(psi):
+        psi = np.asarray(psi, dtype=np.float64)
+        return (np.cos(psi)[..., None] ** (n - k) * np.sin(psi)[..., None] ** k) @ mu
+
+    grid = (np.arange(n_brute) + 0.5) * (math.pi / n_brute)
+    vals = phi(grid)
+    i = int(np.argmax(vals))
+    h = math.pi / n_brute
+    lo, hi = grid[i] - h, grid[i] + h
+    g = (math.sqrt(5.0) - 1.0) / 2.0
+    for _ in range(80):
+        a1, a2 = hi - g * (hi - lo), lo + g * (hi - lo)
+        if phi(a1) >= phi(a2):
+            hi = a2
+        else:
+            lo = a1
+    psi = 0.5 * (lo + hi)
+    lam = float(phi(psi))
+    z = np.array([math.cos(psi), math.sin(psi)])
+    if z[0] < 0 or (z[0] == 0 and z[1] < 0):
+        z = -z
+    # rotation angle between psi and grid points: 2 |delta psi| (mod pi)
+    d = np.abs(((grid - psi) + math.pi / 2) % math.pi - math.pi / 2) * 2.0
+    far = d > math.radians(5.0)
+    second = float(vals[far].max()) if np.any(far) else -np.inf
+    return z, lam, second
+
+
+def rotation_angle_2d_deg(z1, z2) -> float:
+    """Angle of the plane rotation taking ``R(z1)`` to ``R(z2)``, in [0, 180]."""
+    t1 = 2.0 * math.atan2(z1[1], z1[0])
+    t2 = 2.0 * math.atan2(z2[1], z2[0])
+    d = (t2 - t1 + math.pi) % (2.0 * math.pi) - math.pi
+    return abs(math.degrees(d))
+
+
+def find_peaks_2d(F: np.ndarray, L, threshold: float, min_dist: float, max_peaks: int) -> np.ndarray:
+    """The candidate rule of the 3-D case in the plane: strict maxima over the
+    8 neighbours inside the valid region, above ``threshold``, sorted by score
+    (ties by lower linear index), greedy suppression within ``min_dist``, at
+    most ``max_peaks``: (P, 2)."""
+    F3 = np.asarray(F)[None]
+    return find_peaks_fast(F3, (1,) + tuple(L), threshold, min_dist, max_peaks)[:, 1:]
+
+
+def refine_by_ncc_2d(f, t, m, T, n: int, x, eps_v: float = EPS_V_DEFAULT):
+    """The NCC refinement in the plane: each pixel y of the 3x3 neighbourhood
+    (inside the valid region) gets its own rotation, the dominant eigenvector
+    of C_n(y); the candidate moves to the pixel with the largest NCC at that
+    rotation (the centre first on ties, then the lower index 3 (d1+1) +
+    (d2+1)).  Returns (position, z, lambda, ncc)."""
+    N = np.shape(f)
+    L = np.shape(t)
+    c = [l // 2 for l in L]
+    offs = [(d1, d2) for d1 in (-1, 0, 1) for d2 in (-1, 0, 1)]
+    best, res = None, None
+    for k in [4] + [i for i in range(9) if i != 4]:
+        y = np.asarray(x) + np.array(offs[k])
+        if not all(c[i] <= y[i] <= N[i] - L[i] + c[i] for i in range(2)):
+            continue
+        C = tensor_field_at_2d(f, T, m, y[None], eps_v)[0]
+        z, lam, _ = dominant_eigen_2d(C, n)
+        ncc = float(classical_ncc_at_2d(f, t, m, z[None], y[None], eps_v)[0, 0])
+        if best is None or ncc > best or (ncc == best and k < res[4] and res[4] != 4):
+            best, res = ncc, (y, z, lam, ncc, k)
+    return res[0], res[1], res[2], res[3]

@@ -388,3 +388,100 @@ def workload_batch(seed: int = 4000, count: int = 64, edges=(96, 320), template_
     return BatchWorkload(f"ttm-batch{count}-e{edges[0]}-{edges[1]}-L{'-'.join(map(str, template_sizes))}-n{order}",
                          [g.astype(np.float32) for g in grids], [m.astype(np.float32) for m in masks],
                          [r[0] for r in res], [r[1] for r in res], [r[2] for r in res], sigma, order)
+
+
+# --- two-dimensional workloads ------------------------------------------------
+
+def make_blob_template_2d(rng: np.random.Generator, L: int, n_blobs: int, radius: float) -> BlobTemplate:
+    """Planar blob template: as :func:`make_blob_template` in two dimensions
+    (covariance ``U diag(sigma^2) U^T`` with a random plane rotation ``U``,
+    ``sigma_i ~ U[L/16, L/8]``, centres in the disc of radius ``0.55 radius``)."""
+    sig_lo, sig_hi = L / 16.0, L / 8.0
+    centres, precs, amps = [], [], []
+    for _ in range(n_blobs):
+        sig = rng.uniform(sig_lo, sig_hi, size=2)
+        a = rng.uniform(0.0, 2.0 * math.pi)
+        u = np.array([[math.cos(a), -math.sin(a)], [math.sin(a), math.cos(a)]])
+        cov = u @ np.diag(sig ** 2) @ u.T
+        rmax = 0.55 * radius
+        while True:
+            p = rng.uniform(-rmax, rmax, size=2)
+            if np.linalg.norm(p) <= rmax:
+                break
+        centres.append(p)
+        precs.append(np.linalg.inv(cov))
+        amps.append(rng.uniform(0.5, 1.5))
+    return BlobTemplate(L, np.array(centres), np.array(precs), np.array(amps))
+
+
+def disc_mask(L: int, radius: float) -> np.ndarray:
+    """Binary disc on the L^2 grid: 1 where the distance to ``L // 2`` is
+    strictly below ``radius``."""
+    c = L // 2
+    ax = np.arange(L, dtype=np.float64) - c
+    v = np.stack(np.meshgrid(ax, ax, indexing="ij"), axis=-1)
+    return (np.linalg.norm(v, axis=-1) < radius).astype(np.float64)
+
+
+def circle_quadrature(n: int) -> np.ndarray:
+    """``n`` unit complex numbers z = (cos psi, sin psi) with psi equispaced in
+    [0, pi): plane rotations by theta = 2 psi, equispaced over the full turn."""
+    psi = (np.arange(n, dtype=np.float64) + 0.5) * (math.pi / n)
+    return np.stack([np.cos(psi), np.sin(psi)], axis=1)
+
+
+@dataclasses.dataclass
+class Workload2D:
+    """A stack of seeded planar template-matching problems sharing one template."""
+    name: str
+    images: np.ndarray         # float32 (B, n1, n2)
+    template: np.ndarray       # float32 (L, L)
+    mask: np.ndarray           # float32 (L, L)
+    order: int
+    positions: list            # per image: (P, 2) int64 planted centres
+    angles: list               # per image: (P,) planted rotation angles (radians)
+    noise_sigma: float
+
+
+def workload_2d(seed: int = 7000, count: int = 16, size: int = 512, L: int = 32, order: int = 8,
+                plants: int = 12, snr: float = 0.5, n_blobs: int = 5) -> Workload2D:
+    """``count`` images of ``size``^2, each with ``plants`` copies of one planar
+    blob template (rendered analytically at ``R^-1 (y - x)``, uniform angles),
+    at least L apart, plus Gaussian noise of variance ``var_signal / snr``.
+    Sub-seeds: +0 template, then +1 + 3i, +2 + 3i, +3 + 3i for the positions,
+    angles and noise of image i."""
+    r = L / 2.0
+    tmpl = make_blob_template_2d(np.random.default_rng(seed), L, n_blobs, r)
+    c = L // 2
+    ax = np.arange(L, dtype=np.float64) - c
+    tgrid = tmpl.evaluate(np.stack(np.meshgrid(ax, ax, indexing="ij"), axis=-1))
+    mask = disc_mask(L, r)
+    sigma = math.sqrt(float(tgrid[mask > 0].var()) / snr)
+    images, positions, angles = [], [], []
+    for i in range(count):
+        rng_p = np.random.default_rng(seed + 1 + 3 * i)
+        pts = []
+        tries = 0
+        while len(pts) < plants:
+            tries += 1
+            if tries > 200000:
+                raise RuntimeError("could not place the requested number of copies")
+            p = np.array([rng_p.integers(c, size - (L - c) + 1) for _ in range(2)])
+            if all(np.linalg.norm(p - q) >= L for q in pts):
+                pts.append(p)
+        ang = np.random.default_rng(seed + 2 + 3 * i).uniform(0.0, 2.0 * math.pi, plants)
+        img = np.zeros((size, size))
+        for x, a in zip(pts, ang):
+            rm = np.array([[math.cos(a), -math.sin(a)], [math.sin(a), math.cos(a)]])
+            lo = [max(int(x[k]) - L, 0) for k in range(2)]
+            hi = [min(int(x[k]) + L + 1, size) for k in range(2)]
+            g = np.stack(np.meshgrid(np.arange(lo[0], hi[0]) - x[0], np.arange(lo[1], hi[1]) - x[1],
+                                     indexing="ij"), axis=-1).astype(np.float64)
+            img[lo[0]:hi[0], lo[1]:hi[1]] += tmpl.evaluate(g @ rm)   # row-vector form of R^-1 y
+        img += sigma * np.random.default_rng(seed + 3 + 3 * i).standard_normal(img.shape)
+        images.append(img.astype(np.float32))
+        positions.append(np.array(pts, dtype=np.int64))
+        angles.append(ang)
+    name = f"ttm2d-{count}x{size}sq-L{L}-n{order}"
+    return Workload2D(name, np.stack(images), tgrid.astype(np.float32), mask.astype(np.float32), order,
+                      positions, angles, sigma)
