@@ -94,6 +94,8 @@ def parse():
     p.add_argument("--batch-replays", type=int, default=2)
     p.add_argument("--batch-streams", type=int, default=4, help="concurrent branches of the batch graph")
     p.add_argument("--batch-workers", type=int, default=16, help="processes generating the batch tomograms")
+    p.add_argument("--rotations-2d", type=int, default=720,
+                   help="rotations of the planar leg's tensor template and classical matching (0: skip the leg)")
     p.add_argument("--snorm-steps", type=int, default=3,
                    help="timed runs of the S'-normalisation of the peaks (0: skip)")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -158,6 +160,104 @@ def err_stats(errs):
         return {"n": 0, "median_deg": None, "p90_deg": None}
     return {"n": len(errs), "median_deg": round(float(np.median(errs)), 3),
             "p90_deg": round(float(np.percentile(errs, 90)), 3)}
+
+
+def angle_deg(q1, q2):
+    """Angle of the rotation taking R(q1) to R(q2): 2 acos |<q1, q2>| (unit
+    quaternions, either sign)."""
+    q1 = np.asarray(q1, dtype=np.float64)
+    q2 = np.asarray(q2, dtype=np.float64)
+    d = abs(float(q1 @ q2)) / (np.linalg.norm(q1) * np.linalg.norm(q2))
+    return float(np.degrees(2.0 * np.arccos(min(1.0, d))))
+
+
+def angle2d_deg(z1, z2):
+    """Angle between the plane rotations of the half-angle unit complex
+    numbers z1 and z2, in [0, 180]."""
+    t = 2.0 * (np.arctan2(z2[1], z2[0]) - np.arctan2(z1[1], z1[0]))
+    return float(abs(np.degrees((t + np.pi) % (2.0 * np.pi) - np.pi)))
+
+
+def run_2d(args, ttm, synth, torch, dev):
+    """Planar TTM on a stack of 16 images of 512^2 (32^2 template, order 8,
+    iterated refinement), against classical matching of the same stack with
+    the same rotations on the same GPU."""
+    wl = synth.workload_2d()
+    B, n1, n2 = wl.images.shape
+    L = wl.template.shape
+    n = wl.order
+    P = len(wl.positions[0])
+    J = args.rotations_2d
+    zs = synth.circle_quadrature(J).astype(np.float32)
+    w = np.full(J, 1.0 / J)
+    imgs = torch.as_tensor(wl.images, device=dev)
+    tm2 = torch.as_tensor(wl.template, device=dev)
+    mk2 = torch.as_tensor(wl.mask, device=dev)
+    torch.cuda.synchronize()
+    tb = time.time()
+    comps, bank = ttm.build_tensor_template_2d(tm2, mk2, n, zs, w, stack_shape=(B, n1, n2))
+    torch.cuda.synchronize()
+    build_ms = (time.time() - tb) * 1e3
+    opt = ttm.default_options(max_peaks=P, min_dist=float(L[0]) / 2, threshold=0.0, refine=args.refine)
+    bufs = ttm.Match2DBuffers((B, n1, n2), L, n, opt, dev)
+    ms, prof = time_steps(lambda: ttm.match_2d(imgs, bank, comps, mk2, n, opt, bufs, tmpl=tm2), args.steps,
+                          args.warmup, ttm, torch)
+    errs = []
+    for b in range(B):
+        res = bufs.result(b)
+        pos, z = res["pos"].cpu().numpy(), res["z"].cpu().numpy()
+        for x, a in zip(wl.positions[b], wl.angles[b]):
+            if len(pos) == 0:
+                break
+            d = np.linalg.norm(pos - x[None], axis=1)
+            i = int(np.argmin(d))
+            if d[i] <= 2.0:
+                errs.append(angle2d_deg(z[i], [np.cos(a / 2), np.sin(a / 2)]))
+    V = B * n1 * n2
+    out = {"workload": wl.name, "images": B, "size": [n1, n2], "template": list(L), "order": n,
+           "components": n + 1, "rotations": J, "build_ms": round(build_ms, 1), "ms": round(ms, 4),
+           "pixels_per_s": V / (ms / 1e3), "refine": args.refine,
+           "pose_detected": dict(err_stats(errs), recall=len(errs) / (B * P)),
+           "kernels_ms": {k: round(v[0] / args.steps, 4) for k, v in prof.items() if v[1]}}
+    log(f"2-D: {B} x {n1}x{n2}, template {L}, order {n}: {ms:.3f} ms per stack "
+        f"({V / (ms / 1e3):.3g} pixels/s), recall {len(errs) / (B * P):.2f}, {err_stats(errs)}")
+    if args.classical_rotations > 0:
+        q3 = np.stack([zs[:, 0], zs[:, 1], np.zeros(J), np.zeros(J)], axis=1).astype(np.float32)
+        tm3, mk3 = tm2[None].contiguous(), mk2[None].contiguous()
+        ttm.tm_classical(imgs, tm3, mk3, q3[:64])
+        torch.cuda.synchronize()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record()
+        best, idx = ttm.tm_classical(imgs, tm3, mk3, q3)
+        c1.record()
+        torch.cuda.synchronize()
+        cms = c0.elapsed_time(c1)
+        idx_np = idx.cpu().numpy()
+        at = [angle2d_deg(zs[idx_np[b, x[0], x[1]]], [np.cos(a / 2), np.sin(a / 2)])
+              for b in range(B) for x, a in zip(wl.positions[b], wl.angles[b])]
+        # classical peaks: the same picker, plane by plane, on the best-NCC map
+        comps3, _ = ttm.build_tensor_template(tm3, mk3, n, q3, w)
+        opt0 = ttm.default_options(max_peaks=P, min_dist=float(L[0]) / 2, threshold=0.0)
+        cerr = []
+        for b in range(B):
+            rc = ttm.recover_pose(best[b:b + 1], imgs[b:b + 1], comps3, mk3, n, opt0, want_C=False)
+            cpos = rc["pos"].cpu().numpy()[:, 1:]
+            for x, a in zip(wl.positions[b], wl.angles[b]):
+                if len(cpos) == 0:
+                    break
+                d = np.linalg.norm(cpos - x[None], axis=1)
+                i = int(np.argmin(d))
+                if d[i] <= 2.0:
+                    cerr.append(angle2d_deg(zs[idx_np[b, cpos[i, 0], cpos[i, 1]]], [np.cos(a / 2), np.sin(a / 2)]))
+        out["classical"] = {"rotations": J, "ms": round(cms, 2), "pixels_per_s": V / (cms / 1e3),
+                            "speedup_ttm_vs_classical": round(cms / ms, 1),
+                            "pose_at_planted": err_stats(at),
+                            "pose_detected": dict(err_stats(cerr), recall=len(cerr) / (B * P))}
+        log(f"2-D classical, {J} rotations: {cms:.1f} ms ({cms / ms:.1f}x the TTM stack), detected {err_stats(cerr)}")
+        del best, idx
+    del bufs
+    return out
 
 
 def match_errors(pos, quats, planted, truth, angle, radius=2.0):
@@ -453,7 +553,7 @@ def main():
         print(json.dumps({"copy_bytes": n * 4}), flush=True)
         return
 
-    from oracle.ttm_oracle import rotation_angle_deg as angle   # reporting only: angle between quaternions
+    angle = angle_deg
     from paper_2311_07561_amd import synth, ttm
 
     dev = torch.device("cuda:0")
@@ -504,6 +604,8 @@ def main():
     rmap = None
     if args.rmap_seeds > 0:
         rmap = run_rotation_map(wl, img, mask, main_run["_bank"], K, args, ttm, synth, torch, dev, angle)
+
+    planar = run_2d(args, ttm, synth, torch, dev) if args.rotations_2d > 0 else None
 
     batch = run_batch(bwl, args, ttm, synth, torch, dev, angle) if bwl is not None else None
     del bwl
@@ -566,6 +668,7 @@ def main():
         "ttm_order6": order6,
         "rotation_map": rmap,
         "batch": batch,
+        "planar": planar,
         "classical": classical,
         "kernels": kernels,
     }

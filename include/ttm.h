@@ -292,6 +292,67 @@ ttm_status ttm_rotation_map(
     size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Two-dimensional TTM (Sections 2 and 3 with d = 2; Theorem 1 is stated for
+ * R^3 only, so the planar case has its own checks).
+ * A plane rotation is described by the unit complex number z = (a, b) of
+ * half its angle: R(z) = [[a^2 - b^2, -2ab], [2ab, a^2 - b^2]], the rotation
+ * by theta = 2 atan2(b, a) of the (axis 1, axis 2) plane; z and -z give the
+ * same rotation, and even orders make them equivalent (with the full angle an
+ * even order could not tell theta from theta + pi).  The planar tensor
+ * C_n(x) in S^n(R^2) has the n + 1 entries C_k of the multi-indices
+ * (n - k, k), multiplicity C(n, k); its Frobenius norm is the score and its
+ * dominant eigenvector on the unit circle the rotation.
+ *
+ * Images come as a stack of B planes [B][n1][n2] (B, n1, n2 supported
+ * lengths), the template and mask as [L1][L2] (L1 <= n1, L2 <= n2, L2 <= 512,
+ * L1 <= 1023); orders n = 2, 4, 6, 8.  The planes are correlated together and
+ * never mix; the mean shift and the variance floor of ttm_options.eps_v are
+ * those of the whole stack.
+ *
+ * ttm_build_tensor_template_2d: T_k(u) = sum_j omega_j a_j^(n-k) b_j^k s_j(u)
+ * (s_j the raw template rotated bilinearly by R(z_j) about (L1/2, L2/2), zero
+ * outside the box, then normalised under the mask), written to
+ * out_components [(n+1)][L1][L2]; with out_bank non-NULL also the correlation
+ * bank for stacks of shape (B, n1, n2) (ttm_bank_bytes_2d bytes).
+ *   z_host        n_rot x 2 float32 host array of unit complex numbers
+ *                 (normalised here); weights_host n_rot float64, sum 1
+ * ttm_match_2d: per plane b, the score and w maps (out_score, out_w
+ * [B][n1][n2]; out_w may be NULL), the candidates of the 3-D rule restricted
+ * to the plane (strict maxima over the 8 neighbours inside the valid region,
+ * sorted, suppression within opt->min_dist, at most opt->max_peaks), the
+ * tensor at each by direct float64 window sums and its dominant eigenpair,
+ * refined as opt->refine (0..3, the neighbourhood being the 3 x 3 pixels):
+ *   out_pos        [B][max_peaks][2] int32 (x1, x2)
+ *   out_z          [B][max_peaks][2] float32, unit, a > 0 (or a = 0, b > 0)
+ *   out_lambda     [B][max_peaks] float64
+ *   out_peak_score [B][max_peaks] float32, out_flags [B][max_peaks] int32
+ *   out_count      [B][2] int32: the count of each plane and TTM_PEAKS_* bits
+ * Entries past each plane's count are not written.  tmpl ([L1][L2]) is read
+ * when opt->refine >= 2.  Classical matching of a stack is tm_classical with
+ * L = (1, L1, L2) and the quaternions (a, b, 0, 0).
+ * Errors: TTM_E_ARG, TTM_E_SIZE, TTM_E_WORKSPACE, TTM_E_HIP.
+ * ------------------------------------------------------------------------- */
+size_t ttm_bank_bytes_2d(int32_t B, int32_t n1, int32_t n2, int32_t L1,
+                         int32_t L2, int32_t order_n);
+size_t ttm_build_workspace_bytes_2d(int32_t L1, int32_t L2, int32_t order_n,
+                                    int32_t n_rot);
+ttm_status ttm_build_tensor_template_2d(
+    const float* tmpl, const float* mask, int32_t L1, int32_t L2,
+    int32_t order_n, const float* z_host, const double* weights_host,
+    int32_t n_rot, float* out_components, int32_t B, int32_t n1, int32_t n2,
+    void* out_bank, void* ws, size_t ws_bytes, hipStream_t stream);
+size_t ttm_match_2d_workspace_bytes(int32_t B, int32_t n1, int32_t n2,
+                                    int32_t L1, int32_t L2, int32_t order_n,
+                                    const ttm_options* opt);
+ttm_status ttm_match_2d(
+    const float* images, int32_t B, int32_t n1, int32_t n2, const void* bank,
+    const float* components, const float* tmpl, const float* mask,
+    int32_t L1, int32_t L2, int32_t order_n, const ttm_options* opt,
+    float* out_score, float* out_w, int32_t* out_pos, float* out_z,
+    double* out_lambda, float* out_peak_score, int32_t* out_flags,
+    int32_t* out_count, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * S'-consistent normalisation of peak scores (Section 3.4, the discussion of
  * false positives; S_2 and S' = S_2 S from the proof of Theorem 1).
  * The tensor correlation lambda(x) = w(x) <tau_x f, t_Q>_{S'} is an inner

@@ -366,11 +366,16 @@ size_t ttm_correlate_workspace_bytes(ttm_dims N, ttm_dims L, int32_t K) {
 // out_C (optional): C_alpha over the valid box, [K][W0][W1][W2]; then only w
 // is written here (out_score is not touched).  stats_in (optional): image
 // statistics taken elsewhere (see image_forward).
+// planar: the K = n + 1 components of a planar tensor (multiplicities C(n, k))
 static ttm_status correlate_into(const Geo& g, int order_n, int K, const float* image, const float2* bk,
                                  const float* mask, float eps_v, float* out_score, float* out_w, CorrWs& w,
-                                 hipStream_t stream, float* out_C = nullptr, const double* stats_in = nullptr) {
+                                 hipStream_t stream, float* out_C = nullptr, const double* stats_in = nullptr,
+                                 bool planar = false) {
   const long half = g.half();
-  TTM_PROF(PC_STATS, launch_multiplicities(order_n, w.mu, stream));
+  if (planar)
+    TTM_PROF(PC_STATS, launch_planar_mu(order_n, w.mu, stream));
+  else
+    TTM_PROF(PC_STATS, launch_multiplicities(order_n, w.mu, stream));
   TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream, stats_in));
   // K components and the mask against f, then the mask against f^2
   const Pass1Args p1{w.Xf, bk, K + 1, w.Xg, bk + (long)K * g.bank_slab(), 1, g.bank_slab(), w.H, half};
@@ -995,6 +1000,144 @@ ttm_status ttm_rotation_map(const float* image, ttm_dims N, const void* bank, tt
   TTM_PROF(PC_RMAP_POLISH, launch_rmap_polish(g, order_n, rw.planes, seeds, rw.group, opt->hopm_max_iter,
                                               opt->hopm_tol, out_score, out_quat, out_lambda, out_unconverged,
                                               stream));
+  return TTM_OK;
+}
+
+// --- two-dimensional TTM -----------------------------------------------------------
+// volume index of each planar multi-index (n - k, k, 0, 0), in the packed order
+// (alpha_1 from n down, then alpha_2, then alpha_3)
+static PlanarIdx planar_idx(int n) {
+  PlanarIdx p{};
+  int idx = 0;
+  for (int a1 = n; a1 >= 0; --a1)
+    for (int a2 = n - a1; a2 >= 0; --a2)
+      for (int a3 = n - a1 - a2; a3 >= 0; --a3) {
+        if (a3 == 0 && a1 + a2 == n) p.k3[a2] = idx;
+        ++idx;
+      }
+  return p;
+}
+
+static bool planar_box_ok(int L1, int L2) {
+  return L1 >= 1 && L2 >= 1 && L1 <= 1023 && L2 <= 512;
+}
+
+static bool planar_quadrature_ok(const float* z, const double* w, int n_rot) {
+  double wsum = 0.0;
+  for (int j = 0; j < n_rot; ++j) {
+    const double nz = (double)z[2 * j] * z[2 * j] + (double)z[2 * j + 1] * z[2 * j + 1];
+    if (!std::isfinite(nz) || nz <= 0.0 || !std::isfinite(w[j])) return false;
+    wsum += w[j];
+  }
+  return std::fabs(wsum - 1.0) <= 1e-6;
+}
+
+size_t ttm_bank_bytes_2d(int32_t B, int32_t n1, int32_t n2, int32_t L1, int32_t L2, int32_t order_n) {
+  if (ttm_num_components(order_n) < 0 || order_n > kPlanarMaxOrder) return 0;
+  return ttm_bank_bytes(ttm_dims{B, n1, n2}, ttm_dims{1, L1, L2}, order_n + 1);
+}
+
+size_t ttm_build_workspace_bytes_2d(int32_t L1, int32_t L2, int32_t order_n, int32_t n_rot) {
+  const int K3 = ttm_num_components(order_n);
+  if (K3 < 0 || order_n > kPlanarMaxOrder || n_rot < 1 || !planar_box_ok(L1, L2)) return 0;
+  Carve c(nullptr);
+  build_layout(c, n_rot, K3);
+  c.take<float>(2 * (size_t)n_rot);
+  c.take<float>((size_t)K3 * L1 * L2);
+  return c.size();
+}
+
+ttm_status ttm_build_tensor_template_2d(const float* tmpl, const float* mask, int32_t L1, int32_t L2,
+                                        int32_t order_n, const float* z_host, const double* weights_host,
+                                        int32_t n_rot, float* out_components, int32_t B, int32_t n1, int32_t n2,
+                                        void* out_bank, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!tmpl || !mask || !z_host || !weights_host || !out_components) return TTM_E_ARG;
+  const int K3 = ttm_num_components(order_n);
+  if (K3 < 0 || order_n > kPlanarMaxOrder || n_rot < 1) return TTM_E_ARG;
+  if (!planar_quadrature_ok(z_host, weights_host, n_rot)) return TTM_E_ARG;
+  if (!planar_box_ok(L1, L2)) return TTM_E_SIZE;
+  const ttm_dims N{B, n1, n2}, L{1, L1, L2};
+  if (out_bank && (!image_dims_ok(N) || !fits(L, N))) return TTM_E_SIZE;
+  if (!ws || ws_bytes < ttm_build_workspace_bytes_2d(L1, L2, order_n, n_rot)) return TTM_E_WORKSPACE;
+  Carve c(ws);
+  BuildWs w = build_layout(c, n_rot, K3);
+  float* zd = c.take<float>(2 * (size_t)n_rot);
+  float* comps3 = c.take<float>((size_t)K3 * L1 * L2);
+  TTM_TRY(hipMemcpyAsync(zd, z_host, sizeof(float) * 2 * (size_t)n_rot, hipMemcpyHostToDevice, stream));
+  TTM_TRY(hipMemcpyAsync(w.weights, weights_host, sizeof(double) * (size_t)n_rot, hipMemcpyHostToDevice, stream));
+  TTM_PROF(PC_BUILD, launch_planar_quats(zd, n_rot, w.quats, stream));
+  TTM_PROF(PC_BUILD, launch_rot_stats(tmpl, mask, 1, L1, L2, w.quats, n_rot, w.rstats, stream));
+  TTM_PROF(PC_BUILD, launch_build_coef(w.quats, w.weights, w.rstats, n_rot, order_n, w.coef, stream));
+  TTM_PROF(PC_BUILD, launch_build_accum(tmpl, mask, 1, L1, L2, w.quats, w.rstats, w.coef, n_rot, K3, comps3,
+                                        w.rtab, stream));
+  TTM_PROF(PC_BUILD, launch_planar_gather(comps3, planar_idx(order_n), order_n + 1, (long)L1 * L2, out_components,
+                                          stream));
+  if (out_bank) {
+    const int K2 = order_n + 1;
+    const Geo g = make_geo(N, L);
+    float2* bank = static_cast<float2*>(out_bank);
+    TTM_CALL(bank_forward(g, out_components, K2, bank, stream));
+    TTM_CALL(bank_forward(g, mask, 1, bank + (long)K2 * g.bank_slab(), stream));
+  }
+  return TTM_OK;
+}
+
+struct Match2dWs {
+  CorrWs cw; PoseWs pw; float* comps3; int* pos3; float* quat3; double* C3;
+};
+static Match2dWs match2d_layout(Carve& c, const Geo& gs, const Geo& gp, int B, int order_n,
+                                const ttm_options* opt) {
+  const int K3 = ttm_num_components(order_n);
+  const size_t P = (size_t)opt->max_peaks;
+  Match2dWs m;
+  m.cw = corr_layout(c, gs, order_n + 1);
+  m.pw = pose_layout(c, gp, opt->max_peaks, K3, opt->refine, opt->n_seeds);
+  m.comps3 = c.take<float>((size_t)K3 * gp.L1 * gp.L2);
+  m.pos3 = c.take<int>((size_t)B * P * 3);
+  m.quat3 = c.take<float>((size_t)B * P * 4);
+  m.C3 = c.take<double>(P * (size_t)K3);
+  return m;
+}
+
+size_t ttm_match_2d_workspace_bytes(int32_t B, int32_t n1, int32_t n2, int32_t L1, int32_t L2, int32_t order_n,
+                                    const ttm_options* opt) {
+  if (ttm_num_components(order_n) < 0 || order_n > kPlanarMaxOrder || !opt || !pose_opts_ok(opt)) return 0;
+  const ttm_dims N{B, n1, n2}, L{1, L1, L2};
+  if (!planar_box_ok(L1, L2) || !image_dims_ok(N) || !fits(L, N)) return 0;
+  Carve c(nullptr);
+  match2d_layout(c, make_geo(N, L), make_geo(ttm_dims{1, n1, n2}, L), B, order_n, opt);
+  return c.size();
+}
+
+ttm_status ttm_match_2d(const float* images, int32_t B, int32_t n1, int32_t n2, const void* bank,
+                        const float* components, const float* tmpl, const float* mask, int32_t L1, int32_t L2,
+                        int32_t order_n, const ttm_options* opt, float* out_score, float* out_w, int32_t* out_pos,
+                        float* out_z, double* out_lambda, float* out_peak_score, int32_t* out_flags,
+                        int32_t* out_count, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!images || !bank || !components || !mask || !opt || !out_score || !out_pos || !out_z || !out_lambda ||
+      !out_peak_score || !out_flags || !out_count)
+    return TTM_E_ARG;
+  if (opt->refine >= 2 && !tmpl) return TTM_E_ARG;
+  const int K3 = ttm_num_components(order_n);
+  if (K3 < 0 || order_n > kPlanarMaxOrder || !pose_opts_ok(opt)) return TTM_E_ARG;
+  const ttm_dims N{B, n1, n2}, L{1, L1, L2};
+  if (!planar_box_ok(L1, L2) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
+  if (!ws || ws_bytes < ttm_match_2d_workspace_bytes(B, n1, n2, L1, L2, order_n, opt)) return TTM_E_WORKSPACE;
+  const Geo gs = make_geo(N, L), gp = make_geo(ttm_dims{1, n1, n2}, L);
+  Carve c(ws);
+  Match2dWs m = match2d_layout(c, gs, gp, B, order_n, opt);
+  const int K2 = order_n + 1;
+  TTM_CALL(correlate_into(gs, order_n, K2, images, static_cast<const float2*>(bank), mask, opt->eps_v, out_score,
+                          out_w, m.cw, stream, nullptr, nullptr, true));
+  TTM_PROF(PC_POSE, launch_planar_embed(components, planar_idx(order_n), K2, K3, (long)L1 * L2, m.comps3, stream));
+  const long V2 = (long)n1 * n2;
+  const int P = opt->max_peaks;
+  for (int b = 0; b < B; ++b)
+    TTM_CALL(recover_pose_into(gp, out_score + b * V2, images + b * V2, m.comps3, mask, tmpl, order_n, K3, opt,
+                               m.pos3 + (long)b * P * 3, m.quat3 + (long)b * P * 4, out_lambda + (long)b * P,
+                               out_peak_score + (long)b * P, out_flags + (long)b * P, m.C3, out_count + 2 * b,
+                               m.pw, stream));
+  TTM_PROF(PC_POSE, launch_planar_out(B, P, out_count, m.pos3, m.quat3, out_pos, out_z, stream));
   return TTM_OK;
 }
 

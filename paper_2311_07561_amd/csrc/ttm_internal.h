@@ -194,6 +194,20 @@ hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int 
 hipError_t launch_mask_list(const float* mask, int L0, int L1, int L2, unsigned* list, float* mval, int* count,
                             hipStream_t s);
 
+// --- two-dimensional TTM (ttm_planar.hip) -----------------------------------
+constexpr int kPlanarMaxOrder = 8;
+struct PlanarIdx {
+  int k3[kPlanarMaxOrder + 1];   // volume index of the multi-index (n - k, k, 0, 0)
+};
+hipError_t launch_planar_quats(const float* z, int nrot, float* quats, hipStream_t s);
+hipError_t launch_planar_mu(int order_n, float* mu, hipStream_t s);
+hipError_t launch_planar_gather(const float* comps3, const PlanarIdx& idx, int np, long A, float* comps2,
+                                hipStream_t s);
+hipError_t launch_planar_embed(const float* comps2, const PlanarIdx& idx, int np, int K3, long A, float* comps3,
+                               hipStream_t s);
+hipError_t launch_planar_out(int B, int P, const int* counts, const int* pos3, const float* quat3, int* pos2,
+                             float* z2, hipStream_t s);
+
 // --- S'-consistent normalisation (ttm_snorm.hip) ------------------------------
 constexpr double kSnormFlatRel = 1e-6;
 struct SnormGeo {

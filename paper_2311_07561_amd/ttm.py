@@ -93,6 +93,13 @@ _SIGS = {
     "ttm_rotation_map_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32, _I32]),
     "ttm_rotation_map": (_I32, [_P, _DIMS, _P, _DIMS, _I32, _P, _OPTP, _P, _I32, _P, _P, _P, _P, _P, _P, _SZ,
                                 _P]),
+    "ttm_bank_bytes_2d": (_SZ, [_I32, _I32, _I32, _I32, _I32, _I32]),
+    "ttm_build_workspace_bytes_2d": (_SZ, [_I32, _I32, _I32, _I32]),
+    "ttm_build_tensor_template_2d": (_I32, [_P, _P, _I32, _I32, _I32, _P, _P, _I32, _P, _I32, _I32, _I32, _P, _P,
+                                            _SZ, _P]),
+    "ttm_match_2d_workspace_bytes": (_SZ, [_I32, _I32, _I32, _I32, _I32, _I32, _OPTP]),
+    "ttm_match_2d": (_I32, [_P, _I32, _I32, _I32, _P, _P, _P, _P, _I32, _I32, _I32, _OPTP, _P, _P, _P, _P, _P, _P,
+                            _P, _P, _P, _SZ, _P]),
     "ttm_snorm_workspace_bytes": (_SZ, [_DIMS, _I32, _I32]),
     "ttm_snorm": (_I32, [_P, _DIMS, _P, _P, _DIMS, _I32, _P, _P, _I32, _P, _P, _P, _I32, _P, _P, _P, _P, _SZ, _P]),
     "ttm_tile_count": (_I32, [_DIMS, _DIMS, _I32]),
@@ -420,6 +427,82 @@ def match(image: torch.Tensor, bank: torch.Tensor, mask: torch.Tensor, order: in
                          bufs.flags.data_ptr(), bufs.C.data_ptr(), bufs.count.data_ptr(), bufs.ws.data_ptr(),
                          bufs.ws.numel(), _stream(dev))
     _check(st, "ttm_match")
+
+
+def build_tensor_template_2d(tmpl: torch.Tensor, mask: torch.Tensor, order: int, zs, weights,
+                             stack_shape=None):
+    """Planar tensor template (ttm_build_tensor_template_2d): components
+    (n + 1, L1, L2) and, if ``stack_shape`` = (B, n1, n2) is given, the bank
+    for stacks of that shape.  ``zs`` are unit complex numbers (J, 2) of half
+    the rotation angles."""
+    dev = tmpl.device
+    L1, L2 = (int(v) for v in tmpl.shape)
+    z = torch.as_tensor(zs, dtype=torch.float32).contiguous().cpu()
+    w = torch.as_tensor(weights, dtype=torch.float64).contiguous().cpu()
+    nrot = z.shape[0]
+    if z.shape != (nrot, 2) or w.shape != (nrot,):
+        raise ValueError("zs must be (J, 2) and weights (J,)")
+    comps = torch.empty((order + 1, L1, L2), dtype=torch.float32, device=dev)
+    B = n1 = n2 = 0
+    bank = None
+    if stack_shape is not None:
+        B, n1, n2 = (int(v) for v in stack_shape)
+        nb = lib().ttm_bank_bytes_2d(B, n1, n2, L1, L2, order)
+        if nb == 0:
+            raise TTMError(-2, "ttm_bank_bytes_2d")
+        bank = torch.empty(nb, dtype=torch.uint8, device=dev)
+    nws = lib().ttm_build_workspace_bytes_2d(L1, L2, order, nrot)
+    ws = _workspace(nws, dev)
+    st = lib().ttm_build_tensor_template_2d(
+        _dev(tmpl, "tmpl"), _dev(mask, "mask"), L1, L2, order, z.data_ptr(), w.data_ptr(), nrot,
+        comps.data_ptr(), B, n1, n2, bank.data_ptr() if bank is not None else None, ws.data_ptr(), nws,
+        _stream(dev))
+    _check(st, "ttm_build_tensor_template_2d")
+    return comps, bank
+
+
+class Match2DBuffers:
+    """Preallocated outputs and workspace of ``match_2d`` for stacks of shape
+    (B, n1, n2) and an (L1, L2) template."""
+
+    def __init__(self, stack_shape, L, order: int, opt: Options, device, want_w: bool = True):
+        B, n1, n2 = (int(v) for v in stack_shape)
+        P = int(opt.max_peaks)
+        self.shape = (B, n1, n2)
+        self.score = torch.empty((B, n1, n2), dtype=torch.float32, device=device)
+        self.w = torch.empty((B, n1, n2), dtype=torch.float32, device=device) if want_w else None
+        self.pos = torch.zeros((B, P, 2), dtype=torch.int32, device=device)
+        self.z = torch.zeros((B, P, 2), dtype=torch.float32, device=device)
+        self.lam = torch.zeros((B, P), dtype=torch.float64, device=device)
+        self.peak_score = torch.zeros((B, P), dtype=torch.float32, device=device)
+        self.flags = torch.zeros((B, P), dtype=torch.int32, device=device)
+        self.count = torch.zeros((B, 2), dtype=torch.int32, device=device)
+        nws = lib().ttm_match_2d_workspace_bytes(B, n1, n2, int(L[0]), int(L[1]), order, ctypes.byref(opt))
+        if nws == 0:
+            raise TTMError(-2, "ttm_match_2d_workspace_bytes")
+        self.ws = _workspace(nws, device)
+
+    def result(self, b: int) -> dict:
+        """Plane b's peaks, trimmed to its count (one sync)."""
+        n = int(self.count[b, 0])
+        return dict(pos=self.pos[b, :n], z=self.z[b, :n], lam=self.lam[b, :n], score=self.peak_score[b, :n],
+                    flags=self.flags[b, :n], count=n)
+
+
+def match_2d(images: torch.Tensor, bank: torch.Tensor, comps: torch.Tensor, mask: torch.Tensor, order: int,
+             opt: Options, bufs: Match2DBuffers, tmpl: torch.Tensor | None = None):
+    """Planar TTM on a stack (ttm_match_2d): score maps, peaks and rotations
+    of every plane into ``bufs``, asynchronously."""
+    dev = images.device
+    B, n1, n2 = (int(v) for v in images.shape)
+    L1, L2 = (int(v) for v in mask.shape)
+    st = lib().ttm_match_2d(
+        _dev(images, "images"), B, n1, n2, bank.data_ptr(), _dev(comps, "comps"), _opt_dev(tmpl, "tmpl"),
+        _dev(mask, "mask"), L1, L2, order, ctypes.byref(opt), bufs.score.data_ptr(),
+        bufs.w.data_ptr() if bufs.w is not None else None, bufs.pos.data_ptr(), bufs.z.data_ptr(),
+        bufs.lam.data_ptr(), bufs.peak_score.data_ptr(), bufs.flags.data_ptr(), bufs.count.data_ptr(),
+        bufs.ws.data_ptr(), bufs.ws.numel(), _stream(dev))
+    _check(st, "ttm_match_2d")
 
 
 SNORM_FLAT, SNORM_NONPOS, SNORM_OUTSIDE, SNORM_TEMPLATE = 1, 2, 4, 8

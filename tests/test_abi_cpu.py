@@ -289,3 +289,42 @@ def test_snorm_validation_without_gpu():
     assert L.ttm_snorm_workspace_bytes(T, 2, 0) == 0
     need = L.ttm_snorm_workspace_bytes(T, 10000, 64)
     assert need >= 65 * 16 ** 3 * 4 + 10000 * (12 * 4 + 8)
+
+
+def test_planar_validation_without_gpu():
+    """The two-dimensional entry points reject bad arguments before any
+    device work; sizes follow the volume path's with a depth-1 box and n + 1
+    components."""
+    L = ttm.lib()
+    fake = ctypes.c_void_p(256)
+    big = 1 << 40
+    z = np.array([[1.0, 0.0], [0.0, 1.0]], dtype=np.float32)
+    w = np.array([0.5, 0.5])
+
+    def build(order=4, L1=16, L2=16, zp=z.ctypes.data, wp=w.ctypes.data, n_rot=2, B=16, n1=64, n2=64, bank=fake,
+              ws=big):
+        return L.ttm_build_tensor_template_2d(fake, fake, L1, L2, order, zp, wp, n_rot, fake, B, n1, n2, bank,
+                                              fake, ws, None)
+
+    assert build(order=3) == -1
+    assert build(order=10) == -1
+    assert build(n_rot=0) == -1
+    assert build(zp=np.zeros((2, 2), dtype=np.float32).ctypes.data) == -1
+    assert build(wp=np.array([0.5, 0.6]).ctypes.data) == -1
+    assert build(L2=513) == -2
+    assert build(n1=96) == -2                     # not a supported length
+    assert build(L1=80) == -2                     # larger than the image
+    assert build(ws=16) == -3
+    assert L.ttm_bank_bytes_2d(16, 64, 64, 16, 16, 4) == L.ttm_bank_bytes(ttm.Dims(16, 64, 64), ttm.Dims(1, 16, 16), 5)
+    o = _opt(max_peaks=8, refine=2)
+
+    def match(B=16, n1=64, n2=64, order=4, tmpl=fake, opt=o, ws=big):
+        return L.ttm_match_2d(fake, B, n1, n2, fake, fake, tmpl, fake, 16, 16, order, ctypes.byref(opt), fake, None,
+                              fake, fake, fake, fake, fake, fake, fake, ws, None)
+
+    assert match(tmpl=None) == -1                 # refine 2 reads the template
+    assert match(order=5) == -1
+    assert match(opt=_opt(max_peaks=0)) == -1
+    assert match(B=12) == -2
+    assert match(ws=1024) == -3
+    assert L.ttm_match_2d_workspace_bytes(16, 64, 64, 16, 16, 4, ctypes.byref(o)) > 0

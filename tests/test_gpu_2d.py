@@ -1,0 +1,173 @@
+"""Two-dimensional TTM (ttm_build_tensor_template_2d, ttm_match_2d) through
+the C ABI against the float64 planar oracle.
+
+Tolerances as for the volume path: components relative 1e-5 of their
+largest entry, score F absolute 1e-4, w relative 1e-4, zeros outside each
+plane's valid region; peak positions bit-exact when the oracle's picker runs
+on the GPU's own float32 map (refine 0); rotations within 1 degree of the
+oracle's eigenpair at the same position where it is unambiguous (the second
+maximum, at least 5 degrees of rotation away, below the first by more than
+1e-3 of it); refined positions within one pixel of the candidates (one
+round).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ttm_oracle as O
+from paper_2311_07561_amd import synth, ttm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ttm.lib()
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _planar_template(seed, L1, L2, r):
+    rng = np.random.default_rng(seed)
+    tm = synth.make_blob_template_2d(rng, max(L1, L2), 5, r)
+    g = np.stack(np.meshgrid(np.arange(L1) - L1 // 2, np.arange(L2) - L2 // 2, indexing="ij"), axis=-1)
+    t = tm.evaluate(g.astype(np.float64))
+    m = (np.sqrt(((g.astype(float)) ** 2).sum(-1)) < r).astype(np.float64)
+    return t.astype(np.float32), m.astype(np.float32), tm
+
+
+@pytest.mark.parametrize("L1,L2,n,J", [(11, 13, 2, 37), (16, 16, 4, 180), (15, 12, 8, 361)])
+def test_planar_components_match_oracle(L1, L2, n, J):
+    t, m, _ = _planar_template(3 + n, L1, L2, min(L1, L2) / 2 - 0.5)
+    zs = synth.circle_quadrature(J)
+    w = np.random.default_rng(n).uniform(0.5, 1.5, J)
+    w /= w.sum()
+    comps, _ = ttm.build_tensor_template_2d(dev(t), dev(m), n, zs, w)
+    torch.cuda.synchronize()
+    ref = O.tensor_template_2d(t.astype(np.float64), m.astype(np.float64), n, zs, w)
+    got = comps.cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"\nplanar components {L1}x{L2}, order {n}, {J} rotations: max rel err {err:.2e}")
+    assert got.shape == (n + 1, L1, L2)
+    assert err <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def small_stack():
+    wl = synth.workload_2d(seed=7100, count=16, size=64, L=15, order=4, plants=2, snr=2.0)
+    return wl
+
+
+@pytest.mark.parametrize("refine", [0, 2])
+def test_match_2d_against_oracle(small_stack, refine):
+    wl = small_stack
+    n = wl.order
+    L = wl.template.shape
+    zs = synth.circle_quadrature(360)
+    w = np.full(360, 1 / 360)
+    t64, m64 = wl.template.astype(np.float64), wl.mask.astype(np.float64)
+    T = O.tensor_template_2d(t64, m64, n, zs, w)
+    imgs = dev(wl.images)
+    comps, bank = ttm.build_tensor_template_2d(dev(wl.template), dev(wl.mask), n, zs, w,
+                                               stack_shape=wl.images.shape)
+    opt = ttm.default_options(max_peaks=4, min_dist=7.0, threshold=0.0, refine=refine)
+    bufs = ttm.Match2DBuffers(wl.images.shape, L, n, opt, "cuda")
+    ttm.match_2d(imgs, bank, comps, dev(wl.mask), n, opt, bufs, tmpl=dev(wl.template))
+    torch.cuda.synchronize()
+    score = bufs.score.cpu().numpy()
+    wmap = bufs.w.cpu().numpy()
+    c = np.array(L) // 2
+    worst_F = 0.0
+    worst_rot = 0.0
+    for b in (0, 5, 15):
+        f = wl.images[b].astype(np.float64)
+        F_ref = O.score_map_2d(f, T, m64, n)
+        worst_F = max(worst_F, float(np.abs(score[b] - F_ref).max()))
+        assert np.abs(score[b] - F_ref).max() <= 1e-4
+        # w inside the valid region
+        lo, hi = c, np.array(f.shape) - np.array(L) + c + 1
+        g = np.meshgrid(np.arange(lo[0], hi[0]), np.arange(lo[1], hi[1]), indexing="ij")
+        xs = np.stack([g[0].reshape(-1), g[1].reshape(-1)], axis=1)
+        w_ref = O.local_norm_at_2d(f, m64, xs)
+        assert np.allclose(wmap[b][xs[:, 0], xs[:, 1]], w_ref, rtol=1e-4, atol=0)
+        res = bufs.result(b)
+        cand = O.find_peaks_2d(score[b], L, opt.threshold, opt.min_dist, opt.max_peaks)
+        assert res["count"] == len(cand)
+        pos = res["pos"].cpu().numpy()
+        if refine == 0:
+            assert np.array_equal(pos, cand)
+        else:
+            assert np.all(np.abs(pos - cand).max(axis=1) <= 1)
+        C = O.tensor_field_at_2d(f, T, m64, pos)
+        for p in range(len(pos)):
+            zo, lo_, second = O.dominant_eigen_2d(C[p], n)
+            lam = float(res["lam"][p])
+            assert abs(lam - lo_) <= 1e-4 * max(1.0, abs(lo_))
+            if second < lo_ - 1e-3 * abs(lo_):
+                d = O.rotation_angle_2d_deg(res["z"][p].cpu().numpy(), zo)
+                worst_rot = max(worst_rot, d)
+                assert d <= 1.0
+        if refine == 2 and len(pos):
+            # the first candidate's step against the oracle's planar refinement:
+            # the same pixel, or one whose NCC at its own rotation is within
+            # 1e-4 of the oracle's best (a near tie decided by rounding)
+            p_ref, z_ref, _, ncc_ref = O.refine_by_ncc_2d(f, t64, m64, T, n, cand[0])
+            if tuple(pos[0]) != tuple(p_ref):
+                zg, _, _ = O.dominant_eigen_2d(C[0], n)
+                ncc_g = float(O.classical_ncc_at_2d(f, t64, m64, zg[None], pos[:1])[0, 0])
+                assert ncc_ref - ncc_g <= 1e-4, (pos[0], p_ref, ncc_g, ncc_ref)
+    print(f"\n16 x 64^2, L {L}, order {n}, refine {refine}: score max |err| {worst_F:.2e}, "
+          f"rotation max err {worst_rot:.3f} deg")
+
+
+def test_match_2d_full_stack_sampled():
+    """16 images of 512^2, a 32^2 template, order 8 (9 components), 720
+    rotations, iterated refinement: F at sampled pixels against direct sums,
+    the rotation at every found peak against the oracle's eigenpair there,
+    and the planted copies found."""
+    wl = synth.workload_2d()
+    n = wl.order
+    L = wl.template.shape
+    zs = synth.circle_quadrature(720)
+    w = np.full(720, 1 / 720)
+    t64, m64 = wl.template.astype(np.float64), wl.mask.astype(np.float64)
+    T = O.tensor_template_2d(t64, m64, n, zs, w)
+    comps, bank = ttm.build_tensor_template_2d(dev(wl.template), dev(wl.mask), n, zs, w,
+                                               stack_shape=wl.images.shape)
+    opt = ttm.default_options(max_peaks=len(wl.positions[0]), min_dist=16.0, threshold=0.0, refine=3)
+    bufs = ttm.Match2DBuffers(wl.images.shape, L, n, opt, "cuda")
+    ttm.match_2d(dev(wl.images), bank, comps, dev(wl.mask), n, opt, bufs, tmpl=dev(wl.template))
+    torch.cuda.synchronize()
+    score = bufs.score.cpu().numpy()
+    rng = np.random.default_rng(5)
+    c = np.array(L) // 2
+    found = 0
+    errs = []
+    for b in (0, 7, 15):
+        f = wl.images[b].astype(np.float64)
+        xs = np.stack([rng.integers(c[a], 512 - L[a] + c[a] + 1, 200) for a in range(2)], axis=1)
+        F_ref = O.score_from_field_2d(O.tensor_field_at_2d(f, T, m64, xs), n)
+        assert np.abs(score[b][xs[:, 0], xs[:, 1]] - F_ref).max() <= 1e-4
+        res = bufs.result(b)
+        pos = res["pos"].cpu().numpy()
+        C = O.tensor_field_at_2d(f, T, m64, pos)
+        for p in range(len(pos)):
+            zo, lo_, second = O.dominant_eigen_2d(C[p], n)
+            if second < lo_ - 1e-3 * abs(lo_):
+                assert O.rotation_angle_2d_deg(res["z"][p].cpu().numpy(), zo) <= 1.0
+        for x, a in zip(wl.positions[b], wl.angles[b]):
+            d = np.linalg.norm(pos - x[None], axis=1)
+            if len(d) and d.min() <= 2.0:
+                found += 1
+                i = int(np.argmin(d))
+                errs.append(O.rotation_angle_2d_deg(res["z"][i].cpu().numpy(), [math.cos(a / 2), math.sin(a / 2)]))
+    total = 3 * len(wl.positions[0])
+    print(f"\n16 x 512^2, L 32, order 8: {found}/{total} planted copies found within 2 px in 3 planes, "
+          f"rotation error median {np.median(errs):.2f} deg, max {np.max(errs):.2f} deg")
+    assert found >= 0.5 * total
