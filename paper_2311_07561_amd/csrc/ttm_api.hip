@@ -1083,29 +1083,42 @@ ttm_status ttm_build_tensor_template_2d(const float* tmpl, const float* mask, in
 }
 
 struct Match2dWs {
-  CorrWs cw; PoseWs pw; float* comps3; int* pos3; float* quat3; double* C3;
+  CorrWs cw; PoseWs pw; float* comps3; int* cand; float* cand_score; int* list; int* idx; int* total;
+  int* pos3; float* quat3; double* lam3; float* score3; int* flags3; double* C3;
 };
-static Match2dWs match2d_layout(Carve& c, const Geo& gs, const Geo& gp, int B, int order_n,
-                                const ttm_options* opt) {
+// the pose scratch serves all B P candidates of the stack at once; the peak
+// scratch inside it (sized for the stack) is reused plane after plane
+static Match2dWs match2d_layout(Carve& c, const Geo& gs, int B, int order_n, const ttm_options* opt) {
   const int K3 = ttm_num_components(order_n);
-  const size_t P = (size_t)opt->max_peaks;
+  const size_t P = (size_t)opt->max_peaks, BP = (size_t)B * P;
   Match2dWs m;
   m.cw = corr_layout(c, gs, order_n + 1);
-  m.pw = pose_layout(c, gp, opt->max_peaks, K3, opt->refine, opt->n_seeds);
-  m.comps3 = c.take<float>((size_t)K3 * gp.L1 * gp.L2);
-  m.pos3 = c.take<int>((size_t)B * P * 3);
-  m.quat3 = c.take<float>((size_t)B * P * 4);
-  m.C3 = c.take<double>(P * (size_t)K3);
+  m.pw = pose_layout(c, gs, (int)BP, K3, opt->refine, opt->n_seeds);
+  m.comps3 = c.take<float>((size_t)K3 * gs.L1 * gs.L2);
+  m.cand = c.take<int>(BP * 3);
+  m.cand_score = c.take<float>(P);
+  m.list = c.take<int>(BP * 3);
+  m.idx = c.take<int>(BP);
+  m.total = c.take<int>(1);
+  m.pos3 = c.take<int>(BP * 3);
+  m.quat3 = c.take<float>(BP * 4);
+  m.lam3 = c.take<double>(BP);
+  m.score3 = c.take<float>(BP);
+  m.flags3 = c.take<int>(BP);
+  m.C3 = c.take<double>(BP * (size_t)K3);
   return m;
 }
+
+constexpr long kPlanarMaxCandidates = 65536;
 
 size_t ttm_match_2d_workspace_bytes(int32_t B, int32_t n1, int32_t n2, int32_t L1, int32_t L2, int32_t order_n,
                                     const ttm_options* opt) {
   if (ttm_num_components(order_n) < 0 || order_n > kPlanarMaxOrder || !opt || !pose_opts_ok(opt)) return 0;
   const ttm_dims N{B, n1, n2}, L{1, L1, L2};
   if (!planar_box_ok(L1, L2) || !image_dims_ok(N) || !fits(L, N)) return 0;
+  if ((long)B * opt->max_peaks > kPlanarMaxCandidates) return 0;
   Carve c(nullptr);
-  match2d_layout(c, make_geo(N, L), make_geo(ttm_dims{1, n1, n2}, L), B, order_n, opt);
+  match2d_layout(c, make_geo(N, L), B, order_n, opt);
   return c.size();
 }
 
@@ -1122,22 +1135,45 @@ ttm_status ttm_match_2d(const float* images, int32_t B, int32_t n1, int32_t n2, 
   if (K3 < 0 || order_n > kPlanarMaxOrder || !pose_opts_ok(opt)) return TTM_E_ARG;
   const ttm_dims N{B, n1, n2}, L{1, L1, L2};
   if (!planar_box_ok(L1, L2) || !image_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
+  if ((long)B * opt->max_peaks > kPlanarMaxCandidates) return TTM_E_SIZE;
   if (!ws || ws_bytes < ttm_match_2d_workspace_bytes(B, n1, n2, L1, L2, order_n, opt)) return TTM_E_WORKSPACE;
-  const Geo gs = make_geo(N, L), gp = make_geo(ttm_dims{1, n1, n2}, L);
+  Geo gs = make_geo(N, L);
+  const Geo gp = make_geo(ttm_dims{1, n1, n2}, L);
   Carve c(ws);
-  Match2dWs m = match2d_layout(c, gs, gp, B, order_n, opt);
+  Match2dWs m = match2d_layout(c, gs, B, order_n, opt);
+  PoseWs& w = m.pw;
   const int K2 = order_n + 1;
   TTM_CALL(correlate_into(gs, order_n, K2, images, static_cast<const float2*>(bank), mask, opt->eps_v, out_score,
                           out_w, m.cw, stream, nullptr, nullptr, true));
   TTM_PROF(PC_POSE, launch_planar_embed(components, planar_idx(order_n), K2, K3, (long)L1 * L2, m.comps3, stream));
+  // candidates plane by plane (the suppression and the count are per image)
   const long V2 = (long)n1 * n2;
-  const int P = opt->max_peaks;
+  const int P = opt->max_peaks, BP = B * P;
+  PeakWs pk{w.hist, w.ctrl, w.allc, w.cand};
   for (int b = 0; b < B; ++b)
-    TTM_CALL(recover_pose_into(gp, out_score + b * V2, images + b * V2, m.comps3, mask, tmpl, order_n, K3, opt,
-                               m.pos3 + (long)b * P * 3, m.quat3 + (long)b * P * 4, out_lambda + (long)b * P,
-                               out_peak_score + (long)b * P, out_flags + (long)b * P, m.C3, out_count + 2 * b,
-                               m.pw, stream));
-  TTM_PROF(PC_POSE, launch_planar_out(B, P, out_count, m.pos3, m.quat3, out_pos, out_z, stream));
+    TTM_PROF(PC_PEAKS, launch_peaks(gp, out_score + b * V2, opt->threshold, opt->min_dist, P, pk,
+                                    m.cand + (long)b * P * 3, m.cand_score, out_count + 2 * b, stream));
+  TTM_PROF(PC_POSE, launch_planar_compact(B, P, out_count, m.cand, m.list, m.idx, m.total, stream));
+  // the poses of all planes' candidates at once, on the stack; the refinement
+  // neighbourhood stays inside each plane
+  gs.planar = 1;
+  TTM_PROF(PC_STATS, launch_image_stats(images, gs.vol(), nullptr, 0, w.partials, w.stats, stream));
+  const int rf = opt->refine == 3 ? 2 : opt->refine;
+  TTM_PROF(PC_POSE, launch_pose_tensor(gs, images, m.comps3, mask, order_n, w.stats, opt->eps_v, BP, rf, m.list,
+                                       m.total, 0, w.ps, stream));
+  TTM_PROF(PC_POSE, launch_pose_solve(gs, out_score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol, BP, rf,
+                                      m.list, m.total, 0, images, tmpl, mask, m.pos3, m.quat3, m.lam3, m.score3,
+                                      m.flags3, m.C3, w.ps, stream));
+  if (opt->refine == 3) {
+    auto tensor = [&](const int* pos, const int* cnt) {
+      return launch_pose_tensor(gs, images, m.comps3, mask, order_n, w.stats, opt->eps_v, BP, 2, pos, cnt, 0, w.ps,
+                                stream);
+    };
+    TTM_CALL(refine_rounds(gs, out_score, order_n, K3, opt, BP, m.total, 0, m.list, images, tmpl, mask, m.pos3,
+                           m.quat3, m.lam3, m.score3, m.flags3, m.C3, w, tensor, stream));
+  }
+  TTM_PROF(PC_POSE, launch_planar_scatter(BP, m.total, m.idx, m.pos3, m.quat3, m.lam3, m.score3, m.flags3, out_pos,
+                                          out_z, out_lambda, out_peak_score, out_flags, stream));
   return TTM_OK;
 }
 

@@ -29,6 +29,7 @@ struct Geo {
                        // tile, which the XCD-aware tile order keeps in one L2)
   int L0, L1, L2;      // template extents
   int c0, c1, c2;      // template centre (L / 2)
+  int planar = 0;      // a stack of planes: the pose neighbourhood stays in each plane
   long vol() const { return (long)n0 * n1 * n2; }
   long half() const { return (long)n0 * n1 * p2; }     // complex elements of a half spectrum
   long bank_slab() const { return (long)L0 * n1 * p2; } // complex elements per bank entry
@@ -205,8 +206,15 @@ hipError_t launch_planar_gather(const float* comps3, const PlanarIdx& idx, int n
                                 hipStream_t s);
 hipError_t launch_planar_embed(const float* comps2, const PlanarIdx& idx, int np, int K3, long A, float* comps3,
                                hipStream_t s);
-hipError_t launch_planar_out(int B, int P, const int* counts, const int* pos3, const float* quat3, int* pos2,
-                             float* z2, hipStream_t s);
+// the candidates of every plane (counts[2 b], cand [B][P][3] with plane
+// coordinates) in one list of stack positions (b, x1, x2), with the flat index
+// b P + p of each and their total
+hipError_t launch_planar_compact(int B, int P, const int* counts, const int* cand, int* list, int* idx, int* total,
+                                 hipStream_t s);
+// the compact-order poses back to [B][P]: positions (x1, x2), z = (a, b) / |(a, b)|
+hipError_t launch_planar_scatter(int cap, const int* total, const int* idx, const int* pos3, const float* quat3,
+                                 const double* lam3, const float* score3, const int* flags3, int* pos2, float* z2,
+                                 double* lam, float* score, int* flags, hipStream_t s);
 
 // --- S'-consistent normalisation (ttm_snorm.hip) ------------------------------
 constexpr double kSnormFlatRel = 1e-6;

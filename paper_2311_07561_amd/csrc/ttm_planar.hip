@@ -53,21 +53,51 @@ __global__ void k_planar_embed(const float* __restrict__ comps2, PlanarIdx idx, 
   comps3[e] = v;
 }
 
-// volume poses of a stack's images to planar ones: pos (x0 = 0, x1, x2) ->
-// (x1, x2), quaternion (a, b, c, d) -> z = (a, b) / |(a, b)|; entries past
-// each image's count are left untouched
-__global__ void k_planar_out(int B, int P, const int* __restrict__ counts, const int* __restrict__ pos3,
-                             const float* __restrict__ quat3, int* __restrict__ pos2, float* __restrict__ z2) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= B * P) return;
-  const int b = e / P, p = e % P;
-  if (p >= counts[2 * b]) return;
-  pos2[2 * e] = pos3[3 * e + 1];
-  pos2[2 * e + 1] = pos3[3 * e + 2];
-  const float a = quat3[4 * e], bb = quat3[4 * e + 1];
+// one list of the stack's candidates: an exclusive scan of the per-plane
+// counts (B <= 512) in LDS, then each entry copied with its plane index; one
+// block
+__global__ void __launch_bounds__(1024) k_planar_compact(int B, int P, const int* __restrict__ counts,
+                                                         const int* __restrict__ cand, int* __restrict__ list,
+                                                         int* __restrict__ idx, int* __restrict__ total) {
+  __shared__ int off[513];
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int b = 0; b < B; ++b) {
+      off[b] = t;
+      t += min(max(counts[2 * b], 0), P);
+    }
+    off[B] = t;
+    total[0] = t;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < B * P; e += blockDim.x) {
+    const int b = e / P, p = e % P;
+    if (p >= off[b + 1] - off[b]) continue;
+    const int o = off[b] + p;
+    list[3 * o] = b;
+    list[3 * o + 1] = cand[3 * e + 1];
+    list[3 * o + 2] = cand[3 * e + 2];
+    idx[o] = e;
+  }
+}
+
+__global__ void k_planar_scatter(int cap, const int* __restrict__ total, const int* __restrict__ idx,
+                                 const int* __restrict__ pos3, const float* __restrict__ quat3,
+                                 const double* __restrict__ lam3, const float* __restrict__ score3,
+                                 const int* __restrict__ flags3, int* __restrict__ pos2, float* __restrict__ z2,
+                                 double* __restrict__ lam, float* __restrict__ score, int* __restrict__ flags) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= cap || o >= total[0]) return;
+  const int e = idx[o];
+  pos2[2 * e] = pos3[3 * o + 1];
+  pos2[2 * e + 1] = pos3[3 * o + 2];
+  const float a = quat3[4 * o], bb = quat3[4 * o + 1];
   const float r = sqrtf(a * a + bb * bb);
   z2[2 * e] = r > 0.0f ? a / r : 1.0f;
   z2[2 * e + 1] = r > 0.0f ? bb / r : 0.0f;
+  lam[e] = lam3[o];
+  score[e] = score3[o];
+  flags[e] = flags3[o];
 }
 
 hipError_t launch_planar_quats(const float* z, int nrot, float* quats, hipStream_t s) {
@@ -96,10 +126,18 @@ hipError_t launch_planar_embed(const float* comps2, const PlanarIdx& idx, int np
   return hipGetLastError();
 }
 
-hipError_t launch_planar_out(int B, int P, const int* counts, const int* pos3, const float* quat3, int* pos2,
-                             float* z2, hipStream_t s) {
-  hipLaunchKernelGGL(k_planar_out, dim3((B * P + 255) / 256), dim3(256), 0, s, B, P, counts, pos3, quat3, pos2,
-                     z2);
+hipError_t launch_planar_compact(int B, int P, const int* counts, const int* cand, int* list, int* idx, int* total,
+                                 hipStream_t s) {
+  if (B < 1 || B > 512) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_planar_compact, dim3(1), dim3(1024), 0, s, B, P, counts, cand, list, idx, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_planar_scatter(int cap, const int* total, const int* idx, const int* pos3, const float* quat3,
+                                 const double* lam3, const float* score3, const int* flags3, int* pos2, float* z2,
+                                 double* lam, float* score, int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_planar_scatter, dim3((cap + 255) / 256), dim3(256), 0, s, cap, total, idx, pos3, quat3, lam3,
+                     score3, flags3, pos2, z2, lam, score, flags);
   return hipGetLastError();
 }
 

@@ -326,6 +326,7 @@ hipError_t launch_peaks(const Geo& gg, const float* score, float threshold, floa
 struct PoseGeo {
   int n0, n1, n2, L0, L1, L2;
   int lo0, hi0, lo1, hi1, lo2, hi2;
+  int planar;   // a stack of planes: neighbours in other planes are outside
 };
 
 constexpr int kTensorChunk = 36;
@@ -406,7 +407,8 @@ __global__ void __launch_bounds__(256) k_pose_tensor(PoseGeo g, const float* __r
   int o0, o1, o2;
   neighbour_offset(k, NB, o0, o1, o2);
   const int x0 = pos[3 * p] + o0, x1 = pos[3 * p + 1] + o1, x2 = pos[3 * p + 2] + o2;
-  const bool inside = x0 >= g.lo0 && x0 <= g.hi0 && x1 >= g.lo1 && x1 <= g.hi1 && x2 >= g.lo2 && x2 <= g.hi2;
+  const bool inside = x0 >= g.lo0 && x0 <= g.hi0 && x1 >= g.lo1 && x1 <= g.hi1 && x2 >= g.lo2 && x2 <= g.hi2 &&
+                      !(g.planar && o0 != 0);
   if (!inside) {
     if (tid == 0) {
       okbuf[b] = 0;
@@ -1028,6 +1030,7 @@ static PoseGeo make_posegeo(const Geo& gg) {
   g.lo0 = gg.c0; g.hi0 = gg.n0 - gg.L0 + gg.c0;
   g.lo1 = gg.c1; g.hi1 = gg.n1 - gg.L1 + gg.c1;
   g.lo2 = gg.c2; g.hi2 = gg.n2 - gg.L2 + gg.c2;
+  g.planar = gg.planar;
   return g;
 }
 
