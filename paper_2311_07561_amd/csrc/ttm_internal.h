@@ -188,7 +188,7 @@ hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int 
                              int count_host, const float* image, const float* tmpl, const float* mask,
                              int* out_pos, float* out_quat, double* out_lambda, float* out_score, int* out_flags,
                              double* out_C, const PoseScratch& ps, hipStream_t s, bool reuse_tables = false,
-                             int ncc_groups = 3);
+                             int ncc_groups = 9);
 
 // the mask voxels with m != 0 (packed u0 | u1 << 10 | u2 << 20), their
 // values and their count; one block

@@ -654,15 +654,27 @@ __global__ void __launch_bounds__(1024) k_mask_list(const float* __restrict__ ma
   const int B0 = (L0 + 3) / 4, B1 = (L1 + 3) / 4, B2 = (L2 + 3) / 4, nB = B0 * B1 * B2;
   const int j0 = lane >> 4, j1 = (lane >> 2) & 3, j2 = lane & 3;
   if (tid == 0) base = 0;
+  // loads in flight per wave: the bricks of a wave are independent, so their
+  // mask values are loaded in groups of kLoads before any ballot waits on one
+  constexpr int kLoads = 8;
   for (int c0 = 0; c0 < nB; c0 += kChunk) {
     const int nc = min(kChunk, nB - c0);
-    for (int i = wave; i < nc; i += 16) {
-      const int br = c0 + i;
-      const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
-      const int u0 = 4 * b0 + j0, u1 = 4 * b1 + j1, u2 = 4 * b2 + j2;
-      const bool on = u0 < L0 && u1 < L1 && u2 < L2 && mask[(u0 * L1 + u1) * L2 + u2] != 0.0f;
-      const unsigned long long bl = __ballot(on);
-      if (lane == 0) bits_s[i] = bl;
+    for (int i0 = wave; i0 < nc; i0 += 16 * kLoads) {
+      float v[kLoads];
+#pragma unroll
+      for (int j = 0; j < kLoads; ++j) {
+        const int i = i0 + 16 * j;
+        const int br = c0 + i;
+        const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
+        const int u0 = 4 * b0 + j0, u1 = 4 * b1 + j1, u2 = 4 * b2 + j2;
+        v[j] = (i < nc && u0 < L0 && u1 < L1 && u2 < L2) ? mask[(u0 * L1 + u1) * L2 + u2] : 0.0f;
+      }
+#pragma unroll
+      for (int j = 0; j < kLoads; ++j) {
+        const int i = i0 + 16 * j;
+        const unsigned long long bl = __ballot(v[j] != 0.0f);
+        if (lane == 0 && i < nc) bits_s[i] = bl;
+      }
     }
     __syncthreads();
     // exclusive scan of the brick counts: each thread sums a run of 2 bricks
@@ -689,15 +701,32 @@ __global__ void __launch_bounds__(1024) k_mask_list(const float* __restrict__ ma
       }
     }
     __syncthreads();
-    for (int i = wave; i < nc; i += 16) {
-      const unsigned long long bl = bits_s[i];
-      if ((bl >> lane) & 1ull) {
-        const int br = c0 + i;
-        const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
-        const int u0 = 4 * b0 + j0, u1 = 4 * b1 + j1, u2 = 4 * b2 + j2;
-        const int o = off_s[i] + __popcll(bl & ((1ull << lane) - 1ull));
-        list[o] = (unsigned)u0 | ((unsigned)u1 << 10) | ((unsigned)u2 << 20);
-        mval[o] = mask[(u0 * L1 + u1) * L2 + u2];
+    for (int i0 = wave; i0 < nc; i0 += 16 * kLoads) {
+      float v[kLoads];
+#pragma unroll
+      for (int j = 0; j < kLoads; ++j) {
+        const int i = i0 + 16 * j;
+        v[j] = 0.0f;
+        if (i < nc && ((bits_s[i] >> lane) & 1ull)) {
+          const int br = c0 + i;
+          const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
+          const int u0 = 4 * b0 + j0, u1 = 4 * b1 + j1, u2 = 4 * b2 + j2;
+          v[j] = mask[(u0 * L1 + u1) * L2 + u2];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kLoads; ++j) {
+        const int i = i0 + 16 * j;
+        if (i >= nc) continue;
+        const unsigned long long bl = bits_s[i];
+        if ((bl >> lane) & 1ull) {
+          const int br = c0 + i;
+          const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
+          const int u0 = 4 * b0 + j0, u1 = 4 * b1 + j1, u2 = 4 * b2 + j2;
+          const int o = off_s[i] + __popcll(bl & ((1ull << lane) - 1ull));
+          list[o] = (unsigned)u0 | ((unsigned)u1 << 10) | ((unsigned)u2 << 20);
+          mval[o] = v[j];
+        }
       }
     }
     __syncthreads();
