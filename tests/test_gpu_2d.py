@@ -171,3 +171,37 @@ def test_match_2d_full_stack_sampled():
     print(f"\n16 x 512^2, L 32, order 8: {found}/{total} planted copies found within 2 px in 3 planes, "
           f"rotation error median {np.median(errs):.2f} deg, max {np.max(errs):.2f} deg")
     assert found >= 0.5 * total
+
+
+def test_classical_matching_of_a_stack_with_planar_rotations(small_stack):
+    """Classical matching of a stack is tm_classical with a depth-1 box and
+    the quaternions (a, b, 0, 0): its best NCC and argmax equal the planar
+    oracle's classical NCC at every valid pixel of three planes (best within
+    1e-4; the argmax where the best two rotations differ by more than 1e-4)."""
+    wl = small_stack
+    L = wl.template.shape
+    J = 48
+    zs = synth.circle_quadrature(J)
+    q3 = np.stack([zs[:, 0], zs[:, 1], np.zeros(J), np.zeros(J)], axis=1).astype(np.float32)
+    tm3 = dev(wl.template[None])
+    mk3 = dev(wl.mask[None])
+    best, idx = ttm.tm_classical(dev(wl.images), tm3, mk3, q3)
+    torch.cuda.synchronize()
+    best = best.cpu().numpy()
+    idx = idx.cpu().numpy()
+    c = np.array(L) // 2
+    t64, m64 = wl.template.astype(np.float64), wl.mask.astype(np.float64)
+    checked = 0
+    for b in (1, 8, 14):
+        f = wl.images[b].astype(np.float64)
+        g = np.meshgrid(np.arange(c[0], 64 - L[0] + c[0] + 1), np.arange(c[1], 64 - L[1] + c[1] + 1), indexing="ij")
+        xs = np.stack([g[0].reshape(-1), g[1].reshape(-1)], axis=1)
+        ncc = O.classical_ncc_at_2d(f, t64, m64, zs, xs)
+        ref_best = ncc.max(axis=1)
+        assert np.abs(best[b][xs[:, 0], xs[:, 1]] - ref_best).max() <= 1e-4
+        srt = np.sort(ncc, axis=1)
+        clear = srt[:, -1] - srt[:, -2] > 1e-4
+        got_idx = idx[b][xs[:, 0], xs[:, 1]]
+        assert np.array_equal(got_idx[clear], np.argmax(ncc, axis=1)[clear])
+        checked += int(clear.sum())
+    print(f"\nclassical on the 16 x 64^2 stack, {J} rotations: {checked} argmax pixels checked")
