@@ -136,11 +136,12 @@ def class_bytes(n0, n1, n2, L0, L1, K):
 
 
 def time_steps(step, steps, warmup, ttm, torch):
+    """Milliseconds per step over ``steps`` uninstrumented steps, then the
+    per-kernel-class event timings of as many instrumented steps (the event
+    pairs around each kernel group add their own gaps, so they are kept out
+    of the step time)."""
     for _ in range(warmup):
         step()
-    torch.cuda.synchronize()
-    ttm.profile_enable(True)
-    ttm.profile_read()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -150,6 +151,11 @@ def time_steps(step, steps, warmup, ttm, torch):
     stop.record()
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(stop)
+    ttm.profile_enable(True)
+    ttm.profile_read()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
     prof = ttm.profile_read()
     ttm.profile_enable(False)
     return total_ms / steps, prof

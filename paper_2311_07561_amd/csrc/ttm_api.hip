@@ -179,6 +179,9 @@ static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refi
 // refine 3: after the first round (the refinement of refine 2, already
 // written to the outputs from the start positions), rounds on the candidates
 // whose position changed, until none moves or kRefineRounds rounds in all.
+// Most candidates move in the first round, so the second spreads each
+// candidate's neighbours over 9 blocks as the first does; the later rounds,
+// with few candidates left, over 27.
 // tensor(pos, count_dev) fills the pose scratch with C_n at the 27
 // neighbours of the listed candidates.
 template <class TensorFn>
@@ -195,7 +198,7 @@ static ttm_status refine_rounds(const Geo& g, const float* score, int order_n, i
     TTM_PROF(PC_POSE, launch_pose_solve(g, score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
                                         max_peaks, 2, w.act_pos, w.act_count, 0, image, tmpl, mask, w.tmp.pos,
                                         w.tmp.quat, w.tmp.lam, out_score ? w.tmp.score : nullptr, w.tmp.flags,
-                                        out_C ? w.tmp.C : nullptr, w.ps, stream, true, 27));
+                                        out_C ? w.tmp.C : nullptr, w.ps, stream, true, r == 1 ? 9 : 27));
     TTM_PROF(PC_POSE, launch_refine_scatter(w.act_count, w.act_idx, K, w.tmp, out_pos, out_quat, out_lambda,
                                             out_score, out_flags, out_C, w.moved, max_peaks, stream));
   }

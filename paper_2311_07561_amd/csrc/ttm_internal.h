@@ -153,9 +153,10 @@ struct PoseScratch {
   double* sbest;    // max_peaks * NB * 64: seed scan, best lambda per slot
   int* sidx;        // max_peaks * NB * 64: and its seed index
 };
-// iterated refinement (refine 3): the rounds after the first (few candidates
-// still move there, so the NCC kernel spreads each candidate's 27 neighbours
-// over 27 blocks instead of 3, trading template loads for latency)
+// iterated refinement (refine 3): the rounds after the first (fewer
+// candidates move in each, so from the third round on the NCC kernel spreads
+// each candidate's 27 neighbours over 27 blocks instead of 9, trading
+// template loads for latency)
 constexpr int kRefineRounds = 4;
 struct RefineTmp {            // one round's outputs, in compact order
   int* pos; float* quat; double* lam; float* score; int* flags; double* C;

@@ -876,18 +876,36 @@ __global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, int ngroups, c
     const float* __restrict__ base = image + ((long)(x0 - c0) * g.n1 + (x1 - c1)) * g.n2 + (x2 - c2);
     const Rot R = quat_rot(qbuf + 4 * b);
     float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, v3 = 0.0f, v4 = 0.0f;
-    for (int i = tid; i < nm; i += 1024) {
-      const unsigned pk = mlist[i];
-      const int u0 = (int)(pk & 1023u), u1 = (int)((pk >> 10) & 1023u), u2 = (int)(pk >> 20);
-      const float mv = mval[i];
-      const float gv = sample_rotated_lds(tl, L0, L1, L2, P2, P01, R, u0, u1, u2);
-      const float fv = base[u0 * rs0 + u1 * rs1 + u2];
-      const float mg = mv * gv;
-      v0 += mv;
-      v1 += mg;
-      v2 += mg * gv;
-      v3 += mv * fv;
-      v4 += mg * fv;
+    // kNccLoads of a thread's mask voxels at a time: their list entries, then
+    // their image values, are loaded before any sample waits on them.  Past
+    // the list's end a slot holds voxel 0 with weight 0 and adds nothing, so
+    // each thread's sums are those of the plain loop over its voxels.
+    constexpr int kNccLoads = 4;
+    for (int i0 = tid; i0 < nm; i0 += 1024 * kNccLoads) {
+      unsigned pk[kNccLoads];
+      float mv[kNccLoads], fv[kNccLoads];
+#pragma unroll
+      for (int j = 0; j < kNccLoads; ++j) {
+        const int i = i0 + 1024 * j;
+        pk[j] = i < nm ? mlist[i] : 0u;
+        mv[j] = i < nm ? mval[i] : 0.0f;
+      }
+#pragma unroll
+      for (int j = 0; j < kNccLoads; ++j) {
+        const int u0 = (int)(pk[j] & 1023u), u1 = (int)((pk[j] >> 10) & 1023u), u2 = (int)(pk[j] >> 20);
+        fv[j] = base[u0 * rs0 + u1 * rs1 + u2];
+      }
+#pragma unroll
+      for (int j = 0; j < kNccLoads; ++j) {
+        const int u0 = (int)(pk[j] & 1023u), u1 = (int)((pk[j] >> 10) & 1023u), u2 = (int)(pk[j] >> 20);
+        const float gv = sample_rotated_lds(tl, L0, L1, L2, P2, P01, R, u0, u1, u2);
+        const float mg = mv[j] * gv;
+        v0 += mv[j];
+        v1 += mg;
+        v2 += mg * gv;
+        v3 += mv[j] * fv[j];
+        v4 += mg * fv[j];
+      }
     }
     double v[5] = {v0, v1, v2, v3, v4};
 #pragma unroll
