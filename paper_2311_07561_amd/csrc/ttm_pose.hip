@@ -572,7 +572,44 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
   __shared__ int starts[kStarts];
   __shared__ int nstart;
   __shared__ double sel[kStarts][4];
-  if (lane == 0) {
+  // each slot's place in the order (best first, the lower lane on ties),
+  // found by all lanes at once, so that lane 0 walks the slots once instead
+  // of searching the unused ones for every start it takes; NaN slot values
+  // (a non-finite tensor) keep the search
+  __shared__ int order[64];
+  __shared__ int any_nan;
+  if (lane == 0) any_nan = 0;
+  __syncthreads();
+  {
+    int rank = 0;
+    for (int l = 0; l < 64; ++l) {
+      const double v = red[l * 6];
+      rank += (v > best) || (v == best && l < lane);
+    }
+    if (best != best) any_nan = 1;
+    else order[rank] = lane;
+  }
+  __syncthreads();
+  if (lane == 0 && !any_nan) {
+    const double cosx = 0.99619469809174553;
+    int ns = 0;
+    for (int k = 0; k < 64 && ns < kStarts; ++k) {
+      const int bl = order[k];
+      if (!(red[bl * 6] > -INFINITY)) break;
+      const int si = (int)red[bl * 6 + 1];
+      const double q[4] = {seeds[4 * si], seeds[4 * si + 1], seeds[4 * si + 2], seeds[4 * si + 3]};
+      bool far = true;
+      for (int i = 0; i < ns; ++i) {
+        const double dp = q[0] * sel[i][0] + q[1] * sel[i][1] + q[2] * sel[i][2] + q[3] * sel[i][3];
+        if (fabs(dp) > cosx) far = false;
+      }
+      if (!far) continue;
+      for (int d = 0; d < 4; ++d) sel[ns][d] = q[d];
+      starts[ns++] = si;
+    }
+    nstart = ns;
+  }
+  if (lane == 0 && any_nan) {
     const double cosx = 0.99619469809174553;
     unsigned long long used = 0ull;
     int ns = 0;
