@@ -877,7 +877,7 @@ __global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, int ngroups, c
                                                        const int* __restrict__ okbuf, const float* __restrict__ qbuf,
                                                        double* __restrict__ nccbuf) {
   __shared__ float tl[kNccLdsCap];
-  __shared__ double red[16][5];
+  __shared__ double red[16][15];
   constexpr int NB = 27;
   const int p = blockIdx.x / ngroups, grp = blockIdx.x % ngroups;
   const int gsize = (NB + ngroups - 1) / ngroups;
@@ -887,79 +887,122 @@ __global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, int ngroups, c
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int L0 = g.L0, L1 = g.L1, L2 = g.L2, nL = L0 * L1 * L2;
   const int P2 = L2 + 3, P01 = L1 * P2 + 5;
-  for (int r = wave; r < L0 * L1; r += 16) {
-    const int i0 = r / L1, i1 = r % L1;
-    for (int i2 = lane; i2 < L2; i2 += 64) tl[i0 * P01 + i1 * P2 + i2] = tmpl[r * L2 + i2];
-  }
+  fill_lds_box(tl, tmpl, L0, L1, L2, P2, P01, tid, 1024);
   __syncthreads();
   const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;
   const int rs1 = g.n2, rs0 = g.n1 * g.n2;
   const int nm = mcount[0];
-  for (int k = k_lo; k < k_hi; ++k) {
-    const long b = (long)p * NB + k;
-    // block-uniform: the neighbour's validity and w
-    if (!okbuf[b]) {
-      if (tid == 0) nccbuf[b] = -INFINITY;
-      continue;
+  // the block's neighbours in passes of up to kNccPass: one pass over the
+  // mask voxels loads each list entry once and samples it under every live
+  // neighbour's rotation (each neighbour's sums keep the voxel order of a
+  // pass of its own)
+  constexpr int kNccPass = 3;
+  constexpr int kNccLoads = 4;
+  for (int k0 = k_lo; k0 < k_hi; k0 += kNccPass) {
+    bool live[kNccPass];
+    double wk[kNccPass];
+    const float* bases[kNccPass];
+    Rot R[kNccPass];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < kNccPass; ++j) {
+      const int k = k0 + j;
+      live[j] = false;
+      wk[j] = 0.0;
+      bases[j] = image;
+      for (int i = 0; i < 9; ++i) R[j].r[i] = 0.0f;
+      if (k >= k_hi) continue;
+      // block-uniform: the neighbour's validity and w
+      const long b = (long)p * NB + k;
+      if (!okbuf[b]) {
+        if (tid == 0) nccbuf[b] = -INFINITY;
+        continue;
+      }
+      const double w = wbuf[b];
+      if (!(w > 0.0)) {
+        if (tid == 0) nccbuf[b] = 0.0;
+        continue;
+      }
+      int o0, o1, o2;
+      neighbour_offset(k, NB, o0, o1, o2);
+      const int x0 = pos[3 * p] + o0, x1 = pos[3 * p + 1] + o1, x2 = pos[3 * p + 2] + o2;
+      bases[j] = image + ((long)(x0 - c0) * g.n1 + (x1 - c1)) * g.n2 + (x2 - c2);
+      const Rot Rj = quat_rot(qbuf + 4 * b);
+      // the same matrix in every lane: kept in scalar registers
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+        R[j].r[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Rj.r[i])));
+      wk[j] = w;
+      live[j] = true;
+      any = true;
     }
-    const double w = wbuf[b];
-    if (!(w > 0.0)) {
-      if (tid == 0) nccbuf[b] = 0.0;
-      continue;
-    }
-    int o0, o1, o2;
-    neighbour_offset(k, NB, o0, o1, o2);
-    const int x0 = pos[3 * p] + o0, x1 = pos[3 * p + 1] + o1, x2 = pos[3 * p + 2] + o2;
-    const float* __restrict__ base = image + ((long)(x0 - c0) * g.n1 + (x1 - c1)) * g.n2 + (x2 - c2);
-    const Rot R = quat_rot(qbuf + 4 * b);
-    float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, v3 = 0.0f, v4 = 0.0f;
+    if (!any) continue;
+    float v[kNccPass][5];
+#pragma unroll
+    for (int j = 0; j < kNccPass; ++j)
+#pragma unroll
+      for (int i = 0; i < 5; ++i) v[j][i] = 0.0f;
     // kNccLoads of a thread's mask voxels at a time: their list entries, then
     // their image values, are loaded before any sample waits on them.  Past
     // the list's end a slot holds voxel 0 with weight 0 and adds nothing, so
     // each thread's sums are those of the plain loop over its voxels.
-    constexpr int kNccLoads = 4;
     for (int i0 = tid; i0 < nm; i0 += 1024 * kNccLoads) {
       unsigned pk[kNccLoads];
-      float mv[kNccLoads], fv[kNccLoads];
+      float mv[kNccLoads], fv[kNccPass][kNccLoads];
 #pragma unroll
-      for (int j = 0; j < kNccLoads; ++j) {
-        const int i = i0 + 1024 * j;
-        pk[j] = i < nm ? mlist[i] : 0u;
-        mv[j] = i < nm ? mval[i] : 0.0f;
+      for (int jj = 0; jj < kNccLoads; ++jj) {
+        const int i = i0 + 1024 * jj;
+        pk[jj] = i < nm ? mlist[i] : 0u;
+        mv[jj] = i < nm ? mval[i] : 0.0f;
       }
 #pragma unroll
-      for (int j = 0; j < kNccLoads; ++j) {
-        const int u0 = (int)(pk[j] & 1023u), u1 = (int)((pk[j] >> 10) & 1023u), u2 = (int)(pk[j] >> 20);
-        fv[j] = base[u0 * rs0 + u1 * rs1 + u2];
-      }
+      for (int j = 0; j < kNccPass; ++j)
 #pragma unroll
-      for (int j = 0; j < kNccLoads; ++j) {
-        const int u0 = (int)(pk[j] & 1023u), u1 = (int)((pk[j] >> 10) & 1023u), u2 = (int)(pk[j] >> 20);
-        const float gv = sample_rotated_lds(tl, L0, L1, L2, P2, P01, R, u0, u1, u2);
-        const float mg = mv[j] * gv;
-        v0 += mv[j];
-        v1 += mg;
-        v2 += mg * gv;
-        v3 += mv[j] * fv[j];
-        v4 += mg * fv[j];
+        for (int jj = 0; jj < kNccLoads; ++jj) {
+          const int u0 = (int)(pk[jj] & 1023u), u1 = (int)((pk[jj] >> 10) & 1023u), u2 = (int)(pk[jj] >> 20);
+          fv[j][jj] = live[j] ? bases[j][u0 * rs0 + u1 * rs1 + u2] : 0.0f;
+        }
+#pragma unroll
+      for (int jj = 0; jj < kNccLoads; ++jj) {
+        const int u0 = (int)(pk[jj] & 1023u), u1 = (int)((pk[jj] >> 10) & 1023u), u2 = (int)(pk[jj] >> 20);
+#pragma unroll
+        for (int j = 0; j < kNccPass; ++j) {
+          if (!live[j]) continue;
+          const float gv = sample_rotated_lds(tl, L0, L1, L2, P2, P01, R[j], u0, u1, u2);
+          const float mg = mv[jj] * gv;
+          v[j][0] += mv[jj];
+          v[j][1] += mg;
+          v[j][2] += mg * gv;
+          v[j][3] += mv[jj] * fv[j][jj];
+          v[j][4] += mg * fv[j][jj];
+        }
       }
     }
-    double v[5] = {v0, v1, v2, v3, v4};
 #pragma unroll
-    for (int i = 0; i < 5; ++i)
-      for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off);
-    if (lane == 0)
+    for (int j = 0; j < kNccPass; ++j) {
+      if (!live[j]) continue;
+      double d[5] = {v[j][0], v[j][1], v[j][2], v[j][3], v[j][4]};
 #pragma unroll
-      for (int i = 0; i < 5; ++i) red[wave][i] = v[i];
+      for (int i = 0; i < 5; ++i)
+        for (int off = 32; off > 0; off >>= 1) d[i] += __shfl_xor(d[i], off);
+      if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) red[wave][j * 5 + i] = d[i];
+    }
     __syncthreads();
     if (tid == 0) {
-      double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      for (int wv = 0; wv < 16; ++wv)
 #pragma unroll
-        for (int i = 0; i < 5; ++i) t[i] += red[wv][i];
-      const double mu = t[0] > 0.0 ? t[1] / t[0] : 0.0;
-      const double var = t[2] - mu * t[1];
-      nccbuf[b] = var > 1e-6 * (t[2] > 0.0 ? t[2] : 1.0) ? w * (t[4] - mu * t[3]) / sqrt(var) : 0.0;
+      for (int j = 0; j < kNccPass; ++j) {
+        if (!live[j]) continue;
+        double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int wv = 0; wv < 16; ++wv)
+#pragma unroll
+          for (int i = 0; i < 5; ++i) t[i] += red[wv][j * 5 + i];
+        const double mu = t[0] > 0.0 ? t[1] / t[0] : 0.0;
+        const double var = t[2] - mu * t[1];
+        nccbuf[(long)p * NB + k0 + j] = var > 1e-6 * (t[2] > 0.0 ? t[2] : 1.0) ? wk[j] * (t[4] - mu * t[3]) / sqrt(var)
+                                                                              : 0.0;
+      }
     }
     __syncthreads();
   }

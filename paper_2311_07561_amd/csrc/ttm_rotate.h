@@ -119,4 +119,30 @@ __device__ __forceinline__ float sample_rotated_lds(const float* t, int L0, int 
 }
 
 
+// Copies the L0 x L1 x L2 box src (C order) into the padded LDS layout above.
+// Each of the block's nthreads threads keeps eight loads in flight before
+// its stores, so the copy is not a chain of dependent load-store steps.  The
+// caller synchronises before the box is read.
+__device__ __forceinline__ void fill_lds_box(float* tl, const float* __restrict__ src, int L0, int L1, int L2,
+                                             int P2, int P01, int tid, int nthreads) {
+  const int nL = L0 * L1 * L2;
+  constexpr int U = 8;
+  for (int e0 = tid; e0 < nL; e0 += nthreads * U) {
+    float v[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int e = e0 + j * nthreads;
+      v[j] = e < nL ? src[e] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int e = e0 + j * nthreads;
+      if (e < nL) {
+        const int i2 = e % L2, r = e / L2;
+        tl[(r / L1) * P01 + (r % L1) * P2 + i2] = v[j];
+      }
+    }
+  }
+}
+
 }  // namespace ttm

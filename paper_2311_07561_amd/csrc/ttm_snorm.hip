@@ -178,10 +178,7 @@ __global__ void __launch_bounds__(1024) k_snorm_rot(SnormGeo g, int nchunk, int 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (LDS) {
-    for (int r = wave; r < L0 * L1; r += 16) {
-      const int i0 = r / L1, i1 = r % L1;
-      for (int i2 = lane; i2 < L2; i2 += 64) tl[i0 * P01 + i1 * P2 + i2] = slab[(long)r * L2 + i2];
-    }
+    fill_lds_box(tl, slab, L0, L1, L2, P2, P01, tid, 1024);
     __syncthreads();
   }
   const double msum = st[0], mht = st[1];
