@@ -48,13 +48,26 @@ __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F,
   __shared__ float tile[H0 * H1 * H2];
   const int tid = threadIdx.x;
   const int b0 = g.lo0 + blockIdx.z * PT0, b1 = g.lo1 + blockIdx.y * PT1, b2 = g.lo2 + blockIdx.x * PT2;
-  for (int e = tid; e < H0 * H1 * H2; e += 256) {
-    const int t2 = e % H2, t1 = (e / H2) % H1, t0 = e / (H1 * H2);
-    const int y0 = b0 - 1 + t0, y1 = b1 - 1 + t1, y2 = b2 - 1 + t2;
-    float v = -INFINITY;
-    if (y0 >= 0 && y0 < g.n0 && y1 >= 0 && y1 < g.n1 && y2 >= 0 && y2 < g.n2)
-      v = F[((long)y0 * g.n1 + y1) * g.n2 + y2];
-    tile[e] = v;
+  // the halo tile, eight loads in flight per thread: each load is
+  // unconditional (of voxel 0 outside the map) so that the compiler issues
+  // them before it waits, and the value outside the map is -inf
+  constexpr int NT = H0 * H1 * H2, U = 8;
+  for (int e0 = tid; e0 < NT; e0 += 256 * U) {
+    float v[U];
+    bool in[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int e = e0 + 256 * j;
+      const int t2 = e % H2, t1 = (e / H2) % H1, t0 = e / (H1 * H2);
+      const int y0 = b0 - 1 + t0, y1 = b1 - 1 + t1, y2 = b2 - 1 + t2;
+      in[j] = e < NT && y0 >= 0 && y0 < g.n0 && y1 >= 0 && y1 < g.n1 && y2 >= 0 && y2 < g.n2;
+      v[j] = F[in[j] ? ((long)y0 * g.n1 + y1) * g.n2 + y2 : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int e = e0 + 256 * j;
+      if (e < NT) tile[e] = in[j] ? v[j] : -INFINITY;
+    }
   }
   __shared__ unsigned long long lkeys[PT0 * PT1 * PT2 / 8];   // strict maxima: at most one per 2x2x2 cell
   __shared__ unsigned lcount, lbase;
@@ -704,7 +717,11 @@ __global__ void __launch_bounds__(1024) k_mask_list(const float* __restrict__ ma
         const int br = c0 + i;
         const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
         const int u0 = 4 * b0 + j0, u1 = 4 * b1 + j1, u2 = 4 * b2 + j2;
-        v[j] = (i < nc && u0 < L0 && u1 < L1 && u2 < L2) ? mask[(u0 * L1 + u1) * L2 + u2] : 0.0f;
+        // an unconditional load (of voxel 0 where out of range), so that the
+        // compiler issues the group's loads before it waits
+        const bool in = i < nc && u0 < L0 && u1 < L1 && u2 < L2;
+        const float m = mask[in ? (u0 * L1 + u1) * L2 + u2 : 0];
+        v[j] = in ? m : 0.0f;
       }
 #pragma unroll
       for (int j = 0; j < kLoads; ++j) {
@@ -743,13 +760,12 @@ __global__ void __launch_bounds__(1024) k_mask_list(const float* __restrict__ ma
 #pragma unroll
       for (int j = 0; j < kLoads; ++j) {
         const int i = i0 + 16 * j;
-        v[j] = 0.0f;
-        if (i < nc && ((bits_s[i] >> lane) & 1ull)) {
-          const int br = c0 + i;
-          const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
-          const int u0 = 4 * b0 + j0, u1 = 4 * b1 + j1, u2 = 4 * b2 + j2;
-          v[j] = mask[(u0 * L1 + u1) * L2 + u2];
-        }
+        const bool on = i < nc && ((bits_s[i] >> lane) & 1ull);
+        const int br = c0 + i;
+        const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
+        const int u0 = 4 * b0 + j0, u1 = 4 * b1 + j1, u2 = 4 * b2 + j2;
+        const float m = mask[on ? (u0 * L1 + u1) * L2 + u2 : 0];
+        v[j] = on ? m : 0.0f;
       }
 #pragma unroll
       for (int j = 0; j < kLoads; ++j) {
