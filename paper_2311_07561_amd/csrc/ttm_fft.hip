@@ -312,6 +312,26 @@ __global__ void __launch_bounds__(256) k_pass1(Pass1Args A, long P, int p2, int 
   const unsigned off = (unsigned)a * P32 + pu;
   float2 x[R2], F[R2], T[R2], y[R2];
   const int nt = A.nt0 + A.nt1;
+  // the template rows of entry i, loaded one entry ahead so that their
+  // latency overlaps the previous entry's transforms; each load is
+  // unconditional (element 0 of the entry where the row is absent, the value
+  // then discarded), and only the BM rows the template can occupy are loaded
+  float2 nx[R2];
+  auto load_rows = [&](int i, float2* dst) {
+    const float2* __restrict__ tb = i < A.nt0 ? A.tmpl0 + (long)i * A.tmpl_stride
+                                              : A.tmpl1 + (long)(i - A.nt0) * A.tmpl_stride;
+#pragma unroll
+    for (int b = 0; b < R2; ++b) {
+      if (b < BM) {
+        const bool ok = valid && a + R1 * b < L0;
+        const float2 v = tb[ok ? off + b * step : 0u];
+        dst[b] = ok ? v : make_float2(0.0f, 0.0f);
+      } else {
+        dst[b] = make_float2(0.0f, 0.0f);
+      }
+    }
+  };
+  load_rows(0, nx);
 #pragma unroll 1
   for (int i = 0; i < nt; ++i) {
     if (i == 0 || i == A.nt0) {
@@ -325,13 +345,9 @@ __global__ void __launch_bounds__(256) k_pass1(Pass1Args A, long P, int p2, int 
       }
       engineA<N0, PW, false>(x, F, lds, tw, pl, a);
     }
-    const float2* __restrict__ tb = i < A.nt0 ? A.tmpl0 + (long)i * A.tmpl_stride
-                                              : A.tmpl1 + (long)(i - A.nt0) * A.tmpl_stride;
 #pragma unroll
-    for (int b = 0; b < R2; ++b) {
-      x[b] = make_float2(0.0f, 0.0f);
-      if (b < BM && valid && a + R1 * b < L0) x[b] = tb[off + b * step];
-    }
+    for (int b = 0; b < R2; ++b) x[b] = nx[b];
+    if (i + 1 < nt) load_rows(i + 1, nx);
     engineA<N0, PW, false, BM>(x, T, lds, tw, pl, a);
 #pragma unroll
     for (int j = 0; j < R2; ++j) T[j] = cmulc(F[j], T[j]);
