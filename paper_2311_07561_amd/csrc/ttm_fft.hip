@@ -503,13 +503,16 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
     const int e = tid + 256 * i;
     ld_ok[i] = e < nvalid && g.row_valid(r0 + e / H2);
   }
+  // unconditional loads (element 0 of the tile in place of a skipped one, the
+  // value then discarded), so that no branch sits between them
   float2 pf[PF];
   {
     const float2* Hn = A.H + (long)pair_of(0) * A.pstride + r0 * P2;
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int e = tid + 256 * i;
-      pf[i] = ld_ok[i] ? Hn[e] : make_float2(0.0f, 0.0f);
+      const float2 v = Hn[ld_ok[i] ? e : 0];
+      pf[i] = ld_ok[i] ? v : make_float2(0.0f, 0.0f);
     }
   }
 #pragma unroll 1
@@ -527,7 +530,8 @@ __global__ void __launch_bounds__(256) k_pass3(P3Geo g, Pass3Args A) {
 #pragma unroll
       for (int i = 0; i < PF; ++i) {
         const int e = tid + 256 * i;
-        pf[i] = ld_ok[i] ? Hn[e] : make_float2(0.0f, 0.0f);
+        const float2 v = Hn[ld_ok[i] ? e : 0];
+        pf[i] = ld_ok[i] ? v : make_float2(0.0f, 0.0f);
       }
     }
     float2 z[R2], o[R2];
