@@ -18,7 +18,11 @@
  * - Every call is asynchronous on `stream`: arguments are validated on the
  *   host before anything is enqueued, and a non-OK status means nothing was
  *   enqueued (TTM_E_HIP: a launch failed part-way; the stream's work is then
- *   undefined).  Host arrays are only read during the call.
+ *   undefined).  Host arrays are only read during the call: the calls that
+ *   copy host arrays to the device (the tensor builds, ttm_snorm,
+ *   ttm_score_backward, tm_classical) wait for those copies, and so for the
+ *   stream's earlier work, before they return, and cannot be recorded into a
+ *   graph.
  * - Correlation is circular: (f * g)(x) = sum_u f((x + u - c) mod N) g(u)
  *   (Section 2, eq. "correlation", with the template measured from its
  *   centre).  Outputs are defined in the VALID region, the positions whose

@@ -346,6 +346,10 @@ ttm_status ttm_build_tensor_template(const float* tmpl, const float* mask, ttm_d
   BuildWs w = build_layout(c, n_rot, K);
   TTM_TRY(hipMemcpyAsync(w.quats, quats_host, sizeof(float) * 4 * (size_t)n_rot, hipMemcpyHostToDevice, stream));
   TTM_TRY(hipMemcpyAsync(w.weights, weights_host, sizeof(double) * (size_t)n_rot, hipMemcpyHostToDevice, stream));
+  // the host arrays are read before this call returns, so the caller may
+  // free or reuse them at once: an asynchronous copy from pageable memory may
+  // otherwise be staged after the caller has released it
+  TTM_TRY(hipStreamSynchronize(stream));
   TTM_PROF(PC_BUILD, launch_rot_stats(tmpl, mask, L.n0, L.n1, L.n2, w.quats, n_rot, w.rstats, stream));
   TTM_PROF(PC_BUILD, launch_build_coef(w.quats, w.weights, w.rstats, n_rot, order_n, w.coef, stream));
   TTM_PROF(PC_BUILD, launch_build_accum(tmpl, mask, L.n0, L.n1, L.n2, w.quats, w.rstats, w.coef, n_rot, K, out_components,
@@ -1068,6 +1072,10 @@ ttm_status ttm_build_tensor_template_2d(const float* tmpl, const float* mask, in
   float* comps3 = c.take<float>((size_t)K3 * L1 * L2);
   TTM_TRY(hipMemcpyAsync(zd, z_host, sizeof(float) * 2 * (size_t)n_rot, hipMemcpyHostToDevice, stream));
   TTM_TRY(hipMemcpyAsync(w.weights, weights_host, sizeof(double) * (size_t)n_rot, hipMemcpyHostToDevice, stream));
+  // the host arrays are read before this call returns, so the caller may
+  // free or reuse them at once: an asynchronous copy from pageable memory may
+  // otherwise be staged after the caller has released it
+  TTM_TRY(hipStreamSynchronize(stream));
   TTM_PROF(PC_BUILD, launch_planar_quats(zd, n_rot, w.quats, stream));
   TTM_PROF(PC_BUILD, launch_rot_stats(tmpl, mask, 1, L1, L2, w.quats, n_rot, w.rstats, stream));
   TTM_PROF(PC_BUILD, launch_build_coef(w.quats, w.weights, w.rstats, n_rot, order_n, w.coef, stream));
@@ -1241,6 +1249,10 @@ ttm_status ttm_snorm(const float* image, ttm_dims N, const float* tmpl, const fl
   g.n_pad = snorm_pad(n_rot);
   TTM_TRY(hipMemcpyAsync(w.quats, quats_host, sizeof(float) * 4 * (size_t)n_rot, hipMemcpyHostToDevice, stream));
   TTM_TRY(hipMemcpyAsync(w.weights, weights_host, sizeof(double) * (size_t)n_rot, hipMemcpyHostToDevice, stream));
+  // the host arrays are read before this call returns, so the caller may
+  // free or reuse them at once: an asynchronous copy from pageable memory may
+  // otherwise be staged after the caller has released it
+  TTM_TRY(hipStreamSynchronize(stream));
   TTM_PROF(PC_SNORM, launch_snorm(g, image, tmpl, mask, w.quats, w.weights, n_rot, order_n, pos, count, lambda, w,
                                   out_rho, out_D, out_flags, stream));
   return TTM_OK;
@@ -1356,6 +1368,10 @@ ttm_status ttm_score_backward(const float* image, ttm_dims N, const float* tmpl,
                            stream));
     TTM_TRY(hipMemcpyAsync(w.b.weights, weights_host, sizeof(double) * (size_t)n_rot, hipMemcpyHostToDevice,
                            stream));
+    // the host arrays are read before this call returns, so the caller may
+    // free or reuse them at once: an asynchronous copy from pageable memory may
+    // otherwise be staged after the caller has released it
+    TTM_TRY(hipStreamSynchronize(stream));
     TTM_PROF(PC_BUILD, launch_rot_stats(tmpl, mask, L.n0, L.n1, L.n2, w.b.quats, n_rot, w.b.rstats, stream));
     TTM_PROF(PC_BUILD, launch_build_coef(w.b.quats, w.b.weights, w.b.rstats, n_rot, order_n, w.b.coef, stream));
     TTM_PROF(PC_BUILD, launch_fill_f32(out_grad_tmpl, nL, 0.0f, stream));
@@ -1389,6 +1405,10 @@ ttm_status tm_classical(const float* image, ttm_dims N, const float* tmpl, const
   ClassWs w = class_layout(c, g, n_rot);
   const long half = g.half();
   TTM_TRY(hipMemcpyAsync(w.quats, quats_host, sizeof(float) * 4 * (size_t)n_rot, hipMemcpyHostToDevice, stream));
+  // the host arrays are read before this call returns, so the caller may
+  // free or reuse them at once: an asynchronous copy from pageable memory may
+  // otherwise be staged after the caller has released it
+  TTM_TRY(hipStreamSynchronize(stream));
   TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream));
   // w(x) from the two masked moments
   TTM_CALL(bank_forward(g, mask, 1, w.bbank, stream));
