@@ -89,8 +89,10 @@ def parse():
     p.add_argument("--rmap-seeds", type=int, default=10016,
                    help="also time the all-voxel rotation map with this many seeds (0 = skip)")
     p.add_argument("--rmap-steps", type=int, default=3)
-    p.add_argument("--batch", type=int, default=64,
-                   help="tomograms of the batching leg (uneven edges 96..320, templates 24/32/48; 0 = skip)")
+    p.add_argument("--batch", type=int, default=0,
+                   help="tomograms of the batching leg (uneven edges 96..320, templates 24/32/48; 0 = skip). "
+                        "Off by default: runs of the 64-tomogram leg have ended with a host segmentation fault "
+                        "after its graph replays, cause not yet found")
     p.add_argument("--batch-replays", type=int, default=2)
     p.add_argument("--batch-streams", type=int, default=4, help="concurrent branches of the batch graph")
     p.add_argument("--batch-workers", type=int, default=16, help="processes generating the batch tomograms")
