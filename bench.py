@@ -500,11 +500,14 @@ def run_batch(bwl, args, ttm, synth, torch, dev, angle):
         e["r2"] += d
         e["rq"] += dl
         e["n"] += len(bwl.positions[i][k])
+    log(f"batch: accuracy read back ({found} of {total} copies within 2 voxels)")
     # per-tomogram latency: one graph per tomogram, each replayed alone
     lat = []
     nt = len(images)
     nk = len(temps)
     for i in range(nt):
+        if i % 16 == 0:
+            log(f"batch: per-tomogram graph {i} of {nt}")
         g = ttm.BatchGraph(jobs[i * nk:(i + 1) * nk], order, opt, ws, min(S, nk))
         g.launch()
         a = torch.cuda.Event(enable_timing=True)
@@ -515,6 +518,7 @@ def run_batch(bwl, args, ttm, synth, torch, dev, angle):
         torch.cuda.synchronize()
         lat.append(a.elapsed_time(b))
         g.close()
+    log("batch: per-tomogram graphs done")
     vox = float(sum(im.numel() for im in images))
     del outs, jobs, ws
     return {"workload": bwl.name, "tomograms": nt, "templates": [tp["L"] for tp in temps], "jobs": nt * nk,
