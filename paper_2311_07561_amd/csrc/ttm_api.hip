@@ -1094,20 +1094,25 @@ ttm_status ttm_build_tensor_template_2d(const float* tmpl, const float* mask, in
 }
 
 struct Match2dWs {
-  CorrWs cw; PoseWs pw; float* comps3; int* cand; float* cand_score; int* list; int* idx; int* total;
+  CorrWs cw; PoseWs pw; PeakWs pk; float* comps3; int* cand; float* cand_score; int* list; int* idx; int* total;
   int* pos3; float* quat3; double* lam3; float* score3; int* flags3; double* C3;
 };
 // the pose scratch serves all B P candidates of the stack at once; the peak
-// scratch inside it (sized for the stack) is reused plane after plane
-static Match2dWs match2d_layout(Carve& c, const Geo& gs, int B, int order_n, const ttm_options* opt) {
+// search of every plane runs at once on B copies of the peak scratch
+static Match2dWs match2d_layout(Carve& c, const Geo& gs, const Geo& gp, int B, int order_n,
+                                const ttm_options* opt) {
   const int K3 = ttm_num_components(order_n);
   const size_t P = (size_t)opt->max_peaks, BP = (size_t)B * P;
   Match2dWs m;
   m.cw = corr_layout(c, gs, order_n + 1);
   m.pw = pose_layout(c, gs, (int)BP, K3, opt->refine, opt->n_seeds);
+  m.pk.hist = c.take<unsigned>((size_t)kHistBins * B);
+  m.pk.ctrl = c.take<unsigned>((size_t)kPeakCtrlWords * B);
+  m.pk.allc = c.take<unsigned long long>((size_t)peaks_bigcap(gp) * B);
+  m.pk.cand = c.take<unsigned long long>((size_t)kCandCap * B);
   m.comps3 = c.take<float>((size_t)K3 * gs.L1 * gs.L2);
   m.cand = c.take<int>(BP * 3);
-  m.cand_score = c.take<float>(P);
+  m.cand_score = c.take<float>(BP);
   m.list = c.take<int>(BP * 3);
   m.idx = c.take<int>(BP);
   m.total = c.take<int>(1);
@@ -1129,7 +1134,7 @@ size_t ttm_match_2d_workspace_bytes(int32_t B, int32_t n1, int32_t n2, int32_t L
   if (!planar_box_ok(L1, L2) || !image_dims_ok(N) || !fits(L, N)) return 0;
   if ((long)B * opt->max_peaks > kPlanarMaxCandidates) return 0;
   Carve c(nullptr);
-  match2d_layout(c, make_geo(N, L), B, order_n, opt);
+  match2d_layout(c, make_geo(N, L), make_geo(ttm_dims{1, n1, n2}, L), B, order_n, opt);
   return c.size();
 }
 
@@ -1151,19 +1156,17 @@ ttm_status ttm_match_2d(const float* images, int32_t B, int32_t n1, int32_t n2, 
   Geo gs = make_geo(N, L);
   const Geo gp = make_geo(ttm_dims{1, n1, n2}, L);
   Carve c(ws);
-  Match2dWs m = match2d_layout(c, gs, B, order_n, opt);
+  Match2dWs m = match2d_layout(c, gs, gp, B, order_n, opt);
   PoseWs& w = m.pw;
   const int K2 = order_n + 1;
   TTM_CALL(correlate_into(gs, order_n, K2, images, static_cast<const float2*>(bank), mask, opt->eps_v, out_score,
                           out_w, m.cw, stream, nullptr, nullptr, true));
   TTM_PROF(PC_POSE, launch_planar_embed(components, planar_idx(order_n), K2, K3, (long)L1 * L2, m.comps3, stream));
-  // candidates plane by plane (the suppression and the count are per image)
-  const long V2 = (long)n1 * n2;
+  // the candidates of every plane at once (the suppression and the count are
+  // per image)
   const int P = opt->max_peaks, BP = B * P;
-  PeakWs pk{w.hist, w.ctrl, w.allc, w.cand};
-  for (int b = 0; b < B; ++b)
-    TTM_PROF(PC_PEAKS, launch_peaks(gp, out_score + b * V2, opt->threshold, opt->min_dist, P, pk,
-                                    m.cand + (long)b * P * 3, m.cand_score, out_count + 2 * b, stream));
+  TTM_PROF(PC_PEAKS, launch_peaks(gp, out_score, opt->threshold, opt->min_dist, P, m.pk, m.cand, m.cand_score,
+                                  out_count, stream, B));
   TTM_PROF(PC_POSE, launch_planar_compact(B, P, out_count, m.cand, m.list, m.idx, m.total, stream));
   // the poses of all planes' candidates at once, on the stack; the refinement
   // neighbourhood stays inside each plane

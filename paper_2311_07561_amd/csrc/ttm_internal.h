@@ -135,9 +135,15 @@ struct PeakWs {
 long peaks_bigcap(const Geo& g);  // V/8 + 1024 >= the number of strict 26-neighbour maxima
 constexpr int kHistBins = 32768;
 constexpr int kCandCap = 16384;
+constexpr int kPeakCtrlWords = 16;
+// planes > 1: `planes` maps of g's extents stored one after another (the
+// planes of a stack), each searched on its own; the workspace holds planes
+// copies of each buffer (kHistBins bins, kPeakCtrlWords control words,
+// peaks_bigcap(g) and kCandCap keys) and the outputs are max_peaks x 3
+// positions, max_peaks scores and 2 count words per map
 hipError_t launch_peaks(const Geo& g, const float* score, float threshold, float min_dist,
                         int max_peaks, const PeakWs& w, int* out_pos, float* out_score,
-                        int* out_count, hipStream_t s);
+                        int* out_count, hipStream_t s, int planes = 1);
 struct PoseScratch {
   double* seeds;  // n_seeds * 4: the S^3 seed points
   double* C;      // max_peaks * NB * K

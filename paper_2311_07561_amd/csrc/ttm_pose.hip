@@ -43,11 +43,17 @@ __device__ __forceinline__ unsigned long long peak_key(float v, long lin) {
 constexpr int PT0 = 4, PT1 = 8, PT2 = 64;
 __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F, PeakGeo g, float threshold,
                                                     unsigned* __restrict__ ctrl,
-                                                    unsigned long long* __restrict__ allc, long bigcap) {
+                                                    unsigned long long* __restrict__ allc, long bigcap,
+                                                    int ztiles, long fplane) {
   constexpr int H0 = PT0 + 2, H1 = PT1 + 2, H2 = PT2 + 2;
   __shared__ float tile[H0 * H1 * H2];
   const int tid = threadIdx.x;
-  const int b0 = g.lo0 + blockIdx.z * PT0, b1 = g.lo1 + blockIdx.y * PT1, b2 = g.lo2 + blockIdx.x * PT2;
+  // several maps (planes of a stack) at once: blockIdx.z = plane * ztiles + tile
+  const int plane = blockIdx.z / ztiles, bz = blockIdx.z % ztiles;
+  F += plane * fplane;
+  ctrl += kPeakCtrlWords * plane;
+  allc += bigcap * plane;
+  const int b0 = g.lo0 + bz * PT0, b1 = g.lo1 + blockIdx.y * PT1, b2 = g.lo2 + blockIdx.x * PT2;
   // the halo tile, eight loads in flight per thread: each load is
   // unconditional (of voxel 0 outside the map) so that the compiler issues
   // them before it waits, and the value outside the map is -inf
@@ -118,6 +124,10 @@ __global__ void __launch_bounds__(1024) k_peaks_hist(const unsigned* __restrict_
                                                      unsigned* __restrict__ hist) {
   __shared__ unsigned lh[kHistBins];
   const int tid = threadIdx.x;
+  const int plane = blockIdx.y;
+  ctrl += kPeakCtrlWords * plane;
+  allc += bigcap * plane;
+  hist += (long)kHistBins * plane;
   for (int i = tid; i < kHistBins; i += 1024) lh[i] = 0u;
   __syncthreads();
   const long total = min((long)ctrl[PK_TOTAL], bigcap);
@@ -135,6 +145,8 @@ __global__ void __launch_bounds__(1024) k_peaks_hist(const unsigned* __restrict_
 // round r: the smallest bin b with sum_{k >= b} hist[k] <= cap
 __global__ void __launch_bounds__(1024) k_peaks_select(const unsigned* __restrict__ hist,
                                                        unsigned* __restrict__ ctrl, int round, unsigned cap) {
+  hist += (long)kHistBins * blockIdx.x;
+  ctrl += kPeakCtrlWords * blockIdx.x;
   if (round == 2 && ctrl[PK_REDO] == 0u) return;
   __shared__ unsigned part[1024];
   constexpr int per = kHistBins / 1024;
@@ -174,6 +186,10 @@ __global__ void __launch_bounds__(256) k_peaks_gather(unsigned* __restrict__ ctr
                                                       const unsigned long long* __restrict__ allc, long bigcap,
                                                       unsigned long long* __restrict__ cand, int round,
                                                       unsigned cap) {
+  const int plane = blockIdx.y;
+  ctrl += kPeakCtrlWords * plane;
+  allc += bigcap * plane;
+  cand += (long)kCandCap * plane;
   if (round == 2 && ctrl[PK_REDO] == 0u) return;
   const unsigned bmin = ctrl[round == 1 ? PK_B1 : PK_B2];
   unsigned* cnt = &ctrl[round == 1 ? PK_CNT1 : PK_CNT2];
@@ -200,6 +216,8 @@ __device__ __forceinline__ void decode_lin(unsigned long long key, int n1, int n
 template <int CAP>
 __global__ void __launch_bounds__(1024) k_peaks_sort(const unsigned* __restrict__ ctrl,
                                                      unsigned long long* __restrict__ cand, int round) {
+  ctrl += kPeakCtrlWords * blockIdx.x;
+  cand += (long)kCandCap * blockIdx.x;
   if (round == 2 && ctrl[PK_REDO] == 0u) return;
   __shared__ unsigned long long keys[CAP];
   const int tid = threadIdx.x;
@@ -237,6 +255,12 @@ __global__ void __launch_bounds__(64) k_peaks_nms(PeakGeo g, unsigned* __restric
                                                   unsigned cap, float min_dist, int max_peaks,
                                                   int* __restrict__ out_pos, float* __restrict__ out_score,
                                                   int* __restrict__ out_count) {
+  const int plane = blockIdx.x;
+  ctrl += kPeakCtrlWords * plane;
+  cand += (long)kCandCap * plane;
+  out_pos += 3L * max_peaks * plane;
+  out_score += (long)max_peaks * plane;
+  out_count += 2 * plane;
   if (round == 2 && ctrl[PK_REDO] == 0u) return;
   __shared__ int acc_pos[3 * 4096];
   const int lane = threadIdx.x;
@@ -304,7 +328,7 @@ long peaks_bigcap(const Geo& g) { return g.vol() / 8 + 1024; }
 
 hipError_t launch_peaks(const Geo& gg, const float* score, float threshold, float min_dist,
                         int max_peaks, const PeakWs& w, int* out_pos, float* out_score,
-                        int* out_count, hipStream_t s) {
+                        int* out_count, hipStream_t s, int planes) {
   PeakGeo g;
   g.n0 = gg.n0; g.n1 = gg.n1; g.n2 = gg.n2;
   g.lo0 = gg.c0; g.hi0 = gg.n0 - gg.L0 + gg.c0;
@@ -312,22 +336,26 @@ hipError_t launch_peaks(const Geo& gg, const float* score, float threshold, floa
   g.lo2 = gg.c2; g.hi2 = gg.n2 - gg.L2 + gg.c2;
   const long bigcap = peaks_bigcap(gg);
   hipError_t e;
-  if ((e = launch_fill_i32(reinterpret_cast<int*>(w.hist), kHistBins, 0, s)) != hipSuccess) return e;
-  if ((e = launch_fill_i32(reinterpret_cast<int*>(w.ctrl), 16, 0, s)) != hipSuccess) return e;
+  const unsigned P = (unsigned)planes;
+  if ((e = launch_fill_i32(reinterpret_cast<int*>(w.hist), (long)kHistBins * planes, 0, s)) != hipSuccess) return e;
+  if ((e = launch_fill_i32(reinterpret_cast<int*>(w.ctrl), (long)kPeakCtrlWords * planes, 0, s)) != hipSuccess)
+    return e;
   const int e0 = g.hi0 - g.lo0 + 1, e1 = g.hi1 - g.lo1 + 1, e2 = g.hi2 - g.lo2 + 1;
-  dim3 sgrid((e2 + PT2 - 1) / PT2, (e1 + PT1 - 1) / PT1, (e0 + PT0 - 1) / PT0);
-  hipLaunchKernelGGL(k_peaks_scan, sgrid, dim3(256), 0, s, score, g, threshold, w.ctrl, w.allc, bigcap);
-  hipLaunchKernelGGL(k_peaks_hist, dim3(kHistBlocks), dim3(1024), 0, s, w.ctrl, w.allc, bigcap, w.hist);
+  const int ztiles = (e0 + PT0 - 1) / PT0;
+  dim3 sgrid((e2 + PT2 - 1) / PT2, (e1 + PT1 - 1) / PT1, (unsigned)ztiles * P);
+  hipLaunchKernelGGL(k_peaks_scan, sgrid, dim3(256), 0, s, score, g, threshold, w.ctrl, w.allc, bigcap, ztiles,
+                     gg.vol());
+  hipLaunchKernelGGL(k_peaks_hist, dim3(kHistBlocks, P), dim3(1024), 0, s, w.ctrl, w.allc, bigcap, w.hist);
   constexpr unsigned cap1 = 2048, cap2 = kCandCap;
   for (int round = 1; round <= 2; ++round) {
     const unsigned cap = round == 1 ? cap1 : cap2;
-    hipLaunchKernelGGL(k_peaks_select, dim3(1), dim3(1024), 0, s, w.hist, w.ctrl, round, cap);
-    hipLaunchKernelGGL(k_peaks_gather, dim3(256), dim3(256), 0, s, w.ctrl, w.allc, bigcap, w.cand, round, cap);
+    hipLaunchKernelGGL(k_peaks_select, dim3(P), dim3(1024), 0, s, w.hist, w.ctrl, round, cap);
+    hipLaunchKernelGGL(k_peaks_gather, dim3(256, P), dim3(256), 0, s, w.ctrl, w.allc, bigcap, w.cand, round, cap);
     if (round == 1)
-      hipLaunchKernelGGL(k_peaks_sort<cap1>, dim3(1), dim3(1024), 0, s, w.ctrl, w.cand, round);
+      hipLaunchKernelGGL(k_peaks_sort<cap1>, dim3(P), dim3(1024), 0, s, w.ctrl, w.cand, round);
     else
-      hipLaunchKernelGGL(k_peaks_sort<cap2>, dim3(1), dim3(1024), 0, s, w.ctrl, w.cand, round);
-    hipLaunchKernelGGL(k_peaks_nms, dim3(1), dim3(64), 0, s, g, w.ctrl, w.cand, round, cap, min_dist, max_peaks,
+      hipLaunchKernelGGL(k_peaks_sort<cap2>, dim3(P), dim3(1024), 0, s, w.ctrl, w.cand, round);
+    hipLaunchKernelGGL(k_peaks_nms, dim3(P), dim3(64), 0, s, g, w.ctrl, w.cand, round, cap, min_dist, max_peaks,
                        out_pos, out_score, out_count);
   }
   return hipGetLastError();
