@@ -486,20 +486,43 @@ __global__ void __launch_bounds__(256) k_pose_tensor(PoseGeo g, const float* __r
   const double var = block_sum(s2, sh);
   const double floor_v = (double)eps_v * msum * img_stats[1];
   const double w = var > floor_v ? 1.0 / sqrt(var) : 0.0;
-  for (int k0 = 0; k0 < K; k0 += kTensorChunk) {
-    const int kc = min(kTensorChunk, K - k0);
+  // a planar stack: only the entries (n - k, k, 0, 0), at packed index
+  // C(k + 2, 3), can be non-zero; the others are written as zeros
+  int Kc = K;
+  if (g.planar) {
+    Kc = 0;
+    while ((Kc + 1) * (Kc + 2) * (Kc + 3) / 6 < K) ++Kc;
+    ++Kc;
+    for (int e = tid; e < K; e += 256) {
+      bool on = false;
+      for (int i = 0; i < Kc; ++i) on = on || e == i * (i + 1) * (i + 2) / 6;
+      if (!on) Cbuf[(long)b * K + e] = 0.0;
+    }
+  }
+  auto comp_of = [&](int i) { return g.planar ? i * (i + 1) * (i + 2) / 6 : i; };
+  for (int k0 = 0; k0 < Kc; k0 += kTensorChunk) {
+    const int kc = min(kTensorChunk, Kc - k0);
     double acc[kTensorChunk];
 #pragma unroll
     for (int i = 0; i < kTensorChunk; ++i) acc[i] = 0.0;
-    for (int u = tid; u < nL; u += 256) {
-      const double v = img_at(u);
-      const float* cu = comps + (long)k0 * nL + u;
+    if (g.planar) {
+      for (int u = tid; u < nL; u += 256) {
+        const double v = img_at(u);
 #pragma unroll
-      for (int i = 0; i < kTensorChunk; ++i)
-        if (i < kc) acc[i] += v * (double)cu[(long)i * nL];
+        for (int i = 0; i <= kPlanarMaxOrder; ++i)
+          if (i < kc) acc[i] += v * (double)comps[(long)(i * (i + 1) * (i + 2) / 6) * nL + u];
+      }
+    } else {
+      for (int u = tid; u < nL; u += 256) {
+        const double v = img_at(u);
+        const float* cu = comps + (long)k0 * nL + u;
+#pragma unroll
+        for (int i = 0; i < kTensorChunk; ++i)
+          if (i < kc) acc[i] += v * (double)cu[(long)i * nL];
+      }
     }
     block_sum_chunk(acc, kc, sh);
-    if (tid < kc) Cbuf[(long)b * K + k0 + tid] = acc[0] * w;
+    if (tid < kc) Cbuf[(long)b * K + comp_of(k0 + tid)] = acc[0] * w;
   }
   if (tid == 0) {
     okbuf[b] = 1;
@@ -709,6 +732,123 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
     lambuf[b] = red[bl * 6];
     flagbuf[b] = red[bl * 6 + 5] != 0.0 ? TTM_POSE_NOT_CONVERGED : 0;
   }
+}
+
+// The dominant eigenpair of a planar tensor (a stack of planes: every
+// rotation is about axis 0, the quaternion (a, b, 0, 0) with (a, b) the unit
+// complex number of half the angle, and only the volume entries
+// (n - k, k, 0, 0), at packed index C(k + 2, 3), are non-zero).  On the unit
+// circle phi(psi) = sum_k C(n, k) C_k cos^(n-k) psi sin^k psi; psi in [0, pi)
+// covers every rotation once.  One wavefront per tensor, in float64:
+// kPlanarScan samples psi_j = (j + 1/2) pi / kPlanarScan (lane l takes
+// j = l, l + 64, ..., stepping its (cos, sin) by one complex product), the
+// best sample (lowest j on ties); then kPlanarZoom parallel zoom levels, each
+// sampling 64 points evenly over [c - h, c + h] around the best point c so
+// far and narrowing h to the sample spacing (h / 31.5), which shrinks the
+// bracket of one scan step to below 1e-12 rad.
+constexpr int kPlanarScan = 4096;
+constexpr int kPlanarZoom = 6;
+template <int N>
+__device__ __forceinline__ double planar_phi(const double (&a)[N + 1], double c, double s) {
+  double cp[N + 1], sp[N + 1];
+  cp[0] = sp[0] = 1.0;
+#pragma unroll
+  for (int e = 1; e <= N; ++e) {
+    cp[e] = cp[e - 1] * c;
+    sp[e] = sp[e - 1] * s;
+  }
+  double v = 0.0;
+#pragma unroll
+  for (int k = 0; k <= N; ++k) v += a[k] * cp[N - k] * sp[k];
+  return v;
+}
+
+// wave argmax of (v, key): the larger v, the lower key on ties; every lane
+// ends with the winner
+__device__ __forceinline__ void wave_argmax(double& v, int& key) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off);
+    const int ok = __shfl_xor(key, off);
+    if (ov > v || (ov == v && ok < key)) {
+      v = ov;
+      key = ok;
+    }
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(64) k_planar_eig(const double* __restrict__ Cbuf, const int* __restrict__ okbuf,
+                                                  const int* __restrict__ count_dev, int count_host, int NB,
+                                                  float* __restrict__ qbuf, double* __restrict__ lambuf,
+                                                  int* __restrict__ flagbuf) {
+  constexpr int K = (N + 1) * (N + 2) * (N + 3) / 6;
+  const int b = blockIdx.x;
+  const int p = b / NB;
+  const int count = count_dev ? count_dev[0] : count_host;
+  if (p >= count) return;
+  const int lane = threadIdx.x;
+  if (!okbuf[b]) {
+    if (lane == 0) {
+      lambuf[b] = -INFINITY;
+      flagbuf[b] = 0;
+    }
+    return;
+  }
+  double a[N + 1];
+#pragma unroll
+  for (int k = 0; k <= N; ++k) {
+    double binom = 1.0;
+    for (int i = 1; i <= k; ++i) binom = binom * (N - k + i) / i;
+    a[k] = binom * Cbuf[(long)b * K + k * (k + 1) * (k + 2) / 6];
+  }
+  const double pi = 3.14159265358979323846;
+  const double step = pi / kPlanarScan;
+  // scan: lane l at psi_l = (l + 1/2) step, advanced by 64 steps per sample
+  double c, s, dc, ds;
+  sincos((lane + 0.5) * step, &s, &c);
+  sincos(64.0 * step, &ds, &dc);
+  double best = -INFINITY;
+  int bj = 0;
+  for (int j = lane; j < kPlanarScan; j += 64) {
+    const double v = planar_phi<N>(a, c, s);
+    if (v > best) {
+      best = v;
+      bj = j;
+    }
+    const double cn = c * dc - s * ds;
+    s = s * dc + c * ds;
+    c = cn;
+  }
+  wave_argmax(best, bj);
+  // zoom: the best point so far stays a candidate, so lambda never drops
+  double centre = (bj + 0.5) * step, h = step;
+  sincos(centre, &s, &c);
+  best = planar_phi<N>(a, c, s);
+  for (int lev = 0; lev < kPlanarZoom; ++lev) {
+    const double x = centre + (lane - 31.5) * (h / 31.5);
+    sincos(x, &s, &c);
+    double v = planar_phi<N>(a, c, s);
+    int key = lane;
+    wave_argmax(v, key);
+    if (v > best) {
+      best = v;
+      centre = centre + (key - 31.5) * (h / 31.5);
+    }
+    h = h / 31.5;
+  }
+  if (lane != 0) return;
+  double za, zb;
+  sincos(centre, &zb, &za);
+  if (za < 0.0 || (za == 0.0 && zb < 0.0)) {
+    za = -za;
+    zb = -zb;
+  }
+  qbuf[4 * b] = (float)za;
+  qbuf[4 * b + 1] = (float)zb;
+  qbuf[4 * b + 2] = 0.0f;
+  qbuf[4 * b + 3] = 0.0f;
+  lambuf[b] = best;
+  flagbuf[b] = 0;
 }
 
 // The voxels of the mask box with m(u) != 0, packed as u0 | u1 << 10 | u2 << 20
@@ -1226,10 +1366,30 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
   const PoseGeo g = make_posegeo(gg);
   const int K = num_components(order_n);
   const int NB = refine ? 27 : 1;
-  if (!reuse_tables)
+  if (!reuse_tables && !g.planar)
     hipLaunchKernelGGL(k_seed_table, dim3((n_seeds + 255) / 256), dim3(256), 0, s, n_seeds, ps.seeds);
   const dim3 eg((unsigned)(max_peaks * NB));
-  switch (order_n) {
+  if (g.planar) {
+    switch (order_n) {
+      case 2:
+        hipLaunchKernelGGL(k_planar_eig<2>, eg, dim3(64), 0, s, ps.C, ps.ok, count_dev, count_host, NB, ps.q,
+                           ps.lam, ps.flags);
+        break;
+      case 4:
+        hipLaunchKernelGGL(k_planar_eig<4>, eg, dim3(64), 0, s, ps.C, ps.ok, count_dev, count_host, NB, ps.q,
+                           ps.lam, ps.flags);
+        break;
+      case 6:
+        hipLaunchKernelGGL(k_planar_eig<6>, eg, dim3(64), 0, s, ps.C, ps.ok, count_dev, count_host, NB, ps.q,
+                           ps.lam, ps.flags);
+        break;
+      case 8:
+        hipLaunchKernelGGL(k_planar_eig<8>, eg, dim3(64), 0, s, ps.C, ps.ok, count_dev, count_host, NB, ps.q,
+                           ps.lam, ps.flags);
+        break;
+      default: return hipErrorInvalidValue;
+    }
+  } else switch (order_n) {
     case 2:
       hipLaunchKernelGGL(k_seed_scan<2>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
                          n_seeds, ps.sbest, ps.sidx);
