@@ -1095,7 +1095,7 @@ ttm_status ttm_build_tensor_template_2d(const float* tmpl, const float* mask, in
 
 struct Match2dWs {
   CorrWs cw; PoseWs pw; PeakWs pk; float* comps3; int* cand; float* cand_score; int* list; int* idx; int* total;
-  int* pos3; float* quat3; double* lam3; float* score3; int* flags3; double* C3;
+  int* pos3; float* quat3; double* lam3; float* score3; int* flags3;
 };
 // the pose scratch serves all B P candidates of the stack at once; the peak
 // search of every plane runs at once on B copies of the peak scratch
@@ -1121,7 +1121,6 @@ static Match2dWs match2d_layout(Carve& c, const Geo& gs, const Geo& gp, int B, i
   m.lam3 = c.take<double>(BP);
   m.score3 = c.take<float>(BP);
   m.flags3 = c.take<int>(BP);
-  m.C3 = c.take<double>(BP * (size_t)K3);
   return m;
 }
 
@@ -1177,14 +1176,14 @@ ttm_status ttm_match_2d(const float* images, int32_t B, int32_t n1, int32_t n2, 
                                        m.total, 0, w.ps, stream));
   TTM_PROF(PC_POSE, launch_pose_solve(gs, out_score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol, BP, rf,
                                       m.list, m.total, 0, images, tmpl, mask, m.pos3, m.quat3, m.lam3, m.score3,
-                                      m.flags3, m.C3, w.ps, stream));
+                                      m.flags3, nullptr, w.ps, stream));
   if (opt->refine == 3) {
     auto tensor = [&](const int* pos, const int* cnt) {
       return launch_pose_tensor(gs, images, m.comps3, mask, order_n, w.stats, opt->eps_v, BP, 2, pos, cnt, 0, w.ps,
                                 stream);
     };
     TTM_CALL(refine_rounds(gs, out_score, order_n, K3, opt, BP, m.total, 0, m.list, images, tmpl, mask, m.pos3,
-                           m.quat3, m.lam3, m.score3, m.flags3, m.C3, w, tensor, stream));
+                           m.quat3, m.lam3, m.score3, m.flags3, nullptr, w, tensor, stream));
   }
   TTM_PROF(PC_POSE, launch_planar_scatter(BP, m.total, m.idx, m.pos3, m.quat3, m.lam3, m.score3, m.flags3, out_pos,
                                           out_z, out_lambda, out_peak_score, out_flags, stream));

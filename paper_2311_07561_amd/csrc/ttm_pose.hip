@@ -1194,44 +1194,55 @@ __global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, int ngroups, c
 
 // per candidate: the neighbour with the largest dominant Z-eigenvalue
 // (refine 1) or with the largest NCC at its own dominant rotation (refine 2);
-// the centre first on ties, then the lower neighbour index
-__global__ void k_pose_pick(PoseGeo g, const float* __restrict__ score, int K, const int* __restrict__ pos_in,
-                            const int* __restrict__ count_dev, int count_host, int NB,
-                            const double* __restrict__ Cbuf, const double* __restrict__ wbuf,
-                            const float* __restrict__ qbuf, const double* __restrict__ lambuf,
-                            const double* __restrict__ keybuf, const int* __restrict__ flagbuf,
-                            int* __restrict__ out_pos, float* __restrict__ out_quat,
-                            double* __restrict__ out_lambda, float* __restrict__ out_score,
-                            int* __restrict__ out_flags, double* __restrict__ out_C) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+// the centre first on ties, then the lower neighbour index.  One wavefront per
+// candidate: the keys are read in parallel, lane 0 picks and writes the
+// scalars, and the lanes copy the picked tensor together.
+__global__ void __launch_bounds__(64) k_pose_pick(PoseGeo g, const float* __restrict__ score, int K,
+                                                  const int* __restrict__ pos_in, const int* __restrict__ count_dev,
+                                                  int count_host, int NB, const double* __restrict__ Cbuf,
+                                                  const double* __restrict__ wbuf, const float* __restrict__ qbuf,
+                                                  const double* __restrict__ lambuf,
+                                                  const double* __restrict__ keybuf, const int* __restrict__ flagbuf,
+                                                  int* __restrict__ out_pos, float* __restrict__ out_quat,
+                                                  double* __restrict__ out_lambda, float* __restrict__ out_score,
+                                                  int* __restrict__ out_flags, double* __restrict__ out_C) {
+  __shared__ double keys[27];
+  __shared__ int pick;
+  const int p = blockIdx.x;
   const int count = count_dev ? count_dev[0] : count_host;
   if (p >= count) return;
-  const int centre = NB == 27 ? 13 : 0;
-  int bk = centre;
-  double bv = keybuf[(long)p * NB + centre];
-  for (int k = 0; k < NB; ++k) {
-    const double v = keybuf[(long)p * NB + k];
-    if (v > bv) {
-      bv = v;
-      bk = k;
-    }
+  const int lane = threadIdx.x;
+  if (lane < NB) keys[lane] = keybuf[(long)p * NB + lane];
+  __syncthreads();
+  if (lane == 0) {
+    const int centre = NB == 27 ? 13 : 0;
+    int bk = centre;
+    double bv = keys[centre];
+    for (int k = 0; k < NB; ++k)
+      if (keys[k] > bv) {
+        bv = keys[k];
+        bk = k;
+      }
+    pick = bk;
+    const long b = (long)p * NB + bk;
+    int o0, o1, o2;
+    neighbour_offset(bk, NB, o0, o1, o2);
+    const int x0 = pos_in[3 * p] + o0, x1 = pos_in[3 * p + 1] + o1, x2 = pos_in[3 * p + 2] + o2;
+    out_pos[3 * p] = x0;
+    out_pos[3 * p + 1] = x1;
+    out_pos[3 * p + 2] = x2;
+    for (int d = 0; d < 4; ++d) out_quat[4 * p + d] = qbuf[4 * b + d];
+    out_lambda[p] = lambuf[b];
+    int flags = flagbuf[b];
+    if (!(wbuf[b] > 0.0)) flags |= TTM_POSE_ZERO_NORM;
+    out_flags[p] = flags;
+    if (out_score) out_score[p] = score ? score[((long)x0 * g.n1 + x1) * g.n2 + x2] : 0.0f;
   }
-  const long b = (long)p * NB + bk;
-  const double bl = lambuf[b];
-  int o0, o1, o2;
-  neighbour_offset(bk, NB, o0, o1, o2);
-  const int x0 = pos_in[3 * p] + o0, x1 = pos_in[3 * p + 1] + o1, x2 = pos_in[3 * p + 2] + o2;
-  out_pos[3 * p] = x0;
-  out_pos[3 * p + 1] = x1;
-  out_pos[3 * p + 2] = x2;
-  for (int d = 0; d < 4; ++d) out_quat[4 * p + d] = qbuf[4 * b + d];
-  out_lambda[p] = bl;
-  int flags = flagbuf[b];
-  if (!(wbuf[b] > 0.0)) flags |= TTM_POSE_ZERO_NORM;
-  out_flags[p] = flags;
-  if (out_score) out_score[p] = score ? score[((long)x0 * g.n1 + x1) * g.n2 + x2] : 0.0f;
-  if (out_C)
-    for (int k = 0; k < K; ++k) out_C[(long)p * K + k] = Cbuf[b * K + k];
+  if (out_C) {
+    __syncthreads();
+    const long b = (long)p * NB + pick;
+    for (int k = lane; k < K; k += 64) out_C[(long)p * K + k] = Cbuf[b * K + k];
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -1286,17 +1297,25 @@ __global__ void __launch_bounds__(1024) k_refine_compact(const int* __restrict__
 }
 
 // the round's results written back to the candidates' rows; a candidate moves
-// on to the next round if its position changed
-__global__ void k_refine_scatter(const int* __restrict__ act_count, const int* __restrict__ act_idx, int K,
-                                 const int* __restrict__ t_pos, const float* __restrict__ t_quat,
-                                 const double* __restrict__ t_lam, const float* __restrict__ t_score,
-                                 const int* __restrict__ t_flags, const double* __restrict__ t_C,
-                                 int* __restrict__ out_pos, float* __restrict__ out_quat,
-                                 double* __restrict__ out_lambda, float* __restrict__ out_score,
-                                 int* __restrict__ out_flags, double* __restrict__ out_C, int* __restrict__ moved) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// on to the next round if its position changed.  One wavefront per entry of
+// the round's list: lane 0 writes the scalars, the lanes copy the tensor.
+__global__ void __launch_bounds__(64) k_refine_scatter(const int* __restrict__ act_count,
+                                                       const int* __restrict__ act_idx, int K,
+                                                       const int* __restrict__ t_pos, const float* __restrict__ t_quat,
+                                                       const double* __restrict__ t_lam,
+                                                       const float* __restrict__ t_score,
+                                                       const int* __restrict__ t_flags, const double* __restrict__ t_C,
+                                                       int* __restrict__ out_pos, float* __restrict__ out_quat,
+                                                       double* __restrict__ out_lambda, float* __restrict__ out_score,
+                                                       int* __restrict__ out_flags, double* __restrict__ out_C,
+                                                       int* __restrict__ moved) {
+  const int j = blockIdx.x;
   if (j >= act_count[0]) return;
   const int p = act_idx[j];
+  const int lane = threadIdx.x;
+  if (out_C)
+    for (int k = lane; k < K; k += 64) out_C[(long)p * K + k] = t_C[(long)j * K + k];
+  if (lane != 0) return;
   bool mv = false;
   for (int d = 0; d < 3; ++d) {
     mv = mv || t_pos[3 * j + d] != out_pos[3 * p + d];
@@ -1307,8 +1326,6 @@ __global__ void k_refine_scatter(const int* __restrict__ act_count, const int* _
   out_lambda[p] = t_lam[j];
   if (out_score) out_score[p] = t_score[j];
   out_flags[p] = t_flags[j];
-  if (out_C)
-    for (int k = 0; k < K; ++k) out_C[(long)p * K + k] = t_C[(long)j * K + k];
 }
 
 hipError_t launch_refine_init(const int* count_dev, int count_host, const int* start, const int* pos, int* moved,
@@ -1328,7 +1345,8 @@ hipError_t launch_refine_compact(const int* count_dev, int count_host, int* move
 hipError_t launch_refine_scatter(const int* act_count, const int* act_idx, int K, const RefineTmp& t,
                                  int* out_pos, float* out_quat, double* out_lambda, float* out_score,
                                  int* out_flags, double* out_C, int* moved, int max_peaks, hipStream_t s) {
-  hipLaunchKernelGGL(k_refine_scatter, dim3((max_peaks + 255) / 256), dim3(256), 0, s, act_count, act_idx, K,
+  if (max_peaks < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_refine_scatter, dim3((unsigned)max_peaks), dim3(64), 0, s, act_count, act_idx, K,
                      t.pos, t.quat, t.lam, t.score, t.flags, t.C, out_pos, out_quat, out_lambda, out_score,
                      out_flags, out_C, moved);
   return hipGetLastError();
@@ -1431,7 +1449,7 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
       hipLaunchKernelGGL(k_pose_ncc, eg, dim3(256), 0, s, g, image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in,
                          count_dev, count_host, NB, ps.w, ps.ok, ps.q, ps.ncc);
   }
-  hipLaunchKernelGGL(k_pose_pick, dim3((max_peaks + 63) / 64), dim3(64), 0, s, g, score, K, pos_in, count_dev,
+  hipLaunchKernelGGL(k_pose_pick, dim3((unsigned)max_peaks), dim3(64), 0, s, g, score, K, pos_in, count_dev,
                      count_host, NB, ps.C, ps.w, ps.q, ps.lam, refine == 2 ? ps.ncc : ps.lam, ps.flags, out_pos,
                      out_quat, out_lambda, out_score, out_flags, out_C);
   return hipGetLastError();
