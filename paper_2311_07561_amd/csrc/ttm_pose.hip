@@ -54,10 +54,14 @@ __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F,
   ctrl += kPeakCtrlWords * plane;
   allc += bigcap * plane;
   const int b0 = g.lo0 + bz * PT0, b1 = g.lo1 + blockIdx.y * PT1, b2 = g.lo2 + blockIdx.x * PT2;
+  // the tile's planes along axis 0 that hold valid voxels (one for a map of
+  // depth 1): only they and their two halo planes are loaded and tested
+  const int nv0 = min(PT0, g.hi0 - b0 + 1);
+  const int NT = (nv0 + 2) * H1 * H2;
   // the halo tile, eight loads in flight per thread: each load is
   // unconditional (of voxel 0 outside the map) so that the compiler issues
   // them before it waits, and the value outside the map is -inf
-  constexpr int NT = H0 * H1 * H2, U = 8;
+  constexpr int U = 8;
   for (int e0 = tid; e0 < NT; e0 += 256 * U) {
     float v[U];
     bool in[U];
@@ -79,14 +83,14 @@ __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F,
   __shared__ unsigned lcount, lbase;
   if (tid == 0) lcount = 0u;
   __syncthreads();
-  for (int e = tid; e < PT0 * PT1 * PT2; e += 256) {
+  // the 26 neighbour reads are unconditional and combined with a bitwise and,
+  // so that they issue together instead of one read, wait and branch each
+  for (int e = tid; e < nv0 * PT1 * PT2; e += 256) {
     const int t2 = e % PT2, t1 = (e / PT2) % PT1, t0 = e / (PT1 * PT2);
     const int x0 = b0 + t0, x1 = b1 + t1, x2 = b2 + t2;
-    if (x0 > g.hi0 || x1 > g.hi1 || x2 > g.hi2) continue;
     const int c = ((t0 + 1) * H1 + (t1 + 1)) * H2 + (t2 + 1);
     const float v = tile[c];
-    if (!(v > threshold)) continue;
-    bool ok = true;
+    bool ok = x0 <= g.hi0 && x1 <= g.hi1 && x2 <= g.hi2 && v > threshold;
 #pragma unroll
     for (int d0 = -1; d0 <= 1; ++d0)
 #pragma unroll
@@ -94,7 +98,7 @@ __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F,
 #pragma unroll
         for (int d2 = -1; d2 <= 1; ++d2) {
           if (d0 == 0 && d1 == 0 && d2 == 0) continue;
-          ok = ok && (v > tile[c + (d0 * H1 + d1) * H2 + d2]);
+          ok = ok & (v > tile[c + (d0 * H1 + d1) * H2 + d2]);
         }
     if (!ok) continue;
     const long lin = ((long)x0 * g.n1 + x1) * g.n2 + x2;
