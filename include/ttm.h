@@ -324,8 +324,11 @@ ttm_status ttm_rotation_map(
  * [B][n1][n2]; out_w may be NULL), the candidates of the 3-D rule restricted
  * to the plane (strict maxima over the 8 neighbours inside the valid region,
  * sorted, suppression within opt->min_dist, at most opt->max_peaks), the
- * tensor at each by direct float64 window sums and its dominant eigenpair,
- * refined as opt->refine (0..3, the neighbourhood being the 3 x 3 pixels):
+ * tensor at each by direct float64 window sums and its dominant eigenpair
+ * (on the circle: a 4096-point scan of the half-angle, then a parallel zoom
+ * to below 1e-12 rad, in float64; opt->n_seeds, hopm_max_iter and hopm_tol
+ * are not used and TTM_POSE_NOT_CONVERGED is never set), refined as
+ * opt->refine (0..3, the neighbourhood being the 3 x 3 pixels):
  *   out_pos        [B][max_peaks][2] int32 (x1, x2)
  *   out_z          [B][max_peaks][2] float32, unit, a > 0 (or a = 0, b > 0)
  *   out_lambda     [B][max_peaks] float64
