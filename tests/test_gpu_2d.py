@@ -205,3 +205,67 @@ def test_classical_matching_of_a_stack_with_planar_rotations(small_stack):
         assert np.array_equal(got_idx[clear], np.argmax(ncc, axis=1)[clear])
         checked += int(clear.sum())
     print(f"\nclassical on the 16 x 64^2 stack, {J} rotations: {checked} argmax pixels checked")
+
+
+def test_planar_eigenpair_at_the_ends_of_the_half_angle_range():
+    """Copies turned by 0, 0.2, 90, 179.9, 180 and 359.8 degrees (half-angles
+    at both ends of [0, pi) and in its middle) in the first two planes of a
+    stack of 16 x 128^2 (stack extents are powers of two), order 8, refine 0:
+    at every found peak of those planes lambda within 1e-4 and the rotation
+    within 1 degree of the oracle's eigenpair at the same pixel, and every
+    copy found within 2 pixels."""
+    L, n, size, B = 32, 8, 128, 16
+    # two blobs: an anisotropic template whose eigenvalue on the circle has a
+    # clear maximum (the best value 5 degrees away is 0.8% lower)
+    tm = synth.make_blob_template_2d(np.random.default_rng(73), L, 2, L / 2)
+    c = L // 2
+    ax = np.arange(L, dtype=np.float64) - c
+    t64 = tm.evaluate(np.stack(np.meshgrid(ax, ax, indexing="ij"), axis=-1))
+    m64 = synth.disc_mask(L, L / 2).astype(np.float64)
+    pts = np.array([[36, 36], [36, 92], [92, 64]])
+    angles = [[0.0, 0.2, 90.0], [179.9, 180.0, 359.8]]
+    imgs = np.zeros((B, size, size))
+    for b in range(2):
+        for x, deg in zip(pts, angles[b]):
+            a = math.radians(deg)
+            rm = np.array([[math.cos(a), -math.sin(a)], [math.sin(a), math.cos(a)]])
+            lo = [max(int(x[k]) - L, 0) for k in range(2)]
+            hi = [min(int(x[k]) + L + 1, size) for k in range(2)]
+            g = np.stack(np.meshgrid(np.arange(lo[0], hi[0]) - x[0], np.arange(lo[1], hi[1]) - x[1],
+                                     indexing="ij"), axis=-1)
+            imgs[b, lo[0]:hi[0], lo[1]:hi[1]] += tm.evaluate(g.astype(np.float64) @ rm)
+    imgs += 0.02 * float(t64.std()) * np.random.default_rng(72).standard_normal(imgs.shape)
+    J = 720
+    zs = synth.circle_quadrature(J)
+    w = np.full(J, 1.0 / J)
+    T = O.tensor_template_2d(t64, m64, n, zs, w)
+    comps, bank = ttm.build_tensor_template_2d(dev(t64), dev(m64), n, zs, w, stack_shape=imgs.shape)
+    opt = ttm.default_options(max_peaks=3, min_dist=16.0, threshold=0.0, refine=0)
+    bufs = ttm.Match2DBuffers(imgs.shape, (L, L), n, opt, "cuda")
+    ttm.match_2d(dev(imgs), bank, comps, dev(m64), n, opt, bufs)
+    torch.cuda.synchronize()
+    worst_rot, worst_truth, checked = 0.0, 0.0, 0
+    for b in range(2):
+        f = imgs[b]
+        res = bufs.result(b)
+        pos = res["pos"].cpu().numpy()
+        z = res["z"].cpu().numpy()
+        C = O.tensor_field_at_2d(f, T, m64, pos)
+        for p in range(len(pos)):
+            zo, lo_, second = O.dominant_eigen_2d(C[p], n)
+            assert abs(float(res["lam"][p]) - lo_) <= 1e-4 * max(1.0, abs(lo_))
+            assert z[p][0] > 0.0 or (z[p][0] == 0.0 and z[p][1] > 0.0)
+            if second < lo_ - 1e-3 * abs(lo_):
+                d = O.rotation_angle_2d_deg(z[p], zo)
+                worst_rot = max(worst_rot, d)
+                checked += 1
+                assert d <= 1.0
+        for x, deg in zip(pts, angles[b]):
+            dist = np.linalg.norm(pos - x[None], axis=1)
+            assert len(dist) and dist.min() <= 2.0, (b, x, pos)
+            i = int(np.argmin(dist))
+            a = math.radians(deg)
+            worst_truth = max(worst_truth, O.rotation_angle_2d_deg(z[i], [math.cos(a / 2), math.sin(a / 2)]))
+    assert checked == 6
+    print(f"\nedge angles: {checked} eigenpairs checked, rotation max err {worst_rot:.4f} deg against the oracle, "
+          f"{worst_truth:.2f} deg against the planted angles")
