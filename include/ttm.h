@@ -325,8 +325,8 @@ ttm_status ttm_rotation_map(
  * to the plane (strict maxima over the 8 neighbours inside the valid region,
  * sorted, suppression within opt->min_dist, at most opt->max_peaks), the
  * tensor at each by direct float64 window sums and its dominant eigenpair
- * (on the circle: a 4096-point scan of the half-angle, then a parallel zoom
- * to below 1e-12 rad, in float64; opt->n_seeds, hopm_max_iter and hopm_tol
+ * (on the circle: a 1024-point scan of the half-angle, then a parallel zoom
+ * to below 1e-11 rad, in float64; opt->n_seeds, hopm_max_iter and hopm_tol
  * are not used and TTM_POSE_NOT_CONVERGED is never set), refined as
  * opt->refine (0..3, the neighbourhood being the 3 x 3 pixels):
  *   out_pos        [B][max_peaks][2] int32 (x1, x2)

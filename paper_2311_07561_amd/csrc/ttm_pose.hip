@@ -749,8 +749,8 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
 // best sample (lowest j on ties); then kPlanarZoom parallel zoom levels, each
 // sampling 64 points evenly over [c - h, c + h] around the best point c so
 // far and narrowing h to the sample spacing (h / 31.5), which shrinks the
-// bracket of one scan step to below 1e-12 rad.
-constexpr int kPlanarScan = 4096;
+// bracket of one scan step (pi / 1024) to below 1e-11 rad.
+constexpr int kPlanarScan = 1024;
 constexpr int kPlanarZoom = 6;
 template <int N>
 __device__ __forceinline__ double planar_phi(const double (&a)[N + 1], double c, double s) {
