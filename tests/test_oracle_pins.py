@@ -841,6 +841,32 @@ def test_planar_theorem_recovers_planted_rotations():
     assert O.rotation_angle_2d_deg(z, [math.cos(a / 2), math.sin(a / 2)]) < 2.0
 
 
+@pytest.mark.parametrize("n", [2, 4, 6, 8])
+def test_planar_eigenpair_closed_forms(n):
+    """The dominant eigenpair on the circle in two closed forms.  For the
+    rank-one tensor z^n (C_k = a^(n-k) b^k) the eigenvalue on the circle is
+    (a cos psi + b sin psi)^n = cos^n(psi - theta/2): lambda = 1 exactly, at
+    z, and the best value more than 5 degrees of rotation away (2.5 degrees of
+    half-angle) is cos^n(2.5 deg) up to one scan step.  The tensor of
+    (x^2 + y^2)^(n/2) (C_k = C(n/2, k/2) / C(n, k) for even k, 0 for odd k)
+    is 1 on the whole circle: lambda and that best value both equal 1."""
+    step = 180.0 / 20000
+    for deg in (0.0, 0.2, 37.0, 90.0, 179.9, 180.0, 270.0, 359.8):
+        th = math.radians(deg)
+        a, b = math.cos(th / 2), math.sin(th / 2)
+        C = np.array([a ** (n - k) * b ** k for k in range(n + 1)])
+        z, lam, second = O.dominant_eigen_2d(C, n)
+        assert abs(lam - 1.0) <= 1e-12, (deg, lam)
+        assert O.rotation_angle_2d_deg(z, [a, b]) <= 1e-5, (deg, z)
+        assert z[0] > 0.0 or (z[0] == 0.0 and z[1] > 0.0)
+        hi = math.cos(math.radians(2.5)) ** n
+        lo = math.cos(math.radians(2.5 + step)) ** n
+        assert lo - 1e-12 <= second <= hi + 1e-12, (deg, second, lo, hi)
+    C = np.array([math.comb(n // 2, k // 2) / math.comb(n, k) if k % 2 == 0 else 0.0 for k in range(n + 1)])
+    z, lam, second = O.dominant_eigen_2d(C, n)
+    assert abs(lam - 1.0) <= 1e-12 and abs(second - 1.0) <= 1e-12
+
+
 def test_planar_refinement_returns_to_a_copy():
     n, L = 6, 21
     rng = _rng(63)
