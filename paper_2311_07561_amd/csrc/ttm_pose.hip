@@ -1046,7 +1046,7 @@ __global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __rest
   }
 }
 
-// The same NCC with the template held in LDS: one 1024-thread block per
+// The same NCC with the template held in LDS: one block of NT threads per
 // (candidate, group of its neighbours) loads the template once and
 // evaluates the group's neighbours one after another, sampling trilinearly
 // from LDS without branches (corners outside the box get weight 0 and read
@@ -1054,8 +1054,15 @@ __global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __rest
 // P01 = L1 P2 + 5 (for L = 32 the banks see j2 + 35 j1 + 37 j0 mod 64 rather
 // than only j2 and the parity of j1); with the 4x4x4 brick order of the mask
 // voxels this cuts the distinct addresses per bank of a wave's gather about
-// fourfold.  The layout must fit kNccLdsCap floats.
-__global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, int ngroups, const float* __restrict__ image,
+// fourfold.  The layout must fit CAP floats.  Volumes take 1024 threads and
+// CAP = kNccLdsCap (one block per CU).  A box that fits kNccLdsSmall floats
+// (the depth-1 boxes of a planar stack) takes 256 threads and that much LDS,
+// so that eight blocks share a CU: its window holds too few mask voxels to
+// occupy 1024 threads, and with the large LDS reservation the blocks of a
+// stack's candidates would run one per CU.
+constexpr int kNccLdsSmall = 4096;
+template <int NT, int CAP>
+__global__ void __launch_bounds__(NT) k_pose_ncc_lds(PoseGeo g, int ngroups, const float* __restrict__ image,
                                                        const float* __restrict__ tmpl,
                                                        const unsigned* __restrict__ mlist,
                                                        const float* __restrict__ mval,
@@ -1064,8 +1071,9 @@ __global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, int ngroups, c
                                                        const double* __restrict__ wbuf,
                                                        const int* __restrict__ okbuf, const float* __restrict__ qbuf,
                                                        double* __restrict__ nccbuf) {
-  __shared__ float tl[kNccLdsCap];
-  __shared__ double red[16][15];
+  constexpr int NW = NT / 64;
+  __shared__ float tl[CAP];
+  __shared__ double red[NW][15];
   constexpr int NB = 27;
   const int p = blockIdx.x / ngroups, grp = blockIdx.x % ngroups;
   const int gsize = (NB + ngroups - 1) / ngroups;
@@ -1075,7 +1083,7 @@ __global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, int ngroups, c
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int L0 = g.L0, L1 = g.L1, L2 = g.L2, nL = L0 * L1 * L2;
   const int P2 = L2 + 3, P01 = L1 * P2 + 5;
-  fill_lds_box(tl, tmpl, L0, L1, L2, P2, P01, tid, 1024);
+  fill_lds_box(tl, tmpl, L0, L1, L2, P2, P01, tid, NT);
   __syncthreads();
   const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;
   const int rs1 = g.n2, rs0 = g.n1 * g.n2;
@@ -1134,12 +1142,12 @@ __global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, int ngroups, c
     // their image values, are loaded before any sample waits on them.  Past
     // the list's end a slot holds voxel 0 with weight 0 and adds nothing, so
     // each thread's sums are those of the plain loop over its voxels.
-    for (int i0 = tid; i0 < nm; i0 += 1024 * kNccLoads) {
+    for (int i0 = tid; i0 < nm; i0 += NT * kNccLoads) {
       unsigned pk[kNccLoads];
       float mv[kNccLoads], fv[kNccPass][kNccLoads];
 #pragma unroll
       for (int jj = 0; jj < kNccLoads; ++jj) {
-        const int i = i0 + 1024 * jj;
+        const int i = i0 + NT * jj;
         pk[jj] = i < nm ? mlist[i] : 0u;
         mv[jj] = i < nm ? mval[i] : 0.0f;
       }
@@ -1183,7 +1191,7 @@ __global__ void __launch_bounds__(1024) k_pose_ncc_lds(PoseGeo g, int ngroups, c
       for (int j = 0; j < kNccPass; ++j) {
         if (!live[j]) continue;
         double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int wv = 0; wv < 16; ++wv)
+        for (int wv = 0; wv < NW; ++wv)
 #pragma unroll
           for (int i = 0; i < 5; ++i) t[i] += red[wv][j * 5 + i];
         const double mu = t[0] > 0.0 ? t[1] / t[0] : 0.0;
@@ -1441,13 +1449,19 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
   if (refine == 2) {
     if (!reuse_tables)
       (void)launch_mask_list(mask, g.L0, g.L1, g.L2, ps.mlist, ps.mval, ps.mcount, s);
-    if (ncc_lds_floats(g.L0, g.L1, g.L2) <= kNccLdsCap) {
+    const long lds = ncc_lds_floats(g.L0, g.L1, g.L2);
+    const int ngroups = ncc_groups;
+    if (lds <= kNccLdsSmall) {
+      // small boxes: 256 threads and 16 KiB of LDS per block
+      hipLaunchKernelGGL((k_pose_ncc_lds<256, kNccLdsSmall>), dim3((unsigned)(max_peaks * ngroups)), dim3(256), 0, s,
+                         g, ngroups, image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in, count_dev, count_host, ps.w,
+                         ps.ok, ps.q, ps.ncc);
+    } else if (lds <= kNccLdsCap) {
       // one block per CU (the template fills most of the LDS); each block
       // loads the template once for 27 / ngroups neighbours of a candidate
-      const int ngroups = ncc_groups;
-      hipLaunchKernelGGL(k_pose_ncc_lds, dim3((unsigned)(max_peaks * ngroups)), dim3(1024), 0, s, g, ngroups,
-                         image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in, count_dev, count_host, ps.w, ps.ok,
-                         ps.q, ps.ncc);
+      hipLaunchKernelGGL((k_pose_ncc_lds<1024, kNccLdsCap>), dim3((unsigned)(max_peaks * ngroups)), dim3(1024), 0,
+                         s, g, ngroups, image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in, count_dev, count_host,
+                         ps.w, ps.ok, ps.q, ps.ncc);
     }
     else
       hipLaunchKernelGGL(k_pose_ncc, eg, dim3(256), 0, s, g, image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in,
