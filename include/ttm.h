@@ -51,7 +51,8 @@ typedef enum {
   TTM_E_SIZE = -2,       /* a dimension is unsupported or inconsistent         */
   TTM_E_WORKSPACE = -3,  /* the workspace is NULL or smaller than required     */
   TTM_E_HIP = -4,        /* a HIP launch or call failed                        */
-  TTM_E_NONFINITE = -5   /* reserved: non-finite input detected                */
+  TTM_E_NONFINITE = -5   /* a NaN or infinity in the image or mask, found by
+                            the check that ttm_options.check_finite asks for  */
 } ttm_status;
 
 typedef struct {
@@ -79,6 +80,17 @@ typedef struct {
                             most 4 rounds in all (only moving candidates are
                             recomputed; two candidates may end on the same
                             voxel); default 0                                 */
+  int32_t check_finite;  /* 1: ttm_correlate, ttm_match, ttm_correlate_tiled and
+                            ttm_rotation_map first reduce the image and the
+                            mask to their float64 moments (sum f, sum f^2,
+                            sum m), copy those to the host and wait for them;
+                            a non-finite moment (a NaN or an infinity in
+                            either input) returns TTM_E_NONFINITE with only
+                            that reduction enqueued and no output written.
+                            The call then synchronises with the stream once,
+                            so it cannot be recorded into a graph (the batch
+                            calls reject it with TTM_E_ARG).  0 (default): no
+                            check; a non-finite input gives NaN outputs     */
 } ttm_options;
 
 /* Pose flags (bit set in out_flags). */
@@ -88,7 +100,8 @@ typedef struct {
                                       than max_peaks may have been accepted   */
 
 /* Fills *opt with the defaults (eps_v 1e-5, threshold 0, min_dist 8,
- * max_peaks 64, n_seeds 4096, hopm_max_iter 1000, hopm_tol 1e-12, refine 0). */
+ * max_peaks 64, n_seeds 4096, hopm_max_iter 1000, hopm_tol 1e-12, refine 0,
+ * check_finite 0). */
 void ttm_default_options(ttm_options* opt);
 
 /* Number of independent components of a symmetric tensor of order n on R^4:
@@ -158,7 +171,9 @@ ttm_status ttm_build_tensor_template(
  *   opt        options (eps_v is used)
  *   out_score  [n0][n1][n2] float32 F(x) (written)
  *   out_w      [n0][n1][n2] float32 w(x), or NULL
- * Errors: TTM_E_ARG, TTM_E_SIZE, TTM_E_WORKSPACE, TTM_E_HIP.
+ * Errors: TTM_E_ARG, TTM_E_SIZE, TTM_E_WORKSPACE, TTM_E_HIP, and
+ * TTM_E_NONFINITE when opt->check_finite is set and the image or the mask
+ * holds a NaN or an infinity.
  * ------------------------------------------------------------------------- */
 size_t ttm_correlate_workspace_bytes(ttm_dims N, ttm_dims L, int32_t K);
 ttm_status ttm_correlate(

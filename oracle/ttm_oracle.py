@@ -35,6 +35,7 @@ Readings of points where the paper is silent:
 """
 from __future__ import annotations
 
+import functools
 import itertools
 import math
 
@@ -96,14 +97,18 @@ def rotation_angle_deg(q1, q2) -> float:
 # packed symmetric tensors (Section 3.1)
 # ----------------------------------------------------------------------------
 
+@functools.lru_cache(maxsize=None)
 def multi_indices(n: int) -> np.ndarray:
-    """Multi-indices ``alpha`` of ``S^n(R^4)`` in storage order."""
+    """Multi-indices ``alpha`` of ``S^n(R^4)`` in storage order (one shared,
+    read-only array per order)."""
     out = []
     for a1 in range(n, -1, -1):
         for a2 in range(n - a1, -1, -1):
             for a3 in range(n - a1 - a2, -1, -1):
                 out.append((a1, a2, a3, n - a1 - a2 - a3))
-    return np.array(out, dtype=np.int64)
+    arr = np.array(out, dtype=np.int64)
+    arr.setflags(write=False)
+    return arr
 
 
 def num_components(n: int) -> int:
@@ -111,12 +116,16 @@ def num_components(n: int) -> int:
     return math.comb(n + 3, 3)
 
 
+@functools.lru_cache(maxsize=None)
 def multiplicities(n: int) -> np.ndarray:
     """How many of the ``4^n`` entries of a symmetric tensor equal the packed
-    entry ``alpha``: ``n! / (alpha_1! alpha_2! alpha_3! alpha_4!)``."""
+    entry ``alpha``: ``n! / (alpha_1! alpha_2! alpha_3! alpha_4!)`` (one
+    shared, read-only array per order)."""
     f = math.factorial
-    return np.array([f(n) // (f(a[0]) * f(a[1]) * f(a[2]) * f(a[3]))
-                     for a in multi_indices(n)], dtype=np.float64)
+    arr = np.array([f(n) // (f(a[0]) * f(a[1]) * f(a[2]) * f(a[3]))
+                    for a in multi_indices(n)], dtype=np.float64)
+    arr.setflags(write=False)
+    return arr
 
 
 def monomials(q: np.ndarray, n: int) -> np.ndarray:
@@ -648,15 +657,18 @@ def refine_by_ncc(f, t, m, T, n: int, x, eps_v: float = EPS_V_DEFAULT,
 
 
 def refine_by_ncc_iterated(f, t, m, T, n: int, x, eps_v: float = EPS_V_DEFAULT,
-                           n_brute: int = 100000, max_rounds: int = 4):
+                           n_brute: int = 100000, max_rounds: int = 4, trace=None):
     """The NCC refinement of :func:`refine_by_ncc` repeated from its own result
     until the position no longer moves, at most ``max_rounds`` times (a hill
     climb on the NCC at each voxel's own rotation, for Frobenius-score peaks
     more than one voxel from the copy's centre).  Returns (position, q,
-    lambda, ncc, rounds taken)."""
+    lambda, ncc, rounds taken).  ``trace`` (a list, optional) receives the
+    start position and the 27 NCC values of every round."""
     x = np.asarray(x)
     for r in range(1, max_rounds + 1):
-        pos, q, lam, ncc, _ = refine_by_ncc(f, t, m, T, n, x, eps_v, n_brute)
+        pos, q, lam, ncc, nccs = refine_by_ncc(f, t, m, T, n, x, eps_v, n_brute)
+        if trace is not None:
+            trace.append((x.copy(), nccs))
         if np.array_equal(pos, x) or r == max_rounds:
             return pos, q, lam, ncc, r
         x = pos

@@ -268,6 +268,19 @@ static hipError_t pencils_inverse_valid(const Geo& g, float2* H, int nb, long ha
     if (_st != TTM_OK) return _st;         \
   } while (0)
 
+// the finiteness check of ttm_options.check_finite: the float64 moments
+// (sum f, sum f^2 as mean and variance, and sum m) are finite exactly when no
+// input value is a NaN or an infinity; they are copied to the host and waited
+// for
+static ttm_status moments_finite(const double* stats_dev, hipStream_t stream) {
+  double h[3] = {0.0, 0.0, 0.0};
+  TTM_TRY(hipMemcpyAsync(h, stats_dev, sizeof(h), hipMemcpyDeviceToHost, stream));
+  TTM_TRY(hipStreamSynchronize(stream));
+  for (double v : h)
+    if (!std::isfinite(v)) return TTM_E_NONFINITE;
+  return TTM_OK;
+}
+
 }  // namespace ttm
 
 using namespace ttm;
@@ -284,6 +297,7 @@ void ttm_default_options(ttm_options* o) {
   o->hopm_max_iter = 1000;
   o->hopm_tol = 1e-12;
   o->refine = 0;
+  o->check_finite = 0;
 }
 
 int32_t ttm_num_components(int32_t n) {
@@ -377,8 +391,15 @@ size_t ttm_correlate_workspace_bytes(ttm_dims N, ttm_dims L, int32_t K) {
 static ttm_status correlate_into(const Geo& g, int order_n, int K, const float* image, const float2* bk,
                                  const float* mask, float eps_v, float* out_score, float* out_w, CorrWs& w,
                                  hipStream_t stream, float* out_C = nullptr, const double* stats_in = nullptr,
-                                 bool planar = false) {
+                                 bool planar = false, bool check_finite = false) {
   const long half = g.half();
+  if (check_finite && !stats_in) {
+    // the image moments first, checked before anything else is enqueued
+    TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), mask, (long)g.L0 * g.L1 * g.L2, w.partials, w.stats,
+                                          stream));
+    TTM_CALL(moments_finite(w.stats, stream));
+    stats_in = w.stats;
+  }
   if (planar)
     TTM_PROF(PC_STATS, launch_planar_mu(order_n, w.mu, stream));
   else
@@ -418,7 +439,7 @@ ttm_status ttm_correlate(const float* image, ttm_dims N, const void* bank, ttm_d
   Carve c(ws);
   CorrWs w = corr_layout(c, g, K);
   return correlate_into(g, order_n, K, image, static_cast<const float2*>(bank), mask, opt->eps_v, out_score,
-                        out_w, w, stream);
+                        out_w, w, stream, nullptr, nullptr, false, opt->check_finite != 0);
 }
 
 static bool pose_opts_ok(const ttm_options* opt) {
@@ -560,7 +581,7 @@ ttm_status ttm_match(const float* image, ttm_dims N, const void* bank, ttm_dims 
   float* wmap = c.take<float>(g.vol());
   float* wout = out_w ? out_w : wmap;
   TTM_CALL(correlate_into(g, order_n, K, image, static_cast<const float2*>(bank), mask, opt->eps_v, out_score,
-                          wout, cw, stream));
+                          wout, cw, stream, nullptr, nullptr, false, opt->check_finite != 0));
   PeakWs pk{pw.hist, pw.ctrl, pw.allc, pw.cand};
   float* cand_score = reinterpret_cast<float*>(pw.ps.w);
   TTM_PROF(PC_PEAKS, launch_peaks(g, out_score, opt->threshold, opt->min_dist, opt->max_peaks, pk, pw.cand_pos,
@@ -612,10 +633,11 @@ static TiledWs tiled_layout(Carve& c, int T, const ttm_dims& L, int K) {
 // those statistics), scatter of the tile's valid part
 static ttm_status correlate_tiled_into(const float* image, const ttm_dims& N, const float2* bank, const ttm_dims& L,
                                        int order_n, int K, int T, const float* mask, float eps_v, float* out_score,
-                                       float* out_w, TiledWs& w, hipStream_t stream) {
+                                       float* out_w, TiledWs& w, hipStream_t stream, bool check_finite = false) {
   const Geo gT = make_geo(ttm_dims{T, T, T}, L);
   const long vol = (long)N.n0 * N.n1 * N.n2;
   TTM_PROF(PC_STATS, launch_image_stats(image, vol, mask, (long)L.n0 * L.n1 * L.n2, w.partials, w.stats, stream));
+  if (check_finite) TTM_CALL(moments_finite(w.stats, stream));
   TTM_PROF(PC_EPI, launch_fill_f32(out_score, vol, 0.0f, stream));
   if (out_w) TTM_PROF(PC_EPI, launch_fill_f32(out_w, vol, 0.0f, stream));
   TileGeo tg;
@@ -680,7 +702,7 @@ ttm_status ttm_correlate_tiled(const float* image, ttm_dims N, const void* bank,
   Carve c(ws);
   TiledWs w = tiled_layout(c, T, L, K);
   return correlate_tiled_into(image, N, static_cast<const float2*>(bank), L, order_n, K, T, mask, opt->eps_v,
-                              out_score, out_w, w, stream);
+                              out_score, out_w, w, stream, opt->check_finite != 0);
 }
 
 size_t ttm_autotune_workspace_bytes(ttm_dims L, int32_t order_n, const int32_t* tiles_host, int32_t n) {
@@ -800,6 +822,7 @@ static ttm_status batch_check(const ttm_batch_job* jobs_host, int32_t n_jobs, in
   if (!jobs_host || n_jobs < 1 || !opt) return TTM_E_ARG;
   const int K = ttm_num_components(order_n);
   if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
+  if (opt->check_finite) return TTM_E_ARG;   // the check waits on the stream: not in a batch or graph
   for (int i = 0; i < n_jobs; ++i) {
     if (!job_ok(jobs_host[i], order_n, opt)) return TTM_E_ARG;
     const ttm_status st = job_sizes(jobs_host[i]);
@@ -997,7 +1020,7 @@ ttm_status ttm_rotation_map(const float* image, ttm_dims N, const void* bank, tt
   RmapWs rw = rmap_layout(c, g, order_n, K, n_seeds);
   float* wout = out_w ? out_w : rw.wmap;
   TTM_CALL(correlate_into(g, order_n, K, image, static_cast<const float2*>(bank), mask, opt->eps_v, out_score,
-                          wout, cw, stream, rw.planes));
+                          wout, cw, stream, rw.planes, nullptr, false, opt->check_finite != 0));
   TTM_PROF(PC_RMAP_POLISH, launch_rmap_table(order_n, seeds, n_seeds, rw.table, stream));
   TTM_PROF(PC_RMAP_SCAN, launch_rmap_scan(g, order_n, rw.planes, rw.table, n_seeds, rw.group, stream));
   TTM_PROF(PC_RMAP_POLISH, launch_fill_f32(out_score, g.vol(), 0.0f, stream));

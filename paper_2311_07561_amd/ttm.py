@@ -47,7 +47,8 @@ class Options(ctypes.Structure):
     _fields_ = [("eps_v", ctypes.c_float), ("threshold", ctypes.c_float),
                 ("min_dist", ctypes.c_float), ("max_peaks", ctypes.c_int32),
                 ("n_seeds", ctypes.c_int32), ("hopm_max_iter", ctypes.c_int32),
-                ("hopm_tol", ctypes.c_double), ("refine", ctypes.c_int32)]
+                ("hopm_tol", ctypes.c_double), ("refine", ctypes.c_int32),
+                ("check_finite", ctypes.c_int32)]
 
 
 class BatchJob(ctypes.Structure):

@@ -34,6 +34,11 @@ def test_host_only_functions():
     o = ttm.default_options()
     assert o.max_peaks == 64 and o.n_seeds == 4096 and o.hopm_max_iter == 1000
     assert abs(o.eps_v - 1e-5) < 1e-12 and o.hopm_tol == 1e-12
+    assert o.refine == 0 and o.check_finite == 0
+    # ttm_options's layout: natural alignment of its C declaration
+    assert ctypes.sizeof(ttm.Options) == 40
+    assert (ttm.Options.hopm_tol.offset, ttm.Options.refine.offset, ttm.Options.check_finite.offset) == (24, 32, 36)
+    assert L.ttm_status_string(-5).startswith(b"TTM_E_NONFINITE")
 
 
 def test_sizes():
@@ -249,6 +254,11 @@ def test_batch_and_tiled_validation_without_gpu():
                                     ctypes.byref(h)) == -3
     assert L.ttm_graph_launch(None, None) == -1
     L.ttm_graph_destroy(None)
+    # the finiteness check waits on the stream: a batch or graph rejects it
+    cf = _opt(check_finite=1)
+    assert L.ttm_batch_match(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(cf), 1, fake, big, None) == -1
+    assert L.ttm_batch_graph_create(ctypes.cast(arr, ctypes.c_void_p), 1, 4, ctypes.byref(cf), 1, fake, big, fake,
+                                    ctypes.byref(h)) == -1
     # ttm_batch_job's layout: natural alignment of its C declaration
     assert ctypes.sizeof(ttm.BatchJob) == 144
     assert (ttm.BatchJob.N.offset, ttm.BatchJob.tile.offset, ttm.BatchJob.L.offset,

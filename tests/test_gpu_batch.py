@@ -140,6 +140,7 @@ def test_batch_match_against_oracle(batch_setup):
     wl, n, q, w, temps, opt, jobs, outs, meta, ws = batch_setup
     ttm.batch_match(jobs, n, opt, ws)
     torch.cuda.synchronize()
+    checked, total = 0, 0
     for out, (i, k, T, im) in zip(outs, meta):
         img = wl.images[i]
         t, m = wl.templates[k], wl.masks[k]
@@ -166,10 +167,14 @@ def test_batch_match_against_oracle(batch_setup):
         C = O.tensor_field_at(img.astype(np.float64), Tt, m.astype(np.float64), pos)
         for p in range(len(pos)):
             qo, lo_, second = O.dominant_z_eigenpair(C[p], n, n_brute=60000)
-            if second < lo_ - 1e-2 * abs(lo_):
+            total += 1
+            if second < lo_ - 1e-3 * abs(lo_):
                 assert O.rotation_angle_deg(res["quat"][p].cpu().numpy(), qo) <= 1.0
+                checked += 1
         print(f"\ntomogram {i} ({img.shape[0]}^3), template {t.shape[0]}^3, tile {T}: "
               f"{res['count']} peaks, planted at {wl.positions[i][k].tolist()}, found {pos.tolist()}")
+    print(f"rotations: {checked} of {total} unambiguous and checked")
+    assert total > 0 and checked >= total - 2, (checked, total)
 
 
 @pytest.mark.parametrize("n_streams", [1, 3])

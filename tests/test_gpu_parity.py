@@ -16,6 +16,10 @@ from paper_2311_07561_amd import synth, ttm
 pytestmark = pytest.mark.gpu
 
 SCORE_TOL = 1e-4
+# a tensor is ambiguous when its second local maximum more than 5 degrees from
+# the first is within this fraction of |lambda|: rotations are compared only
+# where it is not
+AMBIGUOUS = 1e-3
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -175,12 +179,16 @@ def test_small_workload_end_to_end():
     # rotations: GPU eigenvector vs the oracle's dominant Z-eigenpair
     quats = res["quat"].cpu().numpy()
     lam = res["lam"].cpu().numpy()
+    checked = 0
     for i in range(len(got_peaks)):
         qo, lo, second = O.dominant_z_eigenpair(C_ref[i], n, n_brute=100000)
         assert abs(lam[i] - lo) <= 1e-6 * abs(lo) + 1e-9
-        if second > lo - 1e-3 * abs(lo):
+        if second > lo - AMBIGUOUS * abs(lo):
             continue        # ambiguous: a second maximum as high as the first
         assert O.rotation_angle_deg(quats[i], qo) <= 1.0
+        checked += 1
+    # at order 2 the objective has one maximum up to sign: every peak is checked
+    assert checked == len(got_peaks) == 8, checked
     assert np.all((res["flags"].cpu().numpy() & ttm.POSE_NOT_CONVERGED) == 0)
 
 
@@ -202,8 +210,9 @@ def test_pose_high_order(n):
     qo, lo, second = O.dominant_z_eigenpair(C_ref[0], n, n_brute=100000)
     lam = res["lam"].cpu().numpy()[0]
     assert abs(lam - lo) <= 1e-6 * abs(lo) + 1e-9
-    if second < lo - 1e-3 * abs(lo):
-        assert O.rotation_angle_deg(res["quat"].cpu().numpy()[0], qo) <= 1.0
+    # the planted copy's tensor has one clear maximum: its rotation is checked
+    assert second < lo - AMBIGUOUS * abs(lo), (lo, second)
+    assert O.rotation_angle_deg(res["quat"].cpu().numpy()[0], qo) <= 1.0
 
 
 def test_tomogram_sampled_parity():
@@ -248,11 +257,16 @@ def test_pose_at_given_positions_and_refinement():
     C_ref = O.tensor_field_at(f64, T, m64, xs)
     assert np.abs(res["C"].cpu().numpy() - C_ref).max() <= 1e-5 * np.abs(C_ref).max()
     assert np.array_equal(res["pos"].cpu().numpy(), xs)
+    checked = 0
     for i in range(len(xs)):
         qo, lo, second = O.dominant_z_eigenpair(C_ref[i], n, n_brute=100000)
         assert abs(res["lam"].cpu().numpy()[i] - lo) <= 1e-6 * abs(lo) + 1e-9
-        if second < lo - 1e-3 * abs(lo):
+        if second < lo - AMBIGUOUS * abs(lo):
             assert O.rotation_angle_deg(res["quat"].cpu().numpy()[i], qo) <= 1.0
+            checked += 1
+    # all four tensors have one clear maximum (the oracle finds no second
+    # maximum within the ambiguity margin): every rotation is checked
+    assert checked == len(xs) == 4, checked
     # refinement: the chosen neighbour maximises lambda
     opt = ttm.default_options(max_peaks=4, refine=1)
     rr = ttm.pose_at(dev(img), comps, dev(mask), n, xs[:2], opt)
@@ -284,6 +298,7 @@ def test_pose_at_refinement_by_ncc():
         ttm.pose_at(dev(img), comps, dev(mask), n, xs, opt)          # refine 2 needs the template
     rr = ttm.pose_at(dev(img), comps, dev(mask), n, xs, opt, tmpl=dev(tmpl))
     offs = O.neighbourhood_offsets()
+    checked = 0
     for i in range(len(xs)):
         pos, qo, lo, ncc, nccs = O.refine_by_ncc(f64, t64, m64, T, n, xs[i], n_brute=30000)
         got = rr["pos"].cpu().numpy()[i]
@@ -296,8 +311,10 @@ def test_pose_at_refinement_by_ncc():
         C_k = O.tensor_field_at(f64, T, m64, np.asarray(got)[None])[0]
         qk, lk, second = O.dominant_z_eigenpair(C_k, n, n_brute=30000)
         assert abs(rr["lam"].cpu().numpy()[i] - lk) <= 1e-6 * abs(lk) + 1e-9
-        if second < lk - 1e-3 * abs(lk):
+        if second < lk - AMBIGUOUS * abs(lk):
             assert O.rotation_angle_deg(rr["quat"].cpu().numpy()[i], qk) <= 1.0
+            checked += 1
+    assert checked == len(xs) == 2, checked
     # the planted copy is found from one voxel off
     assert np.array_equal(rr["pos"].cpu().numpy()[0], [15, 15, 15])
 
@@ -336,11 +353,15 @@ def test_match_uses_the_correlated_field(refine):
         assert np.all(np.abs(got - cand).max(axis=1) <= 1)
     lam = res["lam"].cpu().numpy()
     quats = res["quat"].cpu().numpy()
+    checked = 0
     for i in range(len(got)):
         qo, lo, second = O.dominant_z_eigenpair(C_ref[i], n, n_brute=100000)
         assert abs(lam[i] - lo) <= 2e-4 * abs(lo)
-        if second < lo - 1e-2 * abs(lo):
+        if second < lo - AMBIGUOUS * abs(lo):
             assert O.rotation_angle_deg(quats[i], qo) <= 1.0
+            checked += 1
+    # the six peaks of this workload have one clear maximum each
+    assert checked == len(got) == 6, checked
     if refine == 1:
         # the reported neighbour maximises the eigenvalue among the 27 (oracle,
         # up to the float32 field precision)
@@ -456,3 +477,152 @@ def test_match_iterated_refinement():
         assert O.rotation_angle_deg(q3[i], qi) <= 0.01
         moved += int(not np.array_equal(pi, p2[i]))
     print(f"\nrefine 3 moved {moved} of {len(p2)} candidates further than refine 2")
+
+
+def _clear_path(trace, tol):
+    """True when every round of an oracle refinement chose its voxel by an NCC
+    margin above tol (both sides then take the same decisions)."""
+    for _, nccs in trace:
+        fin = np.sort(nccs[np.isfinite(nccs)])[::-1]
+        if len(fin) > 1 and fin[0] - fin[1] <= tol:
+            return False
+    return True
+
+
+def test_refine3_against_oracle_small_workload():
+    """refine = 3 against the oracle's iterated NCC refinement
+    (refine_by_ncc_iterated) on the 64^3 / 16^3 / order-2 workload:
+    ttm_pose_at started two voxels off each planted copy along a corner
+    diagonal (direct float64 tensors), and ttm_match from its own candidates
+    (tensors from the float32 field).  Where every round of the oracle's climb
+    decides by a clear NCC margin the final voxel must be the same, and the
+    rotation there within 1 degree of the oracle's eigenpair."""
+    wl = synth.workload_small()
+    n = wl.order
+    q = synth.super_fibonacci(500).astype(np.float32)
+    wts = np.full(len(q), 1.0 / len(q))
+    img, mk, tm = dev(wl.image), dev(wl.mask), dev(wl.template)
+    comps, bank = ttm.build_tensor_template(tm, mk, n, q, wts, image_shape=wl.image.shape)
+    T = oracle_T(wl.template, wl.mask, n, q, wts)
+    f64, m64, t64 = (wl.image.astype(np.float64), wl.mask.astype(np.float64),
+                     wl.template.astype(np.float64))
+    starts = (wl.positions + np.array([[2, -2, 2], [-2, 2, -2], [2, 2, -2]])).astype(np.int32)
+    opt = ttm.default_options(max_peaks=len(starts), refine=3)
+    rr = ttm.pose_at(img, comps, mk, n, starts, opt, tmpl=tm)
+    bufs_opt = ttm.default_options(max_peaks=6, min_dist=8.0, threshold=0.0, refine=3)
+    bufs = ttm.MatchBuffers(wl.image.shape, wl.template.shape, n, bufs_opt, "cuda")
+    ttm.match(img, bank, mk, n, bufs_opt, bufs, tmpl=tm)
+    res = bufs.result()
+    cand = O.find_peaks_fast(bufs.score.cpu().numpy(), wl.template.shape, 0.0, 8.0, 6)
+    cases = [("pose_at", starts[i], rr["pos"].cpu().numpy()[i], rr["quat"].cpu().numpy()[i], 1e-4)
+             for i in range(len(starts))]
+    cases += [("match", cand[i], res["pos"].cpu().numpy()[i], res["quat"].cpu().numpy()[i], 2e-3)
+              for i in range(len(cand))]
+    compared = {"pose_at": 0, "match": 0}
+    for kind, start, got, gq, tol in cases:
+        trace = []
+        pos, qo, lo, ncc, rounds = O.refine_by_ncc_iterated(f64, t64, m64, T, n, start, n_brute=30000,
+                                                            trace=trace)
+        if not _clear_path(trace, tol):
+            continue
+        assert np.array_equal(got, pos), (kind, start, got, pos, rounds)
+        C = O.tensor_field_at(f64, T, m64, pos[None])[0]
+        qk, lk, second = O.dominant_z_eigenpair(C, n, n_brute=30000)
+        assert second < lk - AMBIGUOUS * abs(lk)
+        assert O.rotation_angle_deg(gq, qk) <= 1.0, (kind, start)
+        compared[kind] += 1
+    print(f"\nrefine 3 against the oracle's climb: {compared}")
+    assert compared["pose_at"] == 3 and compared["match"] >= 5, compared
+
+
+def _oracle_climb(args):
+    """Worker: the oracle's iterated NCC refinement from one start on the
+    256^3 tomogram (regenerated from its seed in the worker process)."""
+    start, T, n, tol = args
+    wl = synth.workload_tomogram()
+    trace = []
+    pos, q, lam, ncc, rounds = O.refine_by_ncc_iterated(
+        wl.image.astype(np.float64), wl.template.astype(np.float64), wl.mask.astype(np.float64), T, n,
+        start, n_brute=10000, trace=trace)
+    C = O.tensor_field_at(wl.image.astype(np.float64), T, wl.mask.astype(np.float64), pos[None])[0]
+    qk, lk, second = O.dominant_z_eigenpair(C, n, n_brute=30000)
+    return pos, qk, lk, second, rounds, _clear_path(trace, tol)
+
+
+def test_match_full_size_peaks_and_refine3_against_oracle():
+    """The benchmarked call: ttm_match on the 256^3 / 32^3 / order-4 tomogram
+    with 50 peaks.  At refine 0 its candidates are exactly the oracle picker's
+    on the GPU's own float32 map (all 50); at refine 3, ten of them are followed
+    by the oracle's iterated NCC refinement from the same candidates, and
+    where the oracle's climb decides by a clear margin in every round the
+    final voxel is the same and the rotation within 1 degree."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+    wl = synth.workload_tomogram()
+    n = wl.order
+    q = synth.super_fibonacci(300).astype(np.float32)
+    wts = np.full(len(q), 1.0 / len(q))
+    img, mk, tm = dev(wl.image), dev(wl.mask), dev(wl.template)
+    comps, bank = ttm.build_tensor_template(tm, mk, n, q, wts, image_shape=wl.image.shape)
+    out = {}
+    for rf in (0, 3):
+        opt = ttm.default_options(max_peaks=len(wl.positions), min_dist=16.0, threshold=0.0, refine=rf)
+        bufs = ttm.MatchBuffers(wl.image.shape, wl.template.shape, n, opt, "cuda")
+        ttm.match(img, bank, mk, n, opt, bufs, tmpl=tm)
+        out[rf] = (bufs.score.cpu().numpy(), bufs.result())
+    F0, r0 = out[0]
+    cand = O.find_peaks_fast(F0, wl.template.shape, 0.0, 16.0, len(wl.positions))
+    assert len(cand) == len(wl.positions) == 50
+    assert np.array_equal(r0["pos"].cpu().numpy(), cand)
+    assert np.array_equal(out[3][0], F0)
+    p3, q3 = out[3][1]["pos"].cpu().numpy(), out[3][1]["quat"].cpu().numpy()
+    T = oracle_T(wl.template, wl.mask, n, q, wts)
+    pick = list(range(10))
+    workers = max(1, min(10, os.cpu_count() or 1))
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        ref = list(ex.map(_oracle_climb, [(cand[i], T, n, 2e-3) for i in pick]))
+    compared, moved = 0, 0
+    for i, (pos, qk, lk, second, rounds, clear) in zip(pick, ref):
+        moved += int(rounds > 2)
+        if not clear:
+            continue
+        assert np.array_equal(p3[i], pos), (i, cand[i], p3[i], pos, rounds)
+        if second < lk - AMBIGUOUS * abs(lk):
+            assert O.rotation_angle_deg(q3[i], qk) <= 1.0, i
+        compared += 1
+    print(f"\n256^3 refine 3: {compared} of {len(pick)} climbs compared ({moved} took more than one move)")
+    assert compared >= 8, compared
+
+
+def test_check_finite():
+    """ttm_options.check_finite: a NaN in the image or an infinity in the mask
+    returns TTM_E_NONFINITE (from ttm_correlate and ttm_match) with no output
+    written; a finite input gives the unchecked call's maps bit for bit."""
+    img, tmpl, mask, q, w = rand_setup(71, (32, 32, 32), (8, 8, 8), 4.0, 16)
+    n = 2
+    comps, bank = ttm.build_tensor_template(dev(tmpl), dev(mask), n, q, w, image_shape=(32, 32, 32))
+    chk = ttm.default_options(check_finite=1)
+    s0, w0 = ttm.correlate(dev(img), bank, dev(mask), n)
+    s1, w1 = ttm.correlate(dev(img), bank, dev(mask), n, chk)
+    assert torch.equal(s0, s1) and torch.equal(w0, w1)
+    bad = img.copy()
+    bad[3, 17, 9] = np.nan
+    out = (torch.full((32, 32, 32), 7.0, device="cuda"), torch.full((32, 32, 32), 7.0, device="cuda"))
+    with pytest.raises(ttm.TTMError) as e:
+        ttm.correlate(dev(bad), bank, dev(mask), n, chk, out=out)
+    assert e.value.status == -5
+    torch.cuda.synchronize()
+    assert torch.all(out[0] == 7.0) and torch.all(out[1] == 7.0)
+    badm = mask.copy()
+    badm[0, 0, 0] = np.inf
+    with pytest.raises(ttm.TTMError) as e:
+        ttm.correlate(dev(img), bank, dev(badm), n, chk)
+    assert e.value.status == -5
+    mopt = ttm.default_options(max_peaks=2, check_finite=1)
+    bufs = ttm.MatchBuffers((32, 32, 32), (8, 8, 8), n, mopt, "cuda")
+    with pytest.raises(ttm.TTMError) as e:
+        ttm.match(dev(bad), bank, dev(mask), n, mopt, bufs)
+    assert e.value.status == -5
+    ttm.match(dev(img), bank, dev(mask), n, mopt, bufs)
+    assert torch.equal(bufs.score, s0)

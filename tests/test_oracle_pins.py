@@ -496,6 +496,67 @@ def test_refinement_returns_to_a_noiseless_copy():
         assert len(fin) == 27 and fin.max() == ncc
 
 
+def _order2_matrix(C):
+    """The 4 x 4 symmetric matrix M of a packed order-2 tensor, C Q^2 = Q^T M Q:
+    at order 2 the dominant Z-eigenvalue is the largest eigenvalue of M (a
+    textbook symmetric eigenproblem)."""
+    M = np.zeros((4, 4))
+    for c, a in zip(C, O.multi_indices(2)):
+        i, j = [k for k in range(4) for _ in range(a[k])]
+        M[i, j] = M[j, i] = c
+    return M
+
+
+def _rule_pick(lams):
+    """The selection rule of the eigenvalue refinement, written out: the
+    largest value; the centre (index 13) among equal values, then the lowest
+    neighbour index."""
+    best = max(lams)
+    if lams[13] == best:
+        return 13
+    return min(k for k in range(27) if lams[k] == best)
+
+
+def test_refine_by_eigenvalue_rule_and_ties():
+    # Section 3.4 reading: the candidate moves to the voxel of its 3x3x3
+    # neighbourhood with the largest dominant Z-eigenvalue; the centre first on
+    # ties, then the lower neighbour index.  An image constant along axis 2
+    # makes the three voxels of each (d0, d1) column of the neighbourhood see
+    # bit-identical windows, hence bit-identical tensors and eigenvalues: exact
+    # three-way ties in every column.  At order 2 the 27 eigenvalues are pinned
+    # against numpy's symmetric eigensolver, and the chosen voxel against the
+    # rule applied to them.  At (12, 8, 8) the centre column is largest (the
+    # centre must win over its lower-index equal, 12); at (6, 11, 8) the column
+    # (+1, +1) is (its d2 = -1 voxel, index 24, must win over 25 and 26).
+    n, L = 2, 7
+    rng = _rng(90)
+    g = rng.standard_normal((20, 20))
+    f = np.repeat(g[:, :, None], 16, axis=2)
+    t = synth.make_blob_template(rng, L, 3, L / 2).grid()
+    m = synth.ball_mask(L, L / 2)
+    qs = synth.super_fibonacci(400)
+    T = O.tensor_template(t, m, n, qs, np.full(len(qs), 1.0 / len(qs)))
+    offs = O.neighbourhood_offsets()
+    for x, want in (([12, 8, 8], 13), ([6, 11, 8], 24)):
+        x = np.array(x)
+        pos, q, lam, lams = O.refine_by_eigenvalue(f, T, m, n, x, n_brute=5000)
+        for k in range(0, 27, 3):
+            assert lams[k] == lams[k + 1] == lams[k + 2]
+        C = O.tensor_field_at(f, T, m, x[None] + offs)
+        for k in range(27):
+            ev = np.linalg.eigvalsh(_order2_matrix(C[k]))[-1]
+            assert abs(lams[k] - ev) <= 1e-10 * O.frobenius_norm(C[k], n), (k, lams[k], ev)
+        k = _rule_pick(list(lams))
+        assert k == want, (k, want)
+        assert np.array_equal(pos, x + offs[k]) and lam == lams[k]
+    # a flat neighbourhood: w = 0 and C = 0 at all 27 voxels, every eigenvalue
+    # is 0, and the candidate stays where it is
+    f0 = np.zeros((20, 20, 16))
+    f0[0, 0, 0] = 1.0
+    pos, q, lam, lams = O.refine_by_eigenvalue(f0, T, m, n, np.array([10, 10, 8]), n_brute=2000)
+    assert np.all(lams == 0.0) and np.array_equal(pos, [10, 10, 8])
+
+
 def test_iterated_refinement_climbs_to_a_noiseless_copy():
     # the same nearly noiseless copy, started two voxels away along a corner
     # diagonal: one NCC refinement step moves one voxel; repeated from its own
@@ -865,6 +926,42 @@ def test_planar_eigenpair_closed_forms(n):
     C = np.array([math.comb(n // 2, k // 2) / math.comb(n, k) if k % 2 == 0 else 0.0 for k in range(n + 1)])
     z, lam, second = O.dominant_eigen_2d(C, n)
     assert abs(lam - 1.0) <= 1e-12 and abs(second - 1.0) <= 1e-12
+
+
+def test_planar_local_norm_two_pass_equals_one_pass_fft_and_loops():
+    # ||P_S tau_x f||_S^2 = <(tau_x f)^2, m> - <tau_x f, m>^2 / <1, m> in the
+    # plane (Section 2, with d = 2): the two-pass oracle against the one-pass
+    # form evaluated with the library FFT, and against explicit loops for the
+    # masked mean and variance; a constant window gives w = 0
+    r = _rng(13)
+    f = 3.0 + r.standard_normal((17, 14))
+    L = (7, 6)
+    m = r.uniform(0.2, 1.0, L)
+    m[0, 0] = 0.0
+    c = [l // 2 for l in L]
+    big = np.zeros(f.shape)
+    for u0 in range(L[0]):
+        for u1 in range(L[1]):
+            big[(u0 - c[0]) % f.shape[0], (u1 - c[1]) % f.shape[1]] += m[u0, u1]
+    corr = lambda a: np.real(np.fft.ifft2(np.fft.fft2(a) * np.conj(np.fft.fft2(big))))
+    v = corr(f * f) - corr(f) ** 2 / m.sum()
+    g = np.meshgrid(np.arange(f.shape[0]), np.arange(f.shape[1]), indexing="ij")
+    xs = np.stack([g[0].ravel(), g[1].ravel()], axis=1)
+    w = O.local_norm_at_2d(f, m, xs).reshape(f.shape)
+    assert np.allclose(w, 1.0 / np.sqrt(v), rtol=1e-9)
+    for x in [(0, 0), (8, 5), (16, 13)]:
+        vals, wts = [], []
+        for u0 in range(L[0]):
+            for u1 in range(L[1]):
+                vals.append(f[(x[0] + u0 - c[0]) % 17, (x[1] + u1 - c[1]) % 14])
+                wts.append(m[u0, u1])
+        vals, wts = np.array(vals), np.array(wts)
+        mu = sum(a * b for a, b in zip(vals, wts)) / wts.sum()
+        var = sum(b * (a - mu) ** 2 for a, b in zip(vals, wts))
+        assert w[x] == pytest.approx(1.0 / math.sqrt(var), rel=1e-12)
+    f1 = np.full((17, 14), 2.5)
+    f1[0, 0] = 9.0
+    assert O.local_norm_at_2d(f1, m, np.array([[8, 7]]))[0] == 0.0
 
 
 def test_planar_refinement_returns_to_a_copy():
