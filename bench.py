@@ -18,11 +18,14 @@ Prints one JSON line on stdout (progress goes to stderr).
 from __future__ import annotations
 
 import argparse
+import faulthandler
 import hashlib
 import json
 import os
 import sys
 import time
+
+faulthandler.enable()
 
 import numpy as np
 
@@ -91,8 +94,8 @@ def parse():
     p.add_argument("--rmap-steps", type=int, default=3)
     p.add_argument("--batch", type=int, default=0,
                    help="tomograms of the batching leg (uneven edges 96..320, templates 24/32/48; 0 = skip). "
-                        "Off by default: runs of the 64-tomogram leg have ended with a host segmentation fault "
-                        "after its graph replays, cause not yet found")
+                        "Refused for now: runs of the 64-tomogram leg have ended with a host segmentation fault "
+                        "after its graph replays, and its cause has not been shown")
     p.add_argument("--batch-replays", type=int, default=2)
     p.add_argument("--batch-streams", type=int, default=4, help="concurrent branches of the batch graph")
     p.add_argument("--batch-workers", type=int, default=16, help="processes generating the batch tomograms")
@@ -544,6 +547,10 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only (--gpus 1): the path shards by "
                                    "slabs of the tomogram with a halo, which is not run here", "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.batch > 0:
+        print(json.dumps({"error": "the batching leg (--batch) is refused: runs of it have ended with a host "
+                                   "segmentation fault after its graph replays whose cause has not been shown"}))
         sys.exit(2)
     # the batching leg's tomograms are generated before anything touches the
     # GPU (worker processes are started from a process without a GPU context)
