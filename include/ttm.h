@@ -236,6 +236,29 @@ ttm_status ttm_pose_at(
     const int32_t* positions, int32_t n_pos, int32_t* out_pos,
     float* out_quat, double* out_lambda, int32_t* out_flags, double* out_C,
     void* ws, size_t ws_bytes, hipStream_t stream);
+/* ttm_pose_at for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and outputs as ttm_pose_at, with its scratch (the
+ * image moments, the seed table, the tensors, eigenpairs and NCC values of
+ * the max_peaks x 27 voxels, the mask list and the refinement rounds) in a
+ * static 8 MiB device array of the library instead of a workspace.  The call
+ * allocates nothing (no hipMalloc, no library allocation, no profiler
+ * events) and takes the array's device address once per GPU.
+ *   Limit: the pose scratch of (max_peaks, K = C(n+3,3), refine, n_seeds, L)
+ *   must fit 8 MiB, else TTM_E_WORKSPACE; e.g. max_peaks 64 at refine 3 with
+ *   n_seeds 4096 fits for K <= 84 and L0 L1 L2 <= 64^3.
+ *   The array is one per GPU and shared by every call on it, and keeps the
+ *   last call's contents (nothing in it needs clearing): calls that overlap
+ *   on one GPU (two streams, two threads) race and must be serialised by the
+ *   caller.  `stream` must belong to the current device (else TTM_E_ARG).
+ * Arguments and the other errors as ttm_pose_at. */
+ttm_status ttm_pose_at_noalloc(
+    const float* image, const float* components, const float* mask,
+    const float* tmpl, ttm_dims N, ttm_dims L, int32_t order_n,
+    const ttm_options* opt,
+    const int32_t* positions, int32_t n_pos, int32_t* out_pos,
+    float* out_quat, double* out_lambda, int32_t* out_flags, double* out_C,
+    hipStream_t stream);
 ttm_status ttm_recover_pose(
     const float* score, const float* image, const float* components,
     const float* mask, const float* tmpl, ttm_dims N, ttm_dims L,

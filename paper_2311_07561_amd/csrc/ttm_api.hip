@@ -66,12 +66,23 @@ static Prof& prof() {
   static Prof p;
   return p;
 }
+// set on this thread while a call that must create nothing runs (the
+// profiler's event pairs are created lazily)
+static bool& prof_suppressed() {
+  static thread_local bool off = false;
+  return off;
+}
+struct ProfSuppress {
+  ProfSuppress() { prof_suppressed() = true; }
+  ~ProfSuppress() { prof_suppressed() = false; }
+};
 // RAII: records the start event on construction and the stop event on
 // destruction (both on stream s) when profiling is on.
 struct ProfScope {
   int idx = -1;
   hipStream_t s;
   ProfScope(int cls, hipStream_t st) : s(st) {
+    if (prof_suppressed()) return;
     Prof& p = prof();
     std::lock_guard<std::mutex> g(p.mu);
     if (!p.on) return;
@@ -134,18 +145,21 @@ struct PoseWs {
   // refine 3: per-candidate moved flags, the compact list of a round, its outputs
   int* moved; int* act_pos; int* act_idx; int* act_count; RefineTmp tmp;
 };
-static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refine, int n_seeds) {
+// peaks = false: only the pose part (poses at given positions, no peak
+// search buffers)
+static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refine, int n_seeds,
+                          bool peaks = true) {
   PoseWs w;
   const size_t nb = (size_t)max_peaks * (refine ? 27 : 1);
-  w.hist = c.take<unsigned>(kHistBins);
-  w.ctrl = c.take<unsigned>(16);
-  w.allc = c.take<unsigned long long>((size_t)peaks_bigcap(g));
-  w.cand = c.take<unsigned long long>(kCandCap);
+  w.hist = peaks ? c.take<unsigned>(kHistBins) : nullptr;
+  w.ctrl = peaks ? c.take<unsigned>(16) : nullptr;
+  w.allc = peaks ? c.take<unsigned long long>((size_t)peaks_bigcap(g)) : nullptr;
+  w.cand = peaks ? c.take<unsigned long long>(kCandCap) : nullptr;
   w.seeds = c.take<double>((size_t)n_seeds * 4);
   w.ps.seeds = w.seeds;
   w.stats = c.take<double>(4);
   w.partials = c.take<double>(3 * kStatPartials);
-  w.cand_pos = c.take<int>((size_t)max_peaks * 3);
+  w.cand_pos = peaks ? c.take<int>((size_t)max_peaks * 3) : nullptr;
   w.ps.C = c.take<double>(nb * (size_t)K);
   w.ps.w = c.take<double>(nb);
   w.ps.ok = c.take<int>(nb);
@@ -267,6 +281,39 @@ static hipError_t pencils_inverse_valid(const Geo& g, float2* H, int nb, long ha
     const ttm_status _st = (expr);         \
     if (_st != TTM_OK) return _st;         \
   } while (0)
+
+// ---- the static scratch of ttm_pose_at_noalloc -------------------------------------
+// Device memory that no call allocates: one array per GPU in the library's
+// code object, held until the process ends.  In host code `scratch` names a
+// host-side stand-in; its device address on the current GPU comes from
+// hipGetSymbolAddress, taken once per device and kept.
+constexpr size_t kStaticScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+
+// the device address of `scratch` on the GPU of `stream` (which must be the
+// current device: the symbol is resolved there)
+static ttm_status static_scratch(hipStream_t stream, void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int cur = 0;
+  TTM_TRY(hipGetDevice(&cur));
+  if (stream) {
+    hipDevice_t sd = 0;
+    TTM_TRY(hipStreamGetDevice(stream, &sd));
+    if ((int)sd != cur) return TTM_E_ARG;
+  }
+  if (cur < 0 || cur >= kMaxDevices) return TTM_E_ARG;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[cur]) {
+    void* p = nullptr;
+    TTM_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return TTM_E_HIP;
+    addr[cur] = p;
+  }
+  *out = addr[cur];
+  return TTM_OK;
+}
 
 // the finiteness check of ttm_options.check_finite: the float64 moments
 // (sum f, sum f^2 as mean and variance, and sum m) are finite exactly when no
@@ -515,10 +562,11 @@ ttm_status ttm_recover_pose(const float* score, const float* image, const float*
                            out_peak_score, out_flags, out_C, out_count, w, stream);
 }
 
-ttm_status ttm_pose_at(const float* image, const float* components, const float* mask, const float* tmpl,
-                       ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt, const int32_t* positions,
-                       int32_t n_pos, int32_t* out_pos, float* out_quat, double* out_lambda, int32_t* out_flags,
-                       double* out_C, void* ws, size_t ws_bytes, hipStream_t stream) {
+// host-side checks of a pose_at call (every argument but the workspace)
+static ttm_status pose_at_check(const float* image, const float* components, const float* mask, const float* tmpl,
+                                const ttm_dims& N, const ttm_dims& L, int32_t order_n, const ttm_options* opt,
+                                const int32_t* positions, int32_t n_pos, int32_t* out_pos, float* out_quat,
+                                double* out_lambda, int32_t* out_flags) {
   if (!image || !components || !mask || !opt || !positions || !out_pos || !out_quat || !out_lambda ||
       !out_flags)
     return TTM_E_ARG;
@@ -527,11 +575,15 @@ ttm_status ttm_pose_at(const float* image, const float* components, const float*
   if (K < 0 || !pose_opts_ok(opt)) return TTM_E_ARG;
   if (n_pos < 0 || n_pos > opt->max_peaks) return TTM_E_ARG;
   if (!dims_ok(L) || !any_dims_ok(N) || !fits(L, N)) return TTM_E_SIZE;
-  if (!ws || ws_bytes < ttm_pose_workspace_bytes(N, L, order_n, opt)) return TTM_E_WORKSPACE;
-  if (n_pos == 0) return TTM_OK;
-  const Geo g = make_geo(N, L);
-  Carve c(ws);
-  PoseWs w = pose_layout(c, g, opt->max_peaks, K, opt->refine, opt->n_seeds);
+  return TTM_OK;
+}
+
+// the launch sequence of a pose_at call on a carved workspace
+static ttm_status pose_at_into(const Geo& g, const float* image, const float* components, const float* mask,
+                               const float* tmpl, int32_t order_n, int K, const ttm_options* opt,
+                               const int32_t* positions, int32_t n_pos, int32_t* out_pos, float* out_quat,
+                               double* out_lambda, int32_t* out_flags, double* out_C, PoseWs& w,
+                               hipStream_t stream) {
   TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), nullptr, 0, w.partials, w.stats, stream));
   const int rf = opt->refine == 3 ? 2 : opt->refine;
   TTM_PROF(PC_POSE, launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, n_pos,
@@ -548,6 +600,43 @@ ttm_status ttm_pose_at(const float* image, const float* components, const float*
                            out_quat, out_lambda, nullptr, out_flags, out_C, w, tensor, stream));
   }
   return TTM_OK;
+}
+
+ttm_status ttm_pose_at(const float* image, const float* components, const float* mask, const float* tmpl,
+                       ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt, const int32_t* positions,
+                       int32_t n_pos, int32_t* out_pos, float* out_quat, double* out_lambda, int32_t* out_flags,
+                       double* out_C, void* ws, size_t ws_bytes, hipStream_t stream) {
+  TTM_CALL(pose_at_check(image, components, mask, tmpl, N, L, order_n, opt, positions, n_pos, out_pos, out_quat,
+                         out_lambda, out_flags));
+  if (!ws || ws_bytes < ttm_pose_workspace_bytes(N, L, order_n, opt)) return TTM_E_WORKSPACE;
+  if (n_pos == 0) return TTM_OK;
+  const int K = ttm_num_components(order_n);
+  const Geo g = make_geo(N, L);
+  Carve c(ws);
+  PoseWs w = pose_layout(c, g, opt->max_peaks, K, opt->refine, opt->n_seeds);
+  return pose_at_into(g, image, components, mask, tmpl, order_n, K, opt, positions, n_pos, out_pos, out_quat,
+                      out_lambda, out_flags, out_C, w, stream);
+}
+
+ttm_status ttm_pose_at_noalloc(const float* image, const float* components, const float* mask, const float* tmpl,
+                               ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt,
+                               const int32_t* positions, int32_t n_pos, int32_t* out_pos, float* out_quat,
+                               double* out_lambda, int32_t* out_flags, double* out_C, hipStream_t stream) {
+  TTM_CALL(pose_at_check(image, components, mask, tmpl, N, L, order_n, opt, positions, n_pos, out_pos, out_quat,
+                         out_lambda, out_flags));
+  const int K = ttm_num_components(order_n);
+  const Geo g = make_geo(N, L);
+  Carve need(nullptr);
+  pose_layout(need, g, opt->max_peaks, K, opt->refine, opt->n_seeds, false);
+  if (need.size() > kStaticScratchBytes) return TTM_E_WORKSPACE;
+  void* base = nullptr;
+  TTM_CALL(static_scratch(stream, &base));
+  if (n_pos == 0) return TTM_OK;
+  const ProfSuppress quiet;
+  Carve c(base);
+  PoseWs w = pose_layout(c, g, opt->max_peaks, K, opt->refine, opt->n_seeds, false);
+  return pose_at_into(g, image, components, mask, tmpl, order_n, K, opt, positions, n_pos, out_pos, out_quat,
+                      out_lambda, out_flags, out_C, w, stream);
 }
 
 size_t ttm_match_workspace_bytes(ttm_dims N, ttm_dims L, int32_t order_n, const ttm_options* opt) {

@@ -83,6 +83,7 @@ _SIGS = {
                                 _P, _SZ, _P]),
     "ttm_pose_at": (_I32, [_P, _P, _P, _P, _DIMS, _DIMS, _I32, _OPTP, _P, _I32, _P, _P, _P, _P, _P, _P, _SZ,
                            _P]),
+    "ttm_pose_at_noalloc": (_I32, [_P, _P, _P, _P, _DIMS, _DIMS, _I32, _OPTP, _P, _I32, _P, _P, _P, _P, _P, _P]),
     "ttm_match_workspace_bytes": (_SZ, [_DIMS, _DIMS, _I32, _OPTP]),
     "ttm_match": (_I32, [_P, _DIMS, _P, _DIMS, _I32, _P, _P, _OPTP, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                          _SZ, _P]),
@@ -351,6 +352,28 @@ def pose_at(image: torch.Tensor, components: torch.Tensor, mask: torch.Tensor, o
     if C is not None:
         out["C"] = C
     return out
+
+
+def pose_at_noalloc(image: torch.Tensor, components: torch.Tensor, mask: torch.Tensor, order: int,
+                    positions: torch.Tensor, opt: Options, out: dict, tmpl: torch.Tensor | None = None):
+    """ttm_pose_at_noalloc: ``pose_at`` with the library's static device
+    scratch instead of a workspace; nothing is allocated here either.
+    ``positions`` is an (P, 3) int32 CUDA tensor, ``out`` holds preallocated
+    ``pos`` (P, 3) int32, ``quat`` (P, 4) float32, ``lam`` (P,) float64,
+    ``flags`` (P,) int32 and optionally ``C`` (P, K) float64, all written on
+    the current stream."""
+    dev = image.device
+    P = positions.shape[0]
+    if positions.shape != (P, 3):
+        raise ValueError("positions must be (P, 3)")
+    C = out.get("C")
+    st = lib().ttm_pose_at_noalloc(_dev(image, "image"), _dev(components, "components"), _dev(mask, "mask"),
+                                   _opt_dev(tmpl, "tmpl"), _dims(image.shape), _dims(mask.shape), order,
+                                   ctypes.byref(opt), _i32_dev(positions, "positions"), P,
+                                   _i32_dev(out["pos"], "pos"), out["quat"].data_ptr(), out["lam"].data_ptr(),
+                                   _i32_dev(out["flags"], "flags"), C.data_ptr() if C is not None else None,
+                                   _stream(dev))
+    _check(st, "ttm_pose_at_noalloc")
 
 
 class PoseBuffers:
