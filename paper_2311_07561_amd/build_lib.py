@@ -20,7 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libttm.so")
-SOURCES = ["ttm_fft.hip", "ttm_build.hip", "ttm_pose.hip", "ttm_grad.hip", "ttm_filter.hip", "ttm_rmap.hip", "ttm_tile.hip", "ttm_snorm.hip", "ttm_planar.hip", "ttm_api.hip"]
+SOURCES = ["ttm_fft.hip", "ttm_fft2.hip", "ttm_build.hip", "ttm_pose.hip", "ttm_grad.hip", "ttm_filter.hip", "ttm_rmap.hip", "ttm_tile.hip", "ttm_snorm.hip", "ttm_planar.hip", "ttm_api.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", f"-I{INCLUDE}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

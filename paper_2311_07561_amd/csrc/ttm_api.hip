@@ -127,6 +127,7 @@ static BuildWs build_layout(Carve& c, int nrot, int K) {
 
 struct CorrWs {
   float2* Xf; float2* Xg; float2* H; double* stats; double* partials; float* mu;
+  float* wtmp;   // w when the caller passes none (the two-pass inverse reads it back)
 };
 static CorrWs corr_layout(Carve& c, const Geo& g, int K) {
   CorrWs w;
@@ -136,6 +137,7 @@ static CorrWs corr_layout(Carve& c, const Geo& g, int K) {
   w.stats = c.take<double>(4);
   w.partials = c.take<double>(3 * kStatPartials);
   w.mu = c.take<float>(kMaxK);
+  w.wtmp = two_pass_supported(g) ? c.take<float>((size_t)g.vol()) : nullptr;
   return w;
 }
 
@@ -435,10 +437,13 @@ size_t ttm_correlate_workspace_bytes(ttm_dims N, ttm_dims L, int32_t K) {
 // is written here (out_score is not touched).  stats_in (optional): image
 // statistics taken elsewhere (see image_forward).
 // planar: the K = n + 1 components of a planar tensor (multiplicities C(n, k))
+// two_pass: the two-pass inverse (k_pass1x, k_pass3x) where the shape allows
+// it and only the score and w are wanted; its arrays are then not laid out
+// for k_field_at
 static ttm_status correlate_into(const Geo& g, int order_n, int K, const float* image, const float2* bk,
                                  const float* mask, float eps_v, float* out_score, float* out_w, CorrWs& w,
                                  hipStream_t stream, float* out_C = nullptr, const double* stats_in = nullptr,
-                                 bool planar = false, bool check_finite = false) {
+                                 bool planar = false, bool check_finite = false, bool two_pass = true) {
   const long half = g.half();
   if (check_finite && !stats_in) {
     // the image moments first, checked before anything else is enqueued
@@ -454,6 +459,22 @@ static ttm_status correlate_into(const Geo& g, int order_n, int K, const float* 
   TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream, stats_in));
   // K components and the mask against f, then the mask against f^2
   const Pass1Args p1{w.Xf, bk, K + 1, w.Xg, bk + (long)K * g.bank_slab(), 1, g.bank_slab(), w.H, half};
+  if (two_pass && !out_C && !planar && two_pass_supported(g)) {
+    Pass3Args a;
+    std::memset(&a, 0, sizeof(a));
+    a.H = w.H;
+    a.pstride = half;
+    a.npairs = K;
+    a.mode = P3_SCORE;
+    a.mu = w.mu;
+    a.stats = stats_in ? stats_in : w.stats;
+    a.eps_v = eps_v;
+    a.out_score = out_score;
+    a.out_w = out_w ? out_w : w.wtmp;
+    TTM_PROF(PC_PASS1, launch_pass1x(g, p1, stream));
+    TTM_PROF(PC_PASS3, launch_pass3x(g, a, stream));
+    return TTM_OK;
+  }
   TTM_PROF(PC_PASS1, launch_pass1(g, p1, stream));
   TTM_PROF(PC_PEN_INV, pencils_inverse_valid(g, w.H, K + 2, half, stream));
   Pass3Args a;
@@ -670,7 +691,7 @@ ttm_status ttm_match(const float* image, ttm_dims N, const void* bank, ttm_dims 
   float* wmap = c.take<float>(g.vol());
   float* wout = out_w ? out_w : wmap;
   TTM_CALL(correlate_into(g, order_n, K, image, static_cast<const float2*>(bank), mask, opt->eps_v, out_score,
-                          wout, cw, stream, nullptr, nullptr, false, opt->check_finite != 0));
+                          wout, cw, stream, nullptr, nullptr, false, opt->check_finite != 0, false));
   PeakWs pk{pw.hist, pw.ctrl, pw.allc, pw.cand};
   float* cand_score = reinterpret_cast<float*>(pw.ps.w);
   TTM_PROF(PC_PEAKS, launch_peaks(g, out_score, opt->threshold, opt->min_dist, opt->max_peaks, pk, pw.cand_pos,

@@ -80,6 +80,11 @@ struct Pass1Args {
   long out_stride;
 };
 hipError_t launch_pass1(const Geo& g, const Pass1Args& a, hipStream_t s);
+// the two-pass inverse (axes 1 and 2 of 256): pass A writes the arrays as
+// Z[x0][ja][kb][k2] (axis 0 and the 4-point digit of axis 1 done), pass B
+// reduces them to the score and w (P3_SCORE only)
+bool two_pass_supported(const Geo& g);
+hipError_t launch_pass1x(const Geo& g, const Pass1Args& a, hipStream_t s);
 // last inverse pass (axis-2 C2R) fused with the per-voxel reduction.  Only
 // rows (x0, x1) of the valid region are read; outputs outside it are zero
 // (P3_SCORE, P3_W) or left untouched (P3_MAX).
@@ -101,6 +106,7 @@ struct Pass3Args {
   long c_plane;        // P3_FIELD: W0 W1 W2
 };
 hipError_t launch_pass3(const Geo& g, const Pass3Args& a, hipStream_t s);
+hipError_t launch_pass3x(const Geo& g, const Pass3Args& a, hipStream_t s);
 // classical epilogue: ncc = best * w / V inside the valid region where w > 0
 hipError_t launch_classical_final(const Geo& g, const float* w, float* best, int* idx,
                                   hipStream_t s);

@@ -47,7 +47,12 @@ def test_sizes():
     assert L.ttm_bank_bytes(N, T, 35) == 36 * 32 * 256 * 129 * 8
     half = 256 * 256 * 129 * 8
     ws = L.ttm_correlate_workspace_bytes(N, T, 35)
-    assert ws >= (2 + 37) * half and ws < (2 + 37) * half + (1 << 20)
+    # two image spectra, 37 arrays, and (the two-pass inverse) one float32 w field
+    assert ws >= (2 + 37) * half + 4 * 256 ** 3 and ws < (2 + 37) * half + 4 * 256 ** 3 + (1 << 20)
+    n64 = ttm.Dims(64, 64, 64)
+    h64 = 64 * 64 * 33 * 8
+    ws = L.ttm_correlate_workspace_bytes(n64, T, 35)
+    assert ws >= (2 + 37) * h64 and ws < (2 + 37) * h64 + (1 << 20)
     assert L.ttm_correlate_workspace_bytes(ttm.Dims(0, 1, 1), T, 35) == 0
     assert L.ttm_build_workspace_bytes(T, 4, 100, N) >= 100 * (16 + 8 + 16 + 35 * 8)
     assert L.ttm_build_workspace_bytes(T, 3, 100, N) == 0

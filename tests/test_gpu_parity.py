@@ -646,3 +646,34 @@ def test_check_finite():
     assert e.value.status == -5
     ttm.match(dev(img), bank, dev(mask), n, mopt, bufs)
     assert torch.equal(bufs.score, s0)
+
+
+@pytest.mark.parametrize("N,L,n,r", [
+    ((16, 256, 256), (9, 8, 10), 2, 3.5),
+    ((32, 256, 256), (7, 12, 5), 4, 2.4),
+])
+def test_two_pass_inverse_full_map(N, L, n, r):
+    """Images with 256-long axes 1 and 2 take the two-pass inverse (axis 0
+    with the 4-point digit of axis 1, then the 64-point digit with the axis-2
+    C2R and the reduction): the full score and w maps against the oracle's
+    direct sums, zeros outside the valid region, ragged template boxes."""
+    img, tmpl, mask, q, w = rand_setup(80 + n, N, L, r, 24)
+    s = O.rotated_template(tmpl, mask, q[2])
+    c = np.array(L) // 2
+    x0 = np.array([N[0] // 2, 100, 170])
+    sl = tuple(slice(x0[i] - c[i], x0[i] - c[i] + L[i]) for i in range(3))
+    img[sl] += 3.0 * np.sqrt(mask.sum()) * s.astype(np.float32)
+    comps, bank = ttm.build_tensor_template(dev(tmpl), dev(mask), n, q, w, image_shape=N)
+    score, wv = ttm.correlate(dev(img), bank, dev(mask), n)
+    score_nw, _ = ttm.correlate(dev(img), bank, dev(mask), n, want_w=False)
+    T = oracle_T(tmpl, mask, n, q, w)
+    F_ref = O.score_map(img.astype(np.float64), T, mask.astype(np.float64), n)
+    w_ref = O.w_map(img.astype(np.float64), mask.astype(np.float64))
+    F = score.cpu().numpy()
+    W = wv.cpu().numpy()
+    assert np.abs(F - F_ref).max() <= SCORE_TOL, np.abs(F - F_ref).max()
+    assert np.allclose(W, w_ref, rtol=1e-4, atol=0), np.abs(W / np.where(w_ref > 0, w_ref, 1) - 1).max()
+    vm = O.valid_mask(N, L)
+    assert np.all(F[~vm] == 0) and np.all(W[~vm] == 0)
+    assert torch.equal(score, score_nw)
+    assert F[tuple(x0)] > 0.5 * F.max()
