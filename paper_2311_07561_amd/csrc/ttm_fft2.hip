@@ -216,7 +216,7 @@ struct P3xGeo {
 
 // A.out_w is required here: w is written once the moments are transformed
 // and read back for the score at the end (no registers held across arrays)
-__global__ void __launch_bounds__(kThreadsB)
+__global__ void __launch_bounds__(kThreadsB) __attribute__((amdgpu_waves_per_eu(4, 4)))
     k_pass3x(P3xGeo g, Pass3Args A) {
   constexpr int N2 = 2 * kM;
   constexpr int R1 = Plan<kM>::R1, R2 = Plan<kM>::R2;   // row transforms: 8 x 16
@@ -245,9 +245,9 @@ __global__ void __launch_bounds__(kThreadsB)
     return;
   }
   // column phase: thread (k2, kq) holds the elements kb = kq + 4 b of column k2
-  const int k2 = tid & (kM - 1), kq = tid >> 7;
+  int k2 = tid & (kM - 1), kq = tid >> 7;
   // row phase: thread (p = row jb, a)
-  const int p = tid & (kQ - 1), a = tid >> 6;
+  int p = tid & (kQ - 1), a = tid >> 6;
   const double msum = A.stats[2];
   const double inv_msum = 1.0 / msum;
   const double floor_v = (double)A.eps_v * msum * A.stats[1];
@@ -295,17 +295,15 @@ __global__ void __launch_bounds__(kThreadsB)
         ostage[p * kOutP + 2 * n + 1] = val[j].y;
       }
   };
-  // the next array's column elements are fetched while this one is
-  // transformed
-  float2 nv[16];
-  load(0, nv);
   __syncthreads();   // twiddle tables
 #pragma unroll 1
   for (int it = 0; it < npass; ++it) {
+    // the lane coordinates are made opaque here, so that the LDS and global
+    // addresses derived from them are recomputed in each iteration instead
+    // of being hoisted out of the loop and held in registers
+    asm volatile("" : "+v"(k2), "+v"(kq), "+v"(p), "+v"(a));
     float2 v[16];
-#pragma unroll
-    for (int b = 0; b < 16; ++b) v[b] = nv[b];
-    if (it + 1 < npass) load(it + 1, nv);
+    load(it, v);
     // 16-point inverse transform over b, then e^{2 pi i s kq / Q}
     fft_reg<16, true>(v);
 #pragma unroll
