@@ -174,6 +174,7 @@ static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refi
   w.ps.mcount = c.take<int>(1);
   w.ps.sbest = c.take<double>(nb * 64);
   w.ps.sidx = c.take<int>(nb * 64);
+  w.ps.mom = c.take<double>(nb * 3);
   w.moved = w.act_pos = w.act_idx = w.act_count = nullptr;
   w.tmp = RefineTmp{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   if (refine == 3) {

@@ -164,7 +164,9 @@ struct PoseScratch {
   int* mcount;      // 1: their number
   double* sbest;    // max_peaks * NB * 64: seed scan, best lambda per slot
   int* sidx;        // max_peaks * NB * 64: and its seed index
+  double* mom;      // max_peaks * NB * 3: sum m f, sum m f^2, sum m (direct tensor)
 };
+
 // iterated refinement (refine 3): the rounds after the first (fewer
 // candidates move in each, so from the third round on the NCC kernel spreads
 // each candidate's 27 neighbours over 27 blocks instead of 9, trading

@@ -534,6 +534,161 @@ __global__ void __launch_bounds__(256) k_pose_tensor(PoseGeo g, const float* __r
   }
 }
 
+// ---- the direct tensor at candidates, all neighbours of a candidate together ----
+// G_alpha(y) = <tau_y f, T_alpha> in float64 for the voxels y = x + o of a
+// candidate x: the 27 neighbours (o in {-1, 0, 1}^3) or the voxel itself.  A
+// block takes one candidate, one offset o0 along axis 0 and a group of four
+// components; each thread takes template columns (u0, u2) and walks u1,
+// keeping the 3 x 3 patch f(x + o + u - c), o = (o0, o1, o2), in registers
+// (three new values per step) and a 9 x 4 tile of partial sums (offsets x
+// components).
+// The partial sums are added over the block in a fixed order.  The last
+// component group of each candidate takes the masked moments instead:
+// sum m f, sum m f^2 and sum m per offset, for w (Section 2, local
+// normalisation), which k_pose_direct_finish applies.
+constexpr int kDirThreads = 256;
+constexpr int kDirGroup = 4;   // components per block
+
+template <int O>   // 3: the 27 neighbours; 1: the voxel only
+__global__ void __launch_bounds__(kDirThreads) k_pose_direct(PoseGeo g, const float* __restrict__ image,
+                                                             const float* __restrict__ comps,
+                                                             const float* __restrict__ mask, int K,
+                                                             const int* __restrict__ pos,
+                                                             const int* __restrict__ count_dev, int count_host,
+                                                             double* __restrict__ Gbuf, double* __restrict__ mom) {
+  constexpr int NO = O * O;                  // offsets (o1, o2) per block
+  constexpr int NBT = O * O * O;
+  __shared__ double red[4][NO * kDirGroup];
+  const int p = blockIdx.x;
+  const int count = count_dev ? count_dev[0] : count_host;
+  if (p >= count) return;
+  const int o0 = (int)blockIdx.y - (O / 2);
+  const int ag = blockIdx.z;
+  const int ngroups = (K + kDirGroup - 1) / kDirGroup;
+  const bool moments = ag == ngroups;
+  const int L0 = g.L0, L1 = g.L1, L2 = g.L2;
+  const long nL = (long)L0 * L1 * L2;
+  const int tid = threadIdx.x;
+  // window origin: image voxel of template voxel u = 0 at offset o = 0
+  const int b0 = pos[3 * p] - L0 / 2 + o0, b1 = pos[3 * p + 1] - L1 / 2, b2 = pos[3 * p + 2] - L2 / 2;
+  const int H = O / 2;
+  double acc[NO][kDirGroup];
+#pragma unroll
+  for (int j = 0; j < NO; ++j)
+#pragma unroll
+    for (int a = 0; a < kDirGroup; ++a) acc[j][a] = 0.0;
+  // f at image (x0, x1, x2), zero outside the image (such neighbours are
+  // outside the valid region and discarded)
+  auto img = [&](int x0, int x1, int x2) -> double {
+    const bool in = x0 >= 0 && x0 < g.n0 && x1 >= 0 && x1 < g.n1 && x2 >= 0 && x2 < g.n2;
+    const float v = image[in ? ((long)x0 * g.n1 + x1) * g.n2 + x2 : 0];
+    return in ? (double)v : 0.0;
+  };
+  // each thread walks template columns (u0, u2) along u1; neighbouring lanes
+  // take neighbouring u2, so every load of the walk is coalesced
+  for (int col = tid; col < L0 * L2; col += kDirThreads) {
+    const int u0 = col / L2, u2 = col - u0 * L2;
+    const int x0 = b0 + u0;
+    // the patch rows u1 - 1, u1, u1 + 1 (O = 3) of columns o2 = -1, 0, 1:
+    // win[i][j] = f at offset (o1, o2) = (i - H, j - H)
+    double win[O][O];
+#pragma unroll
+    for (int i = 0; i + 1 < O; ++i)
+#pragma unroll
+      for (int j = 0; j < O; ++j) win[i + 1][j] = img(x0, b1 + i - H, b2 + u2 + j - H);
+    for (int u1 = 0; u1 < L1; ++u1) {
+#pragma unroll
+      for (int i = 0; i + 1 < O; ++i)
+#pragma unroll
+        for (int j = 0; j < O; ++j) win[i][j] = win[i + 1][j];
+#pragma unroll
+      for (int j = 0; j < O; ++j) win[O - 1][j] = img(x0, b1 + u1 + H, b2 + u2 + j - H);
+      const long tu = ((long)u0 * L1 + u1) * L2 + u2;
+      double t[kDirGroup];
+      if (moments) {
+        const double m = (double)mask[tu];
+        t[0] = m; t[1] = m; t[2] = m; t[3] = 0.0;
+      } else {
+#pragma unroll
+        for (int a = 0; a < kDirGroup; ++a) {
+          const int al = ag * kDirGroup + a;
+          const float v = comps[(al < K ? al : 0) * nL + tu];
+          t[a] = al < K ? (double)v : 0.0;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < O; ++i)
+#pragma unroll
+        for (int j = 0; j < O; ++j) {
+          const double f = win[i][j];
+          if (moments) {
+            acc[i * O + j][0] += t[0] * f;
+            acc[i * O + j][1] += t[1] * f * f;
+            acc[i * O + j][2] += t[2];
+          } else {
+#pragma unroll
+            for (int a = 0; a < kDirGroup; ++a) acc[i * O + j][a] += t[a] * f;
+          }
+        }
+    }
+  }
+  // block sums in a fixed order: waves by shuffles, then the four wave sums
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int j = 0; j < NO; ++j)
+#pragma unroll
+    for (int a = 0; a < kDirGroup; ++a) {
+      double v = acc[j][a];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) red[wave][j * kDirGroup + a] = v;
+    }
+  __syncthreads();
+  if (tid < NO * kDirGroup) {
+    const double sum = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    const int j = tid / kDirGroup, a = tid % kDirGroup;
+    // neighbour index k = 9 (o0 + 1) + 3 (o1 + 1) + (o2 + 1) (O = 3), or 0
+    const int k = O == 3 ? 9 * (o0 + 1) + j : 0;
+    const long b = (long)p * NBT + k;
+    if (moments) {
+      if (a < 3) mom[3 * b + a] = sum;
+    } else {
+      const int al = ag * kDirGroup + a;
+      if (al < K) Gbuf[b * K + al] = sum;
+    }
+  }
+}
+
+// w = 1 / sqrt(sum m f^2 - (sum m f)^2 / sum m) (0 at or below the variance
+// floor), the ok flag (the voxel inside the valid region), C_alpha = w G_alpha
+__global__ void __launch_bounds__(256) k_pose_direct_finish(PoseGeo g, int K, const double* __restrict__ img_stats,
+                                                            float eps_v, const int* __restrict__ pos,
+                                                            const int* __restrict__ count_dev, int count_host,
+                                                            int NB, int total, const double* __restrict__ mom,
+                                                            double* __restrict__ Cbuf, double* __restrict__ wbuf,
+                                                            int* __restrict__ okbuf) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= total) return;
+  const int p = b / NB, k = b % NB;
+  const int count = count_dev ? count_dev[0] : count_host;
+  if (p >= count) return;
+  int o0, o1, o2;
+  neighbour_offset(k, NB, o0, o1, o2);
+  const int x0 = pos[3 * p] + o0, x1 = pos[3 * p + 1] + o1, x2 = pos[3 * p + 2] + o2;
+  const bool inside = x0 >= g.lo0 && x0 <= g.hi0 && x1 >= g.lo1 && x1 <= g.hi1 && x2 >= g.lo2 && x2 <= g.hi2;
+  if (!inside) {
+    okbuf[b] = 0;
+    wbuf[b] = 0.0;
+    return;
+  }
+  const double s1 = mom[3 * (long)b], s2 = mom[3 * (long)b + 1], msum = mom[3 * (long)b + 2];
+  const double var = s2 - s1 * s1 / msum;
+  const double floor_v = (double)eps_v * msum * img_stats[1];
+  const double w = var > floor_v ? 1.0 / sqrt(var) : 0.0;
+  for (int a = 0; a < K; ++a) Cbuf[(long)b * K + a] *= w;
+  okbuf[b] = 1;
+  wbuf[b] = w;
+}
+
 // Per-wave LDS table of the eigen-solver: the packed tensor entries C.
 struct EigLds {
   double C[kMaxK];
@@ -1382,6 +1537,19 @@ hipError_t launch_pose_tensor(const Geo& gg, const float* image, const float* co
   const PoseGeo g = make_posegeo(gg);
   const int K = num_components(order_n);
   const int NB = refine ? 27 : 1;
+  if (!g.planar) {
+    const int ngroups = (K + kDirGroup - 1) / kDirGroup;
+    if (refine)
+      hipLaunchKernelGGL(k_pose_direct<3>, dim3((unsigned)max_peaks, 3, (unsigned)(ngroups + 1)), dim3(kDirThreads),
+                         0, s, g, image, comps, mask, K, pos_in, count_dev, count_host, ps.C, ps.mom);
+    else
+      hipLaunchKernelGGL(k_pose_direct<1>, dim3((unsigned)max_peaks, 1, (unsigned)(ngroups + 1)), dim3(kDirThreads),
+                         0, s, g, image, comps, mask, K, pos_in, count_dev, count_host, ps.C, ps.mom);
+    const int total = max_peaks * NB;
+    hipLaunchKernelGGL(k_pose_direct_finish, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, K, img_stats,
+                       eps_v, pos_in, count_dev, count_host, NB, total, ps.mom, ps.C, ps.w, ps.ok);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_pose_tensor, dim3((unsigned)(max_peaks * NB)), dim3(256), 0, s, g, image, comps, mask, K,
                      img_stats, eps_v, pos_in, count_dev, count_host, NB, ps.C, ps.w, ps.ok);
   return hipGetLastError();
