@@ -103,6 +103,9 @@ def parse():
                    help="rotations of the planar leg's tensor template and classical matching (0: skip the leg)")
     p.add_argument("--snorm-steps", type=int, default=3,
                    help="timed runs of the S'-normalisation of the peaks (0: skip)")
+    p.add_argument("--legs", default="correlate,c1,c3,classical45k",
+                   help="extra legs: correlate (ttm_correlate + ttm_recover_pose), c1 (64^3 workload, GPU and "
+                        "oracle seconds), c3 (512x512x256, order 6), classical45k (classical TM at 45123 rotations)")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU time of the oracle baseline sample (0 = skip)")
     p.add_argument("--seed", type=int, default=2000)
@@ -138,6 +141,31 @@ def class_bytes(n0, n1, n2, L0, L1, K):
         "pose": 0.0,
         "units": {"U_c": Uc, "U_r": Ur, "B_e": Be, "r0": r0, "r01": r01, "arrays": E},
     }
+
+
+def path_model_bytes(n0, n1, n2, K):
+    """Algorithmic HBM bytes of one correlation (image R2C, the K + 2 spectral
+    products and inverses, local normalisation and score) on the fused
+    two-pass model: every 3-D FFT reads and writes its array twice, the K
+    template spectra are precomputed and read once, the product is fused into
+    the first inverse pass and the score into the last, C is not stored:
+    4 U_r + 14 U_c + 3 K U_c (8.32 GB at 256^3, K = 35)."""
+    Uc = 8.0 * n0 * n1 * (n2 // 2 + 1)
+    Ur = 4.0 * n0 * n1 * n2
+    return 4 * Ur + 14 * Uc + 3 * K * Uc
+
+
+def two_pass_class_bytes(n0, n1, n2, L0, L1, K):
+    """Algorithmic HBM bytes of the kernel classes of ttm_correlate on the
+    two-pass inverse (axes 1 and 2 of 256): pass A as pass 1 (axis 0 and the
+    4-point digit of axis 1), pass B reading the v0 valid planes of the E
+    arrays whole and writing F and w."""
+    cb = class_bytes(n0, n1, n2, L0, L1, K)
+    u = cb["units"]
+    E, Uc, Ur, r0 = u["arrays"], u["U_c"], u["U_r"], u["r0"]
+    cb["pass3_c2r_reduce"] = E * r0 * Uc + 2 * Ur
+    cb.pop("pencils_inv")
+    return cb
 
 
 def time_steps(step, steps, warmup, ttm, torch):
@@ -391,6 +419,119 @@ def run_order(order, wl, img, tmpl, mask, args, ttm, synth, torch, dev, angle, w
     return out
 
 
+def run_correlate(wl, img, mask, bank, K, comps, tmpl, args, ttm, torch):
+    """ttm_correlate alone (the two-pass inverse at this size: pass A = axis 0
+    with the 4-point digit of axis 1, pass B = the 64-point digit, axis-2 C2R
+    and the score), then ttm_recover_pose (direct float64 tensors) on its
+    score at refine 0 / 2 / 3: the boundary's call sequence."""
+    N = wl.image.shape
+    L = wl.template.shape
+    ws = ttm.correlate_workspace(N, L, 4, img.device)
+    out = (torch.empty_like(img), torch.empty_like(img))
+    ms, prof = time_steps(lambda: ttm.correlate(img, bank, mask, 4, workspace=ws, out=out), args.steps,
+                          args.warmup, ttm, torch)
+    cb = two_pass_class_bytes(N[0], N[1], N[2], L[0], L[1], K)
+    kernels = {}
+    for name, (kms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        ms_step = kms / args.steps
+        byts = cb.get(name) or 0.0
+        kernels[name] = {"ms_per_step": round(ms_step, 4), "model_bytes_per_step": byts,
+                         "model_GBps": round(byts / (ms_step / 1e3) / 1e9, 1) if byts else None}
+    pb = path_model_bytes(N[0], N[1], N[2], K)
+    gbps = pb / (ms / 1e3) / 1e9
+    res = {"ms": round(ms, 4), "voxels_per_s": float(np.prod(N)) / (ms / 1e3),
+           "path_model_GB": round(pb / 1e9, 3), "path_GBps": round(gbps, 1),
+           "path_frac": round(gbps / HBM_PEAK_GBPS, 4), "kernels": kernels}
+    log(f"ttm_correlate: {ms:.3f} ms, {pb / 1e9:.2f} GB model at {gbps:.0f} GB/s = {gbps / HBM_PEAK_GBPS:.3f} of peak")
+    pose = {}
+    score = out[0]
+    for rf in (0, 2, 3):
+        opt = ttm.default_options(max_peaks=len(wl.positions), min_dist=float(L[0]) / 2, threshold=0.0, refine=rf)
+        call = lambda: ttm.recover_pose(score, img, comps, mask, 4, opt, want_C=False, tmpl=tmpl)
+        pms, pprof = time_steps(call, max(2, args.steps // 4), 1, ttm, torch)
+        pose[f"refine{rf}_ms"] = round(pms, 4)
+    res["recover_pose"] = pose
+    log(f"ttm_recover_pose (50 peaks): {pose}")
+    return res
+
+
+def run_c1(args, ttm, synth, torch, dev, angle):
+    """The 64^3 / 16^3 / order-2 workload (3 plants, sigma 0.3): the GPU
+    seconds of the whole TTM path (build and match, refine 3) and of
+    classical matching at 500 rotations; the CPU seconds of the same work by
+    the oracle are in cpu_baseline."""
+    wl = synth.workload_small()
+    L = wl.template.shape
+    n = wl.order
+    q = synth.super_fibonacci(500).astype(np.float32)
+    w = np.full(len(q), 1.0 / len(q))
+    img, tm, mk = (torch.as_tensor(a, device=dev) for a in (wl.image, wl.template, wl.mask))
+    ttm.build_tensor_template(tm, mk, n, q, w, image_shape=wl.image.shape)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    comps, bank = ttm.build_tensor_template(tm, mk, n, q, w, image_shape=wl.image.shape)
+    torch.cuda.synchronize()
+    build_ms = (time.time() - t0) * 1e3
+    opt = ttm.default_options(max_peaks=len(wl.positions), min_dist=float(L[0]) / 2, threshold=0.0, refine=3)
+    bufs = ttm.MatchBuffers(wl.image.shape, L, n, opt, dev)
+    ms, _ = time_steps(lambda: ttm.match(img, bank, mk, n, opt, bufs, tmpl=tm), args.steps, args.warmup, ttm, torch)
+    res = bufs.result()
+    det = match_errors(res["pos"].cpu().numpy(), res["quat"].cpu().numpy(), wl.positions, wl.true_quats, angle)
+    ttm.tm_classical(img, tm, mk, q[:16])
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    best, idx = ttm.tm_classical(img, tm, mk, q)
+    c1.record()
+    torch.cuda.synchronize()
+    cms = c0.elapsed_time(c1)
+    idx_np = idx.cpu().numpy()
+    at = [angle(q[idx_np[tuple(p)]], t) for p, t in zip(wl.positions, wl.true_quats)]
+    log(f"c1 {wl.name}: build {build_ms:.2f} ms, match {ms:.3f} ms, classical 500 rotations {cms:.2f} ms")
+    return {"workload": wl.name, "rotations": len(q), "gpu_build_ms": round(build_ms, 3),
+            "gpu_match_ms": round(ms, 4), "gpu_ttm_seconds": round((build_ms + ms) / 1e3, 6),
+            "gpu_classical_ms": round(cms, 3), "gpu_classical_seconds": round(cms / 1e3, 6),
+            "ttm_pose_detected": dict(err_stats(det), recall=len(det) / len(wl.positions)),
+            "classical_pose_at_planted": err_stats(at)}
+
+
+def run_c3(args, ttm, synth, torch, dev, angle):
+    """The 512 x 512 x 256 / 40^3 / order-6 workload (84 components, 40
+    plants): build at 10^4 rotations, ttm_match (refine 3) and ttm_correlate
+    per tomogram.  The per-output error against the float64 oracle is the
+    precision test's (tests/test_gpu_precision.py)."""
+    wl = synth.workload_precision()
+    N, L, n = wl.image.shape, wl.template.shape, wl.order
+    K = ttm.num_components(n)
+    img, tm, mk = (torch.as_tensor(a, device=dev) for a in (wl.image, wl.template, wl.mask))
+    q = synth.super_fibonacci(args.build_rotations).astype(np.float32)
+    w = np.full(len(q), 1.0 / len(q))
+    torch.cuda.synchronize()
+    t0 = time.time()
+    comps, bank = ttm.build_tensor_template(tm, mk, n, q, w, image_shape=N)
+    torch.cuda.synchronize()
+    build_ms = (time.time() - t0) * 1e3
+    opt = ttm.default_options(max_peaks=len(wl.positions), min_dist=float(L[0]) / 2, threshold=0.0, refine=3)
+    bufs = ttm.MatchBuffers(N, L, n, opt, dev)
+    steps = max(3, args.steps // 4)
+    ms, _ = time_steps(lambda: ttm.match(img, bank, mk, n, opt, bufs, tmpl=tm), steps, 1, ttm, torch)
+    res = bufs.result()
+    det = match_errors(res["pos"].cpu().numpy(), res["quat"].cpu().numpy(), wl.positions, wl.true_quats, angle)
+    del bufs
+    ws = ttm.correlate_workspace(N, L, n, dev)
+    out = (torch.empty_like(img), torch.empty_like(img))
+    cms, _ = time_steps(lambda: ttm.correlate(img, bank, mk, n, workspace=ws, out=out), steps, 1, ttm, torch)
+    pb = path_model_bytes(N[0], N[1], N[2], K)
+    log(f"c3 {wl.name}: build {build_ms:.1f} ms, match {ms:.3f} ms, correlate {cms:.3f} ms")
+    return {"workload": wl.name, "order": n, "components": K, "build_ms": round(build_ms, 1),
+            "match_ms": round(ms, 4), "voxels_per_s": float(np.prod(N)) / (ms / 1e3),
+            "correlate_ms": round(cms, 4), "path_model_GB": round(pb / 1e9, 3),
+            "path_frac": round(pb / (cms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "pose_detected": dict(err_stats(det), recall=len(det) / len(wl.positions))}
+
+
 def run_rotation_map(wl, img, mask, bank, K, args, ttm, synth, torch, dev, angle):
     """The all-voxel rotation map at the same workload: the correlation with
     the field kept, the fp16 MFMA seed scan (dominant kernel: 2 V_valid J K
@@ -620,6 +761,16 @@ def main():
            "step_model_GBps": round(sum(k["model_bytes_per_step"] for k in kernels.values()) /
                                     (ms_per_step / 1e3) / 1e9, 1)}
 
+    legs = set(x for x in args.legs.split(",") if x)
+    corr = None
+    if "correlate" in legs:
+        corr = run_correlate(wl, img, mask, main_run["_bank"], K, main_run["_comps"], tmpl, args, ttm, torch)
+    hbm["path_model_GB"] = round(path_model_bytes(N[0], N[1], N[2], K) / 1e9, 3)
+    hbm["match_correlate_path_frac"] = round(path_model_bytes(N[0], N[1], N[2], K) / (corr_ms / 1e3) / 1e9 /
+                                             HBM_PEAK_GBPS, 4)
+    if corr:
+        hbm["correlate_path_frac"] = corr["path_frac"]
+
     rmap = None
     if args.rmap_seeds > 0:
         rmap = run_rotation_map(wl, img, mask, main_run["_bank"], K, args, ttm, synth, torch, dev, angle)
@@ -660,16 +811,39 @@ def main():
         cq = np.array([qc[idx_np[tuple(p)]] for p in cpos]) if len(cpos) else np.zeros((0, 4))
         det = match_errors(cpos, cq, wl.positions, wl.true_quats, angle)
         step_deg = (8 * np.pi ** 2 / args.classical_rotations) ** (1.0 / 3.0) * 180 / np.pi
+        c45 = None
+        if "classical45k" in legs:
+            q45 = synth.super_fibonacci(45123).astype(np.float32)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b45, i45 = ttm.tm_classical(img, tmpl, mask, q45)
+            e1.record()
+            torch.cuda.synchronize()
+            ms45 = e0.elapsed_time(e1)
+            i45 = i45.cpu().numpy()
+            at45 = [angle(q45[i45[tuple(p)]], t) for p, t in zip(wl.positions, wl.true_quats)]
+            c45 = {"rotations": 45123, "sampling_step_deg": round((8 * np.pi ** 2 / 45123) ** (1 / 3) * 180 / np.pi, 2),
+                   "ms": round(ms45, 2), "speedup_ttm_order4_vs_classical": round(ms45 / ms_per_step, 1),
+                   "speedup_ttm_order6_vs_classical": round(ms45 / order6["ms_per_step"], 1) if order6 else None,
+                   "pose_at_planted": err_stats(at45)}
+            log(f"classical TM 45123 rotations: {ms45:.1f} ms, pose at planted {err_stats(at45)}")
+            del b45
         classical = {"rotations": args.classical_rotations, "ms": round(cms, 2),
                      "voxels_per_s": V / (cms / 1e3),
                      "speedup_ttm_order4_vs_classical": round(cms / ms_per_step, 1),
                      "speedup_ttm_order6_vs_classical": round(cms / order6["ms_per_step"], 1) if order6 else None,
                      "sampling_step_deg": round(step_deg, 2),
                      "pose_at_planted": err_stats(at),
-                     "pose_detected": dict(err_stats(det), recall=len(det) / len(wl.positions))}
+                     "pose_detected": dict(err_stats(det), recall=len(det) / len(wl.positions)),
+                     "at_45123_rotations": c45}
         del best, idx
 
-    cpu = cpu_baseline(wl, args.cpu_seconds) if args.cpu_seconds > 0 else None
+    c1 = run_c1(args, ttm, synth, torch, dev, angle) if "c1" in legs else None
+    c3 = run_c3(args, ttm, synth, torch, dev, angle) if "c3" in legs else None
+
+    cpu = cpu_baseline(wl, args.cpu_seconds, "c1" in legs) if args.cpu_seconds > 0 else None
+    if c1 and cpu and cpu.get("c1"):
+        c1["cpu"] = cpu["c1"]
 
     ttm4 = {k: v for k, v in main_run.items() if not k.startswith("_")}
     ttm4["ms_per_step"] = round(ttm4["ms_per_step"], 4)
@@ -685,6 +859,9 @@ def main():
         "cpu_baseline": cpu,
         "ttm_order4": ttm4,
         "ttm_order6": order6,
+        "correlate": corr,
+        "c1": c1,
+        "c3": c3,
         "rotation_map": rmap,
         "batch": batch,
         "planar": planar,
@@ -697,9 +874,13 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(wl, seconds):
+def cpu_baseline(wl, seconds, with_c1=False):
     """The FP64 oracle (direct spatial sums) at sampled voxels of the same
-    tomogram: voxels/s for local normalisation + tensor field + score."""
+    tomogram: voxels/s for local normalisation + tensor field + score.  With
+    with_c1, also the 64^3 / 16^3 / order-2 workload's CPU seconds: the
+    tensor template (500 rotations) and the full-field score map by direct
+    sums, and classical matching at 500 rotations extrapolated from two
+    rotations over the whole valid region."""
     from oracle import ttm_oracle as O
     from paper_2311_07561_amd import synth
     try:
@@ -727,7 +908,26 @@ def cpu_baseline(wl, seconds):
     count = int(max(probe, min(65536, probe * seconds / max(tp, 1e-3))))
     t = run(count)
     log(f"oracle: {count} voxels in {t:.1f}s")
-    return {"value": count / t, "unit": "voxels/s", "cores": threads, "kind": "oracle",
+    c1 = None
+    if with_c1:
+        s1 = synth.workload_small()
+        q1 = synth.super_fibonacci(500)
+        f1, m1, t1 = (a.astype(np.float64) for a in (s1.image, s1.mask, s1.template))
+        c0 = time.perf_counter()
+        T1 = O.tensor_template(t1, m1, s1.order, q1, np.full(len(q1), 1.0 / len(q1)))
+        tb = time.perf_counter() - c0
+        xs1 = np.argwhere(O.valid_mask(s1.image.shape, s1.template.shape))
+        c0 = time.perf_counter()
+        O.score_from_field(O.tensor_field_at(f1, T1, m1, xs1), s1.order)
+        tf = time.perf_counter() - c0
+        c0 = time.perf_counter()
+        O.classical_best_at(f1, t1, m1, q1[:2], xs1)
+        tc = (time.perf_counter() - c0) * len(q1) / 2
+        log(f"oracle c1: build {tb:.1f}s, full field {tf:.1f}s, classical 500 rotations ~{tc:.0f}s (from 2)")
+        c1 = {"workload": s1.name, "ttm_build_seconds": round(tb, 2), "ttm_field_seconds": round(tf, 2),
+              "ttm_seconds": round(tb + tf, 2), "classical_500_seconds_extrapolated": round(tc, 1),
+              "classical_rotations_timed": 2, "valid_voxels": len(xs1), "cores": threads}
+    return {"value": count / t, "unit": "voxels/s", "cores": threads, "kind": "oracle", "c1": c1,
             "sample": f"{count} random valid voxels of the 256^3 tomogram: FP64 direct local normalisation "
                       f"+ {wl.template.shape[0]}^3-window 35-component tensor field + Frobenius score "
                       f"(tensor template built beforehand with 64 rotations, not timed); window gathers "
