@@ -144,8 +144,8 @@ static CorrWs corr_layout(Carve& c, const Geo& g, int K) {
 struct PoseWs {
   unsigned* hist; unsigned* ctrl; unsigned long long* allc; unsigned long long* cand; double* stats;
   double* partials; int* cand_pos; double* seeds; PoseScratch ps;
-  // refine 3: per-candidate moved flags, the compact list of a round, its outputs
-  int* moved; int* act_pos; int* act_idx; int* act_count; RefineTmp tmp;
+  // refine 3: per-candidate moved flags, the compact list of a round
+  int* moved; int* act_pos; int* act_idx; int* act_count;
 };
 // peaks = false: only the pose part (poses at given positions, no peak
 // search buffers)
@@ -175,49 +175,40 @@ static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refi
   w.ps.sbest = c.take<double>(nb * 64);
   w.ps.sidx = c.take<int>(nb * 64);
   w.ps.mom = c.take<double>(nb * 3);
+  w.ps.mbits = c.take<unsigned long long>((size_t)mask_bricks(g.L0, g.L1, g.L2));
   w.moved = w.act_pos = w.act_idx = w.act_count = nullptr;
-  w.tmp = RefineTmp{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   if (refine == 3) {
     const size_t P = (size_t)max_peaks;
     w.moved = c.take<int>(P);
     w.act_pos = c.take<int>(P * 3);
     w.act_idx = c.take<int>(P);
     w.act_count = c.take<int>(1);
-    w.tmp.pos = c.take<int>(P * 3);
-    w.tmp.quat = c.take<float>(P * 4);
-    w.tmp.lam = c.take<double>(P);
-    w.tmp.score = c.take<float>(P);
-    w.tmp.flags = c.take<int>(P);
-    w.tmp.C = c.take<double>(P * (size_t)K);
   }
   return w;
 }
 
-// refine 3: after the first round (the refinement of refine 2, already
-// written to the outputs from the start positions), rounds on the candidates
-// whose position changed, until none moves or kRefineRounds rounds in all.
-// Most candidates move in the first round, so the second spreads each
-// candidate's neighbours over 9 blocks as the first does; the later rounds,
-// with few candidates left, over 27.
-// tensor(pos, count_dev) fills the pose scratch with C_n at the 27
+// refine 3: after the first round (the refinement of refine 2 from the
+// start positions, already written to the outputs, with w.moved set for the
+// candidates that moved), rounds on the candidates whose position changed,
+// until none moves or kRefineRounds rounds in all.  Most candidates move in
+// the first round, so the second spreads each candidate's neighbours over 9
+// blocks as the first does; the later rounds, with few candidates left, over
+// 27.  tensor(pos, count_dev) fills the pose scratch with C_n at the 27
 // neighbours of the listed candidates.
 template <class TensorFn>
-static ttm_status refine_rounds(const Geo& g, const float* score, int order_n, int K, const ttm_options* opt,
-                                int max_peaks, const int* count_dev, int count_host, const int* start,
-                                const float* image, const float* tmpl, const float* mask, int32_t* out_pos,
-                                float* out_quat, double* out_lambda, float* out_score, int32_t* out_flags,
-                                double* out_C, PoseWs& w, TensorFn tensor, hipStream_t stream) {
-  TTM_PROF(PC_POSE, launch_refine_init(count_dev, count_host, start, out_pos, w.moved, max_peaks, stream));
+static ttm_status refine_rounds(const Geo& g, const float* score, int order_n, const ttm_options* opt,
+                                int max_peaks, const int* count_dev, int count_host, const float* image,
+                                const float* tmpl, const float* mask, int32_t* out_pos, float* out_quat,
+                                double* out_lambda, float* out_score, int32_t* out_flags, double* out_C, PoseWs& w,
+                                TensorFn tensor, hipStream_t stream) {
   for (int r = 1; r < kRefineRounds; ++r) {
     TTM_PROF(PC_POSE, launch_refine_compact(count_dev, count_host, w.moved, out_pos, w.act_pos, w.act_idx,
                                             w.act_count, stream));
     TTM_PROF(PC_POSE, tensor(w.act_pos, w.act_count));
     TTM_PROF(PC_POSE, launch_pose_solve(g, score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
-                                        max_peaks, 2, w.act_pos, w.act_count, 0, image, tmpl, mask, w.tmp.pos,
-                                        w.tmp.quat, w.tmp.lam, out_score ? w.tmp.score : nullptr, w.tmp.flags,
-                                        out_C ? w.tmp.C : nullptr, w.ps, stream, true, r == 1 ? 9 : 27));
-    TTM_PROF(PC_POSE, launch_refine_scatter(w.act_count, w.act_idx, K, w.tmp, out_pos, out_quat, out_lambda,
-                                            out_score, out_flags, out_C, w.moved, max_peaks, stream));
+                                        max_peaks, 2, w.act_pos, w.act_count, 0, image, tmpl, mask, out_pos,
+                                        out_quat, out_lambda, out_score, out_flags, out_C, w.ps, stream, true,
+                                        r == 1 ? 9 : 27, w.act_idx, w.moved));
   }
   return TTM_OK;
 }
@@ -545,14 +536,14 @@ static ttm_status recover_pose_into(const Geo& g, const float* score, const floa
   TTM_PROF(PC_POSE, launch_pose_solve(g, score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
                                       opt->max_peaks, rf, w.cand_pos, out_count, 0, image, tmpl, mask,
                                       out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, w.ps,
-                                      stream));
+                                      stream, false, 9, nullptr, w.moved));
   if (opt->refine == 3) {
     auto tensor = [&](const int* pos, const int* cnt) {
       return launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, opt->max_peaks, 2, pos,
                                 cnt, 0, w.ps, stream);
     };
-    TTM_CALL(refine_rounds(g, score, order_n, K, opt, opt->max_peaks, out_count, 0, w.cand_pos, image, tmpl, mask,
-                           out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, w, tensor, stream));
+    TTM_CALL(refine_rounds(g, score, order_n, opt, opt->max_peaks, out_count, 0, image, tmpl, mask, out_pos,
+                           out_quat, out_lambda, out_peak_score, out_flags, out_C, w, tensor, stream));
   }
   return TTM_OK;
 }
@@ -612,14 +603,15 @@ static ttm_status pose_at_into(const Geo& g, const float* image, const float* co
                                        rf, positions, nullptr, n_pos, w.ps, stream));
   TTM_PROF(PC_POSE, launch_pose_solve(g, nullptr, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol, n_pos,
                                       rf, positions, nullptr, n_pos, image, tmpl, mask, out_pos, out_quat,
-                                      out_lambda, nullptr, out_flags, out_C, w.ps, stream));
+                                      out_lambda, nullptr, out_flags, out_C, w.ps, stream, false, 9, nullptr,
+                                      w.moved));
   if (opt->refine == 3) {
     auto tensor = [&](const int* pos, const int* cnt) {
       return launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, n_pos, 2, pos, cnt, 0,
                                 w.ps, stream);
     };
-    TTM_CALL(refine_rounds(g, nullptr, order_n, K, opt, n_pos, nullptr, n_pos, positions, image, tmpl, mask, out_pos,
-                           out_quat, out_lambda, nullptr, out_flags, out_C, w, tensor, stream));
+    TTM_CALL(refine_rounds(g, nullptr, order_n, opt, n_pos, nullptr, n_pos, image, tmpl, mask, out_pos, out_quat,
+                           out_lambda, nullptr, out_flags, out_C, w, tensor, stream));
   }
   return TTM_OK;
 }
@@ -703,14 +695,13 @@ ttm_status ttm_match(const float* image, ttm_dims N, const void* bank, ttm_dims 
   TTM_PROF(PC_POSE, launch_pose_solve(g, out_score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
                                       opt->max_peaks, rf, pw.cand_pos, out_count, 0, image, tmpl, mask,
                                       out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, pw.ps,
-                                      stream));
+                                      stream, false, 9, nullptr, pw.moved));
   if (opt->refine == 3) {
     auto tensor = [&](const int* pos, const int* cnt) {
       return launch_field_at(g, cw.H, g.half(), K, wout, opt->max_peaks, 2, pos, cnt, 0, pw.ps, stream);
     };
-    TTM_CALL(refine_rounds(g, out_score, order_n, K, opt, opt->max_peaks, out_count, 0, pw.cand_pos, image, tmpl,
-                           mask, out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, pw, tensor,
-                           stream));
+    TTM_CALL(refine_rounds(g, out_score, order_n, opt, opt->max_peaks, out_count, 0, image, tmpl, mask, out_pos,
+                           out_quat, out_lambda, out_peak_score, out_flags, out_C, pw, tensor, stream));
   }
   return TTM_OK;
 }
@@ -1310,14 +1301,14 @@ ttm_status ttm_match_2d(const float* images, int32_t B, int32_t n1, int32_t n2, 
                                        m.total, 0, w.ps, stream));
   TTM_PROF(PC_POSE, launch_pose_solve(gs, out_score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol, BP, rf,
                                       m.list, m.total, 0, images, tmpl, mask, m.pos3, m.quat3, m.lam3, m.score3,
-                                      m.flags3, nullptr, w.ps, stream));
+                                      m.flags3, nullptr, w.ps, stream, false, 9, nullptr, w.moved));
   if (opt->refine == 3) {
     auto tensor = [&](const int* pos, const int* cnt) {
       return launch_pose_tensor(gs, images, m.comps3, mask, order_n, w.stats, opt->eps_v, BP, 2, pos, cnt, 0, w.ps,
                                 stream);
     };
-    TTM_CALL(refine_rounds(gs, out_score, order_n, K3, opt, BP, m.total, 0, m.list, images, tmpl, mask, m.pos3,
-                           m.quat3, m.lam3, m.score3, m.flags3, nullptr, w, tensor, stream));
+    TTM_CALL(refine_rounds(gs, out_score, order_n, opt, BP, m.total, 0, images, tmpl, mask, m.pos3, m.quat3, m.lam3,
+                           m.score3, m.flags3, nullptr, w, tensor, stream));
   }
   TTM_PROF(PC_POSE, launch_planar_scatter(BP, m.total, m.idx, m.pos3, m.quat3, m.lam3, m.score3, m.flags3, out_pos,
                                           out_z, out_lambda, out_peak_score, out_flags, stream));

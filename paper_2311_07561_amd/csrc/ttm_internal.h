@@ -165,23 +165,19 @@ struct PoseScratch {
   double* sbest;    // max_peaks * NB * 64: seed scan, best lambda per slot
   int* sidx;        // max_peaks * NB * 64: and its seed index
   double* mom;      // max_peaks * NB * 3: sum m f, sum m f^2, sum m (direct tensor)
+  unsigned long long* mbits;  // mask_bricks(L): per 4x4x4 brick of the mask box, its voxels with m != 0
 };
 
 // iterated refinement (refine 3): the rounds after the first (fewer
 // candidates move in each, so from the third round on the NCC kernel spreads
 // each candidate's 27 neighbours over 27 blocks instead of 9, trading
-// template loads for latency)
+// template loads for latency).  Each round refines the candidates whose
+// moved flag is set (compacted into act_pos / act_idx / act_count, their
+// flags cleared) and writes its results to their rows, setting the flag of
+// each candidate that moved again.
 constexpr int kRefineRounds = 4;
-struct RefineTmp {            // one round's outputs, in compact order
-  int* pos; float* quat; double* lam; float* score; int* flags; double* C;
-};
-hipError_t launch_refine_init(const int* count_dev, int count_host, const int* start, const int* pos, int* moved,
-                              int max_peaks, hipStream_t s);
 hipError_t launch_refine_compact(const int* count_dev, int count_host, int* moved, const int* pos, int* act_pos,
                                  int* act_idx, int* act_count, hipStream_t s);
-hipError_t launch_refine_scatter(const int* act_count, const int* act_idx, int K, const RefineTmp& t,
-                                 int* out_pos, float* out_quat, double* out_lambda, float* out_score,
-                                 int* out_flags, double* out_C, int* moved, int max_peaks, hipStream_t s);
 // C_n(x) in float64 by direct window sums at max_peaks candidates (count from
 // count_dev if non-null, else count_host), at the 27 neighbours if refine
 hipError_t launch_pose_tensor(const Geo& g, const float* image, const float* comps, const float* mask,
@@ -197,18 +193,25 @@ hipError_t launch_field_at(const Geo& g, const float2* H, long pstride, int K, c
 // dominant Z-eigenpairs of the tensors in ps and, per candidate, the
 // neighbour with the largest lambda (refine 1) or with the largest NCC of the
 // image window against the template rotated by the voxel's own eigenvector
-// (refine 2: image, tmpl and mask are read)
+// (refine 2: image, tmpl and mask are read).  Candidate p's outputs go to
+// row out_rows[p] (row p if null); moved (if given) gets, per row, whether
+// the candidate left its position.
 hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int n_seeds, int max_iter,
                              double tol, int max_peaks, int refine, const int* pos_in, const int* count_dev,
                              int count_host, const float* image, const float* tmpl, const float* mask,
                              int* out_pos, float* out_quat, double* out_lambda, float* out_score, int* out_flags,
                              double* out_C, const PoseScratch& ps, hipStream_t s, bool reuse_tables = false,
-                             int ncc_groups = 9);
+                             int ncc_groups = 9, const int* out_rows = nullptr, int* moved = nullptr);
 
 // the mask voxels with m != 0 (packed u0 | u1 << 10 | u2 << 20), their
-// values and their count; one block
+// values and their count, in 4x4x4 bricks in C order (C order within a
+// brick).  With bits (mask_bricks words) and at most kMaskFastBricks bricks:
+// the bricks' ballots, then the entries at prefix-sum offsets, over the
+// whole chip; otherwise one block.
+constexpr long kMaskFastBricks = 4096;
+inline long mask_bricks(int L0, int L1, int L2) { return (long)((L0 + 3) / 4) * ((L1 + 3) / 4) * ((L2 + 3) / 4); }
 hipError_t launch_mask_list(const float* mask, int L0, int L1, int L2, unsigned* list, float* mval, int* count,
-                            hipStream_t s);
+                            hipStream_t s, unsigned long long* bits = nullptr);
 
 // --- two-dimensional TTM (ttm_planar.hip) -----------------------------------
 constexpr int kPlanarMaxOrder = 8;

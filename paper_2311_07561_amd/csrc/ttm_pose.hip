@@ -27,6 +27,9 @@ struct PeakGeo {
   int lo0, hi0, lo1, hi1, lo2, hi2;
 };
 
+// candidates sorted in the first round (the second takes kCandCap)
+constexpr unsigned kCandCap1 = 2048;
+
 // control words of the peak search
 enum PeakCtrl { PK_TOTAL = 0, PK_B1 = 1, PK_MORE1 = 2, PK_CNT1 = 3, PK_B2 = 4, PK_MORE2 = 5, PK_CNT2 = 6,
                 PK_REDO = 7, PK_OVER = 8 };
@@ -36,31 +39,44 @@ __device__ __forceinline__ unsigned long long peak_key(float v, long lin) {
   return ((unsigned long long)(0xFFFFFFFFu - __float_as_uint(v)) << 32) | (unsigned long long)lin;
 }
 
-// One pass over the valid region in 4 x 8 x 64 tiles staged (with a one-voxel
-// halo) in LDS: every strict local maximum above the threshold is appended to
-// the full candidate list.  Out-of-image neighbours are not compared (they
-// hold -inf in the tile).
-constexpr int PT0 = 4, PT1 = 8, PT2 = 64;
+// One pass over the valid region in blocks of 4 rows x 64 columns and runs
+// of up to 16 planes along axis 0, staged with a one-voxel halo in LDS:
+// every strict local maximum above the threshold is appended to the full
+// candidate list.  Each thread walks its column (x1, x2) through the run and
+// reduces every plane it reads to the maximum of its 3 x 3 window with and
+// without the centre, so a plane's window is read once and serves the test
+// of its own voxel and of the voxels above and below: v is a strict maximum
+// when it exceeds the window maximum without the centre in its own plane
+// and the window maxima of both neighbouring planes.  The maxima propagate
+// NaN, so a NaN anywhere among the 26 neighbours rejects v, as a comparison
+// with each of them would.  Out-of-image neighbours hold -inf.
+constexpr int QS1 = 4, QS2 = 64, QRUN = 16;
+constexpr int QH0 = QRUN + 2, QH1 = QS1 + 2, QH2 = QS2 + 2;
+
+// max(a, b), NaN when either is NaN
+__device__ __forceinline__ float max_nan(float a, float b) { return (a >= b || a != a) ? a : b; }
+
 __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F, PeakGeo g, float threshold,
                                                     unsigned* __restrict__ ctrl,
                                                     unsigned long long* __restrict__ allc, long bigcap,
                                                     int ztiles, long fplane) {
-  constexpr int H0 = PT0 + 2, H1 = PT1 + 2, H2 = PT2 + 2;
-  __shared__ float tile[H0 * H1 * H2];
+  static_assert(QS1 * QS2 == 256, "one column per thread");
+  __shared__ float tile[QH0 * QH1 * QH2];
+  __shared__ unsigned long long lkeys[QRUN * QS1 * QS2 / 8];   // strict maxima: at most one per 2x2x2 cell
+  __shared__ unsigned lcount, lbase;
   const int tid = threadIdx.x;
-  // several maps (planes of a stack) at once: blockIdx.z = plane * ztiles + tile
+  // several maps (planes of a stack) at once: blockIdx.z = plane * ztiles + run
   const int plane = blockIdx.z / ztiles, bz = blockIdx.z % ztiles;
   F += plane * fplane;
   ctrl += kPeakCtrlWords * plane;
   allc += bigcap * plane;
-  const int b0 = g.lo0 + bz * PT0, b1 = g.lo1 + blockIdx.y * PT1, b2 = g.lo2 + blockIdx.x * PT2;
-  // the tile's planes along axis 0 that hold valid voxels (one for a map of
-  // depth 1): only they and their two halo planes are loaded and tested
-  const int nv0 = min(PT0, g.hi0 - b0 + 1);
-  const int NT = (nv0 + 2) * H1 * H2;
-  // the halo tile, eight loads in flight per thread: each load is
-  // unconditional (of voxel 0 outside the map) so that the compiler issues
-  // them before it waits, and the value outside the map is -inf
+  const int b0 = g.lo0 + bz * QRUN, b1 = g.lo1 + blockIdx.y * QS1, b2 = g.lo2 + blockIdx.x * QS2;
+  // the run's planes that hold valid voxels (one for a map of depth 1) and
+  // their two halo planes
+  const int nv0 = min(QRUN, g.hi0 - b0 + 1);
+  const int NT = (nv0 + 2) * QH1 * QH2;
+  // eight loads in flight per thread: each load is unconditional (of voxel 0
+  // outside the map) so that the compiler issues them before it waits
   constexpr int U = 8;
   for (int e0 = tid; e0 < NT; e0 += 256 * U) {
     float v[U];
@@ -68,7 +84,7 @@ __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F,
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const int e = e0 + 256 * j;
-      const int t2 = e % H2, t1 = (e / H2) % H1, t0 = e / (H1 * H2);
+      const int t2 = e % QH2, t1 = (e / QH2) % QH1, t0 = e / (QH1 * QH2);
       const int y0 = b0 - 1 + t0, y1 = b1 - 1 + t1, y2 = b2 - 1 + t2;
       in[j] = e < NT && y0 >= 0 && y0 < g.n0 && y1 >= 0 && y1 < g.n1 && y2 >= 0 && y2 < g.n2;
       v[j] = F[in[j] ? ((long)y0 * g.n1 + y1) * g.n2 + y2 : 0];
@@ -79,31 +95,37 @@ __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F,
       if (e < NT) tile[e] = in[j] ? v[j] : -INFINITY;
     }
   }
-  __shared__ unsigned long long lkeys[PT0 * PT1 * PT2 / 8];   // strict maxima: at most one per 2x2x2 cell
-  __shared__ unsigned lcount, lbase;
   if (tid == 0) lcount = 0u;
   __syncthreads();
-  // the 26 neighbour reads are unconditional and combined with a bitwise and,
-  // so that they issue together instead of one read, wait and branch each
-  for (int e = tid; e < nv0 * PT1 * PT2; e += 256) {
-    const int t2 = e % PT2, t1 = (e / PT2) % PT1, t0 = e / (PT1 * PT2);
-    const int x0 = b0 + t0, x1 = b1 + t1, x2 = b2 + t2;
-    const int c = ((t0 + 1) * H1 + (t1 + 1)) * H2 + (t2 + 1);
-    const float v = tile[c];
-    bool ok = x0 <= g.hi0 && x1 <= g.hi1 && x2 <= g.hi2 && v > threshold;
-#pragma unroll
-    for (int d0 = -1; d0 <= 1; ++d0)
-#pragma unroll
-      for (int d1 = -1; d1 <= 1; ++d1)
-#pragma unroll
-        for (int d2 = -1; d2 <= 1; ++d2) {
-          if (d0 == 0 && d1 == 0 && d2 == 0) continue;
-          ok = ok & (v > tile[c + (d0 * H1 + d1) * H2 + d2]);
-        }
-    if (!ok) continue;
-    const long lin = ((long)x0 * g.n1 + x1) * g.n2 + x2;
-    const unsigned ls = atomicAdd(&lcount, 1u);
-    lkeys[ls] = peak_key(v, lin);
+  const int t2 = tid % QS2, t1 = tid / QS2;
+  const int x1 = b1 + t1, x2 = b2 + t2;
+  const bool col_ok = x1 <= g.hi1 && x2 <= g.hi2;
+  // window maxima of tile plane t at this column: pe without the centre,
+  // pi with it; v the centre
+  auto window = [&](int t, float& v, float& pe, float& pi) {
+    const float* r = tile + (t * QH1 + t1) * QH2 + t2;
+    const float a0 = max_nan(max_nan(r[0], r[1]), r[2]);
+    const float a2 = max_nan(max_nan(r[2 * QH2], r[2 * QH2 + 1]), r[2 * QH2 + 2]);
+    pe = max_nan(max_nan(a0, a2), max_nan(r[QH2], r[QH2 + 2]));
+    v = r[QH2 + 1];
+    pi = max_nan(pe, v);
+  };
+  float v_c, pe_c, pi_p, pi_c, tmp_v, tmp_e;
+  window(0, tmp_v, tmp_e, pi_p);
+  window(1, v_c, pe_c, pi_c);
+  for (int t = 0; t < nv0; ++t) {
+    float v_n, pe_n, pi_n;
+    window(t + 2, v_n, pe_n, pi_n);
+    // the centre plane t + 1 holds x0 = b0 + t
+    if (col_ok && v_c > threshold && v_c > pe_c && v_c > pi_p && v_c > pi_n) {
+      const long lin = ((long)(b0 + t) * g.n1 + x1) * g.n2 + x2;
+      const unsigned ls = atomicAdd(&lcount, 1u);
+      lkeys[ls] = peak_key(v_c, lin);
+    }
+    pi_p = pi_c;
+    v_c = v_n;
+    pe_c = pe_n;
+    pi_c = pi_n;
   }
   __syncthreads();
   const unsigned nl = lcount;
@@ -146,13 +168,12 @@ __global__ void __launch_bounds__(1024) k_peaks_hist(const unsigned* __restrict_
   }
 }
 
-// round r: the smallest bin b with sum_{k >= b} hist[k] <= cap
-__global__ void __launch_bounds__(1024) k_peaks_select(const unsigned* __restrict__ hist,
-                                                       unsigned* __restrict__ ctrl, int round, unsigned cap) {
-  hist += (long)kHistBins * blockIdx.x;
-  ctrl += kPeakCtrlWords * blockIdx.x;
-  if (round == 2 && ctrl[PK_REDO] == 0u) return;
-  __shared__ unsigned part[1024];
+// round r: the smallest bin b with sum_{k >= b} hist[k] <= cap (one block
+// of 1024 threads; part: 1024 words of LDS); the outcome (bin, whether
+// candidates below it exist) goes to the round's control words and, if
+// out is given, to out[0], out[1] (exactly one thread writes it)
+__device__ void select_bin(const unsigned* __restrict__ hist, unsigned* __restrict__ ctrl, int round,
+                           unsigned cap, unsigned* part, unsigned* out = nullptr) {
   constexpr int per = kHistBins / 1024;
   const int tid = threadIdx.x;
   const int base = round == 1 ? PK_B1 : PK_B2;
@@ -178,27 +199,36 @@ __global__ void __launch_bounds__(1024) k_peaks_select(const unsigned* __restric
     }
     ctrl[base] = (unsigned)b;
     ctrl[base + 1] = 1u;           // candidates below b exist
+    if (out) {
+      out[0] = (unsigned)b;
+      out[1] = 1u;
+    }
   }
   if (tid == 0 && part[0] <= cap) {
     ctrl[base] = 0u;
     ctrl[base + 1] = 0u;
+    if (out) {
+      out[0] = 0u;
+      out[1] = 0u;
+    }
   }
 }
 
-// round r: the candidates whose key bin is >= the round's bin
-__global__ void __launch_bounds__(256) k_peaks_gather(unsigned* __restrict__ ctrl,
-                                                      const unsigned long long* __restrict__ allc, long bigcap,
-                                                      unsigned long long* __restrict__ cand, int round,
-                                                      unsigned cap) {
-  const int plane = blockIdx.y;
-  ctrl += kPeakCtrlWords * plane;
-  allc += bigcap * plane;
-  cand += (long)kCandCap * plane;
-  if (round == 2 && ctrl[PK_REDO] == 0u) return;
-  const unsigned bmin = ctrl[round == 1 ? PK_B1 : PK_B2];
-  unsigned* cnt = &ctrl[round == 1 ? PK_CNT1 : PK_CNT2];
-  const long total = min((long)ctrl[PK_TOTAL], bigcap);
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+__global__ void __launch_bounds__(1024) k_peaks_select(const unsigned* __restrict__ hist,
+                                                       unsigned* __restrict__ ctrl) {
+  hist += (long)kHistBins * blockIdx.x;
+  ctrl += kPeakCtrlWords * blockIdx.x;
+  __shared__ unsigned part[1024];
+  select_bin(hist, ctrl, 1, kCandCap1, part);
+}
+
+// the candidates whose key bin is >= bmin among the first total entries of
+// allc, appended to cand (at most cap; cnt counts them all), each thread
+// taking entries first, first + stride, ...
+__device__ void gather_keys(unsigned* __restrict__ cnt, unsigned bmin, long total,
+                            const unsigned long long* __restrict__ allc, unsigned long long* __restrict__ cand,
+                            unsigned cap, long first, long stride) {
+  for (long i = first; i < total; i += stride) {
     const unsigned long long k = allc[i];
     const unsigned bits = 0xFFFFFFFFu - (unsigned)(k >> 32);
     if ((bits >> 16) >= bmin) {
@@ -206,6 +236,18 @@ __global__ void __launch_bounds__(256) k_peaks_gather(unsigned* __restrict__ ctr
       if (slot < cap) cand[slot] = k;
     }
   }
+}
+
+// round 1: the candidates above the round's bin
+__global__ void __launch_bounds__(256) k_peaks_gather(unsigned* __restrict__ ctrl,
+                                                      const unsigned long long* __restrict__ allc, long bigcap,
+                                                      unsigned long long* __restrict__ cand) {
+  const int plane = blockIdx.y;
+  ctrl += kPeakCtrlWords * plane;
+  allc += bigcap * plane;
+  cand += (long)kCandCap * plane;
+  gather_keys(&ctrl[PK_CNT1], ctrl[PK_B1], min((long)ctrl[PK_TOTAL], bigcap), allc, cand, kCandCap1,
+              (long)blockIdx.x * blockDim.x + threadIdx.x, (long)gridDim.x * blockDim.x);
 }
 
 __device__ __forceinline__ void decode_lin(unsigned long long key, int n1, int n2, int& x0, int& x1, int& x2) {
@@ -216,19 +258,66 @@ __device__ __forceinline__ void decode_lin(unsigned long long key, int n1, int n
   x0 = (int)(r / n1);
 }
 
-// one block: bitonic sort of the round's candidate keys in LDS, in place
-template <int CAP>
-__global__ void __launch_bounds__(1024) k_peaks_sort(const unsigned* __restrict__ ctrl,
-                                                     unsigned long long* __restrict__ cand, int round) {
+// one block: bitonic sort of the round's candidate keys (ascending), in
+// place.  Round 1 (at most 2048 keys): thread t holds the keys t and t + 1024
+// (missing keys are ~0, sorted to the end) in registers; a compare-exchange
+// at distance j < 64 pairs lanes of one wavefront (cross-lane shuffles), at
+// distance 1024 the two keys of one thread, and only distances 64..512 go
+// through LDS.
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int j) {
+  const unsigned lo = (unsigned)__shfl_xor((int)(unsigned)v, j);
+  const unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(v >> 32), j);
+  return ((unsigned long long)hi << 32) | lo;
+}
+// the key that element i keeps after the compare-exchange with its partner
+// i ^ j (holding y) in the merge of blocks of k
+__device__ __forceinline__ unsigned long long bitonic_keep(unsigned long long x, unsigned long long y, int i, int j,
+                                                           int k) {
+  const bool up = (i & k) == 0, lower = (i & j) == 0;
+  return (lower == up) ? (x < y ? x : y) : (x < y ? y : x);
+}
+
+__global__ void __launch_bounds__(1024) k_peaks_sort1(const unsigned* __restrict__ ctrl,
+                                                      unsigned long long* __restrict__ cand) {
   ctrl += kPeakCtrlWords * blockIdx.x;
   cand += (long)kCandCap * blockIdx.x;
-  if (round == 2 && ctrl[PK_REDO] == 0u) return;
-  __shared__ unsigned long long keys[CAP];
+  __shared__ unsigned long long keys[kCandCap1];
+  const unsigned nc = min(ctrl[PK_CNT1], kCandCap1);
+  const int ia = threadIdx.x, ib = threadIdx.x + 1024;
+  unsigned long long a = ia < (int)nc ? cand[ia] : ~0ull;
+  unsigned long long b = ib < (int)nc ? cand[ib] : ~0ull;
+  for (int k = 2; k <= (int)kCandCap1; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      unsigned long long pa, pb;
+      if (j == 1024) {
+        pa = b;
+        pb = a;
+      } else if (j >= 64) {
+        keys[ia] = a;
+        keys[ib] = b;
+        __syncthreads();
+        pa = keys[ia ^ j];
+        pb = keys[ib ^ j];
+        __syncthreads();
+      } else {
+        pa = shfl_xor_u64(a, j);
+        pb = shfl_xor_u64(b, j);
+      }
+      a = bitonic_keep(a, pa, ia, j, k);
+      b = bitonic_keep(b, pb, ib, j, k);
+    }
+  }
+  if (ia < (int)nc) cand[ia] = a;
+  if (ib < (int)nc) cand[ib] = b;
+}
+
+// the whole network in LDS over keys[0, np2) (np2 the power of two >= n,
+// keys past n set to ~0), by a block of 1024 threads
+__device__ void sort_keys_lds(unsigned long long* keys, int n) {
   const int tid = threadIdx.x;
-  const unsigned nc = min(ctrl[round == 1 ? PK_CNT1 : PK_CNT2], (unsigned)CAP);
   int np2 = 1;
-  while (np2 < (int)nc) np2 <<= 1;
-  for (int i = tid; i < np2; i += 1024) keys[i] = (i < (int)nc) ? cand[i] : ~0ull;
+  while (np2 < n) np2 <<= 1;
+  for (int i = n + tid; i < np2; i += 1024) keys[i] = ~0ull;
   __syncthreads();
   for (int k = 2; k <= np2; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
@@ -246,31 +335,25 @@ __global__ void __launch_bounds__(1024) k_peaks_sort(const unsigned* __restrict_
       __syncthreads();
     }
   }
-  for (int i = tid; i < (int)nc; i += 1024) cand[i] = keys[i];
 }
 
-// one wavefront: greedy suppression over the sorted candidates, 64 at a time.
-// Each lane tests its candidate against the accepted list; conflicts inside
-// the chunk are resolved in candidate order with lane broadcasts.  Round 1
-// asks for round 2 (a larger candidate list) when its list ran out before
-// max_peaks peaks were accepted while lower candidates exist.
-__global__ void __launch_bounds__(64) k_peaks_nms(PeakGeo g, unsigned* __restrict__ ctrl,
-                                                  const unsigned long long* __restrict__ cand, int round,
-                                                  unsigned cap, float min_dist, int max_peaks,
-                                                  int* __restrict__ out_pos, float* __restrict__ out_score,
-                                                  int* __restrict__ out_count) {
-  const int plane = blockIdx.x;
-  ctrl += kPeakCtrlWords * plane;
-  cand += (long)kCandCap * plane;
-  out_pos += 3L * max_peaks * plane;
-  out_score += (long)max_peaks * plane;
-  out_count += 2 * plane;
-  if (round == 2 && ctrl[PK_REDO] == 0u) return;
-  __shared__ int acc_pos[3 * 4096];
-  const int lane = threadIdx.x;
-  const unsigned ncount = ctrl[round == 1 ? PK_CNT1 : PK_CNT2];
-  const unsigned nc = min(ncount, cap);
-  const bool more_below = ctrl[round == 1 ? PK_MORE1 : PK_MORE2] != 0u || ncount > cap;
+// LDS writes of a wavefront made visible to its other lanes
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// one wavefront: greedy suppression over the nc sorted candidate keys, 64 at
+// a time.  Each lane tests its candidate against the accepted list
+// (acc_pos, 3 x max_peaks coordinates); conflicts inside the chunk are
+// resolved in candidate order with lane broadcasts.  exhausted: the list ran
+// out before max_peaks peaks were accepted.
+template <class AccT>
+__device__ void nms_wave(const PeakGeo& g, const unsigned long long* keys, unsigned nc, float min_dist,
+                         int max_peaks, AccT* acc_pos, int* __restrict__ out_pos, float* __restrict__ out_score,
+                         int& nacc_out, bool& exhausted_out) {
+  const int lane = threadIdx.x & 63;
   const float d2min = min_dist * min_dist;
   int nacc = 0;
   bool exhausted = true;
@@ -281,13 +364,13 @@ __global__ void __launch_bounds__(64) k_peaks_nms(PeakGeo g, unsigned* __restric
     }
     const int i = base + lane;
     const bool have = i < (int)nc;
-    const unsigned long long key = have ? cand[i] : ~0ull;
+    const unsigned long long key = have ? keys[i] : ~0ull;
     int x0 = 0, x1 = 0, x2 = 0;
     if (have) decode_lin(key, g.n1, g.n2, x0, x1, x2);
     bool sup = !have;
     for (int q = 0; q < nacc && !sup; ++q) {
-      const float d0 = (float)(x0 - acc_pos[3 * q]), d1 = (float)(x1 - acc_pos[3 * q + 1]),
-                  d2 = (float)(x2 - acc_pos[3 * q + 2]);
+      const float d0 = (float)(x0 - (int)acc_pos[3 * q]), d1 = (float)(x1 - (int)acc_pos[3 * q + 1]),
+                  d2 = (float)(x2 - (int)acc_pos[3 * q + 2]);
       if (d0 * d0 + d1 * d1 + d2 * d2 < d2min) sup = true;
     }
     unsigned long long conf = 0ull;
@@ -310,22 +393,99 @@ __global__ void __launch_bounds__(64) k_peaks_nms(PeakGeo g, unsigned* __restric
     }
     if ((accepted >> lane) & 1ull) {
       const int rank = nacc0 + __popcll(accepted & ((1ull << lane) - 1ull));
-      acc_pos[3 * rank] = x0;
-      acc_pos[3 * rank + 1] = x1;
-      acc_pos[3 * rank + 2] = x2;
+      acc_pos[3 * rank] = (AccT)x0;
+      acc_pos[3 * rank + 1] = (AccT)x1;
+      acc_pos[3 * rank + 2] = (AccT)x2;
       out_pos[3 * rank] = x0;
       out_pos[3 * rank + 1] = x1;
       out_pos[3 * rank + 2] = x2;
       out_score[rank] = __uint_as_float(0xFFFFFFFFu - (unsigned)(key >> 32));
     }
-    __syncthreads();
+    wave_sync();
   }
-  if (lane == 0) {
+  nacc_out = nacc;
+  exhausted_out = exhausted;
+}
+
+// round 1's suppression, one wavefront per map; asks for round 2 (a larger
+// candidate list) when its list ran out before max_peaks peaks were
+// accepted while lower candidates exist
+__global__ void __launch_bounds__(64) k_peaks_nms(PeakGeo g, unsigned* __restrict__ ctrl,
+                                                  const unsigned long long* __restrict__ cand, float min_dist,
+                                                  int max_peaks, int* __restrict__ out_pos,
+                                                  float* __restrict__ out_score, int* __restrict__ out_count) {
+  const int plane = blockIdx.x;
+  ctrl += kPeakCtrlWords * plane;
+  cand += (long)kCandCap * plane;
+  out_pos += 3L * max_peaks * plane;
+  out_score += (long)max_peaks * plane;
+  out_count += 2 * plane;
+  __shared__ int acc_pos[3 * 4096];
+  const unsigned ncount = ctrl[PK_CNT1];
+  const bool more_below = ctrl[PK_MORE1] != 0u || ncount > kCandCap1;
+  int nacc = 0;
+  bool exhausted = true;
+  nms_wave(g, cand, min(ncount, kCandCap1), min_dist, max_peaks, acc_pos, out_pos, out_score, nacc, exhausted);
+  if (threadIdx.x == 0) {
     const bool short_list = nacc < max_peaks && exhausted && more_below;
     out_count[0] = nacc;
-    out_count[1] = (round == 2 && short_list) || ctrl[PK_OVER] ? TTM_PEAKS_TRUNCATED : 0;
-    if (round == 1 && short_list) ctrl[PK_REDO] = 1u;
+    out_count[1] = ctrl[PK_OVER] ? TTM_PEAKS_TRUNCATED : 0;
+    if (short_list) ctrl[PK_REDO] = 1u;
   }
+}
+
+// round 2, only where round 1 asked for it, in one block per map: the bin
+// for kCandCap candidates, their gather, a sort in LDS and the suppression
+// by the first wavefront (its accepted coordinates as 16-bit values: every
+// extent is at most 8192)
+__global__ void __launch_bounds__(1024) k_peaks_round2(PeakGeo g, const unsigned* __restrict__ hist,
+                                                       unsigned* __restrict__ ctrl,
+                                                       const unsigned long long* __restrict__ allc, long bigcap,
+                                                       unsigned long long* __restrict__ cand, float min_dist,
+                                                       int max_peaks, int* __restrict__ out_pos,
+                                                       float* __restrict__ out_score, int* __restrict__ out_count) {
+  const int plane = blockIdx.x;
+  hist += (long)kHistBins * plane;
+  ctrl += kPeakCtrlWords * plane;
+  allc += bigcap * plane;
+  cand += (long)kCandCap * plane;
+  out_pos += 3L * max_peaks * plane;
+  out_score += (long)max_peaks * plane;
+  out_count += 2 * plane;
+  if (ctrl[PK_REDO] == 0u) return;
+  __shared__ unsigned long long keys[kCandCap];   // the select's partial sums, then the keys
+  __shared__ short acc_pos[3 * 4096];
+  __shared__ unsigned sel[2], s_count;
+  const int tid = threadIdx.x;
+  select_bin(hist, ctrl, 2, kCandCap, reinterpret_cast<unsigned*>(keys), sel);
+  __syncthreads();
+  const unsigned bmin = sel[0];
+  const bool more_flag = sel[1] != 0u;
+  gather_keys(&ctrl[PK_CNT2], bmin, min((long)ctrl[PK_TOTAL], bigcap), allc, cand, kCandCap, tid, 1024);
+  __syncthreads();
+  // the count from the atomic unit (the counter's cache line was read at the start)
+  if (tid == 0) s_count = atomicAdd(&ctrl[PK_CNT2], 0u);
+  __syncthreads();
+  const unsigned ncount = s_count;
+  const unsigned nc = min(ncount, (unsigned)kCandCap);
+  for (int i = tid; i < (int)nc; i += 1024) keys[i] = cand[i];
+  sort_keys_lds(keys, (int)nc);
+  if (tid >= 64) return;
+  int nacc = 0;
+  bool exhausted = true;
+  nms_wave(g, keys, nc, min_dist, max_peaks, acc_pos, out_pos, out_score, nacc, exhausted);
+  if (tid == 0) {
+    const bool short_list = nacc < max_peaks && exhausted && (more_flag || ncount > (unsigned)kCandCap);
+    out_count[0] = nacc;
+    out_count[1] = short_list || ctrl[PK_OVER] ? TTM_PEAKS_TRUNCATED : 0;
+  }
+}
+
+// the histogram and control words of every map cleared in one launch
+__global__ void k_peaks_clear(unsigned* __restrict__ hist, long nh, unsigned* __restrict__ ctrl, int nc) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nh) hist[i] = 0u;
+  else if (i < nh + nc) ctrl[i - nh] = 0u;
 }
 
 long peaks_bigcap(const Geo& g) { return g.vol() / 8 + 1024; }
@@ -339,29 +499,24 @@ hipError_t launch_peaks(const Geo& gg, const float* score, float threshold, floa
   g.lo1 = gg.c1; g.hi1 = gg.n1 - gg.L1 + gg.c1;
   g.lo2 = gg.c2; g.hi2 = gg.n2 - gg.L2 + gg.c2;
   const long bigcap = peaks_bigcap(gg);
-  hipError_t e;
   const unsigned P = (unsigned)planes;
-  if ((e = launch_fill_i32(reinterpret_cast<int*>(w.hist), (long)kHistBins * planes, 0, s)) != hipSuccess) return e;
-  if ((e = launch_fill_i32(reinterpret_cast<int*>(w.ctrl), (long)kPeakCtrlWords * planes, 0, s)) != hipSuccess)
-    return e;
+  const long nh = (long)kHistBins * planes;
+  const int nctl = kPeakCtrlWords * planes;
+  hipLaunchKernelGGL(k_peaks_clear, dim3((unsigned)((nh + nctl + 255) / 256)), dim3(256), 0, s, w.hist, nh, w.ctrl,
+                     nctl);
   const int e0 = g.hi0 - g.lo0 + 1, e1 = g.hi1 - g.lo1 + 1, e2 = g.hi2 - g.lo2 + 1;
-  const int ztiles = (e0 + PT0 - 1) / PT0;
-  dim3 sgrid((e2 + PT2 - 1) / PT2, (e1 + PT1 - 1) / PT1, (unsigned)ztiles * P);
+  const int ztiles = (e0 + QRUN - 1) / QRUN;
+  dim3 sgrid((e2 + QS2 - 1) / QS2, (e1 + QS1 - 1) / QS1, (unsigned)ztiles * P);
   hipLaunchKernelGGL(k_peaks_scan, sgrid, dim3(256), 0, s, score, g, threshold, w.ctrl, w.allc, bigcap, ztiles,
                      gg.vol());
   hipLaunchKernelGGL(k_peaks_hist, dim3(kHistBlocks, P), dim3(1024), 0, s, w.ctrl, w.allc, bigcap, w.hist);
-  constexpr unsigned cap1 = 2048, cap2 = kCandCap;
-  for (int round = 1; round <= 2; ++round) {
-    const unsigned cap = round == 1 ? cap1 : cap2;
-    hipLaunchKernelGGL(k_peaks_select, dim3(P), dim3(1024), 0, s, w.hist, w.ctrl, round, cap);
-    hipLaunchKernelGGL(k_peaks_gather, dim3(256, P), dim3(256), 0, s, w.ctrl, w.allc, bigcap, w.cand, round, cap);
-    if (round == 1)
-      hipLaunchKernelGGL(k_peaks_sort<cap1>, dim3(P), dim3(1024), 0, s, w.ctrl, w.cand, round);
-    else
-      hipLaunchKernelGGL(k_peaks_sort<cap2>, dim3(P), dim3(1024), 0, s, w.ctrl, w.cand, round);
-    hipLaunchKernelGGL(k_peaks_nms, dim3(P), dim3(64), 0, s, g, w.ctrl, w.cand, round, cap, min_dist, max_peaks,
-                       out_pos, out_score, out_count);
-  }
+  hipLaunchKernelGGL(k_peaks_select, dim3(P), dim3(1024), 0, s, w.hist, w.ctrl);
+  hipLaunchKernelGGL(k_peaks_gather, dim3(256, P), dim3(256), 0, s, w.ctrl, w.allc, bigcap, w.cand);
+  hipLaunchKernelGGL(k_peaks_sort1, dim3(P), dim3(1024), 0, s, w.ctrl, w.cand);
+  hipLaunchKernelGGL(k_peaks_nms, dim3(P), dim3(64), 0, s, g, w.ctrl, w.cand, min_dist, max_peaks, out_pos,
+                     out_score, out_count);
+  hipLaunchKernelGGL(k_peaks_round2, dim3(P), dim3(1024), 0, s, g, w.hist, w.ctrl, w.allc, bigcap, w.cand, min_dist,
+                     max_peaks, out_pos, out_score, out_count);
   return hipGetLastError();
 }
 
@@ -1120,8 +1275,65 @@ __global__ void __launch_bounds__(1024) k_mask_list(const float* __restrict__ ma
   if (tid == 0) count[0] = base;
 }
 
+// the same list over the whole chip: one wavefront per brick takes the
+// ballot of its voxels with m != 0 ...
+__global__ void __launch_bounds__(256) k_mask_bits(const float* __restrict__ mask, int L0, int L1, int L2, int nB,
+                                                   unsigned long long* __restrict__ bits) {
+  const int lane = threadIdx.x & 63;
+  const int br = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (br >= nB) return;
+  const int B1 = (L1 + 3) / 4, B2 = (L2 + 3) / 4;
+  const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
+  const int u0 = 4 * b0 + (lane >> 4), u1 = 4 * b1 + ((lane >> 2) & 3), u2 = 4 * b2 + (lane & 3);
+  const bool in = u0 < L0 && u1 < L1 && u2 < L2;
+  const float m = in ? mask[(u0 * L1 + u1) * L2 + u2] : 0.0f;
+  const unsigned long long bl = __ballot(m != 0.0f);
+  if (lane == 0) bits[br] = bl;
+}
+
+// ... then each block places the voxels of four bricks after the count of
+// all earlier bricks (a sum over their ballots)
+__global__ void __launch_bounds__(256) k_mask_write(const float* __restrict__ mask, int L0, int L1, int L2, int nB,
+                                                    const unsigned long long* __restrict__ bits,
+                                                    unsigned* __restrict__ list, float* __restrict__ mval,
+                                                    int* __restrict__ count) {
+  __shared__ int wsum[4], bc[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int first = blockIdx.x * 4;
+  int acc = 0;
+  for (int i = tid; i < first; i += 256) acc += __popcll(bits[i]);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  const int br = first + wave;
+  const unsigned long long bl = br < nB ? bits[br] : 0ull;
+  if (lane == 0) {
+    wsum[wave] = acc;
+    bc[wave] = __popcll(bl);
+  }
+  __syncthreads();
+  int base = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  for (int w = 0; w < wave; ++w) base += bc[w];
+  if (br >= nB) return;
+  if ((bl >> lane) & 1ull) {
+    const int B1 = (L1 + 3) / 4, B2 = (L2 + 3) / 4;
+    const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
+    const int u0 = 4 * b0 + (lane >> 4), u1 = 4 * b1 + ((lane >> 2) & 3), u2 = 4 * b2 + (lane & 3);
+    const int o = base + __popcll(bl & ((1ull << lane) - 1ull));
+    list[o] = (unsigned)u0 | ((unsigned)u1 << 10) | ((unsigned)u2 << 20);
+    mval[o] = mask[(u0 * L1 + u1) * L2 + u2];
+  }
+  if (br == nB - 1 && lane == 0) count[0] = base + bc[wave];
+}
+
 hipError_t launch_mask_list(const float* mask, int L0, int L1, int L2, unsigned* list, float* mval, int* count,
-                            hipStream_t s) {
+                            hipStream_t s, unsigned long long* bits) {
+  const long nB = mask_bricks(L0, L1, L2);
+  if (bits && nB <= kMaskFastBricks) {
+    const unsigned nblk = (unsigned)((nB + 3) / 4);
+    hipLaunchKernelGGL(k_mask_bits, dim3(nblk), dim3(256), 0, s, mask, L0, L1, L2, (int)nB, bits);
+    hipLaunchKernelGGL(k_mask_write, dim3(nblk), dim3(256), 0, s, mask, L0, L1, L2, (int)nB, bits, list, mval,
+                       count);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_mask_list, dim3(1), dim3(1024), 0, s, mask, L0, L1, L2, list, mval, count);
   return hipGetLastError();
 }
@@ -1363,7 +1575,9 @@ __global__ void __launch_bounds__(NT) k_pose_ncc_lds(PoseGeo g, int ngroups, con
 // (refine 1) or with the largest NCC at its own dominant rotation (refine 2);
 // the centre first on ties, then the lower neighbour index.  One wavefront per
 // candidate: the keys are read in parallel, lane 0 picks and writes the
-// scalars, and the lanes copy the picked tensor together.
+// scalars, and the lanes copy the picked tensor together.  Candidate p's
+// outputs go to row out_rows[p] (row p if null); moved (if given) records
+// whether the candidate left its position.
 __global__ void __launch_bounds__(64) k_pose_pick(PoseGeo g, const float* __restrict__ score, int K,
                                                   const int* __restrict__ pos_in, const int* __restrict__ count_dev,
                                                   int count_host, int NB, const double* __restrict__ Cbuf,
@@ -1372,7 +1586,8 @@ __global__ void __launch_bounds__(64) k_pose_pick(PoseGeo g, const float* __rest
                                                   const double* __restrict__ keybuf, const int* __restrict__ flagbuf,
                                                   int* __restrict__ out_pos, float* __restrict__ out_quat,
                                                   double* __restrict__ out_lambda, float* __restrict__ out_score,
-                                                  int* __restrict__ out_flags, double* __restrict__ out_C) {
+                                                  int* __restrict__ out_flags, double* __restrict__ out_C,
+                                                  const int* __restrict__ out_rows, int* __restrict__ moved) {
   __shared__ double keys[27];
   __shared__ int pick;
   const int p = blockIdx.x;
@@ -1395,20 +1610,23 @@ __global__ void __launch_bounds__(64) k_pose_pick(PoseGeo g, const float* __rest
     int o0, o1, o2;
     neighbour_offset(bk, NB, o0, o1, o2);
     const int x0 = pos_in[3 * p] + o0, x1 = pos_in[3 * p + 1] + o1, x2 = pos_in[3 * p + 2] + o2;
-    out_pos[3 * p] = x0;
-    out_pos[3 * p + 1] = x1;
-    out_pos[3 * p + 2] = x2;
-    for (int d = 0; d < 4; ++d) out_quat[4 * p + d] = qbuf[4 * b + d];
-    out_lambda[p] = lambuf[b];
+    const int r = out_rows ? out_rows[p] : p;
+    out_pos[3 * r] = x0;
+    out_pos[3 * r + 1] = x1;
+    out_pos[3 * r + 2] = x2;
+    for (int d = 0; d < 4; ++d) out_quat[4 * r + d] = qbuf[4 * b + d];
+    out_lambda[r] = lambuf[b];
     int flags = flagbuf[b];
     if (!(wbuf[b] > 0.0)) flags |= TTM_POSE_ZERO_NORM;
-    out_flags[p] = flags;
-    if (out_score) out_score[p] = score ? score[((long)x0 * g.n1 + x1) * g.n2 + x2] : 0.0f;
+    out_flags[r] = flags;
+    if (out_score) out_score[r] = score ? score[((long)x0 * g.n1 + x1) * g.n2 + x2] : 0.0f;
+    if (moved) moved[r] = bk != centre ? 1 : 0;
   }
   if (out_C) {
     __syncthreads();
     const long b = (long)p * NB + pick;
-    for (int k = lane; k < K; k += 64) out_C[(long)p * K + k] = Cbuf[b * K + k];
+    const long r = out_rows ? out_rows[p] : p;
+    for (int k = lane; k < K; k += 64) out_C[r * K + k] = Cbuf[b * K + k];
   }
 }
 
@@ -1416,15 +1634,6 @@ __global__ void __launch_bounds__(64) k_pose_pick(PoseGeo g, const float* __rest
 // iterated refinement (refine 3): after the first refinement, the candidates
 // that moved are compacted into a list that the next round refines again
 // ----------------------------------------------------------------------------
-__global__ void k_refine_init(const int* __restrict__ count_dev, int count_host, const int* __restrict__ start,
-                              const int* __restrict__ pos, int* __restrict__ moved) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = count_dev ? count_dev[0] : count_host;
-  if (p >= n) return;
-  moved[p] = (pos[3 * p] != start[3 * p] || pos[3 * p + 1] != start[3 * p + 1] ||
-              pos[3 * p + 2] != start[3 * p + 2]) ? 1 : 0;
-}
-
 // one block: the moving candidates in index order (an LDS prefix sum per
 // chunk of 1024); their flags are cleared for the round
 __global__ void __launch_bounds__(1024) k_refine_compact(const int* __restrict__ count_dev, int count_host,
@@ -1463,59 +1672,10 @@ __global__ void __launch_bounds__(1024) k_refine_compact(const int* __restrict__
   if (tid == 0) act_count[0] = base;
 }
 
-// the round's results written back to the candidates' rows; a candidate moves
-// on to the next round if its position changed.  One wavefront per entry of
-// the round's list: lane 0 writes the scalars, the lanes copy the tensor.
-__global__ void __launch_bounds__(64) k_refine_scatter(const int* __restrict__ act_count,
-                                                       const int* __restrict__ act_idx, int K,
-                                                       const int* __restrict__ t_pos, const float* __restrict__ t_quat,
-                                                       const double* __restrict__ t_lam,
-                                                       const float* __restrict__ t_score,
-                                                       const int* __restrict__ t_flags, const double* __restrict__ t_C,
-                                                       int* __restrict__ out_pos, float* __restrict__ out_quat,
-                                                       double* __restrict__ out_lambda, float* __restrict__ out_score,
-                                                       int* __restrict__ out_flags, double* __restrict__ out_C,
-                                                       int* __restrict__ moved) {
-  const int j = blockIdx.x;
-  if (j >= act_count[0]) return;
-  const int p = act_idx[j];
-  const int lane = threadIdx.x;
-  if (out_C)
-    for (int k = lane; k < K; k += 64) out_C[(long)p * K + k] = t_C[(long)j * K + k];
-  if (lane != 0) return;
-  bool mv = false;
-  for (int d = 0; d < 3; ++d) {
-    mv = mv || t_pos[3 * j + d] != out_pos[3 * p + d];
-    out_pos[3 * p + d] = t_pos[3 * j + d];
-  }
-  moved[p] = mv ? 1 : 0;
-  for (int d = 0; d < 4; ++d) out_quat[4 * p + d] = t_quat[4 * j + d];
-  out_lambda[p] = t_lam[j];
-  if (out_score) out_score[p] = t_score[j];
-  out_flags[p] = t_flags[j];
-}
-
-hipError_t launch_refine_init(const int* count_dev, int count_host, const int* start, const int* pos, int* moved,
-                              int max_peaks, hipStream_t s) {
-  hipLaunchKernelGGL(k_refine_init, dim3((max_peaks + 255) / 256), dim3(256), 0, s, count_dev, count_host, start,
-                     pos, moved);
-  return hipGetLastError();
-}
-
 hipError_t launch_refine_compact(const int* count_dev, int count_host, int* moved, const int* pos, int* act_pos,
                                  int* act_idx, int* act_count, hipStream_t s) {
   hipLaunchKernelGGL(k_refine_compact, dim3(1), dim3(1024), 0, s, count_dev, count_host, moved, pos, act_pos,
                      act_idx, act_count);
-  return hipGetLastError();
-}
-
-hipError_t launch_refine_scatter(const int* act_count, const int* act_idx, int K, const RefineTmp& t,
-                                 int* out_pos, float* out_quat, double* out_lambda, float* out_score,
-                                 int* out_flags, double* out_C, int* moved, int max_peaks, hipStream_t s) {
-  if (max_peaks < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_refine_scatter, dim3((unsigned)max_peaks), dim3(64), 0, s, act_count, act_idx, K,
-                     t.pos, t.quat, t.lam, t.score, t.flags, t.C, out_pos, out_quat, out_lambda, out_score,
-                     out_flags, out_C, moved);
   return hipGetLastError();
 }
 
@@ -1560,7 +1720,7 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
                              int count_host, const float* image, const float* tmpl, const float* mask,
                              int* out_pos, float* out_quat, double* out_lambda, float* out_score, int* out_flags,
                              double* out_C, const PoseScratch& ps, hipStream_t s, bool reuse_tables,
-                             int ncc_groups) {
+                             int ncc_groups, const int* out_rows, int* moved) {
   const PoseGeo g = make_posegeo(gg);
   const int K = num_components(order_n);
   const int NB = refine ? 27 : 1;
@@ -1616,7 +1776,7 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
   }
   if (refine == 2) {
     if (!reuse_tables)
-      (void)launch_mask_list(mask, g.L0, g.L1, g.L2, ps.mlist, ps.mval, ps.mcount, s);
+      (void)launch_mask_list(mask, g.L0, g.L1, g.L2, ps.mlist, ps.mval, ps.mcount, s, ps.mbits);
     const long lds = ncc_lds_floats(g.L0, g.L1, g.L2);
     const int ngroups = ncc_groups;
     if (lds <= kNccLdsSmall) {
@@ -1637,7 +1797,7 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
   }
   hipLaunchKernelGGL(k_pose_pick, dim3((unsigned)max_peaks), dim3(64), 0, s, g, score, K, pos_in, count_dev,
                      count_host, NB, ps.C, ps.w, ps.q, ps.lam, refine == 2 ? ps.ncc : ps.lam, ps.flags, out_pos,
-                     out_quat, out_lambda, out_score, out_flags, out_C);
+                     out_quat, out_lambda, out_score, out_flags, out_C, out_rows, moved);
   return hipGetLastError();
 }
 

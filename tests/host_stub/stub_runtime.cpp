@@ -571,34 +571,11 @@ hipError_t launch_peaks(const Geo& g, const float* score, float, float, int max_
          _c.push_back(C(out_score, (long)planes * max_peaks, "out_score"));
          _c.push_back(C(out_count, 2L * planes, "out_count")););
 }
-hipError_t launch_refine_init(const int* count_dev, int, const int* start, const int* pos, int* moved, int max_peaks,
-                              hipStream_t s) {
-  LAUNCH("refine_init", s, if (count_dev) _c.push_back(C(count_dev, 1, "count"));
-         _c.push_back(C(start, 3L * max_peaks, "start")); _c.push_back(C(pos, 3L * max_peaks, "pos"));
-         _c.push_back(C(moved, max_peaks, "moved")););
-}
 hipError_t launch_refine_compact(const int* count_dev, int, int* moved, const int* pos, int* act_pos, int* act_idx,
                                  int* act_count, hipStream_t s) {
   LAUNCH("refine_compact", s, if (count_dev) _c.push_back(C(count_dev, 1, "count"));
          _c.push_back(C(moved, 1, "moved")); _c.push_back(C(pos, 3, "pos")); _c.push_back(C(act_pos, 3, "act_pos"));
          _c.push_back(C(act_idx, 1, "act_idx")); _c.push_back(C(act_count, 1, "act_count")););
-}
-hipError_t launch_refine_scatter(const int* act_count, const int* act_idx, int K, const RefineTmp& t, int* out_pos,
-                                 float* out_quat, double* out_lambda, float* out_score, int* out_flags,
-                                 double* out_C, int* moved, int max_peaks, hipStream_t s) {
-  const long P = max_peaks;
-  LAUNCH("refine_scatter", s, _c.push_back(C(act_count, 1, "act_count")); _c.push_back(C(act_idx, P, "act_idx"));
-         _c.push_back(C(t.pos, 3 * P, "t.pos")); _c.push_back(C(t.quat, 4 * P, "t.quat"));
-         _c.push_back(C(t.lam, P, "t.lam")); _c.push_back(C(t.flags, P, "t.flags"));
-         _c.push_back(C(out_pos, 3 * P, "out_pos")); _c.push_back(C(out_quat, 4 * P, "out_quat"));
-         _c.push_back(C(out_lambda, P, "out_lambda")); _c.push_back(C(out_flags, P, "out_flags"));
-         _c.push_back(C(moved, P, "moved")); if (out_score) {
-           _c.push_back(C(t.score, P, "t.score"));
-           _c.push_back(C(out_score, P, "out_score"));
-         } if (out_C) {
-           _c.push_back(C(t.C, P * K, "t.C"));
-           _c.push_back(C(out_C, P * K, "out_C"));
-         });
 }
 hipError_t launch_pose_tensor(const Geo& g, const float* image, const float* comps, const float* mask, int order_n,
                               const double* img_stats, float, int max_peaks, int refine, const int* pos_in,
@@ -623,7 +600,7 @@ hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int 
                              int refine, const int* pos_in, const int* count_dev, int, const float* image,
                              const float* tmpl, const float* mask, int* out_pos, float* out_quat, double* out_lambda,
                              float* out_score, int* out_flags, double* out_C, const PoseScratch& ps, hipStream_t s,
-                             bool, int) {
+                             bool, int, const int* out_rows, int* moved) {
   const long K = num_components(order_n), nb = (long)max_peaks * (refine ? 27 : 1), l3 = L3(g.L0, g.L1, g.L2);
   const long P = max_peaks;
   LAUNCH("pose_solve", s, if (score) _c.push_back(C(score, g.vol(), "score"));
@@ -640,16 +617,18 @@ hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int 
            _c.push_back(C(ps.mval, l3, "ps.mval"));
            _c.push_back(C(ps.mcount, 1, "ps.mcount"));
            _c.push_back(C(ps.ncc, nb, "ps.ncc"));
+           _c.push_back(C(ps.mbits, mask_bricks(g.L0, g.L1, g.L2), "ps.mbits"));
          } _c.push_back(C(out_pos, 3 * P, "out_pos"));
          _c.push_back(C(out_quat, 4 * P, "out_quat")); _c.push_back(C(out_lambda, P, "out_lambda"));
          _c.push_back(C(out_flags, P, "out_flags")); if (out_score) _c.push_back(C(out_score, P, "out_score"));
-         if (out_C) _c.push_back(C(out_C, P * K, "out_C")););
+         if (out_C) _c.push_back(C(out_C, P * K, "out_C")); if (out_rows) _c.push_back(C(out_rows, P, "out_rows"));
+         if (moved) _c.push_back(C(moved, P, "moved")););
 }
 hipError_t launch_mask_list(const float* mask, int L0, int L1, int L2, unsigned* list, float* mval, int* count,
-                            hipStream_t s) {
+                            hipStream_t s, unsigned long long* bits) {
   LAUNCH("mask_list", s, _c.push_back(C(mask, L3(L0, L1, L2), "mask"));
          _c.push_back(C(list, L3(L0, L1, L2), "list")); _c.push_back(C(mval, L3(L0, L1, L2), "mval"));
-         _c.push_back(C(count, 1, "count")););
+         _c.push_back(C(count, 1, "count")); if (bits) _c.push_back(C(bits, mask_bricks(L0, L1, L2), "bits")););
 }
 
 // the rest: each buffer must at least start inside a live range
