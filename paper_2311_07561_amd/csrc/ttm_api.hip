@@ -177,24 +177,12 @@ static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refi
   w.ps.mom = c.take<double>(nb * 3);
   w.ps.mbits = c.take<unsigned long long>((size_t)mask_bricks(g.L0, g.L1, g.L2));
   w.moved = w.act_pos = w.act_idx = w.act_count = nullptr;
-  w.ps.reuse = nullptr;
-  w.ps.cache = RefineCache{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   if (refine == 3) {
     const size_t P = (size_t)max_peaks;
     w.moved = c.take<int>(P);
     w.act_pos = c.take<int>(P * 3);
     w.act_idx = c.take<int>(P);
     w.act_count = c.take<int>(1);
-    w.ps.reuse = c.take<int>(P * 27);
-    RefineCache& rc = w.ps.cache;
-    rc.centre = c.take<int>(P * 3);
-    rc.C = c.take<double>(P * 27 * (size_t)K);
-    rc.w = c.take<double>(P * 27);
-    rc.ok = c.take<int>(P * 27);
-    rc.q = c.take<float>(P * 27 * 4);
-    rc.lam = c.take<double>(P * 27);
-    rc.flags = c.take<int>(P * 27);
-    rc.ncc = c.take<double>(P * 27);
   }
   return w;
 }
@@ -205,25 +193,22 @@ static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refi
 // until none moves or kRefineRounds rounds in all.  Most candidates move in
 // the first round, so the second spreads each candidate's neighbours over 9
 // blocks as the first does; the later rounds, with few candidates left, over
-// 27.  tensor(pos, count_dev, reuse) fills the pose scratch with C_n at the
-// 27 neighbours of the listed candidates (copying the entries with
-// ps.reuse >= 0 from the cache).  Volumes keep each round's neighbourhoods
-// in the cache (the first round's included); planar stacks recompute.
+// 27.  tensor(pos, count_dev) fills the pose scratch with C_n at the 27
+// neighbours of the listed candidates.
 template <class TensorFn>
 static ttm_status refine_rounds(const Geo& g, const float* score, int order_n, const ttm_options* opt,
                                 int max_peaks, const int* count_dev, int count_host, const float* image,
                                 const float* tmpl, const float* mask, int32_t* out_pos, float* out_quat,
                                 double* out_lambda, float* out_score, int32_t* out_flags, double* out_C, PoseWs& w,
                                 TensorFn tensor, hipStream_t stream) {
-  const bool cache = !g.planar;
   for (int r = 1; r < kRefineRounds; ++r) {
     TTM_PROF(PC_POSE, launch_refine_compact(count_dev, count_host, w.moved, out_pos, w.act_pos, w.act_idx,
-                                            w.act_count, stream, cache ? &w.ps : nullptr));
-    TTM_PROF(PC_POSE, tensor(w.act_pos, w.act_count, cache));
+                                            w.act_count, stream));
+    TTM_PROF(PC_POSE, tensor(w.act_pos, w.act_count));
     TTM_PROF(PC_POSE, launch_pose_solve(g, score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
                                         max_peaks, 2, w.act_pos, w.act_count, 0, image, tmpl, mask, out_pos,
                                         out_quat, out_lambda, out_score, out_flags, out_C, w.ps, stream, true,
-                                        r == 1 ? 9 : 27, w.act_idx, w.moved, cache, cache && r + 1 < kRefineRounds));
+                                        r == 1 ? 9 : 27, w.act_idx, w.moved));
   }
   return TTM_OK;
 }
@@ -551,11 +536,11 @@ static ttm_status recover_pose_into(const Geo& g, const float* score, const floa
   TTM_PROF(PC_POSE, launch_pose_solve(g, score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
                                       opt->max_peaks, rf, w.cand_pos, out_count, 0, image, tmpl, mask,
                                       out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, w.ps,
-                                      stream, false, 9, nullptr, w.moved, false, opt->refine == 3));
+                                      stream, false, 9, nullptr, w.moved));
   if (opt->refine == 3) {
-    auto tensor = [&](const int* pos, const int* cnt, bool reuse) {
+    auto tensor = [&](const int* pos, const int* cnt) {
       return launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, opt->max_peaks, 2, pos,
-                                cnt, 0, w.ps, stream, reuse);
+                                cnt, 0, w.ps, stream);
     };
     TTM_CALL(refine_rounds(g, score, order_n, opt, opt->max_peaks, out_count, 0, image, tmpl, mask, out_pos,
                            out_quat, out_lambda, out_peak_score, out_flags, out_C, w, tensor, stream));
@@ -619,11 +604,11 @@ static ttm_status pose_at_into(const Geo& g, const float* image, const float* co
   TTM_PROF(PC_POSE, launch_pose_solve(g, nullptr, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol, n_pos,
                                       rf, positions, nullptr, n_pos, image, tmpl, mask, out_pos, out_quat,
                                       out_lambda, nullptr, out_flags, out_C, w.ps, stream, false, 9, nullptr,
-                                      w.moved, false, opt->refine == 3));
+                                      w.moved));
   if (opt->refine == 3) {
-    auto tensor = [&](const int* pos, const int* cnt, bool reuse) {
+    auto tensor = [&](const int* pos, const int* cnt) {
       return launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, n_pos, 2, pos, cnt, 0,
-                                w.ps, stream, reuse);
+                                w.ps, stream);
     };
     TTM_CALL(refine_rounds(g, nullptr, order_n, opt, n_pos, nullptr, n_pos, image, tmpl, mask, out_pos, out_quat,
                            out_lambda, nullptr, out_flags, out_C, w, tensor, stream));
@@ -710,10 +695,10 @@ ttm_status ttm_match(const float* image, ttm_dims N, const void* bank, ttm_dims 
   TTM_PROF(PC_POSE, launch_pose_solve(g, out_score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
                                       opt->max_peaks, rf, pw.cand_pos, out_count, 0, image, tmpl, mask,
                                       out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, pw.ps,
-                                      stream, false, 9, nullptr, pw.moved, false, opt->refine == 3));
+                                      stream, false, 9, nullptr, pw.moved));
   if (opt->refine == 3) {
-    auto tensor = [&](const int* pos, const int* cnt, bool reuse) {
-      return launch_field_at(g, cw.H, g.half(), K, wout, opt->max_peaks, 2, pos, cnt, 0, pw.ps, stream, reuse);
+    auto tensor = [&](const int* pos, const int* cnt) {
+      return launch_field_at(g, cw.H, g.half(), K, wout, opt->max_peaks, 2, pos, cnt, 0, pw.ps, stream);
     };
     TTM_CALL(refine_rounds(g, out_score, order_n, opt, opt->max_peaks, out_count, 0, image, tmpl, mask, out_pos,
                            out_quat, out_lambda, out_peak_score, out_flags, out_C, pw, tensor, stream));
@@ -1318,9 +1303,9 @@ ttm_status ttm_match_2d(const float* images, int32_t B, int32_t n1, int32_t n2, 
                                       m.list, m.total, 0, images, tmpl, mask, m.pos3, m.quat3, m.lam3, m.score3,
                                       m.flags3, nullptr, w.ps, stream, false, 9, nullptr, w.moved));
   if (opt->refine == 3) {
-    auto tensor = [&](const int* pos, const int* cnt, bool reuse) {
+    auto tensor = [&](const int* pos, const int* cnt) {
       return launch_pose_tensor(gs, images, m.comps3, mask, order_n, w.stats, opt->eps_v, BP, 2, pos, cnt, 0, w.ps,
-                                stream, reuse);
+                                stream);
     };
     TTM_CALL(refine_rounds(gs, out_score, order_n, opt, BP, m.total, 0, images, tmpl, mask, m.pos3, m.quat3, m.lam3,
                            m.score3, m.flags3, nullptr, w, tensor, stream));

@@ -714,8 +714,7 @@ __global__ void __launch_bounds__(256) k_field_at(P3Geo g, const float2* __restr
                                                   const float* __restrict__ wmap, int refine,
                                                   const int* __restrict__ pos, const int* __restrict__ count_dev,
                                                   int count_host, double* __restrict__ Cbuf,
-                                                  double* __restrict__ wbuf, int* __restrict__ okbuf,
-                                                  const int* __restrict__ reuse, RefineCache cache) {
+                                                  double* __restrict__ wbuf, int* __restrict__ okbuf) {
   extern __shared__ float2 twf[];            // n2 entries: (cos, sin)(2 pi j / n2)
   const int rows = refine ? 9 : 1;
   const int NB = refine ? 27 : 1;
@@ -741,16 +740,6 @@ __global__ void __launch_bounds__(256) k_field_at(P3Geo g, const float2* __restr
     const int x2 = pos[3 * p + 2] + o2;
     const int k = refine ? (o0 + 1) * 9 + (o1 + 1) * 3 + (o2 + 1) : 0;
     const long cb = (long)p * NB + k;
-    const int src = reuse ? reuse[cb] : -1;
-    if (src >= 0) {
-      // the same voxel in the candidate's previous neighbourhood
-      Cbuf[cb * K + alpha] = cache.C[(long)src * K + alpha];
-      if (alpha == 0) {
-        okbuf[cb] = cache.ok[src];
-        wbuf[cb] = cache.w[src];
-      }
-      continue;
-    }
     const bool ok = row_ok && x2 >= g.lo2 && x2 <= g.hi2;
     if (!ok) {
       Cbuf[cb * K + alpha] = 0.0;
@@ -782,12 +771,11 @@ __global__ void __launch_bounds__(256) k_field_at(P3Geo g, const float2* __restr
 
 hipError_t launch_field_at(const Geo& gg, const float2* H, long pstride, int K, const float* wmap,
                            int max_peaks, int refine, const int* pos_in, const int* count_dev, int count_host,
-                           const PoseScratch& ps, hipStream_t s, bool reuse) {
+                           const PoseScratch& ps, hipStream_t s) {
   const P3Geo q = make_p3geo(gg);
   const unsigned nblk = (unsigned)(max_peaks * (refine ? 9 : 1));
   hipLaunchKernelGGL(k_field_at, dim3(nblk), dim3(256), sizeof(float2) * gg.n2, s, q, H, pstride, K, wmap,
-                     refine, pos_in, count_dev, count_host, ps.C, ps.w, ps.ok, reuse && refine ? ps.reuse : nullptr,
-                     ps.cache);
+                     refine, pos_in, count_dev, count_host, ps.C, ps.w, ps.ok);
   return hipGetLastError();
 }
 

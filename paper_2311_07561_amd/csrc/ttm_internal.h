@@ -150,22 +150,6 @@ constexpr int kPeakCtrlWords = 16;
 hipError_t launch_peaks(const Geo& g, const float* score, float threshold, float min_dist,
                         int max_peaks, const PeakWs& w, int* out_pos, float* out_score,
                         int* out_count, hipStream_t s, int planes = 1);
-// refine 3: per candidate row, the results at the 27 neighbours of the
-// position it was last refined at (rows of 27 entries).  The tensor, its
-// eigenpair and the NCC at a voxel depend on that voxel alone, so a round
-// copies the entries its candidate shares with the previous round instead of
-// computing them again.
-struct RefineCache {
-  int* centre;     // P x 3: the position whose neighbourhood a row holds
-  double* C;       // P x 27 x K
-  double* w;       // P x 27
-  int* ok;         // P x 27
-  float* q;        // P x 27 x 4
-  double* lam;     // P x 27
-  int* flags;      // P x 27
-  double* ncc;     // P x 27
-};
-
 struct PoseScratch {
   double* seeds;  // n_seeds * 4: the S^3 seed points
   double* C;      // max_peaks * NB * K
@@ -182,8 +166,6 @@ struct PoseScratch {
   int* sidx;        // max_peaks * NB * 64: and its seed index
   double* mom;      // max_peaks * NB * 3: sum m f, sum m f^2, sum m (direct tensor)
   unsigned long long* mbits;  // mask_bricks(L): per 4x4x4 brick of the mask box, its voxels with m != 0
-  int* reuse;       // refine 3: max_peaks * 27, per entry of a round its cache entry (row * 27 + k) or -1
-  RefineCache cache;
 };
 
 // iterated refinement (refine 3): the rounds after the first (fewer
@@ -194,37 +176,32 @@ struct PoseScratch {
 // flags cleared) and writes its results to their rows, setting the flag of
 // each candidate that moved again.
 constexpr int kRefineRounds = 4;
-// with ps: also, per entry (j, k) of the round, ps->reuse = the cache entry
-// holding the same voxel (row act_idx[j]) or -1
 hipError_t launch_refine_compact(const int* count_dev, int count_host, int* moved, const int* pos, int* act_pos,
-                                 int* act_idx, int* act_count, hipStream_t s, const PoseScratch* ps = nullptr);
+                                 int* act_idx, int* act_count, hipStream_t s);
 // C_n(x) in float64 by direct window sums at max_peaks candidates (count from
 // count_dev if non-null, else count_host), at the 27 neighbours if refine
 hipError_t launch_pose_tensor(const Geo& g, const float* image, const float* comps, const float* mask,
                               int order_n, const double* img_stats, float eps_v, int max_peaks, int refine,
                               const int* pos_in, const int* count_dev, int count_host, const PoseScratch& ps,
-                              hipStream_t s, bool reuse = false);
+                              hipStream_t s);
 // C_n(x) read from the correlated field: the K inverse-transformed arrays
 // before their last (axis-2) pass, evaluated at the (neighbour) voxels by a
 // direct inverse real DFT of their rows, times w(x)/V
 hipError_t launch_field_at(const Geo& g, const float2* H, long pstride, int K, const float* wmap,
                            int max_peaks, int refine, const int* pos_in, const int* count_dev, int count_host,
-                           const PoseScratch& ps, hipStream_t s, bool reuse = false);
+                           const PoseScratch& ps, hipStream_t s);
 // dominant Z-eigenpairs of the tensors in ps and, per candidate, the
 // neighbour with the largest lambda (refine 1) or with the largest NCC of the
 // image window against the template rotated by the voxel's own eigenvector
 // (refine 2: image, tmpl and mask are read).  Candidate p's outputs go to
 // row out_rows[p] (row p if null); moved (if given) gets, per row, whether
-// the candidate left its position.  reuse: entries with ps.reuse >= 0 are
-// copied from ps.cache; fill_cache: each candidate's 27 entries are kept in
-// its row of ps.cache.
+// the candidate left its position.
 hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int n_seeds, int max_iter,
                              double tol, int max_peaks, int refine, const int* pos_in, const int* count_dev,
                              int count_host, const float* image, const float* tmpl, const float* mask,
                              int* out_pos, float* out_quat, double* out_lambda, float* out_score, int* out_flags,
                              double* out_C, const PoseScratch& ps, hipStream_t s, bool reuse_tables = false,
-                             int ncc_groups = 9, const int* out_rows = nullptr, int* moved = nullptr,
-                             bool reuse = false, bool fill_cache = false);
+                             int ncc_groups = 9, const int* out_rows = nullptr, int* moved = nullptr);
 
 // the mask voxels with m != 0 (packed u0 | u1 << 10 | u2 << 20), their
 // values and their count, in 4x4x4 bricks in C order (C order within a

@@ -712,20 +712,13 @@ __global__ void __launch_bounds__(kDirThreads) k_pose_direct(PoseGeo g, const fl
                                                              const float* __restrict__ mask, int K,
                                                              const int* __restrict__ pos,
                                                              const int* __restrict__ count_dev, int count_host,
-                                                             double* __restrict__ Gbuf, double* __restrict__ mom,
-                                                             const int* __restrict__ reuse) {
+                                                             double* __restrict__ Gbuf, double* __restrict__ mom) {
   constexpr int NO = O * O;                  // offsets (o1, o2) per block
   constexpr int NBT = O * O * O;
   __shared__ double red[4][NO * kDirGroup];
   const int p = blockIdx.x;
   const int count = count_dev ? count_dev[0] : count_host;
   if (p >= count) return;
-  if (reuse) {
-    // every neighbour of this slice comes from the cache
-    bool all = true;
-    for (int j = 0; j < NO; ++j) all = all && reuse[(long)p * NBT + (long)blockIdx.y * NO + j] >= 0;
-    if (all) return;
-  }
   const int o0 = (int)blockIdx.y - (O / 2);
   const int ag = blockIdx.z;
   const int ngroups = (K + kDirGroup - 1) / kDirGroup;
@@ -829,20 +822,12 @@ __global__ void __launch_bounds__(256) k_pose_direct_finish(PoseGeo g, int K, co
                                                             const int* __restrict__ count_dev, int count_host,
                                                             int NB, int total, const double* __restrict__ mom,
                                                             double* __restrict__ Cbuf, double* __restrict__ wbuf,
-                                                            int* __restrict__ okbuf, const int* __restrict__ reuse,
-                                                            RefineCache cache) {
+                                                            int* __restrict__ okbuf) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= total) return;
   const int p = b / NB, k = b % NB;
   const int count = count_dev ? count_dev[0] : count_host;
   if (p >= count) return;
-  const int src = reuse ? reuse[b] : -1;
-  if (src >= 0) {
-    for (int a = 0; a < K; ++a) Cbuf[(long)b * K + a] = cache.C[(long)src * K + a];
-    okbuf[b] = cache.ok[src];
-    wbuf[b] = cache.w[src];
-    return;
-  }
   int o0, o1, o2;
   neighbour_offset(k, NB, o0, o1, o2);
   const int x0 = pos[3 * p] + o0, x1 = pos[3 * p + 1] + o1, x2 = pos[3 * p + 2] + o2;
@@ -876,8 +861,7 @@ __global__ void __launch_bounds__(256) k_seed_scan(const double* __restrict__ se
                                                    const double* __restrict__ Cbuf,
                                                    const int* __restrict__ okbuf, const int* __restrict__ count_dev,
                                                    int count_host, int NB, int n_seeds,
-                                                   double* __restrict__ slot_best, int* __restrict__ slot_idx,
-                                                   const int* __restrict__ reuse) {
+                                                   double* __restrict__ slot_best, int* __restrict__ slot_idx) {
   constexpr int K = (N + 1) * (N + 2) * (N + 3) / 6;
   __shared__ double muA[K];
   __shared__ double rb[256];
@@ -886,7 +870,6 @@ __global__ void __launch_bounds__(256) k_seed_scan(const double* __restrict__ se
   const int p = b / NB;
   const int count = count_dev ? count_dev[0] : count_host;
   if (p >= count || !okbuf[b]) return;
-  if (reuse && reuse[b] >= 0) return;   // the eigenpair comes from the cache
   const int tid = threadIdx.x;
   for (int k = tid; k < K; k += 256) {
     int al[4];
@@ -939,8 +922,7 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
                                                  int count_host, int NB, const double* __restrict__ slot_best,
                                                  const int* __restrict__ slot_idx, int max_iter, double tol,
                                                  float* __restrict__ qbuf, double* __restrict__ lambuf,
-                                                 int* __restrict__ flagbuf, const int* __restrict__ reuse,
-                                                 RefineCache cache) {
+                                                 int* __restrict__ flagbuf) {
   constexpr int n = N;
   __shared__ EigLds t;
   __shared__ double red[64 * 6];
@@ -950,16 +932,6 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
   const int count = count_dev ? count_dev[0] : count_host;
   if (p >= count) return;
   const int lane = threadIdx.x;
-  const int src = reuse ? reuse[b] : -1;
-  if (src >= 0) {
-    // the same voxel in the candidate's previous neighbourhood
-    if (lane < 4) qbuf[4 * b + lane] = cache.q[4 * (long)src + lane];
-    if (lane == 0) {
-      lambuf[b] = cache.lam[src];
-      flagbuf[b] = cache.flags[src];
-    }
-    return;
-  }
   if (!okbuf[b]) {
     if (lane == 0) {
       lambuf[b] = -INFINITY;
@@ -1384,18 +1356,13 @@ __global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __rest
                                                   const int* __restrict__ mcount, const int* __restrict__ pos,
                                                   const int* __restrict__ count_dev, int count_host, int NB,
                                                   const double* __restrict__ wbuf, const int* __restrict__ okbuf,
-                                                  const float* __restrict__ qbuf, double* __restrict__ nccbuf,
-                                                  const int* __restrict__ reuse, const double* __restrict__ cache_ncc) {
+                                                  const float* __restrict__ qbuf, double* __restrict__ nccbuf) {
   __shared__ double red[4][5];
   const int b = blockIdx.x;
   const int p = b / NB, k = b % NB;
   const int count = count_dev ? count_dev[0] : count_host;
   if (p >= count) return;
   const int tid = threadIdx.x;
-  if (reuse && reuse[b] >= 0) {
-    if (tid == 0) nccbuf[b] = cache_ncc[reuse[b]];
-    return;
-  }
   if (!okbuf[b]) {
     if (tid == 0) nccbuf[b] = -INFINITY;
     return;
@@ -1472,8 +1439,7 @@ __global__ void __launch_bounds__(NT) k_pose_ncc_lds(PoseGeo g, int ngroups, con
                                                        const int* __restrict__ count_dev, int count_host,
                                                        const double* __restrict__ wbuf,
                                                        const int* __restrict__ okbuf, const float* __restrict__ qbuf,
-                                                       double* __restrict__ nccbuf, const int* __restrict__ reuse,
-                                                       const double* __restrict__ cache_ncc) {
+                                                       double* __restrict__ nccbuf) {
   constexpr int NW = NT / 64;
   __shared__ float tl[CAP];
   __shared__ double red[NW][15];
@@ -1484,20 +1450,6 @@ __global__ void __launch_bounds__(NT) k_pose_ncc_lds(PoseGeo g, int ngroups, con
   const int count = count_dev ? count_dev[0] : count_host;
   if (p >= count) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // neighbours whose NCC is in the cache are copied; a block with nothing
-  // else to do leaves before it loads the template
-  if (reuse) {
-    bool all = true;
-    for (int k = k_lo; k < k_hi; ++k) {
-      const int src = reuse[(long)p * NB + k];
-      if (src >= 0) {
-        if (tid == 0) nccbuf[(long)p * NB + k] = cache_ncc[src];
-      } else {
-        all = false;
-      }
-    }
-    if (all) return;
-  }
   const int L0 = g.L0, L1 = g.L1, L2 = g.L2, nL = L0 * L1 * L2;
   const int P2 = L2 + 3, P01 = L1 * P2 + 5;
   fill_lds_box(tl, tmpl, L0, L1, L2, P2, P01, tid, NT);
@@ -1527,7 +1479,6 @@ __global__ void __launch_bounds__(NT) k_pose_ncc_lds(PoseGeo g, int ngroups, con
       if (k >= k_hi) continue;
       // block-uniform: the neighbour's validity and w
       const long b = (long)p * NB + k;
-      if (reuse && reuse[b] >= 0) continue;
       if (!okbuf[b]) {
         if (tid == 0) nccbuf[b] = -INFINITY;
         continue;
@@ -1635,12 +1586,10 @@ __global__ void __launch_bounds__(64) k_pose_pick(PoseGeo g, const float* __rest
                                                   const double* __restrict__ wbuf, const float* __restrict__ qbuf,
                                                   const double* __restrict__ lambuf,
                                                   const double* __restrict__ keybuf, const int* __restrict__ flagbuf,
-                                                  const int* __restrict__ okbuf,
                                                   int* __restrict__ out_pos, float* __restrict__ out_quat,
                                                   double* __restrict__ out_lambda, float* __restrict__ out_score,
                                                   int* __restrict__ out_flags, double* __restrict__ out_C,
-                                                  const int* __restrict__ out_rows, int* __restrict__ moved,
-                                                  RefineCache fill) {
+                                                  const int* __restrict__ out_rows, int* __restrict__ moved) {
   __shared__ double keys[27];
   __shared__ int pick;
   const int p = blockIdx.x;
@@ -1681,21 +1630,6 @@ __global__ void __launch_bounds__(64) k_pose_pick(PoseGeo g, const float* __rest
     const long r = out_rows ? out_rows[p] : p;
     for (int k = lane; k < K; k += 64) out_C[r * K + k] = Cbuf[b * K + k];
   }
-  if (fill.centre && NB == 27) {
-    // the candidate's 27 entries, kept in its row for the next round
-    const long r = out_rows ? out_rows[p] : p;
-    const long b0 = (long)p * 27, c0 = r * 27;
-    if (lane < 3) fill.centre[3 * r + lane] = pos_in[3 * p + lane];
-    for (long e = lane; e < 27L * K; e += 64) fill.C[c0 * K + e] = Cbuf[b0 * K + e];
-    if (lane < 27) {
-      fill.w[c0 + lane] = wbuf[b0 + lane];
-      fill.ok[c0 + lane] = okbuf[b0 + lane];
-      fill.lam[c0 + lane] = lambuf[b0 + lane];
-      fill.flags[c0 + lane] = flagbuf[b0 + lane];
-      fill.ncc[c0 + lane] = keybuf[b0 + lane];
-      for (int d = 0; d < 4; ++d) fill.q[4 * (c0 + lane) + d] = qbuf[4 * (b0 + lane) + d];
-    }
-  }
 }
 
 // ----------------------------------------------------------------------------
@@ -1703,19 +1637,12 @@ __global__ void __launch_bounds__(64) k_pose_pick(PoseGeo g, const float* __rest
 // that moved are compacted into a list that the next round refines again
 // ----------------------------------------------------------------------------
 // one block: the moving candidates in index order (an LDS prefix sum per
-// chunk of 1024); their flags are cleared for the round.  With a cache:
-// then, per entry (j, k) of the round, the cache entry of candidate
-// act_idx[j] that holds the same voxel (its previous neighbourhood is
-// centred at cache_centre), or -1
-constexpr int kCompactMax = 4096;   // max_peaks <= 4096
+// chunk of 1024); their flags are cleared for the round
 __global__ void __launch_bounds__(1024) k_refine_compact(const int* __restrict__ count_dev, int count_host,
                                                          int* __restrict__ moved, const int* __restrict__ pos,
                                                          int* __restrict__ act_pos, int* __restrict__ act_idx,
-                                                         int* __restrict__ act_count,
-                                                         const int* __restrict__ cache_centre,
-                                                         int* __restrict__ reuse) {
+                                                         int* __restrict__ act_count) {
   __shared__ int sh[1024];
-  __shared__ int s_act[kCompactMax];
   __shared__ int base;
   const int tid = threadIdx.x;
   const int n = count_dev ? count_dev[0] : count_host;
@@ -1735,7 +1662,6 @@ __global__ void __launch_bounds__(1024) k_refine_compact(const int* __restrict__
     if (f) {
       const int j = base + sh[tid] - 1;
       act_idx[j] = p;
-      if (j < kCompactMax) s_act[j] = p;
       act_pos[3 * j] = pos[3 * p];
       act_pos[3 * j + 1] = pos[3 * p + 1];
       act_pos[3 * j + 2] = pos[3 * p + 2];
@@ -1745,29 +1671,13 @@ __global__ void __launch_bounds__(1024) k_refine_compact(const int* __restrict__
     if (tid == 1023) base += sh[1023];
     __syncthreads();
   }
-  const int nact = base;
-  if (tid == 0) act_count[0] = nact;
-  if (!reuse) return;
-  for (int e = tid; e < nact * 27; e += 1024) {
-    const int j = e / 27, k = e % 27;
-    const int p = s_act[j];
-    int src = -1;
-    int d[3];
-    bool near = true;
-    for (int a = 0; a < 3; ++a) {
-      const int o = a == 0 ? k / 9 - 1 : (a == 1 ? (k / 3) % 3 - 1 : k % 3 - 1);
-      d[a] = pos[3 * p + a] + o - cache_centre[3 * p + a];
-      near = near && d[a] >= -1 && d[a] <= 1;
-    }
-    if (near) src = p * 27 + (d[0] + 1) * 9 + (d[1] + 1) * 3 + (d[2] + 1);
-    reuse[e] = src;
-  }
+  if (tid == 0) act_count[0] = base;
 }
 
 hipError_t launch_refine_compact(const int* count_dev, int count_host, int* moved, const int* pos, int* act_pos,
-                                 int* act_idx, int* act_count, hipStream_t s, const PoseScratch* ps) {
+                                 int* act_idx, int* act_count, hipStream_t s) {
   hipLaunchKernelGGL(k_refine_compact, dim3(1), dim3(1024), 0, s, count_dev, count_host, moved, pos, act_pos,
-                     act_idx, act_count, ps ? ps->cache.centre : nullptr, ps ? ps->reuse : nullptr);
+                     act_idx, act_count);
   return hipGetLastError();
 }
 
@@ -1785,22 +1695,21 @@ static PoseGeo make_posegeo(const Geo& gg) {
 hipError_t launch_pose_tensor(const Geo& gg, const float* image, const float* comps, const float* mask,
                               int order_n, const double* img_stats, float eps_v, int max_peaks, int refine,
                               const int* pos_in, const int* count_dev, int count_host, const PoseScratch& ps,
-                              hipStream_t s, bool reuse) {
+                              hipStream_t s) {
   const PoseGeo g = make_posegeo(gg);
   const int K = num_components(order_n);
   const int NB = refine ? 27 : 1;
   if (!g.planar) {
     const int ngroups = (K + kDirGroup - 1) / kDirGroup;
-    const int* ru = reuse && refine ? ps.reuse : nullptr;
     if (refine)
       hipLaunchKernelGGL(k_pose_direct<3>, dim3((unsigned)max_peaks, 3, (unsigned)(ngroups + 1)), dim3(kDirThreads),
-                         0, s, g, image, comps, mask, K, pos_in, count_dev, count_host, ps.C, ps.mom, ru);
+                         0, s, g, image, comps, mask, K, pos_in, count_dev, count_host, ps.C, ps.mom);
     else
       hipLaunchKernelGGL(k_pose_direct<1>, dim3((unsigned)max_peaks, 1, (unsigned)(ngroups + 1)), dim3(kDirThreads),
-                         0, s, g, image, comps, mask, K, pos_in, count_dev, count_host, ps.C, ps.mom, ru);
+                         0, s, g, image, comps, mask, K, pos_in, count_dev, count_host, ps.C, ps.mom);
     const int total = max_peaks * NB;
     hipLaunchKernelGGL(k_pose_direct_finish, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, K, img_stats,
-                       eps_v, pos_in, count_dev, count_host, NB, total, ps.mom, ps.C, ps.w, ps.ok, ru, ps.cache);
+                       eps_v, pos_in, count_dev, count_host, NB, total, ps.mom, ps.C, ps.w, ps.ok);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_pose_tensor, dim3((unsigned)(max_peaks * NB)), dim3(256), 0, s, g, image, comps, mask, K,
@@ -1813,13 +1722,10 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
                              int count_host, const float* image, const float* tmpl, const float* mask,
                              int* out_pos, float* out_quat, double* out_lambda, float* out_score, int* out_flags,
                              double* out_C, const PoseScratch& ps, hipStream_t s, bool reuse_tables,
-                             int ncc_groups, const int* out_rows, int* moved, bool reuse, bool fill_cache) {
+                             int ncc_groups, const int* out_rows, int* moved) {
   const PoseGeo g = make_posegeo(gg);
   const int K = num_components(order_n);
   const int NB = refine ? 27 : 1;
-  const int* ru = reuse && refine == 2 && !g.planar ? ps.reuse : nullptr;
-  RefineCache fill = ps.cache;
-  if (!(fill_cache && refine == 2 && !g.planar)) fill.centre = nullptr;
   if (!reuse_tables && !g.planar)
     hipLaunchKernelGGL(k_seed_table, dim3((n_seeds + 255) / 256), dim3(256), 0, s, n_seeds, ps.seeds);
   const dim3 eg((unsigned)(max_peaks * NB));
@@ -1846,27 +1752,27 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
   } else switch (order_n) {
     case 2:
       hipLaunchKernelGGL(k_seed_scan<2>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         n_seeds, ps.sbest, ps.sidx, ru);
+                         n_seeds, ps.sbest, ps.sidx);
       hipLaunchKernelGGL(k_pose_eig<2>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags, ru, ps.cache);
+                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags);
       break;
     case 4:
       hipLaunchKernelGGL(k_seed_scan<4>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         n_seeds, ps.sbest, ps.sidx, ru);
+                         n_seeds, ps.sbest, ps.sidx);
       hipLaunchKernelGGL(k_pose_eig<4>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags, ru, ps.cache);
+                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags);
       break;
     case 6:
       hipLaunchKernelGGL(k_seed_scan<6>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         n_seeds, ps.sbest, ps.sidx, ru);
+                         n_seeds, ps.sbest, ps.sidx);
       hipLaunchKernelGGL(k_pose_eig<6>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags, ru, ps.cache);
+                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags);
       break;
     case 8:
       hipLaunchKernelGGL(k_seed_scan<8>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         n_seeds, ps.sbest, ps.sidx, ru);
+                         n_seeds, ps.sbest, ps.sidx);
       hipLaunchKernelGGL(k_pose_eig<8>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags, ru, ps.cache);
+                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -1879,21 +1785,21 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
       // small boxes: 256 threads and 16 KiB of LDS per block
       hipLaunchKernelGGL((k_pose_ncc_lds<256, kNccLdsSmall>), dim3((unsigned)(max_peaks * ngroups)), dim3(256), 0, s,
                          g, ngroups, image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in, count_dev, count_host, ps.w,
-                         ps.ok, ps.q, ps.ncc, ru, ps.cache.ncc);
+                         ps.ok, ps.q, ps.ncc);
     } else if (lds <= kNccLdsCap) {
       // one block per CU (the template fills most of the LDS); each block
       // loads the template once for 27 / ngroups neighbours of a candidate
       hipLaunchKernelGGL((k_pose_ncc_lds<1024, kNccLdsCap>), dim3((unsigned)(max_peaks * ngroups)), dim3(1024), 0,
                          s, g, ngroups, image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in, count_dev, count_host,
-                         ps.w, ps.ok, ps.q, ps.ncc, ru, ps.cache.ncc);
+                         ps.w, ps.ok, ps.q, ps.ncc);
     }
     else
       hipLaunchKernelGGL(k_pose_ncc, eg, dim3(256), 0, s, g, image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in,
-                         count_dev, count_host, NB, ps.w, ps.ok, ps.q, ps.ncc, ru, ps.cache.ncc);
+                         count_dev, count_host, NB, ps.w, ps.ok, ps.q, ps.ncc);
   }
   hipLaunchKernelGGL(k_pose_pick, dim3((unsigned)max_peaks), dim3(64), 0, s, g, score, K, pos_in, count_dev,
-                     count_host, NB, ps.C, ps.w, ps.q, ps.lam, refine == 2 ? ps.ncc : ps.lam, ps.flags, ps.ok, out_pos,
-                     out_quat, out_lambda, out_score, out_flags, out_C, out_rows, moved, fill);
+                     count_host, NB, ps.C, ps.w, ps.q, ps.lam, refine == 2 ? ps.ncc : ps.lam, ps.flags, out_pos,
+                     out_quat, out_lambda, out_score, out_flags, out_C, out_rows, moved);
   return hipGetLastError();
 }
 
