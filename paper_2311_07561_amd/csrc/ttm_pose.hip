@@ -1423,12 +1423,13 @@ __global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __rest
 // P01 = L1 P2 + 5 (for L = 32 the banks see j2 + 35 j1 + 37 j0 mod 64 rather
 // than only j2 and the parity of j1); with the 4x4x4 brick order of the mask
 // voxels this cuts the distinct addresses per bank of a wave's gather about
-// fourfold.  The layout must fit CAP floats.  Volumes take 1024 threads and
-// CAP = kNccLdsCap (one block per CU).  A box that fits kNccLdsSmall floats
-// (the depth-1 boxes of a planar stack) takes 256 threads and that much LDS,
-// so that eight blocks share a CU: its window holds too few mask voxels to
-// occupy 1024 threads, and with the large LDS reservation the blocks of a
-// stack's candidates would run one per CU.
+// fourfold.  The layout must fit CAP floats.  Every box whose padded layout
+// fits kNccLdsSmall floats (the depth-1 boxes of a planar stack, and volumes
+// up to about 14^3) takes 256 threads and that much LDS, four blocks per CU at
+// its register use: such a window holds too few mask voxels to occupy 1024
+// threads, and with the large LDS reservation its blocks would run one per
+// CU.  Larger boxes take 1024 threads and CAP = kNccLdsCap (one block per
+// CU).
 constexpr int kNccLdsSmall = 4096;
 template <int NT, int CAP>
 __global__ void __launch_bounds__(NT) k_pose_ncc_lds(PoseGeo g, int ngroups, const float* __restrict__ image,
