@@ -373,6 +373,9 @@ static hipError_t pass1_n(const Geo& g, const Pass1Args& a, hipStream_t s) {
     hipLaunchKernelGGL((k_pass1<N0, 1>), grid, dim3(256), 0, s, a, P, g.p2, g.h2, g.L0, g.c0, g.lo0(), g.hi0());
   else if (bm == 2)
     hipLaunchKernelGGL((k_pass1<N0, 2>), grid, dim3(256), 0, s, a, P, g.p2, g.h2, g.L0, g.c0, g.lo0(), g.hi0());
+  else if (bm <= 4 && R2 > 4)
+    hipLaunchKernelGGL((k_pass1<N0, (R2 > 4 ? 4 : R2)>), grid, dim3(256), 0, s, a, P, g.p2, g.h2, g.L0, g.c0,
+                       g.lo0(), g.hi0());
   else
     hipLaunchKernelGGL((k_pass1<N0, R2>), grid, dim3(256), 0, s, a, P, g.p2, g.h2, g.L0, g.c0, g.lo0(), g.hi0());
   return hipGetLastError();

@@ -188,6 +188,9 @@ static hipError_t pass1x_n(const Geo& g, const Pass1Args& a, hipStream_t s) {
     hipLaunchKernelGGL((k_pass1x<N0, 1, CW>), grid, block, 0, s, a, QH, g.h2, g.n1, g.L0, g.c0, g.lo0(), g.hi0());
   else if (bm == 2)
     hipLaunchKernelGGL((k_pass1x<N0, 2, CW>), grid, block, 0, s, a, QH, g.h2, g.n1, g.L0, g.c0, g.lo0(), g.hi0());
+  else if (bm <= 4 && R2 > 4)
+    hipLaunchKernelGGL((k_pass1x<N0, (R2 > 4 ? 4 : R2), CW>), grid, block, 0, s, a, QH, g.h2, g.n1, g.L0, g.c0,
+                       g.lo0(), g.hi0());
   else
     hipLaunchKernelGGL((k_pass1x<N0, R2, CW>), grid, block, 0, s, a, QH, g.h2, g.n1, g.L0, g.c0, g.lo0(), g.hi0());
   return hipGetLastError();

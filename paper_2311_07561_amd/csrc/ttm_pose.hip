@@ -49,20 +49,27 @@ __device__ __forceinline__ unsigned long long peak_key(float v, long lin) {
 // when it exceeds the window maximum without the centre in its own plane
 // and the window maxima of both neighbouring planes.  The maxima propagate
 // NaN, so a NaN anywhere among the 26 neighbours rejects v, as a comparison
-// with each of them would.  Out-of-image neighbours hold -inf.
+// with each of them would.  Out-of-image neighbours hold -inf.  Maps of
+// depth 1 (the planes of a stack) take runs of one plane (RUN = 1), so that
+// their blocks reserve the LDS of three planes, not eighteen.
 constexpr int QS1 = 4, QS2 = 64, QRUN = 16;
-constexpr int QH0 = QRUN + 2, QH1 = QS1 + 2, QH2 = QS2 + 2;
+constexpr int QH1 = QS1 + 2, QH2 = QS2 + 2;
 
 // max(a, b), NaN when either is NaN
 __device__ __forceinline__ float max_nan(float a, float b) { return (a >= b || a != a) ? a : b; }
 
+template <int RUN>
 __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F, PeakGeo g, float threshold,
                                                     unsigned* __restrict__ ctrl,
                                                     unsigned long long* __restrict__ allc, long bigcap,
                                                     int ztiles, long fplane) {
   static_assert(QS1 * QS2 == 256, "one column per thread");
+  constexpr int QH0 = RUN + 2;
+  // strict maxima are never neighbours: at most one per 2x2x2 cell, or per
+  // 2x2 cell of a single plane
+  constexpr int KEYS = RUN == 1 ? QS1 * QS2 / 4 : RUN * QS1 * QS2 / 8;
   __shared__ float tile[QH0 * QH1 * QH2];
-  __shared__ unsigned long long lkeys[QRUN * QS1 * QS2 / 8];   // strict maxima: at most one per 2x2x2 cell
+  __shared__ unsigned long long lkeys[KEYS];
   __shared__ unsigned lcount, lbase;
   const int tid = threadIdx.x;
   // several maps (planes of a stack) at once: blockIdx.z = plane * ztiles + run
@@ -70,10 +77,9 @@ __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F,
   F += plane * fplane;
   ctrl += kPeakCtrlWords * plane;
   allc += bigcap * plane;
-  const int b0 = g.lo0 + bz * QRUN, b1 = g.lo1 + blockIdx.y * QS1, b2 = g.lo2 + blockIdx.x * QS2;
-  // the run's planes that hold valid voxels (one for a map of depth 1) and
-  // their two halo planes
-  const int nv0 = min(QRUN, g.hi0 - b0 + 1);
+  const int b0 = g.lo0 + bz * RUN, b1 = g.lo1 + blockIdx.y * QS1, b2 = g.lo2 + blockIdx.x * QS2;
+  // the run's planes that hold valid voxels and their two halo planes
+  const int nv0 = min(RUN, g.hi0 - b0 + 1);
   const int NT = (nv0 + 2) * QH1 * QH2;
   // all of a thread's loads in flight at once: each load is unconditional (of
   // voxel 0 outside the map) so that the compiler issues them before it waits
@@ -507,10 +513,15 @@ hipError_t launch_peaks(const Geo& gg, const float* score, float threshold, floa
   hipLaunchKernelGGL(k_peaks_clear, dim3((unsigned)((nh + nctl + 255) / 256)), dim3(256), 0, s, w.hist, nh, w.ctrl,
                      nctl);
   const int e0 = g.hi0 - g.lo0 + 1, e1 = g.hi1 - g.lo1 + 1, e2 = g.hi2 - g.lo2 + 1;
-  const int ztiles = (e0 + QRUN - 1) / QRUN;
+  const int run = g.n0 == 1 ? 1 : QRUN;
+  const int ztiles = (e0 + run - 1) / run;
   dim3 sgrid((e2 + QS2 - 1) / QS2, (e1 + QS1 - 1) / QS1, (unsigned)ztiles * P);
-  hipLaunchKernelGGL(k_peaks_scan, sgrid, dim3(256), 0, s, score, g, threshold, w.ctrl, w.allc, bigcap, ztiles,
-                     gg.vol());
+  if (run == 1)
+    hipLaunchKernelGGL(k_peaks_scan<1>, sgrid, dim3(256), 0, s, score, g, threshold, w.ctrl, w.allc, bigcap, ztiles,
+                       gg.vol());
+  else
+    hipLaunchKernelGGL(k_peaks_scan<QRUN>, sgrid, dim3(256), 0, s, score, g, threshold, w.ctrl, w.allc, bigcap,
+                       ztiles, gg.vol());
   hipLaunchKernelGGL(k_peaks_hist, dim3(kHistBlocks, P), dim3(1024), 0, s, w.ctrl, w.allc, bigcap, w.hist);
   hipLaunchKernelGGL(k_peaks_select, dim3(P), dim3(1024), 0, s, w.hist, w.ctrl);
   hipLaunchKernelGGL(k_peaks_gather, dim3(256, P), dim3(256), 0, s, w.ctrl, w.allc, bigcap, w.cand);

@@ -677,3 +677,39 @@ def test_two_pass_inverse_full_map(N, L, n, r):
     assert np.all(F[~vm] == 0) and np.all(W[~vm] == 0)
     assert torch.equal(score, score_nw)
     assert F[tuple(x0)] > 0.5 * F.max()
+
+
+def test_two_pass_inverse_four_template_rows_per_lane():
+    """A 128-long axis 0 with a 20-voxel template: pass A's pruned forward
+    transform of the template rows takes its four-rows-per-lane form (the
+    rows beyond L0 = 20 of those four zero).  Score and w at the planted
+    centre, at the valid region's corners and at random valid voxels against
+    the oracle's direct sums."""
+    N, L, n, r = (128, 256, 256), (20, 6, 5), 2, 2.4
+    img, tmpl, mask, q, w = rand_setup(95, N, L, r, 24)
+    s = O.rotated_template(tmpl, mask, q[5])
+    c = np.array(L) // 2
+    x0 = np.array([60, 120, 30])
+    sl = tuple(slice(x0[i] - c[i], x0[i] - c[i] + L[i]) for i in range(3))
+    img[sl] += 3.0 * np.sqrt(mask.sum()) * s.astype(np.float32)
+    comps, bank = ttm.build_tensor_template(dev(tmpl), dev(mask), n, q, w, image_shape=N)
+    score, wv = ttm.correlate(dev(img), bank, dev(mask), n)
+    F = score.cpu().numpy()
+    W = wv.cpu().numpy()
+    lo, hi = O.valid_region(N, L)
+    rng = np.random.default_rng(96)
+    corners = np.array([[a, b, cc] for a in (lo[0], hi[0] - 1) for b in (lo[1], hi[1] - 1)
+                        for cc in (lo[2], hi[2] - 1)])
+    rnd = np.stack([rng.integers(lo[i], hi[i], 300) for i in range(3)], axis=1)
+    xs = np.concatenate([x0[None], corners, rnd])
+    T = oracle_T(tmpl, mask, n, q, w)
+    f64, m64 = img.astype(np.float64), mask.astype(np.float64)
+    F_ref = O.score_from_field(O.tensor_field_at(f64, T, m64, xs), n)
+    w_ref = O.local_norm_at(f64, m64, xs)
+    Fs = F[xs[:, 0], xs[:, 1], xs[:, 2]]
+    Ws = W[xs[:, 0], xs[:, 1], xs[:, 2]]
+    assert np.abs(Fs - F_ref).max() <= SCORE_TOL, np.abs(Fs - F_ref).max()
+    assert np.allclose(Ws, w_ref, rtol=1e-4, atol=0)
+    vm = O.valid_mask(N, L)
+    assert np.all(F[~vm] == 0) and np.all(W[~vm] == 0)
+    assert F[tuple(x0)] > 0.5 * F.max()
