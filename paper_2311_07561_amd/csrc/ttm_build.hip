@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(1024) k_rot_stats_lds(const float* __restrict_
   extern __shared__ float tl[];
   __shared__ double red[3][16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int P2 = L2 + 3, P01 = L1 * P2 + 5;
+  const int P2 = ncc_lds_p2(L2), P01 = ncc_lds_p01(L1, L2);
   fill_lds_box(tl, t, L0, L1, L2, P2, P01, tid, 1024);
   __syncthreads();
   const int n = L0 * L1 * L2;
@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(1024) k_rot_stats_lds(const float* __restrict_
       const float mv = m[u];
       if (mv == 0.0f) continue;
       const int u2 = u % L2, u1 = (u / L2) % L1, u0 = u / (L1 * L2);
-      const double gv = sample_rotated_lds(tl, L0, L1, L2, P2, P01, R, u0, u1, u2);
+      const double gv = sample_rotated_lds<false>(tl, L0, L1, L2, P2, P01, R, u0, u1, u2);
       s0 += mv;
       s1 += mv * gv;
       s2 += mv * gv * gv;
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(LDS ? 512 : 256) k_build_mfma(const float* __r
                                                                 float* __restrict__ comps) {
   extern __shared__ float tl[];
   constexpr int WPB = LDS ? 8 : 4;   // wavefronts (tiles) per block
-  const int P2 = L2 + 3, P01 = L1 * P2 + 5;
+  const int P2 = ncc_lds_p2(L2), P01 = ncc_lds_p01(L1, L2);
   if (LDS) {
     fill_lds_box(tl, t, L0, L1, L2, P2, P01, threadIdx.x, 64 * WPB);
     __syncthreads();
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(LDS ? 512 : 256) k_build_mfma(const float* __r
         Rot R;
 #pragma unroll
         for (int i = 0; i < 9; ++i) R.r[i] = rtab[9 * j + i];
-        const double g = LDS ? (double)sample_rotated_lds(tl, L0, L1, L2, P2, P01, R, u0, u1, u2)
+        const double g = LDS ? (double)sample_rotated_lds<false>(tl, L0, L1, L2, P2, P01, R, u0, u1, u2)
                              : (double)sample_rotated(t, L0, L1, L2, R, u0, u1, u2);
         sv = (double)mv * (g - rstats[2 * j]);
       }

@@ -1429,14 +1429,12 @@ __global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __rest
 // The same NCC with the template held in LDS: one block of NT threads per
 // (candidate, group of its neighbours) loads the template once and
 // evaluates the group's neighbours one after another, sampling trilinearly
-// from LDS without branches (corners outside the box get weight 0 and read
-// element 0).  LDS layout: row pitch P2 = L2 + 3 and plane pitch
-// P01 = L1 P2 + 5 (for L = 32 the banks see j2 + 35 j1 + 37 j0 mod 64 rather
-// than only j2 and the parity of j1); with the 4x4x4 brick order of the mask
-// voxels this cuts the distinct addresses per bank of a wave's gather about
-// fourfold.  The layout must fit CAP floats.  Every box whose padded layout
-// fits kNccLdsSmall floats (the depth-1 boxes of a planar stack, and volumes
-// up to about 14^3) takes 256 threads and that much LDS, four blocks per CU at
+// from LDS (the padded, zero-guarded layout of sample_rotated_lds: its
+// pitches spread a wave's gathers over the banks, and with the 4x4x4 brick
+// order of the mask voxels a wave samples a compact region).  The layout must
+// fit CAP floats.  Every box whose padded layout fits kNccLdsSmall floats
+// (the depth-1 boxes of a planar stack, and volumes up to about 13^3) takes
+// 256 threads and that much LDS, four blocks per CU at
 // its register use: such a window holds too few mask voxels to occupy 1024
 // threads, and with the large LDS reservation its blocks would run one per
 // CU.  Larger boxes take 1024 threads and CAP = kNccLdsCap (one block per
@@ -1463,7 +1461,7 @@ __global__ void __launch_bounds__(NT) k_pose_ncc_lds(PoseGeo g, int ngroups, con
   if (p >= count) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int L0 = g.L0, L1 = g.L1, L2 = g.L2, nL = L0 * L1 * L2;
-  const int P2 = L2 + 3, P01 = L1 * P2 + 5;
+  const int P2 = ncc_lds_p2(L2), P01 = ncc_lds_p01(L1, L2);
   fill_lds_box(tl, tmpl, L0, L1, L2, P2, P01, tid, NT);
   __syncthreads();
   const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;

@@ -64,15 +64,27 @@ __device__ __forceinline__ float sample_rotated(const float* __restrict__ t, int
   return acc;
 }
 
-// The same sampling from a box held in LDS with padded pitches: row pitch
-// P2 = L2 + 3 and plane pitch P01 = L1 P2 + 5 (for L = 32 the banks see
-// j2 + 35 j1 + 37 j0 mod 64 rather than only j2 and the parity of j1).  No
-// branches around the gathers: corners outside the box get weight 0 and read
-// element 0.  The layout must fit kNccLdsCap floats.
-constexpr int kNccLdsCap = 36864;
+// The same sampling from a box held in LDS with padded pitches and a zero
+// guard one past the box's upper edge on every axis: row pitch P2 = L2 + 3
+// (columns L2..L2+2 zero), L1 + 1 rows per plane (row L1 zero) and plane
+// pitch P01 = (L1 + 1) P2 + 5, L0 + 1 planes (plane L0 zero).  Every cell
+// whose lower corner lies in the box then reads its eight corners without a
+// test: the corners on the guard are zero, as outside the box.  Only points
+// below the box or past its last cell take the branch-free general path,
+// where corners outside the box get weight 0 and read element 0.  For
+// L = 32 the banks see j2 + 35 j1 + 8 j0 mod 64.  The layout must fit
+// kNccLdsCap floats (fill it with fill_lds_box).
+constexpr int kNccLdsCap = 38400;
+__host__ __device__ constexpr int ncc_lds_p2(int L2) { return L2 + 3; }
+__host__ __device__ constexpr int ncc_lds_p01(int L1, int L2) { return (L1 + 1) * (L2 + 3) + 5; }
 __host__ __device__ constexpr long ncc_lds_floats(int L0, int L1, int L2) {
-  return (long)L0 * ((long)L1 * (L2 + 3) + 5);
+  return (long)(L0 + 1) * ncc_lds_p01(L1, L2);
 }
+// GUARD = false keeps the test of a box without the guard (the fast path for
+// cells whose upper corners are in the box too), so that its sums round as
+// they did before the guard existed (the tensor build: its components are
+// compared with tolerances that its float32 rounding nearly fills).
+template <bool GUARD = true>
 __device__ __forceinline__ float sample_rotated_lds(const float* t, int L0, int L1, int L2, int P2, int P01,
                                                     const Rot& R, int u0, int u1, int u2) {
   const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;
@@ -83,8 +95,10 @@ __device__ __forceinline__ float sample_rotated_lds(const float* t, int L0, int 
   const float f0 = floorf(p0), f1 = floorf(p1), f2 = floorf(p2);
   const int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
   const float w0 = p0 - f0, w1 = p1 - f1, w2 = p2 - f2;
-  if ((unsigned)i0 < (unsigned)(L0 - 1) && (unsigned)i1 < (unsigned)(L1 - 1) && (unsigned)i2 < (unsigned)(L2 - 1)) {
-    // all eight corners inside the box (the common case)
+  const int e = GUARD ? 0 : 1;
+  if ((unsigned)i0 < (unsigned)(L0 - e) && (unsigned)i1 < (unsigned)(L1 - e) && (unsigned)i2 < (unsigned)(L2 - e)) {
+    // the lower corner in the box (the common case): the upper corners are
+    // in the box or on its zero guard
     const float* q = t + i0 * P01 + i1 * P2 + i2;
     const float c00 = q[0] + w2 * (q[1] - q[0]);
     const float c01 = q[P2] + w2 * (q[P2 + 1] - q[P2]);
@@ -123,24 +137,34 @@ __device__ __forceinline__ float sample_rotated_lds(const float* t, int L0, int 
 // Each of the block's nthreads threads keeps eight loads in flight before
 // its stores, so the copy is not a chain of dependent load-store steps.  The
 // caller synchronises before the box is read.
+// the box into the padded layout of sample_rotated_lds, the guard rows,
+// columns and plane zero: every float of the layout is written, eight loads
+// in flight per thread.  A layout index e is split into plane, row and column
+// by multiply-high with the reciprocals m = ceil(2^32 / d) of the pitches,
+// exact here: e < 2^17 and d < 2^11, so e (m d - 2^32) < e d < 2^32.
 __device__ __forceinline__ void fill_lds_box(float* tl, const float* __restrict__ src, int L0, int L1, int L2,
                                              int P2, int P01, int tid, int nthreads) {
-  const int nL = L0 * L1 * L2;
+  const int total = (L0 + 1) * P01;
+  const unsigned m01 = (unsigned)((0x100000000ull + (unsigned)P01 - 1) / (unsigned)P01);
+  const unsigned m2 = (unsigned)((0x100000000ull + (unsigned)P2 - 1) / (unsigned)P2);
   constexpr int U = 8;
-  for (int e0 = tid; e0 < nL; e0 += nthreads * U) {
+  for (int e0 = tid; e0 < total; e0 += nthreads * U) {
     float v[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      const int e = e0 + j * nthreads;
-      v[j] = e < nL ? src[e] : 0.0f;
+      const unsigned e = (unsigned)(e0 + j * nthreads);
+      const unsigned j0 = __umulhi(e, m01), rem = e - j0 * (unsigned)P01;
+      const unsigned j1 = __umulhi(rem, m2), j2 = rem - j1 * (unsigned)P2;
+      const bool in = (int)e < total && j0 < (unsigned)L0 && j1 < (unsigned)L1 && j2 < (unsigned)L2;
+      // an unconditional load (of element 0 outside the box), so that the
+      // group's loads issue before any wait
+      const float x = src[in ? ((int)j0 * L1 + (int)j1) * L2 + (int)j2 : 0];
+      v[j] = in ? x : 0.0f;
     }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const int e = e0 + j * nthreads;
-      if (e < nL) {
-        const int i2 = e % L2, r = e / L2;
-        tl[(r / L1) * P01 + (r % L1) * P2 + i2] = v[j];
-      }
+      if (e < total) tl[e] = v[j];
     }
   }
 }

@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(1024) k_snorm_rot(SnormGeo g, int nchunk, int 
     return;
   }
   const int L0 = g.L0, L1 = g.L1, L2 = g.L2;
-  const int P2 = L2 + 3, P01 = L1 * P2 + 5;
+  const int P2 = ncc_lds_p2(L2), P01 = ncc_lds_p01(L1, L2);
   const float* __restrict__ slab = slabs + (long)p * L0 * L1 * L2;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
