@@ -144,8 +144,9 @@ static CorrWs corr_layout(Carve& c, const Geo& g, int K) {
 struct PoseWs {
   unsigned* hist; unsigned* ctrl; unsigned long long* allc; unsigned long long* cand; double* stats;
   double* partials; int* cand_pos; double* seeds; PoseScratch ps;
-  // refine 3: per-candidate moved flags, the compact list of a round
-  int* moved; int* act_pos; int* act_idx; int* act_count;
+  // refine 3: two sets of per-candidate moved flags; a round reads the
+  // previous round's set as its active mask and writes the other
+  int* moved[2];
 };
 // peaks = false: only the pose part (poses at given positions, no peak
 // search buffers)
@@ -172,29 +173,25 @@ static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refi
   w.ps.mlist = c.take<unsigned>((size_t)g.L0 * g.L1 * g.L2);
   w.ps.mval = c.take<float>((size_t)g.L0 * g.L1 * g.L2);
   w.ps.mcount = c.take<int>(1);
-  w.ps.sbest = c.take<double>(nb * 64);
-  w.ps.sidx = c.take<int>(nb * 64);
   w.ps.mom = c.take<double>(nb * 3);
   w.ps.mbits = c.take<unsigned long long>((size_t)mask_bricks(g.L0, g.L1, g.L2));
-  w.moved = w.act_pos = w.act_idx = w.act_count = nullptr;
-  if (refine == 3) {
-    const size_t P = (size_t)max_peaks;
-    w.moved = c.take<int>(P);
-    w.act_pos = c.take<int>(P * 3);
-    w.act_idx = c.take<int>(P);
-    w.act_count = c.take<int>(1);
-  }
+  w.ps.active = nullptr;
+  w.moved[0] = w.moved[1] = nullptr;
+  if (refine == 3)
+    for (int i = 0; i < 2; ++i) w.moved[i] = c.take<int>((size_t)max_peaks);
   return w;
 }
 
 // refine 3: after the first round (the refinement of refine 2 from the
-// start positions, already written to the outputs, with w.moved set for the
-// candidates that moved), rounds on the candidates whose position changed,
-// until none moves or kRefineRounds rounds in all.  Most candidates move in
-// the first round, so the second spreads each candidate's neighbours over 9
-// blocks as the first does; the later rounds, with few candidates left, over
-// 27.  tensor(pos, count_dev) fills the pose scratch with C_n at the 27
-// neighbours of the listed candidates.
+// start positions, already written to the outputs, with w.moved[0] set for
+// the candidates that moved), rounds on the candidates whose position
+// changed in the round before, until none moves or kRefineRounds rounds in
+// all; each round starts from the candidates' rows of out_pos and writes its
+// results to the same rows.  Most candidates move in the first round, so the
+// second spreads each candidate's neighbours over 9 blocks as the first
+// does; the later rounds, with few candidates left, over 27.  tensor(pos,
+// count_dev, count_host, ps) fills the pose scratch ps with C_n at the 27
+// neighbours of the candidates that ps.active marks.
 template <class TensorFn>
 static ttm_status refine_rounds(const Geo& g, const float* score, int order_n, const ttm_options* opt,
                                 int max_peaks, const int* count_dev, int count_host, const float* image,
@@ -202,13 +199,13 @@ static ttm_status refine_rounds(const Geo& g, const float* score, int order_n, c
                                 double* out_lambda, float* out_score, int32_t* out_flags, double* out_C, PoseWs& w,
                                 TensorFn tensor, hipStream_t stream) {
   for (int r = 1; r < kRefineRounds; ++r) {
-    TTM_PROF(PC_POSE, launch_refine_compact(count_dev, count_host, w.moved, out_pos, w.act_pos, w.act_idx,
-                                            w.act_count, stream));
-    TTM_PROF(PC_POSE, tensor(w.act_pos, w.act_count));
+    PoseScratch ps = w.ps;
+    ps.active = w.moved[(r - 1) & 1];
+    TTM_PROF(PC_POSE, tensor(out_pos, count_dev, count_host, ps));
     TTM_PROF(PC_POSE, launch_pose_solve(g, score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
-                                        max_peaks, 2, w.act_pos, w.act_count, 0, image, tmpl, mask, out_pos,
-                                        out_quat, out_lambda, out_score, out_flags, out_C, w.ps, stream, true,
-                                        r == 1 ? 9 : 27, w.act_idx, w.moved));
+                                        max_peaks, 2, out_pos, count_dev, count_host, image, tmpl, mask, out_pos,
+                                        out_quat, out_lambda, out_score, out_flags, out_C, ps, stream, true,
+                                        r == 1 ? 9 : 27, w.moved[r & 1]));
   }
   return TTM_OK;
 }
@@ -536,11 +533,11 @@ static ttm_status recover_pose_into(const Geo& g, const float* score, const floa
   TTM_PROF(PC_POSE, launch_pose_solve(g, score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
                                       opt->max_peaks, rf, w.cand_pos, out_count, 0, image, tmpl, mask,
                                       out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, w.ps,
-                                      stream, false, 9, nullptr, w.moved));
+                                      stream, false, 9, w.moved[0]));
   if (opt->refine == 3) {
-    auto tensor = [&](const int* pos, const int* cnt) {
+    auto tensor = [&](const int* pos, const int* cnt, int cnt_host, const PoseScratch& ps) {
       return launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, opt->max_peaks, 2, pos,
-                                cnt, 0, w.ps, stream);
+                                cnt, cnt_host, ps, stream);
     };
     TTM_CALL(refine_rounds(g, score, order_n, opt, opt->max_peaks, out_count, 0, image, tmpl, mask, out_pos,
                            out_quat, out_lambda, out_peak_score, out_flags, out_C, w, tensor, stream));
@@ -603,12 +600,11 @@ static ttm_status pose_at_into(const Geo& g, const float* image, const float* co
                                        rf, positions, nullptr, n_pos, w.ps, stream));
   TTM_PROF(PC_POSE, launch_pose_solve(g, nullptr, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol, n_pos,
                                       rf, positions, nullptr, n_pos, image, tmpl, mask, out_pos, out_quat,
-                                      out_lambda, nullptr, out_flags, out_C, w.ps, stream, false, 9, nullptr,
-                                      w.moved));
+                                      out_lambda, nullptr, out_flags, out_C, w.ps, stream, false, 9, w.moved[0]));
   if (opt->refine == 3) {
-    auto tensor = [&](const int* pos, const int* cnt) {
-      return launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, n_pos, 2, pos, cnt, 0,
-                                w.ps, stream);
+    auto tensor = [&](const int* pos, const int* cnt, int cnt_host, const PoseScratch& ps) {
+      return launch_pose_tensor(g, image, components, mask, order_n, w.stats, opt->eps_v, n_pos, 2, pos, cnt,
+                                cnt_host, ps, stream);
     };
     TTM_CALL(refine_rounds(g, nullptr, order_n, opt, n_pos, nullptr, n_pos, image, tmpl, mask, out_pos, out_quat,
                            out_lambda, nullptr, out_flags, out_C, w, tensor, stream));
@@ -695,10 +691,10 @@ ttm_status ttm_match(const float* image, ttm_dims N, const void* bank, ttm_dims 
   TTM_PROF(PC_POSE, launch_pose_solve(g, out_score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol,
                                       opt->max_peaks, rf, pw.cand_pos, out_count, 0, image, tmpl, mask,
                                       out_pos, out_quat, out_lambda, out_peak_score, out_flags, out_C, pw.ps,
-                                      stream, false, 9, nullptr, pw.moved));
+                                      stream, false, 9, pw.moved[0]));
   if (opt->refine == 3) {
-    auto tensor = [&](const int* pos, const int* cnt) {
-      return launch_field_at(g, cw.H, g.half(), K, wout, opt->max_peaks, 2, pos, cnt, 0, pw.ps, stream);
+    auto tensor = [&](const int* pos, const int* cnt, int cnt_host, const PoseScratch& ps) {
+      return launch_field_at(g, cw.H, g.half(), K, wout, opt->max_peaks, 2, pos, cnt, cnt_host, ps, stream);
     };
     TTM_CALL(refine_rounds(g, out_score, order_n, opt, opt->max_peaks, out_count, 0, image, tmpl, mask, out_pos,
                            out_quat, out_lambda, out_peak_score, out_flags, out_C, pw, tensor, stream));
@@ -1301,11 +1297,11 @@ ttm_status ttm_match_2d(const float* images, int32_t B, int32_t n1, int32_t n2, 
                                        m.total, 0, w.ps, stream));
   TTM_PROF(PC_POSE, launch_pose_solve(gs, out_score, order_n, opt->n_seeds, opt->hopm_max_iter, opt->hopm_tol, BP, rf,
                                       m.list, m.total, 0, images, tmpl, mask, m.pos3, m.quat3, m.lam3, m.score3,
-                                      m.flags3, nullptr, w.ps, stream, false, 9, nullptr, w.moved));
+                                      m.flags3, nullptr, w.ps, stream, false, 9, w.moved[0]));
   if (opt->refine == 3) {
-    auto tensor = [&](const int* pos, const int* cnt) {
-      return launch_pose_tensor(gs, images, m.comps3, mask, order_n, w.stats, opt->eps_v, BP, 2, pos, cnt, 0, w.ps,
-                                stream);
+    auto tensor = [&](const int* pos, const int* cnt, int cnt_host, const PoseScratch& ps) {
+      return launch_pose_tensor(gs, images, m.comps3, mask, order_n, w.stats, opt->eps_v, BP, 2, pos, cnt, cnt_host,
+                                ps, stream);
     };
     TTM_CALL(refine_rounds(gs, out_score, order_n, opt, BP, m.total, 0, images, tmpl, mask, m.pos3, m.quat3, m.lam3,
                            m.score3, m.flags3, nullptr, w, tensor, stream));

@@ -717,14 +717,15 @@ __global__ void __launch_bounds__(256) k_field_at(P3Geo g, const float2* __restr
                                                   const float* __restrict__ wmap, int refine,
                                                   const int* __restrict__ pos, const int* __restrict__ count_dev,
                                                   int count_host, double* __restrict__ Cbuf,
-                                                  double* __restrict__ wbuf, int* __restrict__ okbuf) {
+                                                  double* __restrict__ wbuf, int* __restrict__ okbuf,
+                                                  const int* __restrict__ active) {
   extern __shared__ float2 twf[];            // n2 entries: (cos, sin)(2 pi j / n2)
   const int rows = refine ? 9 : 1;
   const int NB = refine ? 27 : 1;
   const int b = blockIdx.x;
   const int p = b / rows, r = b % rows;
   const int count = count_dev ? count_dev[0] : count_host;
-  if (p >= count) return;
+  if (p >= count || (active && !active[p])) return;
   const int tid = threadIdx.x;
   for (int j = tid; j < g.n2; j += 256) {
     float sn, cs;
@@ -778,7 +779,7 @@ hipError_t launch_field_at(const Geo& gg, const float2* H, long pstride, int K, 
   const P3Geo q = make_p3geo(gg);
   const unsigned nblk = (unsigned)(max_peaks * (refine ? 9 : 1));
   hipLaunchKernelGGL(k_field_at, dim3(nblk), dim3(256), sizeof(float2) * gg.n2, s, q, H, pstride, K, wmap,
-                     refine, pos_in, count_dev, count_host, ps.C, ps.w, ps.ok);
+                     refine, pos_in, count_dev, count_host, ps.C, ps.w, ps.ok, ps.active);
   return hipGetLastError();
 }
 

@@ -162,22 +162,22 @@ struct PoseScratch {
   unsigned* mlist;  // L0 L1 L2: packed coordinates of the mask voxels (refine 2)
   float* mval;      // L0 L1 L2: their mask values
   int* mcount;      // 1: their number
-  double* sbest;    // max_peaks * NB * 64: seed scan, best lambda per slot
-  int* sidx;        // max_peaks * NB * 64: and its seed index
   double* mom;      // max_peaks * NB * 3: sum m f, sum m f^2, sum m (direct tensor)
   unsigned long long* mbits;  // mask_bricks(L): per 4x4x4 brick of the mask box, its voxels with m != 0
+  // max_peaks or null: the candidates a refinement round refines (a
+  // candidate p with active[p] == 0 is skipped by every pose kernel and its
+  // outputs are left as they are); null: all of them
+  const int* active;
 };
 
 // iterated refinement (refine 3): the rounds after the first (fewer
 // candidates move in each, so from the third round on the NCC kernel spreads
 // each candidate's 27 neighbours over 27 blocks instead of 9, trading
 // template loads for latency).  Each round refines the candidates whose
-// moved flag is set (compacted into act_pos / act_idx / act_count, their
-// flags cleared) and writes its results to their rows, setting the flag of
-// each candidate that moved again.
+// moved flag the previous round set (its flags are the round's active mask)
+// from their current rows and writes its results to the same rows, with
+// moved flags of its own (0 for the candidates it skips).
 constexpr int kRefineRounds = 4;
-hipError_t launch_refine_compact(const int* count_dev, int count_host, int* moved, const int* pos, int* act_pos,
-                                 int* act_idx, int* act_count, hipStream_t s);
 // C_n(x) in float64 by direct window sums at max_peaks candidates (count from
 // count_dev if non-null, else count_host), at the 27 neighbours if refine
 hipError_t launch_pose_tensor(const Geo& g, const float* image, const float* comps, const float* mask,
@@ -194,14 +194,14 @@ hipError_t launch_field_at(const Geo& g, const float2* H, long pstride, int K, c
 // neighbour with the largest lambda (refine 1) or with the largest NCC of the
 // image window against the template rotated by the voxel's own eigenvector
 // (refine 2: image, tmpl and mask are read).  Candidate p's outputs go to
-// row out_rows[p] (row p if null); moved (if given) gets, per row, whether
-// the candidate left its position.
+// row p; moved (if given) gets, per row, whether the candidate left its
+// position.  Candidates that ps.active marks as settled are skipped.
 hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int n_seeds, int max_iter,
                              double tol, int max_peaks, int refine, const int* pos_in, const int* count_dev,
                              int count_host, const float* image, const float* tmpl, const float* mask,
                              int* out_pos, float* out_quat, double* out_lambda, float* out_score, int* out_flags,
                              double* out_C, const PoseScratch& ps, hipStream_t s, bool reuse_tables = false,
-                             int ncc_groups = 9, const int* out_rows = nullptr, int* moved = nullptr);
+                             int ncc_groups = 9, int* moved = nullptr);
 
 // the mask voxels with m != 0 (packed u0 | u1 << 10 | u2 << 20), their
 // values and their count, in 4x4x4 bricks in C order (C order within a

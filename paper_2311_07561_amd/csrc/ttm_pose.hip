@@ -610,12 +610,13 @@ __global__ void __launch_bounds__(256) k_pose_tensor(PoseGeo g, const float* __r
                                                      const double* __restrict__ img_stats, float eps_v,
                                                      const int* __restrict__ pos, const int* __restrict__ count_dev,
                                                      int count_host, int NB, double* __restrict__ Cbuf,
-                                                     double* __restrict__ wbuf, int* __restrict__ okbuf) {
+                                                     double* __restrict__ wbuf, int* __restrict__ okbuf,
+                                                     const int* __restrict__ active) {
   __shared__ double sh[4 * kTensorChunk];
   const int b = blockIdx.x;
   const int p = b / NB, k = b % NB;
   const int count = count_dev ? count_dev[0] : count_host;
-  if (p >= count) return;
+  if (p >= count || (active && !active[p])) return;
   const int tid = threadIdx.x;
   int o0, o1, o2;
   neighbour_offset(k, NB, o0, o1, o2);
@@ -723,13 +724,14 @@ __global__ void __launch_bounds__(kDirThreads) k_pose_direct(PoseGeo g, const fl
                                                              const float* __restrict__ mask, int K,
                                                              const int* __restrict__ pos,
                                                              const int* __restrict__ count_dev, int count_host,
-                                                             double* __restrict__ Gbuf, double* __restrict__ mom) {
+                                                             double* __restrict__ Gbuf, double* __restrict__ mom,
+                                                             const int* __restrict__ active) {
   constexpr int NO = O * O;                  // offsets (o1, o2) per block
   constexpr int NBT = O * O * O;
   __shared__ double red[4][NO * kDirGroup];
   const int p = blockIdx.x;
   const int count = count_dev ? count_dev[0] : count_host;
-  if (p >= count) return;
+  if (p >= count || (active && !active[p])) return;
   const int o0 = (int)blockIdx.y - (O / 2);
   const int ag = blockIdx.z;
   const int ngroups = (K + kDirGroup - 1) / kDirGroup;
@@ -833,12 +835,12 @@ __global__ void __launch_bounds__(256) k_pose_direct_finish(PoseGeo g, int K, co
                                                             const int* __restrict__ count_dev, int count_host,
                                                             int NB, int total, const double* __restrict__ mom,
                                                             double* __restrict__ Cbuf, double* __restrict__ wbuf,
-                                                            int* __restrict__ okbuf) {
+                                                            int* __restrict__ okbuf, const int* __restrict__ active) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= total) return;
   const int p = b / NB, k = b % NB;
   const int count = count_dev ? count_dev[0] : count_host;
-  if (p >= count) return;
+  if (p >= count || (active && !active[p])) return;
   int o0, o1, o2;
   neighbour_offset(k, NB, o0, o1, o2);
   const int x0 = pos[3 * p] + o0, x1 = pos[3 * p + 1] + o1, x2 = pos[3 * p + 2] + o2;
@@ -862,105 +864,92 @@ struct EigLds {
   double C[kMaxK];
 };
 
-// Seed scan of the eigen-solver, one 256-thread block per tensor: lambda(s) =
-// sum_alpha mu_alpha C_alpha s^alpha at every S^3 seed point s; for each of
-// 64 slots l the largest value over the seeds s = l mod 64 and its seed index
-// (the lowest index on ties).  Thread t scans the seeds t, t + 256, ...; the
-// four threads t = l mod 64 are then merged.
+// Dominant Z-eigenpair of one packed tensor per 256-thread block, in two
+// phases.  The seed scan (all four wavefronts): lambda(s) = sum_alpha mu_alpha
+// C_alpha s^alpha at every S^3 seed point s, thread t taking the seeds t,
+// t + 256, ...; for each of 64 slots l the largest value over the seeds
+// s = l mod 64 and its seed index (the lowest index on ties), the four threads
+// t = l mod 64 merged.  Then the first wavefront alone: lane l takes slot l's
+// best seed; the kStarts best mutually distant lane seeds are polished by
+// SS-HOPM (shifted power iteration) accelerated with Newton steps on the
+// sphere: a Newton step is taken when it is an ascent direction and a
+// backtracking search along it raises lambda, otherwise the shifted power
+// step; the wave keeps the best lambda.  The other wavefronts leave after the
+// scan, so the polish synchronises within its wavefront only.
+constexpr int kStarts = 8;
 template <int N>
-__global__ void __launch_bounds__(256) k_seed_scan(const double* __restrict__ seeds,
-                                                   const double* __restrict__ Cbuf,
-                                                   const int* __restrict__ okbuf, const int* __restrict__ count_dev,
-                                                   int count_host, int NB, int n_seeds,
-                                                   double* __restrict__ slot_best, int* __restrict__ slot_idx) {
+__global__ void __launch_bounds__(256) k_pose_eig(const double* __restrict__ seeds,
+                                                  const double* __restrict__ Cbuf,
+                                                  const int* __restrict__ okbuf, const int* __restrict__ count_dev,
+                                                  int count_host, int NB, int n_seeds, int max_iter, double tol,
+                                                  float* __restrict__ qbuf, double* __restrict__ lambuf,
+                                                  int* __restrict__ flagbuf, const int* __restrict__ active) {
+  constexpr int n = N;
   constexpr int K = (N + 1) * (N + 2) * (N + 3) / 6;
   __shared__ double muA[K];
   __shared__ double rb[256];
   __shared__ int ri[256];
-  const int b = blockIdx.x;
-  const int p = b / NB;
-  const int count = count_dev ? count_dev[0] : count_host;
-  if (p >= count || !okbuf[b]) return;
-  const int tid = threadIdx.x;
-  for (int k = tid; k < K; k += 256) {
-    int al[4];
-    alpha_of_dev(N, k, al);
-    double mu = fact_d(N);
-    for (int d = 0; d < 4; ++d) mu /= fact_d(al[d]);
-    muA[k] = mu * Cbuf[(long)b * K + k];
-  }
-  __syncthreads();
-  double best = -INFINITY;
-  int bseed = 0;
-  for (int sd = tid; sd < n_seeds; sd += 256) {
-    const double q[4] = {seeds[4 * sd], seeds[4 * sd + 1], seeds[4 * sd + 2], seeds[4 * sd + 3]};
-    const double v = eval_lambda<N>(muA, q);
-    if (v > best) {
-      best = v;
-      bseed = sd;
-    }
-  }
-  rb[tid] = best;
-  ri[tid] = bseed;
-  __syncthreads();
-  if (tid < 64) {
-    double bv = rb[tid];
-    int bi = ri[tid];
-    for (int j = 1; j < 4; ++j) {
-      const double v = rb[tid + 64 * j];
-      const int i = ri[tid + 64 * j];
-      if (v > bv || (v == bv && v > -INFINITY && i < bi)) {
-        bv = v;
-        bi = i;
-      }
-    }
-    slot_best[(long)b * 64 + tid] = bv;
-    slot_idx[(long)b * 64 + tid] = bi;
-  }
-}
-
-// Dominant Z-eigenpair of one packed tensor per wavefront: lane l takes the
-// best seed of slot l from the seed scan; the kStarts best mutually distant lane seeds
-// are polished by SS-HOPM (shifted power iteration) accelerated with Newton
-// steps on the sphere: a Newton step is taken when it is an ascent direction
-// and a backtracking search along it raises lambda, otherwise the shifted
-// power step; the wave keeps the best lambda.
-constexpr int kStarts = 8;
-template <int N>
-__global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seeds,
-                                                 const double* __restrict__ Cbuf,
-                                                 const int* __restrict__ okbuf, const int* __restrict__ count_dev,
-                                                 int count_host, int NB, const double* __restrict__ slot_best,
-                                                 const int* __restrict__ slot_idx, int max_iter, double tol,
-                                                 float* __restrict__ qbuf, double* __restrict__ lambuf,
-                                                 int* __restrict__ flagbuf) {
-  constexpr int n = N;
   __shared__ EigLds t;
   __shared__ double red[64 * 6];
-  const int K = num_components_dev(n);
   const int b = blockIdx.x;
   const int p = b / NB;
+  const int tid = threadIdx.x;
   const int count = count_dev ? count_dev[0] : count_host;
-  if (p >= count) return;
-  const int lane = threadIdx.x;
+  if (p >= count || (active && !active[p])) return;
   if (!okbuf[b]) {
-    if (lane == 0) {
+    if (tid == 0) {
       lambuf[b] = -INFINITY;
       flagbuf[b] = 0;
     }
     return;
   }
-  for (int k = lane; k < K; k += 64) t.C[k] = Cbuf[(long)b * K + k];
+  for (int k = tid; k < K; k += 256) {
+    int al[4];
+    alpha_of_dev(N, k, al);
+    double mu = fact_d(N);
+    for (int d = 0; d < 4; ++d) mu /= fact_d(al[d]);
+    const double c = Cbuf[(long)b * K + k];
+    muA[k] = mu * c;
+    t.C[k] = c;
+  }
   __syncthreads();
+  {
+    double bv = -INFINITY;
+    int bs = 0;
+    for (int sd = tid; sd < n_seeds; sd += 256) {
+      const double q[4] = {seeds[4 * sd], seeds[4 * sd + 1], seeds[4 * sd + 2], seeds[4 * sd + 3]};
+      const double v = eval_lambda<N>(muA, q);
+      if (v > bv) {
+        bv = v;
+        bs = sd;
+      }
+    }
+    rb[tid] = bv;
+    ri[tid] = bs;
+  }
+  __syncthreads();
+  if (tid >= 64) return;
+  const int lane = tid;
   // the seed scan's best seed of this lane's slot
-  const double best = slot_best[(long)b * 64 + lane];
-  const int bseed = slot_idx[(long)b * 64 + lane];
+  double best = rb[lane];
+  int bseed = ri[lane];
+  for (int j = 1; j < 4; ++j) {
+    const double v = rb[lane + 64 * j];
+    const int i = ri[lane + 64 * j];
+    if (v > best || (v == best && v > -INFINITY && i < bseed)) {
+      best = v;
+      bseed = i;
+    }
+  }
   // the kStarts best lane seeds that are mutually more than 10 degrees apart
   // (|<q, q'>| < cos 5 deg) start the polish
   red[lane * 6 + 0] = best;
   red[lane * 6 + 1] = (double)bseed;
-  __syncthreads();
-  __shared__ int starts[kStarts];
+  // every lane's seed point, loaded by all lanes at once, so that the walk
+  // over the slots below reads LDS only
+  __shared__ double sq[64][4];
+  for (int d = 0; d < 4; ++d) sq[lane][d] = seeds[4 * bseed + d];
+  wave_sync();
   __shared__ int nstart;
   __shared__ double sel[kStarts][4];
   // each slot's place in the order (best first, the lower lane on ties),
@@ -970,7 +959,7 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
   __shared__ int order[64];
   __shared__ int any_nan;
   if (lane == 0) any_nan = 0;
-  __syncthreads();
+  wave_sync();
   {
     int rank = 0;
     for (int l = 0; l < 64; ++l) {
@@ -980,15 +969,14 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
     if (best != best) any_nan = 1;
     else order[rank] = lane;
   }
-  __syncthreads();
+  wave_sync();
   if (lane == 0 && !any_nan) {
     const double cosx = 0.99619469809174553;
     int ns = 0;
     for (int k = 0; k < 64 && ns < kStarts; ++k) {
       const int bl = order[k];
       if (!(red[bl * 6] > -INFINITY)) break;
-      const int si = (int)red[bl * 6 + 1];
-      const double q[4] = {seeds[4 * si], seeds[4 * si + 1], seeds[4 * si + 2], seeds[4 * si + 3]};
+      const double q[4] = {sq[bl][0], sq[bl][1], sq[bl][2], sq[bl][3]};
       bool far = true;
       for (int i = 0; i < ns; ++i) {
         const double dp = q[0] * sel[i][0] + q[1] * sel[i][1] + q[2] * sel[i][2] + q[3] * sel[i][3];
@@ -996,7 +984,7 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
       }
       if (!far) continue;
       for (int d = 0; d < 4; ++d) sel[ns][d] = q[d];
-      starts[ns++] = si;
+      ++ns;
     }
     nstart = ns;
   }
@@ -1010,8 +998,7 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
         if (!((used >> l) & 1ull) && (bl < 0 || red[l * 6] > red[bl * 6])) bl = l;
       if (bl < 0 || !(red[bl * 6] > -INFINITY)) break;
       used |= 1ull << bl;
-      const int si = (int)red[bl * 6 + 1];
-      const double q[4] = {seeds[4 * si], seeds[4 * si + 1], seeds[4 * si + 2], seeds[4 * si + 3]};
+      const double q[4] = {sq[bl][0], sq[bl][1], sq[bl][2], sq[bl][3]};
       bool far = true;
       for (int i = 0; i < ns; ++i) {
         const double dp = q[0] * sel[i][0] + q[1] * sel[i][1] + q[2] * sel[i][2] + q[3] * sel[i][3];
@@ -1019,30 +1006,32 @@ __global__ void __launch_bounds__(64) k_pose_eig(const double* __restrict__ seed
       }
       if (!far) continue;
       for (int d = 0; d < 4; ++d) sel[ns][d] = q[d];
-      starts[ns++] = (int)red[bl * 6 + 1];
+      ++ns;
     }
     nstart = ns;
   }
-  __syncthreads();
+  wave_sync();
   double lam = -INFINITY;
   double x[4] = {1.0, 0.0, 0.0, 0.0};
   bool conv = false;
   // the best seed may iterate up to max_iter; the runner-up seeds, kept for
-  // near-degenerate tensors with competing maxima, stop after 30 iterations
-  const int lane_iters = lane == 0 ? max_iter : min(max_iter, 30);
+  // near-degenerate tensors with competing maxima, stop after 12 iterations
+  // (from the scan's seeds they converge in 4 to 6; the wave waits for its
+  // slowest lane)
+  const int lane_iters = lane == 0 ? max_iter : min(max_iter, 12);
   if (lane < nstart) {
-    for (int d = 0; d < 4; ++d) x[d] = seeds[4 * starts[lane] + d];
+    for (int d = 0; d < 4; ++d) x[d] = sel[lane][d];
     conv = eig_polish<N>(t.C, x, lam, lane_iters, tol);
   }
   // wave argmax of lambda (lowest lane on ties)
-  __syncthreads();
+  wave_sync();
   red[lane * 6 + 0] = lam;
   red[lane * 6 + 1] = x[0];
   red[lane * 6 + 2] = x[1];
   red[lane * 6 + 3] = x[2];
   red[lane * 6 + 4] = x[3];
   red[lane * 6 + 5] = conv ? 0.0 : 1.0;
-  __syncthreads();
+  wave_sync();
   if (lane == 0) {
     int bl = 0;
     for (int l = 1; l < 64; ++l)
@@ -1107,13 +1096,13 @@ template <int N>
 __global__ void __launch_bounds__(64) k_planar_eig(const double* __restrict__ Cbuf, const int* __restrict__ okbuf,
                                                   const int* __restrict__ count_dev, int count_host, int NB,
                                                   float* __restrict__ qbuf, double* __restrict__ lambuf,
-                                                  int* __restrict__ flagbuf) {
+                                                  int* __restrict__ flagbuf, const int* __restrict__ active) {
   constexpr int K = (N + 1) * (N + 2) * (N + 3) / 6;
   const int b = blockIdx.x;
   const int p = b / NB;
-  const int count = count_dev ? count_dev[0] : count_host;
-  if (p >= count) return;
   const int lane = threadIdx.x;
+  const int count = count_dev ? count_dev[0] : count_host;
+  if (p >= count || (active && !active[p])) return;
   if (!okbuf[b]) {
     if (lane == 0) {
       lambuf[b] = -INFINITY;
@@ -1351,6 +1340,82 @@ hipError_t launch_mask_list(const float* mask, int L0, int L1, int L2, unsigned*
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------------------------
+// the pick of each candidate's neighbour
+// ----------------------------------------------------------------------------
+struct PickArgs {
+  const float* score;
+  int K, NB;
+  const int* pos_in;
+  const double* C;
+  const double* w;
+  const float* q;
+  const double* lam;
+  const double* key;
+  const int* flags;
+  int* out_pos;
+  float* out_quat;
+  double* out_lambda;
+  float* out_score;
+  int* out_flags;
+  double* out_C;
+  const int* active;
+  int* moved;
+};
+
+// Per candidate, one wavefront: the neighbour with the largest key (lambda
+// for refine 1, the NCC at its own rotation for refine 2), the centre first
+// on ties, then the lower neighbour index; lane 0 writes the scalars to the
+// candidate's row, the lanes copy the picked tensor together.  moved (if
+// given) records whether the candidate left its position; a candidate that
+// active (if given) marks as settled is left as it is, with moved 0.
+__global__ void __launch_bounds__(64) k_pose_pick(PoseGeo g, PickArgs a, const int* __restrict__ count_dev,
+                                                  int count_host) {
+  __shared__ double keys[27];
+  __shared__ int pickv;
+  const int p = blockIdx.x;
+  const int count = count_dev ? count_dev[0] : count_host;
+  if (p >= count) return;
+  const int lane = threadIdx.x;
+  if (a.active && !a.active[p]) {
+    if (lane == 0 && a.moved) a.moved[p] = 0;
+    return;
+  }
+  const int NB = a.NB;
+  if (lane < NB) keys[lane] = a.key[(long)p * NB + lane];
+  __syncthreads();
+  if (lane == 0) {
+    const int centre = NB == 27 ? 13 : 0;
+    int bk = centre;
+    double bv = keys[centre];
+    for (int k = 0; k < NB; ++k)
+      if (keys[k] > bv) {
+        bv = keys[k];
+        bk = k;
+      }
+    pickv = bk;
+    const long b = (long)p * NB + bk;
+    int o0, o1, o2;
+    neighbour_offset(bk, NB, o0, o1, o2);
+    const int x0 = a.pos_in[3 * p] + o0, x1 = a.pos_in[3 * p + 1] + o1, x2 = a.pos_in[3 * p + 2] + o2;
+    a.out_pos[3 * p] = x0;
+    a.out_pos[3 * p + 1] = x1;
+    a.out_pos[3 * p + 2] = x2;
+    for (int d = 0; d < 4; ++d) a.out_quat[4 * p + d] = a.q[4 * b + d];
+    a.out_lambda[p] = a.lam[b];
+    int flags = a.flags[b];
+    if (!(a.w[b] > 0.0)) flags |= TTM_POSE_ZERO_NORM;
+    a.out_flags[p] = flags;
+    if (a.out_score) a.out_score[p] = a.score ? a.score[((long)x0 * g.n1 + x1) * g.n2 + x2] : 0.0f;
+    if (a.moved) a.moved[p] = bk != centre ? 1 : 0;
+  }
+  if (a.out_C) {
+    __syncthreads();
+    const long b = (long)p * NB + pickv;
+    for (int k = lane; k < a.K; k += 64) a.out_C[(long)p * a.K + k] = a.C[b * a.K + k];
+  }
+}
+
 // c(y, R(q_y)) = w(y) <tau_y f, s_R> for the rotation q_y found at voxel y
 // (Section 2, the normalised correlation of Algorithm 1, with s_R the raw
 // template rotated by R and normalised under the mask):
@@ -1359,30 +1424,16 @@ hipError_t launch_mask_list(const float* mask, int L0, int L1, int L2, unsigned*
 //   f the image window.
 // Per-thread partial sums in float32 over the compacted mask voxels, the block
 // reduction and the normalisation in float64.  -inf outside the valid region;
-// 0 where w(y) = 0 or the rotated template has no masked variance.  One block
-// per (candidate, neighbour).
-__global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __restrict__ image,
-                                                  const float* __restrict__ tmpl, const unsigned* __restrict__ mlist,
-                                                  const float* __restrict__ mval,
-                                                  const int* __restrict__ mcount, const int* __restrict__ pos,
-                                                  const int* __restrict__ count_dev, int count_host, int NB,
-                                                  const double* __restrict__ wbuf, const int* __restrict__ okbuf,
-                                                  const float* __restrict__ qbuf, double* __restrict__ nccbuf) {
+// 0 where w(y) = 0 or the rotated template has no masked variance.
+// k_pose_ncc takes one block per (candidate, neighbour); ncc_one is the NCC of neighbour k of candidate p
+// (its w > 0, its window in the image) by the block's 256 threads, written to
+// *out by thread 0.
+__device__ void ncc_one(const PoseGeo& g, const float* __restrict__ image, const float* __restrict__ tmpl,
+                        const unsigned* __restrict__ mlist, const float* __restrict__ mval,
+                        const int* __restrict__ mcount, const int* __restrict__ pos, int p, int k, int NB, double w,
+                        const float* __restrict__ q4, double* __restrict__ out) {
   __shared__ double red[4][5];
-  const int b = blockIdx.x;
-  const int p = b / NB, k = b % NB;
-  const int count = count_dev ? count_dev[0] : count_host;
-  if (p >= count) return;
   const int tid = threadIdx.x;
-  if (!okbuf[b]) {
-    if (tid == 0) nccbuf[b] = -INFINITY;
-    return;
-  }
-  const double w = wbuf[b];
-  if (!(w > 0.0)) {
-    if (tid == 0) nccbuf[b] = 0.0;
-    return;
-  }
   int o0, o1, o2;
   neighbour_offset(k, NB, o0, o1, o2);
   const int x0 = pos[3 * p] + o0, x1 = pos[3 * p + 1] + o1, x2 = pos[3 * p + 2] + o2;
@@ -1391,7 +1442,7 @@ __global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __rest
   // okbuf: the window lies inside the image (valid region), no wrap needed
   const float* __restrict__ base = image + ((long)(x0 - c0) * g.n1 + (x1 - c1)) * g.n2 + (x2 - c2);
   const int rs1 = g.n2, rs0 = g.n1 * g.n2;       // window strides (< 2^31 elements)
-  const Rot R = quat_rot(qbuf + 4 * (long)b);
+  const Rot R = quat_rot(q4);
   const int nm = mcount[0];
   float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, v3 = 0.0f, v4 = 0.0f;   // m, m g, m g^2, m f, m g f
   for (int i = tid; i < nm; i += 256) {
@@ -1422,7 +1473,29 @@ __global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __rest
     for (int i = 0; i < 5; ++i) t[i] = red[0][i] + red[1][i] + red[2][i] + red[3][i];
     const double mu = t[0] > 0.0 ? t[1] / t[0] : 0.0;
     const double var = t[2] - mu * t[1];
-    nccbuf[b] = var > 1e-6 * (t[2] > 0.0 ? t[2] : 1.0) ? w * (t[4] - mu * t[3]) / sqrt(var) : 0.0;
+    *out = var > 1e-6 * (t[2] > 0.0 ? t[2] : 1.0) ? w * (t[4] - mu * t[3]) / sqrt(var) : 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __restrict__ image,
+                                                  const float* __restrict__ tmpl, const unsigned* __restrict__ mlist,
+                                                  const float* __restrict__ mval,
+                                                  const int* __restrict__ mcount, const int* __restrict__ pos,
+                                                  const int* __restrict__ count_dev, int count_host, int NB,
+                                                  const double* __restrict__ wbuf, const int* __restrict__ okbuf,
+                                                  const float* __restrict__ qbuf, double* __restrict__ nccbuf,
+                                                  const int* __restrict__ active) {
+  const int b = blockIdx.x;
+  const int p = b / NB, k = b % NB;
+  const int count = count_dev ? count_dev[0] : count_host;
+  if (p >= count || (active && !active[p])) return;
+  const int tid = threadIdx.x;
+  if (!okbuf[b]) {
+    if (tid == 0) nccbuf[b] = -INFINITY;
+  } else if (!(wbuf[b] > 0.0)) {
+    if (tid == 0) nccbuf[b] = 0.0;
+  } else {
+    ncc_one(g, image, tmpl, mlist, mval, mcount, pos, p, k, NB, wbuf[b], qbuf + 4 * (long)b, nccbuf + b);
   }
 }
 
@@ -1441,7 +1514,7 @@ __global__ void __launch_bounds__(256) k_pose_ncc(PoseGeo g, const float* __rest
 // CU).
 constexpr int kNccLdsSmall = 4096;
 template <int NT, int CAP>
-__global__ void __launch_bounds__(NT) k_pose_ncc_lds(PoseGeo g, int ngroups, const float* __restrict__ image,
+__global__ void __launch_bounds__(NT, 1024 / NT) k_pose_ncc_lds(PoseGeo g, int ngroups, const float* __restrict__ image,
                                                        const float* __restrict__ tmpl,
                                                        const unsigned* __restrict__ mlist,
                                                        const float* __restrict__ mval,
@@ -1449,7 +1522,8 @@ __global__ void __launch_bounds__(NT) k_pose_ncc_lds(PoseGeo g, int ngroups, con
                                                        const int* __restrict__ count_dev, int count_host,
                                                        const double* __restrict__ wbuf,
                                                        const int* __restrict__ okbuf, const float* __restrict__ qbuf,
-                                                       double* __restrict__ nccbuf) {
+                                                       double* __restrict__ nccbuf,
+                                                       const int* __restrict__ active) {
   constexpr int NW = NT / 64;
   __shared__ float tl[CAP];
   __shared__ double red[NW][15];
@@ -1458,7 +1532,7 @@ __global__ void __launch_bounds__(NT) k_pose_ncc_lds(PoseGeo g, int ngroups, con
   const int gsize = (NB + ngroups - 1) / ngroups;
   const int k_lo = grp * gsize, k_hi = min(NB, k_lo + gsize);
   const int count = count_dev ? count_dev[0] : count_host;
-  if (p >= count) return;
+  if (p >= count || (active && !active[p])) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int L0 = g.L0, L1 = g.L1, L2 = g.L2, nL = L0 * L1 * L2;
   const int P2 = ncc_lds_p2(L2), P01 = ncc_lds_p01(L1, L2);
@@ -1583,114 +1657,6 @@ __global__ void __launch_bounds__(NT) k_pose_ncc_lds(PoseGeo g, int ngroups, con
   }
 }
 
-// per candidate: the neighbour with the largest dominant Z-eigenvalue
-// (refine 1) or with the largest NCC at its own dominant rotation (refine 2);
-// the centre first on ties, then the lower neighbour index.  One wavefront per
-// candidate: the keys are read in parallel, lane 0 picks and writes the
-// scalars, and the lanes copy the picked tensor together.  Candidate p's
-// outputs go to row out_rows[p] (row p if null); moved (if given) records
-// whether the candidate left its position.
-__global__ void __launch_bounds__(64) k_pose_pick(PoseGeo g, const float* __restrict__ score, int K,
-                                                  const int* __restrict__ pos_in, const int* __restrict__ count_dev,
-                                                  int count_host, int NB, const double* __restrict__ Cbuf,
-                                                  const double* __restrict__ wbuf, const float* __restrict__ qbuf,
-                                                  const double* __restrict__ lambuf,
-                                                  const double* __restrict__ keybuf, const int* __restrict__ flagbuf,
-                                                  int* __restrict__ out_pos, float* __restrict__ out_quat,
-                                                  double* __restrict__ out_lambda, float* __restrict__ out_score,
-                                                  int* __restrict__ out_flags, double* __restrict__ out_C,
-                                                  const int* __restrict__ out_rows, int* __restrict__ moved) {
-  __shared__ double keys[27];
-  __shared__ int pick;
-  const int p = blockIdx.x;
-  const int count = count_dev ? count_dev[0] : count_host;
-  if (p >= count) return;
-  const int lane = threadIdx.x;
-  if (lane < NB) keys[lane] = keybuf[(long)p * NB + lane];
-  __syncthreads();
-  if (lane == 0) {
-    const int centre = NB == 27 ? 13 : 0;
-    int bk = centre;
-    double bv = keys[centre];
-    for (int k = 0; k < NB; ++k)
-      if (keys[k] > bv) {
-        bv = keys[k];
-        bk = k;
-      }
-    pick = bk;
-    const long b = (long)p * NB + bk;
-    int o0, o1, o2;
-    neighbour_offset(bk, NB, o0, o1, o2);
-    const int x0 = pos_in[3 * p] + o0, x1 = pos_in[3 * p + 1] + o1, x2 = pos_in[3 * p + 2] + o2;
-    const int r = out_rows ? out_rows[p] : p;
-    out_pos[3 * r] = x0;
-    out_pos[3 * r + 1] = x1;
-    out_pos[3 * r + 2] = x2;
-    for (int d = 0; d < 4; ++d) out_quat[4 * r + d] = qbuf[4 * b + d];
-    out_lambda[r] = lambuf[b];
-    int flags = flagbuf[b];
-    if (!(wbuf[b] > 0.0)) flags |= TTM_POSE_ZERO_NORM;
-    out_flags[r] = flags;
-    if (out_score) out_score[r] = score ? score[((long)x0 * g.n1 + x1) * g.n2 + x2] : 0.0f;
-    if (moved) moved[r] = bk != centre ? 1 : 0;
-  }
-  if (out_C) {
-    __syncthreads();
-    const long b = (long)p * NB + pick;
-    const long r = out_rows ? out_rows[p] : p;
-    for (int k = lane; k < K; k += 64) out_C[r * K + k] = Cbuf[b * K + k];
-  }
-}
-
-// ----------------------------------------------------------------------------
-// iterated refinement (refine 3): after the first refinement, the candidates
-// that moved are compacted into a list that the next round refines again
-// ----------------------------------------------------------------------------
-// one block: the moving candidates in index order (an LDS prefix sum per
-// chunk of 1024); their flags are cleared for the round
-__global__ void __launch_bounds__(1024) k_refine_compact(const int* __restrict__ count_dev, int count_host,
-                                                         int* __restrict__ moved, const int* __restrict__ pos,
-                                                         int* __restrict__ act_pos, int* __restrict__ act_idx,
-                                                         int* __restrict__ act_count) {
-  __shared__ int sh[1024];
-  __shared__ int base;
-  const int tid = threadIdx.x;
-  const int n = count_dev ? count_dev[0] : count_host;
-  if (tid == 0) base = 0;
-  __syncthreads();
-  for (int c0 = 0; c0 < n; c0 += 1024) {
-    const int p = c0 + tid;
-    const int f = (p < n && moved[p]) ? 1 : 0;
-    sh[tid] = f;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const int v = tid >= off ? sh[tid - off] : 0;
-      __syncthreads();
-      sh[tid] += v;
-      __syncthreads();
-    }
-    if (f) {
-      const int j = base + sh[tid] - 1;
-      act_idx[j] = p;
-      act_pos[3 * j] = pos[3 * p];
-      act_pos[3 * j + 1] = pos[3 * p + 1];
-      act_pos[3 * j + 2] = pos[3 * p + 2];
-      moved[p] = 0;
-    }
-    __syncthreads();
-    if (tid == 1023) base += sh[1023];
-    __syncthreads();
-  }
-  if (tid == 0) act_count[0] = base;
-}
-
-hipError_t launch_refine_compact(const int* count_dev, int count_host, int* moved, const int* pos, int* act_pos,
-                                 int* act_idx, int* act_count, hipStream_t s) {
-  hipLaunchKernelGGL(k_refine_compact, dim3(1), dim3(1024), 0, s, count_dev, count_host, moved, pos, act_pos,
-                     act_idx, act_count);
-  return hipGetLastError();
-}
-
 static PoseGeo make_posegeo(const Geo& gg) {
   PoseGeo g;
   g.n0 = gg.n0; g.n1 = gg.n1; g.n2 = gg.n2;
@@ -1713,17 +1679,17 @@ hipError_t launch_pose_tensor(const Geo& gg, const float* image, const float* co
     const int ngroups = (K + kDirGroup - 1) / kDirGroup;
     if (refine)
       hipLaunchKernelGGL(k_pose_direct<3>, dim3((unsigned)max_peaks, 3, (unsigned)(ngroups + 1)), dim3(kDirThreads),
-                         0, s, g, image, comps, mask, K, pos_in, count_dev, count_host, ps.C, ps.mom);
+                         0, s, g, image, comps, mask, K, pos_in, count_dev, count_host, ps.C, ps.mom, ps.active);
     else
       hipLaunchKernelGGL(k_pose_direct<1>, dim3((unsigned)max_peaks, 1, (unsigned)(ngroups + 1)), dim3(kDirThreads),
-                         0, s, g, image, comps, mask, K, pos_in, count_dev, count_host, ps.C, ps.mom);
+                         0, s, g, image, comps, mask, K, pos_in, count_dev, count_host, ps.C, ps.mom, ps.active);
     const int total = max_peaks * NB;
     hipLaunchKernelGGL(k_pose_direct_finish, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, K, img_stats,
-                       eps_v, pos_in, count_dev, count_host, NB, total, ps.mom, ps.C, ps.w, ps.ok);
+                       eps_v, pos_in, count_dev, count_host, NB, total, ps.mom, ps.C, ps.w, ps.ok, ps.active);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_pose_tensor, dim3((unsigned)(max_peaks * NB)), dim3(256), 0, s, g, image, comps, mask, K,
-                     img_stats, eps_v, pos_in, count_dev, count_host, NB, ps.C, ps.w, ps.ok);
+                     img_stats, eps_v, pos_in, count_dev, count_host, NB, ps.C, ps.w, ps.ok, ps.active);
   return hipGetLastError();
 }
 
@@ -1732,7 +1698,7 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
                              int count_host, const float* image, const float* tmpl, const float* mask,
                              int* out_pos, float* out_quat, double* out_lambda, float* out_score, int* out_flags,
                              double* out_C, const PoseScratch& ps, hipStream_t s, bool reuse_tables,
-                             int ncc_groups, const int* out_rows, int* moved) {
+                             int ncc_groups, int* moved) {
   const PoseGeo g = make_posegeo(gg);
   const int K = num_components(order_n);
   const int NB = refine ? 27 : 1;
@@ -1743,46 +1709,38 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
     switch (order_n) {
       case 2:
         hipLaunchKernelGGL(k_planar_eig<2>, eg, dim3(64), 0, s, ps.C, ps.ok, count_dev, count_host, NB, ps.q,
-                           ps.lam, ps.flags);
+                           ps.lam, ps.flags, ps.active);
         break;
       case 4:
         hipLaunchKernelGGL(k_planar_eig<4>, eg, dim3(64), 0, s, ps.C, ps.ok, count_dev, count_host, NB, ps.q,
-                           ps.lam, ps.flags);
+                           ps.lam, ps.flags, ps.active);
         break;
       case 6:
         hipLaunchKernelGGL(k_planar_eig<6>, eg, dim3(64), 0, s, ps.C, ps.ok, count_dev, count_host, NB, ps.q,
-                           ps.lam, ps.flags);
+                           ps.lam, ps.flags, ps.active);
         break;
       case 8:
         hipLaunchKernelGGL(k_planar_eig<8>, eg, dim3(64), 0, s, ps.C, ps.ok, count_dev, count_host, NB, ps.q,
-                           ps.lam, ps.flags);
+                           ps.lam, ps.flags, ps.active);
         break;
       default: return hipErrorInvalidValue;
     }
   } else switch (order_n) {
     case 2:
-      hipLaunchKernelGGL(k_seed_scan<2>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         n_seeds, ps.sbest, ps.sidx);
-      hipLaunchKernelGGL(k_pose_eig<2>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags);
+      hipLaunchKernelGGL(k_pose_eig<2>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                         n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags, ps.active);
       break;
     case 4:
-      hipLaunchKernelGGL(k_seed_scan<4>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         n_seeds, ps.sbest, ps.sidx);
-      hipLaunchKernelGGL(k_pose_eig<4>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags);
+      hipLaunchKernelGGL(k_pose_eig<4>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                         n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags, ps.active);
       break;
     case 6:
-      hipLaunchKernelGGL(k_seed_scan<6>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         n_seeds, ps.sbest, ps.sidx);
-      hipLaunchKernelGGL(k_pose_eig<6>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags);
+      hipLaunchKernelGGL(k_pose_eig<6>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                         n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags, ps.active);
       break;
     case 8:
-      hipLaunchKernelGGL(k_seed_scan<8>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         n_seeds, ps.sbest, ps.sidx);
-      hipLaunchKernelGGL(k_pose_eig<8>, eg, dim3(64), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
-                         ps.sbest, ps.sidx, max_iter, tol, ps.q, ps.lam, ps.flags);
+      hipLaunchKernelGGL(k_pose_eig<8>, eg, dim3(256), 0, s, ps.seeds, ps.C, ps.ok, count_dev, count_host, NB,
+                         n_seeds, max_iter, tol, ps.q, ps.lam, ps.flags, ps.active);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -1795,21 +1753,38 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
       // small boxes: 256 threads and 16 KiB of LDS per block
       hipLaunchKernelGGL((k_pose_ncc_lds<256, kNccLdsSmall>), dim3((unsigned)(max_peaks * ngroups)), dim3(256), 0, s,
                          g, ngroups, image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in, count_dev, count_host, ps.w,
-                         ps.ok, ps.q, ps.ncc);
+                         ps.ok, ps.q, ps.ncc, ps.active);
     } else if (lds <= kNccLdsCap) {
       // one block per CU (the template fills most of the LDS); each block
       // loads the template once for 27 / ngroups neighbours of a candidate
       hipLaunchKernelGGL((k_pose_ncc_lds<1024, kNccLdsCap>), dim3((unsigned)(max_peaks * ngroups)), dim3(1024), 0,
                          s, g, ngroups, image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in, count_dev, count_host,
-                         ps.w, ps.ok, ps.q, ps.ncc);
-    }
-    else
+                         ps.w, ps.ok, ps.q, ps.ncc, ps.active);
+    } else {
       hipLaunchKernelGGL(k_pose_ncc, eg, dim3(256), 0, s, g, image, tmpl, ps.mlist, ps.mval, ps.mcount, pos_in,
-                         count_dev, count_host, NB, ps.w, ps.ok, ps.q, ps.ncc);
+                         count_dev, count_host, NB, ps.w, ps.ok, ps.q, ps.ncc, ps.active);
+    }
   }
-  hipLaunchKernelGGL(k_pose_pick, dim3((unsigned)max_peaks), dim3(64), 0, s, g, score, K, pos_in, count_dev,
-                     count_host, NB, ps.C, ps.w, ps.q, ps.lam, refine == 2 ? ps.ncc : ps.lam, ps.flags, out_pos,
-                     out_quat, out_lambda, out_score, out_flags, out_C, out_rows, moved);
+  PickArgs pa;
+  pa.score = score;
+  pa.K = K;
+  pa.NB = NB;
+  pa.pos_in = pos_in;
+  pa.C = ps.C;
+  pa.w = ps.w;
+  pa.q = ps.q;
+  pa.lam = ps.lam;
+  pa.key = refine == 2 ? ps.ncc : ps.lam;
+  pa.flags = ps.flags;
+  pa.out_pos = out_pos;
+  pa.out_quat = out_quat;
+  pa.out_lambda = out_lambda;
+  pa.out_score = out_score;
+  pa.out_flags = out_flags;
+  pa.out_C = out_C;
+  pa.active = ps.active;
+  pa.moved = moved;
+  hipLaunchKernelGGL(k_pose_pick, dim3((unsigned)max_peaks), dim3(64), 0, s, g, pa, count_dev, count_host);
   return hipGetLastError();
 }
 

@@ -571,12 +571,6 @@ hipError_t launch_peaks(const Geo& g, const float* score, float, float, int max_
          _c.push_back(C(out_score, (long)planes * max_peaks, "out_score"));
          _c.push_back(C(out_count, 2L * planes, "out_count")););
 }
-hipError_t launch_refine_compact(const int* count_dev, int, int* moved, const int* pos, int* act_pos, int* act_idx,
-                                 int* act_count, hipStream_t s) {
-  LAUNCH("refine_compact", s, if (count_dev) _c.push_back(C(count_dev, 1, "count"));
-         _c.push_back(C(moved, 1, "moved")); _c.push_back(C(pos, 3, "pos")); _c.push_back(C(act_pos, 3, "act_pos"));
-         _c.push_back(C(act_idx, 1, "act_idx")); _c.push_back(C(act_count, 1, "act_count")););
-}
 hipError_t launch_pose_tensor(const Geo& g, const float* image, const float* comps, const float* mask, int order_n,
                               const double* img_stats, float, int max_peaks, int refine, const int* pos_in,
                               const int* count_dev, int, const PoseScratch& ps, hipStream_t s) {
@@ -585,7 +579,8 @@ hipError_t launch_pose_tensor(const Geo& g, const float* image, const float* com
          _c.push_back(C(mask, l3, "mask")); _c.push_back(C(img_stats, 2, "img_stats"));
          _c.push_back(C(pos_in, 3L * max_peaks, "pos_in")); if (count_dev) _c.push_back(C(count_dev, 1, "count"));
          _c.push_back(C(ps.C, nb * K, "ps.C")); _c.push_back(C(ps.w, nb, "ps.w")); _c.push_back(C(ps.ok, nb, "ps.ok"));
-         if (!g.planar) _c.push_back(C(ps.mom, nb * 3, "ps.mom")););
+         if (!g.planar) _c.push_back(C(ps.mom, nb * 3, "ps.mom"));
+         if (ps.active) _c.push_back(C(ps.active, max_peaks, "ps.active")););
 }
 hipError_t launch_field_at(const Geo& g, const float2* H, long pstride, int K, const float* wmap, int max_peaks,
                            int refine, const int* pos_in, const int* count_dev, int, const PoseScratch& ps,
@@ -594,19 +589,19 @@ hipError_t launch_field_at(const Geo& g, const float2* H, long pstride, int K, c
   LAUNCH("field_at", s, _c.push_back(C(H, (long)(K - 1) * pstride + g.half(), "H"));
          _c.push_back(C(wmap, g.vol(), "wmap")); _c.push_back(C(pos_in, 3L * max_peaks, "pos_in"));
          if (count_dev) _c.push_back(C(count_dev, 1, "count")); _c.push_back(C(ps.C, nb * K, "ps.C"));
-         _c.push_back(C(ps.w, nb, "ps.w")); _c.push_back(C(ps.ok, nb, "ps.ok")););
+         _c.push_back(C(ps.w, nb, "ps.w")); _c.push_back(C(ps.ok, nb, "ps.ok"));
+         if (ps.active) _c.push_back(C(ps.active, max_peaks, "ps.active")););
 }
 hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int n_seeds, int, double, int max_peaks,
                              int refine, const int* pos_in, const int* count_dev, int, const float* image,
                              const float* tmpl, const float* mask, int* out_pos, float* out_quat, double* out_lambda,
                              float* out_score, int* out_flags, double* out_C, const PoseScratch& ps, hipStream_t s,
-                             bool, int, const int* out_rows, int* moved) {
+                             bool, int, int* moved) {
   const long K = num_components(order_n), nb = (long)max_peaks * (refine ? 27 : 1), l3 = L3(g.L0, g.L1, g.L2);
   const long P = max_peaks;
   LAUNCH("pose_solve", s, if (score) _c.push_back(C(score, g.vol(), "score"));
          _c.push_back(C(ps.seeds, 4L * n_seeds, "ps.seeds")); _c.push_back(C(ps.C, nb * K, "ps.C"));
-         _c.push_back(C(ps.ok, nb, "ps.ok")); _c.push_back(C(ps.sbest, nb * 64, "ps.sbest"));
-         _c.push_back(C(ps.sidx, nb * 64, "ps.sidx")); _c.push_back(C(ps.q, nb * 4, "ps.q"));
+         _c.push_back(C(ps.ok, nb, "ps.ok")); _c.push_back(C(ps.q, nb * 4, "ps.q"));
          _c.push_back(C(ps.lam, nb, "ps.lam")); _c.push_back(C(ps.flags, nb, "ps.flags"));
          _c.push_back(C(ps.w, nb, "ps.w")); _c.push_back(C(pos_in, 3 * P, "pos_in"));
          if (count_dev) _c.push_back(C(count_dev, 1, "count")); if (refine == 2) {
@@ -618,10 +613,11 @@ hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int 
            _c.push_back(C(ps.mcount, 1, "ps.mcount"));
            _c.push_back(C(ps.ncc, nb, "ps.ncc"));
            _c.push_back(C(ps.mbits, mask_bricks(g.L0, g.L1, g.L2), "ps.mbits"));
-         } _c.push_back(C(out_pos, 3 * P, "out_pos"));
+         } if (ps.active) _c.push_back(C(ps.active, P, "ps.active"));
+         _c.push_back(C(out_pos, 3 * P, "out_pos"));
          _c.push_back(C(out_quat, 4 * P, "out_quat")); _c.push_back(C(out_lambda, P, "out_lambda"));
          _c.push_back(C(out_flags, P, "out_flags")); if (out_score) _c.push_back(C(out_score, P, "out_score"));
-         if (out_C) _c.push_back(C(out_C, P * K, "out_C")); if (out_rows) _c.push_back(C(out_rows, P, "out_rows"));
+         if (out_C) _c.push_back(C(out_C, P * K, "out_C"));
          if (moved) _c.push_back(C(moved, P, "moved")););
 }
 hipError_t launch_mask_list(const float* mask, int L0, int L1, int L2, unsigned* list, float* mval, int* count,
