@@ -172,7 +172,7 @@ static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refi
   w.ps.ncc = c.take<double>(nb);
   w.ps.mlist = c.take<unsigned>((size_t)g.L0 * g.L1 * g.L2);
   w.ps.mval = c.take<float>((size_t)g.L0 * g.L1 * g.L2);
-  w.ps.mcount = c.take<int>(1);
+  w.ps.mcount = c.take<int>(2);
   w.ps.mom = c.take<double>(nb * 3);
   w.ps.mbits = c.take<unsigned long long>((size_t)mask_bricks(g.L0, g.L1, g.L2));
   w.ps.active = nullptr;
@@ -1325,7 +1325,7 @@ static SnormWs snorm_layout(Carve& c, const ttm_dims& L, int n_rot, int max_pos)
   w.kap = c.take<double>((size_t)n_pad);
   w.mlist = c.take<unsigned>(nL);
   w.mval = c.take<float>(nL);
-  w.mcount = c.take<int>(1);
+  w.mcount = c.take<int>(2);   // the mask list's count and largest squared radius
   w.slabs = c.take<float>((size_t)n_win * nL);
   w.stat = c.take<double>(4 * (size_t)n_win);
   w.partial = c.take<double>((size_t)n_win * snorm_chunks(n_win, n_pad));

@@ -161,7 +161,7 @@ struct PoseScratch {
   double* ncc;    // max_peaks * NB: NCC at the voxel's own rotation (refine 2)
   unsigned* mlist;  // L0 L1 L2: packed coordinates of the mask voxels (refine 2)
   float* mval;      // L0 L1 L2: their mask values
-  int* mcount;      // 1: their number
+  int* mcount;      // 2: their number, their largest squared distance from the box centre L / 2
   double* mom;      // max_peaks * NB * 3: sum m f, sum m f^2, sum m (direct tensor)
   unsigned long long* mbits;  // mask_bricks(L): per 4x4x4 brick of the mask box, its voxels with m != 0
   // max_peaks or null: the candidates a refinement round refines (a
@@ -204,7 +204,8 @@ hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int 
                              int ncc_groups = 9, int* moved = nullptr);
 
 // the mask voxels with m != 0 (packed u0 | u1 << 10 | u2 << 20), their
-// values and their count, in 4x4x4 bricks in C order (C order within a
+// values, their count (count[0]) and their largest squared distance from the
+// box centre L / 2 (count[1]), in 4x4x4 bricks in C order (C order within a
 // brick).  With bits (mask_bricks words) and at most kMaskFastBricks bricks:
 // the bricks' ballots, then the entries at prefix-sum offsets, over the
 // whole chip; otherwise one block.

@@ -1173,6 +1173,12 @@ __global__ void __launch_bounds__(64) k_planar_eig(const double* __restrict__ Cb
 // lanes of a wave sample a compact region (fewer LDS bank conflicts in the
 // rotated gathers).  The order is fixed, so the float sums over it are
 // deterministic.  One block.
+// squared distance of voxel u from the box centre L / 2 (integer division)
+__device__ __forceinline__ int mask_r2(int u0, int u1, int u2, int L0, int L1, int L2) {
+  const int d0 = u0 - L0 / 2, d1 = u1 - L1 / 2, d2 = u2 - L2 / 2;
+  return d0 * d0 + d1 * d1 + d2 * d2;
+}
+
 __global__ void __launch_bounds__(1024) k_mask_list(const float* __restrict__ mask, int L0, int L1, int L2,
                                                     unsigned* __restrict__ list, float* __restrict__ mval,
                                                     int* __restrict__ count) {
@@ -1183,11 +1189,15 @@ __global__ void __launch_bounds__(1024) k_mask_list(const float* __restrict__ ma
   __shared__ unsigned long long bits_s[kChunk];
   __shared__ int off_s[kChunk + 1];
   __shared__ int wpart[16];
-  __shared__ int base;
+  __shared__ int base, r2s;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int B0 = (L0 + 3) / 4, B1 = (L1 + 3) / 4, B2 = (L2 + 3) / 4, nB = B0 * B1 * B2;
   const int j0 = lane >> 4, j1 = (lane >> 2) & 3, j2 = lane & 3;
-  if (tid == 0) base = 0;
+  int r2max = 0;
+  if (tid == 0) {
+    base = 0;
+    r2s = 0;
+  }
   // loads in flight per wave: the bricks of a wave are independent, so their
   // mask values are loaded in groups of kLoads before any ballot waits on one
   constexpr int kLoads = 8;
@@ -1263,6 +1273,7 @@ __global__ void __launch_bounds__(1024) k_mask_list(const float* __restrict__ ma
           const int o = off_s[i] + __popcll(bl & ((1ull << lane) - 1ull));
           list[o] = (unsigned)u0 | ((unsigned)u1 << 10) | ((unsigned)u2 << 20);
           mval[o] = v[j];
+          r2max = max(r2max, mask_r2(u0, u1, u2, L0, L1, L2));
         }
       }
     }
@@ -1274,15 +1285,21 @@ __global__ void __launch_bounds__(1024) k_mask_list(const float* __restrict__ ma
     }
     __syncthreads();
   }
-  if (tid == 0) count[0] = base;
+  atomicMax(&r2s, r2max);
+  __syncthreads();
+  if (tid == 0) {
+    count[0] = base;
+    count[1] = r2s;
+  }
 }
 
 // the same list over the whole chip: one wavefront per brick takes the
 // ballot of its voxels with m != 0 ...
 __global__ void __launch_bounds__(256) k_mask_bits(const float* __restrict__ mask, int L0, int L1, int L2, int nB,
-                                                   unsigned long long* __restrict__ bits) {
+                                                   unsigned long long* __restrict__ bits, int* __restrict__ count) {
   const int lane = threadIdx.x & 63;
   const int br = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (br == 0 && lane == 0) count[1] = 0;
   if (br >= nB) return;
   const int B1 = (L1 + 3) / 4, B2 = (L2 + 3) / 4;
   const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
@@ -1315,6 +1332,7 @@ __global__ void __launch_bounds__(256) k_mask_write(const float* __restrict__ ma
   int base = wsum[0] + wsum[1] + wsum[2] + wsum[3];
   for (int w = 0; w < wave; ++w) base += bc[w];
   if (br >= nB) return;
+  int r2 = 0;
   if ((bl >> lane) & 1ull) {
     const int B1 = (L1 + 3) / 4, B2 = (L2 + 3) / 4;
     const int b2 = br % B2, b1 = (br / B2) % B1, b0 = br / (B1 * B2);
@@ -1322,7 +1340,10 @@ __global__ void __launch_bounds__(256) k_mask_write(const float* __restrict__ ma
     const int o = base + __popcll(bl & ((1ull << lane) - 1ull));
     list[o] = (unsigned)u0 | ((unsigned)u1 << 10) | ((unsigned)u2 << 20);
     mval[o] = mask[(u0 * L1 + u1) * L2 + u2];
+    r2 = mask_r2(u0, u1, u2, L0, L1, L2);
   }
+  for (int off = 32; off > 0; off >>= 1) r2 = max(r2, __shfl_xor(r2, off));
+  if (lane == 0 && bl != 0ull) atomicMax(count + 1, r2);
   if (br == nB - 1 && lane == 0) count[0] = base + bc[wave];
 }
 
@@ -1331,7 +1352,7 @@ hipError_t launch_mask_list(const float* mask, int L0, int L1, int L2, unsigned*
   const long nB = mask_bricks(L0, L1, L2);
   if (bits && nB <= kMaskFastBricks) {
     const unsigned nblk = (unsigned)((nB + 3) / 4);
-    hipLaunchKernelGGL(k_mask_bits, dim3(nblk), dim3(256), 0, s, mask, L0, L1, L2, (int)nB, bits);
+    hipLaunchKernelGGL(k_mask_bits, dim3(nblk), dim3(256), 0, s, mask, L0, L1, L2, (int)nB, bits, count);
     hipLaunchKernelGGL(k_mask_write, dim3(nblk), dim3(256), 0, s, mask, L0, L1, L2, (int)nB, bits, list, mval,
                        count);
     return hipGetLastError();
@@ -1541,6 +1562,12 @@ __global__ void __launch_bounds__(NT, 1024 / NT) k_pose_ncc_lds(PoseGeo g, int n
   const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;
   const int rs1 = g.n2, rs0 = g.n1 * g.n2;
   const int nm = mcount[0];
+  // mcount[1]: the largest squared distance of a mask voxel from the centre;
+  // below the squared inscribed radius min(L / 2) every rotated sample point
+  // lies inside [0, L) on every axis (with a margin of at least 1 / L voxel,
+  // far above the float error of the rotated coordinates)
+  const int cmin = min(L0 / 2, min(L1 / 2, L2 / 2));
+  const bool inner = mcount[1] < cmin * cmin;
   // the block's neighbours in passes of up to kNccPass: one pass over the
   // mask voxels loads each list entry once and samples it under every live
   // neighbour's rotation (each neighbour's sums keep the voxel order of a
@@ -1594,39 +1621,50 @@ __global__ void __launch_bounds__(NT, 1024 / NT) k_pose_ncc_lds(PoseGeo g, int n
     // kNccLoads of a thread's mask voxels at a time: their list entries, then
     // their image values, are loaded before any sample waits on them.  Past
     // the list's end a slot holds voxel 0 with weight 0 and adds nothing, so
-    // each thread's sums are those of the plain loop over its voxels.
-    for (int i0 = tid; i0 < nm; i0 += NT * kNccLoads) {
-      unsigned pk[kNccLoads];
-      float mv[kNccLoads], fv[kNccPass][kNccLoads];
+    // each thread's sums are those of the plain loop over its voxels.  INNER:
+    // every mask voxel lies in the box's inscribed ball, so every sample
+    // takes the sampler's fast path and the test is left out.
+    auto pass = [&](auto inner_tag) {
+      constexpr bool INNER = decltype(inner_tag)::value;
+      for (int i0 = tid; i0 < nm; i0 += NT * kNccLoads) {
+        unsigned pk[kNccLoads];
+        float mv[kNccLoads], fv[kNccPass][kNccLoads];
 #pragma unroll
-      for (int jj = 0; jj < kNccLoads; ++jj) {
-        const int i = i0 + NT * jj;
-        pk[jj] = i < nm ? mlist[i] : 0u;
-        mv[jj] = i < nm ? mval[i] : 0.0f;
-      }
-#pragma unroll
-      for (int j = 0; j < kNccPass; ++j)
+        for (int jj = 0; jj < kNccLoads; ++jj) {
+          const int i = i0 + NT * jj;
+          pk[jj] = i < nm ? mlist[i] : 0u;
+          mv[jj] = i < nm ? mval[i] : 0.0f;
+        }
 #pragma unroll
         for (int jj = 0; jj < kNccLoads; ++jj) {
           const int u0 = (int)(pk[jj] & 1023u), u1 = (int)((pk[jj] >> 10) & 1023u), u2 = (int)(pk[jj] >> 20);
-          fv[j][jj] = live[j] ? bases[j][u0 * rs0 + u1 * rs1 + u2] : 0.0f;
+          // the voxel's offset in every neighbour's window
+          const int off = u0 * rs0 + u1 * rs1 + u2;
+#pragma unroll
+          for (int j = 0; j < kNccPass; ++j) fv[j][jj] = live[j] ? bases[j][off] : 0.0f;
         }
 #pragma unroll
-      for (int jj = 0; jj < kNccLoads; ++jj) {
-        const int u0 = (int)(pk[jj] & 1023u), u1 = (int)((pk[jj] >> 10) & 1023u), u2 = (int)(pk[jj] >> 20);
+        for (int jj = 0; jj < kNccLoads; ++jj) {
+          const int u0 = (int)(pk[jj] & 1023u), u1 = (int)((pk[jj] >> 10) & 1023u), u2 = (int)(pk[jj] >> 20);
 #pragma unroll
-        for (int j = 0; j < kNccPass; ++j) {
-          if (!live[j]) continue;
-          const float gv = sample_rotated_lds(tl, L0, L1, L2, P2, P01, R[j], u0, u1, u2);
-          const float mg = mv[jj] * gv;
-          v[j][0] += mv[jj];
-          v[j][1] += mg;
-          v[j][2] += mg * gv;
-          v[j][3] += mv[jj] * fv[j][jj];
-          v[j][4] += mg * fv[j][jj];
+          for (int j = 0; j < kNccPass; ++j) {
+            if (!live[j]) continue;
+            const float gv = INNER ? sample_rotated_lds_inner(tl, L0, L1, L2, P2, P01, R[j], u0, u1, u2)
+                                   : sample_rotated_lds(tl, L0, L1, L2, P2, P01, R[j], u0, u1, u2);
+            const float mg = mv[jj] * gv;
+            v[j][0] += mv[jj];
+            v[j][1] += mg;
+            v[j][2] += mg * gv;
+            v[j][3] += mv[jj] * fv[j][jj];
+            v[j][4] += mg * fv[j][jj];
+          }
         }
       }
-    }
+    };
+    if (inner)
+      pass(std::true_type{});
+    else
+      pass(std::false_type{});
 #pragma unroll
     for (int j = 0; j < kNccPass; ++j) {
       if (!live[j]) continue;

@@ -80,6 +80,32 @@ __host__ __device__ constexpr int ncc_lds_p01(int L1, int L2) { return (L1 + 1) 
 __host__ __device__ constexpr long ncc_lds_floats(int L0, int L1, int L2) {
   return (long)(L0 + 1) * ncc_lds_p01(L1, L2);
 }
+// the trilinear interpolation in the cell whose lower corner q points at
+__device__ __forceinline__ float lerp_cell(const float* q, int P2, int P01, float w0, float w1, float w2) {
+  const float c00 = q[0] + w2 * (q[1] - q[0]);
+  const float c01 = q[P2] + w2 * (q[P2 + 1] - q[P2]);
+  const float c10 = q[P01] + w2 * (q[P01 + 1] - q[P01]);
+  const float c11 = q[P01 + P2] + w2 * (q[P01 + P2 + 1] - q[P01 + P2]);
+  const float c0 = c00 + w1 * (c01 - c00), c1 = c10 + w1 * (c11 - c10);
+  return c0 + w0 * (c1 - c0);
+}
+
+// The guarded sampler without its test, for a caller that has shown that
+// every sample point lies in [0, L) on every axis (the sampled voxels within
+// a ball about the centre that rotations keep inside the box): the same
+// arithmetic as the test's fast path, so the same values.
+__device__ __forceinline__ float sample_rotated_lds_inner(const float* t, int L0, int L1, int L2, int P2, int P01,
+                                                          const Rot& R, int u0, int u1, int u2) {
+  const int c0 = L0 / 2, c1 = L1 / 2, c2 = L2 / 2;
+  const float v0 = (float)(u0 - c0), v1 = (float)(u1 - c1), v2 = (float)(u2 - c2);
+  const float p0 = c0 + R.r[0] * v0 + R.r[3] * v1 + R.r[6] * v2;
+  const float p1 = c1 + R.r[1] * v0 + R.r[4] * v1 + R.r[7] * v2;
+  const float p2 = c2 + R.r[2] * v0 + R.r[5] * v1 + R.r[8] * v2;
+  const float f0 = floorf(p0), f1 = floorf(p1), f2 = floorf(p2);
+  const int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
+  return lerp_cell(t + i0 * P01 + i1 * P2 + i2, P2, P01, p0 - f0, p1 - f1, p2 - f2);
+}
+
 // GUARD = false keeps the test of a box without the guard (the fast path for
 // cells whose upper corners are in the box too), so that its sums round as
 // they did before the guard existed (the tensor build: its components are
@@ -99,13 +125,7 @@ __device__ __forceinline__ float sample_rotated_lds(const float* t, int L0, int 
   if ((unsigned)i0 < (unsigned)(L0 - e) && (unsigned)i1 < (unsigned)(L1 - e) && (unsigned)i2 < (unsigned)(L2 - e)) {
     // the lower corner in the box (the common case): the upper corners are
     // in the box or on its zero guard
-    const float* q = t + i0 * P01 + i1 * P2 + i2;
-    const float c00 = q[0] + w2 * (q[1] - q[0]);
-    const float c01 = q[P2] + w2 * (q[P2 + 1] - q[P2]);
-    const float c10 = q[P01] + w2 * (q[P01 + 1] - q[P01]);
-    const float c11 = q[P01 + P2] + w2 * (q[P01 + P2 + 1] - q[P01 + P2]);
-    const float c0 = c00 + w1 * (c01 - c00), c1 = c10 + w1 * (c11 - c10);
-    return c0 + w0 * (c1 - c0);
+    return lerp_cell(t + i0 * P01 + i1 * P2 + i2, P2, P01, w0, w1, w2);
   }
   float a[2], b[2], c[2];
   int j0[2], j1[2], j2[2];

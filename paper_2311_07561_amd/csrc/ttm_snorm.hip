@@ -183,6 +183,11 @@ __global__ void __launch_bounds__(1024) k_snorm_rot(SnormGeo g, int nchunk, int 
   }
   const double msum = st[0], mht = st[1];
   const int nm = mcount[0];
+  // mcount[1]: the largest squared distance of a mask voxel from the centre;
+  // below the squared inscribed radius every rotated sample point lies in
+  // [0, L) on every axis
+  const int cmin = min(L0 / 2, min(L1 / 2, L2 / 2));
+  const bool inner = mcount[1] < cmin * cmin;
   const int g_lo = chunk * groups_per_chunk;
   const int g_hi = min(g.n_pad / kSnormGroup, g_lo + groups_per_chunk);
   double acc = 0.0;
@@ -196,22 +201,32 @@ __global__ void __launch_bounds__(1024) k_snorm_rot(SnormGeo g, int nchunk, int 
     float s1[kSnormGroup], s2[kSnormGroup], s3[kSnormGroup];
 #pragma unroll
     for (int k = 0; k < kSnormGroup; ++k) s1[k] = s2[k] = s3[k] = 0.0f;
-    for (int i = lane; i < nm; i += 64) {
-      const unsigned pk = mlist[i];
-      const int u0 = (int)(pk & 1023u), u1 = (int)((pk >> 10) & 1023u), u2 = (int)(pk >> 20);
-      const float mv = mval[i];
-      const float hv = LDS ? tl[u0 * P01 + u1 * P2 + u2] : slab[((long)u0 * L1 + u1) * L2 + u2];
-      const float mh = mv * hv;
+    // INNER: every mask voxel lies in the box's inscribed ball, so every
+    // sample takes the LDS sampler's fast path and its test is left out
+    auto pass = [&](auto inner_tag) {
+      constexpr bool INNER = decltype(inner_tag)::value;
+      for (int i = lane; i < nm; i += 64) {
+        const unsigned pk = mlist[i];
+        const int u0 = (int)(pk & 1023u), u1 = (int)((pk >> 10) & 1023u), u2 = (int)(pk >> 20);
+        const float mv = mval[i];
+        const float hv = LDS ? tl[u0 * P01 + u1 * P2 + u2] : slab[((long)u0 * L1 + u1) * L2 + u2];
+        const float mh = mv * hv;
 #pragma unroll
-      for (int k = 0; k < kSnormGroup; ++k) {
-        const float r = LDS ? sample_rotated_lds(tl, L0, L1, L2, P2, P01, R[k], u0, u1, u2)
-                            : sample_rotated(slab, L0, L1, L2, R[k], u0, u1, u2);
-        const float mr = mv * r;
-        s1[k] += mr;
-        s2[k] += mr * r;
-        s3[k] += mh * r;
+        for (int k = 0; k < kSnormGroup; ++k) {
+          const float r = !LDS ? sample_rotated(slab, L0, L1, L2, R[k], u0, u1, u2)
+                               : INNER ? sample_rotated_lds_inner(tl, L0, L1, L2, P2, P01, R[k], u0, u1, u2)
+                                       : sample_rotated_lds(tl, L0, L1, L2, P2, P01, R[k], u0, u1, u2);
+          const float mr = mv * r;
+          s1[k] += mr;
+          s2[k] += mr * r;
+          s3[k] += mh * r;
+        }
       }
-    }
+    };
+    if (LDS && inner)
+      pass(std::true_type{});
+    else
+      pass(std::false_type{});
 #pragma unroll
     for (int k = 0; k < kSnormGroup; ++k) {
       double t1 = s1[k], t2 = s2[k], t3 = s3[k];

@@ -610,7 +610,7 @@ hipError_t launch_pose_solve(const Geo& g, const float* score, int order_n, int 
            _c.push_back(C(mask, l3, "mask"));
            _c.push_back(C(ps.mlist, l3, "ps.mlist"));
            _c.push_back(C(ps.mval, l3, "ps.mval"));
-           _c.push_back(C(ps.mcount, 1, "ps.mcount"));
+           _c.push_back(C(ps.mcount, 2, "ps.mcount"));
            _c.push_back(C(ps.ncc, nb, "ps.ncc"));
            _c.push_back(C(ps.mbits, mask_bricks(g.L0, g.L1, g.L2), "ps.mbits"));
          } if (ps.active) _c.push_back(C(ps.active, P, "ps.active"));
@@ -624,7 +624,7 @@ hipError_t launch_mask_list(const float* mask, int L0, int L1, int L2, unsigned*
                             hipStream_t s, unsigned long long* bits) {
   LAUNCH("mask_list", s, _c.push_back(C(mask, L3(L0, L1, L2), "mask"));
          _c.push_back(C(list, L3(L0, L1, L2), "list")); _c.push_back(C(mval, L3(L0, L1, L2), "mval"));
-         _c.push_back(C(count, 1, "count")); if (bits) _c.push_back(C(bits, mask_bricks(L0, L1, L2), "bits")););
+         _c.push_back(C(count, 2, "count")); if (bits) _c.push_back(C(bits, mask_bricks(L0, L1, L2), "bits")););
 }
 
 // the rest: each buffer must at least start inside a live range
@@ -662,7 +662,7 @@ hipError_t launch_snorm(const SnormGeo&, const float* image, const float* tmpl, 
                         const double* weights, int, int, const int* pos, const int* count_dev, const double* lambda,
                         const SnormWs& w, float* out_rho, double* out_D, int* out_flags, hipStream_t s) {
   LAUNCH("snorm", s, P1(image); P1(tmpl); P1(mask); P1(quats); P1(weights); P1(pos); P1(count_dev); P1(lambda);
-         P1(w.rtab); P1(w.kap); P1(w.mlist); P1(w.slabs); P1(w.stat); P1(w.partial); P1(out_rho); P1(out_D);
+         P1(w.rtab); P1(w.kap); P1(w.mlist); _c.push_back(C(w.mcount, 2, "w.mcount")); P1(w.slabs); P1(w.stat); P1(w.partial); P1(out_rho); P1(out_D);
          P1(out_flags););
 }
 hipError_t launch_lowpass(const float* in, float* out, float* tmp_a, float* tmp_b, int n0, int n1, int n2, int,
