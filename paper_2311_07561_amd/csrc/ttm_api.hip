@@ -155,7 +155,7 @@ static PoseWs pose_layout(Carve& c, const Geo& g, int max_peaks, int K, int refi
   PoseWs w;
   const size_t nb = (size_t)max_peaks * (refine ? 27 : 1);
   w.hist = peaks ? c.take<unsigned>(kHistBins) : nullptr;
-  w.ctrl = peaks ? c.take<unsigned>(16) : nullptr;
+  w.ctrl = peaks ? c.take<unsigned>(kPeakCtrlWords) : nullptr;
   w.allc = peaks ? c.take<unsigned long long>((size_t)peaks_bigcap(g)) : nullptr;
   w.cand = peaks ? c.take<unsigned long long>(kCandCap) : nullptr;
   w.seeds = c.take<double>((size_t)n_seeds * 4);

@@ -134,14 +134,15 @@ hipError_t launch_multiplicities(int order_n, float* mu, hipStream_t s);
 // --- peaks and pose (ttm_pose.hip) --------------------------------------------
 struct PeakWs {
   unsigned* hist;                 // kHistBins bins of the candidates' key top bits
-  unsigned* ctrl;                 // 16 control words
-  unsigned long long* allc;       // every strict local maximum (peaks_bigcap entries)
+  unsigned* ctrl;                 // kPeakCtrlWords control words
+  unsigned long long* allc;       // every strict local maximum, in kPeakSubs sub-lists (peaks_bigcap entries)
   unsigned long long* cand;       // the sorted list of a round (kCandCap entries)
 };
-long peaks_bigcap(const Geo& g);  // V/8 + 1024 >= the number of strict 26-neighbour maxima
+long peaks_bigcap(const Geo& g);  // kPeakSubs sub-lists, each long enough for its share of the scan's blocks
 constexpr int kHistBins = 32768;
 constexpr int kCandCap = 16384;
-constexpr int kPeakCtrlWords = 16;
+constexpr int kPeakSubs = 64;                    // sub-lists of the scan's maxima (one counter each)
+constexpr int kPeakCtrlWords = 16 + kPeakSubs;   // control words, then the sub-lists' counters
 // planes > 1: `planes` maps of g's extents stored one after another (the
 // planes of a stack), each searched on its own; the workspace holds planes
 // copies of each buffer (kHistBins bins, kPeakCtrlWords control words,

@@ -2,10 +2,12 @@
 //
 // Peaks: valid-region voxels with F > threshold that are strictly above all
 // 26 neighbours, ordered by (F descending, linear index ascending), greedily
-// suppressed within min_dist of accepted peaks.  Candidates are bounded by a
-// histogram of the float bit patterns of F (F >= 0, so the order of the bit
-// patterns is the order of the values): the top candidates, at most
-// kCandCap, are compacted, sorted with a bitonic network in LDS, and
+// suppressed within min_dist of accepted peaks.  The scan appends each
+// block's maxima to one of kPeakSubs sub-lists (block b to sub-list b mod
+// kPeakSubs, so no counter is shared by the whole grid); candidates are
+// bounded by a histogram of the float bit patterns of F (F >= 0, so the
+// order of the bit patterns is the order of the values): the top candidates,
+// at most kCandCap, are compacted, sorted with a bitonic network in LDS, and
 // suppressed by one wavefront.
 //
 // Pose: at each peak C_n(x) is recomputed directly (float64) from the image
@@ -31,8 +33,7 @@ struct PeakGeo {
 constexpr unsigned kCandCap1 = 2048;
 
 // control words of the peak search
-enum PeakCtrl { PK_TOTAL = 0, PK_B1 = 1, PK_MORE1 = 2, PK_CNT1 = 3, PK_B2 = 4, PK_MORE2 = 5, PK_CNT2 = 6,
-                PK_REDO = 7, PK_OVER = 8 };
+enum PeakCtrl { PK_B1 = 1, PK_MORE1 = 2, PK_CNT1 = 3, PK_B2 = 4, PK_MORE2 = 5, PK_CNT2 = 6, PK_REDO = 7 };
 
 __device__ __forceinline__ unsigned long long peak_key(float v, long lin) {
   // ascending key order = F descending, then linear index ascending
@@ -55,6 +56,37 @@ __device__ __forceinline__ unsigned long long peak_key(float v, long lin) {
 constexpr int QS1 = 4, QS2 = 64, QRUN = 16;
 constexpr int QH1 = QS1 + 2, QH2 = QS2 + 2;
 
+// The scan's output per map: block b appends its maxima (at most KEYS:
+// strict maxima are never neighbours, so there is at most one per 2x2x2
+// cell, or per 2x2 cell of a single plane) to sub-list b mod kPeakSubs of
+// allc, which holds cap_sub keys (its blocks' KEYS each), counted by control
+// word 16 + b mod kPeakSubs.
+constexpr int kPeakSubCtl = 16;
+__host__ __device__ constexpr int peak_region_keys(int run) { return run == 1 ? QS1 * QS2 / 4 : run * QS1 * QS2 / 8; }
+// every key of the sub-lists, shared by the nwaves wavefronts of the grid
+// (this one is number `wave`): with nwaves a multiple of kPeakSubs, the
+// wavefronts of one sub-list take its keys in turns of 64; with fewer, each
+// takes whole sub-lists
+template <class Fn>
+__device__ __forceinline__ void for_each_key(const unsigned long long* __restrict__ allc, long cap_sub,
+                                             const unsigned* __restrict__ ctrl, int wave, int nwaves, Fn&& fn) {
+  const int lane = threadIdx.x & 63;
+  if (nwaves >= kPeakSubs) {
+    const int nparts = nwaves / kPeakSubs;
+    const int sub = wave % kPeakSubs, part = wave / kPeakSubs;
+    if (part >= nparts) return;
+    const int n = __builtin_amdgcn_readfirstlane((int)ctrl[kPeakSubCtl + sub]);
+    const unsigned long long* list = allc + sub * cap_sub;
+    for (int i = part * 64 + lane; i < n; i += nparts * 64) fn(list[i]);
+  } else {
+    for (int sub = wave; sub < kPeakSubs; sub += nwaves) {
+      const int n = __builtin_amdgcn_readfirstlane((int)ctrl[kPeakSubCtl + sub]);
+      const unsigned long long* list = allc + sub * cap_sub;
+      for (int i = lane; i < n; i += 64) fn(list[i]);
+    }
+  }
+}
+
 // max(a, b), NaN when either is NaN
 __device__ __forceinline__ float max_nan(float a, float b) { return (a >= b || a != a) ? a : b; }
 
@@ -62,12 +94,10 @@ template <int RUN>
 __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F, PeakGeo g, float threshold,
                                                     unsigned* __restrict__ ctrl,
                                                     unsigned long long* __restrict__ allc, long bigcap,
-                                                    int ztiles, long fplane) {
+                                                    long cap_sub, int ztiles, long fplane) {
   static_assert(QS1 * QS2 == 256, "one column per thread");
   constexpr int QH0 = RUN + 2;
-  // strict maxima are never neighbours: at most one per 2x2x2 cell, or per
-  // 2x2 cell of a single plane
-  constexpr int KEYS = RUN == 1 ? QS1 * QS2 / 4 : RUN * QS1 * QS2 / 8;
+  constexpr int KEYS = peak_region_keys(RUN);
   __shared__ float tile[QH0 * QH1 * QH2];
   __shared__ unsigned long long lkeys[KEYS];
   __shared__ unsigned lcount, lbase;
@@ -77,6 +107,7 @@ __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F,
   F += plane * fplane;
   ctrl += kPeakCtrlWords * plane;
   allc += bigcap * plane;
+  const int sub = ((bz * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) % kPeakSubs;
   const int b0 = g.lo0 + bz * RUN, b1 = g.lo1 + blockIdx.y * QS1, b2 = g.lo2 + blockIdx.x * QS2;
   // the run's planes that hold valid voxels and their two halo planes
   const int nv0 = min(RUN, g.hi0 - b0 + 1);
@@ -135,25 +166,20 @@ __global__ void __launch_bounds__(256) k_peaks_scan(const float* __restrict__ F,
   }
   __syncthreads();
   const unsigned nl = lcount;
-  if (tid == 0 && nl > 0u) lbase = atomicAdd(&ctrl[PK_TOTAL], nl);
-  __syncthreads();
   if (nl == 0u) return;
-  for (unsigned i = tid; i < nl; i += 256) {
-    const long slot = (long)lbase + i;
-    if (slot < bigcap)
-      allc[slot] = lkeys[i];
-    else
-      ctrl[PK_OVER] = 1u;
-  }
+  if (tid == 0) lbase = atomicAdd(&ctrl[kPeakSubCtl + sub], nl);
+  __syncthreads();
+  unsigned long long* list = allc + sub * cap_sub + lbase;
+  for (unsigned i = tid; i < nl; i += 256) list[i] = lkeys[i];
 }
 
 // Histogram of the candidates' key top bits (the float bits of F >> 16): each
-// block counts a grid-strided share of the list in LDS, then adds its
-// non-zero bins to the global histogram.
+// block counts its wavefronts' share of the scan's sub-lists in LDS, then adds
+// its non-zero bins to the global histogram.
 constexpr int kHistBlocks = 64;
 __global__ void __launch_bounds__(1024) k_peaks_hist(const unsigned* __restrict__ ctrl,
                                                      const unsigned long long* __restrict__ allc, long bigcap,
-                                                     unsigned* __restrict__ hist) {
+                                                     long cap_sub, unsigned* __restrict__ hist) {
   __shared__ unsigned lh[kHistBins];
   const int tid = threadIdx.x;
   const int plane = blockIdx.y;
@@ -162,11 +188,10 @@ __global__ void __launch_bounds__(1024) k_peaks_hist(const unsigned* __restrict_
   hist += (long)kHistBins * plane;
   for (int i = tid; i < kHistBins; i += 1024) lh[i] = 0u;
   __syncthreads();
-  const long total = min((long)ctrl[PK_TOTAL], bigcap);
-  for (long i = (long)blockIdx.x * 1024 + tid; i < total; i += (long)gridDim.x * 1024) {
-    const unsigned bits = 0xFFFFFFFFu - (unsigned)(allc[i] >> 32);
+  for_each_key(allc, cap_sub, ctrl, blockIdx.x * 16 + (tid >> 6), gridDim.x * 16, [&](unsigned long long k) {
+    const unsigned bits = 0xFFFFFFFFu - (unsigned)(k >> 32);
     atomicAdd(&lh[bits >> 16], 1u);
-  }
+  });
   __syncthreads();
   for (int i = tid; i < kHistBins; i += 1024) {
     const unsigned v = lh[i];
@@ -228,32 +253,31 @@ __global__ void __launch_bounds__(1024) k_peaks_select(const unsigned* __restric
   select_bin(hist, ctrl, 1, kCandCap1, part);
 }
 
-// the candidates whose key bin is >= bmin among the first total entries of
-// allc, appended to cand (at most cap; cnt counts them all), each thread
-// taking entries first, first + stride, ...
-__device__ void gather_keys(unsigned* __restrict__ cnt, unsigned bmin, long total,
-                            const unsigned long long* __restrict__ allc, unsigned long long* __restrict__ cand,
-                            unsigned cap, long first, long stride) {
-  for (long i = first; i < total; i += stride) {
-    const unsigned long long k = allc[i];
+// the candidates whose key bin is >= bmin among the scan's sub-lists,
+// appended to cand (at most cap; cnt counts them all); this wavefront is
+// number `wave` of nwaves sharing the lists
+__device__ void gather_keys(unsigned* __restrict__ cnt, unsigned bmin, const unsigned long long* __restrict__ allc,
+                            long cap_sub, const unsigned* __restrict__ ctrl, unsigned long long* __restrict__ cand,
+                            unsigned cap, int wave, int nwaves) {
+  for_each_key(allc, cap_sub, ctrl, wave, nwaves, [&](unsigned long long k) {
     const unsigned bits = 0xFFFFFFFFu - (unsigned)(k >> 32);
     if ((bits >> 16) >= bmin) {
       const unsigned slot = atomicAdd(cnt, 1u);
       if (slot < cap) cand[slot] = k;
     }
-  }
+  });
 }
 
 // round 1: the candidates above the round's bin
 __global__ void __launch_bounds__(256) k_peaks_gather(unsigned* __restrict__ ctrl,
                                                       const unsigned long long* __restrict__ allc, long bigcap,
-                                                      unsigned long long* __restrict__ cand) {
+                                                      long cap_sub, unsigned long long* __restrict__ cand) {
   const int plane = blockIdx.y;
   ctrl += kPeakCtrlWords * plane;
   allc += bigcap * plane;
   cand += (long)kCandCap * plane;
-  gather_keys(&ctrl[PK_CNT1], ctrl[PK_B1], min((long)ctrl[PK_TOTAL], bigcap), allc, cand, kCandCap1,
-              (long)blockIdx.x * blockDim.x + threadIdx.x, (long)gridDim.x * blockDim.x);
+  gather_keys(&ctrl[PK_CNT1], ctrl[PK_B1], allc, cap_sub, ctrl, cand, kCandCap1, blockIdx.x * 4 + (threadIdx.x >> 6),
+              gridDim.x * 4);
 }
 
 __device__ __forceinline__ void decode_lin(unsigned long long key, int n1, int n2, int& x0, int& x1, int& x2) {
@@ -437,7 +461,7 @@ __global__ void __launch_bounds__(64) k_peaks_nms(PeakGeo g, unsigned* __restric
   if (threadIdx.x == 0) {
     const bool short_list = nacc < max_peaks && exhausted && more_below;
     out_count[0] = nacc;
-    out_count[1] = ctrl[PK_OVER] ? TTM_PEAKS_TRUNCATED : 0;
+    out_count[1] = 0;
     if (short_list) ctrl[PK_REDO] = 1u;
   }
 }
@@ -449,6 +473,7 @@ __global__ void __launch_bounds__(64) k_peaks_nms(PeakGeo g, unsigned* __restric
 __global__ void __launch_bounds__(1024) k_peaks_round2(PeakGeo g, const unsigned* __restrict__ hist,
                                                        unsigned* __restrict__ ctrl,
                                                        const unsigned long long* __restrict__ allc, long bigcap,
+                                                       long cap_sub,
                                                        unsigned long long* __restrict__ cand, float min_dist,
                                                        int max_peaks, int* __restrict__ out_pos,
                                                        float* __restrict__ out_score, int* __restrict__ out_count) {
@@ -469,7 +494,7 @@ __global__ void __launch_bounds__(1024) k_peaks_round2(PeakGeo g, const unsigned
   __syncthreads();
   const unsigned bmin = sel[0];
   const bool more_flag = sel[1] != 0u;
-  gather_keys(&ctrl[PK_CNT2], bmin, min((long)ctrl[PK_TOTAL], bigcap), allc, cand, kCandCap, tid, 1024);
+  gather_keys(&ctrl[PK_CNT2], bmin, allc, cap_sub, ctrl, cand, kCandCap, tid >> 6, 16);
   __syncthreads();
   // the count from the atomic unit (the counter's cache line was read at the start)
   if (tid == 0) s_count = atomicAdd(&ctrl[PK_CNT2], 0u);
@@ -485,7 +510,7 @@ __global__ void __launch_bounds__(1024) k_peaks_round2(PeakGeo g, const unsigned
   if (tid == 0) {
     const bool short_list = nacc < max_peaks && exhausted && (more_flag || ncount > (unsigned)kCandCap);
     out_count[0] = nacc;
-    out_count[1] = short_list || ctrl[PK_OVER] ? TTM_PEAKS_TRUNCATED : 0;
+    out_count[1] = short_list ? TTM_PEAKS_TRUNCATED : 0;
   }
 }
 
@@ -496,7 +521,26 @@ __global__ void k_peaks_clear(unsigned* __restrict__ hist, long nh, unsigned* __
   else if (i < nh + nc) ctrl[i - nh] = 0u;
 }
 
-long peaks_bigcap(const Geo& g) { return g.vol() / 8 + 1024; }
+// the scan's grid over one map: runs of `run` planes (one for a single
+// plane) and blocks of QS1 x QS2 columns over the valid region
+struct PeakGrid {
+  int run, ztiles, gy, gx;
+  long nblk() const { return (long)ztiles * gy * gx; }
+  // a sub-list's capacity: its blocks' keys
+  long cap_sub() const { return (nblk() + kPeakSubs - 1) / kPeakSubs * peak_region_keys(run); }
+};
+static PeakGrid peak_grid(const Geo& gg) {
+  const int e0 = gg.n0 - gg.L0 + 1, e1 = gg.n1 - gg.L1 + 1, e2 = gg.n2 - gg.L2 + 1;
+  PeakGrid pg;
+  pg.run = gg.n0 == 1 ? 1 : QRUN;
+  pg.ztiles = (e0 + pg.run - 1) / pg.run;
+  pg.gy = (e1 + QS1 - 1) / QS1;
+  pg.gx = (e2 + QS2 - 1) / QS2;
+  return pg;
+}
+
+// the scan's sub-lists
+long peaks_bigcap(const Geo& g) { return kPeakSubs * peak_grid(g).cap_sub(); }
 
 hipError_t launch_peaks(const Geo& gg, const float* score, float threshold, float min_dist,
                         int max_peaks, const PeakWs& w, int* out_pos, float* out_score,
@@ -507,29 +551,28 @@ hipError_t launch_peaks(const Geo& gg, const float* score, float threshold, floa
   g.lo1 = gg.c1; g.hi1 = gg.n1 - gg.L1 + gg.c1;
   g.lo2 = gg.c2; g.hi2 = gg.n2 - gg.L2 + gg.c2;
   const long bigcap = peaks_bigcap(gg);
+  const PeakGrid pg = peak_grid(gg);
+  const long cap_sub = pg.cap_sub();
   const unsigned P = (unsigned)planes;
   const long nh = (long)kHistBins * planes;
   const int nctl = kPeakCtrlWords * planes;
   hipLaunchKernelGGL(k_peaks_clear, dim3((unsigned)((nh + nctl + 255) / 256)), dim3(256), 0, s, w.hist, nh, w.ctrl,
                      nctl);
-  const int e0 = g.hi0 - g.lo0 + 1, e1 = g.hi1 - g.lo1 + 1, e2 = g.hi2 - g.lo2 + 1;
-  const int run = g.n0 == 1 ? 1 : QRUN;
-  const int ztiles = (e0 + run - 1) / run;
-  dim3 sgrid((e2 + QS2 - 1) / QS2, (e1 + QS1 - 1) / QS1, (unsigned)ztiles * P);
-  if (run == 1)
-    hipLaunchKernelGGL(k_peaks_scan<1>, sgrid, dim3(256), 0, s, score, g, threshold, w.ctrl, w.allc, bigcap, ztiles,
-                       gg.vol());
+  dim3 sgrid((unsigned)pg.gx, (unsigned)pg.gy, (unsigned)pg.ztiles * P);
+  if (pg.run == 1)
+    hipLaunchKernelGGL(k_peaks_scan<1>, sgrid, dim3(256), 0, s, score, g, threshold, w.ctrl, w.allc, bigcap,
+                       cap_sub, pg.ztiles, gg.vol());
   else
     hipLaunchKernelGGL(k_peaks_scan<QRUN>, sgrid, dim3(256), 0, s, score, g, threshold, w.ctrl, w.allc, bigcap,
-                       ztiles, gg.vol());
-  hipLaunchKernelGGL(k_peaks_hist, dim3(kHistBlocks, P), dim3(1024), 0, s, w.ctrl, w.allc, bigcap, w.hist);
+                       cap_sub, pg.ztiles, gg.vol());
+  hipLaunchKernelGGL(k_peaks_hist, dim3(kHistBlocks, P), dim3(1024), 0, s, w.ctrl, w.allc, bigcap, cap_sub, w.hist);
   hipLaunchKernelGGL(k_peaks_select, dim3(P), dim3(1024), 0, s, w.hist, w.ctrl);
-  hipLaunchKernelGGL(k_peaks_gather, dim3(256, P), dim3(256), 0, s, w.ctrl, w.allc, bigcap, w.cand);
+  hipLaunchKernelGGL(k_peaks_gather, dim3(256, P), dim3(256), 0, s, w.ctrl, w.allc, bigcap, cap_sub, w.cand);
   hipLaunchKernelGGL(k_peaks_sort1, dim3(P), dim3(1024), 0, s, w.ctrl, w.cand);
   hipLaunchKernelGGL(k_peaks_nms, dim3(P), dim3(64), 0, s, g, w.ctrl, w.cand, min_dist, max_peaks, out_pos,
                      out_score, out_count);
-  hipLaunchKernelGGL(k_peaks_round2, dim3(P), dim3(1024), 0, s, g, w.hist, w.ctrl, w.allc, bigcap, w.cand, min_dist,
-                     max_peaks, out_pos, out_score, out_count);
+  hipLaunchKernelGGL(k_peaks_round2, dim3(P), dim3(1024), 0, s, g, w.hist, w.ctrl, w.allc, bigcap, cap_sub,
+                     w.cand, min_dist, max_peaks, out_pos, out_score, out_count);
   return hipGetLastError();
 }
 
