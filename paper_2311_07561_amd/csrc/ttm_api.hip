@@ -235,13 +235,15 @@ static ClassWs class_layout(Carve& c, const Geo& g, int nrot) {
 
 // forward axis-2 and axis-1 transforms of the image and of its square
 // stats_in (optional): the image statistics (mean, variance, mask sum) taken
-// elsewhere (the whole image of a tile); otherwise they are computed here
+// elsewhere (the whole image of a tile); otherwise they are computed here,
+// with the multiplicities of order mu_order into mu if mu is given
 static ttm_status image_forward(const Geo& g, const float* image, float2* Xf, float2* Xg,
                                 double* stats, double* partials, const float* mask, hipStream_t stream,
-                                const double* stats_in = nullptr) {
+                                const double* stats_in = nullptr, int mu_order = 0, float* mu = nullptr) {
   const long L3 = (long)g.L0 * g.L1 * g.L2;
   const long rows = (long)g.n0 * g.n1;
-  if (!stats_in) TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), mask, L3, partials, stats, stream));
+  if (!stats_in)
+    TTM_PROF(PC_STATS, launch_image_stats(image, g.vol(), mask, L3, partials, stats, stream, mu_order, mu));
   const double* st = stats_in ? stats_in : stats;
   TTM_PROF(PC_ROWS, launch_r2c_rows(g.n2, image, g.n2, g.n2, rows, Xf, Xg, rows, 0, 1, st, stream));
   TTM_PROF(PC_PEN_FWD, launch_pencils(g.n1, false, Xf, (long)g.n0 * g.p2, g.p2, (long)g.n1 * g.p2, g.p2, g.n1, 0,
@@ -441,11 +443,14 @@ static ttm_status correlate_into(const Geo& g, int order_n, int K, const float* 
     TTM_CALL(moments_finite(w.stats, stream));
     stats_in = w.stats;
   }
+  // the multiplicities: with the image statistics where those are taken here
+  const bool mu_with_stats = !planar && !stats_in;
   if (planar)
     TTM_PROF(PC_STATS, launch_planar_mu(order_n, w.mu, stream));
-  else
+  else if (!mu_with_stats)
     TTM_PROF(PC_STATS, launch_multiplicities(order_n, w.mu, stream));
-  TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream, stats_in));
+  TTM_CALL(image_forward(g, image, w.Xf, w.Xg, w.stats, w.partials, mask, stream, stats_in, order_n,
+                         mu_with_stats ? w.mu : nullptr));
   // K components and the mask against f, then the mask against f^2
   const Pass1Args p1{w.Xf, bk, K + 1, w.Xg, bk + (long)K * g.bank_slab(), 1, g.bank_slab(), w.H, half};
   if (two_pass && !out_C && !planar && two_pass_supported(g)) {

@@ -69,8 +69,22 @@ __global__ void __launch_bounds__(256) k_stats_partial(const float* __restrict__
 }
 
 __global__ void __launch_bounds__(256) k_stats_final(const double* __restrict__ partials, int nb, long n,
-                                                     int with_mask, double* __restrict__ stats) {
+                                                     int with_mask, double* __restrict__ stats, int mu_order,
+                                                     float* __restrict__ mu) {
   __shared__ double sh[768];
+  // the multiplicities n! / (a1! a2! a3! a4!) of the packed multi-indices
+  if (mu) {
+    const int K = (mu_order + 1) * (mu_order + 2) * (mu_order + 3) / 6;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+      int al[4];
+      alpha_of_dev(mu_order, k, al);
+      double f = 1.0;
+      for (int i = 2; i <= mu_order; ++i) f *= i;
+      for (int d = 0; d < 4; ++d)
+        for (int i = 2; i <= al[d]; ++i) f /= i;
+      mu[k] = (float)f;
+    }
+  }
   double s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
     s1 += partials[3 * i];
@@ -88,9 +102,10 @@ __global__ void __launch_bounds__(256) k_stats_final(const double* __restrict__ 
 }
 
 hipError_t launch_image_stats(const float* img, long n, const float* mask, long nm, double* partials,
-                              double* stats, hipStream_t s) {
+                              double* stats, hipStream_t s, int mu_order, float* mu) {
   hipLaunchKernelGGL(k_stats_partial, dim3(kStatBlocks), dim3(256), 0, s, img, n, mask, nm, partials);
-  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(256), 0, s, partials, kStatBlocks, n, mask ? 1 : 0, stats);
+  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(256), 0, s, partials, kStatBlocks, n, mask ? 1 : 0, stats,
+                     mu_order, mu);
   return hipGetLastError();
 }
 

@@ -44,10 +44,11 @@ __host__ __device__ constexpr int row_pitch(int n2) { return n2 / 2 + 1; }
 // --- FFT passes (ttm_fft.hip) -------------------------------------------------
 // image moments in float64: stats[0] = mean, stats[1] = population variance
 // and, if mask is given, stats[2] = m_sum over its nm values; partials holds
-// 3 * kStatPartials doubles
+// 3 * kStatPartials doubles.  mu (optional): the multiplicities of order
+// mu_order (as launch_multiplicities), written by the same launches.
 constexpr int kStatPartials = 512;
 hipError_t launch_image_stats(const float* img, long n, const float* mask, long nm, double* partials,
-                              double* stats, hipStream_t s);
+                              double* stats, hipStream_t s, int mu_order = 0, float* mu = nullptr);
 // axis-2 R2C of rows.  mode 0: src rows (len_valid <= n2 values, rest zero)
 // -> dst0; mode 1: image rows, (f - mean) -> dst0 and (f - mean)^2 -> dst1.
 // dst row of source row r: (r / grp) * grp_stride + r % grp (rows of h2).

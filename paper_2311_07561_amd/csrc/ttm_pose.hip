@@ -1338,10 +1338,10 @@ __global__ void __launch_bounds__(1024) k_mask_list(const float* __restrict__ ma
 
 // the same list over the whole chip: one wavefront per brick takes the
 // ballot of its voxels with m != 0 ...
-__global__ void __launch_bounds__(256) k_mask_bits(const float* __restrict__ mask, int L0, int L1, int L2, int nB,
-                                                   unsigned long long* __restrict__ bits, int* __restrict__ count) {
+__device__ __forceinline__ void mask_bits_block(int blk, const float* __restrict__ mask, int L0, int L1, int L2,
+                                                int nB, unsigned long long* __restrict__ bits, int* __restrict__ count) {
   const int lane = threadIdx.x & 63;
-  const int br = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int br = blk * 4 + (threadIdx.x >> 6);
   if (br == 0 && lane == 0) count[1] = 0;
   if (br >= nB) return;
   const int B1 = (L1 + 3) / 4, B2 = (L2 + 3) / 4;
@@ -1351,6 +1351,23 @@ __global__ void __launch_bounds__(256) k_mask_bits(const float* __restrict__ mas
   const float m = in ? mask[(u0 * L1 + u1) * L2 + u2] : 0.0f;
   const unsigned long long bl = __ballot(m != 0.0f);
   if (lane == 0) bits[br] = bl;
+}
+__global__ void __launch_bounds__(256) k_mask_bits(const float* __restrict__ mask, int L0, int L1, int L2, int nB,
+                                                   unsigned long long* __restrict__ bits, int* __restrict__ count) {
+  mask_bits_block(blockIdx.x, mask, L0, L1, L2, nB, bits, count);
+}
+
+// the S^3 seed table and the mask bricks' ballots in one launch: blocks below
+// seed_blocks take 256 seeds each, the others four bricks each
+__global__ void __launch_bounds__(256) k_pose_tables(int n_seeds, double* __restrict__ seeds, int seed_blocks,
+                                                     const float* __restrict__ mask, int L0, int L1, int L2, int nB,
+                                                     unsigned long long* __restrict__ bits, int* __restrict__ count) {
+  if ((int)blockIdx.x < seed_blocks) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n_seeds) seed_point(i, n_seeds, seeds + 4 * i);
+    return;
+  }
+  mask_bits_block(blockIdx.x - seed_blocks, mask, L0, L1, L2, nB, bits, count);
 }
 
 // ... then each block places the voxels of four bricks after the count of
@@ -1783,8 +1800,16 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
   const PoseGeo g = make_posegeo(gg);
   const int K = num_components(order_n);
   const int NB = refine ? 27 : 1;
-  if (!reuse_tables && !g.planar)
-    hipLaunchKernelGGL(k_seed_table, dim3((n_seeds + 255) / 256), dim3(256), 0, s, n_seeds, ps.seeds);
+  // the mask list's first kernel (the bricks' ballots) joins the seed table's
+  // launch where both are built here
+  const long nB = mask_bricks(g.L0, g.L1, g.L2);
+  const bool tables = !reuse_tables && !g.planar && refine == 2 && ps.mbits && nB <= kMaskFastBricks;
+  const int seed_blocks = (n_seeds + 255) / 256;
+  if (tables)
+    hipLaunchKernelGGL(k_pose_tables, dim3((unsigned)(seed_blocks + (nB + 3) / 4)), dim3(256), 0, s, n_seeds,
+                       ps.seeds, seed_blocks, mask, g.L0, g.L1, g.L2, (int)nB, ps.mbits, ps.mcount);
+  else if (!reuse_tables && !g.planar)
+    hipLaunchKernelGGL(k_seed_table, dim3((unsigned)seed_blocks), dim3(256), 0, s, n_seeds, ps.seeds);
   const dim3 eg((unsigned)(max_peaks * NB));
   if (g.planar) {
     switch (order_n) {
@@ -1826,7 +1851,10 @@ hipError_t launch_pose_solve(const Geo& gg, const float* score, int order_n, int
     default: return hipErrorInvalidValue;
   }
   if (refine == 2) {
-    if (!reuse_tables)
+    if (tables)
+      hipLaunchKernelGGL(k_mask_write, dim3((unsigned)((nB + 3) / 4)), dim3(256), 0, s, mask, g.L0, g.L1, g.L2,
+                         (int)nB, ps.mbits, ps.mlist, ps.mval, ps.mcount);
+    else if (!reuse_tables)
       (void)launch_mask_list(mask, g.L0, g.L1, g.L2, ps.mlist, ps.mval, ps.mcount, s, ps.mbits);
     const long lds = ncc_lds_floats(g.L0, g.L1, g.L2);
     const int ngroups = ncc_groups;

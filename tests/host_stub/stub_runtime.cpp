@@ -457,9 +457,10 @@ static Check C(const T* p, size_t count, const char* what) {
 static long L3(int a, int b, int c) { return (long)a * b * c; }
 
 hipError_t launch_image_stats(const float* img, long n, const float* mask, long nm, double* partials,
-                              double* stats, hipStream_t s) {
+                              double* stats, hipStream_t s, int mu_order, float* mu) {
   LAUNCH("image_stats", s, _c.push_back(C(img, n, "img")); if (mask) _c.push_back(C(mask, nm, "mask"));
-         _c.push_back(C(partials, 3 * kStatPartials, "partials")); _c.push_back(C(stats, 3, "stats")););
+         _c.push_back(C(partials, 3 * kStatPartials, "partials")); _c.push_back(C(stats, 3, "stats"));
+         if (mu) _c.push_back(C(mu, num_components(mu_order), "mu")););
 }
 hipError_t launch_r2c_rows(int n2, const float* src, long src_stride, int len_valid, long nrows, float2* dst0,
                            float2* dst1, long grp, long grp_stride, int mode, const double* stats, hipStream_t s) {
