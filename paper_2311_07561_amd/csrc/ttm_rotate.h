@@ -80,6 +80,13 @@ __host__ __device__ constexpr int ncc_lds_p01(int L1, int L2) { return (L1 + 1) 
 __host__ __device__ constexpr long ncc_lds_floats(int L0, int L1, int L2) {
   return (long)(L0 + 1) * ncc_lds_p01(L1, L2);
 }
+// the layout offset of cell (i0, i1, i2), every index non-negative and every
+// product below 2^24 (the layout fits in LDS): 24-bit multiplies, which run
+// at full rate where a 32-bit multiply takes four passes
+__device__ __forceinline__ int lds_cell(int i0, int i1, int i2, int P2, int P01) {
+  return (int)(__umul24((unsigned)i0, (unsigned)P01) + __umul24((unsigned)i1, (unsigned)P2)) + i2;
+}
+
 // the trilinear interpolation in the cell whose lower corner q points at
 __device__ __forceinline__ float lerp_cell(const float* q, int P2, int P01, float w0, float w1, float w2) {
   const float c00 = q[0] + w2 * (q[1] - q[0]);
@@ -103,7 +110,7 @@ __device__ __forceinline__ float sample_rotated_lds_inner(const float* t, int L0
   const float p2 = c2 + R.r[2] * v0 + R.r[5] * v1 + R.r[8] * v2;
   const float f0 = floorf(p0), f1 = floorf(p1), f2 = floorf(p2);
   const int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
-  return lerp_cell(t + i0 * P01 + i1 * P2 + i2, P2, P01, p0 - f0, p1 - f1, p2 - f2);
+  return lerp_cell(t + lds_cell(i0, i1, i2, P2, P01), P2, P01, p0 - f0, p1 - f1, p2 - f2);
 }
 
 // GUARD = false keeps the test of a box without the guard (the fast path for
@@ -125,7 +132,7 @@ __device__ __forceinline__ float sample_rotated_lds(const float* t, int L0, int 
   if ((unsigned)i0 < (unsigned)(L0 - e) && (unsigned)i1 < (unsigned)(L1 - e) && (unsigned)i2 < (unsigned)(L2 - e)) {
     // the lower corner in the box (the common case): the upper corners are
     // in the box or on its zero guard
-    return lerp_cell(t + i0 * P01 + i1 * P2 + i2, P2, P01, w0, w1, w2);
+    return lerp_cell(t + lds_cell(i0, i1, i2, P2, P01), P2, P01, w0, w1, w2);
   }
   float a[2], b[2], c[2];
   int j0[2], j1[2], j2[2];
@@ -136,8 +143,8 @@ __device__ __forceinline__ float sample_rotated_lds(const float* t, int L0, int 
     a[d] = ok0 ? (d ? w0 : 1.0f - w0) : 0.0f;
     b[d] = ok1 ? (d ? w1 : 1.0f - w1) : 0.0f;
     c[d] = ok2 ? (d ? w2 : 1.0f - w2) : 0.0f;
-    j0[d] = ok0 ? (i0 + d) * P01 : 0;
-    j1[d] = ok1 ? (i1 + d) * P2 : 0;
+    j0[d] = ok0 ? (int)__umul24((unsigned)(i0 + d), (unsigned)P01) : 0;
+    j1[d] = ok1 ? (int)__umul24((unsigned)(i1 + d), (unsigned)P2) : 0;
     j2[d] = ok2 ? i2 + d : 0;
   }
   float acc = 0.0f;
@@ -173,8 +180,8 @@ __device__ __forceinline__ void fill_lds_box(float* tl, const float* __restrict_
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const unsigned e = (unsigned)(e0 + j * nthreads);
-      const unsigned j0 = __umulhi(e, m01), rem = e - j0 * (unsigned)P01;
-      const unsigned j1 = __umulhi(rem, m2), j2 = rem - j1 * (unsigned)P2;
+      const unsigned j0 = __umulhi(e, m01), rem = e - __umul24(j0, (unsigned)P01);
+      const unsigned j1 = __umulhi(rem, m2), j2 = rem - __umul24(j1, (unsigned)P2);
       const bool in = (int)e < total && j0 < (unsigned)L0 && j1 < (unsigned)L1 && j2 < (unsigned)L2;
       // an unconditional load (of element 0 outside the box), so that the
       // group's loads issue before any wait
