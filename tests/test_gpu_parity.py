@@ -280,11 +280,14 @@ def test_pose_at_given_positions_and_refinement():
         assert abs(rr["lam"].cpu().numpy()[i] - lams[k]) <= 1e-6 * abs(lams[k]) + 1e-9
 
 
-def test_pose_at_refinement_by_ncc():
+@pytest.mark.parametrize("radius", [4.0, 6.0])
+def test_pose_at_refinement_by_ncc(radius):
     """refine = 2: each of the 27 voxels gets its own dominant rotation and the
     NCC of the image window against the template rotated by it; the voxel with
-    the largest NCC is reported (oracle: refine_by_ncc)."""
-    img, tmpl, mask, q, w = rand_setup(61, (32, 32, 32), (8, 8, 8), 4.0, 64)
+    the largest NCC is reported (oracle: refine_by_ncc).  Radius 4 keeps the
+    mask in the box's inscribed ball (the NCC kernel leaves out the sampler's
+    bounds test); radius 6 reaches past it (the test runs)."""
+    img, tmpl, mask, q, w = rand_setup(61, (32, 32, 32), (8, 8, 8), radius, 64)
     n = 4
     s = O.rotated_template(tmpl, mask, q[9])
     sl = tuple(slice(15 - 4, 15 + 4) for _ in range(3))

@@ -78,6 +78,7 @@ def _check(img, tmpl, mask, n, q, w, pos, lam, rho, D, flags, expect_flags):
     ((16, 16, 16), 7.0, 301, 4),        # rotation count not a multiple of the group of 8
     ((13, 16, 11), 4.5, 64, 2),         # non-cubic box
     ((12, 12, 12), 6.0, 96, 6),         # mask reaching the box's last voxel: corners outside
+    ((12, 12, 12), 8.0, 96, 4),         # mask past the inscribed ball: the sampler's bounds test runs
 ])
 def test_snorm_matches_oracle(L, radius, n_rot, n):
     rng = np.random.default_rng(7 + n)
