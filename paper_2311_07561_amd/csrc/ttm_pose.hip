@@ -40,7 +40,7 @@ __device__ __forceinline__ unsigned long long peak_key(float v, long lin) {
   return ((unsigned long long)(0xFFFFFFFFu - __float_as_uint(v)) << 32) | (unsigned long long)lin;
 }
 
-// One pass over the valid region in blocks of 4 rows x 64 columns and runs
+// One pass over the valid region in blocks of 8 rows x 32 columns and runs
 // of up to 16 planes along axis 0, staged with a one-voxel halo in LDS:
 // every strict local maximum above the threshold is appended to the full
 // candidate list.  Each thread walks its column (x1, x2) through the run and
@@ -53,7 +53,7 @@ __device__ __forceinline__ unsigned long long peak_key(float v, long lin) {
 // with each of them would.  Out-of-image neighbours hold -inf.  Maps of
 // depth 1 (the planes of a stack) take runs of one plane (RUN = 1), so that
 // their blocks reserve the LDS of three planes, not eighteen.
-constexpr int QS1 = 4, QS2 = 64, QRUN = 16;
+constexpr int QS1 = 8, QS2 = 32, QRUN = 16;
 constexpr int QH1 = QS1 + 2, QH2 = QS2 + 2;
 
 // The scan's output per map: block b appends its maxima (at most KEYS:

@@ -561,12 +561,12 @@ hipError_t launch_multiplicities(int order_n, float* mu, hipStream_t s) {
 }
 
 // the scan's 64 sub-lists: runs of 16 planes (1 for a single plane) by
-// 4 x 64 columns of the valid region, 16 x 4 x 64 / 8 keys per block (64 for
+// 8 x 32 columns of the valid region, 16 x 8 x 32 / 8 keys per block (64 for
 // one plane), each sub-list long enough for its share of the blocks
 long peaks_bigcap(const Geo& g) {
   const long e0 = g.n0 - g.L0 + 1, e1 = g.n1 - g.L1 + 1, e2 = g.n2 - g.L2 + 1;
   const long run = g.n0 == 1 ? 1 : 16, keys = run == 1 ? 64 : run * 32;
-  const long nblk = ((e0 + run - 1) / run) * ((e1 + 3) / 4) * ((e2 + 63) / 64);
+  const long nblk = ((e0 + run - 1) / run) * ((e1 + 7) / 8) * ((e2 + 31) / 32);
   return 64 * ((nblk + 63) / 64 * keys);
 }
 hipError_t launch_peaks(const Geo& g, const float* score, float, float, int max_peaks, const PeakWs& w, int* out_pos,
